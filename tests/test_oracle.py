@@ -1,0 +1,416 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Each test names the fact it relies on.  None re-types the oracle's own
+formulas: the checks are textbook identities, library routines used as black
+boxes (scipy Bessel functions and quadrature, numpy FFT), brute force on tiny
+grids, exact invariances of the method, the paper's printed numbers
+(Table 2) and the convergence bounds of Section 5.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.special as sp
+from scipy.integrate import quad
+
+import oracle
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# FFT (textbook identities and numpy as an independent routine)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("M", [1, 2, 4, 8, 64, 1024])
+def test_fft_naive_dft_and_identities(M):
+    rng = np.random.default_rng(M)
+    x = rng.standard_normal(M) + 1j * rng.standard_normal(M)
+    X = oracle.fft(x)
+    if M <= 64:
+        j = np.arange(M)
+        W = np.exp(-2j * np.pi * np.outer(j, j) / M)
+        assert np.allclose(X, W @ x, rtol=0, atol=1e-12 * M)
+    assert np.allclose(X, np.fft.fft(x), rtol=0, atol=1e-12 * np.sqrt(M))
+    # Parseval: sum |x|^2 = (1/M) sum |X|^2
+    assert abs(np.sum(abs(x) ** 2) - np.sum(abs(X) ** 2) / M) < 1e-12 * M
+    # inverse(forward(x)) = x
+    assert np.allclose(oracle.fft(X, inverse=True), x, rtol=0, atol=1e-13 * M)
+    # FFT of a unit impulse is all ones
+    d = np.zeros(M, complex)
+    d[0] = 1
+    assert np.allclose(oracle.fft(d), np.ones(M), rtol=0, atol=1e-15)
+
+
+def test_fft_rejects_non_power_of_two():
+    with pytest.raises(ValueError):
+        oracle.fft(np.ones(12))
+
+
+# --------------------------------------------------------------------------
+# Bessel functions and the kernel at the origin
+# --------------------------------------------------------------------------
+
+def test_bessel_k0_k1_against_scipy():
+    x = np.concatenate([np.geomspace(1e-4, 2.0, 300),
+                        np.linspace(2.0 + 1e-9, 700.0, 700)])
+    assert np.max(np.abs(oracle.k0(x) / sp.k0(x) - 1)) < 1e-14
+    assert np.max(np.abs(oracle.k1(x) / sp.k1(x) - 1)) < 1e-14
+
+
+@pytest.mark.parametrize("beta", [0.005, 0.05, 0.3, 1.0, 2.6, 6.0])
+def test_kappa0_is_cell_average_of_green(beta):
+    """kappa(0) = ftilde^2 * integral of G over the ball of cell volume.
+    2D: G = K0(ftilde r/hbar)/(2 pi hbar^2); 3D: exp(-ftilde r/hbar)/(4 pi
+    hbar^2 r).  Checked by adaptive quadrature in physical units."""
+    ft, hbar, h = 1.7, 0.03, beta * 0.03 / 1.7
+    r0 = h / np.sqrt(np.pi)
+    g2 = quad(lambda r: 2 * np.pi * r * sp.k0(ft * r / hbar) / (2 * np.pi * hbar ** 2),
+              0, r0, epsabs=1e-300, epsrel=1e-12, limit=400)[0]
+    assert abs(oracle.kappa0(2, beta) / (ft ** 2 * g2) - 1) < 1e-10
+    r3 = h * (3 / (4 * np.pi)) ** (1 / 3)
+    g3 = quad(lambda r: 4 * np.pi * r * r * np.exp(-ft * r / hbar) / (4 * np.pi * hbar ** 2 * r),
+              0, r3, epsabs=1e-300, epsrel=1e-13)[0]
+    assert abs(oracle.kappa0(3, beta) / (ft ** 2 * g3) - 1) < 1e-11
+
+
+def test_kappa_samples_green_functions():
+    """kappa(m) = ftilde^2 h^D G(h m) with G from eqs. GreensFunction2D/3D,
+    evaluated here in physical units with scipy's K0."""
+    ft, hbar, h = 1.3, 0.05, 1.0 / 64
+    beta = ft * h / hbar
+    k2 = oracle.kappa((5, 7), beta)
+    for (a, b) in [(0, 1), (1, 0), (3, 4), (4, 6), (2, 5)]:
+        r = h * np.hypot(a, b)
+        G = sp.k0(ft * r / hbar) / (2 * np.pi * hbar ** 2)
+        assert abs(k2[a, b] / (ft ** 2 * h ** 2 * G) - 1) < 1e-13
+    k3 = oracle.kappa((4, 3, 5), beta)
+    for (a, b, c) in [(0, 0, 1), (1, 2, 3), (3, 2, 4)]:
+        r = h * np.sqrt(a * a + b * b + c * c)
+        G = np.exp(-ft * r / hbar) / (4 * np.pi * hbar ** 2 * r)
+        assert abs(k3[a, b, c] / (ft ** 2 * h ** 3 * G) - 1) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Green's function normalisation and spectrum
+# --------------------------------------------------------------------------
+
+def _full_sum(kap):
+    """Sum of the evenly extended kernel over all offsets."""
+    w = np.ones_like(kap)
+    for ax in range(kap.ndim):
+        sl = [slice(None)] * kap.ndim
+        sl[ax] = slice(1, None)
+        w[tuple(sl)] *= 2
+    return float(np.sum(w * kap))
+
+
+def test_kernel_mass_tends_to_one():
+    """(-hbar^2 lap + ftilde^2) G = delta integrates to ftilde^2 int G = 1,
+    so the lattice sum of kappa tends to 1 as beta -> 0 (grid >> 1/beta)."""
+    prev = None
+    for beta in [0.4, 0.1, 0.03]:
+        n = int(40 / beta)
+        s2 = _full_sum(oracle.kappa((n, n), beta))
+        assert abs(s2 - 1) < 2 * beta ** 2 * (np.log(1 / beta) + 2)
+        if prev is not None:
+            assert abs(s2 - 1) < abs(prev - 1)
+        prev = s2
+    beta = 0.15
+    n = int(30 / beta)
+    s3 = _full_sum(oracle.kappa((n, n, n), beta))
+    assert abs(s3 - 1) < 2 * beta ** 2 * 3
+
+
+def test_kernel_spectrum_low_frequencies():
+    """Fourier transform of the screened Poisson equation: the normalised
+    spectrum is 1/(1 + (hbar w/ftilde)^2) = 1/(1 + (2 pi k/(M beta))^2)."""
+    beta = 0.02
+    n = 1024
+    g = oracle.ghat((n, n), beta)
+    M = 2 * n
+    for k0, k1 in [(0, 0), (1, 0), (0, 3), (2, 2), (5, 1)]:
+        w2 = (2 * np.pi / (M * beta)) ** 2 * (k0 * k0 + k1 * k1)
+        assert abs(g[k0, k1] * (1 + w2) - 1) < 2e-3
+    # real, even kernel: the spectrum the oracle returns is real by
+    # construction; check evenness via numpy on a small case
+    dims = (6, 9)
+    b = 0.4
+    kap = oracle.kappa(dims, b)
+    M0, M1 = oracle.pad_sizes(dims)
+    full = np.zeros((M0, M1))
+    for a in range(-(dims[0] - 1), dims[0]):
+        for c in range(-(dims[1] - 1), dims[1]):
+            full[a % M0, c % M1] = kap[abs(a), abs(c)]
+    F = np.fft.fft2(full)
+    assert np.max(np.abs(F.imag)) < 1e-14
+    assert np.allclose(oracle.ghat(dims, b), F.real[: M0 // 2 + 1, : M1 // 2 + 1],
+                       rtol=0, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Convolution: FFT route == direct definition; brute force on a tiny grid
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dims", [(8, 8), (12, 20), (13, 5), (8, 8, 8), (5, 7, 6)])
+def test_fft_convolution_equals_direct(dims):
+    rng = np.random.default_rng(sum(dims))
+    x = rng.standard_normal(dims)
+    a = oracle.conv(x, 0.35, "fft")
+    b = oracle.conv(x, 0.35, "direct")
+    assert np.max(np.abs(a - b)) < 1e-13 * np.max(np.abs(b))
+
+
+def test_first_term_brute_force():
+    """phi_1 on a 4x5 grid from the definitions, in physical units, with
+    scipy's K0 and quadrature for the cell average: checks kernel, h^D,
+    gamma, phi_0 and the alternating sum of two terms."""
+    rng = np.random.default_rng(7)
+    f = rng.uniform(1.0, 2.0, (4, 5))
+    src = np.array([[1, 3]], np.int32)
+    h, hbar = 0.1, 0.2
+    out = oracle.solve(f, src, h, hbar, 1, want_terms=True)
+    ft = np.sqrt(0.5 * (f.min() ** 2 + f.max() ** 2))
+    P = np.array([[i, j] for i in range(4) for j in range(5)], float) * h
+    y = src[0] * h
+    phi0 = np.exp(-ft * np.linalg.norm(P - y, axis=1) / hbar)
+    r0 = h / np.sqrt(np.pi)
+    G0 = quad(lambda r: r * sp.k0(ft * r / hbar) / hbar ** 2, 0, r0,
+              epsabs=1e-300, epsrel=1e-12, limit=400)[0] / h ** 2  # cell mean
+    phi1 = np.zeros(20)
+    for a in range(20):
+        for b in range(20):
+            r = np.linalg.norm(P[a] - P[b])
+            G = G0 if r == 0 else sp.k0(ft * r / hbar) / (2 * np.pi * hbar ** 2)
+            phi1[a] += G * (f.ravel()[b] ** 2 - ft ** 2) * phi0[b] * h * h
+    assert np.allclose(out["terms"][0].ravel(), phi0, rtol=1e-14, atol=0)
+    assert np.allclose(out["terms"][1].ravel(), phi1, rtol=1e-11, atol=1e-300)
+    assert np.allclose(out["S"].ravel(), -hbar * np.log(phi0 - phi1), rtol=1e-11)
+
+
+# --------------------------------------------------------------------------
+# Closed forms, invariances, linearity (Sections 3 and 5)
+# --------------------------------------------------------------------------
+
+def test_constant_forcing_closed_form():
+    """f = c: gamma = 0 so phi_i = 0 for i >= 1 (end of Section 5) and
+    S = -hbar ln sum_k exp(-c |x - y_k|/hbar) (eq. STilde, C = 1), which
+    lies between c d_min - hbar ln K and c d_min (Euclidean distance)."""
+    n, c, h, hbar = 40, 1.7, 1 / 40, 0.02
+    f = np.full((n, n), c)
+    src = np.array([[5, 7], [30, 22], [12, 35]], np.int32)
+    S = oracle.solve(f, src, h, hbar, 5)["S"]
+    g = np.stack(np.meshgrid(np.arange(n), np.arange(n), indexing="ij"), -1) * h
+    d = np.stack([np.linalg.norm(g - s * h, axis=-1) for s in src])
+    ref = -hbar * np.log(np.sum(np.exp(-c * d / hbar), axis=0))
+    assert np.max(np.abs(S - ref)) < 1e-12
+    dmin = d.min(axis=0)
+    assert np.all(S <= c * dmin + 1e-12)
+    assert np.all(S >= c * dmin - hbar * np.log(len(src)) - 1e-12)
+    # 3D as well
+    f3 = np.full((9, 8, 7), 0.8)
+    s3 = np.array([[4, 4, 3]], np.int32)
+    S3 = oracle.solve(f3, s3, 0.1, 0.05, 3)["S"]
+    g3 = np.stack(np.meshgrid(*[np.arange(k) for k in f3.shape], indexing="ij"), -1)
+    assert np.allclose(S3, 0.8 * np.linalg.norm(g3 - s3[0], axis=-1) * 0.1,
+                       rtol=0, atol=1e-12)
+
+
+def test_grid_rescaling_invariance():
+    """Example 4's remark: shrinking the grid by tau equals scaling f by
+    1/tau; and S(h, a f, a hbar) = a S(h, f, hbar).  Both hold exactly for
+    the discrete method, which depends on beta and gamma only."""
+    p = workloads.problem(1, 24)
+    f = p.f.astype(np.float64)
+    base = oracle.solve(f, p.src, 0.05, 0.1, 4)["S"]
+    tau = 4.0
+    a = oracle.solve(f, p.src, 0.05 * tau, 0.1, 4)["S"]
+    b = oracle.solve(f * tau, p.src, 0.05, 0.1, 4)["S"]
+    assert np.max(np.abs(a - b)) < 1e-12 * np.max(np.abs(a))
+    c = oracle.solve(f * 3.0, p.src, 0.05, 0.3, 4)["S"]
+    assert np.max(np.abs(c - 3.0 * base)) < 1e-12 * np.max(np.abs(c))
+
+
+def test_axis_flips_and_permutation_commute():
+    """kappa is even and isotropic: flipping or permuting axes of (f, Y)
+    commutes with the solve."""
+    rng = np.random.default_rng(3)
+    f = rng.uniform(1, 2, (10, 13))
+    src = np.array([[2, 3], [7, 11]], np.int32)
+    S = oracle.solve(f, src, 0.1, 0.1, 3)["S"]
+    Sf = oracle.solve(f[::-1, :], np.stack([9 - src[:, 0], src[:, 1]], 1).astype(np.int32),
+                      0.1, 0.1, 3)["S"]
+    St = oracle.solve(f.T, src[:, ::-1].copy(), 0.1, 0.1, 3)["S"]
+    assert np.allclose(Sf[::-1, :], S, rtol=1e-13, atol=1e-14)
+    assert np.allclose(St.T, S, rtol=1e-13, atol=1e-14)
+
+
+def test_superposition_over_sources():
+    """The screened Poisson equation is linear in its source term: at fixed
+    ftilde, phi(Y1 u Y2) = phi(Y1) + phi(Y2)."""
+    rng = np.random.default_rng(5)
+    f = rng.uniform(1, 1.6, (16, 11))
+    y1 = np.array([[3, 4]], np.int32)
+    y2 = np.array([[12, 2], [8, 9]], np.int32)
+    kw = dict(h=0.1, hbar=0.15, T=5, ft_mode="given", ftilde=1.4)
+    p1 = oracle.solve(f, y1, **kw)["phi"]
+    p2 = oracle.solve(f, y2, **kw)["phi"]
+    p12 = oracle.solve(f, np.concatenate([y1, y2]), **kw)["phi"]
+    assert np.allclose(p12, p1 + p2, rtol=1e-13, atol=0)
+
+
+# --------------------------------------------------------------------------
+# Convergence bounds of Section 5 / 5.1
+# --------------------------------------------------------------------------
+
+def test_operator_norm_bound_and_dense_limit():
+    """||phi_i|| <= c ||phi_{i-1}|| with c = max|Ghat| max|gamma| (the
+    discrete form of eq. OperatorNormUpperBound), and the truncated series
+    approaches the dense solution of (I + K diag gamma) phi = phi_0 with the
+    tail bound c^(T+1)/(1-c) ||phi_0|| (eq. OperatorNormDiff)."""
+    rng = np.random.default_rng(11)
+    f = 1.0 + 0.8 * rng.uniform(0, 1, (14, 17))
+    src = np.array([[6, 8]], np.int32)
+    h, hbar = 1 / 16, 0.08
+    for mode in ["nu", "fmax"]:
+        T = 12
+        out = oracle.solve(f, src, h, hbar, T, ft_mode=mode, want_terms=True)
+        beta = out["info"]["beta"]
+        c = np.max(np.abs(oracle.ghat(f.shape, beta))) * out["info"]["c0_bound"]
+        assert c < 1
+        # the analytic bound sup|f^2 - ft^2|/ft^2 < 1 (Section 5.1)
+        assert out["info"]["c0_bound"] < 1
+        nrm = [np.linalg.norm(t) for t in out["terms"]]
+        for i in range(1, T + 1):
+            assert nrm[i] <= c * nrm[i - 1] * (1 + 1e-12)
+        phi_inf, p0, _, _ = oracle.dense_limit(f, src, h, hbar, ft_mode=mode)
+        for Tt in range(0, T + 1):
+            part = sum((-1) ** i * out["terms"][i] for i in range(Tt + 1))
+            assert np.linalg.norm(part - phi_inf) <= \
+                c ** (Tt + 1) / (1 - c) * np.linalg.norm(p0) * (1 + 1e-9) + 1e-13
+
+
+def test_nu_minimises_the_bound():
+    """Section 5.1: F(ft) = sup|f^2 - ft^2|/ft^2 is minimal at
+    ft = sqrt((fmin^2 + fmax^2)/2)."""
+    f = workloads.problem(2, 64).f.astype(np.float64)
+    nu = oracle.solve(f, np.array([[3, 3]], np.int32), 1 / 64, 0.05, 0)["info"]
+    F = lambda ft: np.max(np.abs(f ** 2 - ft ** 2)) / ft ** 2
+    assert abs(nu["c0_bound"] - F(nu["ftilde"])) < 1e-14
+    for ft in np.linspace(nu["fmin"], nu["fmax"] * 1.2, 50):
+        assert F(ft) >= nu["c0_bound"] - 1e-14
+
+
+def test_fmax_series_is_monotone():
+    """With ftilde = sup f, gamma <= 0 and kappa > 0, so every (-1)^i phi_i
+    is >= 0: partial sums increase and S decreases with T."""
+    p = workloads.problem(2, 48)
+    f = p.f.astype(np.float64)
+    out = oracle.solve(f, p.src, p.h, p.hbar, 10, ft_mode="fmax", want_terms=True)
+    part = np.zeros_like(f)
+    prevS = None
+    for i, t in enumerate(out["terms"]):
+        assert np.all((-1) ** i * t >= 0)
+        part = part + (-1) ** i * t
+        S = -p.hbar * np.log(part)
+        if prevS is not None:
+            assert np.all(S <= prevS + 1e-15)
+        prevS = S
+
+
+# --------------------------------------------------------------------------
+# The paper's Example 1 (Table 2)
+# --------------------------------------------------------------------------
+
+def test_example1_table2_decrements():
+    """Example 1: exact R = exp(r) - 1.  The per-iteration improvement of the
+    percentage error printed in Table 2 is reproduced to 0.005 points.  The
+    absolute level is not pinned (the paper's multiprecision settings and
+    remaining details are not stated)."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "example1_table2.txt"))
+    n, c, h, hbar = 257, 128, 2.0 ** -10, 0.006
+    i = (np.arange(n) - c) * h
+    r = np.hypot(i[:, None], i[None, :])
+    f = np.exp(r)
+    R = np.exp(r) - 1
+    out = oracle.solve(f, np.array([[c, c]], np.int32), h, hbar, 6, want_terms=True)
+    m = R > 0
+    part = out["terms"][0].copy()
+    errs, maxd = [], []
+    for T in range(1, 7):
+        part = part + (-1) ** T * out["terms"][T]
+        S = -hbar * np.log(part)
+        errs.append(100 * np.mean(np.abs(S - R)[m] / R[m]))
+        maxd.append(np.max(np.abs(S - R)))
+    dec = -np.diff(errs)
+    dec_paper = -np.diff(rows[:, 1])
+    assert np.all(np.abs(dec - dec_paper) < 0.005), (dec, dec_paper)
+    # errors fall with T and settle like the printed column
+    assert errs[-1] < errs[0] and abs(errs[-1] - errs[-2]) < 0.002
+    # max difference is of the printed size (same order, within 25%)
+    assert np.all(np.abs(np.array(maxd) / rows[:, 2] - 1) < 0.25)
+
+
+# --------------------------------------------------------------------------
+# Adjoint (reverse sweep of the recurrence; ftilde held fixed)
+# --------------------------------------------------------------------------
+
+def test_convolution_is_self_adjoint():
+    rng = np.random.default_rng(2)
+    for dims in [(9, 14), (5, 6, 7)]:
+        u = rng.standard_normal(dims)
+        v = rng.standard_normal(dims)
+        lhs = np.sum(oracle.conv(u, 0.3) * v)
+        rhs = np.sum(u * oracle.conv(v, 0.3))
+        assert abs(lhs - rhs) < 1e-13 * np.sqrt(np.sum(u * u) * np.sum(v * v))
+
+
+@pytest.mark.parametrize("dims", [(12, 10), (6, 5, 7)])
+def test_adjoint_matches_finite_differences(dims):
+    rng = np.random.default_rng(len(dims))
+    f = rng.uniform(1.0, 2.0, dims)
+    src = np.array([[d // 3 for d in dims]], np.int32)
+    h, hbar, T = 1.0 / max(dims), 0.12, 6
+    ft = float(np.sqrt(0.5 * (f.min() ** 2 + f.max() ** 2)))
+    w = rng.standard_normal(dims)
+
+    def loss(ff):
+        S = oracle.solve(ff, src, h, hbar, T, ft_mode="given", ftilde=ft)["S"]
+        return 0.5 * np.sum(w * S * S)
+
+    S = oracle.solve(f, src, h, hbar, T, ft_mode="given", ftilde=ft)["S"]
+    g, _ = oracle.adjoint(f, src, h, hbar, T, w * S, ft_mode="given", ftilde=ft)
+    for trial in range(4):
+        d = rng.standard_normal(dims)
+        eps = 1e-5
+        fd = (loss(f + eps * d) - loss(f - eps * d)) / (2 * eps)
+        an = np.sum(g * d)
+        assert abs(fd - an) <= 1e-6 * abs(an) + 1e-12
+    for trial in range(4):
+        idx = tuple(int(rng.integers(0, n)) for n in dims)
+        e = np.zeros(dims)
+        e[idx] = 1
+        eps = 1e-5
+        fd = (loss(f + eps * e) - loss(f - eps * e)) / (2 * eps)
+        assert abs(fd - g[idx]) <= 1e-6 * abs(g[idx]) + 1e-10
+
+
+def test_zero_terms_gives_phi0_and_zero_gradient():
+    f = np.full((6, 7), 1.3)
+    f[2, 3] = 1.9
+    src = np.array([[1, 1]], np.int32)
+    out = oracle.solve(f, src, 0.2, 0.3, 0, want_terms=True)
+    assert np.array_equal(out["phi"], out["terms"][0])
+    g, _ = oracle.adjoint(f, src, 0.2, 0.3, 0, np.ones_like(f))
+    assert np.all(g == 0)
+
+
+def test_invalid_arguments_rejected():
+    f = np.ones((4, 4))
+    with pytest.raises(ValueError):
+        oracle.solve(f, np.array([[4, 0]], np.int32), 0.1, 0.1, 2)
+    with pytest.raises(ValueError):
+        oracle.solve(f, np.array([[0, 0]], np.int32), -0.1, 0.1, 2)
+    with pytest.raises(ValueError):
+        oracle.solve(-f, np.array([[0, 0]], np.int32), 0.1, 0.1, 2)
