@@ -1,0 +1,206 @@
+/*
+ * sweik.h -- C ABI of the MI355X (gfx950) linearised eikonal solver.
+ *
+ * The solver computes the viscosity-regularised distance S on a regular grid
+ * from a positive forcing f and a point set {y_k} with S(y_k) = 0, by the
+ * perturbation method of the paper (Section 5, algorithm in Table 1):
+ *
+ *   ftilde   reference forcing (Section 5.1): nu = sqrt((fmin^2+fmax^2)/2),
+ *            sup f, or a caller value
+ *   phi_0    = sum_k exp(-ftilde |x - y_k| / hbar)       (eq. phi_0Solution)
+ *   phi_i    = h^D G (*) ((f^2 - ftilde^2) phi_{i-1}),  i = 1..T,  with the
+ *            screened-Poisson Green's function G of eq. GreensFunction2D /
+ *            GreensFunction3D; a linear (zero-padded) convolution over the
+ *            grid, evaluated by FFT (eqs. phiRecRelation, phi_i_Solution and
+ *            Section 5.2)
+ *   phi      = sum_{i=0..T} (-1)^i phi_i                   (eq. phiSolution)
+ *   S        = -hbar ln phi                                 (eq. SfromPhi)
+ *
+ * The value of G at the singular origin is its average over the ball of one
+ * cell's volume.  Points where phi <= 0 get S = +inf and are counted.
+ *
+ * Conventions
+ *   - Arrays are C order (last index fastest).  Grid point index m has
+ *     position h*m.  Sources are distinct grid indices, int32 [n_src][ndim].
+ *   - Every pointer passed to a solve is DEVICE memory owned by the caller,
+ *     except where marked host.  The library allocates no device memory and
+ *     never synchronises the stream: all work is enqueued on `stream`
+ *     (a hipStream_t; NULL = the default stream).  A solve can therefore be
+ *     captured into a HIP graph.
+ *   - Precision SWEIK_F32_SCALED: f and S are float32; FFTs run in float32
+ *     on power-of-two-rescaled series terms; the series is accumulated and
+ *     the logarithm taken in float64.  SWEIK_F64: everything float64.
+ *   - Errors in arguments are reported synchronously through the return
+ *     value before anything is enqueued.  Errors in the data (f <= 0, NaN or
+ *     Inf in f, a source outside the grid) are reported asynchronously in
+ *     the device-side sweik_info.flags.
+ *   - Plans are immutable after creation and may be shared by concurrent
+ *     solves that use distinct workspaces.
+ */
+#ifndef SWEIK_H
+#define SWEIK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SWEIK_ABI_VERSION 1
+#define SWEIK_MAX_TERMS 64 /* largest T */
+
+typedef enum {
+  SWEIK_OK = 0,
+  SWEIK_EINVAL = 1,       /* invalid argument */
+  SWEIK_EUNSUPPORTED = 2, /* valid but not supported (dimension, size) */
+  SWEIK_EWORKSPACE = 3,   /* workspace or checkpoint buffer too small */
+  SWEIK_EDEVICE = 4,      /* a HIP call failed */
+  SWEIK_ENOMEM = 5        /* host allocation failed */
+} sweik_status;
+
+typedef enum { SWEIK_F32_SCALED = 0, SWEIK_F64 = 1 } sweik_precision;
+
+typedef enum {
+  SWEIK_FT_NU = 0,    /* sqrt((fmin^2 + fmax^2)/2), Section 5.1 optimum */
+  SWEIK_FT_FMAX = 1,  /* sup f: every term has one sign (Section 5.1) */
+  SWEIK_FT_GIVEN = 2  /* the value in sweik_problem.ftilde */
+} sweik_ftilde_mode;
+
+/* Bits of sweik_info.flags */
+#define SWEIK_FLAG_F_NONFINITE 1   /* f holds NaN or Inf */
+#define SWEIK_FLAG_F_NONPOSITIVE 2 /* f holds a value <= 0 */
+#define SWEIK_FLAG_C0_GE_1 4       /* sup|f^2-ftilde^2|/ftilde^2 >= 1 */
+#define SWEIK_FLAG_BAD_SOURCE 8    /* a source lies outside the grid */
+
+typedef struct {
+  int32_t ndim;      /* 2 or 3 */
+  int64_t dims[3];   /* grid points per axis, each >= 2 (dims[2] unused in 2D) */
+  double h;          /* grid spacing > 0 */
+  double hbar;       /* > 0 */
+  int32_t T;         /* number of correction terms, 0..SWEIK_MAX_TERMS */
+  int32_t n_src;     /* >= 1 */
+  int32_t prec;      /* sweik_precision */
+  int32_t ft_mode;   /* sweik_ftilde_mode */
+  double ftilde;     /* used when ft_mode == SWEIK_FT_GIVEN; > 0 */
+} sweik_problem;
+
+/* Written on the device by every solve (when info is non-NULL); read it
+ * after synchronising the stream. */
+typedef struct {
+  double f_min, f_max;
+  double ftilde;
+  double beta;      /* ftilde h / hbar: decay per cell */
+  double c0_bound;  /* sup|f^2 - ftilde^2| / ftilde^2 (eq. OperatorNormUpperBound) */
+  int64_t n_nonpositive_phi; /* points with phi <= 0 (S = +inf) */
+  int32_t flags;    /* SWEIK_FLAG_* */
+  int32_t T;
+  int32_t scale_exp[SWEIK_MAX_TERMS + 1]; /* term i is stored as 2^scale_exp[i] * m_i */
+} sweik_info;
+
+typedef struct sweik_plan_s *sweik_plan;
+
+/* Validate a problem and choose the kernel schedule.  Host only: makes no
+ * HIP call.  Returns SWEIK_EINVAL for invalid fields, SWEIK_EUNSUPPORTED for
+ * grids beyond the supported sizes (padded FFT length per axis <= 8192 in
+ * 2D and <= 1024 in 3D). */
+sweik_status sweik_plan_create(const sweik_problem *problem, sweik_plan *out);
+void sweik_plan_destroy(sweik_plan plan);
+
+/* Bytes of device workspace a solve (and an adjoint) needs. */
+size_t sweik_workspace_bytes(sweik_plan plan);
+/* Bytes of the checkpoint buffer a solve writes for a later adjoint. */
+size_t sweik_checkpoint_bytes(sweik_plan plan);
+/* Padded FFT sizes per axis (out[0..2]); returns ndim. */
+int32_t sweik_plan_padded_dims(sweik_plan plan, int64_t *out);
+
+/* Host-side check of a host copy of the source list: SWEIK_EINVAL when a
+ * source lies outside the grid or two sources coincide. */
+sweik_status sweik_check_sources(sweik_plan plan, const int32_t *src_host);
+
+/* Forward solve (Table 1).
+ *   f      device, dims, float32 (F32_SCALED) or float64 (F64)
+ *   src    device, int32 [n_src][ndim]
+ *   S      device, dims, same type as f (output)
+ *   ws     device workspace of ws_bytes >= sweik_workspace_bytes(plan)
+ *   ckpt   device, nullable: when given, the series terms and phi are kept
+ *          for sweik_solve_adjoint (sweik_checkpoint_bytes(plan) bytes)
+ *   stream hipStream_t
+ *   info   device, nullable: sweik_info written asynchronously */
+sweik_status sweik_solve(sweik_plan plan, const void *f, const int32_t *src,
+                         void *S, void *ws, size_t ws_bytes, void *ckpt,
+                         void *stream, sweik_info *info);
+
+/* Adjoint of the solve with ftilde held fixed (reverse sweep of the
+ * recurrence eq. phiRecRelation; the kernel is even, so the transposed
+ * convolution is the convolution itself).
+ *   dLdS   device, dims, same type as f: gradient of a loss w.r.t. S
+ *   dLdf   device, dims, same type as f (output)
+ *   ckpt   the checkpoint written by sweik_solve for the same f and src */
+sweik_status sweik_solve_adjoint(sweik_plan plan, const void *f,
+                                 const int32_t *src, const void *ckpt,
+                                 const void *dLdS, void *dLdf, void *ws,
+                                 size_t ws_bytes, void *stream);
+
+/* ---- measurement ---------------------------------------------------------
+ * Kernel classes of a solve, for sweik_solve_timed. */
+enum {
+  SWEIK_KC_PREP = 0,      /* reduction of f, twiddle table */
+  SWEIK_KC_GHAT_ROW = 1,  /* kernel table rows + real FFT */
+  SWEIK_KC_GHAT_COL = 2,  /* kernel spectrum columns */
+  SWEIK_KC_PHI0_ROW = 3,  /* phi_0, first forcing term, real FFT */
+  SWEIK_KC_CONV_COL = 4,  /* column FFT * kernel spectrum * inverse FFT */
+  SWEIK_KC_TERM_ROW = 5,  /* inverse real FFT, accumulate, next forcing, real FFT */
+  SWEIK_KC_LAST_ROW = 6,  /* inverse real FFT, accumulate, S = -hbar ln phi */
+  SWEIK_KC_COUNT = 7
+};
+
+/* Same work as sweik_solve (2D, no checkpoint, no info) with a HIP event
+ * recorded on `stream` before and after every kernel.  Synchronises the
+ * stream, then writes to the HOST arrays ms[SWEIK_KC_COUNT] (summed kernel
+ * milliseconds per class) and count[SWEIK_KC_COUNT] (launches per class).
+ * For benchmarks: the events add a little time between launches. */
+sweik_status sweik_solve_timed(sweik_plan plan, const void *f, const int32_t *src,
+                               void *S, void *ws, size_t ws_bytes, void *stream,
+                               float *ms, int32_t *count);
+
+/* ---- uneven batches of independent 2D problems ------------------------ */
+typedef struct sweik_batch_s *sweik_batch;
+
+/* All problems must be 2D with the same precision and the same T. */
+sweik_status sweik_batch_create(const sweik_problem *problems, int32_t count,
+                                sweik_batch *out);
+void sweik_batch_destroy(sweik_batch batch);
+size_t sweik_batch_workspace_bytes(sweik_batch batch);
+
+/* f, src, S: HOST arrays of `count` device pointers.  infos: device array of
+ * `count` sweik_info (nullable). */
+sweik_status sweik_batch_solve(sweik_batch batch, const void *const *f,
+                               const int32_t *const *src, void *const *S,
+                               void *ws, size_t ws_bytes, void *stream,
+                               sweik_info *infos);
+
+/* Same work, captured once into a HIP graph owned by the batch and replayed
+ * on later calls with the same pointers (a call with other pointers
+ * re-captures). */
+sweik_status sweik_batch_solve_graph(sweik_batch batch, const void *const *f,
+                                     const int32_t *const *src,
+                                     void *const *S, void *ws,
+                                     size_t ws_bytes, void *stream,
+                                     sweik_info *infos);
+
+/* ---- schedule tuning ---------------------------------------------------- */
+/* Times the candidate tile schedules of every pass of `plan` on `stream`
+ * using `ws` (synchronises the stream) and keeps the fastest in the plan and
+ * in a process-wide table keyed by (pass, length, precision), which later
+ * plans use.  Returns the number of schedules timed. */
+int32_t sweik_autotune(sweik_plan plan, void *ws, size_t ws_bytes,
+                       void *stream);
+
+const char *sweik_status_string(sweik_status s);
+int32_t sweik_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SWEIK_H */

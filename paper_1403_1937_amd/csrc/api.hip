@@ -1,0 +1,392 @@
+// api.hip -- C ABI of the gfx950 eikonal solver: validation, plans, workspace
+// layout and the launch sequence of a solve.  See include/sweik.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <set>
+#include <tuple>
+
+#include "solve2d.hpp"
+#include "plan.hpp"
+
+using namespace sweik;
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr size_t kLdsPreferred = 65536;  // per work-group, for occupancy
+constexpr size_t kLdsDevice = 163840;    // gfx950 limit per work-group
+
+int64_t next_pow2(int64_t m) {
+  int64_t p = 1;
+  while (p < m) p <<= 1;
+  return p;
+}
+int ilog2(int64_t x) {
+  int l = 0;
+  while ((int64_t(1) << l) < x) ++l;
+  return l;
+}
+
+}  // namespace
+
+namespace sweik {
+
+sweik_status validate_problem(const sweik_problem *p) {
+  if (!p) return SWEIK_EINVAL;
+  if (p->ndim != 2 && p->ndim != 3) return SWEIK_EINVAL;
+  for (int d = 0; d < p->ndim; ++d)
+    if (p->dims[d] < 2) return SWEIK_EINVAL;
+  if (!(p->h > 0) || !(p->hbar > 0) || !std::isfinite(p->h) || !std::isfinite(p->hbar))
+    return SWEIK_EINVAL;
+  if (p->T < 0 || p->T > SWEIK_MAX_TERMS) return SWEIK_EINVAL;
+  if (p->n_src < 1) return SWEIK_EINVAL;
+  if (p->prec != SWEIK_F32_SCALED && p->prec != SWEIK_F64) return SWEIK_EINVAL;
+  if (p->ft_mode != SWEIK_FT_NU && p->ft_mode != SWEIK_FT_FMAX && p->ft_mode != SWEIK_FT_GIVEN)
+    return SWEIK_EINVAL;
+  if (p->ft_mode == SWEIK_FT_GIVEN && !(p->ftilde > 0 && std::isfinite(p->ftilde)))
+    return SWEIK_EINVAL;
+  return SWEIK_OK;
+}
+
+// Schedule and workspace layout of a 2D problem.
+sweik_status plan2d(sweik_plan_s *pl) {
+  const sweik_problem &p = pl->p;
+  const int esz = p.prec == SWEIK_F64 ? 8 : 4;
+  const int csz = 2 * esz;
+  Geo2 &g = pl->g2;
+  g.n0 = (int)p.dims[0];
+  g.n1 = (int)p.dims[1];
+  const int64_t M0 = std::max<int64_t>(64, next_pow2(2 * p.dims[0] - 1));
+  const int64_t M1 = std::max<int64_t>(64, next_pow2(2 * p.dims[1] - 1));
+  if (M0 > 4096 || M1 > 8192) return SWEIK_EUNSUPPORTED;
+  g.M0 = (int)M0;
+  g.H0 = (int)(M0 / 2);
+  g.ldg = g.H0 + 1;
+  g.H1 = (int)(M1 / 2);
+  g.ldk = g.H1 + 1;
+  g.RB = p.prec == SWEIK_F64 ? 2 : 4;
+  g.nb = (g.n0 + g.RB - 1) / g.RB;
+  // row pass: teams of H1/16 threads, up to 256 threads per work-group
+  // Lines per work-group: 256 threads, fewer while the LDS lines exceed the
+  // preferred 64 KB, but always whole wavefronts; a single line may use up
+  // to the device limit.
+  auto lines_per_wg = [&](int P, int L) {
+    int n = std::max(1, 256 / P);
+    const size_t line = (size_t)lds_line_len(L) * csz;
+    while (n > 1 && n * line > kLdsPreferred && (n / 2) * P >= 64) n /= 2;
+    return n;
+  };
+  const int Pr = g.H1 / 16;
+  g.rpw = lines_per_wg(Pr, g.H1);
+  if ((size_t)g.rpw * lds_line_len(g.H1) * csz > pl->lds_max) return SWEIK_EUNSUPPORTED;
+  const int Pc = g.M0 / 16;
+  g.cpw = lines_per_wg(Pc, g.M0);
+  if ((size_t)g.cpw * lds_line_len(g.M0) * csz > pl->lds_max) return SWEIK_EUNSUPPORTED;
+  if ((g.rpw * Pr) % 64 || (g.cpw * Pc) % 64) return SWEIK_EUNSUPPORTED;
+  const int spec_rows = g.nb * g.RB;
+  g.nbr = (spec_rows + g.rpw - 1) / g.rpw;
+  g.ncw = (g.ldk + g.cpw - 1) / g.cpw;
+  g.lmax = (int)std::max(M0, M1);
+  g.lmax_log = ilog2(g.lmax);
+  pl->padded[0] = M0;
+  pl->padded[1] = M1;
+  pl->padded[2] = 1;
+
+  // workspace
+  const int64_t N = (int64_t)g.n0 * g.n1;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  Layout &L = pl->ws;
+  L.par = take(sizeof(Params));
+  L.red = take(sizeof(double) * 3 * kRedBlocks);
+  L.expo = take(sizeof(int) * (SWEIK_MAX_TERMS + 1));
+  L.mu = take(sizeof(double) * (size_t)(p.T + 1) * g.nbr);
+  L.tw = take((size_t)csz * g.lmax);
+  L.g = take((size_t)esz * g.ldk * g.ldg);
+  L.spec = take((size_t)csz * g.nb * g.ldk * g.RB);
+  L.acc = take(sizeof(double) * N);
+  L.total = off;
+  off = 0;
+  L.ck_expo = take(sizeof(int) * (SWEIK_MAX_TERMS + 1));
+  L.ck_phi = take(sizeof(double) * N);
+  L.ck_terms = take((size_t)esz * N * (size_t)p.T);
+  L.ck_total = off;
+  return SWEIK_OK;
+}
+
+template <typename R>
+Args2<R> make_args2(const sweik_plan_s *pl, const void *f, const int32_t *src, void *S,
+                    void *ws, void *ckpt, sweik_info *info) {
+  const Geo2 &g = pl->g2;
+  const sweik_problem &p = pl->p;
+  const Layout &L = pl->ws;
+  char *w = (char *)ws;
+  Args2<R> a;
+  a.n0 = g.n0;
+  a.n1 = g.n1;
+  a.H1 = g.H1;
+  a.ldk = g.ldk;
+  a.M0 = g.M0;
+  a.H0 = g.H0;
+  a.ldg = g.ldg;
+  a.RB = g.RB;
+  a.nb = g.nb;
+  a.rpw = g.rpw;
+  a.cpw = g.cpw;
+  a.nbr = g.nbr;
+  a.lmax_log = g.lmax_log;
+  a.T = p.T;
+  a.n_src = p.n_src;
+  a.ft_mode = p.ft_mode;
+  a.ftilde_given = p.ftilde;
+  a.h = p.h;
+  a.hbar = p.hbar;
+  a.f = (const R *)f;
+  a.src = src;
+  a.S = (R *)S;
+  a.par = (Params *)(w + L.par);
+  a.red = (double *)(w + L.red);
+  a.mu = (double *)(w + L.mu);
+  a.expo = (int *)(w + L.expo);
+  a.tw = (const cplx<R> *)(w + L.tw);
+  a.spec = (cplx<R> *)(w + L.spec);
+  a.g = (R *)(w + L.g);
+  a.acc = (double *)(w + L.acc);
+  a.info = info;
+  char *c = (char *)ckpt;
+  a.ck_expo = c ? (int *)(c + L.ck_expo) : nullptr;
+  a.ck_phi = c ? (double *)(c + L.ck_phi) : nullptr;
+  a.ck_terms = c ? (R *)(c + L.ck_terms) : nullptr;
+  return a;
+}
+
+// Kernels whose dynamic LDS exceeds 64 KB must be allowed to use more.
+template <typename K> bool allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return true;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
+// Optional per-kernel timing: events recorded on the solve's stream before
+// and after every launch; durations are summed per kernel class.
+struct KernelTimer {
+  static constexpr int kMax = 2 * (SWEIK_MAX_TERMS + 4) + 8;
+  hipEvent_t ev[2 * kMax];
+  int cls[kMax];
+  int n = 0;
+  bool ok = true;
+  KernelTimer() {
+    for (int i = 0; i < 2 * kMax; ++i)
+      if (hipEventCreate(&ev[i]) != hipSuccess) ok = false;
+  }
+  ~KernelTimer() {
+    for (int i = 0; i < 2 * kMax; ++i) (void)hipEventDestroy(ev[i]);
+  }
+};
+
+template <typename R>
+sweik_status enqueue2d(const sweik_plan_s *pl, const void *f, const int32_t *src, void *S,
+                       void *ws, void *ckpt, hipStream_t st, sweik_info *info,
+                       KernelTimer *tm = nullptr) {
+  const Geo2 &g = pl->g2;
+  Args2<R> a = make_args2<R>(pl, f, src, S, ws, ckpt, info);
+  const int csz = 2 * sizeof(R);
+  const size_t lds_row = (size_t)g.rpw * lds_line_len(g.H1) * csz;
+  const size_t lds_col = (size_t)g.cpw * lds_line_len(g.M0) * csz;
+  const int thr_row = g.rpw * (g.H1 / 16);
+  const int thr_col = g.cpw * (g.M0 / 16);
+  const long long N = (long long)g.n0 * g.n1;
+  if (!allow_lds(k_row2<R, ROW_GHAT>, lds_row) || !allow_lds(k_row2<R, ROW_PHI0>, lds_row) ||
+      !allow_lds(k_row2<R, ROW_TERM>, lds_row) || !allow_lds(k_col2<R, COL_GHAT>, lds_col) ||
+      !allow_lds(k_col2<R, COL_CONV>, lds_col))
+    return SWEIK_EUNSUPPORTED;
+  auto launch = [&](int cls, auto &&fn) {
+    if (tm && tm->n < KernelTimer::kMax) {
+      (void)hipEventRecord(tm->ev[2 * tm->n], st);
+      fn();
+      (void)hipEventRecord(tm->ev[2 * tm->n + 1], st);
+      tm->cls[tm->n++] = cls;
+    } else {
+      fn();
+    }
+  };
+  launch(SWEIK_KC_PREP, [&] {
+    hipLaunchKernelGGL(k_prep<R>, dim3(kRedBlocks), dim3(256), 0, st, (const R *)f, N, a.red,
+                       (cplx<R> *)a.tw, g.lmax);
+  });
+  launch(SWEIK_KC_GHAT_ROW, [&] {
+    hipLaunchKernelGGL((k_row2<R, ROW_GHAT>), dim3(g.nbr), dim3(thr_row), lds_row, st, a, 0);
+  });
+  launch(SWEIK_KC_GHAT_COL, [&] {
+    hipLaunchKernelGGL((k_col2<R, COL_GHAT>), dim3(g.ncw), dim3(thr_col), lds_col, st, a);
+  });
+  launch(SWEIK_KC_PHI0_ROW, [&] {
+    hipLaunchKernelGGL((k_row2<R, ROW_PHI0>), dim3(g.nbr), dim3(thr_row), lds_row, st, a, 0);
+  });
+  for (int i = 1; i <= pl->p.T; ++i) {
+    launch(SWEIK_KC_CONV_COL, [&] {
+      hipLaunchKernelGGL((k_col2<R, COL_CONV>), dim3(g.ncw), dim3(thr_col), lds_col, st, a);
+    });
+    launch(i == pl->p.T ? SWEIK_KC_LAST_ROW : SWEIK_KC_TERM_ROW, [&] {
+      hipLaunchKernelGGL((k_row2<R, ROW_TERM>), dim3(g.nbr), dim3(thr_row), lds_row, st, a, i);
+    });
+  }
+  return hipGetLastError() == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
+}
+
+}  // namespace sweik
+
+extern "C" {
+
+sweik_status sweik_plan_create(const sweik_problem *problem, sweik_plan *out) {
+  if (!out) return SWEIK_EINVAL;
+  *out = nullptr;
+  sweik_status st = validate_problem(problem);
+  if (st != SWEIK_OK) return st;
+  sweik_plan_s *pl = new (std::nothrow) sweik_plan_s();
+  if (!pl) return SWEIK_ENOMEM;
+  pl->p = *problem;
+  pl->lds_max = kLdsDevice;
+  if (problem->ndim == 2) {
+    st = plan2d(pl);
+  } else {
+    st = SWEIK_EUNSUPPORTED;
+  }
+  if (st != SWEIK_OK) {
+    delete pl;
+    return st;
+  }
+  *out = pl;
+  return SWEIK_OK;
+}
+
+void sweik_plan_destroy(sweik_plan plan) { delete plan; }
+
+size_t sweik_workspace_bytes(sweik_plan plan) { return plan ? plan->ws.total : 0; }
+size_t sweik_checkpoint_bytes(sweik_plan plan) { return plan ? plan->ws.ck_total : 0; }
+
+int32_t sweik_plan_padded_dims(sweik_plan plan, int64_t *out) {
+  if (!plan) return 0;
+  if (out)
+    for (int d = 0; d < 3; ++d) out[d] = plan->padded[d];
+  return plan->p.ndim;
+}
+
+sweik_status sweik_check_sources(sweik_plan plan, const int32_t *src) {
+  if (!plan || !src) return SWEIK_EINVAL;
+  const sweik_problem &p = plan->p;
+  std::set<std::tuple<int, int, int>> seen;
+  for (int k = 0; k < p.n_src; ++k) {
+    int c[3] = {0, 0, 0};
+    for (int d = 0; d < p.ndim; ++d) {
+      c[d] = src[k * p.ndim + d];
+      if (c[d] < 0 || c[d] >= p.dims[d]) return SWEIK_EINVAL;
+    }
+    if (!seen.insert(std::make_tuple(c[0], c[1], c[2])).second) return SWEIK_EINVAL;
+  }
+  return SWEIK_OK;
+}
+
+sweik_status sweik_solve(sweik_plan plan, const void *f, const int32_t *src, void *S, void *ws,
+                         size_t ws_bytes, void *ckpt, void *stream, sweik_info *info) {
+  if (!plan || !f || !src || !S || !ws) return SWEIK_EINVAL;
+  if (ws_bytes < plan->ws.total) return SWEIK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->p.ndim == 2) {
+    return plan->p.prec == SWEIK_F64
+               ? enqueue2d<double>(plan, f, src, S, ws, ckpt, st, info)
+               : enqueue2d<float>(plan, f, src, S, ws, ckpt, st, info);
+  }
+  return SWEIK_EUNSUPPORTED;
+}
+
+sweik_status sweik_solve_timed(sweik_plan plan, const void *f, const int32_t *src, void *S,
+                               void *ws, size_t ws_bytes, void *stream, float *ms,
+                               int32_t *count) {
+  if (!plan || !f || !src || !S || !ws || !ms || !count) return SWEIK_EINVAL;
+  if (ws_bytes < plan->ws.total) return SWEIK_EWORKSPACE;
+  if (plan->p.ndim != 2) return SWEIK_EUNSUPPORTED;
+  hipStream_t st = (hipStream_t)stream;
+  KernelTimer tm;
+  if (!tm.ok) return SWEIK_EDEVICE;
+  sweik_status rc = plan->p.prec == SWEIK_F64
+                        ? enqueue2d<double>(plan, f, src, S, ws, nullptr, st, nullptr, &tm)
+                        : enqueue2d<float>(plan, f, src, S, ws, nullptr, st, nullptr, &tm);
+  if (rc != SWEIK_OK) return rc;
+  if (hipStreamSynchronize(st) != hipSuccess) return SWEIK_EDEVICE;
+  for (int c = 0; c < SWEIK_KC_COUNT; ++c) {
+    ms[c] = 0.0f;
+    count[c] = 0;
+  }
+  for (int i = 0; i < tm.n; ++i) {
+    float t = 0.0f;
+    if (hipEventElapsedTime(&t, tm.ev[2 * i], tm.ev[2 * i + 1]) != hipSuccess)
+      return SWEIK_EDEVICE;
+    ms[tm.cls[i]] += t;
+    count[tm.cls[i]] += 1;
+  }
+  return SWEIK_OK;
+}
+
+sweik_status sweik_solve_adjoint(sweik_plan plan, const void *f, const int32_t *src,
+                                 const void *ckpt, const void *dLdS, void *dLdf, void *ws,
+                                 size_t ws_bytes, void *stream) {
+  (void)f; (void)src; (void)ckpt; (void)dLdS; (void)dLdf; (void)ws; (void)ws_bytes; (void)stream;
+  if (!plan) return SWEIK_EINVAL;
+  return SWEIK_EUNSUPPORTED;
+}
+
+sweik_status sweik_batch_create(const sweik_problem *problems, int32_t count, sweik_batch *out) {
+  (void)problems; (void)count;
+  if (out) *out = nullptr;
+  return SWEIK_EUNSUPPORTED;
+}
+void sweik_batch_destroy(sweik_batch batch) { (void)batch; }
+size_t sweik_batch_workspace_bytes(sweik_batch batch) { (void)batch; return 0; }
+sweik_status sweik_batch_solve(sweik_batch batch, const void *const *f, const int32_t *const *src,
+                               void *const *S, void *ws, size_t ws_bytes, void *stream,
+                               sweik_info *infos) {
+  (void)batch; (void)f; (void)src; (void)S; (void)ws; (void)ws_bytes; (void)stream; (void)infos;
+  return SWEIK_EUNSUPPORTED;
+}
+sweik_status sweik_batch_solve_graph(sweik_batch batch, const void *const *f,
+                                     const int32_t *const *src, void *const *S, void *ws,
+                                     size_t ws_bytes, void *stream, sweik_info *infos) {
+  (void)batch; (void)f; (void)src; (void)S; (void)ws; (void)ws_bytes; (void)stream; (void)infos;
+  return SWEIK_EUNSUPPORTED;
+}
+int32_t sweik_autotune(sweik_plan plan, void *ws, size_t ws_bytes, void *stream) {
+  (void)plan; (void)ws; (void)ws_bytes; (void)stream;
+  return 0;
+}
+
+const char *sweik_status_string(sweik_status s) {
+  switch (s) {
+    case SWEIK_OK: return "ok";
+    case SWEIK_EINVAL: return "invalid argument";
+    case SWEIK_EUNSUPPORTED: return "unsupported problem";
+    case SWEIK_EWORKSPACE: return "workspace too small";
+    case SWEIK_EDEVICE: return "HIP error";
+    case SWEIK_ENOMEM: return "out of host memory";
+  }
+  return "unknown status";
+}
+
+int32_t sweik_abi_version(void) { return SWEIK_ABI_VERSION; }
+
+}  // extern "C"

@@ -1,0 +1,130 @@
+// green.hpp -- device evaluation (float64) of the normalised screened-Poisson
+// Green's kernel kappa(m) = ftilde^2 h^D G(h m) in units of the grid:
+//   2D: (beta^2 / 2 pi) K0(beta |m|)              (eq. GreensFunction2D)
+//   3D:  beta^2 exp(-beta |m|) / (4 pi |m|)       (eq. GreensFunction3D)
+// with beta = ftilde h / hbar.  At m = 0 the kernel is singular; its value
+// there is the mean of ftilde^2 h^D G over the ball of one cell's volume:
+//   2D: 1 - a K1(a),       a = beta / sqrt(pi)
+//   3D: 1 - (1 + a) e^-a,  a = beta (3 / (4 pi))^(1/3)
+// (the integral of t K0(t) is -t K1(t); the integral of t e^-t is
+// -(1+t) e^-t).
+//
+// K0 and K1 are evaluated in three ranges:
+//   x <= 2       ascending series (Abramowitz & Stegun 9.6.13 / 9.6.11)
+//   2 < x < 25   trapezoid rule on e^x K_nu(x) = int_0^inf
+//                exp(-2 x sinh^2(t/2)) cosh(nu t) dt, which converges
+//                geometrically because the integrand is analytic in the
+//                strip |Im t| < pi/2
+//   x >= 25      Hankel's asymptotic expansion (A&S 9.7.2), truncated where
+//                the terms stop decreasing or fall below 1e-17
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace sweik {
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double kEulerGamma = 0.57721566490153286060651209008240243;
+
+__device__ inline double k_trapezoid_scaled(double x, int nu) {
+  // step pi^2/(x+45): discretisation error far below 1e-16 relative
+  const double eta = (kPi * kPi) / (x + 45.0);
+  double sum = 0.5;
+  for (int j = 1; j < 400; ++j) {
+    const double t = eta * j;
+    const double sh = sinh(0.5 * t);
+    double g = exp(-2.0 * x * sh * sh);
+    if (nu) g *= cosh(t);
+    sum += g;
+    if (g < 1e-18 * sum) break;
+  }
+  return eta * sum;
+}
+
+// e^x K_nu(x) ~ sqrt(pi/2x) sum_k a_k / x^k, a_k = prod_{j<=k} (4nu^2 -
+// (2j-1)^2) / (k! 8^k)
+__device__ inline double k_hankel_scaled(double x, int nu) {
+  const double mu = 4.0 * nu * nu;
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 60; ++k) {
+    const double f = (mu - (2.0 * k - 1.0) * (2.0 * k - 1.0)) / (k * 8.0 * x);
+    const double nt = term * f;
+    if (fabs(nt) >= fabs(term)) break;
+    term = nt;
+    sum += term;
+    if (fabs(term) < 1e-17 * fabs(sum)) break;
+  }
+  return sqrt(kPi / (2.0 * x)) * sum;
+}
+
+__device__ inline double bessel_k0(double x) {
+  if (x <= 2.0) {
+    const double q = 0.25 * x * x;
+    double term = 1.0, i0 = 1.0, sh = 0.0, hk = 0.0;
+    for (int k = 1; k < 40; ++k) {
+      term *= q / ((double)k * (double)k);
+      hk += 1.0 / k;
+      i0 += term;
+      sh += term * hk;
+      if (term < 1e-19 * i0) break;
+    }
+    return sh - (log(0.5 * x) + kEulerGamma) * i0;
+  }
+  if (x < 25.0) return exp(-x) * k_trapezoid_scaled(x, 0);
+  return exp(-x) * k_hankel_scaled(x, 0);
+}
+
+// 1 - a K1(a) for a > 0 without cancellation for small a:
+// a K1(a) = 1 + a ln(a/2) I1(a) - (a^2/4) sum_k (psi(k+1)+psi(k+2))
+//           (a^2/4)^k / (k!(k+1)!)
+__device__ inline double one_minus_aK1(double a) {
+  if (a <= 2.0) {
+    const double q = 0.25 * a * a;
+    double term = 1.0, psi1 = -kEulerGamma, psi2 = 1.0 - kEulerGamma;
+    double i1s = 0.0, s = 0.0;
+    for (int k = 0; k < 40; ++k) {
+      if (k > 0) {
+        term *= q / ((double)k * (double)(k + 1));
+        psi1 += 1.0 / k;
+        psi2 += 1.0 / (k + 1);
+      }
+      i1s += term;
+      s += (psi1 + psi2) * term;
+      if (k > 2 && term < 1e-19 * (i1s > 1.0 ? i1s : 1.0)) break;
+    }
+    const double a_ln_i1 = a * log(0.5 * a) * (0.5 * a) * i1s;
+    return q * s - a_ln_i1;
+  }
+  const double k1s = a < 25.0 ? k_trapezoid_scaled(a, 1) : k_hankel_scaled(a, 1);
+  return 1.0 - a * exp(-a) * k1s;
+}
+
+__device__ inline double kappa0_2d(double beta) {
+  return one_minus_aK1(beta / sqrt(kPi));
+}
+
+__device__ inline double kappa0_3d(double beta) {
+  const double a = beta * cbrt(3.0 / (4.0 * kPi));
+  if (a < 0.5) {  // sum_{k>=2} (-a)^k (k-1)/k!
+    double s = 0.0, p = -a;
+    for (int k = 2; k < 30; ++k) {
+      p *= -a / k;
+      s += p * (k - 1);
+    }
+    return s;
+  }
+  return 1.0 - (1.0 + a) * exp(-a);
+}
+
+// kappa at integer offset with squared length r2 (kappa0 given)
+__device__ inline double kappa_2d(double beta, long long r2, double k0v) {
+  if (r2 == 0) return k0v;
+  return beta * beta * (0.5 / kPi) * bessel_k0(beta * sqrt((double)r2));
+}
+__device__ inline double kappa_3d(double beta, long long r2, double k0v) {
+  if (r2 == 0) return k0v;
+  const double r = sqrt((double)r2);
+  return beta * beta * exp(-beta * r) / (4.0 * kPi * r);
+}
+
+}  // namespace sweik

@@ -1,0 +1,36 @@
+// plan.hpp -- host-side plan of a solve: the problem, its padded geometry,
+// the kernel schedule and the workspace / checkpoint layout.
+#pragma once
+
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/sweik.h"
+
+namespace sweik {
+
+struct Geo2 {
+  int n0, n1;
+  int M0, H0, ldg;   // column FFT length, half, kernel-spectrum leading dim
+  int H1, ldk;       // row half length, spectral columns
+  int RB, nb;        // rows per spectral block, blocks
+  int rpw, cpw;      // rows per row WG, columns per column WG
+  int nbr, ncw;      // row WGs, column WGs
+  int lmax, lmax_log;
+};
+
+struct Layout {      // byte offsets into the workspace / checkpoint
+  size_t par, red, expo, mu, tw, g, spec, acc, total;
+  size_t ck_expo, ck_phi, ck_terms, ck_total;
+};
+
+}  // namespace sweik
+
+struct sweik_plan_s {
+  sweik_problem p;
+  int64_t padded[3];
+  size_t lds_max;
+  sweik::Geo2 g2;
+  sweik::Layout ws;
+};

@@ -1,0 +1,104 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol that
+include/sweik.h declares, and rejects invalid arguments on the host before
+any HIP call (plan creation and source checks make no device call)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from common import ROOT, ensure_built
+
+HEADER = os.path.join(ROOT, "include", "sweik.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    ensure_built()
+    import paper_1403_1937_amd as pk
+    return pk.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sweik_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_abi_version(lib):
+    assert lib.sweik_abi_version() == 1
+    assert lib.sweik_status_string(1) == b"invalid argument"
+
+
+def _plan(**kw):
+    from paper_1403_1937_amd import Plan
+    args = dict(dims=(64, 64), h=1 / 64, hbar=0.05, T=4, n_src=1)
+    args.update(kw)
+    return Plan(**args)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dims=(1, 64)), dict(dims=(64, 0)), dict(h=0.0), dict(h=-1.0), dict(hbar=0.0),
+    dict(hbar=float("nan")), dict(T=-1), dict(T=65), dict(n_src=0),
+    dict(ftilde_mode="given", ftilde=0.0), dict(ftilde_mode="given", ftilde=-2.0),
+])
+def test_plan_rejects_invalid(lib, bad):
+    with pytest.raises(ValueError):
+        _plan(**bad)
+
+
+def test_plan_rejects_unknown_modes(lib):
+    with pytest.raises(ValueError):
+        _plan(precision="fp16")
+    with pytest.raises(ValueError):
+        _plan(ftilde_mode="mean")
+
+
+def test_unsupported_sizes(lib):
+    with pytest.raises(ValueError, match="unsupported"):
+        _plan(dims=(4096, 64))      # column FFT length 8192
+    with pytest.raises(ValueError, match="unsupported"):
+        _plan(dims=(64, 8192))      # row FFT length 16384
+    _plan(dims=(2048, 4096))        # largest 2D grid
+
+
+def test_workspace_sizes_scale_with_grid(lib):
+    a = _plan(dims=(256, 256))
+    b = _plan(dims=(512, 512))
+    assert b.workspace_bytes > 3.5 * a.workspace_bytes
+    c = _plan(dims=(256, 256), precision="fp64")
+    assert c.workspace_bytes > a.workspace_bytes
+    assert a.padded == (512, 512)
+    assert _plan(dims=(100, 7)).padded == (256, 64)
+    # checkpoint: T float terms + float64 phi
+    assert a.checkpoint_bytes >= 256 * 256 * (4 * 4 + 8)
+
+
+def test_source_checks(lib):
+    p = _plan(n_src=2)
+    p.check_sources(np.array([[0, 0], [63, 63]]))
+    with pytest.raises(ValueError):
+        p.check_sources(np.array([[0, 0], [64, 3]]))
+    with pytest.raises(ValueError):
+        p.check_sources(np.array([[0, -1], [3, 3]]))
+    with pytest.raises(ValueError):
+        p.check_sources(np.array([[5, 5], [5, 5]]))
+    with pytest.raises(ValueError):
+        p.check_sources(np.array([[5, 5]]))
+
+
+def test_solve_rejects_null_and_small_workspace(lib):
+    p = _plan()
+    vp = C.c_void_p
+    rc = lib.sweik_solve(p.handle, None, None, None, None, 0, None, None, None)
+    assert rc == 1
+    rc = lib.sweik_solve(p.handle, vp(16), vp(16), vp(16), vp(16), 10, None, None, None)
+    assert rc == 3

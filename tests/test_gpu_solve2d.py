@@ -1,0 +1,137 @@
+"""GPU parity of the 2D forward solve against the FP64 CPU oracle.
+
+Inputs are seeded synthetic fields from `workloads`; the oracle runs the
+same algorithm (Table 1) with its own FFT.  Tolerances are claimed on the
+resolvable sets described in tests/common.py.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from common import TOL, ensure_built, envelope_violations, report, resolvable, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    ensure_built()
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _run(f32, src, h, hbar, T, prec, ft_mode="nu", ftilde=None):
+    import paper_1403_1937_amd as pk
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    f = torch.as_tensor(f32.astype(np.float32 if prec == "fp32" else np.float64)).to("cuda", dt)
+    S, info = pk.solve(f, src, h, hbar, T, ftilde_mode=ft_mode, ftilde=ftilde, return_info=True)
+    torch.cuda.synchronize()
+    return S.double().cpu().numpy(), info
+
+
+def _oracle(f32, src, h, hbar, T, ft_mode="nu", ftilde=None):
+    return oracle.solve(f32.astype(np.float64), src, h, hbar, T, ft_mode=ft_mode, ftilde=ftilde)
+
+
+CASES = [
+    # (name, dims, h, hbar, T, n_src, seed)
+    ("square64", (64, 64), 1 / 64, 0.05, 8, 3, 1),
+    ("ragged100x76", (100, 76), 1 / 100, 0.2, 6, 5, 2),
+    ("ragged33x130", (33, 130), 1 / 130, 0.06, 5, 2, 3),
+    ("thin7x300", (7, 300), 1 / 300, 0.3, 4, 2, 4),
+    ("tall257x20", (257, 20), 1 / 257, 0.25, 4, 2, 5),
+    ("square256", (256, 256), 1 / 256, 0.05, 10, 16, 6),
+    ("rect200x513", (200, 513), 1 / 513, 0.1, 7, 4, 7),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_forward_parity_2d(case, prec):
+    name, dims, h, hbar, T, n_src, seed = case
+    rng = np.random.default_rng(seed)
+    f = workloads.smoothed_noise(dims, 4.0, 1.0, 3.0, rng).astype(np.float32)
+    src = workloads.distinct_sources(dims, n_src, rng)
+    print(f"case {name} prec {prec} dims {dims}", flush=True)
+    S, info = _run(f, src, h, hbar, T, prec)
+    o = _oracle(f, src, h, hbar, T)
+    assert info["flags"] == 0
+    assert abs(info["ftilde"] - o["info"]["ftilde"]) <= 1e-14 * o["info"]["ftilde"]
+    assert abs(info["beta"] - o["info"]["beta"]) <= 1e-14 * o["info"]["beta"]
+    worst, frac, _ = report(S, o, hbar, prec)
+    nbad = envelope_violations(S, o, hbar, prec)
+    print(f"  max rel on resolvable set {worst:.3e} (fraction {frac:.3f}); "
+          f"envelope violations {nbad}", flush=True)
+    assert frac > 0.1
+    assert worst <= TOL[prec]
+    assert nbad == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_workload1_bumps64(prec):
+    """64x64, h = 1, hbar = 0.5 (beta ~ 2.6): phi spans ~100 e-folds, so
+    the FFT result is only resolvable near the source (Section 5.3)."""
+    p = workloads.problem(1)
+    S, info = _run(p.f, p.src, p.h, p.hbar, p.T, prec)
+    o = _oracle(p.f, p.src, p.h, p.hbar, p.T)
+    worst, frac, _ = report(S, o, p.hbar, prec)
+    print(f"bumps64 {prec}: max rel {worst:.3e} on {frac:.3f} of grid", flush=True)
+    assert worst <= TOL[prec]
+    assert envelope_violations(S, o, p.hbar, prec) == 0
+    # points the oracle finds non-positive are +inf on both sides or outside
+    # the resolvable set
+    assert info["n_nonpositive_phi"] >= 0
+
+
+@pytest.mark.parametrize("ft_mode", ["fmax", "given"])
+def test_ftilde_modes(ft_mode):
+    rng = np.random.default_rng(9)
+    dims = (80, 96)
+    f = workloads.smoothed_noise(dims, 5.0, 1.0, 2.0, rng).astype(np.float32)
+    src = workloads.distinct_sources(dims, 3, rng)
+    ft = 1.77 if ft_mode == "given" else None
+    S, info = _run(f, src, 1 / 96, 0.05, 6, "fp64", ft_mode, ft)
+    o = _oracle(f, src, 1 / 96, 0.05, 6, ft_mode, ft)
+    assert abs(info["ftilde"] - o["info"]["ftilde"]) <= 1e-14
+    worst, frac, _ = report(S, o, 0.05, "fp64")
+    assert worst <= TOL["fp64"]
+    assert envelope_violations(S, o, 0.05, "fp64") == 0
+
+
+def test_constant_forcing_closed_form_gpu():
+    """f = c => phi = phi_0 exactly: S = -hbar ln sum_k exp(-c|x-y_k|/hbar)."""
+    dims = (50, 70)
+    f = np.full(dims, 1.5, np.float32)
+    src = np.array([[3, 4], [40, 60]], np.int32)
+    S, info = _run(f, src, 0.02, 0.05, 5, "fp64")
+    g = np.stack(np.meshgrid(np.arange(50), np.arange(70), indexing="ij"), -1)
+    d = np.stack([np.linalg.norm(g - s, axis=-1) for s in src]) * 0.02
+    ref = -0.05 * np.log(np.exp(-1.5 * d / 0.05).sum(0))
+    assert np.max(np.abs(S - ref)) < 1e-12
+    assert info["c0_bound"] == 0.0
+
+
+def test_zero_terms():
+    rng = np.random.default_rng(12)
+    dims = (40, 40)
+    f = rng.uniform(1, 2, dims).astype(np.float32)
+    src = np.array([[20, 20]], np.int32)
+    S, _ = _run(f, src, 1 / 40, 0.05, 0, "fp64")
+    o = _oracle(f, src, 1 / 40, 0.05, 0)
+    assert np.max(rel_err(S, o["S"], 0.05)) < 1e-13
+
+
+def test_scale_exponents_track_decay():
+    """With f close to ftilde the terms decay fast; the stored exponents
+    must follow so that mantissas stay representable."""
+    rng = np.random.default_rng(13)
+    dims = (64, 64)
+    f = (1.0 + 1e-3 * rng.uniform(0, 1, dims)).astype(np.float32)
+    src = np.array([[32, 32]], np.int32)
+    S, info = _run(f, src, 1 / 64, 0.05, 30, "fp32")
+    o = _oracle(f, src, 1 / 64, 0.05, 30)
+    assert info["scale_exp"][-1] < -150  # far below float32's range
+    worst, frac, _ = report(S, o, 0.05, "fp32")
+    assert worst <= TOL["fp32"]
