@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
@@ -10,7 +11,7 @@
 #include <set>
 #include <tuple>
 
-#include "solve2d.hpp"
+#include "launch2d.hpp"
 #include "plan.hpp"
 
 using namespace sweik;
@@ -19,8 +20,6 @@ namespace {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
-constexpr size_t kLdsPreferred = 65536;  // per work-group, for occupancy
-constexpr size_t kLdsDevice = 163840;    // gfx950 limit per work-group
 
 int64_t next_pow2(int64_t m) {
   int64_t p = 1;
@@ -33,9 +32,57 @@ int ilog2(int64_t x) {
   return l;
 }
 
+// e^x K0(x) for x >= 2 by the trapezoid rule on int_0^inf exp(-2x sinh^2(t/2)) dt
+double k0_scaled_host(double x) {
+  const double pi = 3.14159265358979323846;
+  if (x > 60.0) {  // Hankel expansion, terms (2j-1)^2 / (8 j x)
+    double term = 1.0, sum = 1.0;
+    for (int j = 1; j < 40; ++j) {
+      const double nt = -term * (2.0 * j - 1.0) * (2.0 * j - 1.0) / (8.0 * j * x);
+      if (std::fabs(nt) >= std::fabs(term)) break;
+      term = nt;
+      sum += term;
+    }
+    return std::sqrt(pi / (2.0 * x)) * sum;
+  }
+  const double eta = pi * pi / (x + 45.0);
+  double sum = 0.5;
+  for (int j = 1; j < 10000; ++j) {
+    const double sh = std::sinh(0.5 * eta * j);
+    const double g = std::exp(-2.0 * x * sh * sh);
+    sum += g;
+    if (g < 1e-18 * sum) break;
+  }
+  return eta * sum;
+}
+
 }  // namespace
 
 namespace sweik {
+
+// Chebyshev coefficients of sqrt(x) e^x K0(x) on x >= 2 in t = 4/x - 1,
+// from its values at the Chebyshev points (discrete cosine transform).
+const ChebK0 &bessel_cheb_k0() {
+  static const ChebK0 tab = [] {
+    ChebK0 t;
+    const int n = 40;
+    const double pi = 3.14159265358979323846;
+    double g[n];
+    for (int j = 0; j < n; ++j) {
+      const double tj = std::cos(pi * (j + 0.5) / n);
+      const double x = 4.0 / (tj + 1.0);
+      g[j] = std::sqrt(x) * k0_scaled_host(x);
+    }
+    for (int k = 0; k < kChebK0; ++k) {
+      double s = 0.0;
+      for (int j = 0; j < n; ++j) s += g[j] * std::cos(pi * k * (j + 0.5) / n);
+      t.c[k] = (k == 0 ? 1.0 : 2.0) * s / n;
+      t.c32[k] = (float)t.c[k];
+    }
+    return t;
+  }();
+  return tab;
+}
 
 sweik_status validate_problem(const sweik_problem *p) {
   if (!p) return SWEIK_EINVAL;
@@ -70,25 +117,11 @@ sweik_status plan2d(sweik_plan_s *pl) {
   g.ldg = g.H0 + 1;
   g.H1 = (int)(M1 / 2);
   g.ldk = g.H1 + 1;
-  g.RB = p.prec == SWEIK_F64 ? 2 : 4;
+  if (M0 > 4096 || g.H1 > 4096 || g.H1 < 32) return SWEIK_EUNSUPPORTED;
+  g.RB = p.prec == SWEIK_F64 ? spec_rb<double>() : spec_rb<float>();
   g.nb = (g.n0 + g.RB - 1) / g.RB;
-  // row pass: teams of H1/16 threads, up to 256 threads per work-group
-  // Lines per work-group: 256 threads, fewer while the LDS lines exceed the
-  // preferred 64 KB, but always whole wavefronts; a single line may use up
-  // to the device limit.
-  auto lines_per_wg = [&](int P, int L) {
-    int n = std::max(1, 256 / P);
-    const size_t line = (size_t)lds_line_len(L) * csz;
-    while (n > 1 && n * line > kLdsPreferred && (n / 2) * P >= 64) n /= 2;
-    return n;
-  };
-  const int Pr = g.H1 / 16;
-  g.rpw = lines_per_wg(Pr, g.H1);
-  if ((size_t)g.rpw * lds_line_len(g.H1) * csz > pl->lds_max) return SWEIK_EUNSUPPORTED;
-  const int Pc = g.M0 / 16;
-  g.cpw = lines_per_wg(Pc, g.M0);
-  if ((size_t)g.cpw * lds_line_len(g.M0) * csz > pl->lds_max) return SWEIK_EUNSUPPORTED;
-  if ((g.rpw * Pr) % 64 || (g.cpw * Pc) % 64) return SWEIK_EUNSUPPORTED;
+  g.rpw = row_rpw(g.H1);
+  g.cpw = col_cpw(g.M0);
   const int spec_rows = g.nb * g.RB;
   g.nbr = (spec_rows + g.rpw - 1) / g.rpw;
   g.ncw = (g.ldk + g.cpw - 1) / g.cpw;
@@ -115,9 +148,12 @@ sweik_status plan2d(sweik_plan_s *pl) {
   L.g = take((size_t)esz * g.ldk * g.ldg);
   L.spec = take((size_t)csz * g.nb * g.ldk * g.RB);
   L.acc = take(sizeof(double) * N);
+  L.lam = take((size_t)esz * N);
   L.total = off;
   off = 0;
   L.ck_expo = take(sizeof(int) * (SWEIK_MAX_TERMS + 1));
+  L.ck_par = take(sizeof(Params));
+  L.ck_g = take((size_t)esz * g.ldk * g.ldg);
   L.ck_phi = take(sizeof(double) * N);
   L.ck_terms = take((size_t)esz * N * (size_t)p.T);
   L.ck_total = off;
@@ -139,11 +175,9 @@ Args2<R> make_args2(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.M0 = g.M0;
   a.H0 = g.H0;
   a.ldg = g.ldg;
-  a.RB = g.RB;
   a.nb = g.nb;
-  a.rpw = g.rpw;
-  a.cpw = g.cpw;
   a.nbr = g.nbr;
+  a.ncw = g.ncw;
   a.lmax_log = g.lmax_log;
   a.T = p.T;
   a.n_src = p.n_src;
@@ -162,24 +196,20 @@ Args2<R> make_args2(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.spec = (cplx<R> *)(w + L.spec);
   a.g = (R *)(w + L.g);
   a.acc = (double *)(w + L.acc);
+  a.lam = (R *)(w + L.lam);
+  a.k0tab = bessel_cheb_k0();
+  a.dLdS = nullptr;
+  a.dLdf = nullptr;
   a.info = info;
   char *c = (char *)ckpt;
+  if (c) {  // the kernel spectrum and scalars live in the checkpoint
+    a.par = (Params *)(c + L.ck_par);
+    a.g = (R *)(c + L.ck_g);
+  }
   a.ck_expo = c ? (int *)(c + L.ck_expo) : nullptr;
   a.ck_phi = c ? (double *)(c + L.ck_phi) : nullptr;
   a.ck_terms = c ? (R *)(c + L.ck_terms) : nullptr;
   return a;
-}
-
-// Kernels whose dynamic LDS exceeds 64 KB must be allowed to use more.
-template <typename K> bool allow_lds(K kernel, size_t bytes) {
-  if (bytes <= 65536) return true;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    return false;
-  }
-  return true;
 }
 
 // Optional per-kernel timing: events recorded on the solve's stream before
@@ -205,48 +235,52 @@ sweik_status enqueue2d(const sweik_plan_s *pl, const void *f, const int32_t *src
                        KernelTimer *tm = nullptr) {
   const Geo2 &g = pl->g2;
   Args2<R> a = make_args2<R>(pl, f, src, S, ws, ckpt, info);
-  const int csz = 2 * sizeof(R);
-  const size_t lds_row = (size_t)g.rpw * lds_line_len(g.H1) * csz;
-  const size_t lds_col = (size_t)g.cpw * lds_line_len(g.M0) * csz;
-  const int thr_row = g.rpw * (g.H1 / 16);
-  const int thr_col = g.cpw * (g.M0 / 16);
   const long long N = (long long)g.n0 * g.n1;
-  if (!allow_lds(k_row2<R, ROW_GHAT>, lds_row) || !allow_lds(k_row2<R, ROW_PHI0>, lds_row) ||
-      !allow_lds(k_row2<R, ROW_TERM>, lds_row) || !allow_lds(k_col2<R, COL_GHAT>, lds_col) ||
-      !allow_lds(k_col2<R, COL_CONV>, lds_col))
-    return SWEIK_EUNSUPPORTED;
+  hipError_t err = hipSuccess;
   auto launch = [&](int cls, auto &&fn) {
+    if (err != hipSuccess) return;
     if (tm && tm->n < KernelTimer::kMax) {
       (void)hipEventRecord(tm->ev[2 * tm->n], st);
-      fn();
+      err = fn();
       (void)hipEventRecord(tm->ev[2 * tm->n + 1], st);
       tm->cls[tm->n++] = cls;
     } else {
-      fn();
+      err = fn();
     }
   };
-  launch(SWEIK_KC_PREP, [&] {
-    hipLaunchKernelGGL(k_prep<R>, dim3(kRedBlocks), dim3(256), 0, st, (const R *)f, N, a.red,
-                       (cplx<R> *)a.tw, g.lmax);
-  });
-  launch(SWEIK_KC_GHAT_ROW, [&] {
-    hipLaunchKernelGGL((k_row2<R, ROW_GHAT>), dim3(g.nbr), dim3(thr_row), lds_row, st, a, 0);
-  });
-  launch(SWEIK_KC_GHAT_COL, [&] {
-    hipLaunchKernelGGL((k_col2<R, COL_GHAT>), dim3(g.ncw), dim3(thr_col), lds_col, st, a);
-  });
-  launch(SWEIK_KC_PHI0_ROW, [&] {
-    hipLaunchKernelGGL((k_row2<R, ROW_PHI0>), dim3(g.nbr), dim3(thr_row), lds_row, st, a, 0);
-  });
+  const dim3 grow(g.nbr), gcol(g.ncw);
+  launch(SWEIK_KC_PREP, [&] { return launch_prep<R>((const R *)f, N, a.red, (cplx<R> *)a.tw, g.lmax, st); });
+  launch(SWEIK_KC_GHAT_ROW, [&] { return launch_row2<R>(ROW_GHAT, g.H1, grow, st, a, 0); });
+  launch(SWEIK_KC_GHAT_COL, [&] { return launch_col2<R>(COL_GHAT, g.M0, gcol, st, a); });
+  launch(SWEIK_KC_PHI0_ROW, [&] { return launch_row2<R>(ROW_PHI0, g.H1, grow, st, a, 0); });
   for (int i = 1; i <= pl->p.T; ++i) {
-    launch(SWEIK_KC_CONV_COL, [&] {
-      hipLaunchKernelGGL((k_col2<R, COL_CONV>), dim3(g.ncw), dim3(thr_col), lds_col, st, a);
-    });
-    launch(i == pl->p.T ? SWEIK_KC_LAST_ROW : SWEIK_KC_TERM_ROW, [&] {
-      hipLaunchKernelGGL((k_row2<R, ROW_TERM>), dim3(g.nbr), dim3(thr_row), lds_row, st, a, i);
-    });
+    launch(SWEIK_KC_CONV_COL, [&] { return launch_col2<R>(COL_CONV, g.M0, gcol, st, a); });
+    launch(i == pl->p.T ? SWEIK_KC_LAST_ROW : SWEIK_KC_TERM_ROW,
+           [&] { return launch_row2<R>(ROW_TERM, g.H1, grow, st, a, i); });
   }
-  return hipGetLastError() == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
+  return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
+}
+
+template <typename R>
+sweik_status enqueue2d_adjoint(const sweik_plan_s *pl, const void *f, const int32_t *src,
+                               const void *ckpt, const void *dLdS, void *dLdf, void *ws,
+                               hipStream_t st) {
+  const Geo2 &g = pl->g2;
+  Args2<R> a = make_args2<R>(pl, f, src, nullptr, ws, const_cast<void *>(ckpt), nullptr);
+  a.dLdS = (const R *)dLdS;
+  a.dLdf = (R *)dLdf;
+  const long long N = (long long)g.n0 * g.n1;
+  if (pl->p.T == 0)  // ftilde fixed: no term depends on f
+    return launch_fill<R>((R *)dLdf, N, (R)0, st) == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
+  const dim3 grow(g.nbr), gcol(g.ncw);
+  hipError_t err = launch_adj_prep<R>((const R *)dLdS, (const double *)a.ck_phi, N,
+                                      pl->p.hbar, a.red, (cplx<R> *)a.tw, g.lmax, st);
+  if (err == hipSuccess) err = launch_row2<R>(ROW_ADJ0, g.H1, grow, st, a, pl->p.T);
+  for (int i = pl->p.T; i >= 1 && err == hipSuccess; --i) {
+    err = launch_col2<R>(COL_CONV, g.M0, gcol, st, a);
+    if (err == hipSuccess) err = launch_row2<R>(ROW_ADJ, g.H1, grow, st, a, i);
+  }
+  return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
 
 }  // namespace sweik
@@ -346,8 +380,14 @@ sweik_status sweik_solve_timed(sweik_plan plan, const void *f, const int32_t *sr
 sweik_status sweik_solve_adjoint(sweik_plan plan, const void *f, const int32_t *src,
                                  const void *ckpt, const void *dLdS, void *dLdf, void *ws,
                                  size_t ws_bytes, void *stream) {
-  (void)f; (void)src; (void)ckpt; (void)dLdS; (void)dLdf; (void)ws; (void)ws_bytes; (void)stream;
-  if (!plan) return SWEIK_EINVAL;
+  if (!plan || !f || !src || !ckpt || !dLdS || !dLdf || !ws) return SWEIK_EINVAL;
+  if (ws_bytes < plan->ws.total) return SWEIK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  if (plan->p.ndim == 2) {
+    return plan->p.prec == SWEIK_F64
+               ? enqueue2d_adjoint<double>(plan, f, src, ckpt, dLdS, dLdf, ws, st)
+               : enqueue2d_adjoint<float>(plan, f, src, ckpt, dLdS, dLdf, ws, st);
+  }
   return SWEIK_EUNSUPPORTED;
 }
 

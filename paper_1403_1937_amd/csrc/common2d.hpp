@@ -1,0 +1,227 @@
+// common2d.hpp -- gfx950 kernels of the 2D perturbation-series eikonal solve:
+// shared definitions, the reduction of f and block-level helpers.
+//
+// Per correction term i (Table 1, steps 9-13) the 2D linear convolution
+// phi_i = kappa (*) (gamma phi_{i-1}) is evaluated on the zero-padded grid
+// M0 x M1 (M_d >= 2 n_d - 1) in two passes:
+//   column pass  for each spectral column k1: forward FFT of length M0 over
+//                the (zero-padded) rows, product with the real kernel
+//                spectrum Ghat[k0][k1], inverse FFT, keep the first rows
+//   row pass     for each grid row: inverse real FFT of length M1 (a complex
+//                FFT of length M1/2 plus a split step), crop to n1 columns,
+//                rescale, accumulate (-1)^i phi_i in float64, form
+//                gamma * phi_i for the next term and take its forward real
+//                FFT; after the last term write S = -hbar ln phi instead.
+// The half spectrum (H1+1 = M1/2+1 columns, rows 0..n0-1) lives in a
+// blocked transposed layout spec[b][k1][rr] with RB rows per block b: a row
+// pass work-group reads and writes whole contiguous blocks, and a column
+// pass reads RB contiguous rows of CPW neighbouring columns per block.
+// Every pass issues all of its global reads (spectrum, kernel spectrum,
+// twiddles, forcing, accumulator) before its first barrier, so that a pass
+// costs one memory latency rather than one per operand.
+//
+// The same two kernels build the kernel spectrum (mode GHAT): the row pass
+// evaluates the evenly extended kernel table row by row and takes its real
+// FFT; the column pass extends each column evenly, transforms it and keeps
+// the real part.  phi_0 (mode PHI0) is evaluated directly from the sources
+// (eq. phi_0Solution) in the first row pass.
+//
+// Scaling: term i is stored as a mantissa field m_i and an exponent E_i
+// (phi_i = 2^E_i m_i).  The exponent step applied to m_i is the binary
+// exponent of max|m_{i-1}|, known from the previous pass, so the stored
+// values stay near the contraction factor instead of decaying like c0^i.
+#pragma once
+
+#include "geom2d.hpp"
+#include "green.hpp"
+#include "../../include/sweik.h"
+
+namespace sweik {
+
+constexpr int kRedBlocks = 256;  // partial reductions of f
+
+struct Params {      // device-side scalars shared by the kernels of a solve
+  double ftilde, beta, hbar, inv_ft2, kappa0, fmin, fmax, c0;
+  int flags, pad_;
+};
+
+template <typename R> struct Args2 {
+  // geometry
+  int n0, n1;      // grid
+  int H1, ldk;     // M1/2, H1+1 spectral columns
+  int M0, H0, ldg; // column FFT length, M0/2, H0+1
+  int nb;          // spectral row blocks (spec_rb rows each)
+  int nbr;         // number of row-pass WGs
+  int ncw;         // number of column-pass WGs
+  int lmax_log;    // log2 of the twiddle table length
+  int T, n_src, ft_mode;
+  double ftilde_given, h, hbar;
+  // data
+  const R *f;
+  const int *src;
+  R *S;
+  // workspace
+  Params *par;
+  double *red;   // kRedBlocks x 3 (min, max, flags)
+  double *mu;    // (T+1) x nbr partial max |m_i|
+  int *expo;     // T+1 exponents
+  const cplx<R> *tw;
+  cplx<R> *spec;
+  R *g;          // (H1+1) x (H0+1) kernel spectrum, pre-scaled
+  double *acc;   // n0 x n1
+  ChebK0 k0tab;  // K0 for x > 2
+  // adjoint
+  const R *dLdS;
+  R *dLdf;
+  R *lam;        // n0 x n1 lambda mantissas
+  // optional
+  sweik_info *info;
+  int *ck_expo;  // T+1
+  double *ck_phi;// n0 x n1
+  R *ck_terms;   // T x n0 x n1 series-term mantissas
+};
+
+// ---------------------------------------------------------------------------
+// prep: partial min / max / validity of f, and the twiddle table
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256) k_prep(const R *__restrict__ f, long long N,
+                                              double *__restrict__ red,
+                                              cplx<R> *__restrict__ tw, int lmax) {
+  __shared__ double smin[4], smax[4];
+  __shared__ int sfl[4];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
+  int fl = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = (double)f[i];
+    if (!isfinite(v)) {
+      fl |= SWEIK_FLAG_F_NONFINITE;
+      continue;
+    }
+    if (!(v > 0.0)) fl |= SWEIK_FLAG_F_NONPOSITIVE;
+    lo = v < lo ? v : lo;
+    hi = v > hi ? v : hi;
+  }
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  fl = wave_or(fl);
+  if (lane == 0) {
+    smin[wid] = lo;
+    smax[wid] = hi;
+    sfl[wid] = fl;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+      lo = smin[w] < lo ? smin[w] : lo;
+      hi = smax[w] > hi ? smax[w] : hi;
+      fl |= sfl[w];
+    }
+    lo = smin[0] < lo ? smin[0] : lo;
+    hi = smax[0] > hi ? smax[0] : hi;
+    fl |= sfl[0];
+    red[3 * blockIdx.x + 0] = lo;
+    red[3 * blockIdx.x + 1] = hi;
+    red[3 * blockIdx.x + 2] = (double)fl;
+  }
+  // twiddles exp(-2 pi i j / lmax) from an exact argument
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < lmax; j += gridDim.x * blockDim.x) {
+    double s, c;
+    sincospi(2.0 * (double)j / (double)lmax, &s, &c);
+    cplx<R> w;
+    w.x = (R)c;
+    w.y = (R)(-s);
+    tw[j] = w;
+  }
+}
+
+// Reduce the prep partials into the reference forcing (Section 5.1).
+// Every work-group of the first row pass does this; block 0 publishes it.
+__device__ inline void reduce_forcing(const double *__restrict__ red, int ft_mode,
+                                      double ft_given, double *out_lo,
+                                      double *out_hi, int *out_fl) {
+  __shared__ double slo[4], shi[4];
+  __shared__ int sfl[4];
+  double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
+  int fl = 0;
+  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) {
+    lo = red[3 * i] < lo ? red[3 * i] : lo;
+    hi = red[3 * i + 1] > hi ? red[3 * i + 1] : hi;
+    fl |= (int)red[3 * i + 2];
+  }
+  lo = wave_min(lo);
+  hi = wave_max(hi);
+  fl = wave_or(fl);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    slo[wid] = lo;
+    shi[wid] = hi;
+    sfl[wid] = fl;
+  }
+  __syncthreads();
+  lo = slo[0];
+  hi = shi[0];
+  fl = sfl[0];
+  for (int w = 1; w < nw; ++w) {
+    lo = slo[w] < lo ? slo[w] : lo;
+    hi = shi[w] > hi ? shi[w] : hi;
+    fl |= sfl[w];
+  }
+  *out_lo = lo;
+  *out_hi = hi;
+  *out_fl = fl;
+}
+
+__device__ inline double block_max(double x) {
+  __shared__ double s[4];
+  x = wave_max(x);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) s[wid] = x;
+  __syncthreads();
+  x = s[0];
+  for (int w = 1; w < nw; ++w) x = s[w] > x ? s[w] : x;
+  return x;
+}
+
+__device__ inline long long block_sum_ll(long long x) {
+  __shared__ long long s[4];
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  __syncthreads();
+  if (lane == 0) s[wid] = x;
+  __syncthreads();
+  x = s[0];
+  for (int w = 1; w < nw; ++w) x += s[w];
+  return x;
+}
+
+// binary exponent step for a measured maximum (0 when it is 0 or not finite)
+__device__ inline int exp_step(double mu) {
+  if (!(mu > 0.0) || !isfinite(mu)) return 0;
+  return ilogb(mu);
+}
+
+// S = -hbar ln phi (eq. SfromPhi); phi <= 0 or not finite -> +inf.
+// Returns 1 for such a point.
+template <typename R>
+__device__ __forceinline__ int write_S(const Args2<R> &a, size_t i, double phi) {
+  const bool ok = phi > 0.0 && isfinite(phi);
+  a.S[i] = ok ? (R)(-a.hbar * log(phi)) : (R)__builtin_huge_val();
+  return ok ? 0 : 1;
+}
+
+// Work-group index -> tile index such that consecutive tiles run on the same
+// XCD (blocks are dispatched round-robin over the 8 XCDs, each with its own
+// L2): tiles sharing cache lines then share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int nblocks) {
+  constexpr int kXcd = 8;
+  const int q = nblocks / kXcd, rem = nblocks % kXcd;
+  const int x = b % kXcd, m = b / kXcd;
+  return x * q + min(x, rem) + m;
+}
+
+}  // namespace sweik

@@ -1,18 +1,19 @@
 // fft_team.hpp -- register/LDS Stockham FFT for gfx950 (wave64).
 //
 // A "team" of P = L/16 threads transforms one complex line of length L
-// (power of two, 16 <= L <= 8192).  Thread t of the team always holds the
-// 16 elements with indices t + P*j, j = 0..15, in registers: on entry these
-// are the input samples, on exit the transform values at the same indices.
-// Stages are Stockham autosort radix-16 steps (the last one radix 2, 4, 8 or
-// 16); the data moves through LDS only between stages, so a line of length
-// L costs ceil(log16 L) - 1 LDS round trips.  Because the first stage reads
-// and the last stage writes the same index pattern, a forward transform, a
-// pointwise spectral product and an inverse transform chain without any
-// extra exchange.
+// (compile-time power of two, 16 <= L <= 4096).  Thread t of the team always
+// holds the 16 elements with indices t + P*j, j = 0..15, in registers: on
+// entry the input samples, on exit the transform values at the same indices.
+// Stages are Stockham autosort steps of radix 16 with spans p = 1, 16, 256
+// (the last one of radix L/p); data moves through LDS only between stages,
+// so a line costs ceil(log16 L) - 1 LDS round trips.  Because the first stage
+// reads and the last stage writes the same index pattern, a forward
+// transform, a pointwise spectral product and an inverse transform chain
+// without any extra exchange.
 //
-// Twiddles come from a table tw[j] = exp(-2 pi i j / Lmax), j < Lmax, built
-// once per solve in double precision.
+// Twiddles come from a table in LDS, twl[k] = exp(-2 pi i k / 2^TWLOG),
+// which the kernel copies once from the solve's global table; each
+// butterfly reads one base value and forms the rest as its powers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -134,18 +135,19 @@ template <int R, bool INV, typename C> struct Dft {
 
 // LDS index with one pad slot every 16 elements (breaks the stride-16
 // pattern of the first Stockham stage).
-__device__ __forceinline__ int lpad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lpad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lds_line_len(int L) { return L + (L >> 4) + 1; }
+__host__ __device__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
 
-// One Stockham stage of radix R on a team line.  p = product of earlier
-// radices; LAST: results stay in registers (index t + P j), else they go to
+// One Stockham stage of radix R and span p on a team line (compile-time
+// L).  Twiddles exp(-2 pi i q k / (p R)) come from the LDS table (base length
+// 2^TWLOG); LAST: results stay in registers (index t + P j), else they go to
 // LDS at the autosort position.
-template <int R, bool INV, bool LAST, typename C>
-__device__ __forceinline__ void stage(C (&v)[16], int t, int P, int p, int L,
-                                      C *lds, const C *__restrict__ tw,
-                                      int lmax_log) {
+template <int L, int R, int p, int TWLOG, bool INV, bool LAST, typename C>
+__device__ __forceinline__ void stage(C (&v)[16], int t, C *lds, const C *twl) {
+  constexpr int P = L / 16;
   constexpr int NB = 16 / R;  // butterflies per thread
-  const int logpr = 31 - __clz(p * R);
+  constexpr int SH = TWLOG - ilog2c(p * R);
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int i = t + P * b;
@@ -153,13 +155,14 @@ __device__ __forceinline__ void stage(C (&v)[16], int t, int P, int p, int L,
     C u[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) u[q] = v[b + q * NB];
-    if (p > 1) {
-      const int sh = lmax_log - logpr;
+    if constexpr (p > 1) {
+      C w[R];
+      w[1] = twl[k << SH];
+      if (INV) w[1] = cconj(w[1]);
 #pragma unroll
-      for (int q = 1; q < R; ++q) {
-        C w = tw[(q * k) << sh];
-        u[q] = INV ? cmulc(u[q], w) : cmul(u[q], w);
-      }
+      for (int q = 2; q < R; ++q) w[q] = cmul(w[q / 2], w[q - q / 2]);
+#pragma unroll
+      for (int q = 1; q < R; ++q) u[q] = cmul(u[q], w[q]);
     }
     Dft<R, INV, C>::run(u);
     if constexpr (LAST) {
@@ -173,36 +176,36 @@ __device__ __forceinline__ void stage(C (&v)[16], int t, int P, int p, int L,
   }
 }
 
-// Complex FFT of length L (16 <= L, power of two) held by a team.
-// lds: the team's private LDS line (lds_line_len(L) elements).
-// Barriers are block-wide: every thread of the block must call this with the
-// same L.  The caller guarantees that no thread still reads `lds` from
-// earlier work (a leading barrier is taken when lead_sync is set).
-template <bool INV, typename C>
-__device__ void team_fft(C (&v)[16], int t, int P, int L, C *lds,
-                         const C *__restrict__ tw, int lmax_log,
-                         bool lead_sync = true) {
-  if (lead_sync) __syncthreads();
-  int p = 1;
-  while (true) {
-    const int r = (L / p) >= 16 ? 16 : (L / p);
-    const bool last = (p * r == L);
-    if (last) {
-      switch (r) {
-        case 16: stage<16, INV, true>(v, t, P, p, L, lds, tw, lmax_log); break;
-        case 8: stage<8, INV, true>(v, t, P, p, L, lds, tw, lmax_log); break;
-        case 4: stage<4, INV, true>(v, t, P, p, L, lds, tw, lmax_log); break;
-        default: stage<2, INV, true>(v, t, P, p, L, lds, tw, lmax_log); break;
-      }
-      return;
-    }
-    // r == 16 here
-    stage<16, INV, false>(v, t, P, p, L, lds, tw, lmax_log);
-    p *= 16;
-    __syncthreads();
+template <int L, typename C>
+__device__ __forceinline__ void lds_gather(C (&v)[16], int t, const C *lds) {
+  constexpr int P = L / 16;
+  __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = lds[lpad(t + P * j)];
-    __syncthreads();
+  for (int j = 0; j < 16; ++j) v[j] = lds[lpad(t + P * j)];
+  __syncthreads();
+}
+
+// Complex FFT of length L held by a team; twl: LDS twiddle table of base
+// length 2^TWLOG >= L.  Barriers are block-wide: every thread of the block
+// calls this.  With lead_sync a barrier first protects LDS data still being
+// read from earlier work.
+template <int L, int TWLOG, bool INV, typename C>
+__device__ __forceinline__ void team_fft(C (&v)[16], int t, C *lds, const C *twl,
+                                         bool lead_sync = true) {
+  static_assert(L >= 16 && L <= 4096 && (L & (L - 1)) == 0, "line length");
+  if (lead_sync) __syncthreads();
+  if constexpr (L == 16) {
+    stage<L, 16, 1, TWLOG, INV, true>(v, t, lds, twl);
+  } else if constexpr (L <= 256) {
+    stage<L, 16, 1, TWLOG, INV, false>(v, t, lds, twl);
+    lds_gather<L>(v, t, lds);
+    stage<L, L / 16, 16, TWLOG, INV, true>(v, t, lds, twl);
+  } else {
+    stage<L, 16, 1, TWLOG, INV, false>(v, t, lds, twl);
+    lds_gather<L>(v, t, lds);
+    stage<L, 16, 16, TWLOG, INV, false>(v, t, lds, twl);
+    lds_gather<L>(v, t, lds);
+    stage<L, L / 256, 256, TWLOG, INV, true>(v, t, lds, twl);
   }
 }
 

@@ -1,0 +1,54 @@
+// geom2d.hpp -- compile-time geometry of the 2D passes, shared by the host
+// planner and the kernels.
+//
+//   row pass     one team of P = H1/16 threads per grid row; 256 threads per
+//                work-group, i.e. rpw = 256 / P rows (at least 1)
+//   column pass  one team of P = M0/16 threads per spectral column; cpw =
+//                256 / P columns per work-group
+//   spectrum     half spectrum of the rows, blocked transposed:
+//                spec[b][k1][rr], RB = 4 (float) or 2 (double) rows per block,
+//                so that one block entry is 32 bytes
+#pragma once
+
+#include <cstddef>
+
+#include "fft_team.hpp"
+
+namespace sweik {
+
+enum RowMode { ROW_GHAT = 0, ROW_PHI0 = 1, ROW_TERM = 2, ROW_ADJ0 = 3, ROW_ADJ = 4 };
+enum ColMode { COL_GHAT = 0, COL_CONV = 1 };
+
+template <typename R> constexpr int spec_rb() { return sizeof(R) == 4 ? 4 : 2; }
+constexpr int kThreads = 256;
+constexpr int row_rpw(int H) { return H / 16 >= kThreads ? 1 : kThreads / (H / 16); }
+constexpr int col_cpw(int M0) { return M0 / 16 >= kThreads ? 1 : kThreads / (M0 / 16); }
+constexpr size_t kLdsDevice = 163840;  // gfx950 limit per work-group
+
+// Row pass LDS: twiddle table (H entries of exp(-2 pi i k / 2H)), one padded
+// line per row, and (when it fits) staging rows for the pointwise operands
+// so that their loads are issued with the spectrum's.
+template <typename R> constexpr size_t row_lds_core(int H) {
+  return sizeof(R) * 2 * ((size_t)H + (size_t)row_rpw(H) * lds_line_len(H));
+}
+template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
+  // per staged row: f (R) + accumulator (double) for the forward terms;
+  // previous term, f, lambda (R) + gradient (double) for the adjoint
+  return (size_t)row_rpw(H) * H *
+         (mode == ROW_TERM ? sizeof(R) + 8 : mode == ROW_PHI0 ? sizeof(R)
+                                           : mode == ROW_ADJ ? 3 * sizeof(R) + 8 : 0);
+}
+template <typename R> constexpr bool row_staged(int H, int mode) {
+  return row_stage_bytes<R>(H, mode) > 0 &&
+         row_lds_core<R>(H) + row_stage_bytes<R>(H, mode) <= kLdsDevice;
+}
+template <typename R> constexpr size_t row_lds_bytes(int H, int mode) {
+  return row_lds_core<R>(H) + (row_staged<R>(H, mode) ? row_stage_bytes<R>(H, mode) : 0);
+}
+// Column pass LDS: twiddle table (M0/2 entries of exp(-2 pi i k / M0)) and
+// one padded line per column.
+template <typename R> constexpr size_t col_lds_bytes(int M0) {
+  return sizeof(R) * 2 * ((size_t)M0 / 2 + (size_t)col_cpw(M0) * lds_line_len(M0));
+}
+
+}  // namespace sweik

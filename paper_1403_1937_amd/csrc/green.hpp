@@ -11,12 +11,14 @@
 //
 // K0 and K1 are evaluated in three ranges:
 //   x <= 2       ascending series (Abramowitz & Stegun 9.6.13 / 9.6.11)
-//   2 < x < 25   trapezoid rule on e^x K_nu(x) = int_0^inf
-//                exp(-2 x sinh^2(t/2)) cosh(nu t) dt, which converges
-//                geometrically because the integrand is analytic in the
-//                strip |Im t| < pi/2
-//   x >= 25      Hankel's asymptotic expansion (A&S 9.7.2), truncated where
-//                the terms stop decreasing or fall below 1e-17
+//   x > 2        for the kernel table: a Chebyshev series of
+//                sqrt(x) e^x K0(x) in t = 4/x - 1 whose coefficients the host
+//                computes once from the integral below;
+//                for single values (K1 at the origin): the trapezoid rule on
+//                e^x K_nu(x) = int_0^inf exp(-2 x sinh^2(t/2)) cosh(nu t) dt
+//                (geometric convergence: the integrand is analytic in the
+//                strip |Im t| < pi/2) below x = 25, Hankel's asymptotic
+//                expansion (A&S 9.7.2) above
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -57,21 +59,43 @@ __device__ inline double k_hankel_scaled(double x, int nu) {
   return sqrt(kPi / (2.0 * x)) * sum;
 }
 
-__device__ inline double bessel_k0(double x) {
-  if (x <= 2.0) {
-    const double q = 0.25 * x * x;
-    double term = 1.0, i0 = 1.0, sh = 0.0, hk = 0.0;
-    for (int k = 1; k < 40; ++k) {
-      term *= q / ((double)k * (double)k);
-      hk += 1.0 / k;
-      i0 += term;
-      sh += term * hk;
-      if (term < 1e-19 * i0) break;
-    }
-    return sh - (log(0.5 * x) + kEulerGamma) * i0;
+// Chebyshev coefficients of g(t) = sqrt(x) e^x K0(x), t = 4/x - 1, for
+// x >= 2 (t in (-1, 1]); built on the host (see bessel_cheb_k0).
+constexpr int kChebK0 = 28;
+struct ChebK0 {
+  double c[kChebK0];
+  float c32[kChebK0];
+};
+
+__device__ __forceinline__ double k0_cheb(double x, const ChebK0 &tab) {
+  const double t = 4.0 / x - 1.0;
+  const double t2 = 2.0 * t;
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int k = kChebK0 - 1; k >= 1; --k) {
+    const double b0 = fma(t2, b1, tab.c[k] - b2);
+    b2 = b1;
+    b1 = b0;
   }
-  if (x < 25.0) return exp(-x) * k_trapezoid_scaled(x, 0);
-  return exp(-x) * k_hankel_scaled(x, 0);
+  const double g = fma(t, b1, tab.c[0] - b2);
+  return exp(-x) * g / sqrt(x);
+}
+
+__device__ inline double bessel_k0_series(double x) {
+  const double q = 0.25 * x * x;
+  double term = 1.0, i0 = 1.0, sh = 0.0, hk = 0.0;
+  for (int k = 1; k < 40; ++k) {
+    term *= q / ((double)k * (double)k);
+    hk += 1.0 / k;
+    i0 += term;
+    sh += term * hk;
+    if (term < 1e-19 * i0) break;
+  }
+  return sh - (log(0.5 * x) + kEulerGamma) * i0;
+}
+
+__device__ inline double bessel_k0_fast(double x, const ChebK0 &tab) {
+  return x <= 2.0 ? bessel_k0_series(x) : k0_cheb(x, tab);
 }
 
 // 1 - a K1(a) for a > 0 without cancellation for small a:
@@ -117,10 +141,50 @@ __device__ inline double kappa0_3d(double beta) {
 }
 
 // kappa at integer offset with squared length r2 (kappa0 given)
-__device__ inline double kappa_2d(double beta, long long r2, double k0v) {
+__device__ inline double kappa_2d(double beta, long long r2, double k0v, const ChebK0 &tab) {
   if (r2 == 0) return k0v;
-  return beta * beta * (0.5 / kPi) * bessel_k0(beta * sqrt((double)r2));
+  return beta * beta * (0.5 / kPi) * bessel_k0_fast(beta * sqrt((double)r2), tab);
 }
+// float32 variant for the FP32 path (relative error ~1e-6)
+__device__ inline float bessel_k0_f32(float x, const ChebK0 &tab) {
+  if (x <= 2.0f) {
+    const float q = 0.25f * x * x;
+    float term = 1.0f, i0 = 1.0f, sh = 0.0f, hk = 0.0f;
+#pragma unroll
+    for (int k = 1; k < 14; ++k) {
+      term *= q / (float)(k * k);
+      hk += 1.0f / (float)k;
+      i0 += term;
+      sh += term * hk;
+    }
+    return sh - (logf(0.5f * x) + (float)kEulerGamma) * i0;
+  }
+  const float t = 4.0f / x - 1.0f;
+  const float t2 = 2.0f * t;
+  float b1 = 0.0f, b2 = 0.0f;
+#pragma unroll
+  for (int k = kChebK0 - 1; k >= 1; --k) {
+    const float b0 = fmaf(t2, b1, tab.c32[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  const float g = fmaf(t, b1, tab.c32[0] - b2);
+  return expf(-x) * g * rsqrtf(x);
+}
+
+template <typename R>
+__device__ inline R kappa_2d_t(double beta, int r2, double k0v, const ChebK0 &tab);
+template <>
+__device__ inline double kappa_2d_t<double>(double beta, int r2, double k0v, const ChebK0 &tab) {
+  return kappa_2d(beta, r2, k0v, tab);
+}
+template <>
+__device__ inline float kappa_2d_t<float>(double beta, int r2, double k0v, const ChebK0 &tab) {
+  if (r2 == 0) return (float)k0v;
+  const float b = (float)beta;
+  return b * b * (float)(0.5 / kPi) * bessel_k0_f32(b * sqrtf((float)r2), tab);
+}
+
 __device__ inline double kappa_3d(double beta, long long r2, double k0v) {
   if (r2 == 0) return k0v;
   const double r = sqrt((double)r2);

@@ -21,8 +21,8 @@ struct Geo2 {
 };
 
 struct Layout {      // byte offsets into the workspace / checkpoint
-  size_t par, red, expo, mu, tw, g, spec, acc, total;
-  size_t ck_expo, ck_phi, ck_terms, ck_total;
+  size_t par, red, expo, mu, tw, g, spec, acc, lam, total;
+  size_t ck_expo, ck_par, ck_g, ck_phi, ck_terms, ck_total;
 };
 
 }  // namespace sweik

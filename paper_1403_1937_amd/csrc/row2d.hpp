@@ -1,0 +1,568 @@
+// row2d.hpp -- row passes of the 2D solve (forward and adjoint).
+//
+// One team of P = H/16 threads per grid row, RPW rows per work-group.  A
+// pass (i) reads its spectral tile (RPW contiguous rows of the blocked
+// spectrum), the twiddle table and the pointwise operands of its rows,
+// (ii) takes the inverse real FFT of each row (complex FFT of length H
+// plus a split step), (iii) applies the pointwise step of its mode, and
+// (iv) takes the forward real FFT of the new forcing and stores the tile.
+#pragma once
+
+#include "common2d.hpp"
+
+namespace sweik {
+
+// Spectral tile of a row work-group: rows [row0, row0 + rows) of the blocked
+// transposed spectrum spec[b][k1][rr].  Element e <-> (local row, column).
+template <typename R, int H> struct RowTile {
+  static constexpr int RB = spec_rb<R>(), RPW = row_rpw(H), LDK = H + 1;
+  static constexpr int NREG = (RPW * LDK + kThreads - 1) / kThreads;  // per thread
+  cplx<R> *base;
+  int rows;
+  __device__ __forceinline__ void init(cplx<R> *spec, int row0, int spec_rows) {
+    rows = min(RPW, spec_rows - row0);
+    if constexpr (RPW >= RB) {
+      base = spec + (size_t)row0 * LDK;
+    } else {
+      const int b = row0 / RB, rr0 = row0 - b * RB;
+      base = spec + ((size_t)b * LDK * RB + rr0);
+    }
+  }
+  __device__ __forceinline__ void map(int e, int &rl, int &k1, int &off) const {
+    if constexpr (RPW >= RB) {
+      constexpr int PER = LDK * RB;
+      const int bl = e / PER, rem = e - bl * PER;
+      k1 = rem / RB;
+      rl = bl * RB + (rem - k1 * RB);
+      off = e;
+    } else {
+      k1 = e / RPW;
+      rl = e - k1 * RPW;
+      off = k1 * RB + rl;
+    }
+  }
+};
+
+template <typename R, int H>
+__device__ __forceinline__ void tile_issue(const RowTile<R, H> &tile, int tid,
+                                           cplx<R> (&tl)[RowTile<R, H>::NREG]) {
+  const int total = tile.rows * (H + 1);
+#pragma unroll
+  for (int u = 0; u < RowTile<R, H>::NREG; ++u) {
+    const int e = tid + u * kThreads;
+    if (e < total) {
+      int rl, k1, off;
+      tile.map(e, rl, k1, off);
+      tl[u] = tile.base[off];
+    }
+  }
+}
+
+template <typename R, int H>
+__device__ __forceinline__ void tile_to_lds(const RowTile<R, H> &tile, int tid,
+                                            const cplx<R> (&tl)[RowTile<R, H>::NREG],
+                                            cplx<R> *lines) {
+  constexpr int LL = lds_line_len(H);
+  const int total = tile.rows * (H + 1);
+#pragma unroll
+  for (int u = 0; u < RowTile<R, H>::NREG; ++u) {
+    const int e = tid + u * kThreads;
+    if (e < total) {
+      int rl, k1, off;
+      tile.map(e, rl, k1, off);
+      lines[rl * LL + lpad(k1)] = tl[u];
+    }
+  }
+}
+
+template <typename R, int H>
+__device__ __forceinline__ void tile_store(const RowTile<R, H> &tile, int tid,
+                                           const cplx<R> *lines) {
+  constexpr int LL = lds_line_len(H);
+  const int total = tile.rows * (H + 1);
+  cplx<R> out[RowTile<R, H>::NREG];
+#pragma unroll
+  for (int u = 0; u < RowTile<R, H>::NREG; ++u) {
+    const int e = tid + u * kThreads;
+    if (e < total) {
+      int rl, k1, off;
+      tile.map(e, rl, k1, off);
+      out[u] = lines[rl * LL + lpad(k1)];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < RowTile<R, H>::NREG; ++u) {
+    const int e = tid + u * kThreads;
+    if (e < total) {
+      int rl, k1, off;
+      tile.map(e, rl, k1, off);
+      tile.base[off] = out[u];
+    }
+  }
+}
+
+// Inverse real FFT of this team's row (already in LDS): on return
+// v[j] = (x[2k], x[2k+1]) * 2 M1, k = t + P j, x the real row (M1 = 2H).
+template <typename R, int H>
+__device__ __forceinline__ void row_c2r(cplx<R> (&v)[16], int t, cplx<R> *line,
+                                        const cplx<R> *twl) {
+  using C = cplx<R>;
+  constexpr int P = H / 16;
+  // split step: Z = (X_k + conj X_{H-k}) + i (X_k - conj X_{H-k}) conj(w^k)
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int k = t + P * j;
+    C xk = line[lpad(k)];
+    C xc = cconj(line[lpad(H - k)]);
+    C e = cadd(xk, xc);
+    C o = cmulc(csub(xk, xc), twl[k]);
+    v[j] = cmake<C>(e.x - o.y, e.y + o.x);
+  }
+  team_fft<H, ilog2c(2 * H), true>(v, t, line, twl, true);
+}
+
+// Forward real FFT of this team's row (v[j] = (x[2k], x[2k+1]), k = t + P j)
+// into its LDS line as the half spectrum (twice the DFT), then the store of
+// the work-group's tile.
+template <typename R, int H>
+__device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[16], int t, int tid,
+                                              cplx<R> *line, const cplx<R> *lines,
+                                              const cplx<R> *twl, const RowTile<R, H> &tile) {
+  using C = cplx<R>;
+  constexpr int P = H / 16;
+  team_fft<H, ilog2c(2 * H), false>(v, t, line, twl, true);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) line[lpad(t + P * j)] = v[j];
+  __syncthreads();
+  C x[16];
+  C xH = cmake<C>((R)0, (R)0);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int k = t + P * j;
+    C zk = line[lpad(k)];
+    C zc = cconj(line[lpad((H - k) & (H - 1))]);
+    C e = cadd(zk, zc);
+    C d = csub(zk, zc);
+    C o = cmake<C>(d.y, -d.x);  // d / i
+    x[j] = cadd(e, cmul(twl[k], o));
+    if (k == 0) xH = cmake<C>((R)2 * (zk.x - zk.y), (R)0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) line[lpad(t + P * j)] = x[j];
+  if (t == 0) line[lpad(H)] = xH;
+  __syncthreads();
+  tile_store(tile, tid, lines);
+}
+
+// ---------------------------------------------------------------------------
+// Row pass, all modes.
+//   ROW_GHAT  kernel table rows (evenly extended), forward real FFT
+//   ROW_PHI0  phi_0 from the sources, first forcing term, forward real FFT
+//   ROW_TERM  term `term`: inverse FFT, rescale, accumulate; then either the
+//             next forcing term and its FFT, or (term == T) S = -hbar ln phi
+//   ROW_ADJ0  adjoint start: lambda = -hbar dL/dS / phi, a_T = (-1)^T lambda
+//   ROW_ADJ   adjoint step `term` = i: b_i = kappa (*) a_i, dL/dgamma +=
+//             phi_{i-1} b_i, a_{i-1} = (-1)^{i-1} lambda + gamma b_i; at
+//             i = 1, dL/df = dL/dgamma 2 f / ftilde^2
+// ---------------------------------------------------------------------------
+template <typename R, int MODE, int H>
+__global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
+  using C = cplx<R>;
+  using Tile = RowTile<R, H>;
+  constexpr int P = H / 16, RPW = row_rpw(H), LL = lds_line_len(H);
+  constexpr int TWLOG = ilog2c(2 * H);
+  constexpr bool STG = row_staged<R>(H, MODE);
+  constexpr int NTW = (H + kThreads - 1) / kThreads;
+  constexpr bool LOADS_TILE = MODE == ROW_TERM || MODE == ROW_ADJ;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / 2H), k < H
+  C *lines = twl + H;
+  unsigned char *stg = reinterpret_cast<unsigned char *>(lines + RPW * LL);
+  __shared__ double s_par[2];
+
+  const int tid = threadIdx.x, team = tid / P, t = tid - team * P;
+  const int row0 = blockIdx.x * RPW, r = row0 + team;
+  C *line = lines + team * LL;
+  const bool row_ok = r < a.n0;
+  const size_t rowoff = (size_t)r * a.n1;
+  const size_t N = (size_t)a.n0 * a.n1;
+  const bool last = (MODE == ROW_TERM && term == a.T) || (MODE == ROW_PHI0 && a.T == 0);
+  Tile tile;
+  tile.init(a.spec, row0, a.nb * spec_rb<R>());
+
+  // staging rows of this team (written and read by the same thread)
+  R *sR = reinterpret_cast<R *>(stg) + (size_t)team * H;                   // first R row
+  constexpr int NRSTG = MODE == ROW_ADJ ? 3 : 1;
+  double *sD = reinterpret_cast<double *>(reinterpret_cast<R *>(stg) + (size_t)RPW * H * NRSTG) +
+               (size_t)team * H;
+
+  // ---- 1. issue the global reads of the pass ------------------------------
+  C twr[NTW];
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) {
+    const int k = tid + u * kThreads;
+    if (k < H) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
+  }
+  C tl[Tile::NREG];
+  if constexpr (LOADS_TILE) tile_issue(tile, tid, tl);
+  // pointwise operands of this thread's columns c = 2(t + P j) + e
+  constexpr int NOP = STG ? 32 : 1;
+  R o1[NOP], o2[NOP], o3[NOP];
+  double od[NOP];
+  if constexpr (STG) {
+    const R *p1 = nullptr, *p2 = nullptr, *p3 = nullptr;
+    const double *pd = nullptr;
+    if (MODE == ROW_PHI0) p1 = last ? nullptr : a.f;
+    if (MODE == ROW_TERM) {
+      p1 = last ? nullptr : a.f;
+      pd = a.acc;
+    }
+    if (MODE == ROW_ADJ) {
+      p1 = a.ck_terms + (size_t)(term - 1) * N;
+      p2 = a.f;
+      p3 = term > 1 ? a.lam : nullptr;
+      pd = term != a.T ? a.acc : nullptr;
+    }
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      const int cc = 2 * (t + P * (q >> 1)) + (q & 1);
+      const bool ok = row_ok && cc < a.n1;
+      o1[q] = (ok && p1) ? p1[rowoff + cc] : (R)0;
+      if (MODE == ROW_ADJ) {
+        o2[q] = (ok && p2) ? p2[rowoff + cc] : (R)0;
+        o3[q] = (ok && p3) ? p3[rowoff + cc] : (R)0;
+      }
+      od[q] = (ok && pd) ? pd[rowoff + cc] : 0.0;
+    }
+  }
+
+  // ---- 2. scalars ----------------------------------------------------------
+  double beta, inv_ft2, ft;
+  if (MODE == ROW_GHAT) {
+    double lo, hi;
+    int fl;
+    reduce_forcing(a.red, a.ft_mode, a.ftilde_given, &lo, &hi, &fl);
+    ft = a.ft_mode == SWEIK_FT_NU ? sqrt(0.5 * (lo * lo + hi * hi))
+         : a.ft_mode == SWEIK_FT_FMAX ? hi : a.ftilde_given;
+    beta = ft * a.h / a.hbar;
+    inv_ft2 = 1.0 / (ft * ft);
+    if (tid == 0) {
+      s_par[0] = kappa0_2d(beta);
+      const double c0 = fmax((hi - ft) * (hi + ft), (ft - lo) * (ft + lo)) * inv_ft2;
+      if (!(c0 < 1.0)) fl |= SWEIK_FLAG_C0_GE_1;
+      for (int k = 0; k < a.n_src; ++k) {
+        const int y0 = a.src[2 * k], y1 = a.src[2 * k + 1];
+        if (y0 < 0 || y0 >= a.n0 || y1 < 0 || y1 >= a.n1) fl |= SWEIK_FLAG_BAD_SOURCE;
+      }
+      if (blockIdx.x == 0) {
+        Params p;
+        p.ftilde = ft;
+        p.beta = beta;
+        p.hbar = a.hbar;
+        p.inv_ft2 = inv_ft2;
+        p.kappa0 = s_par[0];
+        p.fmin = lo;
+        p.fmax = hi;
+        p.c0 = c0;
+        p.flags = fl;
+        p.pad_ = 0;
+        *a.par = p;
+        if (a.info) {
+          a.info->f_min = lo;
+          a.info->f_max = hi;
+          a.info->ftilde = ft;
+          a.info->beta = beta;
+          a.info->c0_bound = c0;
+          a.info->n_nonpositive_phi = 0;
+          a.info->flags = fl;
+          a.info->T = a.T;
+        }
+      }
+    }
+    __syncthreads();
+  } else {
+    beta = a.par->beta;
+    inv_ft2 = a.par->inv_ft2;
+    ft = a.par->ftilde;
+  }
+
+  // exponents: forward phi_i = 2^E_i m_i; adjoint a_i = 2^e_lam (mantissa)
+  int dstep = 0, E = 0, elam = 0;
+  if (MODE == ROW_TERM) {
+    double mu = 0.0;
+    for (int i = tid; i < a.nbr; i += kThreads) mu = fmax(mu, a.mu[(size_t)(term - 1) * a.nbr + i]);
+    mu = block_max(mu);
+    dstep = exp_step(mu);
+    E = a.expo[term - 1] + dstep;
+  }
+  if ((MODE == ROW_TERM || MODE == ROW_PHI0) && blockIdx.x == 0 && tid == 0) {
+    const int slot = MODE == ROW_TERM ? term : 0;
+    a.expo[slot] = E;
+    if (a.info) a.info->scale_exp[slot] = E;
+    if (a.ck_expo) a.ck_expo[slot] = E;
+  }
+  if (MODE == ROW_ADJ0) {
+    double mx = 0.0;
+    for (int i = tid; i < kRedBlocks; i += kThreads) mx = fmax(mx, a.red[i]);
+    mx = block_max(mx);
+    elam = exp_step(mx);
+    if (blockIdx.x == 0 && tid == 0) a.expo[0] = elam;
+  }
+  if (MODE == ROW_ADJ) {
+    __shared__ int s_e[2];
+    if (tid == 0) {
+      s_e[0] = a.expo[0];
+      s_e[1] = a.ck_expo[term - 1];
+    }
+    __syncthreads();
+    elam = s_e[0];
+    E = s_e[1];
+  }
+
+  // ---- 3. operands into LDS -------------------------------------------------
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) {
+    const int k = tid + u * kThreads;
+    if (k < H) twl[k] = twr[u];
+  }
+  if constexpr (LOADS_TILE) tile_to_lds(tile, tid, tl, lines);
+  if constexpr (STG) {
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      // a staging row holds H >= n1 entries
+      const int cc = 2 * (t + P * (q >> 1)) + (q & 1);
+      if (cc < a.n1) {
+        sR[cc] = o1[q];
+        if (MODE == ROW_ADJ) {
+          sR[(size_t)RPW * H + cc] = o2[q];
+          sR[(size_t)2 * RPW * H + cc] = o3[q];
+        }
+        if (MODE == ROW_TERM || MODE == ROW_ADJ) sD[cc] = od[q];
+      }
+    }
+  }
+  __syncthreads();
+
+  // operand access: staged copy or direct global read
+  auto op1 = [&](int cc, const R *g) -> R { return STG ? sR[cc] : g[rowoff + cc]; };
+  auto op2 = [&](int cc, const R *g) -> R { return STG ? sR[(size_t)RPW * H + cc] : g[rowoff + cc]; };
+  auto op3 = [&](int cc, const R *g) -> R { return STG ? sR[(size_t)2 * RPW * H + cc] : g[rowoff + cc]; };
+  auto opd = [&](int cc, const double *g) -> double { return STG ? sD[cc] : g[rowoff + cc]; };
+
+  C v[16];
+
+  // ---- 4. kernel table ------------------------------------------------------
+  if constexpr (MODE == ROW_GHAT) {
+    // Row r of the evenly extended kernel table, x[m] = kappa(r, min(m,
+    // 2H - m)) (zero for offsets >= n1): the first half is evaluated, the
+    // mirrored half is read back through LDS.
+    R *xl = reinterpret_cast<R *>(line);
+    const double k0v = s_par[0];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c0 = 2 * (t + P * j);
+      R z0 = 0, z1 = 0;
+      if (row_ok) {
+        const int rr = r * r;
+        if (c0 < a.n1) z0 = kappa_2d_t<R>(beta, rr + c0 * c0, k0v, a.k0tab);
+        if (c0 + 1 < a.n1) z1 = kappa_2d_t<R>(beta, rr + (c0 + 1) * (c0 + 1), k0v, a.k0tab);
+      }
+      xl[c0] = z0;
+      xl[c0 + 1] = z1;
+      v[j] = cmake<C>(z0, z1);
+    }
+    if (t == 0) xl[H] = (R)0;  // offset H >= n1 is never used
+    __syncthreads();
+#pragma unroll
+    for (int j = 8; j < 16; ++j) {
+      const int c0 = 2 * (t + P * j);
+      v[j] = cmake<C>(xl[2 * H - c0], xl[2 * H - c0 - 1]);
+    }
+    row_r2c_store<R, H>(v, t, tid, line, lines, twl, tile);
+    return;
+  }
+
+  if constexpr (LOADS_TILE) row_c2r<R, H>(v, t, line, twl);
+
+  // ---- 5. pointwise step over columns 2k, 2k+1 (k = t + P j) --------------
+  double mloc = 0.0;
+  long long nbad = 0;
+  if constexpr (MODE == ROW_PHI0 || MODE == ROW_TERM) {
+    const double scale_m = ldexp(1.0, -dstep);
+    const double scale_E = ldexp(1.0, E);
+    const double sgn = (MODE == ROW_TERM && (term & 1)) ? -1.0 : 1.0;
+    const int slot = MODE == ROW_TERM ? term : 0;
+    R *ckt = a.ck_terms ? a.ck_terms + (size_t)slot * N + rowoff : nullptr;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int c0 = 2 * (t + P * j);
+      R z0 = 0, z1 = 0;
+      if (row_ok && c0 < a.n1) {
+        const bool ok1 = c0 + 1 < a.n1;
+        double p0, p1;  // phi after this term
+        R m0, m1;       // stored mantissas of this term
+        if constexpr (MODE == ROW_PHI0) {
+          // phi_0 = sum_k exp(-beta |m - y_k|)  (eq. phi_0Solution, C = 1)
+          double s0 = 0.0, s1 = 0.0;
+          if constexpr (sizeof(R) == 4) {
+            const float nb = (float)(-beta * 1.4426950408889634);  // exp(x) = 2^(x log2 e)
+            float f0 = 0.0f, f1 = 0.0f;
+            for (int k = 0; k < a.n_src; ++k) {
+              const float d0 = (float)(r - a.src[2 * k]);
+              const float d1 = (float)(c0 - a.src[2 * k + 1]);
+              const float q0 = d0 * d0;
+              f0 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + d1 * d1));
+              f1 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + (d1 + 1.0f) * (d1 + 1.0f)));
+            }
+            s0 = f0;
+            s1 = f1;
+          } else {
+            for (int k = 0; k < a.n_src; ++k) {
+              const double d0 = (double)(r - a.src[2 * k]);
+              const double d1 = (double)(c0 - a.src[2 * k + 1]);
+              s0 += exp(-beta * sqrt(d0 * d0 + d1 * d1));
+              s1 += exp(-beta * sqrt(d0 * d0 + (d1 + 1) * (d1 + 1)));
+            }
+          }
+          m0 = (R)s0;
+          m1 = (R)s1;
+          p0 = s0;
+          p1 = s1;
+        } else {
+          m0 = (R)((double)v[j].x * scale_m);
+          m1 = (R)((double)v[j].y * scale_m);
+          p0 = opd(c0, a.acc) + sgn * ((double)m0 * scale_E);
+          p1 = (ok1 ? opd(c0 + 1, a.acc) : 0.0) + sgn * ((double)m1 * scale_E);
+        }
+        if (last) {
+          nbad += write_S(a, rowoff + c0, p0);
+          if (a.ck_phi) a.ck_phi[rowoff + c0] = p0;
+          if (ok1) {
+            nbad += write_S(a, rowoff + c0 + 1, p1);
+            if (a.ck_phi) a.ck_phi[rowoff + c0 + 1] = p1;
+          }
+        } else {
+          a.acc[rowoff + c0] = p0;
+          if (ok1) a.acc[rowoff + c0 + 1] = p1;
+          if (ckt) {
+            ckt[c0] = m0;
+            if (ok1) ckt[c0 + 1] = m1;
+          }
+          // gamma = f^2/ftilde^2 - 1, exactly 0 where f = ftilde
+          const double fa = (double)op1(c0, a.f);
+          z0 = (R)((fa - ft) * (fa + ft) * inv_ft2) * m0;
+          mloc = fmax(mloc, fabs((double)m0));
+          if (ok1) {
+            const double fb = (double)op1(c0 + 1, a.f);
+            z1 = (R)((fb - ft) * (fb + ft) * inv_ft2) * m1;
+            mloc = fmax(mloc, fabs((double)m1));
+          }
+        }
+      }
+      v[j] = cmake<C>(z0, z1);
+    }
+    if (last) {
+      const long long nb = block_sum_ll(nbad);
+      if (tid == 0 && a.info && nb)
+        atomicAdd((unsigned long long *)&a.info->n_nonpositive_phi, (unsigned long long)nb);
+      return;
+    }
+    const double bm = block_max(mloc);
+    if (tid == 0) a.mu[(size_t)slot * a.nbr + blockIdx.x] = bm;
+  }
+
+  if constexpr (MODE == ROW_ADJ0) {
+    // lambda mantissa (scale 2^-e_lam); a_T = (-1)^T lambda
+    const double lam_scale = ldexp(1.0, -elam);
+    const double sgnT = (a.T & 1) ? -1.0 : 1.0;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      R zz[2] = {(R)0, (R)0};
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int cc = 2 * (t + P * j) + e;
+        if (row_ok && cc < a.n1) {
+          const double ph = a.ck_phi[rowoff + cc];
+          double l = 0.0;
+          if (ph > 0.0 && isfinite(ph)) l = -a.hbar * (double)a.dLdS[rowoff + cc] / ph * lam_scale;
+          const R q = (R)l;
+          a.lam[rowoff + cc] = q;
+          zz[e] = (R)(sgnT * (double)q);
+        }
+      }
+      v[j] = cmake<C>(zz[0], zz[1]);
+    }
+  }
+
+  if constexpr (MODE == ROW_ADJ) {
+    const double gscale = ldexp(1.0, E + elam);
+    const double sgn_prev = ((term - 1) & 1) ? -1.0 : 1.0;  // (-1)^(i-1)
+    const R *mprev = a.ck_terms + (size_t)(term - 1) * N;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      R zz[2] = {(R)0, (R)0};
+      const double bb[2] = {(double)v[j].x, (double)v[j].y};
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int cc = 2 * (t + P * j) + e;
+        if (row_ok && cc < a.n1) {
+          // dL/dgamma += phi_{i-1} b_i  (true scale 2^(E_{i-1} + e_lam))
+          double g = (double)op1(cc, mprev) * bb[e] * gscale;
+          if (term != a.T) g += opd(cc, a.acc);
+          const double fa = (double)op2(cc, a.f);
+          if (term > 1) {
+            a.acc[rowoff + cc] = g;
+            const double ga = (fa - ft) * (fa + ft) * inv_ft2;
+            zz[e] = (R)(sgn_prev * (double)op3(cc, a.lam) + ga * bb[e]);
+          } else {
+            // dL/df = dL/dgamma * 2 f / ftilde^2
+            a.dLdf[rowoff + cc] = (R)(g * 2.0 * fa * inv_ft2);
+          }
+        }
+      }
+      v[j] = cmake<C>(zz[0], zz[1]);
+    }
+    if (term == 1) return;
+  }
+
+  // ---- 6. forward real FFT of the new forcing, store the tile --------------
+  row_r2c_store<R, H>(v, t, tid, line, lines, twl, tile);
+}
+
+// Adjoint start: max |lambda| partials (with the twiddle table).
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_prep(const R *__restrict__ dLdS,
+                                                  const double *__restrict__ phi, long long N,
+                                                  double hbar, double *__restrict__ red,
+                                                  cplx<R> *__restrict__ tw, int lmax) {
+  double mx = 0.0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double p = phi[i];
+    if (p > 0.0 && isfinite(p)) {
+      const double l = fabs(hbar * (double)dLdS[i] / p);
+      if (isfinite(l)) mx = l > mx ? l : mx;
+    }
+  }
+  mx = block_max(mx);
+  if (threadIdx.x == 0) red[blockIdx.x] = mx;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < lmax; j += gridDim.x * blockDim.x) {
+    double s, cs;
+    sincospi(2.0 * (double)j / (double)lmax, &s, &cs);
+    cplx<R> w;
+    w.x = (R)cs;
+    w.y = (R)(-s);
+    tw[j] = w;
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_fill(R *__restrict__ out, long long N, R v) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = v;
+}
+
+}  // namespace sweik
