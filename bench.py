@@ -33,11 +33,12 @@ HBM_PEAK_GBPS = 8000.0
 def alg_bytes_2d(n0, n1, H1, H0, esz, T):
     """Algorithmic HBM bytes per kernel class of a 2D forward solve: every
     pass reads its inputs once and writes its outputs once at the stored
-    precision; the spectrum is the n0 x (H1+1) half spectrum, the kernel
-    spectrum the (H1+1) x (H0+1) orthant."""
+    precision; the spectrum is the n0 x H1 half spectrum (the real DC and
+    Nyquist bins share a column), the kernel spectrum the (H1+1) x (H0+1)
+    orthant."""
     N = n0 * n1
     csz = 2 * esz
-    spec = csz * n0 * (H1 + 1)
+    spec = csz * n0 * H1
     ghat = esz * (H1 + 1) * (H0 + 1)
     return {
         "prep": esz * N,

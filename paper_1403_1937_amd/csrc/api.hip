@@ -116,10 +116,18 @@ sweik_status plan2d(sweik_plan_s *pl) {
   g.H0 = (int)(M0 / 2);
   g.ldg = g.H0 + 1;
   g.H1 = (int)(M1 / 2);
-  g.ldk = g.H1 + 1;
+  g.ldk = g.H1;  // spectral columns; column 0 carries bins 0 and H1
   if (M0 > 4096 || g.H1 > 4096 || g.H1 < 32) return SWEIK_EUNSUPPORTED;
   g.RB = p.prec == SWEIK_F64 ? spec_rb<double>() : spec_rb<float>();
   g.nb = (g.n0 + g.RB - 1) / g.RB;
+  // every pass must fit the work-group LDS limit
+  const bool f64 = p.prec == SWEIK_F64;
+  for (int mode = ROW_GHAT; mode <= ROW_ADJ; ++mode) {
+    const size_t b = f64 ? row_lds_bytes<double>(g.H1, mode) : row_lds_bytes<float>(g.H1, mode);
+    if (b > kLdsDevice) return SWEIK_EUNSUPPORTED;
+  }
+  if ((f64 ? col_lds_bytes<double>(g.M0) : col_lds_bytes<float>(g.M0)) > kLdsDevice)
+    return SWEIK_EUNSUPPORTED;
   g.rpw = row_rpw(g.H1);
   g.cpw = col_cpw(g.M0);
   const int spec_rows = g.nb * g.RB;
@@ -145,15 +153,16 @@ sweik_status plan2d(sweik_plan_s *pl) {
   L.expo = take(sizeof(int) * (SWEIK_MAX_TERMS + 1));
   L.mu = take(sizeof(double) * (size_t)(p.T + 1) * g.nbr);
   L.tw = take((size_t)csz * g.lmax);
-  L.g = take((size_t)esz * g.ldk * g.ldg);
+  L.g = take((size_t)esz * (g.ldk + 1) * g.ldg);
   L.spec = take((size_t)csz * g.nb * g.ldk * g.RB);
   L.acc = take(sizeof(double) * N);
   L.lam = take((size_t)esz * N);
+  L.gam = take((size_t)esz * N);
   L.total = off;
   off = 0;
   L.ck_expo = take(sizeof(int) * (SWEIK_MAX_TERMS + 1));
   L.ck_par = take(sizeof(Params));
-  L.ck_g = take((size_t)esz * g.ldk * g.ldg);
+  L.ck_g = take((size_t)esz * (g.ldk + 1) * g.ldg);
   L.ck_phi = take(sizeof(double) * N);
   L.ck_terms = take((size_t)esz * N * (size_t)p.T);
   L.ck_total = off;
@@ -197,6 +206,7 @@ Args2<R> make_args2(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.g = (R *)(w + L.g);
   a.acc = (double *)(w + L.acc);
   a.lam = (R *)(w + L.lam);
+  a.gam = (R *)(w + L.gam);
   a.k0tab = bessel_cheb_k0();
   a.dLdS = nullptr;
   a.dLdf = nullptr;

@@ -9,29 +9,36 @@
 //             kernel spectrum Ghat[k0][k1], inverse FFT, keep the first rows
 //   COL_GHAT  even extension of the column of the kernel table's row
 //             transforms, forward FFT, keep the real part: Ghat
+// Column k1 = 0 holds two real sequences, the DC (re) and Nyquist (im) bins
+// of the rows.  Their transforms A, B are Hermitian, so the product with
+// their own kernel columns is Y = (Ga + Gb)/2 F + (Ga - Gb)/2 conj F(-k)
+// with F = A + iB; the partner value F(-k) comes through LDS.  In the GHAT
+// mode A and B are real: Ghat[.][0] = Re F, Ghat[.][H1] = Im F.
 #pragma once
 
 #include "common2d.hpp"
 
 namespace sweik {
 
-template <typename R, int MODE, int M0>
-__global__ void __launch_bounds__(kThreads) k_col2(Args2<R> a) {
+// FULL: every column of the work-group exists and every loaded row lies in
+// the spectrum, so no element needs a bounds check.
+template <typename R, int MODE, int M0, bool FULL>
+__device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned char *smem_raw) {
   using C = cplx<R>;
   constexpr int P = M0 / 16, CPW = col_cpw(M0), RB = spec_rb<R>(), LL = lds_line_len(M0);
   constexpr int H0 = M0 / 2, TWLOG = ilog2c(M0);
-  constexpr int NTW = (H0 + kThreads - 1) / kThreads;
+  constexpr int NTW = (M0 + kThreads - 1) / kThreads;
   static_assert(P % RB == 0, "column team must cover whole row blocks");
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / M0), k < M0/2
-  C *lines = twl + H0;
+  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / M0), k < M0
+  C *lines = twl + M0;
 
   const int tid = threadIdx.x;
   const int grp = tid / RB, rr = tid - grp * RB;
   const int team = grp % CPW;
   const int t = (grp / CPW) * RB + rr;
-  const int k1 = xcd_tile(blockIdx.x, gridDim.x) * CPW + team;
-  const bool active = k1 < a.ldk;
+  const int k1 = tile * CPW + team;
+  const bool packed_wg = tile == 0;  // holds column 0 (uniform per work-group)
+  const bool active = FULL || k1 < a.ldk;
   C *line = lines + team * LL;
   const int spec_rows = a.nb * RB;
   const size_t cstride = (size_t)a.ldk * RB;  // elements between blocks
@@ -42,16 +49,16 @@ __global__ void __launch_bounds__(kThreads) k_col2(Args2<R> a) {
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int k = tid + u * kThreads;
-    if (k < H0) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
+    if (k < M0) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
   }
   C v[16];
-  R gv[16];
+  R gv[16], gb[16];
   if constexpr (MODE == COL_CONV) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int rho = t + P * j;
       C x = cmake<C>((R)0, (R)0);
-      if (j < 8 && active && rho < spec_rows) {
+      if (j < 8 && (FULL || (active && rho < spec_rows))) {
         const int b = rho / RB;
         x = col[b * cstride + (rho - b * RB)];
       }
@@ -62,6 +69,14 @@ __global__ void __launch_bounds__(kThreads) k_col2(Args2<R> a) {
     for (int j = 0; j < 16; ++j) {
       const int k0 = t + P * j;
       gv[j] = gcol[k0 <= H0 ? k0 : M0 - k0];
+    }
+    if (packed_wg && k1 == 0) {
+      const R *gnyq = a.g + (size_t)a.ldk * a.ldg;  // kernel column of bin H1
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int k0 = t + P * j;
+        gb[j] = gnyq[k0 <= H0 ? k0 : M0 - k0];
+      }
     }
   } else {
     // even extension of the column: x[rho] = x[M0 - rho]
@@ -80,20 +95,40 @@ __global__ void __launch_bounds__(kThreads) k_col2(Args2<R> a) {
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int k = tid + u * kThreads;
-    if (k < H0) twl[k] = twr[u];
+    if (k < M0) twl[k] = twr[u];
   }
   __syncthreads();
 
   team_fft<M0, TWLOG, false>(v, t, line, twl, false);
   if constexpr (MODE == COL_CONV) {
+    if (packed_wg) {
+      C pv[16];
+      __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 16; ++j) v[j] = cscale(v[j], gv[j]);
+      for (int j = 0; j < 16; ++j) line[lpad(t + P * j)] = v[j];
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < 16; ++j) pv[j] = line[lpad((M0 - (t + P * j)) & (M0 - 1))];
+      if (k1 == 0) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const R al = (gv[j] + gb[j]) * (R)0.5, de = (gv[j] - gb[j]) * (R)0.5;
+          v[j] = cadd(cscale(v[j], al), cscale(cconj(pv[j]), de));
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = cscale(v[j], gv[j]);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = cscale(v[j], gv[j]);
+    }
     team_fft<M0, TWLOG, true>(v, t, line, twl, true);
     if (active) {
 #pragma unroll
       for (int j = 0; j < 8; ++j) {
         const int rho = t + P * j;
-        if (rho < spec_rows) {
+        if (FULL || rho < spec_rows) {
           const int b = rho / RB;
           col[b * cstride + (rho - b * RB)] = v[j];
         }
@@ -105,13 +140,27 @@ __global__ void __launch_bounds__(kThreads) k_col2(Args2<R> a) {
       // round trips contribute M0 and 2 M1: store Ghat / (2 M0 M1)
       const double sc = 1.0 / (4.0 * (double)M0 * (double)(2 * a.H1));
       R *gcol = a.g + (size_t)k1 * a.ldg;
+      R *gnyq = a.g + (size_t)a.ldk * a.ldg;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         const int k0 = t + P * j;
-        if (k0 <= H0) gcol[k0] = (R)((double)v[j].x * sc);
+        if (k0 <= H0) {
+          gcol[k0] = (R)((double)v[j].x * sc);
+          if (k1 == 0) gnyq[k0] = (R)((double)v[j].y * sc);
+        }
       }
     }
   }
+}
+
+template <typename R, int MODE, int M0>
+__global__ void __launch_bounds__(kThreads) k_col2(Args2<R> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  if ((tile + 1) * col_cpw(M0) <= a.ldk && a.nb * spec_rb<R>() >= M0 / 2)
+    col_pass<R, MODE, M0, true>(a, tile, smem_raw);
+  else
+    col_pass<R, MODE, M0, false>(a, tile, smem_raw);
 }
 
 }  // namespace sweik

@@ -34,7 +34,7 @@
 
 #include "geom2d.hpp"
 #include "green.hpp"
-#include "../../include/sweik.h"
+#include "sweik.h"
 
 namespace sweik {
 
@@ -48,7 +48,7 @@ struct Params {      // device-side scalars shared by the kernels of a solve
 template <typename R> struct Args2 {
   // geometry
   int n0, n1;      // grid
-  int H1, ldk;     // M1/2, H1+1 spectral columns
+  int H1, ldk;     // M1/2, H1 stored spectral columns (bins 0 and H1 share column 0)
   int M0, H0, ldg; // column FFT length, M0/2, H0+1
   int nb;          // spectral row blocks (spec_rb rows each)
   int nbr;         // number of row-pass WGs
@@ -67,8 +67,9 @@ template <typename R> struct Args2 {
   int *expo;     // T+1 exponents
   const cplx<R> *tw;
   cplx<R> *spec;
-  R *g;          // (H1+1) x (H0+1) kernel spectrum, pre-scaled
+  R *g;          // (H1+1) x (H0+1) kernel spectrum orthant, pre-scaled
   double *acc;   // n0 x n1
+  R *gam;        // n0 x n1 gamma = f^2/ftilde^2 - 1
   ChebK0 k0tab;  // K0 for x > 2
   // adjoint
   const R *dLdS;

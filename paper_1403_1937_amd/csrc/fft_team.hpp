@@ -11,9 +11,8 @@
 // transform, a pointwise spectral product and an inverse transform chain
 // without any extra exchange.
 //
-// Twiddles come from a table in LDS, twl[k] = exp(-2 pi i k / 2^TWLOG),
-// which the kernel copies once from the solve's global table; each
-// butterfly reads one base value and forms the rest as its powers.
+// Twiddles come from a table in LDS, twl[k] = exp(-2 pi i k / 2^TWLOG) for
+// k < 2^TWLOG, which the kernel copies once from the solve's global table.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -156,6 +155,7 @@ __device__ __forceinline__ void stage(C (&v)[16], int t, C *lds, const C *twl) {
 #pragma unroll
     for (int q = 0; q < R; ++q) u[q] = v[b + q * NB];
     if constexpr (p > 1) {
+      // one table read per butterfly; the other twiddles are its powers
       C w[R];
       w[1] = twl[k << SH];
       if (INV) w[1] = cconj(w[1]);
@@ -185,8 +185,8 @@ __device__ __forceinline__ void lds_gather(C (&v)[16], int t, const C *lds) {
   __syncthreads();
 }
 
-// Complex FFT of length L held by a team; twl: LDS twiddle table of base
-// length 2^TWLOG >= L.  Barriers are block-wide: every thread of the block
+// Complex FFT of length L held by a team; twl: LDS twiddle table with all
+// 2^TWLOG >= L entries.  Barriers are block-wide: every thread of the block
 // calls this.  With lead_sync a barrier first protects LDS data still being
 // read from earlier work.
 template <int L, int TWLOG, bool INV, typename C>

@@ -25,15 +25,15 @@ constexpr int row_rpw(int H) { return H / 16 >= kThreads ? 1 : kThreads / (H / 1
 constexpr int col_cpw(int M0) { return M0 / 16 >= kThreads ? 1 : kThreads / (M0 / 16); }
 constexpr size_t kLdsDevice = 163840;  // gfx950 limit per work-group
 
-// Row pass LDS: twiddle table (H entries of exp(-2 pi i k / 2H)), one padded
+// Row pass LDS: twiddle table (2H entries of exp(-2 pi i k / 2H)), one padded
 // line per row, and (when it fits) staging rows for the pointwise operands
 // so that their loads are issued with the spectrum's.
 template <typename R> constexpr size_t row_lds_core(int H) {
-  return sizeof(R) * 2 * ((size_t)H + (size_t)row_rpw(H) * lds_line_len(H));
+  return sizeof(R) * 2 * ((size_t)2 * H + (size_t)row_rpw(H) * lds_line_len(H));
 }
 template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
-  // per staged row: f (R) + accumulator (double) for the forward terms;
-  // previous term, f, lambda (R) + gradient (double) for the adjoint
+  // per staged row: gamma (R) + accumulator (double) for the forward terms;
+  // previous term, gamma or f, lambda (R) + gradient (double) for the adjoint
   return (size_t)row_rpw(H) * H *
          (mode == ROW_TERM ? sizeof(R) + 8 : mode == ROW_PHI0 ? sizeof(R)
                                            : mode == ROW_ADJ ? 3 * sizeof(R) + 8 : 0);
@@ -45,10 +45,10 @@ template <typename R> constexpr bool row_staged(int H, int mode) {
 template <typename R> constexpr size_t row_lds_bytes(int H, int mode) {
   return row_lds_core<R>(H) + (row_staged<R>(H, mode) ? row_stage_bytes<R>(H, mode) : 0);
 }
-// Column pass LDS: twiddle table (M0/2 entries of exp(-2 pi i k / M0)) and
+// Column pass LDS: twiddle table (M0 entries of exp(-2 pi i k / M0)) and
 // one padded line per column.
 template <typename R> constexpr size_t col_lds_bytes(int M0) {
-  return sizeof(R) * 2 * ((size_t)M0 / 2 + (size_t)col_cpw(M0) * lds_line_len(M0));
+  return sizeof(R) * 2 * ((size_t)M0 + (size_t)col_cpw(M0) * lds_line_len(M0));
 }
 
 }  // namespace sweik

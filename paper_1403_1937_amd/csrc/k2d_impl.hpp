@@ -17,11 +17,14 @@ template <typename K> static hipError_t set_lds(K kernel, size_t bytes) {
 template <typename R, int MODE, int H>
 static hipError_t row_one(dim3 grid, hipStream_t st, const Args2<R> &a, int term) {
   constexpr size_t lds = row_lds_bytes<R>(H, MODE);
-  static_assert(lds <= kLdsDevice, "row pass LDS");
-  static const hipError_t attr = set_lds(k_row2<R, MODE, H>, lds);
-  if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL((k_row2<R, MODE, H>), grid, dim3(kThreads), lds, st, a, term);
-  return hipGetLastError();
+  if constexpr (lds > kLdsDevice) {  // rejected by the planner
+    return hipErrorInvalidValue;
+  } else {
+    static const hipError_t attr = set_lds(k_row2<R, MODE, H>, lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k_row2<R, MODE, H>), grid, dim3(kThreads), lds, st, a, term);
+    return hipGetLastError();
+  }
 }
 
 template <typename R, int MODE>
@@ -54,11 +57,14 @@ hipError_t launch_row2(int mode, int H, dim3 grid, hipStream_t st, const Args2<R
 template <typename R, int MODE, int M0>
 static hipError_t col_one(dim3 grid, hipStream_t st, const Args2<R> &a) {
   constexpr size_t lds = col_lds_bytes<R>(M0);
-  static_assert(lds <= kLdsDevice, "column pass LDS");
-  static const hipError_t attr = set_lds(k_col2<R, MODE, M0>, lds);
-  if (attr != hipSuccess) return attr;
-  hipLaunchKernelGGL((k_col2<R, MODE, M0>), grid, dim3(kThreads), lds, st, a);
-  return hipGetLastError();
+  if constexpr (lds > kLdsDevice) {  // rejected by the planner
+    return hipErrorInvalidValue;
+  } else {
+    static const hipError_t attr = set_lds(k_col2<R, MODE, M0>, lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k_col2<R, MODE, M0>), grid, dim3(kThreads), lds, st, a);
+    return hipGetLastError();
+  }
 }
 
 template <typename R, int MODE>

@@ -6,7 +6,7 @@
 #include <cstddef>
 #include <cstdint>
 
-#include "../../include/sweik.h"
+#include "sweik.h"
 
 namespace sweik {
 
@@ -21,7 +21,7 @@ struct Geo2 {
 };
 
 struct Layout {      // byte offsets into the workspace / checkpoint
-  size_t par, red, expo, mu, tw, g, spec, acc, lam, total;
+  size_t par, red, expo, mu, tw, g, spec, acc, lam, gam, total;
   size_t ck_expo, ck_par, ck_g, ck_phi, ck_terms, ck_total;
 };
 

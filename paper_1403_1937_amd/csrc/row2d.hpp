@@ -13,9 +13,11 @@
 namespace sweik {
 
 // Spectral tile of a row work-group: rows [row0, row0 + rows) of the blocked
-// transposed spectrum spec[b][k1][rr].  Element e <-> (local row, column).
+// transposed spectrum spec[b][k1][rr], k1 < H (column 0 holds the real DC
+// and Nyquist bins of the row as one complex number).  Element e <-> (local
+// row, column).
 template <typename R, int H> struct RowTile {
-  static constexpr int RB = spec_rb<R>(), RPW = row_rpw(H), LDK = H + 1;
+  static constexpr int RB = spec_rb<R>(), RPW = row_rpw(H), LDK = H;
   static constexpr int NREG = (RPW * LDK + kThreads - 1) / kThreads;  // per thread
   cplx<R> *base;
   int rows;
@@ -43,14 +45,14 @@ template <typename R, int H> struct RowTile {
   }
 };
 
-template <typename R, int H>
+template <bool FULL, typename R, int H>
 __device__ __forceinline__ void tile_issue(const RowTile<R, H> &tile, int tid,
                                            cplx<R> (&tl)[RowTile<R, H>::NREG]) {
-  const int total = tile.rows * (H + 1);
+  const int total = tile.rows * H;
 #pragma unroll
   for (int u = 0; u < RowTile<R, H>::NREG; ++u) {
     const int e = tid + u * kThreads;
-    if (e < total) {
+    if (FULL || e < total) {
       int rl, k1, off;
       tile.map(e, rl, k1, off);
       tl[u] = tile.base[off];
@@ -58,16 +60,16 @@ __device__ __forceinline__ void tile_issue(const RowTile<R, H> &tile, int tid,
   }
 }
 
-template <typename R, int H>
+template <bool FULL, typename R, int H>
 __device__ __forceinline__ void tile_to_lds(const RowTile<R, H> &tile, int tid,
                                             const cplx<R> (&tl)[RowTile<R, H>::NREG],
                                             cplx<R> *lines) {
   constexpr int LL = lds_line_len(H);
-  const int total = tile.rows * (H + 1);
+  const int total = tile.rows * H;
 #pragma unroll
   for (int u = 0; u < RowTile<R, H>::NREG; ++u) {
     const int e = tid + u * kThreads;
-    if (e < total) {
+    if (FULL || e < total) {
       int rl, k1, off;
       tile.map(e, rl, k1, off);
       lines[rl * LL + lpad(k1)] = tl[u];
@@ -75,16 +77,16 @@ __device__ __forceinline__ void tile_to_lds(const RowTile<R, H> &tile, int tid,
   }
 }
 
-template <typename R, int H>
+template <bool FULL, typename R, int H>
 __device__ __forceinline__ void tile_store(const RowTile<R, H> &tile, int tid,
                                            const cplx<R> *lines) {
   constexpr int LL = lds_line_len(H);
-  const int total = tile.rows * (H + 1);
+  const int total = tile.rows * H;
   cplx<R> out[RowTile<R, H>::NREG];
 #pragma unroll
   for (int u = 0; u < RowTile<R, H>::NREG; ++u) {
     const int e = tid + u * kThreads;
-    if (e < total) {
+    if (FULL || e < total) {
       int rl, k1, off;
       tile.map(e, rl, k1, off);
       out[u] = lines[rl * LL + lpad(k1)];
@@ -93,7 +95,7 @@ __device__ __forceinline__ void tile_store(const RowTile<R, H> &tile, int tid,
 #pragma unroll
   for (int u = 0; u < RowTile<R, H>::NREG; ++u) {
     const int e = tid + u * kThreads;
-    if (e < total) {
+    if (FULL || e < total) {
       int rl, k1, off;
       tile.map(e, rl, k1, off);
       tile.base[off] = out[u];
@@ -108,23 +110,25 @@ __device__ __forceinline__ void row_c2r(cplx<R> (&v)[16], int t, cplx<R> *line,
                                         const cplx<R> *twl) {
   using C = cplx<R>;
   constexpr int P = H / 16;
-  // split step: Z = (X_k + conj X_{H-k}) + i (X_k - conj X_{H-k}) conj(w^k)
+  // split step: Z = (X_k + conj X_{H-k}) + i (X_k - conj X_{H-k}) conj(w^k);
+  // for k = 0 the stored pair (X_0, X_H) gives Z = (X_0 + X_H, X_0 - X_H)
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int k = t + P * j;
     C xk = line[lpad(k)];
-    C xc = cconj(line[lpad(H - k)]);
+    C xc = cconj(line[lpad((H - k) & (H - 1))]);
     C e = cadd(xk, xc);
     C o = cmulc(csub(xk, xc), twl[k]);
     v[j] = cmake<C>(e.x - o.y, e.y + o.x);
+    if (k == 0) v[j] = cmake<C>(xk.x + xk.y, xk.x - xk.y);
   }
   team_fft<H, ilog2c(2 * H), true>(v, t, line, twl, true);
 }
 
 // Forward real FFT of this team's row (v[j] = (x[2k], x[2k+1]), k = t + P j)
-// into its LDS line as the half spectrum (twice the DFT), then the store of
-// the work-group's tile.
-template <typename R, int H>
+// into its LDS line as the half spectrum (twice the DFT, bins 0 and H packed
+// into column 0), then the store of the work-group's tile.
+template <bool FULL, typename R, int H>
 __device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[16], int t, int tid,
                                               cplx<R> *line, const cplx<R> *lines,
                                               const cplx<R> *twl, const RowTile<R, H> &tile) {
@@ -136,7 +140,6 @@ __device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[16], int t, int tid,
   for (int j = 0; j < 16; ++j) line[lpad(t + P * j)] = v[j];
   __syncthreads();
   C x[16];
-  C xH = cmake<C>((R)0, (R)0);
 #pragma unroll
   for (int j = 0; j < 16; ++j) {
     const int k = t + P * j;
@@ -146,14 +149,14 @@ __device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[16], int t, int tid,
     C d = csub(zk, zc);
     C o = cmake<C>(d.y, -d.x);  // d / i
     x[j] = cadd(e, cmul(twl[k], o));
-    if (k == 0) xH = cmake<C>((R)2 * (zk.x - zk.y), (R)0);
+    // k = 0: the real bins X_0 and X_H travel together
+    if (k == 0) x[j] = cmake<C>((R)2 * (zk.x + zk.y), (R)2 * (zk.x - zk.y));
   }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < 16; ++j) line[lpad(t + P * j)] = x[j];
-  if (t == 0) line[lpad(H)] = xH;
   __syncthreads();
-  tile_store(tile, tid, lines);
+  tile_store<FULL>(tile, tid, lines);
 }
 
 // ---------------------------------------------------------------------------
@@ -167,28 +170,32 @@ __device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[16], int t, int tid,
 //             phi_{i-1} b_i, a_{i-1} = (-1)^{i-1} lambda + gamma b_i; at
 //             i = 1, dL/df = dL/dgamma 2 f / ftilde^2
 // ---------------------------------------------------------------------------
-template <typename R, int MODE, int H>
-__global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
+// FULL: every row of the work-group lies in the grid and n1 == H, so no
+// element needs a bounds check (columns >= H are zero padding, known
+// statically).
+template <typename R, int MODE, int H, bool FULL>
+__device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned char *smem_raw) {
   using C = cplx<R>;
   using Tile = RowTile<R, H>;
   constexpr int P = H / 16, RPW = row_rpw(H), LL = lds_line_len(H);
   constexpr int TWLOG = ilog2c(2 * H);
   constexpr bool STG = row_staged<R>(H, MODE);
-  constexpr int NTW = (H + kThreads - 1) / kThreads;
+  constexpr int NTW = (2 * H + kThreads - 1) / kThreads;
   constexpr bool LOADS_TILE = MODE == ROW_TERM || MODE == ROW_ADJ;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / 2H), k < H
-  C *lines = twl + H;
+  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / 2H), k < 2H
+  C *lines = twl + 2 * H;
   unsigned char *stg = reinterpret_cast<unsigned char *>(lines + RPW * LL);
   __shared__ double s_par[2];
 
   const int tid = threadIdx.x, team = tid / P, t = tid - team * P;
   const int row0 = blockIdx.x * RPW, r = row0 + team;
   C *line = lines + team * LL;
-  const bool row_ok = r < a.n0;
+  const bool row_ok = FULL || r < a.n0;
   const size_t rowoff = (size_t)r * a.n1;
   const size_t N = (size_t)a.n0 * a.n1;
   const bool last = (MODE == ROW_TERM && term == a.T) || (MODE == ROW_PHI0 && a.T == 0);
+  // column c of this thread's pair j (c = 2(t + P j) + e) lies in the grid
+  auto col_ok = [&](int c) { return FULL ? true : (row_ok && c < a.n1); };
   Tile tile;
   tile.init(a.spec, row0, a.nb * spec_rb<R>());
 
@@ -203,12 +210,12 @@ __global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int k = tid + u * kThreads;
-    if (k < H) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
+    if (k < 2 * H) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
   }
   C tl[Tile::NREG];
-  if constexpr (LOADS_TILE) tile_issue(tile, tid, tl);
+  if constexpr (LOADS_TILE) tile_issue<FULL>(tile, tid, tl);
   // pointwise operands of this thread's columns c = 2(t + P j) + e
-  constexpr int NOP = STG ? 32 : 1;
+  constexpr int NOP = STG ? 16 : 1;
   R o1[NOP], o2[NOP], o3[NOP];
   double od[NOP];
   if constexpr (STG) {
@@ -216,25 +223,53 @@ __global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
     const double *pd = nullptr;
     if (MODE == ROW_PHI0) p1 = last ? nullptr : a.f;
     if (MODE == ROW_TERM) {
-      p1 = last ? nullptr : a.f;
+      p1 = last ? nullptr : a.gam;
       pd = a.acc;
     }
     if (MODE == ROW_ADJ) {
       p1 = a.ck_terms + (size_t)(term - 1) * N;
-      p2 = a.f;
+      p2 = term > 1 ? a.gam : a.f;
       p3 = term > 1 ? a.lam : nullptr;
       pd = term != a.T ? a.acc : nullptr;
     }
+    // columns 2(t + P j) for j >= 8 are >= H >= n1: zero padding
+    if ((a.n1 & 1) == 0) {  // column pairs are aligned: vector loads
 #pragma unroll
-    for (int q = 0; q < 32; ++q) {
-      const int cc = 2 * (t + P * (q >> 1)) + (q & 1);
-      const bool ok = row_ok && cc < a.n1;
-      o1[q] = (ok && p1) ? p1[rowoff + cc] : (R)0;
-      if (MODE == ROW_ADJ) {
-        o2[q] = (ok && p2) ? p2[rowoff + cc] : (R)0;
-        o3[q] = (ok && p3) ? p3[rowoff + cc] : (R)0;
+      for (int j = 0; j < 8; ++j) {
+        const int c0 = 2 * (t + P * j);
+        const bool ok = col_ok(c0);
+        using V = cplx<R>;  // a pair of R
+        V x1 = cmake<V>((R)0, (R)0), x2 = x1, x3 = x1;
+        double2 xd = make_double2(0.0, 0.0);
+        if (ok && p1) x1 = *reinterpret_cast<const V *>(p1 + rowoff + c0);
+        if (MODE == ROW_ADJ) {
+          if (ok && p2) x2 = *reinterpret_cast<const V *>(p2 + rowoff + c0);
+          if (ok && p3) x3 = *reinterpret_cast<const V *>(p3 + rowoff + c0);
+        }
+        if (ok && pd) xd = *reinterpret_cast<const double2 *>(pd + rowoff + c0);
+        o1[2 * j] = x1.x;
+        o1[2 * j + 1] = x1.y;
+        if (MODE == ROW_ADJ) {
+          o2[2 * j] = x2.x;
+          o2[2 * j + 1] = x2.y;
+          o3[2 * j] = x3.x;
+          o3[2 * j + 1] = x3.y;
+        }
+        od[2 * j] = xd.x;
+        od[2 * j + 1] = xd.y;
       }
-      od[q] = (ok && pd) ? pd[rowoff + cc] : 0.0;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int cc = 2 * (t + P * (q >> 1)) + (q & 1);
+        const bool ok = col_ok(cc);
+        o1[q] = (ok && p1) ? p1[rowoff + cc] : (R)0;
+        if (MODE == ROW_ADJ) {
+          o2[q] = (ok && p2) ? p2[rowoff + cc] : (R)0;
+          o3[q] = (ok && p3) ? p3[rowoff + cc] : (R)0;
+        }
+        od[q] = (ok && pd) ? pd[rowoff + cc] : 0.0;
+      }
     }
   }
 
@@ -321,19 +356,25 @@ __global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
     E = s_e[1];
   }
 
+  // sources of phi_0 (the first kSrcLds of them through LDS)
+  constexpr int kSrcLds = MODE == ROW_PHI0 ? 512 : 1;
+  __shared__ int s_src[2 * kSrcLds];
+  if (MODE == ROW_PHI0)
+    for (int i = tid; i < 2 * min(a.n_src, kSrcLds); i += kThreads) s_src[i] = a.src[i];
+
   // ---- 3. operands into LDS -------------------------------------------------
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int k = tid + u * kThreads;
-    if (k < H) twl[k] = twr[u];
+    if (k < 2 * H) twl[k] = twr[u];
   }
-  if constexpr (LOADS_TILE) tile_to_lds(tile, tid, tl, lines);
+  if constexpr (LOADS_TILE) tile_to_lds<FULL>(tile, tid, tl, lines);
   if constexpr (STG) {
 #pragma unroll
-    for (int q = 0; q < 32; ++q) {
+    for (int q = 0; q < 16; ++q) {
       // a staging row holds H >= n1 entries
       const int cc = 2 * (t + P * (q >> 1)) + (q & 1);
-      if (cc < a.n1) {
+      if (FULL || cc < a.n1) {
         sR[cc] = o1[q];
         if (MODE == ROW_ADJ) {
           sR[(size_t)RPW * H + cc] = o2[q];
@@ -380,27 +421,30 @@ __global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
       const int c0 = 2 * (t + P * j);
       v[j] = cmake<C>(xl[2 * H - c0], xl[2 * H - c0 - 1]);
     }
-    row_r2c_store<R, H>(v, t, tid, line, lines, twl, tile);
+    row_r2c_store<FULL, R, H>(v, t, tid, line, lines, twl, tile);
     return;
   }
 
   if constexpr (LOADS_TILE) row_c2r<R, H>(v, t, line, twl);
+  // the forcing of the next FFT is zero in the padding half (columns >= H)
+#pragma unroll
+  for (int j = 8; j < 16; ++j) v[j] = cmake<C>((R)0, (R)0);
 
   // ---- 5. pointwise step over columns 2k, 2k+1 (k = t + P j) --------------
-  double mloc = 0.0;
   long long nbad = 0;
   if constexpr (MODE == ROW_PHI0 || MODE == ROW_TERM) {
-    const double scale_m = ldexp(1.0, -dstep);
-    const double scale_E = ldexp(1.0, E);
-    const double sgn = (MODE == ROW_TERM && (term & 1)) ? -1.0 : 1.0;
+    const bool even_n1 = FULL || (a.n1 & 1) == 0;
+    const R sm = (R)ldexp(1.0, -dstep);
+    const double sE = ((MODE == ROW_TERM && (term & 1)) ? -1.0 : 1.0) * ldexp(1.0, E);
+    R mlr = (R)0;
     const int slot = MODE == ROW_TERM ? term : 0;
     R *ckt = a.ck_terms ? a.ck_terms + (size_t)slot * N + rowoff : nullptr;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < 8; ++j) {
       const int c0 = 2 * (t + P * j);
       R z0 = 0, z1 = 0;
-      if (row_ok && c0 < a.n1) {
-        const bool ok1 = c0 + 1 < a.n1;
+      if (col_ok(c0)) {
+        const bool ok1 = FULL || c0 + 1 < a.n1;
         double p0, p1;  // phi after this term
         R m0, m1;       // stored mantissas of this term
         if constexpr (MODE == ROW_PHI0) {
@@ -410,8 +454,10 @@ __global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
             const float nb = (float)(-beta * 1.4426950408889634);  // exp(x) = 2^(x log2 e)
             float f0 = 0.0f, f1 = 0.0f;
             for (int k = 0; k < a.n_src; ++k) {
-              const float d0 = (float)(r - a.src[2 * k]);
-              const float d1 = (float)(c0 - a.src[2 * k + 1]);
+              const int y0 = k < kSrcLds ? s_src[2 * k] : a.src[2 * k];
+              const int y1 = k < kSrcLds ? s_src[2 * k + 1] : a.src[2 * k + 1];
+              const float d0 = (float)(r - y0);
+              const float d1 = (float)(c0 - y1);
               const float q0 = d0 * d0;
               f0 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + d1 * d1));
               f1 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + (d1 + 1.0f) * (d1 + 1.0f)));
@@ -420,8 +466,10 @@ __global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
             s1 = f1;
           } else {
             for (int k = 0; k < a.n_src; ++k) {
-              const double d0 = (double)(r - a.src[2 * k]);
-              const double d1 = (double)(c0 - a.src[2 * k + 1]);
+              const int y0 = k < kSrcLds ? s_src[2 * k] : a.src[2 * k];
+              const int y1 = k < kSrcLds ? s_src[2 * k + 1] : a.src[2 * k + 1];
+              const double d0 = (double)(r - y0);
+              const double d1 = (double)(c0 - y1);
               s0 += exp(-beta * sqrt(d0 * d0 + d1 * d1));
               s1 += exp(-beta * sqrt(d0 * d0 + (d1 + 1) * (d1 + 1)));
             }
@@ -431,10 +479,10 @@ __global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
           p0 = s0;
           p1 = s1;
         } else {
-          m0 = (R)((double)v[j].x * scale_m);
-          m1 = (R)((double)v[j].y * scale_m);
-          p0 = opd(c0, a.acc) + sgn * ((double)m0 * scale_E);
-          p1 = (ok1 ? opd(c0 + 1, a.acc) : 0.0) + sgn * ((double)m1 * scale_E);
+          m0 = v[j].x * sm;  // power-of-two rescale: exact
+          m1 = v[j].y * sm;
+          p0 = fma((double)m0, sE, opd(c0, a.acc));
+          p1 = ok1 ? fma((double)m1, sE, opd(c0 + 1, a.acc)) : 0.0;
         }
         if (last) {
           nbad += write_S(a, rowoff + c0, p0);
@@ -444,21 +492,36 @@ __global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
             if (a.ck_phi) a.ck_phi[rowoff + c0 + 1] = p1;
           }
         } else {
-          a.acc[rowoff + c0] = p0;
-          if (ok1) a.acc[rowoff + c0 + 1] = p1;
+          if (even_n1)
+            *reinterpret_cast<double2 *>(a.acc + rowoff + c0) = make_double2(p0, p1);
+          else {
+            a.acc[rowoff + c0] = p0;
+            if (ok1) a.acc[rowoff + c0 + 1] = p1;
+          }
           if (ckt) {
             ckt[c0] = m0;
             if (ok1) ckt[c0 + 1] = m1;
           }
-          // gamma = f^2/ftilde^2 - 1, exactly 0 where f = ftilde
-          const double fa = (double)op1(c0, a.f);
-          z0 = (R)((fa - ft) * (fa + ft) * inv_ft2) * m0;
-          mloc = fmax(mloc, fabs((double)m0));
-          if (ok1) {
-            const double fb = (double)op1(c0 + 1, a.f);
-            z1 = (R)((fb - ft) * (fb + ft) * inv_ft2) * m1;
-            mloc = fmax(mloc, fabs((double)m1));
+          // gamma = f^2/ftilde^2 - 1 (exactly 0 where f = ftilde); the
+          // first pass forms it from f and keeps it for the later ones
+          R g0, g1 = (R)0;
+          if constexpr (MODE == ROW_PHI0) {
+            const double fa = (double)op1(c0, a.f);
+            g0 = (R)((fa - ft) * (fa + ft) * inv_ft2);
+            a.gam[rowoff + c0] = g0;
+            if (ok1) {
+              const double fb = (double)op1(c0 + 1, a.f);
+              g1 = (R)((fb - ft) * (fb + ft) * inv_ft2);
+              a.gam[rowoff + c0 + 1] = g1;
+            }
+          } else {
+            g0 = op1(c0, a.gam);
+            if (ok1) g1 = op1(c0 + 1, a.gam);
           }
+          z0 = g0 * m0;
+          z1 = g1 * m1;
+          mlr = fmax(mlr, fabs(m0));
+          if (ok1) mlr = fmax(mlr, fabs(m1));
         }
       }
       v[j] = cmake<C>(z0, z1);
@@ -469,7 +532,7 @@ __global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
         atomicAdd((unsigned long long *)&a.info->n_nonpositive_phi, (unsigned long long)nb);
       return;
     }
-    const double bm = block_max(mloc);
+    const double bm = block_max((double)mlr);
     if (tid == 0) a.mu[(size_t)slot * a.nbr + blockIdx.x] = bm;
   }
 
@@ -478,12 +541,14 @@ __global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
     const double lam_scale = ldexp(1.0, -elam);
     const double sgnT = (a.T & 1) ? -1.0 : 1.0;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < 8; ++j) {
       R zz[2] = {(R)0, (R)0};
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int cc = 2 * (t + P * j) + e;
-        if (row_ok && cc < a.n1) {
+        if (col_ok(cc)) {
+          const double fa = (double)a.f[rowoff + cc];
+          a.gam[rowoff + cc] = (R)((fa - ft) * (fa + ft) * inv_ft2);
           const double ph = a.ck_phi[rowoff + cc];
           double l = 0.0;
           if (ph > 0.0 && isfinite(ph)) l = -a.hbar * (double)a.dLdS[rowoff + cc] / ph * lam_scale;
@@ -501,23 +566,23 @@ __global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
     const double sgn_prev = ((term - 1) & 1) ? -1.0 : 1.0;  // (-1)^(i-1)
     const R *mprev = a.ck_terms + (size_t)(term - 1) * N;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < 8; ++j) {
       R zz[2] = {(R)0, (R)0};
       const double bb[2] = {(double)v[j].x, (double)v[j].y};
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const int cc = 2 * (t + P * j) + e;
-        if (row_ok && cc < a.n1) {
+        if (col_ok(cc)) {
           // dL/dgamma += phi_{i-1} b_i  (true scale 2^(E_{i-1} + e_lam))
           double g = (double)op1(cc, mprev) * bb[e] * gscale;
           if (term != a.T) g += opd(cc, a.acc);
-          const double fa = (double)op2(cc, a.f);
           if (term > 1) {
             a.acc[rowoff + cc] = g;
-            const double ga = (fa - ft) * (fa + ft) * inv_ft2;
+            const double ga = (double)op2(cc, a.gam);
             zz[e] = (R)(sgn_prev * (double)op3(cc, a.lam) + ga * bb[e]);
           } else {
             // dL/df = dL/dgamma * 2 f / ftilde^2
+            const double fa = (double)op2(cc, a.f);
             a.dLdf[rowoff + cc] = (R)(g * 2.0 * fa * inv_ft2);
           }
         }
@@ -528,7 +593,17 @@ __global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
   }
 
   // ---- 6. forward real FFT of the new forcing, store the tile --------------
-  row_r2c_store<R, H>(v, t, tid, line, lines, twl, tile);
+  row_r2c_store<FULL, R, H>(v, t, tid, line, lines, twl, tile);
+}
+
+template <typename R, int MODE, int H>
+__global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int row0 = blockIdx.x * row_rpw(H);
+  if (row0 + row_rpw(H) <= a.n0 && a.n1 == H)
+    row_pass<R, MODE, H, true>(a, term, smem_raw);
+  else
+    row_pass<R, MODE, H, false>(a, term, smem_raw);
 }
 
 // Adjoint start: max |lambda| partials (with the twiddle table).
