@@ -10,6 +10,7 @@
 #include <new>
 #include <set>
 #include <tuple>
+#include <vector>
 
 #include "launch2d.hpp"
 #include "plan.hpp"
@@ -293,6 +294,179 @@ sweik_status enqueue2d_adjoint(const sweik_plan_s *pl, const void *f, const int3
   return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
 
+
+// ---- uneven batches ---------------------------------------------------------
+// Instances are grouped into size classes of equal (H1, M0): one launch per
+// pass and class covers every instance of the class.  The per-instance
+// arguments (BatchItem) live at the head of the workspace; they are written
+// from a pinned host staging buffer by an asynchronous copy at the start of
+// every solve.  Class chains run on forked streams joined back into the
+// caller's stream.
+struct BatchClass {
+  int H1, M0;
+  std::vector<int> members;
+  size_t row_items, col_items;  // workspace offsets of the two item lists
+  int row_blocks, col_blocks;
+  double work;
+};
+
+struct BatchKey {
+  std::vector<const void *> ptrs;
+  void *ws = nullptr;
+  void *infos = nullptr;
+  bool operator==(const BatchKey &o) const {
+    return ptrs == o.ptrs && ws == o.ws && infos == o.infos;
+  }
+};
+
+}  // namespace sweik
+
+struct sweik_batch_s {
+  int count = 0, prec = 0, T = 0;
+  std::vector<sweik_plan_s> plans;
+  std::vector<size_t> inst_off;
+  std::vector<sweik::BatchClass> classes;
+  size_t items_bytes = 0, total = 0;
+  // created on the first solve (device of that call)
+  bool rt = false;
+  std::vector<hipStream_t> side;
+  hipEvent_t fork = nullptr;
+  std::vector<hipEvent_t> join;
+  static constexpr int kRing = 4;
+  void *stage[kRing] = {};
+  hipEvent_t stage_ev[kRing] = {};
+  bool stage_used[kRing] = {};
+  int ring = 0;
+  void *gstage = nullptr;
+  hipStream_t cap = nullptr;
+  hipGraphExec_t exec = nullptr;
+  sweik::BatchKey key;
+
+  ~sweik_batch_s() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    for (int i = 0; i < kRing; ++i) {
+      if (stage_ev[i]) {
+        (void)hipEventSynchronize(stage_ev[i]);
+        (void)hipEventDestroy(stage_ev[i]);
+      }
+      if (stage[i]) (void)hipHostFree(stage[i]);
+    }
+    if (gstage) (void)hipHostFree(gstage);
+    for (hipStream_t s : side) (void)hipStreamDestroy(s);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (fork) (void)hipEventDestroy(fork);
+    for (hipEvent_t e : join) (void)hipEventDestroy(e);
+  }
+};
+
+namespace sweik {
+
+size_t batch_item_bytes(int prec) {
+  return prec == SWEIK_F64 ? sizeof(BatchItem<double>) : sizeof(BatchItem<float>);
+}
+
+sweik_status batch_runtime(sweik_batch_s *b) {
+  if (b->rt) return SWEIK_OK;
+  const int nside = (int)b->classes.size() - 1;
+  for (int c = 0; c < nside; ++c) {
+    hipStream_t s;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return SWEIK_EDEVICE;
+    b->side.push_back(s);
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SWEIK_EDEVICE;
+    b->join.push_back(e);
+  }
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+    return SWEIK_EDEVICE;
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) return SWEIK_EDEVICE;
+  for (int i = 0; i < sweik_batch_s::kRing; ++i) {
+    if (hipHostMalloc(&b->stage[i], b->items_bytes, hipHostMallocDefault) != hipSuccess)
+      return SWEIK_EDEVICE;
+    if (hipEventCreateWithFlags(&b->stage_ev[i], hipEventDisableTiming) != hipSuccess)
+      return SWEIK_EDEVICE;
+  }
+  if (hipHostMalloc(&b->gstage, b->items_bytes, hipHostMallocDefault) != hipSuccess)
+    return SWEIK_EDEVICE;
+  b->rt = true;
+  return SWEIK_OK;
+}
+
+template <typename R>
+void batch_fill_items(const sweik_batch_s *b, const void *const *f, const int32_t *const *src,
+                      void *const *S, void *ws, sweik_info *infos, void *host) {
+  char *h = (char *)host;
+  char *w = (char *)ws;
+  for (const BatchClass &c : b->classes) {
+    BatchItem<R> *ri = (BatchItem<R> *)(h + c.row_items);
+    BatchItem<R> *ci = (BatchItem<R> *)(h + c.col_items);
+    int rbeg = 0, cbeg = 0;
+    for (size_t j = 0; j < c.members.size(); ++j) {
+      const int i = c.members[j];
+      const sweik_plan_s &pl = b->plans[i];
+      Args2<R> a = make_args2<R>(&pl, f[i], src[i], S[i], w + b->inst_off[i], nullptr,
+                                 infos ? infos + i : nullptr);
+      ri[j].a = a;
+      ri[j].begin = rbeg;
+      ri[j].pad_ = 0;
+      ci[j].a = a;
+      ci[j].begin = cbeg;
+      ci[j].pad_ = 0;
+      rbeg += pl.g2.nbr;
+      cbeg += pl.g2.ncw;
+    }
+  }
+}
+
+template <typename R>
+hipError_t batch_class_chain(const sweik_batch_s *b, const BatchClass &c, char *ws,
+                             hipStream_t st) {
+  const BatchItem<R> *ri = (const BatchItem<R> *)(ws + c.row_items);
+  const BatchItem<R> *ci = (const BatchItem<R> *)(ws + c.col_items);
+  const int n = (int)c.members.size();
+  hipError_t err = launch_prep_batch<R>(n, st, ri);
+  if (err == hipSuccess) err = launch_row2_batch<R>(ROW_GHAT, c.H1, c.row_blocks, st, ri, n, 0);
+  if (err == hipSuccess) err = launch_col2_batch<R>(COL_GHAT, c.M0, c.col_blocks, st, ci, n);
+  if (err == hipSuccess) err = launch_row2_batch<R>(ROW_PHI0, c.H1, c.row_blocks, st, ri, n, 0);
+  for (int i = 1; i <= b->T && err == hipSuccess; ++i) {
+    err = launch_col2_batch<R>(COL_CONV, c.M0, c.col_blocks, st, ci, n);
+    if (err == hipSuccess) err = launch_row2_batch<R>(ROW_TERM, c.H1, c.row_blocks, st, ri, n, i);
+  }
+  return err;
+}
+
+// Upload the item lists from `host` and enqueue every class chain, forked
+// from and joined back into `st`.
+template <typename R>
+sweik_status batch_enqueue(sweik_batch_s *b, void *host, char *ws, hipStream_t st,
+                           hipEvent_t upload_done) {
+  if (hipMemcpyAsync(ws, host, b->items_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+    return SWEIK_EDEVICE;
+  if (upload_done && hipEventRecord(upload_done, st) != hipSuccess) return SWEIK_EDEVICE;
+  const int nc = (int)b->classes.size();
+  if (nc > 1 && hipEventRecord(b->fork, st) != hipSuccess) return SWEIK_EDEVICE;
+  for (int c = 1; c < nc; ++c)
+    if (hipStreamWaitEvent(b->side[c - 1], b->fork, 0) != hipSuccess) return SWEIK_EDEVICE;
+  for (int c = 0; c < nc; ++c) {
+    hipStream_t s = c == 0 ? st : b->side[c - 1];
+    if (batch_class_chain<R>(b, b->classes[c], ws, s) != hipSuccess) return SWEIK_EDEVICE;
+  }
+  for (int c = 1; c < nc; ++c) {
+    if (hipEventRecord(b->join[c - 1], b->side[c - 1]) != hipSuccess) return SWEIK_EDEVICE;
+    if (hipStreamWaitEvent(st, b->join[c - 1], 0) != hipSuccess) return SWEIK_EDEVICE;
+  }
+  return SWEIK_OK;
+}
+
+sweik_status batch_args_ok(const sweik_batch_s *b, const void *const *f,
+                           const int32_t *const *src, void *const *S, void *ws,
+                           size_t ws_bytes) {
+  if (!b || !f || !src || !S || !ws) return SWEIK_EINVAL;
+  if (ws_bytes < b->total) return SWEIK_EWORKSPACE;
+  for (int i = 0; i < b->count; ++i)
+    if (!f[i] || !src[i] || !S[i]) return SWEIK_EINVAL;
+  return SWEIK_OK;
+}
+
 }  // namespace sweik
 
 extern "C" {
@@ -402,24 +576,139 @@ sweik_status sweik_solve_adjoint(sweik_plan plan, const void *f, const int32_t *
 }
 
 sweik_status sweik_batch_create(const sweik_problem *problems, int32_t count, sweik_batch *out) {
-  (void)problems; (void)count;
-  if (out) *out = nullptr;
-  return SWEIK_EUNSUPPORTED;
+  if (!out) return SWEIK_EINVAL;
+  *out = nullptr;
+  if (!problems || count < 1) return SWEIK_EINVAL;
+  for (int i = 0; i < count; ++i) {
+    sweik_status st = validate_problem(&problems[i]);
+    if (st != SWEIK_OK) return st;
+    if (problems[i].ndim != 2) return SWEIK_EUNSUPPORTED;
+    if (problems[i].prec != problems[0].prec || problems[i].T != problems[0].T)
+      return SWEIK_EINVAL;
+  }
+  sweik_batch_s *b = new (std::nothrow) sweik_batch_s();
+  if (!b) return SWEIK_ENOMEM;
+  b->count = count;
+  b->prec = problems[0].prec;
+  b->T = problems[0].T;
+  b->plans.resize(count);
+  for (int i = 0; i < count; ++i) {
+    sweik_plan_s &pl = b->plans[i];
+    pl.p = problems[i];
+    pl.lds_max = kLdsDevice;
+    sweik_status st = plan2d(&pl);
+    if (st != SWEIK_OK) {
+      delete b;
+      return st;
+    }
+  }
+  // size classes, largest total work first (it runs on the caller's stream)
+  for (int i = 0; i < count; ++i) {
+    const Geo2 &g = b->plans[i].g2;
+    auto it = std::find_if(b->classes.begin(), b->classes.end(),
+                           [&](const BatchClass &c) { return c.H1 == g.H1 && c.M0 == g.M0; });
+    if (it == b->classes.end()) {
+      b->classes.push_back(BatchClass{g.H1, g.M0, {}, 0, 0, 0, 0, 0.0});
+      it = b->classes.end() - 1;
+    }
+    it->members.push_back(i);
+    it->row_blocks += g.nbr;
+    it->col_blocks += g.ncw;
+    it->work += (double)g.M0 * g.H1;
+  }
+  std::stable_sort(b->classes.begin(), b->classes.end(),
+                   [](const BatchClass &x, const BatchClass &y) { return x.work > y.work; });
+  const size_t isz = batch_item_bytes(b->prec);
+  size_t off = 0;
+  for (BatchClass &c : b->classes) {
+    c.row_items = off;
+    off = align256(off + isz * c.members.size());
+    c.col_items = off;
+    off = align256(off + isz * c.members.size());
+  }
+  b->items_bytes = off;
+  b->inst_off.resize(count);
+  for (int i = 0; i < count; ++i) {
+    b->inst_off[i] = off;
+    off = align256(off + b->plans[i].ws.total);
+  }
+  b->total = off;
+  *out = b;
+  return SWEIK_OK;
 }
-void sweik_batch_destroy(sweik_batch batch) { (void)batch; }
-size_t sweik_batch_workspace_bytes(sweik_batch batch) { (void)batch; return 0; }
-sweik_status sweik_batch_solve(sweik_batch batch, const void *const *f, const int32_t *const *src,
+
+void sweik_batch_destroy(sweik_batch batch) { delete batch; }
+
+size_t sweik_batch_workspace_bytes(sweik_batch batch) { return batch ? batch->total : 0; }
+
+sweik_status sweik_batch_solve(sweik_batch b, const void *const *f, const int32_t *const *src,
                                void *const *S, void *ws, size_t ws_bytes, void *stream,
                                sweik_info *infos) {
-  (void)batch; (void)f; (void)src; (void)S; (void)ws; (void)ws_bytes; (void)stream; (void)infos;
-  return SWEIK_EUNSUPPORTED;
+  sweik_status rc = batch_args_ok(b, f, src, S, ws, ws_bytes);
+  if (rc != SWEIK_OK) return rc;
+  if ((rc = batch_runtime(b)) != SWEIK_OK) return rc;
+  // staging slot: wait (host side) only for the copy issued kRing calls ago
+  const int slot = b->ring;
+  b->ring = (b->ring + 1) % sweik_batch_s::kRing;
+  if (b->stage_used[slot] && hipEventSynchronize(b->stage_ev[slot]) != hipSuccess)
+    return SWEIK_EDEVICE;
+  b->stage_used[slot] = true;
+  void *host = b->stage[slot];
+  hipStream_t st = (hipStream_t)stream;
+  if (b->prec == SWEIK_F64) {
+    batch_fill_items<double>(b, f, src, S, ws, infos, host);
+    return batch_enqueue<double>(b, host, (char *)ws, st, b->stage_ev[slot]);
+  }
+  batch_fill_items<float>(b, f, src, S, ws, infos, host);
+  return batch_enqueue<float>(b, host, (char *)ws, st, b->stage_ev[slot]);
 }
-sweik_status sweik_batch_solve_graph(sweik_batch batch, const void *const *f,
+
+sweik_status sweik_batch_solve_graph(sweik_batch b, const void *const *f,
                                      const int32_t *const *src, void *const *S, void *ws,
                                      size_t ws_bytes, void *stream, sweik_info *infos) {
-  (void)batch; (void)f; (void)src; (void)S; (void)ws; (void)ws_bytes; (void)stream; (void)infos;
-  return SWEIK_EUNSUPPORTED;
+  sweik_status rc = batch_args_ok(b, f, src, S, ws, ws_bytes);
+  if (rc != SWEIK_OK) return rc;
+  if ((rc = batch_runtime(b)) != SWEIK_OK) return rc;
+  BatchKey key;
+  for (int i = 0; i < b->count; ++i) {
+    key.ptrs.push_back(f[i]);
+    key.ptrs.push_back(src[i]);
+    key.ptrs.push_back(S[i]);
+  }
+  key.ws = ws;
+  key.infos = infos;
+  if (!b->exec || !(key == b->key)) {
+    if (b->exec) {
+      // the staging buffer is read by earlier replays: let them finish
+      if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return SWEIK_EDEVICE;
+      (void)hipGraphExecDestroy(b->exec);
+      b->exec = nullptr;
+    }
+    if (b->prec == SWEIK_F64)
+      batch_fill_items<double>(b, f, src, S, ws, infos, b->gstage);
+    else
+      batch_fill_items<float>(b, f, src, S, ws, infos, b->gstage);
+    if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return SWEIK_EDEVICE;
+    rc = b->prec == SWEIK_F64 ? batch_enqueue<double>(b, b->gstage, (char *)ws, b->cap, nullptr)
+                              : batch_enqueue<float>(b, b->gstage, (char *)ws, b->cap, nullptr);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(b->cap, &graph);
+    if (rc != SWEIK_OK || ec != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return SWEIK_EDEVICE;
+    }
+    const hipError_t ei = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      b->exec = nullptr;
+      return SWEIK_EDEVICE;
+    }
+    b->key = key;
+  }
+  return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
+
 int32_t sweik_autotune(sweik_plan plan, void *ws, size_t ws_bytes, void *stream) {
   (void)plan; (void)ws; (void)ws_bytes; (void)stream;
   return 0;

@@ -154,13 +154,28 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
 }
 
 template <typename R, int MODE, int M0>
-__global__ void __launch_bounds__(kThreads) k_col2(Args2<R> a) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void col_block(const Args2<R> &a, int tile, unsigned char *smem_raw) {
   if ((tile + 1) * col_cpw(M0) <= a.ldk && a.nb * spec_rb<R>() >= M0 / 2)
     col_pass<R, MODE, M0, true>(a, tile, smem_raw);
   else
     col_pass<R, MODE, M0, false>(a, tile, smem_raw);
+}
+
+template <typename R, int MODE, int M0>
+__global__ void __launch_bounds__(kThreads) k_col2(Args2<R> a) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  col_block<R, MODE, M0>(a, xcd_tile(blockIdx.x, gridDim.x), smem_raw);
+}
+
+// Uneven batch: one launch over the column work-groups of every instance of
+// a size class (neighbouring tiles of an instance share an XCD).
+template <typename R, int MODE, int M0>
+__global__ void __launch_bounds__(kThreads) k_col2_batch(const BatchItem<R> *__restrict__ items,
+                                                         int nitems) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int g = xcd_tile(blockIdx.x, gridDim.x);
+  const int i = find_item(items, nitems, g);
+  col_block<R, MODE, M0>(items[i].a, g - items[i].begin, smem_raw);
 }
 
 }  // namespace sweik

@@ -86,16 +86,16 @@ template <typename R> struct Args2 {
 // prep: partial min / max / validity of f, and the twiddle table
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ void __launch_bounds__(256) k_prep(const R *__restrict__ f, long long N,
-                                              double *__restrict__ red,
-                                              cplx<R> *__restrict__ tw, int lmax) {
+__device__ __forceinline__ void prep_block(const R *__restrict__ f, long long N,
+                                           double *__restrict__ red, cplx<R> *__restrict__ tw,
+                                           int lmax, int bid, int nblk) {
   __shared__ double smin[4], smax[4];
   __shared__ int sfl[4];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
   int fl = 0;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-       i += (long long)gridDim.x * blockDim.x) {
+  for (long long i = (long long)bid * blockDim.x + threadIdx.x; i < N;
+       i += (long long)nblk * blockDim.x) {
     const double v = (double)f[i];
     if (!isfinite(v)) {
       fl |= SWEIK_FLAG_F_NONFINITE;
@@ -123,12 +123,12 @@ __global__ void __launch_bounds__(256) k_prep(const R *__restrict__ f, long long
     lo = smin[0] < lo ? smin[0] : lo;
     hi = smax[0] > hi ? smax[0] : hi;
     fl |= sfl[0];
-    red[3 * blockIdx.x + 0] = lo;
-    red[3 * blockIdx.x + 1] = hi;
-    red[3 * blockIdx.x + 2] = (double)fl;
+    red[3 * bid + 0] = lo;
+    red[3 * bid + 1] = hi;
+    red[3 * bid + 2] = (double)fl;
   }
   // twiddles exp(-2 pi i j / lmax) from an exact argument
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < lmax; j += gridDim.x * blockDim.x) {
+  for (int j = bid * blockDim.x + threadIdx.x; j < lmax; j += nblk * blockDim.x) {
     double s, c;
     sincospi(2.0 * (double)j / (double)lmax, &s, &c);
     cplx<R> w;
@@ -136,6 +136,13 @@ __global__ void __launch_bounds__(256) k_prep(const R *__restrict__ f, long long
     w.y = (R)(-s);
     tw[j] = w;
   }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_prep(const R *__restrict__ f, long long N,
+                                              double *__restrict__ red,
+                                              cplx<R> *__restrict__ tw, int lmax) {
+  prep_block(f, N, red, tw, lmax, (int)blockIdx.x, (int)gridDim.x);
 }
 
 // Reduce the prep partials into the reference forcing (Section 5.1).
@@ -213,6 +220,34 @@ __device__ __forceinline__ int write_S(const Args2<R> &a, size_t i, double phi) 
   const bool ok = phi > 0.0 && isfinite(phi);
   a.S[i] = ok ? (R)(-a.hbar * log(phi)) : (R)__builtin_huge_val();
   return ok ? 0 : 1;
+}
+
+// One instance of an uneven batch: its arguments and the first work-group
+// of its share of a batched launch.
+template <typename R> struct BatchItem {
+  Args2<R> a;
+  int begin;
+  int pad_;
+};
+
+// Instance owning work-group g (items sorted by begin; small lists).
+template <typename R>
+__device__ __forceinline__ int find_item(const BatchItem<R> *items, int n, int g) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].begin <= g) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_prep_batch(const BatchItem<R> *__restrict__ items) {
+  const int i = blockIdx.x / kRedBlocks, bid = blockIdx.x % kRedBlocks;
+  const Args2<R> &a = items[i].a;
+  prep_block(a.f, (long long)a.n0 * a.n1, a.red, const_cast<cplx<R> *>(a.tw),
+             1 << a.lmax_log, bid, kRedBlocks);
 }
 
 // Work-group index -> tile index such that consecutive tiles run on the same

@@ -87,6 +87,92 @@ hipError_t launch_col2(int mode, int M0, dim3 grid, hipStream_t st, const Args2<
                           : col_mode<R, COL_CONV>(M0, grid, st, a);
 }
 
+// ---- uneven batches -------------------------------------------------------
+template <typename R, int MODE, int H>
+static hipError_t row_batch_one(int nblocks, hipStream_t st, const BatchItem<R> *items,
+                                int nitems, int term) {
+  constexpr size_t lds = row_lds_bytes<R>(H, MODE);
+  if constexpr (lds > kLdsDevice) {
+    return hipErrorInvalidValue;
+  } else {
+    static const hipError_t attr = set_lds(k_row2_batch<R, MODE, H>, lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k_row2_batch<R, MODE, H>), dim3(nblocks), dim3(kThreads), lds, st, items,
+                       nitems, term);
+    return hipGetLastError();
+  }
+}
+
+template <typename R, int MODE>
+static hipError_t row_batch_mode(int H, int nblocks, hipStream_t st, const BatchItem<R> *items,
+                                 int nitems, int term) {
+  switch (H) {
+    case 32: return row_batch_one<R, MODE, 32>(nblocks, st, items, nitems, term);
+    case 64: return row_batch_one<R, MODE, 64>(nblocks, st, items, nitems, term);
+    case 128: return row_batch_one<R, MODE, 128>(nblocks, st, items, nitems, term);
+    case 256: return row_batch_one<R, MODE, 256>(nblocks, st, items, nitems, term);
+    case 512: return row_batch_one<R, MODE, 512>(nblocks, st, items, nitems, term);
+    case 1024: return row_batch_one<R, MODE, 1024>(nblocks, st, items, nitems, term);
+    case 2048: return row_batch_one<R, MODE, 2048>(nblocks, st, items, nitems, term);
+    case 4096: return row_batch_one<R, MODE, 4096>(nblocks, st, items, nitems, term);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename R>
+hipError_t launch_row2_batch(int mode, int H, int nblocks, hipStream_t st,
+                             const BatchItem<R> *items, int nitems, int term) {
+  switch (mode) {
+    case ROW_GHAT: return row_batch_mode<R, ROW_GHAT>(H, nblocks, st, items, nitems, term);
+    case ROW_PHI0: return row_batch_mode<R, ROW_PHI0>(H, nblocks, st, items, nitems, term);
+    case ROW_TERM: return row_batch_mode<R, ROW_TERM>(H, nblocks, st, items, nitems, term);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename R, int MODE, int M0>
+static hipError_t col_batch_one(int nblocks, hipStream_t st, const BatchItem<R> *items,
+                                int nitems) {
+  constexpr size_t lds = col_lds_bytes<R>(M0);
+  if constexpr (lds > kLdsDevice) {
+    return hipErrorInvalidValue;
+  } else {
+    static const hipError_t attr = set_lds(k_col2_batch<R, MODE, M0>, lds);
+    if (attr != hipSuccess) return attr;
+    hipLaunchKernelGGL((k_col2_batch<R, MODE, M0>), dim3(nblocks), dim3(kThreads), lds, st,
+                       items, nitems);
+    return hipGetLastError();
+  }
+}
+
+template <typename R, int MODE>
+static hipError_t col_batch_mode(int M0, int nblocks, hipStream_t st, const BatchItem<R> *items,
+                                 int nitems) {
+  switch (M0) {
+    case 64: return col_batch_one<R, MODE, 64>(nblocks, st, items, nitems);
+    case 128: return col_batch_one<R, MODE, 128>(nblocks, st, items, nitems);
+    case 256: return col_batch_one<R, MODE, 256>(nblocks, st, items, nitems);
+    case 512: return col_batch_one<R, MODE, 512>(nblocks, st, items, nitems);
+    case 1024: return col_batch_one<R, MODE, 1024>(nblocks, st, items, nitems);
+    case 2048: return col_batch_one<R, MODE, 2048>(nblocks, st, items, nitems);
+    case 4096: return col_batch_one<R, MODE, 4096>(nblocks, st, items, nitems);
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename R>
+hipError_t launch_col2_batch(int mode, int M0, int nblocks, hipStream_t st,
+                             const BatchItem<R> *items, int nitems) {
+  return mode == COL_GHAT ? col_batch_mode<R, COL_GHAT>(M0, nblocks, st, items, nitems)
+                          : col_batch_mode<R, COL_CONV>(M0, nblocks, st, items, nitems);
+}
+
+template <typename R>
+hipError_t launch_prep_batch(int nitems, hipStream_t st, const BatchItem<R> *items) {
+  hipLaunchKernelGGL(k_prep_batch<R>, dim3(nitems * kRedBlocks), dim3(256), 0, st, items);
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_prep(const R *f, long long N, double *red, cplx<R> *tw, int lmax,
                        hipStream_t st) {
@@ -114,6 +200,11 @@ template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream
                                      hipStream_t);                                         \
   template hipError_t launch_adj_prep<R>(const R *, const double *, long long, double,     \
                                          double *, cplx<R> *, int, hipStream_t);           \
-  template hipError_t launch_fill<R>(R *, long long, R, hipStream_t);
+  template hipError_t launch_fill<R>(R *, long long, R, hipStream_t);                      \
+  template hipError_t launch_row2_batch<R>(int, int, int, hipStream_t, const BatchItem<R> *, \
+                                           int, int);                                      \
+  template hipError_t launch_col2_batch<R>(int, int, int, hipStream_t, const BatchItem<R> *, \
+                                           int);                                           \
+  template hipError_t launch_prep_batch<R>(int, hipStream_t, const BatchItem<R> *);
 
 }  // namespace sweik

@@ -19,5 +19,13 @@ template <typename R>
 hipError_t launch_adj_prep(const R *dLdS, const double *phi, long long N, double hbar,
                            double *red, cplx<R> *tw, int lmax, hipStream_t st);
 template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream_t st);
+template <typename R>
+hipError_t launch_row2_batch(int mode, int H, int nblocks, hipStream_t st,
+                             const BatchItem<R> *items, int nitems, int term);
+template <typename R>
+hipError_t launch_col2_batch(int mode, int M0, int nblocks, hipStream_t st,
+                             const BatchItem<R> *items, int nitems);
+template <typename R>
+hipError_t launch_prep_batch(int nitems, hipStream_t st, const BatchItem<R> *items);
 
 }  // namespace sweik

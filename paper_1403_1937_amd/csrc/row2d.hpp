@@ -174,7 +174,8 @@ __device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[16], int t, int tid,
 // element needs a bounds check (columns >= H are zero padding, known
 // statically).
 template <typename R, int MODE, int H, bool FULL>
-__device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned char *smem_raw) {
+__device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned char *smem_raw,
+                                         const int bid) {
   using C = cplx<R>;
   using Tile = RowTile<R, H>;
   constexpr int P = H / 16, RPW = row_rpw(H), LL = lds_line_len(H);
@@ -188,7 +189,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   __shared__ double s_par[2];
 
   const int tid = threadIdx.x, team = tid / P, t = tid - team * P;
-  const int row0 = blockIdx.x * RPW, r = row0 + team;
+  const int row0 = bid * RPW, r = row0 + team;
   C *line = lines + team * LL;
   const bool row_ok = FULL || r < a.n0;
   const size_t rowoff = (size_t)r * a.n1;
@@ -291,7 +292,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
         const int y0 = a.src[2 * k], y1 = a.src[2 * k + 1];
         if (y0 < 0 || y0 >= a.n0 || y1 < 0 || y1 >= a.n1) fl |= SWEIK_FLAG_BAD_SOURCE;
       }
-      if (blockIdx.x == 0) {
+      if (bid == 0) {
         Params p;
         p.ftilde = ft;
         p.beta = beta;
@@ -332,7 +333,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     dstep = exp_step(mu);
     E = a.expo[term - 1] + dstep;
   }
-  if ((MODE == ROW_TERM || MODE == ROW_PHI0) && blockIdx.x == 0 && tid == 0) {
+  if ((MODE == ROW_TERM || MODE == ROW_PHI0) && bid == 0 && tid == 0) {
     const int slot = MODE == ROW_TERM ? term : 0;
     a.expo[slot] = E;
     if (a.info) a.info->scale_exp[slot] = E;
@@ -343,7 +344,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     for (int i = tid; i < kRedBlocks; i += kThreads) mx = fmax(mx, a.red[i]);
     mx = block_max(mx);
     elam = exp_step(mx);
-    if (blockIdx.x == 0 && tid == 0) a.expo[0] = elam;
+    if (bid == 0 && tid == 0) a.expo[0] = elam;
   }
   if (MODE == ROW_ADJ) {
     __shared__ int s_e[2];
@@ -533,7 +534,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
       return;
     }
     const double bm = block_max((double)mlr);
-    if (tid == 0) a.mu[(size_t)slot * a.nbr + blockIdx.x] = bm;
+    if (tid == 0) a.mu[(size_t)slot * a.nbr + bid] = bm;
   }
 
   if constexpr (MODE == ROW_ADJ0) {
@@ -597,13 +598,29 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
 }
 
 template <typename R, int MODE, int H>
+__device__ __forceinline__ void row_block(const Args2<R> &a, int term, unsigned char *smem_raw,
+                                          int bid) {
+  const int row0 = bid * row_rpw(H);
+  if (row0 + row_rpw(H) <= a.n0 && a.n1 == H)
+    row_pass<R, MODE, H, true>(a, term, smem_raw, bid);
+  else
+    row_pass<R, MODE, H, false>(a, term, smem_raw, bid);
+}
+
+template <typename R, int MODE, int H>
 __global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int row0 = blockIdx.x * row_rpw(H);
-  if (row0 + row_rpw(H) <= a.n0 && a.n1 == H)
-    row_pass<R, MODE, H, true>(a, term, smem_raw);
-  else
-    row_pass<R, MODE, H, false>(a, term, smem_raw);
+  row_block<R, MODE, H>(a, term, smem_raw, blockIdx.x);
+}
+
+// Uneven batch: one launch over the row work-groups of every instance of a
+// size class; items[i].begin is the first work-group of instance i.
+template <typename R, int MODE, int H>
+__global__ void __launch_bounds__(kThreads) k_row2_batch(const BatchItem<R> *__restrict__ items,
+                                                         int nitems, int term) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int i = find_item(items, nitems, (int)blockIdx.x);
+  row_block<R, MODE, H>(items[i].a, term, smem_raw, (int)blockIdx.x - items[i].begin);
 }
 
 // Adjoint start: max |lambda| partials (with the twiddle table).

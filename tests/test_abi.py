@@ -102,3 +102,21 @@ def test_solve_rejects_null_and_small_workspace(lib):
     assert rc == 1
     rc = lib.sweik_solve(p.handle, vp(16), vp(16), vp(16), vp(16), 10, None, None, None)
     assert rc == 3
+
+
+def test_batch_create_checks_and_layout(lib):
+    from paper_1403_1937_amd import Batch
+    base = {"dims": (64, 64), "h": 1 / 64, "hbar": 0.1, "T": 4, "n_src": 1}
+    with pytest.raises(ValueError):
+        Batch([], "fp32")
+    with pytest.raises(ValueError):
+        Batch([base, dict(base, T=5)], "fp32")          # T must agree
+    with pytest.raises(ValueError):
+        Batch([base, dict(base, dims=(8, 8, 8))], "fp32")  # 2D only
+    with pytest.raises(ValueError):
+        Batch([base, dict(base, hbar=-1.0)], "fp32")
+    probs = [base, dict(base, dims=(100, 76)), dict(base, dims=(7, 300)), base]
+    b = Batch(probs, "fp32")
+    singles = sum(_plan(dims=q["dims"], T=4).workspace_bytes for q in probs)
+    # per-instance regions plus the work lists at the head
+    assert singles < b.workspace_bytes < singles + 64 * 1024
