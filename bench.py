@@ -1,21 +1,40 @@
 #!/usr/bin/env python3
 """Benchmark of the linearised eikonal solve on one MI355X.
 
-Workload (default): 2D grid 1024 x 1024 on the unit box (h = 1/1024),
-forcing = seeded smoothed noise (sigma 16 px) mapped to [1, 3], 16 seeded
-point sources, hbar = 0.05, T = 16 correction terms, FP32 with per-term
-power-of-two scaling and FP64 accumulation.  A step is one whole solve:
-reduction of f, kernel spectrum, phi_0, T terms, logarithm.  Inputs are
-resident in HBM before timing starts.
+Workload (the line's `value`): 2D grid 1024 x 1024 on the unit box
+(h = 1/1024), forcing = seeded smoothed noise (sigma 16 px) mapped to [1, 3],
+16 seeded point sources, hbar = 0.05, T = 16 correction terms, FP32 with
+per-term power-of-two scaling and FP64 accumulation.  A step is one whole
+solve: reduction of f, kernel spectrum, phi_0, T terms, logarithm.  Inputs
+are resident in HBM before timing starts.
 
-Prints ONE JSON line with grid points per second, the roofline of the
-dominant kernel (algorithmic bytes per launch / event-timed launch
-duration), the plain FP64 GPU solve as comparator and the CPU oracle timed
-on the host cores.
+Also reported on the same JSON line:
+  fp64_comparator  the plain FP64 GPU solve of the same workload
+  fwd_bwd          forward (with checkpoints) + adjoint dL/df on the 2048^2,
+                   T = 12, 4-source differentiation workload, FP32-scaled,
+                   loss = sum over 256 receivers of (S - target)^2
+  batched          64 uneven instances (edges from {256, 512, 1024, 2048},
+                   T = 12, FP32-scaled) solved by one replay of a HIP graph
+  roofline         of the dominant kernel: algorithmic bytes per launch over
+                   its HIP-event-timed duration; `traffic` from the committed
+                   FETCH_SIZE / WRITE_SIZE counter summary when it was taken
+                   on the current kernel sources, else null
+  cpu_baseline     the FP64 CPU oracle timed on the host cores
+
+Other modes (for profiling runs):
+  --pmc-run                 a copy-calibration kernel, then a few solves of
+                            the main workload (run under rocprofv3 --pmc)
+  --traffic-summary F W     turn the counter CSVs of a FETCH_SIZE run (F) and
+                            a WRITE_SIZE run (W) into the traffic summary
+  --stats-summary CSV       turn a rocprofv3 kernel_stats.csv into a short
+                            text summary
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -28,27 +47,342 @@ import numpy as np  # noqa: E402
 
 METRIC = ("grid pts/s for K-term eikonal solve, FP32-scaled vs FP64, fwd and fwd+bwd")
 HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_term_row_noise2d_1024x1024_fp32.txt")
+COPY_ELEMS = 64 << 20  # float32 elements of the calibration copy (256 MiB each way)
 
 
-def alg_bytes_2d(n0, n1, H1, H0, esz, T):
+def source_hash() -> str:
+    """Hash of the kernel sources: counter figures are valid only for these."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1403_1937_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(d, "*.hpp")) + glob.glob(os.path.join(d, "*.hip"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def alg_bytes_2d(n0, n1, H1, H0, esz, ckpt=False):
     """Algorithmic HBM bytes per kernel class of a 2D forward solve: every
     pass reads its inputs once and writes its outputs once at the stored
     precision; the spectrum is the n0 x H1 half spectrum (the real DC and
     Nyquist bins share a column), the kernel spectrum the (H1+1) x (H0+1)
-    orthant."""
+    orthant.  With checkpoints the forward also stores phi_0..phi_{T-1}
+    (esz N each) and phi (8 N)."""
     N = n0 * n1
-    csz = 2 * esz
-    spec = csz * n0 * H1
+    spec = 2 * esz * n0 * H1
     ghat = esz * (H1 + 1) * (H0 + 1)
+    ck = esz * N if ckpt else 0
     return {
         "prep": esz * N,
         "ghat_row": spec,
         "ghat_col": spec + ghat,
-        "phi0_row": esz * N + 8 * N + spec,
+        "phi0_row": 2 * esz * N + 8 * N + spec + ck,        # f in; acc, gamma, spectrum out
         "conv_col": 2 * spec + ghat,
-        "term_row": 2 * spec + esz * N + 16 * N,
-        "last_row": spec + 8 * N + esz * N,
+        "term_row": 2 * spec + esz * N + 16 * N + ck,        # spec in/out, gamma, acc RMW
+        "last_row": spec + 8 * N + esz * N + (8 * N if ckpt else 0),
     }
+
+
+def alg_bytes_adjoint_2d(n0, n1, H1, H0, esz, T):
+    """Algorithmic bytes of the adjoint sweep (same rule): lambda start,
+    then per term a column convolution and a row pass that reads the
+    checkpointed term, gamma and lambda and updates the FP64 dL/dgamma."""
+    N = n0 * n1
+    spec = 2 * esz * n0 * H1
+    ghat = esz * (H1 + 1) * (H0 + 1)
+    total = esz * N + 8 * N                                   # max |lambda|
+    total += 2 * esz * N + 8 * N + 2 * esz * N + spec         # lambda, gamma, a_T spectrum
+    for i in range(T, 0, -1):
+        total += 2 * spec + ghat                              # b_i = kappa * a_i
+        row = spec + esz * N + esz * N                        # spectrum, term, gamma or f
+        if i != T:
+            row += 8 * N                                      # dL/dgamma read
+        if i > 1:
+            row += esz * N + 8 * N + spec                     # lambda, dL/dgamma, a_{i-1}
+        else:
+            row += esz * N                                    # dL/df
+        total += row
+    return total
+
+
+def read_traffic(kernel_hash: str):
+    """Per-launch HBM bytes of the dominant kernel from the committed
+    counter summary, or None when it is missing or stale."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            d = json.loads(fh.read().split("\n---\n", 1)[1])
+    except (OSError, IndexError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_hash:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def _events(torch, stream):
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    return e0, e1
+
+
+def run_main(pk, torch, dev, p, precision, steps, warmup):
+    n0, n1 = p.dims
+    dt = torch.float32 if precision == "fp32" else torch.float64
+    f = torch.as_tensor(p.f.astype(np.float32 if precision == "fp32" else np.float64)).to(dev, dt)
+    src = torch.as_tensor(p.src).to(dev)
+    plan = pk.Plan(p.dims, p.h, p.hbar, p.T, len(p.src), precision)
+    plan.check_sources(p.src)
+    ws = plan.workspace(dev)
+    S = torch.empty_like(f)
+    for _ in range(warmup):
+        plan.solve(f, src, S, ws)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = _events(torch, st)
+    e0.record(st)
+    for _ in range(steps):
+        plan.solve(f, src, S, ws)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # per-kernel durations: HIP events around every launch on the solve's
+    # stream, over as many solves as the timed region
+    acc = {}
+    for _ in range(steps):
+        t = plan.solve_timed(f, src, S, ws)
+        for k, (m, c) in t.items():
+            a = acc.setdefault(k, [0.0, 0])
+            a[0] += m
+            a[1] += c
+    esz = 4 if precision == "fp32" else 8
+    H1, H0 = plan.padded[1] // 2, plan.padded[0] // 2
+    ab = alg_bytes_2d(n0, n1, H1, H0, esz)
+    kern = {}
+    for k, (m, c) in acc.items():
+        if c == 0:
+            continue
+        avg_ms = m / c
+        kern[k] = {"launches_per_step": c // steps, "avg_us": 1e3 * avg_ms,
+                   "alg_bytes": ab[k], "GBps": ab[k] / (avg_ms * 1e-3) / 1e9}
+    total_bytes = sum(ab[k] * kern[k]["launches_per_step"] for k in kern)
+    return ms, kern, total_bytes
+
+
+def run_fwd_bwd(pk, torch, dev, steps, warmup):
+    """Forward with checkpoints + adjoint on the 2048^2 differentiation
+    workload; dL/dS = 2 (S - target) at 256 receivers, 0 elsewhere."""
+    import workloads
+    p = workloads.problem(5)
+    rec, f_t = workloads.loss_setup(p)
+    n0, n1 = p.dims
+    N = n0 * n1
+    f = torch.as_tensor(p.f).to(dev)
+    src = torch.as_tensor(p.src).to(dev)
+    plan = pk.Plan(p.dims, p.h, p.hbar, p.T, len(p.src), "fp32")
+    plan.check_sources(p.src)
+    ws, ck = plan.workspace(dev), plan.checkpoint(dev)
+    S = torch.empty_like(f)
+    # target: the same solve for the perturbed forcing
+    tgt = torch.empty_like(f)
+    plan.solve(torch.as_tensor(f_t).to(dev), src, tgt, ws)
+    ridx = torch.as_tensor(rec[:, 0].astype(np.int64) * n1 + rec[:, 1]).to(dev)
+    dLdS = torch.zeros(N, dtype=torch.float32, device=dev)
+    dLdf = torch.empty_like(f)
+
+    def step():
+        plan.solve(f, src, S, ws, ck)
+        # the loss gradient w.r.t. S (a gather and a scatter of 256 values)
+        dLdS[ridx] = 2.0 * (S.view(-1)[ridx] - tgt.view(-1)[ridx])
+        plan.adjoint(f, src, ck, dLdS.view(n0, n1), dLdf, ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = _events(torch, st)
+    e0.record(st)
+    for _ in range(steps):
+        step()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    # forward alone with checkpoints, for the split
+    e0.record(st)
+    for _ in range(steps):
+        plan.solve(f, src, S, ws, ck)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms_fwd = e0.elapsed_time(e1) / steps
+    H1, H0 = plan.padded[1] // 2, plan.padded[0] // 2
+    ab = alg_bytes_2d(n0, n1, H1, H0, 4, ckpt=True)
+    fwd_bytes = (ab["prep"] + ab["ghat_row"] + ab["ghat_col"] + ab["phi0_row"]
+                 + p.T * ab["conv_col"] + (p.T - 1) * ab["term_row"] + ab["last_row"])
+    bwd_bytes = alg_bytes_adjoint_2d(n0, n1, H1, H0, 4, p.T)
+    ok = bool(torch.isfinite(dLdf).all().item())
+    return {"workload": f"noise2d_{n0}x{n1}_T{p.T}_src{len(p.src)}_rec{len(rec)}",
+            "value": N / (ms * 1e-3), "unit": "grid pts/s", "ms_per_step": ms,
+            "ms_forward_with_checkpoints": ms_fwd, "ms_adjoint": ms - ms_fwd,
+            "alg_bytes": fwd_bytes + bwd_bytes,
+            "alg_GBps": (fwd_bytes + bwd_bytes) / (ms * 1e-3) / 1e9,
+            "precision": "fp32-scaled", "gradient_finite": ok}
+
+
+def run_batched(pk, torch, dev, steps, warmup):
+    """64 uneven instances, one HIP graph replay per step."""
+    import workloads
+    probs = workloads.batch_problems()
+    T = probs[0].T
+    b = pk.Batch([{"dims": q.dims, "h": q.h, "hbar": q.hbar, "T": q.T, "n_src": len(q.src)}
+                  for q in probs], "fp32")
+    fs = [torch.as_tensor(q.f).to(dev) for q in probs]
+    srcs = [torch.as_tensor(q.src).to(dev) for q in probs]
+    Ss = [torch.empty_like(f) for f in fs]
+    ws = torch.empty(b.workspace_bytes, dtype=torch.uint8, device=dev)
+    for _ in range(max(1, warmup)):
+        b.solve(fs, srcs, Ss, ws, graph=True)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = _events(torch, st)
+    e0.record(st)
+    for _ in range(steps):
+        b.solve(fs, srcs, Ss, ws, graph=True)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    e0.record(st)
+    for _ in range(steps):
+        b.solve(fs, srcs, Ss, ws, graph=False)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms_eager = e0.elapsed_time(e1) / steps
+    sumN = sum(q.dims[0] * q.dims[1] for q in probs)
+    total = 0
+    for q in probs:
+        n0, n1 = q.dims
+        M0 = max(64, 1 << int(np.ceil(np.log2(2 * n0 - 1))))
+        M1 = max(64, 1 << int(np.ceil(np.log2(2 * n1 - 1))))
+        ab = alg_bytes_2d(n0, n1, M1 // 2, M0 // 2, 4)
+        total += (ab["prep"] + ab["ghat_row"] + ab["ghat_col"] + ab["phi0_row"]
+                  + T * ab["conv_col"] + (T - 1) * ab["term_row"] + ab["last_row"])
+    sizes = {}
+    for q in probs:
+        sizes[q.dims[0]] = sizes.get(q.dims[0], 0) + 1
+    return {"workload": f"batch64_uneven_T{T}", "instances_per_edge": sizes,
+            "sum_grid_pts": sumN, "value": sumN / (ms * 1e-3), "unit": "grid pts/s",
+            "ms_per_step": ms, "ms_per_step_eager": ms_eager, "alg_bytes": total,
+            "alg_GBps": total / (ms * 1e-3) / 1e9, "precision": "fp32-scaled",
+            "execution": "one HIP graph replay per step"}
+
+
+def cpu_baseline(p, budget_s=10.0):
+    """The FP64 CPU oracle on the host cores: whole solves of the main
+    workload, repeated until `budget_s` seconds have passed; plus one
+    single-thread solve."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n0, n1 = p.dims
+    f64 = p.f.astype(np.float64)
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.solve(f64, p.src, p.h, p.hbar, p.T, nthreads=threads)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s:
+            break
+    t1 = time.perf_counter()
+    oracle.solve(f64, p.src, p.h, p.hbar, p.T, nthreads=1)
+    t1s = time.perf_counter() - t1
+    return {"value": reps * n0 * n1 / el, "unit": "grid pts/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{reps} full {n0}x{n1} T={p.T} solves (FP64, own radix-2 FFT) in "
+                      f"{el:.1f} s on {threads} threads",
+            "single_thread": {"value": n0 * n1 / t1s, "seconds_per_solve": t1s}}
+
+
+# ---- counter and trace summaries --------------------------------------------
+
+def _counter_rows(path):
+    files = [path] if os.path.isfile(path) else glob.glob(
+        os.path.join(path, "**", "*counter_collection.csv"), recursive=True)
+    rows = []
+    for fn in files:
+        with open(fn) as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def _per_dispatch(rows, counter):
+    """{dispatch id: (kernel name, value)} summed over the counter's
+    instances within the dispatch."""
+    out = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter:
+            continue
+        d = int(r["Dispatch_Id"])
+        name = r["Kernel_Name"]
+        v = float(r["Counter_Value"])
+        prev = out.get(d, (name, 0.0))
+        out[d] = (name, prev[1] + v)
+    return out
+
+
+def traffic_summary(fetch_path, write_path, command):
+    """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the term-row
+    kernel and of the calibration copy; the copy's reading over its known
+    byte count is the factor that turns counter KiB into HBM bytes."""
+    res = {}
+    for counter, path in (("FETCH_SIZE", fetch_path), ("WRITE_SIZE", write_path)):
+        disp = _per_dispatch(_counter_rows(path), counter)
+        ids = sorted(disp)
+        term, copy = [], []
+        for j, d in enumerate(ids):
+            name, v = disp[d]
+            if "neg" in name.lower():
+                copy.append(v)
+            elif "k_row2" in name and "float" in name and ", 2, 1024>" in name:
+                # the last term-row dispatch of a solve is the log pass:
+                # it is followed by the next solve's prep (or nothing)
+                nxt = disp[ids[j + 1]][0] if j + 1 < len(ids) else ""
+                if "k_col2" in nxt:
+                    term.append(v)
+        if not term or not copy:
+            raise SystemExit(f"{counter}: no term-row or copy dispatches in {path}")
+        res[counter] = {"term_row_kib": float(np.mean(term)), "term_row_dispatches": len(term),
+                        "copy_kib": float(np.mean(copy)), "copy_dispatches": len(copy)}
+    copy_bytes = 4.0 * COPY_ELEMS
+    f_fac = res["FETCH_SIZE"]["copy_kib"] * 1024.0 / copy_bytes
+    w_fac = res["WRITE_SIZE"]["copy_kib"] * 1024.0 / copy_bytes
+    fetch_b = res["FETCH_SIZE"]["term_row_kib"] * 1024.0 / f_fac
+    write_b = res["WRITE_SIZE"]["term_row_kib"] * 1024.0 / w_fac
+    d = {"kernel": "term_row (k_row2<float, ROW_TERM, 1024>)",
+         "workload": "noise2d_1024x1024_T16_src16 fp32-scaled",
+         "counters": res,
+         "copy_bytes_each_way": copy_bytes,
+         "fetch_factor": f_fac, "write_factor": w_fac,
+         "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+         "traffic_bytes_per_launch": fetch_b + write_b,
+         "source_hash": source_hash()}
+    head = ("HBM traffic of the term-row kernel (FETCH_SIZE and WRITE_SIZE, one rocprofv3\n"
+            "--pmc run each), scaled by the same counters' reading for a plain float32\n"
+            "elementwise copy (torch.neg) of known size.\n"
+            f"command: {command}\n")
+    return head + "\n---\n" + json.dumps(d, indent=1) + "\n"
+
+
+def stats_summary(csv_path, command, top=12):
+    with open(csv_path) as fh:
+        rows = list(csv.DictReader(fh))
+    rows.sort(key=lambda r: -float(r.get("TotalDurationNs", 0)))
+    lines = [f"command: {command}", "",
+             f"{'calls':>6} {'avg_us':>9} {'min_us':>9} {'max_us':>9} {'pct':>6}  kernel"]
+    for r in rows[:top]:
+        name = r["Name"]
+        if len(name) > 90:
+            name = name[:87] + "..."
+        lines.append(f"{int(r['Calls']):6d} {float(r['AverageNs']) / 1e3:9.2f} "
+                     f"{float(r['MinNs']) / 1e3:9.2f} {float(r['MaxNs']) / 1e3:9.2f} "
+                     f"{float(r['Percentage']):6.2f}  {name}")
+    return "\n".join(lines) + "\n"
 
 
 def main():
@@ -57,13 +391,30 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--n", type=int, default=1024, help="grid edge of the workload")
+    ap.add_argument("--n", type=int, default=1024, help="grid edge of the main workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip fwd+bwd and batched")
+    ap.add_argument("--pmc-run", action="store_true")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH", "WRITE"))
+    ap.add_argument("--stats-summary", metavar="CSV")
+    ap.add_argument("--command", default="", help="command text recorded in a summary")
+    ap.add_argument("--out", help="summary output file")
     args = ap.parse_args()
 
+    if args.traffic_summary or args.stats_summary:
+        text = (traffic_summary(*args.traffic_summary, args.command) if args.traffic_summary
+                else stats_summary(args.stats_summary, args.command))
+        if args.out:
+            with open(args.out, "w") as fh:
+                fh.write(text)
+        print(text)
+        return
+
     if args.gpus != 1:
-        print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this solver runs on one GPU; --gpus must be 1 "
+                                   "(independent instances would be spread over GPUs by the "
+                                   "caller; a single grid is not split)"}))
         sys.exit(2)
 
     import torch
@@ -71,59 +422,29 @@ def main():
     import workloads
 
     if not os.path.exists(pk.lib_path()):
-        from paper_1403_1937_amd import build
-        build.build()
+        raise SystemExit(f"{pk.lib_path()} is not built: run paper_1403_1937_amd/build.py")
     dev = torch.device("cuda:0")
     p = workloads.problem(2, args.n)
     n0, n1 = p.dims
     N = n0 * n1
 
-    def run(precision, steps, warmup):
-        dt = torch.float32 if precision == "fp32" else torch.float64
-        f = torch.as_tensor(p.f.astype(np.float32 if precision == "fp32" else np.float64)).to(dev, dt)
-        src = torch.as_tensor(p.src).to(dev)
-        plan = pk.Plan(p.dims, p.h, p.hbar, p.T, len(p.src), precision)
-        plan.check_sources(p.src)
-        ws = plan.workspace(dev)
-        S = torch.empty_like(f)
-        for _ in range(warmup):
-            plan.solve(f, src, S, ws)
+    if args.pmc_run:
+        a = torch.rand(COPY_ELEMS, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.neg(a, out=b)
         torch.cuda.synchronize()
-        st = torch.cuda.current_stream()
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(st)
-        for _ in range(steps):
-            plan.solve(f, src, S, ws)
-        e1.record(st)
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / steps
-        # per-kernel durations: HIP events around every launch on the solve's
-        # stream, over as many solves as the timed region
-        acc = {}
-        for _ in range(steps):
-            t = plan.solve_timed(f, src, S, ws)
-            for k, (m, c) in t.items():
-                a = acc.setdefault(k, [0.0, 0])
-                a[0] += m
-                a[1] += c
-        esz = 4 if precision == "fp32" else 8
-        H1, H0 = plan.padded[1] // 2, plan.padded[0] // 2
-        ab = alg_bytes_2d(n0, n1, H1, H0, esz, p.T)
-        kern = {}
-        for k, (m, c) in acc.items():
-            if c == 0:
-                continue
-            avg_ms = m / c
-            kern[k] = {"launches_per_step": c // steps, "avg_us": 1e3 * avg_ms,
-                       "alg_bytes": ab[k], "GBps": ab[k] / (avg_ms * 1e-3) / 1e9}
-        total_bytes = sum(ab[k] * kern[k]["launches_per_step"] for k in kern)
-        return ms, kern, total_bytes, S
+        del a, b
+        ms, _, _ = run_main(pk, torch, dev, p, "fp32", args.steps, args.warmup)
+        print(f"pmc run done: {ms:.3f} ms per solve", flush=True)
+        return
 
-    ms, kern, total_bytes, S = run(args.precision, args.steps, args.warmup)
+    ms, kern, total_bytes = run_main(pk, torch, dev, p, args.precision, args.steps, args.warmup)
     value = N / (ms * 1e-3)
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches_per_step"])
     d = kern[dom]
+    traffic = read_traffic(source_hash()) if (dom == "term_row" and args.precision == "fp32"
+                                              and args.n == 1024) else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -144,27 +465,22 @@ def main():
                    "mode": "fwd"},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GBps"],
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": d["GBps"] / HBM_PEAK_GBPS, "traffic": None,
+                     "frac": d["GBps"] / HBM_PEAK_GBPS, "traffic": traffic,
                      "alg_bytes_per_launch": d["alg_bytes"], "avg_us": d["avg_us"]},
         "solve_alg_GBps": total_bytes / (ms * 1e-3) / 1e9,
         "solve_alg_bytes": total_bytes,
         "kernels": kern,
     }
     if not args.no_fp64 and args.precision == "fp32":
-        ms64, kern64, tb64, _ = run("fp64", max(5, args.steps // 2), 2)
+        ms64, _, tb64 = run_main(pk, torch, dev, p, "fp64", max(5, args.steps // 2), 2)
         out["fp64_comparator"] = {"value": N / (ms64 * 1e-3), "ms_per_step": ms64,
                                   "solve_alg_GBps": tb64 / (ms64 * 1e-3) / 1e9,
                                   "speedup_fp32_over_fp64": ms64 / ms}
+    if not args.no_extra:
+        out["fwd_bwd"] = run_fwd_bwd(pk, torch, dev, max(3, args.steps // 2), 2)
+        out["batched"] = run_batched(pk, torch, dev, max(3, args.steps // 4), 1)
     if not args.no_cpu_baseline:
-        import oracle
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-        t0 = time.perf_counter()
-        oracle.solve(p.f.astype(np.float64), p.src, p.h, p.hbar, p.T, nthreads=threads)
-        t1 = time.perf_counter()
-        out["cpu_baseline"] = {"value": N / (t1 - t0), "unit": "grid pts/s", "cores": threads,
-                               "kind": "oracle",
-                               "sample": f"one full {n0}x{n1} T={p.T} solve (FP64, own radix-2 "
-                                         f"FFT), {t1 - t0:.2f} s"}
+        out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out))
 
 

@@ -156,9 +156,11 @@ enum {
 };
 
 /* Same work as sweik_solve (2D, no checkpoint, no info) with a HIP event
- * recorded on `stream` before and after every kernel.  Synchronises the
- * stream, then writes to the HOST arrays ms[SWEIK_KC_COUNT] (summed kernel
- * milliseconds per class) and count[SWEIK_KC_COUNT] (launches per class).
+ * recorded on `stream` before the first kernel and after every kernel.
+ * Synchronises the stream, then writes to the HOST arrays
+ * ms[SWEIK_KC_COUNT] (per class, the summed intervals between the event
+ * before and the event after each of its kernels: the kernel plus the
+ * dispatch gap before it) and count[SWEIK_KC_COUNT] (launches per class).
  * For benchmarks: the events add a little time between launches. */
 sweik_status sweik_solve_timed(sweik_plan plan, const void *f, const int32_t *src,
                                void *S, void *ws, size_t ws_bytes, void *stream,
