@@ -223,20 +223,21 @@ Args2<R> make_args2(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   return a;
 }
 
-// Optional per-kernel timing: events recorded on the solve's stream before
-// and after every launch; durations are summed per kernel class.
+// Optional per-kernel timing: one event on the solve's stream before the
+// first kernel and one after every kernel, so that each interval covers one
+// kernel and the dispatch gap before it; durations are summed per class.
 struct KernelTimer {
   static constexpr int kMax = 2 * (SWEIK_MAX_TERMS + 4) + 8;
-  hipEvent_t ev[2 * kMax];
+  hipEvent_t ev[kMax + 1];
   int cls[kMax];
   int n = 0;
   bool ok = true;
   KernelTimer() {
-    for (int i = 0; i < 2 * kMax; ++i)
-      if (hipEventCreate(&ev[i]) != hipSuccess) ok = false;
+    for (int i = 0; i <= kMax; ++i)
+      if (hipEventCreateWithFlags(&ev[i], hipEventDisableSystemFence) != hipSuccess) ok = false;
   }
   ~KernelTimer() {
-    for (int i = 0; i < 2 * kMax; ++i) (void)hipEventDestroy(ev[i]);
+    for (int i = 0; i <= kMax; ++i) (void)hipEventDestroy(ev[i]);
   }
 };
 
@@ -251,9 +252,9 @@ sweik_status enqueue2d(const sweik_plan_s *pl, const void *f, const int32_t *src
   auto launch = [&](int cls, auto &&fn) {
     if (err != hipSuccess) return;
     if (tm && tm->n < KernelTimer::kMax) {
-      (void)hipEventRecord(tm->ev[2 * tm->n], st);
+      if (tm->n == 0) (void)hipEventRecord(tm->ev[0], st);
       err = fn();
-      (void)hipEventRecord(tm->ev[2 * tm->n + 1], st);
+      (void)hipEventRecord(tm->ev[tm->n + 1], st);
       tm->cls[tm->n++] = cls;
     } else {
       err = fn();
@@ -553,7 +554,7 @@ sweik_status sweik_solve_timed(sweik_plan plan, const void *f, const int32_t *sr
   }
   for (int i = 0; i < tm.n; ++i) {
     float t = 0.0f;
-    if (hipEventElapsedTime(&t, tm.ev[2 * i], tm.ev[2 * i + 1]) != hipSuccess)
+    if (hipEventElapsedTime(&t, tm.ev[i], tm.ev[i + 1]) != hipSuccess)
       return SWEIK_EDEVICE;
     ms[tm.cls[i]] += t;
     count[tm.cls[i]] += 1;
