@@ -19,6 +19,11 @@
  * The value of G at the singular origin is its average over the ball of one
  * cell's volume.  Points where phi <= 0 get S = +inf and are counted.
  *
+ * In 3D the real transform along the last axis samples the odd frequencies
+ * (k + 1/2)/M; with zero padding to M >= 2n - 1 the nega-cyclic convolution
+ * it implies equals the linear convolution (Section 5.2's discrete
+ * convolution), like the cyclic one.
+ *
  * Conventions
  *   - Arrays are C order (last index fastest).  Grid point index m has
  *     position h*m.  Sources are distinct grid indices, int32 [n_src][ndim].
@@ -102,8 +107,9 @@ typedef struct sweik_plan_s *sweik_plan;
 
 /* Validate a problem and choose the kernel schedule.  Host only: makes no
  * HIP call.  Returns SWEIK_EINVAL for invalid fields, SWEIK_EUNSUPPORTED for
- * grids beyond the supported sizes (padded FFT length per axis <= 8192 in
- * 2D and <= 1024 in 3D). */
+ * grids beyond the supported sizes.  Padded FFT lengths (the next power of
+ * two >= 2n-1, at least 64): 2D axis 0 <= 4096 and axis 1 <= 8192 (FP64:
+ * axis 1 <= 4096); 3D every axis <= 1024. */
 sweik_status sweik_plan_create(const sweik_problem *problem, sweik_plan *out);
 void sweik_plan_destroy(sweik_plan plan);
 
@@ -124,14 +130,15 @@ sweik_status sweik_check_sources(sweik_plan plan, const int32_t *src_host);
  *   S      device, dims, same type as f (output)
  *   ws     device workspace of ws_bytes >= sweik_workspace_bytes(plan)
  *   ckpt   device, nullable: when given, the series terms and phi are kept
- *          for sweik_solve_adjoint (sweik_checkpoint_bytes(plan) bytes)
+ *          for sweik_solve_adjoint (sweik_checkpoint_bytes(plan) bytes);
+ *          2D only (SWEIK_EUNSUPPORTED in 3D)
  *   stream hipStream_t
  *   info   device, nullable: sweik_info written asynchronously */
 sweik_status sweik_solve(sweik_plan plan, const void *f, const int32_t *src,
                          void *S, void *ws, size_t ws_bytes, void *ckpt,
                          void *stream, sweik_info *info);
 
-/* Adjoint of the solve with ftilde held fixed (reverse sweep of the
+/* Adjoint (2D) of the solve with ftilde held fixed (reverse sweep of the
  * recurrence eq. phiRecRelation; the kernel is even, so the transposed
  * convolution is the convolution itself).
  *   dLdS   device, dims, same type as f: gradient of a loss w.r.t. S
@@ -146,16 +153,19 @@ sweik_status sweik_solve_adjoint(sweik_plan plan, const void *f,
  * Kernel classes of a solve, for sweik_solve_timed. */
 enum {
   SWEIK_KC_PREP = 0,      /* reduction of f, twiddle table */
-  SWEIK_KC_GHAT_ROW = 1,  /* kernel table rows + real FFT */
-  SWEIK_KC_GHAT_COL = 2,  /* kernel spectrum columns */
+  SWEIK_KC_GHAT_ROW = 1,  /* kernel table lines + real FFT (last axis) */
+  SWEIK_KC_GHAT_COL = 2,  /* kernel spectrum: 2D columns; 3D axis 1 */
   SWEIK_KC_PHI0_ROW = 3,  /* phi_0, first forcing term, real FFT */
-  SWEIK_KC_CONV_COL = 4,  /* column FFT * kernel spectrum * inverse FFT */
+  SWEIK_KC_CONV_COL = 4,  /* FFT * kernel spectrum * inverse FFT (2D columns, 3D axis 0) */
   SWEIK_KC_TERM_ROW = 5,  /* inverse real FFT, accumulate, next forcing, real FFT */
   SWEIK_KC_LAST_ROW = 6,  /* inverse real FFT, accumulate, S = -hbar ln phi */
-  SWEIK_KC_COUNT = 7
+  SWEIK_KC_Y_FWD = 7,     /* 3D: FFT along axis 1 */
+  SWEIK_KC_Y_INV = 8,     /* 3D: inverse FFT along axis 1 */
+  SWEIK_KC_GHAT_Z = 9,    /* 3D: kernel spectrum along axis 0 */
+  SWEIK_KC_COUNT = 10
 };
 
-/* Same work as sweik_solve (2D, no checkpoint, no info) with a HIP event
+/* Same work as sweik_solve (no checkpoint, no info) with a HIP event
  * recorded on `stream` before the first kernel and after every kernel.
  * Synchronises the stream, then writes to the HOST arrays
  * ms[SWEIK_KC_COUNT] (per class, the summed intervals between the event

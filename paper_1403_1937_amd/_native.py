@@ -190,7 +190,7 @@ class Plan:
             "sweik_solve")
 
     KERNEL_CLASSES = ("prep", "ghat_row", "ghat_col", "phi0_row", "conv_col", "term_row",
-                      "last_row")
+                      "last_row", "y_fwd", "y_inv", "ghat_z")
 
     def solve_timed(self, f, src, S, ws, stream=None) -> dict:
         """Solve with HIP events around every kernel (synchronises); returns

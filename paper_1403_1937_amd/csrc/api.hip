@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "launch2d.hpp"
+#include "launch3d.hpp"
 #include "plan.hpp"
 
 using namespace sweik;
@@ -227,7 +228,7 @@ Args2<R> make_args2(const sweik_plan_s *pl, const void *f, const int32_t *src, v
 // first kernel and one after every kernel, so that each interval covers one
 // kernel and the dispatch gap before it; durations are summed per class.
 struct KernelTimer {
-  static constexpr int kMax = 2 * (SWEIK_MAX_TERMS + 4) + 8;
+  static constexpr int kMax = 4 * (SWEIK_MAX_TERMS + 2) + 8;
   hipEvent_t ev[kMax + 1];
   int cls[kMax];
   int n = 0;
@@ -295,6 +296,147 @@ sweik_status enqueue2d_adjoint(const sweik_plan_s *pl, const void *f, const int3
   return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
 
+
+// Schedule and workspace layout of a 3D problem.
+sweik_status plan3d(sweik_plan_s *pl) {
+  const sweik_problem &p = pl->p;
+  const bool f64 = p.prec == SWEIK_F64;
+  const int esz = f64 ? 8 : 4;
+  const int csz = 2 * esz;
+  Geo3 &g = pl->g3;
+  int64_t M[3];
+  for (int d = 0; d < 3; ++d) {
+    M[d] = std::max<int64_t>(64, next_pow2(2 * p.dims[d] - 1));
+    if (M[d] > 1024) return SWEIK_EUNSUPPORTED;
+  }
+  g.n0 = (int)p.dims[0];
+  g.n1 = (int)p.dims[1];
+  g.n2 = (int)p.dims[2];
+  g.M0 = (int)M[0];
+  g.M1 = (int)M[1];
+  g.M2 = (int)M[2];
+  g.H0 = g.M0 / 2;
+  g.H1 = g.M1 / 2;
+  g.H2 = g.M2 / 2;
+  const size_t xl = f64 ? x_lds_bytes<double>(g.H2) : x_lds_bytes<float>(g.H2);
+  const size_t c0 = f64 ? c3_lds_bytes<double>(g.M0) : c3_lds_bytes<float>(g.M0);
+  const size_t c1 = f64 ? c3_lds_bytes<double>(g.M1) : c3_lds_bytes<float>(g.M1);
+  if (xl > kLdsDevice || c0 > kLdsDevice || c1 > kLdsDevice) return SWEIK_EUNSUPPORTED;
+  g.nlines = g.n0 * g.n1;
+  g.nbx = (g.nlines + x_lpw(g.H2) - 1) / x_lpw(g.H2);
+  g.ncb0 = g.H2 / c3_cpw(g.M0);
+  g.ncb1 = g.H2 / c3_cpw(g.M1);
+  g.lmax = std::max(2 * g.M2, std::max(g.M0, g.M1));
+  g.lmax_log = ilog2(g.lmax);
+  for (int d = 0; d < 3; ++d) pl->padded[d] = M[d];
+
+  const int64_t N = (int64_t)g.n0 * g.n1 * g.n2;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  Layout &L = pl->ws;
+  L.par = take(sizeof(Params));
+  L.red = take(sizeof(double) * 3 * kRedBlocks);
+  L.expo = take(sizeof(int) * (SWEIK_MAX_TERMS + 1));
+  L.mu = take(sizeof(double) * (size_t)(p.T + 1) * g.nbx);
+  L.mu_red = take(sizeof(double) * (size_t)(p.T + 1));
+  L.tw = take((size_t)csz * g.lmax);
+  L.g = take((size_t)esz * (g.H1 + 1) * (g.H0 + 1) * g.H2);
+  L.spec = take((size_t)csz * g.nlines * g.H2);
+  L.s2 = take((size_t)csz * g.n0 * g.M1 * g.H2);
+  L.acc = take(sizeof(double) * N);
+  L.gam = take((size_t)esz * N);
+  L.lam = 0;
+  L.total = off;
+  L.ck_total = 0;  // no adjoint in 3D
+  return SWEIK_OK;
+}
+
+template <typename R>
+Args3<R> make_args3(const sweik_plan_s *pl, const void *f, const int32_t *src, void *S,
+                    void *ws, sweik_info *info) {
+  const Geo3 &g = pl->g3;
+  const sweik_problem &p = pl->p;
+  const Layout &L = pl->ws;
+  char *w = (char *)ws;
+  Args3<R> a;
+  a.n0 = g.n0;
+  a.n1 = g.n1;
+  a.n2 = g.n2;
+  a.M0 = g.M0;
+  a.M1 = g.M1;
+  a.M2 = g.M2;
+  a.H0 = g.H0;
+  a.H1 = g.H1;
+  a.H2 = g.H2;
+  a.nlines = g.nlines;
+  a.nbx = g.nbx;
+  a.lmax_log = g.lmax_log;
+  a.T = p.T;
+  a.n_src = p.n_src;
+  a.ft_mode = p.ft_mode;
+  a.ftilde_given = p.ftilde;
+  a.h = p.h;
+  a.hbar = p.hbar;
+  a.f = (const R *)f;
+  a.src = src;
+  a.S = (R *)S;
+  a.par = (Params *)(w + L.par);
+  a.red = (double *)(w + L.red);
+  a.mu = (double *)(w + L.mu);
+  a.mu_red = (double *)(w + L.mu_red);
+  a.expo = (int *)(w + L.expo);
+  a.tw = (const cplx<R> *)(w + L.tw);
+  a.s1 = (cplx<R> *)(w + L.spec);
+  a.s2 = (cplx<R> *)(w + L.s2);
+  a.g = (R *)(w + L.g);
+  a.acc = (double *)(w + L.acc);
+  a.gam = (R *)(w + L.gam);
+  a.info = info;
+  return a;
+}
+
+// One 3D solve: reduction of f, kernel spectrum (x, y, z passes), phi_0,
+// then per term y forward, z convolution, y inverse and the x pass.
+template <typename R>
+sweik_status enqueue3d(const sweik_plan_s *pl, const void *f, const int32_t *src, void *S,
+                       void *ws, hipStream_t st, sweik_info *info, KernelTimer *tm = nullptr) {
+  const Geo3 &g = pl->g3;
+  Args3<R> a = make_args3<R>(pl, f, src, S, ws, info);
+  const long long N = (long long)g.n0 * g.n1 * g.n2;
+  hipError_t err = hipSuccess;
+  auto launch = [&](int cls, auto &&fn) {
+    if (err != hipSuccess) return;
+    if (tm && tm->n < KernelTimer::kMax) {
+      if (tm->n == 0) (void)hipEventRecord(tm->ev[0], st);
+      err = fn();
+      (void)hipEventRecord(tm->ev[tm->n + 1], st);
+      tm->cls[tm->n++] = cls;
+    } else {
+      err = fn();
+    }
+  };
+  const int ny = g.n0 * g.ncb1;  // y passes: planes i0
+  const int T = pl->p.T;
+  launch(SWEIK_KC_PREP, [&] { return launch_prep<R>((const R *)f, N, a.red, (cplx<R> *)a.tw, g.lmax, st); });
+  launch(SWEIK_KC_GHAT_ROW, [&] { return launch_x3<R>(X_GHAT, g.H2, g.nbx, st, a, 0); });
+  if (T > 0) {
+    launch(SWEIK_KC_GHAT_COL, [&] { return launch_c3<R>(C3_GY, g.M1, ny, st, a, -1); });
+    launch(SWEIK_KC_GHAT_Z, [&] { return launch_c3<R>(C3_GZ, g.M0, (g.H1 + 1) * g.ncb0, st, a, -1); });
+  }
+  launch(SWEIK_KC_PHI0_ROW, [&] { return launch_x3<R>(X_PHI0, g.H2, g.nbx, st, a, 0); });
+  for (int i = 1; i <= T; ++i) {
+    launch(SWEIK_KC_Y_FWD, [&] { return launch_c3<R>(C3_YF, g.M1, ny, st, a, i - 1); });
+    launch(SWEIK_KC_CONV_COL, [&] { return launch_c3<R>(C3_Z, g.M0, g.M1 * g.ncb0, st, a, -1); });
+    launch(SWEIK_KC_Y_INV, [&] { return launch_c3<R>(C3_YI, g.M1, ny, st, a, -1); });
+    launch(i == T ? SWEIK_KC_LAST_ROW : SWEIK_KC_TERM_ROW,
+           [&] { return launch_x3<R>(X_TERM, g.H2, g.nbx, st, a, i); });
+  }
+  return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
+}
 
 // ---- uneven batches ---------------------------------------------------------
 // Instances are grouped into size classes of equal (H1, M0): one launch per
@@ -481,11 +623,7 @@ sweik_status sweik_plan_create(const sweik_problem *problem, sweik_plan *out) {
   if (!pl) return SWEIK_ENOMEM;
   pl->p = *problem;
   pl->lds_max = kLdsDevice;
-  if (problem->ndim == 2) {
-    st = plan2d(pl);
-  } else {
-    st = SWEIK_EUNSUPPORTED;
-  }
+  st = problem->ndim == 2 ? plan2d(pl) : plan3d(pl);
   if (st != SWEIK_OK) {
     delete pl;
     return st;
@@ -531,7 +669,9 @@ sweik_status sweik_solve(sweik_plan plan, const void *f, const int32_t *src, voi
                ? enqueue2d<double>(plan, f, src, S, ws, ckpt, st, info)
                : enqueue2d<float>(plan, f, src, S, ws, ckpt, st, info);
   }
-  return SWEIK_EUNSUPPORTED;
+  if (ckpt) return SWEIK_EUNSUPPORTED;  // the adjoint is 2D only
+  return plan->p.prec == SWEIK_F64 ? enqueue3d<double>(plan, f, src, S, ws, st, info)
+                                   : enqueue3d<float>(plan, f, src, S, ws, st, info);
 }
 
 sweik_status sweik_solve_timed(sweik_plan plan, const void *f, const int32_t *src, void *S,
@@ -539,13 +679,16 @@ sweik_status sweik_solve_timed(sweik_plan plan, const void *f, const int32_t *sr
                                int32_t *count) {
   if (!plan || !f || !src || !S || !ws || !ms || !count) return SWEIK_EINVAL;
   if (ws_bytes < plan->ws.total) return SWEIK_EWORKSPACE;
-  if (plan->p.ndim != 2) return SWEIK_EUNSUPPORTED;
   hipStream_t st = (hipStream_t)stream;
   KernelTimer tm;
   if (!tm.ok) return SWEIK_EDEVICE;
-  sweik_status rc = plan->p.prec == SWEIK_F64
-                        ? enqueue2d<double>(plan, f, src, S, ws, nullptr, st, nullptr, &tm)
-                        : enqueue2d<float>(plan, f, src, S, ws, nullptr, st, nullptr, &tm);
+  const bool f64 = plan->p.prec == SWEIK_F64;
+  sweik_status rc =
+      plan->p.ndim == 2
+          ? (f64 ? enqueue2d<double>(plan, f, src, S, ws, nullptr, st, nullptr, &tm)
+                 : enqueue2d<float>(plan, f, src, S, ws, nullptr, st, nullptr, &tm))
+          : (f64 ? enqueue3d<double>(plan, f, src, S, ws, st, nullptr, &tm)
+                 : enqueue3d<float>(plan, f, src, S, ws, st, nullptr, &tm));
   if (rc != SWEIK_OK) return rc;
   if (hipStreamSynchronize(st) != hipSuccess) return SWEIK_EDEVICE;
   for (int c = 0; c < SWEIK_KC_COUNT; ++c) {

@@ -36,6 +36,8 @@
 #include "green.hpp"
 #include "sweik.h"
 
+#include <type_traits>
+
 namespace sweik {
 
 constexpr int kRedBlocks = 256;  // partial reductions of f
@@ -89,8 +91,8 @@ template <typename R>
 __device__ __forceinline__ void prep_block(const R *__restrict__ f, long long N,
                                            double *__restrict__ red, cplx<R> *__restrict__ tw,
                                            int lmax, int bid, int nblk) {
-  __shared__ double smin[4], smax[4];
-  __shared__ int sfl[4];
+  __shared__ double smin[16], smax[16];  // up to 1024 threads
+  __shared__ int sfl[16];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
   int fl = 0;
@@ -150,8 +152,8 @@ __global__ void __launch_bounds__(256) k_prep(const R *__restrict__ f, long long
 __device__ inline void reduce_forcing(const double *__restrict__ red, int ft_mode,
                                       double ft_given, double *out_lo,
                                       double *out_hi, int *out_fl) {
-  __shared__ double slo[4], shi[4];
-  __shared__ int sfl[4];
+  __shared__ double slo[16], shi[16];
+  __shared__ int sfl[16];
   double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
   int fl = 0;
   for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) {
@@ -183,8 +185,9 @@ __device__ inline void reduce_forcing(const double *__restrict__ red, int ft_mod
   *out_fl = fl;
 }
 
+// block reductions for up to 1024 threads (16 waves)
 __device__ inline double block_max(double x) {
-  __shared__ double s[4];
+  __shared__ double s[16];
   x = wave_max(x);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   __syncthreads();
@@ -196,7 +199,7 @@ __device__ inline double block_max(double x) {
 }
 
 __device__ inline long long block_sum_ll(long long x) {
-  __shared__ long long s[4];
+  __shared__ long long s[16];
   x = wave_sum(x);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
   __syncthreads();
@@ -215,9 +218,10 @@ __device__ inline int exp_step(double mu) {
 
 // S = -hbar ln phi (eq. SfromPhi); phi <= 0 or not finite -> +inf.
 // Returns 1 for such a point.
-template <typename R>
-__device__ __forceinline__ int write_S(const Args2<R> &a, size_t i, double phi) {
+template <typename A>
+__device__ __forceinline__ int write_S(const A &a, size_t i, double phi) {
   const bool ok = phi > 0.0 && isfinite(phi);
+  using R = typename std::remove_pointer<decltype(a.S)>::type;
   a.S[i] = ok ? (R)(-a.hbar * log(phi)) : (R)__builtin_huge_val();
   return ok ? 0 : 1;
 }

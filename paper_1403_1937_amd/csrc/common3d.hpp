@@ -1,0 +1,73 @@
+// common3d.hpp -- geometry and arguments of the 3D perturbation-series solve.
+//
+// Grid n0 x n1 x n2 (C order), zero-padded to M0 x M1 x M2 (M_d >= 2 n_d - 1,
+// powers of two, Hd = Md / 2).  One correction term (Table 1, steps 9-13)
+// is four passes over two spectra:
+//   x pass   (axis 2, contiguous) per grid line (i0, i1): inverse real FFT
+//            of the previous term, crop, rescale, accumulate, form gamma *
+//            phi_i, forward real FFT -> s1[i0][i1][k2]      (n0 n1 H2 complex)
+//   y fwd    (axis 1) per (i0, k2): FFT of the n1 rows zero-padded to M1
+//            -> s2[i0][k1][k2]                              (n0 M1 H2 complex)
+//   z conv   (axis 0) per (k1, k2): FFT of the n0 rows zero-padded to M0,
+//            product with the kernel spectrum, inverse FFT, first n0 rows
+//            back into s2
+//   y inv    (axis 1) per (i0, k2): inverse FFT of the M1 rows, first n1
+//            rows -> s1
+// The real transform along axis 2 samples the odd frequencies
+// (k2 + 1/2) / M2: a real line then has exactly H2 independent bins, with no
+// separate zero and Nyquist bins.  With at least 2 n2 - 1 padded samples the
+// convolution it implies (nega-cyclic) equals the linear convolution, as
+// the cyclic one does.  The kernel table is therefore extended nega-cyclically
+// along axis 2 (kappa at -d sits at M2 - d with the opposite sign) and evenly
+// along axes 0 and 1; its spectrum is real and even in k0 and k1, and is
+// stored as the orthant g[k1'][k0'][k2], k0' <= H0, k1' <= H1, k2 < H2,
+// pre-scaled by 1 / (4 M0 M1 M2) (the unnormalised transforms' round trips).
+#pragma once
+
+#include "common2d.hpp"
+
+namespace sweik {
+
+enum XMode { X_GHAT = 0, X_PHI0 = 1, X_TERM = 2 };
+enum C3Mode { C3_YF = 0, C3_Z = 1, C3_YI = 2, C3_GY = 3, C3_GZ = 4 };
+
+// x pass: one team of P = H2/16 threads per line, 256 threads per group
+constexpr int x_lpw(int H) { return kThreads / (H / 16); }
+template <typename R> constexpr size_t x_lds_bytes(int H) {
+  // twiddles exp(-2 pi i q / 4H), q < 4H, and one padded line per team
+  return sizeof(R) * 2 * ((size_t)4 * H + (size_t)x_lpw(H) * lds_line_len(H));
+}
+// column passes: CPW neighbouring k2 columns per group, one team of M/16
+// threads per column, threads ordered column-fastest so that a wave reads
+// CPW contiguous spectrum entries per row
+constexpr int c3_cpw(int M) { return 8192 / M < 32 ? 8192 / M : 32; }
+constexpr int c3_threads(int M) { return c3_cpw(M) * (M / 16); }
+template <typename R> constexpr size_t c3_lds_bytes(int M) {
+  return sizeof(R) * 2 * ((size_t)M + (size_t)c3_cpw(M) * lds_line_len(M));
+}
+
+template <typename R> struct Args3 {
+  int n0, n1, n2;
+  int M0, M1, M2, H0, H1, H2;
+  int nlines;    // n0 n1 grid lines along axis 2
+  int nbx;       // x-pass work-groups
+  int lmax_log;  // log2 of the twiddle table length
+  int T, n_src, ft_mode;
+  double ftilde_given, h, hbar;
+  const R *f;
+  const int *src;
+  R *S;
+  Params *par;
+  double *red;     // kRedBlocks x 3
+  double *mu;      // (T+1) x nbx partial max |m_i|
+  double *mu_red;  // T+1 reduced maxima
+  int *expo;       // T+1 exponents
+  const cplx<R> *tw;
+  cplx<R> *s1, *s2;
+  R *g;            // kernel spectrum orthant
+  double *acc;     // N
+  R *gam;          // N
+  sweik_info *info;
+};
+
+}  // namespace sweik

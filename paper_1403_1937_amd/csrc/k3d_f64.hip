@@ -1,0 +1,6 @@
+// k3d_f64.hip -- double instantiation of the 3D kernels.
+#include "k3d_impl.hpp"
+
+namespace sweik {
+SWEIK_INSTANTIATE_3D(double)
+}

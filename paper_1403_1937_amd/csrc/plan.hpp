@@ -20,8 +20,16 @@ struct Geo2 {
   int lmax, lmax_log;
 };
 
+struct Geo3 {
+  int n0, n1, n2;
+  int M0, M1, M2, H0, H1, H2;
+  int nlines, nbx;     // x-pass lines and work-groups
+  int ncb0, ncb1;      // column blocks per plane of the z and y passes
+  int lmax, lmax_log;
+};
+
 struct Layout {      // byte offsets into the workspace / checkpoint
-  size_t par, red, expo, mu, tw, g, spec, acc, lam, gam, total;
+  size_t par, red, expo, mu, mu_red, tw, g, spec, s2, acc, lam, gam, total;
   size_t ck_expo, ck_par, ck_g, ck_phi, ck_terms, ck_total;
 };
 
@@ -32,5 +40,6 @@ struct sweik_plan_s {
   int64_t padded[3];
   size_t lds_max;
   sweik::Geo2 g2;
+  sweik::Geo3 g3;
   sweik::Layout ws;
 };

@@ -1,0 +1,343 @@
+// x3d.hpp -- passes along the contiguous axis of the 3D solve.
+//   X_GHAT  kernel table lines (nega-cyclic extension), forward real FFT;
+//           also reduces f into the reference forcing and publishes it
+//   X_PHI0  phi_0 from the sources (eq. phi_0Solution), first forcing term,
+//           forward real FFT
+//   X_TERM  term `term`: inverse real FFT, rescale, accumulate; then the next
+//           forcing term and its FFT, or (term == T) S = -hbar ln phi
+#pragma once
+
+#include "common3d.hpp"
+
+namespace sweik {
+
+// Odd-frequency real transform of a line of M = 2H real samples held by a
+// team as u(m) = x(2m) + i x(2m+1), m = t + P j.  With w(q) = exp(-2 pi i q /
+// 2M) (the LDS table, 4H entries):
+//   forward  U = FFT_H(u(m) w(2m));  X(k) = E(k) + w(2k+1) O(k) with
+//            2E = U(k) + conj U(H-1-k), 2iO = U(k) - conj U(H-1-k)
+//            -> returns 2 X(k) = sum_j x(j) exp(-2 pi i j (k + 1/2) / M)
+//   inverse  the same steps backwards; returns 2M times the real line.
+template <typename R, int H, int TWLOG>
+__device__ __forceinline__ void odd_r2c(cplx<R> (&v)[16], int t, cplx<R> *line,
+                                        const cplx<R> *twl) {
+  using C = cplx<R>;
+  constexpr int P = H / 16;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = cmul(v[j], twl[2 * (t + P * j)]);
+  team_fft<H, TWLOG, false>(v, t, line, twl, true);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) line[lpad(t + P * j)] = v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int k = t + P * j;
+    const C up = cconj(line[lpad(H - 1 - k)]);
+    const C e = cadd(v[j], up);
+    const C d = csub(v[j], up);
+    const C o = cmake<C>(d.y, -d.x);  // -i d = 2 O
+    v[j] = cadd(e, cmul(o, twl[2 * k + 1]));
+  }
+}
+
+template <typename R, int H, int TWLOG>
+__device__ __forceinline__ void odd_c2r(cplx<R> (&v)[16], int t, cplx<R> *line,
+                                        const cplx<R> *twl) {
+  using C = cplx<R>;
+  constexpr int P = H / 16;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) line[lpad(t + P * j)] = v[j];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int k = t + P * j;
+    const C xp = cconj(line[lpad(H - 1 - k)]);
+    const C e = cadd(v[j], xp);                         // 2E
+    const C o = cmulc(csub(v[j], xp), twl[2 * k + 1]);  // 2O
+    v[j] = cmake<C>(e.x - o.y, e.y + o.x);              // 2(E + iO)
+  }
+  team_fft<H, TWLOG, true>(v, t, line, twl, true);
+#pragma unroll
+  for (int j = 0; j < 16; ++j) v[j] = cmulc(v[j], twl[2 * (t + P * j)]);
+}
+
+// FULL: every line of the group exists and n2 == H2 (no bounds checks).
+template <typename R, int MODE, int H, bool FULL>
+__device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned char *smem_raw,
+                                       const int bid) {
+  using C = cplx<R>;
+  constexpr int P = H / 16, LPW = x_lpw(H), LL = lds_line_len(H);
+  constexpr int TWLOG = ilog2c(4 * H);
+  constexpr int NTW = (4 * H + kThreads - 1) / kThreads;
+  C *twl = reinterpret_cast<C *>(smem_raw);
+  C *lines = twl + 4 * H;
+  __shared__ double s_par[1];
+
+  const int tid = threadIdx.x, team = tid / P, t = tid - team * P;
+  const int r = bid * LPW + team;  // line index i0 n1 + i1
+  const bool line_ok = FULL || r < a.nlines;
+  const int rs = line_ok ? r : 0;
+  const int i0 = rs / a.n1, i1 = rs - i0 * a.n1;
+  C *line = lines + team * LL;
+  const size_t rowoff = (size_t)rs * a.n2;
+  const bool last = (MODE == X_TERM && term == a.T) || (MODE == X_PHI0 && a.T == 0);
+  auto col_ok = [&](int c) { return FULL ? true : (line_ok && c < a.n2); };
+  const bool vec = FULL || (a.n2 & 1) == 0;  // column pairs aligned: vector access
+
+  // ---- 1. issue the global reads ---------------------------------------------
+  C twr[NTW];
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) {
+    const int k = tid + u * kThreads;
+    if (k < 4 * H) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
+  }
+  C v[16];
+  if constexpr (MODE == X_TERM) {
+    const C *sl = a.s1 + (size_t)rs * H;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = line_ok ? sl[t + P * j] : cmake<C>((R)0, (R)0);
+  }
+  // pointwise operands of columns c = 2m, 2m+1, m = t + P j (only j < 8
+  // can lie in the grid since n2 <= H)
+  R o1[16];
+  double od[16];
+  if constexpr (MODE == X_TERM || MODE == X_PHI0) {
+    const R *p1 = last ? nullptr : (MODE == X_PHI0 ? a.f : a.gam);
+    const double *pd = MODE == X_TERM ? a.acc : nullptr;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c0 = 2 * (t + P * j);
+      if (vec) {
+        using V = cplx<R>;
+        V x1 = cmake<V>((R)0, (R)0);
+        double2 xd = make_double2(0.0, 0.0);
+        if (col_ok(c0)) {
+          if (p1) x1 = *reinterpret_cast<const V *>(p1 + rowoff + c0);
+          if (pd) xd = *reinterpret_cast<const double2 *>(pd + rowoff + c0);
+        }
+        o1[2 * j] = x1.x;
+        o1[2 * j + 1] = x1.y;
+        od[2 * j] = xd.x;
+        od[2 * j + 1] = xd.y;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const bool ok = col_ok(c0 + e);
+          o1[2 * j + e] = (ok && p1) ? p1[rowoff + c0 + e] : (R)0;
+          od[2 * j + e] = (ok && pd) ? pd[rowoff + c0 + e] : 0.0;
+        }
+      }
+    }
+  }
+
+  // ---- 2. scalars ------------------------------------------------------------
+  double beta, inv_ft2, ft;
+  if constexpr (MODE == X_GHAT) {
+    double lo, hi;
+    int fl;
+    reduce_forcing(a.red, a.ft_mode, a.ftilde_given, &lo, &hi, &fl);
+    ft = a.ft_mode == SWEIK_FT_NU ? sqrt(0.5 * (lo * lo + hi * hi))
+         : a.ft_mode == SWEIK_FT_FMAX ? hi : a.ftilde_given;
+    beta = ft * a.h / a.hbar;
+    inv_ft2 = 1.0 / (ft * ft);
+    if (tid == 0) {
+      s_par[0] = kappa0_3d(beta);
+      if (bid == 0) {
+        const double c0 = fmax((hi - ft) * (hi + ft), (ft - lo) * (ft + lo)) * inv_ft2;
+        if (!(c0 < 1.0)) fl |= SWEIK_FLAG_C0_GE_1;
+        for (int k = 0; k < a.n_src; ++k) {
+          const int y0 = a.src[3 * k], y1 = a.src[3 * k + 1], y2 = a.src[3 * k + 2];
+          if (y0 < 0 || y0 >= a.n0 || y1 < 0 || y1 >= a.n1 || y2 < 0 || y2 >= a.n2)
+            fl |= SWEIK_FLAG_BAD_SOURCE;
+        }
+        Params p;
+        p.ftilde = ft;
+        p.beta = beta;
+        p.hbar = a.hbar;
+        p.inv_ft2 = inv_ft2;
+        p.kappa0 = s_par[0];
+        p.fmin = lo;
+        p.fmax = hi;
+        p.c0 = c0;
+        p.flags = fl;
+        p.pad_ = 0;
+        *a.par = p;
+        if (a.info) {
+          a.info->f_min = lo;
+          a.info->f_max = hi;
+          a.info->ftilde = ft;
+          a.info->beta = beta;
+          a.info->c0_bound = c0;
+          a.info->n_nonpositive_phi = 0;
+          a.info->flags = fl;
+          a.info->T = a.T;
+        }
+      }
+    }
+    __syncthreads();
+  } else {
+    beta = a.par->beta;
+    inv_ft2 = a.par->inv_ft2;
+    ft = a.par->ftilde;
+  }
+  int dstep = 0, E = 0;
+  if (MODE == X_TERM) {
+    dstep = exp_step(a.mu_red[term - 1]);
+    E = a.expo[term - 1] + dstep;
+  }
+  if ((MODE == X_TERM || MODE == X_PHI0) && bid == 0 && tid == 0) {
+    const int slot = MODE == X_TERM ? term : 0;
+    a.expo[slot] = E;
+    if (a.info) a.info->scale_exp[slot] = E;
+  }
+  constexpr int kSrcLds = MODE == X_PHI0 ? 512 : 1;
+  __shared__ int s_src[3 * kSrcLds];
+  if (MODE == X_PHI0)
+    for (int i = tid; i < 3 * min(a.n_src, kSrcLds); i += kThreads) s_src[i] = a.src[i];
+
+#pragma unroll
+  for (int u = 0; u < NTW; ++u) {
+    const int k = tid + u * kThreads;
+    if (k < 4 * H) twl[k] = twr[u];
+  }
+  __syncthreads();
+
+  // ---- 3. kernel table -------------------------------------------------------
+  if constexpr (MODE == X_GHAT) {
+    // line (d0, d1) = (i0, i1): x(c) = kappa(|d|) for c < n2, -kappa at M2 - c
+    // for 0 < c < n2, zero between
+    const double k0v = s_par[0];
+    const long long r01 = (long long)i0 * i0 + (long long)i1 * i1;
+    const int M2 = 2 * H;
+    auto tab = [&](int c) -> R {
+      if (!line_ok) return (R)0;
+      if (c < a.n2) return (R)kappa_3d(beta, r01 + (long long)c * c, k0v);
+      const int d = M2 - c;
+      if (d < a.n2) return (R)(-kappa_3d(beta, r01 + (long long)d * d, k0v));
+      return (R)0;
+    };
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const int c0 = 2 * (t + P * j);
+      v[j] = cmake<C>(tab(c0), tab(c0 + 1));
+    }
+  }
+
+  if constexpr (MODE == X_TERM) odd_c2r<R, H, TWLOG>(v, t, line, twl);
+
+  // ---- 4. pointwise step -------------------------------------------------------
+  if constexpr (MODE == X_PHI0 || MODE == X_TERM) {
+    long long nbad = 0;
+    const R sm = (R)ldexp(1.0, -dstep);
+    const double sE = ((MODE == X_TERM && (term & 1)) ? -1.0 : 1.0) * ldexp(1.0, E);
+    R mlr = (R)0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int c0 = 2 * (t + P * j);
+      R z0 = 0, z1 = 0;
+      if (col_ok(c0)) {
+        const bool ok1 = FULL || c0 + 1 < a.n2;
+        double p0, p1 = 0.0;
+        R m0, m1;
+        if constexpr (MODE == X_PHI0) {
+          // phi_0 = sum_k exp(-beta |m - y_k|)  (eq. phi_0Solution, C = 1)
+          double s0 = 0.0, s1 = 0.0;
+          if constexpr (sizeof(R) == 4) {
+            const float nb = (float)(-beta * 1.4426950408889634);  // exp(x) = 2^(x log2 e)
+            float f0 = 0.0f, f1 = 0.0f;
+            for (int k = 0; k < a.n_src; ++k) {
+              const int *y = k < kSrcLds ? s_src + 3 * k : a.src + 3 * k;
+              const float d0 = (float)(i0 - y[0]), d1 = (float)(i1 - y[1]);
+              const float d2 = (float)(c0 - y[2]);
+              const float q = d0 * d0 + d1 * d1;
+              f0 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q + d2 * d2));
+              f1 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q + (d2 + 1.0f) * (d2 + 1.0f)));
+            }
+            s0 = f0;
+            s1 = f1;
+          } else {
+            for (int k = 0; k < a.n_src; ++k) {
+              const int *y = k < kSrcLds ? s_src + 3 * k : a.src + 3 * k;
+              const double d0 = (double)(i0 - y[0]), d1 = (double)(i1 - y[1]);
+              const double d2 = (double)(c0 - y[2]);
+              const double q = d0 * d0 + d1 * d1;
+              s0 += exp(-beta * sqrt(q + d2 * d2));
+              s1 += exp(-beta * sqrt(q + (d2 + 1) * (d2 + 1)));
+            }
+          }
+          m0 = (R)s0;
+          m1 = (R)s1;
+          p0 = s0;
+          p1 = s1;
+        } else {
+          m0 = v[j].x * sm;  // power-of-two rescale: exact
+          m1 = v[j].y * sm;
+          p0 = fma((double)m0, sE, od[2 * j]);
+          p1 = ok1 ? fma((double)m1, sE, od[2 * j + 1]) : 0.0;
+        }
+        if (last) {
+          nbad += write_S(a, rowoff + c0, p0);
+          if (ok1) nbad += write_S(a, rowoff + c0 + 1, p1);
+        } else {
+          if (vec)
+            *reinterpret_cast<double2 *>(a.acc + rowoff + c0) = make_double2(p0, p1);
+          else {
+            a.acc[rowoff + c0] = p0;
+            if (ok1) a.acc[rowoff + c0 + 1] = p1;
+          }
+          R g0, g1 = (R)0;
+          if constexpr (MODE == X_PHI0) {
+            const double fa = (double)o1[2 * j];
+            g0 = (R)((fa - ft) * (fa + ft) * inv_ft2);
+            a.gam[rowoff + c0] = g0;
+            if (ok1) {
+              const double fb = (double)o1[2 * j + 1];
+              g1 = (R)((fb - ft) * (fb + ft) * inv_ft2);
+              a.gam[rowoff + c0 + 1] = g1;
+            }
+          } else {
+            g0 = o1[2 * j];
+            if (ok1) g1 = o1[2 * j + 1];
+          }
+          z0 = g0 * m0;
+          z1 = ok1 ? g1 * m1 : (R)0;
+          mlr = fmax(mlr, fabs(m0));
+          if (ok1) mlr = fmax(mlr, fabs(m1));
+        }
+      }
+      v[j] = cmake<C>(z0, z1);
+    }
+    if (last) {
+      const long long nb = block_sum_ll(nbad);
+      if (tid == 0 && a.info && nb)
+        atomicAdd((unsigned long long *)&a.info->n_nonpositive_phi, (unsigned long long)nb);
+      return;
+    }
+    const double bm = block_max((double)mlr);
+    if (tid == 0) a.mu[(size_t)(MODE == X_TERM ? term : 0) * a.nbx + bid] = bm;
+#pragma unroll
+    for (int j = 8; j < 16; ++j) v[j] = cmake<C>((R)0, (R)0);
+  }
+
+  // ---- 5. forward real FFT, store the line's spectrum ------------------------
+  odd_r2c<R, H, TWLOG>(v, t, line, twl);
+  if (line_ok) {
+    C *sl = a.s1 + (size_t)rs * H;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) sl[t + P * j] = v[j];
+  }
+}
+
+template <typename R, int MODE, int H>
+__global__ void __launch_bounds__(kThreads) k_x3(Args3<R> a, int term) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int bid = blockIdx.x;
+  if ((bid + 1) * x_lpw(H) <= a.nlines && a.n2 == H)
+    x_pass<R, MODE, H, true>(a, term, smem_raw, bid);
+  else
+    x_pass<R, MODE, H, false>(a, term, smem_raw, bid);
+}
+
+}  // namespace sweik

@@ -1,0 +1,134 @@
+"""GPU parity of the 3D forward solve against the FP64 CPU oracle.
+
+The 3D path uses an odd-frequency real transform along the last axis and
+full transforms along the other two; the oracle uses its own complex
+radix-2 FFT over the whole padded box.  Tolerances are claimed on the
+resolvable sets of tests/common.py.  At the full 256^3 size the oracle is
+too slow, so there the checks are properties that hold at any size: the
+constant-forcing closed form and agreement of the FP32-scaled path with the
+FP64 path on the resolvable set.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from common import TOL, ensure_built, envelope_violations, rel_err, report, resolvable
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    ensure_built()
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _run(f32, src, h, hbar, T, prec, ft_mode="nu", ftilde=None):
+    import paper_1403_1937_amd as pk
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    f = torch.as_tensor(f32.astype(np.float64)).to("cuda", dt)
+    S, info = pk.solve(f, src, h, hbar, T, ftilde_mode=ft_mode, ftilde=ftilde, return_info=True)
+    torch.cuda.synchronize()
+    return S.double().cpu().numpy(), info
+
+
+CASES = [
+    # (name, dims, h, hbar, T, n_src, seed)
+    ("cube16", (16, 16, 16), 1 / 16, 0.1, 6, 2, 21),
+    ("ragged5x6x7", (5, 6, 7), 1 / 7, 0.15, 4, 1, 22),
+    ("ragged20x9x33", (20, 9, 33), 1 / 33, 0.08, 5, 3, 23),
+    ("full32", (32, 32, 32), 1 / 32, 0.1, 8, 2, 24),
+    ("mixed16x48x64", (16, 48, 64), 1 / 64, 0.06, 6, 4, 25),
+    ("rect40x33x65", (40, 33, 65), 1 / 65, 0.1, 5, 2, 26),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_forward_parity_3d(case, prec):
+    name, dims, h, hbar, T, n_src, seed = case
+    rng = np.random.default_rng(seed)
+    f = workloads.smoothed_noise(dims, 3.0, 0.5, 2.0, rng).astype(np.float32)
+    src = workloads.distinct_sources(dims, n_src, rng)
+    print(f"case {name} prec {prec} dims {dims}", flush=True)
+    S, info = _run(f, src, h, hbar, T, prec)
+    o = oracle.solve(f.astype(np.float64), src, h, hbar, T)
+    assert info["flags"] == 0
+    assert abs(info["ftilde"] - o["info"]["ftilde"]) <= 1e-14 * o["info"]["ftilde"]
+    worst, frac, _ = report(S, o, hbar, prec)
+    nbad = envelope_violations(S, o, hbar, prec)
+    print(f"  max rel on resolvable set {worst:.3e} (fraction {frac:.3f}); "
+          f"envelope violations {nbad}", flush=True)
+    assert frac > 0.1
+    assert worst <= TOL[prec]
+    assert nbad == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_blobs_workload_reduced(prec):
+    """The 256^3 blob workload's recipe at 48^3 (h = 1/48, hbar = 0.1,
+    one source at the centre, T = 16)."""
+    p = workloads.problem(3, 48)
+    S, info = _run(p.f, p.src, p.h, p.hbar, p.T, prec)
+    o = oracle.solve(p.f.astype(np.float64), p.src, p.h, p.hbar, p.T)
+    worst, frac, _ = report(S, o, p.hbar, prec)
+    print(f"blobs48 {prec}: max rel {worst:.3e} on {frac:.3f}", flush=True)
+    assert worst <= TOL[prec]
+    assert envelope_violations(S, o, p.hbar, prec) == 0
+
+
+def _closed_form(dims, src, c, h, hbar):
+    g = np.stack(np.meshgrid(*[np.arange(n) for n in dims], indexing="ij"), -1)
+    acc = np.zeros(dims)
+    for s in src:
+        acc += np.exp(-c * np.linalg.norm(g - s, axis=-1) * h / hbar)
+    return -hbar * np.log(acc)
+
+
+def test_constant_forcing_closed_form_3d():
+    """f = c => gamma = 0 => phi = phi_0 exactly (eq. phi_0Solution)."""
+    dims = (12, 17, 30)
+    src = np.array([[1, 2, 3], [10, 15, 20]], np.int32)
+    f = np.full(dims, 1.25, np.float32)
+    S, info = _run(f, src, 0.05, 0.1, 4, "fp64")
+    assert info["c0_bound"] == 0.0
+    assert np.max(np.abs(S - _closed_form(dims, src, 1.25, 0.05, 0.1))) < 1e-12
+
+
+def test_full_size_256_closed_form_and_fp32_vs_fp64():
+    """At 256^3 (the blob workload's size): the constant-forcing closed form
+    on a sample of points, and FP32-scaled vs FP64 on the blob forcing."""
+    n = 256
+    p = workloads.problem(3, n)
+    f = np.full((n, n, n), 1.3, np.float32)
+    print("256^3 constant forcing, fp32", flush=True)
+    S, info = _run(f, p.src, p.h, p.hbar, 3, "fp32")
+    rng = np.random.default_rng(31)
+    idx = rng.integers(0, n, (4096, 3))
+    d = np.linalg.norm(idx - p.src[0], axis=-1) * p.h
+    ref = 1.3 * d  # one source: S = ftilde |x - y|
+    got = S[idx[:, 0], idx[:, 1], idx[:, 2]]
+    assert np.max(np.abs(got - ref) / np.maximum(ref, p.hbar)) < 1e-5
+    print("256^3 blobs, fp32 and fp64", flush=True)
+    S32, _ = _run(p.f, p.src, p.h, p.hbar, p.T, "fp32")
+    S64, _ = _run(p.f, p.src, p.h, p.hbar, p.T, "fp64")
+    # resolvable set of the FP32 path judged from the FP64 result
+    phi64 = np.exp(-(S64 - S64.min()) / p.hbar)
+    m = resolvable(phi64, "fp32")
+    e = rel_err(S32, S64, p.hbar)
+    print(f"  fp32 vs fp64: max rel {e[m].max():.3e} on {m.mean():.3f}", flush=True)
+    assert m.mean() > 0.1
+    assert e[m].max() <= TOL["fp32"]
+
+
+def test_zero_terms_3d():
+    rng = np.random.default_rng(32)
+    dims = (9, 10, 11)
+    f = rng.uniform(1, 2, dims).astype(np.float32)
+    src = np.array([[4, 5, 5]], np.int32)
+    S, _ = _run(f, src, 0.1, 0.2, 0, "fp64")
+    o = oracle.solve(f.astype(np.float64), src, 0.1, 0.2, 0)
+    assert np.max(rel_err(S, o["S"], 0.2)) < 1e-13
