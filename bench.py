@@ -15,6 +15,9 @@ Also reported on the same JSON line:
                    loss = sum over 256 receivers of (S - target)^2
   batched          64 uneven instances (edges from {256, 512, 1024, 2048},
                    T = 12, FP32-scaled) solved by one replay of a HIP graph
+  solve3d          256^3 grid, f from 32 Gaussian blobs in [0.5, 2], one
+                   source at the centre, hbar = 0.1, T = 16; FP32-scaled and
+                   FP64, per-kernel classes and the dominant kernel's roofline
   roofline         of the dominant kernel: algorithmic bytes per launch over
                    its HIP-event-timed duration; `traffic` from the committed
                    FETCH_SIZE / WRITE_SIZE counter summary when it was taken
@@ -89,6 +92,33 @@ def alg_bytes_2d(n0, n1, H1, H0, esz, ckpt=False):
     }
 
 
+def alg_bytes_3d(dims, padded, esz):
+    """Algorithmic bytes per kernel class of a 3D forward solve (same rule):
+    s1 = n0 n1 H2 and s2 = n0 M1 H2 complex spectra, the kernel spectrum
+    (H1+1)(H0+1)H2 real."""
+    n0, n1, n2 = dims
+    M0, M1, M2 = padded
+    H0, H1, H2 = M0 // 2, M1 // 2, M2 // 2
+    N = n0 * n1 * n2
+    csz = 2 * esz
+    s1 = csz * n0 * n1 * H2
+    s2 = csz * n0 * M1 * H2
+    g = esz * (H1 + 1) * (H0 + 1) * H2
+    s2g = csz * n0 * (H1 + 1) * H2
+    return {
+        "prep": esz * N,
+        "ghat_row": s1,
+        "ghat_col": s1 + s2g,
+        "ghat_z": s2g + g,
+        "phi0_row": 2 * esz * N + 8 * N + s1,
+        "y_fwd": s1 + s2,
+        "conv_col": 2 * s2 + g,
+        "y_inv": s2 + s1,
+        "term_row": 2 * s1 + esz * N + 16 * N,
+        "last_row": s1 + 8 * N + esz * N,
+    }
+
+
 def alg_bytes_adjoint_2d(n0, n1, H1, H0, esz, T):
     """Algorithmic bytes of the adjoint sweep (same rule): lambda start,
     then per term a column convolution and a row pass that reads the
@@ -131,7 +161,7 @@ def _events(torch, stream):
 
 
 def run_main(pk, torch, dev, p, precision, steps, warmup):
-    n0, n1 = p.dims
+    n0, n1 = p.dims[:2]
     dt = torch.float32 if precision == "fp32" else torch.float64
     f = torch.as_tensor(p.f.astype(np.float32 if precision == "fp32" else np.float64)).to(dev, dt)
     src = torch.as_tensor(p.src).to(dev)
@@ -160,8 +190,11 @@ def run_main(pk, torch, dev, p, precision, steps, warmup):
             a[0] += m
             a[1] += c
     esz = 4 if precision == "fp32" else 8
-    H1, H0 = plan.padded[1] // 2, plan.padded[0] // 2
-    ab = alg_bytes_2d(n0, n1, H1, H0, esz)
+    if len(p.dims) == 3:
+        ab = alg_bytes_3d(p.dims, plan.padded, esz)
+    else:
+        H1, H0 = plan.padded[1] // 2, plan.padded[0] // 2
+        ab = alg_bytes_2d(n0, n1, H1, H0, esz)
     kern = {}
     for k, (m, c) in acc.items():
         if c == 0:
@@ -171,6 +204,25 @@ def run_main(pk, torch, dev, p, precision, steps, warmup):
                    "alg_bytes": ab[k], "GBps": ab[k] / (avg_ms * 1e-3) / 1e9}
     total_bytes = sum(ab[k] * kern[k]["launches_per_step"] for k in kern)
     return ms, kern, total_bytes
+
+
+def run_3d(pk, torch, dev, steps, warmup):
+    """The 256^3 blob workload, FP32-scaled and FP64."""
+    import workloads
+    p = workloads.problem(3)
+    N = int(np.prod(p.dims))
+    out = {"workload": "blobs3d_256x256x256_T16_src1", "unit": "grid pts/s"}
+    for prec in ("fp32", "fp64"):
+        ms, kern, tb = run_main(pk, torch, dev, p, prec, steps, warmup)
+        dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches_per_step"])
+        out[prec] = {"value": N / (ms * 1e-3), "ms_per_step": ms,
+                     "solve_alg_GBps": tb / (ms * 1e-3) / 1e9, "solve_alg_bytes": tb,
+                     "roofline": {"bound": "hbm", "kernel": dom, "achieved": kern[dom]["GBps"],
+                                  "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                                  "frac": kern[dom]["GBps"] / HBM_PEAK_GBPS},
+                     "kernels": kern}
+    out["speedup_fp32_over_fp64"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
+    return out
 
 
 def run_fwd_bwd(pk, torch, dev, steps, warmup):
@@ -400,6 +452,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip fwd+bwd and batched")
+    ap.add_argument("--only", choices=["fwd_bwd", "batched", "solve3d"],
+                    help="run one extra section alone and print its JSON (profiling runs)")
     ap.add_argument("--pmc-run", action="store_true")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH", "WRITE"))
     ap.add_argument("--stats-summary", metavar="CSV")
@@ -432,6 +486,11 @@ def main():
     p = workloads.problem(2, args.n)
     n0, n1 = p.dims
     N = n0 * n1
+
+    if args.only:
+        fn = {"fwd_bwd": run_fwd_bwd, "batched": run_batched, "solve3d": run_3d}[args.only]
+        print(json.dumps(fn(pk, torch, dev, args.steps, args.warmup)))
+        return
 
     if args.pmc_run:
         a = torch.rand(COPY_ELEMS, device=dev)
@@ -484,6 +543,7 @@ def main():
     if not args.no_extra:
         out["fwd_bwd"] = run_fwd_bwd(pk, torch, dev, max(3, args.steps // 2), 2)
         out["batched"] = run_batched(pk, torch, dev, max(3, args.steps // 4), 1)
+        out["solve3d"] = run_3d(pk, torch, dev, max(3, args.steps // 4), 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out))
