@@ -55,7 +55,8 @@ COPY_ELEMS = 64 << 20  # float32 elements of the calibration copy (256 MiB each 
 
 
 KERNEL_SOURCES_2D = ("fft_team.hpp", "geom2d.hpp", "green.hpp", "common2d.hpp", "row2d.hpp",
-                     "col2d.hpp", "k2d_impl.hpp", "k2d_f32.hip")
+                     "col2d.hpp", "k2d_impl.hpp", "k2d_row16_f32.hip", "k2d_row8_f32.hip",
+                     "k2d_col_f32.hip")
 
 
 def source_hash() -> str:
@@ -168,6 +169,7 @@ def run_main(pk, torch, dev, p, precision, steps, warmup):
     plan = pk.Plan(p.dims, p.h, p.hbar, p.T, len(p.src), precision)
     plan.check_sources(p.src)
     ws = plan.workspace(dev)
+    plan.autotune(ws)  # schedule choice (radix / work-group shape), untimed
     S = torch.empty_like(f)
     for _ in range(warmup):
         plan.solve(f, src, S, ws)
@@ -203,6 +205,7 @@ def run_main(pk, torch, dev, p, precision, steps, warmup):
         kern[k] = {"launches_per_step": c // steps, "avg_us": 1e3 * avg_ms,
                    "alg_bytes": ab[k], "GBps": ab[k] / (avg_ms * 1e-3) / 1e9}
     total_bytes = sum(ab[k] * kern[k]["launches_per_step"] for k in kern)
+    kern["schedule"] = plan.schedule
     return ms, kern, total_bytes
 
 
@@ -214,6 +217,7 @@ def run_3d(pk, torch, dev, steps, warmup):
     out = {"workload": "blobs3d_256x256x256_T16_src1", "unit": "grid pts/s"}
     for prec in ("fp32", "fp64"):
         ms, kern, tb = run_main(pk, torch, dev, p, prec, steps, warmup)
+        kern.pop("schedule")
         dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches_per_step"])
         out[prec] = {"value": N / (ms * 1e-3), "ms_per_step": ms,
                      "solve_alg_GBps": tb / (ms * 1e-3) / 1e9, "solve_alg_bytes": tb,
@@ -238,6 +242,7 @@ def run_fwd_bwd(pk, torch, dev, steps, warmup):
     plan = pk.Plan(p.dims, p.h, p.hbar, p.T, len(p.src), "fp32")
     plan.check_sources(p.src)
     ws, ck = plan.workspace(dev), plan.checkpoint(dev)
+    plan.autotune(ws)
     S = torch.empty_like(f)
     # target: the same solve for the perturbed forcing
     tgt = torch.empty_like(f)
@@ -281,7 +286,7 @@ def run_fwd_bwd(pk, torch, dev, steps, warmup):
             "ms_forward_with_checkpoints": ms_fwd, "ms_adjoint": ms - ms_fwd,
             "alg_bytes": fwd_bytes + bwd_bytes,
             "alg_GBps": (fwd_bytes + bwd_bytes) / (ms * 1e-3) / 1e9,
-            "precision": "fp32-scaled", "gradient_finite": ok}
+            "precision": "fp32-scaled", "gradient_finite": ok, "schedule": plan.schedule}
 
 
 def run_batched(pk, torch, dev, steps, warmup):
@@ -289,6 +294,13 @@ def run_batched(pk, torch, dev, steps, warmup):
     import workloads
     probs = workloads.batch_problems()
     T = probs[0].T
+    # tune one plan per edge length: the batch's plans start from the table
+    sched = {}
+    for n in sorted({q.dims[0] for q in probs}):
+        tp = pk.Plan((n, n), 1.0 / n, 0.1, T, 1, "fp32")
+        tp.autotune(tp.workspace(dev))
+        sched[n] = tp.schedule
+    torch.cuda.empty_cache()
     b = pk.Batch([{"dims": q.dims, "h": q.h, "hbar": q.hbar, "T": q.T, "n_src": len(q.src)}
                   for q in probs], "fp32")
     fs = [torch.as_tensor(q.f).to(dev) for q in probs]
@@ -328,7 +340,7 @@ def run_batched(pk, torch, dev, steps, warmup):
             "sum_grid_pts": sumN, "value": sumN / (ms * 1e-3), "unit": "grid pts/s",
             "ms_per_step": ms, "ms_per_step_eager": ms_eager, "alg_bytes": total,
             "alg_GBps": total / (ms * 1e-3) / 1e9, "precision": "fp32-scaled",
-            "execution": "one HIP graph replay per step"}
+            "execution": "one HIP graph replay per step", "schedules": sched}
 
 
 def cpu_baseline(p, budget_s=10.0):
@@ -391,12 +403,22 @@ def traffic_summary(fetch_path, write_path, command):
     for counter, path in (("FETCH_SIZE", fetch_path), ("WRITE_SIZE", write_path)):
         disp = _per_dispatch(_counter_rows(path), counter)
         ids = sorted(disp)
+        # the solves' term-row kernel: the schedule with the most dispatches
+        # (the tuner also launches the other candidate a few times)
+        names = {}
+        for d in ids:
+            name = disp[d][0]
+            if "k_row2<float, 2, 1024," in name:
+                names[name] = names.get(name, 0) + 1
+        if not names:
+            raise SystemExit(f"{counter}: no term-row dispatches in {path}")
+        row_name = max(names, key=names.get)
         term, copy = [], []
         for j, d in enumerate(ids):
             name, v = disp[d]
             if "neg" in name.lower():
                 copy.append(v)
-            elif "k_row2" in name and "float" in name and ", 2, 1024>" in name:
+            elif name == row_name:
                 # the last term-row dispatch of a solve is the log pass:
                 # it is followed by the next solve's prep (or nothing)
                 nxt = disp[ids[j + 1]][0] if j + 1 < len(ids) else ""
@@ -404,14 +426,15 @@ def traffic_summary(fetch_path, write_path, command):
                     term.append(v)
         if not term or not copy:
             raise SystemExit(f"{counter}: no term-row or copy dispatches in {path}")
-        res[counter] = {"term_row_kib": float(np.mean(term)), "term_row_dispatches": len(term),
+        res[counter] = {"kernel_name": row_name,
+                        "term_row_kib": float(np.mean(term)), "term_row_dispatches": len(term),
                         "copy_kib": float(np.mean(copy)), "copy_dispatches": len(copy)}
     copy_bytes = 4.0 * COPY_ELEMS
     f_fac = res["FETCH_SIZE"]["copy_kib"] * 1024.0 / copy_bytes
     w_fac = res["WRITE_SIZE"]["copy_kib"] * 1024.0 / copy_bytes
     fetch_b = res["FETCH_SIZE"]["term_row_kib"] * 1024.0 / f_fac
     write_b = res["WRITE_SIZE"]["term_row_kib"] * 1024.0 / w_fac
-    d = {"kernel": "term_row (k_row2<float, ROW_TERM, 1024>)",
+    d = {"kernel": "term_row (k_row2<float, ROW_TERM, 1024, E>)",
          "workload": "noise2d_1024x1024_T16_src16 fp32-scaled",
          "counters": res,
          "copy_bytes_each_way": copy_bytes,
@@ -505,6 +528,7 @@ def main():
 
     ms, kern, total_bytes = run_main(pk, torch, dev, p, args.precision, args.steps, args.warmup)
     value = N / (ms * 1e-3)
+    sched = kern.pop("schedule")
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches_per_step"])
     d = kern[dom]
     traffic = read_traffic(source_hash()) if (dom == "term_row" and args.precision == "fp32"
@@ -526,7 +550,7 @@ def main():
                    "grid": [n0, n1], "h": p.h, "hbar": p.hbar, "T": p.T,
                    "n_src": int(len(p.src)),
                    "precision": "fp32-scaled" if args.precision == "fp32" else "fp64",
-                   "mode": "fwd"},
+                   "mode": "fwd", "schedule": sched},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["GBps"],
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": d["GBps"] / HBM_PEAK_GBPS, "traffic": traffic,

@@ -201,11 +201,33 @@ sweik_status sweik_batch_solve_graph(sweik_batch batch, const void *const *f,
                                      size_t ws_bytes, void *stream,
                                      sweik_info *infos);
 
-/* ---- schedule tuning ---------------------------------------------------- */
-/* Times the candidate tile schedules of every pass of `plan` on `stream`
- * using `ws` (synchronises the stream) and keeps the fastest in the plan and
- * in a process-wide table keyed by (pass, length, precision), which later
- * plans use.  Returns the number of schedules timed. */
+/* ---- schedules and tuning ------------------------------------------------
+ * A schedule fixes, per pass family, the FFT radix and the work-group shape:
+ * E elements per team thread, i.e. radix-E Stockham stages and 4096/E
+ * threads per work-group (the rows or columns per work-group do not change).
+ *   row_e  2D row passes (all modes): 16 or 8
+ *   col_e  2D column passes (all modes): 16 or 8
+ * 3D plans have the single schedule {16, 16}.  New plans take the entries of
+ * the process-wide table filled by sweik_autotune (default 16). */
+typedef struct {
+  int32_t row_e, col_e;
+  int32_t reserved[6];
+} sweik_schedule;
+
+sweik_status sweik_plan_get_schedule(sweik_plan plan, sweik_schedule *out);
+/* SWEIK_EINVAL for a value other than 16 or 8; SWEIK_EUNSUPPORTED for a 3D
+ * plan with a value other than 16.  Host only.  Not to be called while a
+ * solve with this plan is being enqueued on another thread. */
+sweik_status sweik_plan_set_schedule(sweik_plan plan, const sweik_schedule *s);
+
+/* Times every candidate schedule of the 2D per-term passes (the column
+ * convolution and, when T >= 2, the row pass) with HIP events on `stream`,
+ * five launches each, on the workspace `ws` (its contents are overwritten:
+ * run it before a solve, not between a solve and its adjoint).  Keeps the
+ * fastest in the plan and in the process-wide table keyed by (pass, length,
+ * precision) that later plans start from.  Synchronises the stream.  Returns
+ * the number of schedules timed (0 for 3D plans, negative on a HIP error or
+ * a too-small workspace). */
 int32_t sweik_autotune(sweik_plan plan, void *ws, size_t ws_bytes,
                        void *stream);
 

@@ -34,6 +34,10 @@ class _Problem(C.Structure):
                 ("prec", C.c_int32), ("ft_mode", C.c_int32), ("ftilde", C.c_double)]
 
 
+class _Schedule(C.Structure):
+    _fields_ = [("row_e", C.c_int32), ("col_e", C.c_int32), ("reserved", C.c_int32 * 6)]
+
+
 class _Info(C.Structure):
     _fields_ = [("f_min", C.c_double), ("f_max", C.c_double), ("ftilde", C.c_double),
                 ("beta", C.c_double), ("c0_bound", C.c_double),
@@ -80,6 +84,8 @@ def load_library():
     lib.sweik_batch_solve.argtypes = [vp, PP, PP, PP, vp, sz, vp, vp]
     lib.sweik_batch_solve_graph.argtypes = [vp, PP, PP, PP, vp, sz, vp, vp]
     lib.sweik_autotune.argtypes = [vp, vp, sz, vp]
+    lib.sweik_plan_get_schedule.argtypes = [vp, C.POINTER(_Schedule)]
+    lib.sweik_plan_set_schedule.argtypes = [vp, C.POINTER(_Schedule)]
     lib.sweik_status_string.argtypes = [C.c_int]
     lib.sweik_status_string.restype = C.c_char_p
     lib.sweik_abi_version.restype = C.c_int32
@@ -210,8 +216,24 @@ class Plan:
             "sweik_solve_adjoint")
 
     def autotune(self, ws: torch.Tensor, stream=None) -> int:
-        return int(self._lib.sweik_autotune(self._h, ws.data_ptr(), ws.numel(),
-                                            _stream_ptr(stream)))
+        """Time the candidate schedules on `ws` (overwritten) and keep the
+        fastest; returns the number of schedules timed."""
+        n = int(self._lib.sweik_autotune(self._h, ws.data_ptr(), ws.numel(),
+                                         _stream_ptr(stream)))
+        if n < 0:
+            raise SweikError("sweik_autotune failed")
+        return n
+
+    @property
+    def schedule(self) -> dict:
+        sc = _Schedule()
+        _check(self._lib.sweik_plan_get_schedule(self._h, C.byref(sc)), "schedule")
+        return {"row_e": int(sc.row_e), "col_e": int(sc.col_e)}
+
+    def set_schedule(self, row_e: int = 16, col_e: int = 16):
+        sc = _Schedule()
+        sc.row_e, sc.col_e = int(row_e), int(col_e)
+        _check(self._lib.sweik_plan_set_schedule(self._h, C.byref(sc)), "set_schedule")
 
 
 _plan_cache: Dict[Tuple, Plan] = {}

@@ -8,8 +8,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsweik.so")
-SOURCES = [os.path.join(HERE, "csrc", n) for n in ("api.hip", "k2d_f32.hip", "k2d_f64.hip",
-                                                        "k3d_f32.hip", "k3d_f64.hip")]
+SOURCES = [os.path.join(HERE, "csrc", n) for n in (
+    "api.hip", "k2d_row16_f32.hip", "k2d_row8_f32.hip", "k2d_col_f32.hip",
+    "k2d_row16_f64.hip", "k2d_row8_f64.hip", "k2d_col_f64.hip", "k3d_f32.hip", "k3d_f64.hip")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

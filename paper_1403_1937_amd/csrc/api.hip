@@ -7,6 +7,8 @@
 #include <cstdint>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <set>
 #include <tuple>
@@ -103,6 +105,22 @@ sweik_status validate_problem(const sweik_problem *p) {
   return SWEIK_OK;
 }
 
+// Process-wide schedule table filled by the autotuner: (pass family,
+// length, precision) -> elements per team thread.
+enum { SCHED_ROW2 = 0, SCHED_COL2 = 1 };
+std::mutex g_sched_mu;
+std::map<std::tuple<int, int, int>, int> g_sched;
+
+int sched_lookup(int fam, int len, int prec, int dflt) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  auto it = g_sched.find(std::make_tuple(fam, len, prec));
+  return it == g_sched.end() ? dflt : it->second;
+}
+void sched_store(int fam, int len, int prec, int e) {
+  std::lock_guard<std::mutex> lk(g_sched_mu);
+  g_sched[std::make_tuple(fam, len, prec)] = e;
+}
+
 // Schedule and workspace layout of a 2D problem.
 sweik_status plan2d(sweik_plan_s *pl) {
   const sweik_problem &p = pl->p;
@@ -137,6 +155,8 @@ sweik_status plan2d(sweik_plan_s *pl) {
   g.ncw = (g.ldk + g.cpw - 1) / g.cpw;
   g.lmax = (int)std::max(M0, M1);
   g.lmax_log = ilog2(g.lmax);
+  g.erow = sched_lookup(SCHED_ROW2, g.H1, p.prec, 16);
+  g.ecol = sched_lookup(SCHED_COL2, g.M0, p.prec, 16);
   pl->padded[0] = M0;
   pl->padded[1] = M1;
   pl->padded[2] = 1;
@@ -263,13 +283,13 @@ sweik_status enqueue2d(const sweik_plan_s *pl, const void *f, const int32_t *src
   };
   const dim3 grow(g.nbr), gcol(g.ncw);
   launch(SWEIK_KC_PREP, [&] { return launch_prep<R>((const R *)f, N, a.red, (cplx<R> *)a.tw, g.lmax, st); });
-  launch(SWEIK_KC_GHAT_ROW, [&] { return launch_row2<R>(ROW_GHAT, g.H1, grow, st, a, 0); });
-  launch(SWEIK_KC_GHAT_COL, [&] { return launch_col2<R>(COL_GHAT, g.M0, gcol, st, a); });
-  launch(SWEIK_KC_PHI0_ROW, [&] { return launch_row2<R>(ROW_PHI0, g.H1, grow, st, a, 0); });
+  launch(SWEIK_KC_GHAT_ROW, [&] { return launch_row2<R>(ROW_GHAT, g.H1, g.erow, grow, st, a, 0); });
+  launch(SWEIK_KC_GHAT_COL, [&] { return launch_col2<R>(COL_GHAT, g.M0, g.ecol, gcol, st, a); });
+  launch(SWEIK_KC_PHI0_ROW, [&] { return launch_row2<R>(ROW_PHI0, g.H1, g.erow, grow, st, a, 0); });
   for (int i = 1; i <= pl->p.T; ++i) {
-    launch(SWEIK_KC_CONV_COL, [&] { return launch_col2<R>(COL_CONV, g.M0, gcol, st, a); });
+    launch(SWEIK_KC_CONV_COL, [&] { return launch_col2<R>(COL_CONV, g.M0, g.ecol, gcol, st, a); });
     launch(i == pl->p.T ? SWEIK_KC_LAST_ROW : SWEIK_KC_TERM_ROW,
-           [&] { return launch_row2<R>(ROW_TERM, g.H1, grow, st, a, i); });
+           [&] { return launch_row2<R>(ROW_TERM, g.H1, g.erow, grow, st, a, i); });
   }
   return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
@@ -288,10 +308,10 @@ sweik_status enqueue2d_adjoint(const sweik_plan_s *pl, const void *f, const int3
   const dim3 grow(g.nbr), gcol(g.ncw);
   hipError_t err = launch_adj_prep<R>((const R *)dLdS, (const double *)a.ck_phi, N,
                                       pl->p.hbar, a.red, (cplx<R> *)a.tw, g.lmax, st);
-  if (err == hipSuccess) err = launch_row2<R>(ROW_ADJ0, g.H1, grow, st, a, pl->p.T);
+  if (err == hipSuccess) err = launch_row2<R>(ROW_ADJ0, g.H1, g.erow, grow, st, a, pl->p.T);
   for (int i = pl->p.T; i >= 1 && err == hipSuccess; --i) {
-    err = launch_col2<R>(COL_CONV, g.M0, gcol, st, a);
-    if (err == hipSuccess) err = launch_row2<R>(ROW_ADJ, g.H1, grow, st, a, i);
+    err = launch_col2<R>(COL_CONV, g.M0, g.ecol, gcol, st, a);
+    if (err == hipSuccess) err = launch_row2<R>(ROW_ADJ, g.H1, g.erow, grow, st, a, i);
   }
   return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
@@ -326,6 +346,7 @@ sweik_status plan3d(sweik_plan_s *pl) {
   g.nbx = (g.nlines + x_lpw(g.H2) - 1) / x_lpw(g.H2);
   g.ncb0 = g.H2 / c3_cpw(g.M0);
   g.ncb1 = g.H2 / c3_cpw(g.M1);
+  pl->g2.erow = pl->g2.ecol = 16;  // the 3D passes have one schedule
   g.lmax = std::max(2 * g.M2, std::max(g.M0, g.M1));
   g.lmax_log = ilog2(g.lmax);
   for (int d = 0; d < 3; ++d) pl->padded[d] = M[d];
@@ -446,7 +467,7 @@ sweik_status enqueue3d(const sweik_plan_s *pl, const void *f, const int32_t *src
 // every solve.  Class chains run on forked streams joined back into the
 // caller's stream.
 struct BatchClass {
-  int H1, M0;
+  int H1, M0, erow, ecol;
   std::vector<int> members;
   size_t row_items, col_items;  // workspace offsets of the two item lists
   int row_blocks, col_blocks;
@@ -567,12 +588,12 @@ hipError_t batch_class_chain(const sweik_batch_s *b, const BatchClass &c, char *
   const BatchItem<R> *ci = (const BatchItem<R> *)(ws + c.col_items);
   const int n = (int)c.members.size();
   hipError_t err = launch_prep_batch<R>(n, st, ri);
-  if (err == hipSuccess) err = launch_row2_batch<R>(ROW_GHAT, c.H1, c.row_blocks, st, ri, n, 0);
-  if (err == hipSuccess) err = launch_col2_batch<R>(COL_GHAT, c.M0, c.col_blocks, st, ci, n);
-  if (err == hipSuccess) err = launch_row2_batch<R>(ROW_PHI0, c.H1, c.row_blocks, st, ri, n, 0);
+  if (err == hipSuccess) err = launch_row2_batch<R>(ROW_GHAT, c.H1, c.erow, c.row_blocks, st, ri, n, 0);
+  if (err == hipSuccess) err = launch_col2_batch<R>(COL_GHAT, c.M0, c.ecol, c.col_blocks, st, ci, n);
+  if (err == hipSuccess) err = launch_row2_batch<R>(ROW_PHI0, c.H1, c.erow, c.row_blocks, st, ri, n, 0);
   for (int i = 1; i <= b->T && err == hipSuccess; ++i) {
-    err = launch_col2_batch<R>(COL_CONV, c.M0, c.col_blocks, st, ci, n);
-    if (err == hipSuccess) err = launch_row2_batch<R>(ROW_TERM, c.H1, c.row_blocks, st, ri, n, i);
+    err = launch_col2_batch<R>(COL_CONV, c.M0, c.ecol, c.col_blocks, st, ci, n);
+    if (err == hipSuccess) err = launch_row2_batch<R>(ROW_TERM, c.H1, c.erow, c.row_blocks, st, ri, n, i);
   }
   return err;
 }
@@ -611,6 +632,67 @@ sweik_status batch_args_ok(const sweik_batch_s *b, const void *const *f,
 }
 
 }  // namespace sweik
+
+namespace {
+
+// Average milliseconds of `reps` launches of fn on st (events around all).
+template <typename F> float time_launches(hipStream_t st, int reps, F &&fn, bool *ok) {
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return *ok = false, 0.0f;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return *ok = false, 0.0f;
+  }
+  bool good = fn() == hipSuccess;  // warm-up (also sets the LDS attribute)
+  good = good && hipEventRecord(e0, st) == hipSuccess;
+  for (int r = 0; r < reps && good; ++r) good = fn() == hipSuccess;
+  good = good && hipEventRecord(e1, st) == hipSuccess;
+  good = good && hipEventSynchronize(e1) == hipSuccess;
+  float ms = 0.0f;
+  good = good && hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (!good) *ok = false;
+  return ms / reps;
+}
+
+template <typename R> int32_t autotune2d(sweik_plan_s *pl, void *ws, hipStream_t st) {
+  Geo2 &g = pl->g2;
+  Args2<R> a = make_args2<R>(pl, nullptr, nullptr, nullptr, ws, nullptr, nullptr);
+  const dim3 grow(g.nbr), gcol(g.ncw);
+  const int cand[2] = {16, 8};
+  int timed = 0;
+  bool ok = true;
+  // column convolution: reads the spectrum and the kernel spectrum, writes
+  // the spectrum in place; the data are whatever the workspace holds
+  float best = 0.0f;
+  int be = g.ecol;
+  for (int e : cand) {
+    const float ms = time_launches(st, 5, [&] { return launch_col2<R>(COL_CONV, g.M0, e, gcol, st, a); }, &ok);
+    if (!ok) return -1;
+    ++timed;
+    if (timed == 1 || ms < best) best = ms, be = e;
+  }
+  g.ecol = be;
+  sched_store(SCHED_COL2, g.M0, pl->p.prec, be);
+  // row pass of term 1 (not the last term, so it writes no output)
+  if (pl->p.T >= 2) {
+    int first = timed;
+    be = g.erow;
+    for (int e : cand) {
+      if (g.H1 < e) continue;
+      const float ms = time_launches(st, 5, [&] { return launch_row2<R>(ROW_TERM, g.H1, e, grow, st, a, 1); }, &ok);
+      if (!ok) return -1;
+      if (timed == first || ms < best) best = ms, be = e;
+      ++timed;
+    }
+    g.erow = be;
+    sched_store(SCHED_ROW2, g.H1, pl->p.prec, be);
+  }
+  return timed;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -749,10 +831,11 @@ sweik_status sweik_batch_create(const sweik_problem *problems, int32_t count, sw
   // size classes, largest total work first (it runs on the caller's stream)
   for (int i = 0; i < count; ++i) {
     const Geo2 &g = b->plans[i].g2;
-    auto it = std::find_if(b->classes.begin(), b->classes.end(),
-                           [&](const BatchClass &c) { return c.H1 == g.H1 && c.M0 == g.M0; });
+    auto it = std::find_if(b->classes.begin(), b->classes.end(), [&](const BatchClass &c) {
+      return c.H1 == g.H1 && c.M0 == g.M0 && c.erow == g.erow && c.ecol == g.ecol;
+    });
     if (it == b->classes.end()) {
-      b->classes.push_back(BatchClass{g.H1, g.M0, {}, 0, 0, 0, 0, 0.0});
+      b->classes.push_back(BatchClass{g.H1, g.M0, g.erow, g.ecol, {}, 0, 0, 0, 0, 0.0});
       it = b->classes.end() - 1;
     }
     it->members.push_back(i);
@@ -853,9 +936,34 @@ sweik_status sweik_batch_solve_graph(sweik_batch b, const void *const *f,
   return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
 
+sweik_status sweik_plan_get_schedule(sweik_plan plan, sweik_schedule *out) {
+  if (!plan || !out) return SWEIK_EINVAL;
+  std::memset(out, 0, sizeof(*out));
+  out->row_e = plan->g2.erow;
+  out->col_e = plan->g2.ecol;
+  return SWEIK_OK;
+}
+
+sweik_status sweik_plan_set_schedule(sweik_plan plan, const sweik_schedule *sc) {
+  if (!plan || !sc) return SWEIK_EINVAL;
+  auto ok = [](int e) { return e == 16 || e == 8; };
+  if (!ok(sc->row_e) || !ok(sc->col_e)) return SWEIK_EINVAL;
+  if (plan->p.ndim == 3 && (sc->row_e != 16 || sc->col_e != 16)) return SWEIK_EUNSUPPORTED;
+  if (plan->p.ndim == 2) {
+    const int H = plan->g2.H1;
+    if (H < sc->row_e) return SWEIK_EUNSUPPORTED;
+  }
+  plan->g2.erow = sc->row_e;
+  plan->g2.ecol = sc->col_e;
+  return SWEIK_OK;
+}
+
 int32_t sweik_autotune(sweik_plan plan, void *ws, size_t ws_bytes, void *stream) {
-  (void)plan; (void)ws; (void)ws_bytes; (void)stream;
-  return 0;
+  if (!plan || !ws || ws_bytes < plan->ws.total) return -1;
+  if (plan->p.ndim != 2) return 0;
+  hipStream_t st = (hipStream_t)stream;
+  return plan->p.prec == SWEIK_F64 ? autotune2d<double>(plan, ws, st)
+                                   : autotune2d<float>(plan, ws, st);
 }
 
 const char *sweik_status_string(sweik_status s) {

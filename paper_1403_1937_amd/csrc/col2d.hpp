@@ -1,6 +1,7 @@
 // col2d.hpp -- column passes of the 2D solve.
 //
-// One team of P = M0/16 threads per spectral column k1, CPW columns per
+// One team of P = M0/E threads per spectral column k1 (E = 16 or 8 elements
+// per thread; 4096/E threads per work-group), CPW = 4096/M0 columns per
 // work-group.  Lanes interleave the teams in groups of RB so that one wave
 // reads RB contiguous rows of CPW neighbouring columns from each block of
 // the blocked spectrum; work-groups are mapped so that neighbouring columns
@@ -22,12 +23,13 @@ namespace sweik {
 
 // FULL: every column of the work-group exists and every loaded row lies in
 // the spectrum, so no element needs a bounds check.
-template <typename R, int MODE, int M0, bool FULL>
+template <typename R, int MODE, int M0, int E, bool FULL>
 __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned char *smem_raw) {
   using C = cplx<R>;
-  constexpr int P = M0 / 16, CPW = col_cpw(M0), RB = spec_rb<R>(), LL = lds_line_len(M0);
+  constexpr int P = M0 / E, CPW = col_cpw(M0), RB = spec_rb<R>(), LL = lds_line_len(M0);
+  constexpr int NT = team_threads(E);
   constexpr int H0 = M0 / 2, TWLOG = ilog2c(M0);
-  constexpr int NTW = (M0 + kThreads - 1) / kThreads;
+  constexpr int NTW = (M0 + NT - 1) / NT;
   static_assert(P % RB == 0, "column team must cover whole row blocks");
   C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / M0), k < M0
   C *lines = twl + M0;
@@ -48,17 +50,17 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
   C twr[NTW];
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
-    const int k = tid + u * kThreads;
+    const int k = tid + u * NT;
     if (k < M0) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
   }
-  C v[16];
-  R gv[16], gb[16];
+  C v[E];
+  R gv[E], gb[E];
   if constexpr (MODE == COL_CONV) {
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < E; ++j) {
       const int rho = t + P * j;
       C x = cmake<C>((R)0, (R)0);
-      if (j < 8 && (FULL || (active && rho < spec_rows))) {
+      if (j < E / 2 && (FULL || (active && rho < spec_rows))) {
         const int b = rho / RB;
         x = col[b * cstride + (rho - b * RB)];
       }
@@ -66,14 +68,14 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
     }
     const R *gcol = a.g + (size_t)(active ? k1 : 0) * a.ldg;
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < E; ++j) {
       const int k0 = t + P * j;
       gv[j] = gcol[k0 <= H0 ? k0 : M0 - k0];
     }
     if (packed_wg && k1 == 0) {
       const R *gnyq = a.g + (size_t)a.ldk * a.ldg;  // kernel column of bin H1
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
+      for (int j = 0; j < E; ++j) {
         const int k0 = t + P * j;
         gb[j] = gnyq[k0 <= H0 ? k0 : M0 - k0];
       }
@@ -81,7 +83,7 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
   } else {
     // even extension of the column: x[rho] = x[M0 - rho]
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
+    for (int j = 0; j < E; ++j) {
       const int rho = t + P * j;
       const int sr = rho <= H0 ? rho : M0 - rho;
       C x = cmake<C>((R)0, (R)0);
@@ -94,7 +96,7 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
   }
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
-    const int k = tid + u * kThreads;
+    const int k = tid + u * NT;
     if (k < M0) twl[k] = twr[u];
   }
   __syncthreads();
@@ -102,31 +104,31 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
   team_fft<M0, TWLOG, false>(v, t, line, twl, false);
   if constexpr (MODE == COL_CONV) {
     if (packed_wg) {
-      C pv[16];
+      C pv[E];
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < 16; ++j) line[lpad(t + P * j)] = v[j];
+      for (int j = 0; j < E; ++j) line[lpad(t + P * j)] = v[j];
       __syncthreads();
 #pragma unroll
-      for (int j = 0; j < 16; ++j) pv[j] = line[lpad((M0 - (t + P * j)) & (M0 - 1))];
+      for (int j = 0; j < E; ++j) pv[j] = line[lpad((M0 - (t + P * j)) & (M0 - 1))];
       if (k1 == 0) {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) {
+        for (int j = 0; j < E; ++j) {
           const R al = (gv[j] + gb[j]) * (R)0.5, de = (gv[j] - gb[j]) * (R)0.5;
           v[j] = cadd(cscale(v[j], al), cscale(cconj(pv[j]), de));
         }
       } else {
 #pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = cscale(v[j], gv[j]);
+        for (int j = 0; j < E; ++j) v[j] = cscale(v[j], gv[j]);
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < 16; ++j) v[j] = cscale(v[j], gv[j]);
+      for (int j = 0; j < E; ++j) v[j] = cscale(v[j], gv[j]);
     }
     team_fft<M0, TWLOG, true>(v, t, line, twl, true);
     if (active) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < E / 2; ++j) {
         const int rho = t + P * j;
         if (FULL || rho < spec_rows) {
           const int b = rho / RB;
@@ -142,7 +144,7 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
       R *gcol = a.g + (size_t)k1 * a.ldg;
       R *gnyq = a.g + (size_t)a.ldk * a.ldg;
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
+      for (int j = 0; j < E; ++j) {
         const int k0 = t + P * j;
         if (k0 <= H0) {
           gcol[k0] = (R)((double)v[j].x * sc);
@@ -153,29 +155,29 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
   }
 }
 
-template <typename R, int MODE, int M0>
+template <typename R, int MODE, int M0, int E>
 __device__ __forceinline__ void col_block(const Args2<R> &a, int tile, unsigned char *smem_raw) {
   if ((tile + 1) * col_cpw(M0) <= a.ldk && a.nb * spec_rb<R>() >= M0 / 2)
-    col_pass<R, MODE, M0, true>(a, tile, smem_raw);
+    col_pass<R, MODE, M0, E, true>(a, tile, smem_raw);
   else
-    col_pass<R, MODE, M0, false>(a, tile, smem_raw);
+    col_pass<R, MODE, M0, E, false>(a, tile, smem_raw);
 }
 
-template <typename R, int MODE, int M0>
-__global__ void __launch_bounds__(kThreads) k_col2(Args2<R> a) {
+template <typename R, int MODE, int M0, int E>
+__global__ void __launch_bounds__(team_threads(E)) k_col2(Args2<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  col_block<R, MODE, M0>(a, xcd_tile(blockIdx.x, gridDim.x), smem_raw);
+  col_block<R, MODE, M0, E>(a, xcd_tile(blockIdx.x, gridDim.x), smem_raw);
 }
 
 // Uneven batch: one launch over the column work-groups of every instance of
 // a size class (neighbouring tiles of an instance share an XCD).
-template <typename R, int MODE, int M0>
-__global__ void __launch_bounds__(kThreads) k_col2_batch(const BatchItem<R> *__restrict__ items,
+template <typename R, int MODE, int M0, int E>
+__global__ void __launch_bounds__(team_threads(E)) k_col2_batch(const BatchItem<R> *__restrict__ items,
                                                          int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int g = xcd_tile(blockIdx.x, gridDim.x);
   const int i = find_item(items, nitems, g);
-  col_block<R, MODE, M0>(items[i].a, g - items[i].begin, smem_raw);
+  col_block<R, MODE, M0, E>(items[i].a, g - items[i].begin, smem_raw);
 }
 
 }  // namespace sweik

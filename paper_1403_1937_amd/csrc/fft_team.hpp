@@ -1,12 +1,14 @@
 // fft_team.hpp -- register/LDS Stockham FFT for gfx950 (wave64).
 //
-// A "team" of P = L/16 threads transforms one complex line of length L
-// (compile-time power of two, 16 <= L <= 4096).  Thread t of the team always
-// holds the 16 elements with indices t + P*j, j = 0..15, in registers: on
-// entry the input samples, on exit the transform values at the same indices.
-// Stages are Stockham autosort steps of radix 16 with spans p = 1, 16, 256
-// (the last one of radix L/p); data moves through LDS only between stages,
-// so a line costs ceil(log16 L) - 1 LDS round trips.  Because the first stage
+// A "team" of P = L/E threads transforms one complex line of length L
+// (compile-time power of two, E <= L <= 4096; E = 16 or 8 elements per
+// thread).  Thread t of the team always holds the E elements with indices
+// t + P*j, j < E, in registers: on entry the input samples, on exit the
+// transform values at the same indices.  Stages are Stockham autosort steps
+// of radix E with spans p = 1, E, E^2, ... (the last one of radix L/p); data
+// moves through LDS only between stages, so a line costs ceil(log_E L) - 1
+// LDS round trips.  E = 8 uses twice the threads per line (more waves per
+// SIMD to hide latency) for one more LDS round trip.  Because the first stage
 // reads and the last stage writes the same index pattern, a forward
 // transform, a pointwise spectral product and an inverse transform chain
 // without any extra exchange.
@@ -138,15 +140,16 @@ __host__ __device__ constexpr int lpad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lds_line_len(int L) { return L + (L >> 4) + 1; }
 __host__ __device__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
 
-// One Stockham stage of radix R and span p on a team line (compile-time
-// L).  Twiddles exp(-2 pi i q k / (p R)) come from the LDS table (base length
-// 2^TWLOG); LAST: results stay in registers (index t + P j), else they go to
-// LDS at the autosort position.
-template <int L, int R, int p, int TWLOG, bool INV, bool LAST, typename C>
-__device__ __forceinline__ void stage(C (&v)[16], int t, C *lds, const C *twl) {
-  constexpr int P = L / 16;
-  constexpr int NB = 16 / R;  // butterflies per thread
+// One Stockham stage of radix R and span p on a team line (compile-time L,
+// E elements per thread).  Twiddles exp(-2 pi i q k / (p R)) come from the
+// LDS table (base length 2^TWLOG); LAST: results stay in registers (index
+// t + P j), else they go to LDS at the autosort position.
+template <int L, int R, int p, int TWLOG, bool INV, bool LAST, int E, typename C>
+__device__ __forceinline__ void stage(C (&v)[E], int t, C *lds, const C *twl) {
+  constexpr int P = L / E;
+  constexpr int NB = E / R;  // butterflies per thread
   constexpr int SH = TWLOG - ilog2c(p * R);
+  static_assert(R >= 2 && R <= E && E % R == 0, "stage radix");
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int i = t + P * b;
@@ -176,37 +179,39 @@ __device__ __forceinline__ void stage(C (&v)[16], int t, C *lds, const C *twl) {
   }
 }
 
-template <int L, typename C>
-__device__ __forceinline__ void lds_gather(C (&v)[16], int t, const C *lds) {
-  constexpr int P = L / 16;
+template <int L, int E, typename C>
+__device__ __forceinline__ void lds_gather(C (&v)[E], int t, const C *lds) {
+  constexpr int P = L / E;
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = lds[lpad(t + P * j)];
+  for (int j = 0; j < E; ++j) v[j] = lds[lpad(t + P * j)];
   __syncthreads();
 }
 
-// Complex FFT of length L held by a team; twl: LDS twiddle table with all
-// 2^TWLOG >= L entries.  Barriers are block-wide: every thread of the block
-// calls this.  With lead_sync a barrier first protects LDS data still being
-// read from earlier work.
-template <int L, int TWLOG, bool INV, typename C>
-__device__ __forceinline__ void team_fft(C (&v)[16], int t, C *lds, const C *twl,
-                                         bool lead_sync = true) {
-  static_assert(L >= 16 && L <= 4096 && (L & (L - 1)) == 0, "line length");
-  if (lead_sync) __syncthreads();
-  if constexpr (L == 16) {
-    stage<L, 16, 1, TWLOG, INV, true>(v, t, lds, twl);
-  } else if constexpr (L <= 256) {
-    stage<L, 16, 1, TWLOG, INV, false>(v, t, lds, twl);
-    lds_gather<L>(v, t, lds);
-    stage<L, L / 16, 16, TWLOG, INV, true>(v, t, lds, twl);
+// Stages of span p, p E, p E^2, ... (radix E), the last of radix L / p.
+template <int L, int TWLOG, bool INV, int E, int p, typename C>
+__device__ __forceinline__ void team_stages(C (&v)[E], int t, C *lds, const C *twl) {
+  if constexpr (p * E >= L) {
+    stage<L, L / p, p, TWLOG, INV, true, E>(v, t, lds, twl);
   } else {
-    stage<L, 16, 1, TWLOG, INV, false>(v, t, lds, twl);
-    lds_gather<L>(v, t, lds);
-    stage<L, 16, 16, TWLOG, INV, false>(v, t, lds, twl);
-    lds_gather<L>(v, t, lds);
-    stage<L, L / 256, 256, TWLOG, INV, true>(v, t, lds, twl);
+    stage<L, E, p, TWLOG, INV, false, E>(v, t, lds, twl);
+    lds_gather<L, E>(v, t, lds);
+    team_stages<L, TWLOG, INV, E, p * E>(v, t, lds, twl);
   }
+}
+
+// Complex FFT of length L held by a team of L/E threads (E = 16: radix-16
+// stages; E = 8: radix-8 stages); twl: LDS twiddle table with all 2^TWLOG
+// >= L entries.  Barriers are block-wide: every thread of the block calls
+// this.  With lead_sync a barrier first protects LDS data still being read
+// from earlier work.
+template <int L, int TWLOG, bool INV, int E, typename C>
+__device__ __forceinline__ void team_fft(C (&v)[E], int t, C *lds, const C *twl,
+                                         bool lead_sync = true) {
+  static_assert(L >= E && L <= 4096 && (L & (L - 1)) == 0, "line length");
+  static_assert(E == 8 || E == 16, "elements per thread");
+  if (lead_sync) __syncthreads();
+  team_stages<L, TWLOG, INV, E, 1>(v, t, lds, twl);
 }
 
 // ---- block reductions ----------------------------------------------------

@@ -1,10 +1,11 @@
 // geom2d.hpp -- compile-time geometry of the 2D passes, shared by the host
 // planner and the kernels.
 //
-//   row pass     one team of P = H1/16 threads per grid row; 256 threads per
-//                work-group, i.e. rpw = 256 / P rows (at least 1)
-//   column pass  one team of P = M0/16 threads per spectral column; cpw =
-//                256 / P columns per work-group
+//   row pass     one team of P = H1/E threads per grid row (E = 16 or 8
+//                elements per thread); 4096/E threads per work-group, i.e.
+//                rpw = 4096 / H1 rows (at least 1) for either E
+//   column pass  one team of P = M0/E threads per spectral column; cpw =
+//                4096 / M0 columns per work-group
 //   spectrum     half spectrum of the rows, blocked transposed:
 //                spec[b][k1][rr], RB = 4 (float) or 2 (double) rows per block,
 //                so that one block entry is 32 bytes
@@ -21,6 +22,8 @@ enum ColMode { COL_GHAT = 0, COL_CONV = 1 };
 
 template <typename R> constexpr int spec_rb() { return sizeof(R) == 4 ? 4 : 2; }
 constexpr int kThreads = 256;
+// threads of a 2D pass work-group with E elements per team thread
+constexpr int team_threads(int E) { return kThreads * 16 / E; }
 constexpr int row_rpw(int H) { return H / 16 >= kThreads ? 1 : kThreads / (H / 16); }
 constexpr int col_cpw(int M0) { return M0 / 16 >= kThreads ? 1 : kThreads / (M0 / 16); }
 constexpr size_t kLdsDevice = 163840;  // gfx950 limit per work-group

@@ -1,0 +1,6 @@
+// k2d_col_f64.hip -- double instantiation of the 2D column passes and small kernels.
+#include "k2d_impl.hpp"
+
+namespace sweik {
+SWEIK_INSTANTIATE_2D_COLS(double)
+}

@@ -1,6 +1,11 @@
-// k2d_impl.hpp -- launchers of the 2D kernels: the run-time line lengths
-// select compile-time instantiations.  Included once per precision.
+// k2d_impl.hpp -- launchers of the 2D kernels: the run-time line lengths and
+// the schedule (E elements per team thread) select compile-time
+// instantiations.  Each instantiation unit includes this once and
+// instantiates one family (row passes of one E, or column passes and the
+// small kernels) for one precision.
 #pragma once
+
+#include <algorithm>
 
 #include "col2d.hpp"
 #include "launch2d.hpp"
@@ -14,157 +19,134 @@ template <typename K> static hipError_t set_lds(K kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
-template <typename R, int MODE, int H>
-static hipError_t row_one(dim3 grid, hipStream_t st, const Args2<R> &a, int term) {
-  constexpr size_t lds = row_lds_bytes<R>(H, MODE);
-  if constexpr (lds > kLdsDevice) {  // rejected by the planner
-    return hipErrorInvalidValue;
-  } else {
-    static const hipError_t attr = set_lds(k_row2<R, MODE, H>, lds);
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_row2<R, MODE, H>), grid, dim3(kThreads), lds, st, a, term);
-    return hipGetLastError();
-  }
-}
-
-template <typename R, int MODE>
-static hipError_t row_mode(int H, dim3 grid, hipStream_t st, const Args2<R> &a, int term) {
-  switch (H) {
-    case 32: return row_one<R, MODE, 32>(grid, st, a, term);
-    case 64: return row_one<R, MODE, 64>(grid, st, a, term);
-    case 128: return row_one<R, MODE, 128>(grid, st, a, term);
-    case 256: return row_one<R, MODE, 256>(grid, st, a, term);
-    case 512: return row_one<R, MODE, 512>(grid, st, a, term);
-    case 1024: return row_one<R, MODE, 1024>(grid, st, a, term);
-    case 2048: return row_one<R, MODE, 2048>(grid, st, a, term);
-    case 4096: return row_one<R, MODE, 4096>(grid, st, a, term);
-  }
+// H = M1/2 of a row pass and M0 of a column pass, as template dispatch
+#define SWEIK_ROW_LENGTHS(F, ...)                                                   \
+  switch (H) {                                                                      \
+    case 32: return F<32>(__VA_ARGS__);                                              \
+    case 64: return F<64>(__VA_ARGS__);                                              \
+    case 128: return F<128>(__VA_ARGS__);                                            \
+    case 256: return F<256>(__VA_ARGS__);                                            \
+    case 512: return F<512>(__VA_ARGS__);                                            \
+    case 1024: return F<1024>(__VA_ARGS__);                                          \
+    case 2048: return F<2048>(__VA_ARGS__);                                          \
+    case 4096: return F<4096>(__VA_ARGS__);                                          \
+  }                                                                                 \
   return hipErrorInvalidValue;
-}
+#define SWEIK_COL_LENGTHS(F, ...)                                                   \
+  switch (M0) {                                                                     \
+    case 64: return F<64>(__VA_ARGS__);                                              \
+    case 128: return F<128>(__VA_ARGS__);                                            \
+    case 256: return F<256>(__VA_ARGS__);                                            \
+    case 512: return F<512>(__VA_ARGS__);                                            \
+    case 1024: return F<1024>(__VA_ARGS__);                                          \
+    case 2048: return F<2048>(__VA_ARGS__);                                          \
+    case 4096: return F<4096>(__VA_ARGS__);                                          \
+  }                                                                                 \
+  return hipErrorInvalidValue;
 
-template <typename R>
-hipError_t launch_row2(int mode, int H, dim3 grid, hipStream_t st, const Args2<R> &a, int term) {
+template <typename R, int E, int MODE> struct RowLaunch {
+  template <int H> static hipError_t one(dim3 grid, hipStream_t st, const Args2<R> &a, int term) {
+    constexpr size_t lds = row_lds_bytes<R>(H, MODE);
+    if constexpr (lds > kLdsDevice || H < E) {  // rejected by the planner
+      return hipErrorInvalidValue;
+    } else {
+      static const hipError_t attr = set_lds(k_row2<R, MODE, H, E>, lds);
+      if (attr != hipSuccess) return attr;
+      hipLaunchKernelGGL((k_row2<R, MODE, H, E>), grid, dim3(team_threads(E)), lds, st, a, term);
+      return hipGetLastError();
+    }
+  }
+  template <int H>
+  static hipError_t batch(int nblocks, hipStream_t st, const BatchItem<R> *items, int nitems,
+                          int term) {
+    constexpr size_t lds = row_lds_bytes<R>(H, MODE);
+    if constexpr (lds > kLdsDevice || H < E) {
+      return hipErrorInvalidValue;
+    } else {
+      static const hipError_t attr = set_lds(k_row2_batch<R, MODE, H, E>, lds);
+      if (attr != hipSuccess) return attr;
+      hipLaunchKernelGGL((k_row2_batch<R, MODE, H, E>), dim3(nblocks), dim3(team_threads(E)),
+                         lds, st, items, nitems, term);
+      return hipGetLastError();
+    }
+  }
+  static hipError_t run(int H, dim3 grid, hipStream_t st, const Args2<R> &a, int term) {
+    SWEIK_ROW_LENGTHS(one, grid, st, a, term)
+  }
+  static hipError_t run_batch(int H, int nblocks, hipStream_t st, const BatchItem<R> *items,
+                              int nitems, int term) {
+    SWEIK_ROW_LENGTHS(batch, nblocks, st, items, nitems, term)
+  }
+};
+
+template <typename R, int E>
+hipError_t launch_row2_e(int mode, int H, dim3 grid, hipStream_t st, const Args2<R> &a, int term) {
   switch (mode) {
-    case ROW_GHAT: return row_mode<R, ROW_GHAT>(H, grid, st, a, term);
-    case ROW_PHI0: return row_mode<R, ROW_PHI0>(H, grid, st, a, term);
-    case ROW_TERM: return row_mode<R, ROW_TERM>(H, grid, st, a, term);
-    case ROW_ADJ0: return row_mode<R, ROW_ADJ0>(H, grid, st, a, term);
-    case ROW_ADJ: return row_mode<R, ROW_ADJ>(H, grid, st, a, term);
+    case ROW_GHAT: return RowLaunch<R, E, ROW_GHAT>::run(H, grid, st, a, term);
+    case ROW_PHI0: return RowLaunch<R, E, ROW_PHI0>::run(H, grid, st, a, term);
+    case ROW_TERM: return RowLaunch<R, E, ROW_TERM>::run(H, grid, st, a, term);
+    case ROW_ADJ0: return RowLaunch<R, E, ROW_ADJ0>::run(H, grid, st, a, term);
+    case ROW_ADJ: return RowLaunch<R, E, ROW_ADJ>::run(H, grid, st, a, term);
   }
   return hipErrorInvalidValue;
 }
 
-template <typename R, int MODE, int M0>
-static hipError_t col_one(dim3 grid, hipStream_t st, const Args2<R> &a) {
-  constexpr size_t lds = col_lds_bytes<R>(M0);
-  if constexpr (lds > kLdsDevice) {  // rejected by the planner
-    return hipErrorInvalidValue;
-  } else {
-    static const hipError_t attr = set_lds(k_col2<R, MODE, M0>, lds);
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_col2<R, MODE, M0>), grid, dim3(kThreads), lds, st, a);
-    return hipGetLastError();
-  }
-}
-
-template <typename R, int MODE>
-static hipError_t col_mode(int M0, dim3 grid, hipStream_t st, const Args2<R> &a) {
-  switch (M0) {
-    case 64: return col_one<R, MODE, 64>(grid, st, a);
-    case 128: return col_one<R, MODE, 128>(grid, st, a);
-    case 256: return col_one<R, MODE, 256>(grid, st, a);
-    case 512: return col_one<R, MODE, 512>(grid, st, a);
-    case 1024: return col_one<R, MODE, 1024>(grid, st, a);
-    case 2048: return col_one<R, MODE, 2048>(grid, st, a);
-    case 4096: return col_one<R, MODE, 4096>(grid, st, a);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <typename R>
-hipError_t launch_col2(int mode, int M0, dim3 grid, hipStream_t st, const Args2<R> &a) {
-  return mode == COL_GHAT ? col_mode<R, COL_GHAT>(M0, grid, st, a)
-                          : col_mode<R, COL_CONV>(M0, grid, st, a);
-}
-
-// ---- uneven batches -------------------------------------------------------
-template <typename R, int MODE, int H>
-static hipError_t row_batch_one(int nblocks, hipStream_t st, const BatchItem<R> *items,
-                                int nitems, int term) {
-  constexpr size_t lds = row_lds_bytes<R>(H, MODE);
-  if constexpr (lds > kLdsDevice) {
-    return hipErrorInvalidValue;
-  } else {
-    static const hipError_t attr = set_lds(k_row2_batch<R, MODE, H>, lds);
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_row2_batch<R, MODE, H>), dim3(nblocks), dim3(kThreads), lds, st, items,
-                       nitems, term);
-    return hipGetLastError();
-  }
-}
-
-template <typename R, int MODE>
-static hipError_t row_batch_mode(int H, int nblocks, hipStream_t st, const BatchItem<R> *items,
-                                 int nitems, int term) {
-  switch (H) {
-    case 32: return row_batch_one<R, MODE, 32>(nblocks, st, items, nitems, term);
-    case 64: return row_batch_one<R, MODE, 64>(nblocks, st, items, nitems, term);
-    case 128: return row_batch_one<R, MODE, 128>(nblocks, st, items, nitems, term);
-    case 256: return row_batch_one<R, MODE, 256>(nblocks, st, items, nitems, term);
-    case 512: return row_batch_one<R, MODE, 512>(nblocks, st, items, nitems, term);
-    case 1024: return row_batch_one<R, MODE, 1024>(nblocks, st, items, nitems, term);
-    case 2048: return row_batch_one<R, MODE, 2048>(nblocks, st, items, nitems, term);
-    case 4096: return row_batch_one<R, MODE, 4096>(nblocks, st, items, nitems, term);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <typename R>
-hipError_t launch_row2_batch(int mode, int H, int nblocks, hipStream_t st,
-                             const BatchItem<R> *items, int nitems, int term) {
+template <typename R, int E>
+hipError_t launch_row2_batch_e(int mode, int H, int nblocks, hipStream_t st,
+                               const BatchItem<R> *items, int nitems, int term) {
   switch (mode) {
-    case ROW_GHAT: return row_batch_mode<R, ROW_GHAT>(H, nblocks, st, items, nitems, term);
-    case ROW_PHI0: return row_batch_mode<R, ROW_PHI0>(H, nblocks, st, items, nitems, term);
-    case ROW_TERM: return row_batch_mode<R, ROW_TERM>(H, nblocks, st, items, nitems, term);
+    case ROW_GHAT: return RowLaunch<R, E, ROW_GHAT>::run_batch(H, nblocks, st, items, nitems, term);
+    case ROW_PHI0: return RowLaunch<R, E, ROW_PHI0>::run_batch(H, nblocks, st, items, nitems, term);
+    case ROW_TERM: return RowLaunch<R, E, ROW_TERM>::run_batch(H, nblocks, st, items, nitems, term);
   }
   return hipErrorInvalidValue;
 }
 
-template <typename R, int MODE, int M0>
-static hipError_t col_batch_one(int nblocks, hipStream_t st, const BatchItem<R> *items,
-                                int nitems) {
-  constexpr size_t lds = col_lds_bytes<R>(M0);
-  if constexpr (lds > kLdsDevice) {
-    return hipErrorInvalidValue;
-  } else {
-    static const hipError_t attr = set_lds(k_col2_batch<R, MODE, M0>, lds);
-    if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_col2_batch<R, MODE, M0>), dim3(nblocks), dim3(kThreads), lds, st,
-                       items, nitems);
-    return hipGetLastError();
+template <typename R, int E, int MODE> struct ColLaunch {
+  template <int M0> static hipError_t one(dim3 grid, hipStream_t st, const Args2<R> &a) {
+    constexpr size_t lds = col_lds_bytes<R>(M0);
+    if constexpr (lds > kLdsDevice) {  // rejected by the planner
+      return hipErrorInvalidValue;
+    } else {
+      static const hipError_t attr = set_lds(k_col2<R, MODE, M0, E>, lds);
+      if (attr != hipSuccess) return attr;
+      hipLaunchKernelGGL((k_col2<R, MODE, M0, E>), grid, dim3(team_threads(E)), lds, st, a);
+      return hipGetLastError();
+    }
   }
+  template <int M0>
+  static hipError_t batch(int nblocks, hipStream_t st, const BatchItem<R> *items, int nitems) {
+    constexpr size_t lds = col_lds_bytes<R>(M0);
+    if constexpr (lds > kLdsDevice) {
+      return hipErrorInvalidValue;
+    } else {
+      static const hipError_t attr = set_lds(k_col2_batch<R, MODE, M0, E>, lds);
+      if (attr != hipSuccess) return attr;
+      hipLaunchKernelGGL((k_col2_batch<R, MODE, M0, E>), dim3(nblocks), dim3(team_threads(E)),
+                         lds, st, items, nitems);
+      return hipGetLastError();
+    }
+  }
+  static hipError_t run(int M0, dim3 grid, hipStream_t st, const Args2<R> &a) {
+    SWEIK_COL_LENGTHS(one, grid, st, a)
+  }
+  static hipError_t run_batch(int M0, int nblocks, hipStream_t st, const BatchItem<R> *items,
+                              int nitems) {
+    SWEIK_COL_LENGTHS(batch, nblocks, st, items, nitems)
+  }
+};
+
+template <typename R, int E>
+hipError_t launch_col2_e(int mode, int M0, dim3 grid, hipStream_t st, const Args2<R> &a) {
+  return mode == COL_GHAT ? ColLaunch<R, E, COL_GHAT>::run(M0, grid, st, a)
+                          : ColLaunch<R, E, COL_CONV>::run(M0, grid, st, a);
 }
 
-template <typename R, int MODE>
-static hipError_t col_batch_mode(int M0, int nblocks, hipStream_t st, const BatchItem<R> *items,
-                                 int nitems) {
-  switch (M0) {
-    case 64: return col_batch_one<R, MODE, 64>(nblocks, st, items, nitems);
-    case 128: return col_batch_one<R, MODE, 128>(nblocks, st, items, nitems);
-    case 256: return col_batch_one<R, MODE, 256>(nblocks, st, items, nitems);
-    case 512: return col_batch_one<R, MODE, 512>(nblocks, st, items, nitems);
-    case 1024: return col_batch_one<R, MODE, 1024>(nblocks, st, items, nitems);
-    case 2048: return col_batch_one<R, MODE, 2048>(nblocks, st, items, nitems);
-    case 4096: return col_batch_one<R, MODE, 4096>(nblocks, st, items, nitems);
-  }
-  return hipErrorInvalidValue;
-}
-
-template <typename R>
-hipError_t launch_col2_batch(int mode, int M0, int nblocks, hipStream_t st,
-                             const BatchItem<R> *items, int nitems) {
-  return mode == COL_GHAT ? col_batch_mode<R, COL_GHAT>(M0, nblocks, st, items, nitems)
-                          : col_batch_mode<R, COL_CONV>(M0, nblocks, st, items, nitems);
+template <typename R, int E>
+hipError_t launch_col2_batch_e(int mode, int M0, int nblocks, hipStream_t st,
+                               const BatchItem<R> *items, int nitems) {
+  return mode == COL_GHAT ? ColLaunch<R, E, COL_GHAT>::run_batch(M0, nblocks, st, items, nitems)
+                          : ColLaunch<R, E, COL_CONV>::run_batch(M0, nblocks, st, items, nitems);
 }
 
 template <typename R>
@@ -189,22 +171,29 @@ hipError_t launch_adj_prep(const R *dLdS, const double *phi, long long N, double
 }
 
 template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream_t st) {
-  hipLaunchKernelGGL(k_fill<R>, dim3(kRedBlocks), dim3(256), 0, st, out, N, v);
+  const long long nb = std::min<long long>((N + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_fill<R>, dim3((unsigned)std::max<long long>(nb, 1)), dim3(256), 0, st, out,
+                     N, v);
   return hipGetLastError();
 }
 
-#define SWEIK_INSTANTIATE_2D(R)                                                              \
-  template hipError_t launch_row2<R>(int, int, dim3, hipStream_t, const Args2<R> &, int);  \
-  template hipError_t launch_col2<R>(int, int, dim3, hipStream_t, const Args2<R> &);       \
-  template hipError_t launch_prep<R>(const R *, long long, double *, cplx<R> *, int,       \
-                                     hipStream_t);                                         \
-  template hipError_t launch_adj_prep<R>(const R *, const double *, long long, double,     \
-                                         double *, cplx<R> *, int, hipStream_t);           \
-  template hipError_t launch_fill<R>(R *, long long, R, hipStream_t);                      \
-  template hipError_t launch_row2_batch<R>(int, int, int, hipStream_t, const BatchItem<R> *, \
-                                           int, int);                                      \
-  template hipError_t launch_col2_batch<R>(int, int, int, hipStream_t, const BatchItem<R> *, \
-                                           int);                                           \
+#define SWEIK_INSTANTIATE_2D_ROWS(R, E)                                                     \
+  template hipError_t launch_row2_e<R, E>(int, int, dim3, hipStream_t, const Args2<R> &, int); \
+  template hipError_t launch_row2_batch_e<R, E>(int, int, int, hipStream_t,                 \
+                                                const BatchItem<R> *, int, int);
+
+#define SWEIK_INSTANTIATE_2D_COLS(R)                                                        \
+  template hipError_t launch_col2_e<R, 16>(int, int, dim3, hipStream_t, const Args2<R> &);  \
+  template hipError_t launch_col2_e<R, 8>(int, int, dim3, hipStream_t, const Args2<R> &);   \
+  template hipError_t launch_col2_batch_e<R, 16>(int, int, int, hipStream_t,                \
+                                                 const BatchItem<R> *, int);                \
+  template hipError_t launch_col2_batch_e<R, 8>(int, int, int, hipStream_t,                 \
+                                                const BatchItem<R> *, int);                 \
+  template hipError_t launch_prep<R>(const R *, long long, double *, cplx<R> *, int,        \
+                                     hipStream_t);                                          \
+  template hipError_t launch_adj_prep<R>(const R *, const double *, long long, double,      \
+                                         double *, cplx<R> *, int, hipStream_t);            \
+  template hipError_t launch_fill<R>(R *, long long, R, hipStream_t);                       \
   template hipError_t launch_prep_batch<R>(int, hipStream_t, const BatchItem<R> *);
 
 }  // namespace sweik

@@ -1,5 +1,7 @@
-// launch2d.hpp -- host-side declarations of the 2D kernel launchers (one
-// instantiation per precision, in k2d_f32.hip and k2d_f64.hip).
+// launch2d.hpp -- host-side declarations of the 2D kernel launchers.  The
+// row passes of each schedule E and precision are instantiated in
+// k2d_row<E>_<prec>.hip, the column passes and small kernels in
+// k2d_col_<prec>.hip.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,10 +10,16 @@
 
 namespace sweik {
 
-template <typename R>
-hipError_t launch_row2(int mode, int H, dim3 grid, hipStream_t st, const Args2<R> &a, int term);
-template <typename R>
-hipError_t launch_col2(int mode, int M0, dim3 grid, hipStream_t st, const Args2<R> &a);
+template <typename R, int E>
+hipError_t launch_row2_e(int mode, int H, dim3 grid, hipStream_t st, const Args2<R> &a, int term);
+template <typename R, int E>
+hipError_t launch_col2_e(int mode, int M0, dim3 grid, hipStream_t st, const Args2<R> &a);
+template <typename R, int E>
+hipError_t launch_row2_batch_e(int mode, int H, int nblocks, hipStream_t st,
+                               const BatchItem<R> *items, int nitems, int term);
+template <typename R, int E>
+hipError_t launch_col2_batch_e(int mode, int M0, int nblocks, hipStream_t st,
+                               const BatchItem<R> *items, int nitems);
 template <typename R>
 hipError_t launch_prep(const R *f, long long N, double *red, cplx<R> *tw, int lmax,
                        hipStream_t st);
@@ -20,12 +28,37 @@ hipError_t launch_adj_prep(const R *dLdS, const double *phi, long long N, double
                            double *red, cplx<R> *tw, int lmax, hipStream_t st);
 template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream_t st);
 template <typename R>
-hipError_t launch_row2_batch(int mode, int H, int nblocks, hipStream_t st,
-                             const BatchItem<R> *items, int nitems, int term);
-template <typename R>
-hipError_t launch_col2_batch(int mode, int M0, int nblocks, hipStream_t st,
-                             const BatchItem<R> *items, int nitems);
-template <typename R>
 hipError_t launch_prep_batch(int nitems, hipStream_t st, const BatchItem<R> *items);
+
+// schedule dispatch: E = 16 (radix-16 stages, 256 threads per work-group)
+// or 8 (radix-8 stages, 512 threads)
+template <typename R>
+inline hipError_t launch_row2(int mode, int H, int E, dim3 grid, hipStream_t st,
+                              const Args2<R> &a, int term) {
+  return E == 16  ? launch_row2_e<R, 16>(mode, H, grid, st, a, term)
+         : E == 8 ? launch_row2_e<R, 8>(mode, H, grid, st, a, term)
+                  : hipErrorInvalidValue;
+}
+template <typename R>
+inline hipError_t launch_col2(int mode, int M0, int E, dim3 grid, hipStream_t st,
+                              const Args2<R> &a) {
+  return E == 16  ? launch_col2_e<R, 16>(mode, M0, grid, st, a)
+         : E == 8 ? launch_col2_e<R, 8>(mode, M0, grid, st, a)
+                  : hipErrorInvalidValue;
+}
+template <typename R>
+inline hipError_t launch_row2_batch(int mode, int H, int E, int nblocks, hipStream_t st,
+                                    const BatchItem<R> *items, int nitems, int term) {
+  return E == 16  ? launch_row2_batch_e<R, 16>(mode, H, nblocks, st, items, nitems, term)
+         : E == 8 ? launch_row2_batch_e<R, 8>(mode, H, nblocks, st, items, nitems, term)
+                  : hipErrorInvalidValue;
+}
+template <typename R>
+inline hipError_t launch_col2_batch(int mode, int M0, int E, int nblocks, hipStream_t st,
+                                    const BatchItem<R> *items, int nitems) {
+  return E == 16  ? launch_col2_batch_e<R, 16>(mode, M0, nblocks, st, items, nitems)
+         : E == 8 ? launch_col2_batch_e<R, 8>(mode, M0, nblocks, st, items, nitems)
+                  : hipErrorInvalidValue;
+}
 
 }  // namespace sweik

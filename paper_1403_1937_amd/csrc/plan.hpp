@@ -18,6 +18,7 @@ struct Geo2 {
   int rpw, cpw;      // rows per row WG, columns per column WG
   int nbr, ncw;      // row WGs, column WGs
   int lmax, lmax_log;
+  int erow, ecol;    // schedule: elements per team thread of the row / column passes
 };
 
 struct Geo3 {

@@ -1,6 +1,7 @@
 // row2d.hpp -- row passes of the 2D solve (forward and adjoint).
 //
-// One team of P = H/16 threads per grid row, RPW rows per work-group.  A
+// One team of P = H/E threads per grid row (E = 16 or 8 elements per
+// thread; 4096/E threads per work-group), RPW = 4096/H rows per work-group.  A
 // pass (i) reads its spectral tile (RPW contiguous rows of the blocked
 // spectrum), the twiddle table and the pointwise operands of its rows,
 // (ii) takes the inverse real FFT of each row (complex FFT of length H
@@ -16,9 +17,9 @@ namespace sweik {
 // transposed spectrum spec[b][k1][rr], k1 < H (column 0 holds the real DC
 // and Nyquist bins of the row as one complex number).  Element e <-> (local
 // row, column).
-template <typename R, int H> struct RowTile {
-  static constexpr int RB = spec_rb<R>(), RPW = row_rpw(H), LDK = H;
-  static constexpr int NREG = (RPW * LDK + kThreads - 1) / kThreads;  // per thread
+template <typename R, int H, int E> struct RowTile {
+  static constexpr int RB = spec_rb<R>(), RPW = row_rpw(H), LDK = H, NT = team_threads(E);
+  static constexpr int NREG = (RPW * LDK + NT - 1) / NT;  // per thread
   cplx<R> *base;
   int rows;
   __device__ __forceinline__ void init(cplx<R> *spec, int row0, int spec_rows) {
@@ -45,13 +46,13 @@ template <typename R, int H> struct RowTile {
   }
 };
 
-template <bool FULL, typename R, int H>
-__device__ __forceinline__ void tile_issue(const RowTile<R, H> &tile, int tid,
-                                           cplx<R> (&tl)[RowTile<R, H>::NREG]) {
+template <bool FULL, typename R, int H, int E>
+__device__ __forceinline__ void tile_issue(const RowTile<R, H, E> &tile, int tid,
+                                           cplx<R> (&tl)[RowTile<R, H, E>::NREG]) {
   const int total = tile.rows * H;
 #pragma unroll
-  for (int u = 0; u < RowTile<R, H>::NREG; ++u) {
-    const int e = tid + u * kThreads;
+  for (int u = 0; u < RowTile<R, H, E>::NREG; ++u) {
+    const int e = tid + u * RowTile<R, H, E>::NT;
     if (FULL || e < total) {
       int rl, k1, off;
       tile.map(e, rl, k1, off);
@@ -60,15 +61,15 @@ __device__ __forceinline__ void tile_issue(const RowTile<R, H> &tile, int tid,
   }
 }
 
-template <bool FULL, typename R, int H>
-__device__ __forceinline__ void tile_to_lds(const RowTile<R, H> &tile, int tid,
-                                            const cplx<R> (&tl)[RowTile<R, H>::NREG],
+template <bool FULL, typename R, int H, int E>
+__device__ __forceinline__ void tile_to_lds(const RowTile<R, H, E> &tile, int tid,
+                                            const cplx<R> (&tl)[RowTile<R, H, E>::NREG],
                                             cplx<R> *lines) {
   constexpr int LL = lds_line_len(H);
   const int total = tile.rows * H;
 #pragma unroll
-  for (int u = 0; u < RowTile<R, H>::NREG; ++u) {
-    const int e = tid + u * kThreads;
+  for (int u = 0; u < RowTile<R, H, E>::NREG; ++u) {
+    const int e = tid + u * RowTile<R, H, E>::NT;
     if (FULL || e < total) {
       int rl, k1, off;
       tile.map(e, rl, k1, off);
@@ -77,15 +78,15 @@ __device__ __forceinline__ void tile_to_lds(const RowTile<R, H> &tile, int tid,
   }
 }
 
-template <bool FULL, typename R, int H>
-__device__ __forceinline__ void tile_store(const RowTile<R, H> &tile, int tid,
+template <bool FULL, typename R, int H, int E>
+__device__ __forceinline__ void tile_store(const RowTile<R, H, E> &tile, int tid,
                                            const cplx<R> *lines) {
   constexpr int LL = lds_line_len(H);
   const int total = tile.rows * H;
-  cplx<R> out[RowTile<R, H>::NREG];
+  cplx<R> out[RowTile<R, H, E>::NREG];
 #pragma unroll
-  for (int u = 0; u < RowTile<R, H>::NREG; ++u) {
-    const int e = tid + u * kThreads;
+  for (int u = 0; u < RowTile<R, H, E>::NREG; ++u) {
+    const int e = tid + u * RowTile<R, H, E>::NT;
     if (FULL || e < total) {
       int rl, k1, off;
       tile.map(e, rl, k1, off);
@@ -93,8 +94,8 @@ __device__ __forceinline__ void tile_store(const RowTile<R, H> &tile, int tid,
     }
   }
 #pragma unroll
-  for (int u = 0; u < RowTile<R, H>::NREG; ++u) {
-    const int e = tid + u * kThreads;
+  for (int u = 0; u < RowTile<R, H, E>::NREG; ++u) {
+    const int e = tid + u * RowTile<R, H, E>::NT;
     if (FULL || e < total) {
       int rl, k1, off;
       tile.map(e, rl, k1, off);
@@ -105,15 +106,15 @@ __device__ __forceinline__ void tile_store(const RowTile<R, H> &tile, int tid,
 
 // Inverse real FFT of this team's row (already in LDS): on return
 // v[j] = (x[2k], x[2k+1]) * 2 M1, k = t + P j, x the real row (M1 = 2H).
-template <typename R, int H>
-__device__ __forceinline__ void row_c2r(cplx<R> (&v)[16], int t, cplx<R> *line,
+template <typename R, int H, int E>
+__device__ __forceinline__ void row_c2r(cplx<R> (&v)[E], int t, cplx<R> *line,
                                         const cplx<R> *twl) {
   using C = cplx<R>;
-  constexpr int P = H / 16;
+  constexpr int P = H / E;
   // split step: Z = (X_k + conj X_{H-k}) + i (X_k - conj X_{H-k}) conj(w^k);
   // for k = 0 the stored pair (X_0, X_H) gives Z = (X_0 + X_H, X_0 - X_H)
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
+  for (int j = 0; j < E; ++j) {
     const int k = t + P * j;
     C xk = line[lpad(k)];
     C xc = cconj(line[lpad((H - k) & (H - 1))]);
@@ -128,20 +129,20 @@ __device__ __forceinline__ void row_c2r(cplx<R> (&v)[16], int t, cplx<R> *line,
 // Forward real FFT of this team's row (v[j] = (x[2k], x[2k+1]), k = t + P j)
 // into its LDS line as the half spectrum (twice the DFT, bins 0 and H packed
 // into column 0), then the store of the work-group's tile.
-template <bool FULL, typename R, int H>
-__device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[16], int t, int tid,
+template <bool FULL, typename R, int H, int E>
+__device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[E], int t, int tid,
                                               cplx<R> *line, const cplx<R> *lines,
-                                              const cplx<R> *twl, const RowTile<R, H> &tile) {
+                                              const cplx<R> *twl, const RowTile<R, H, E> &tile) {
   using C = cplx<R>;
-  constexpr int P = H / 16;
+  constexpr int P = H / E;
   team_fft<H, ilog2c(2 * H), false>(v, t, line, twl, true);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 16; ++j) line[lpad(t + P * j)] = v[j];
+  for (int j = 0; j < E; ++j) line[lpad(t + P * j)] = v[j];
   __syncthreads();
-  C x[16];
+  C x[E];
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
+  for (int j = 0; j < E; ++j) {
     const int k = t + P * j;
     C zk = line[lpad(k)];
     C zc = cconj(line[lpad((H - k) & (H - 1))]);
@@ -154,7 +155,7 @@ __device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[16], int t, int tid,
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < 16; ++j) line[lpad(t + P * j)] = x[j];
+  for (int j = 0; j < E; ++j) line[lpad(t + P * j)] = x[j];
   __syncthreads();
   tile_store<FULL>(tile, tid, lines);
 }
@@ -173,15 +174,15 @@ __device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[16], int t, int tid,
 // FULL: every row of the work-group lies in the grid and n1 == H, so no
 // element needs a bounds check (columns >= H are zero padding, known
 // statically).
-template <typename R, int MODE, int H, bool FULL>
+template <typename R, int MODE, int H, int E, bool FULL>
 __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned char *smem_raw,
                                          const int bid) {
   using C = cplx<R>;
-  using Tile = RowTile<R, H>;
-  constexpr int P = H / 16, RPW = row_rpw(H), LL = lds_line_len(H);
+  using Tile = RowTile<R, H, E>;
+  constexpr int P = H / E, RPW = row_rpw(H), LL = lds_line_len(H), NT = team_threads(E);
   constexpr int TWLOG = ilog2c(2 * H);
   constexpr bool STG = row_staged<R>(H, MODE);
-  constexpr int NTW = (2 * H + kThreads - 1) / kThreads;
+  constexpr int NTW = (2 * H + NT - 1) / NT;
   constexpr bool LOADS_TILE = MODE == ROW_TERM || MODE == ROW_ADJ;
   C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / 2H), k < 2H
   C *lines = twl + 2 * H;
@@ -210,13 +211,13 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   C twr[NTW];
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
-    const int k = tid + u * kThreads;
+    const int k = tid + u * NT;
     if (k < 2 * H) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
   }
   C tl[Tile::NREG];
   if constexpr (LOADS_TILE) tile_issue<FULL>(tile, tid, tl);
   // pointwise operands of this thread's columns c = 2(t + P j) + e
-  constexpr int NOP = STG ? 16 : 1;
+  constexpr int NOP = STG ? E : 1;
   R o1[NOP], o2[NOP], o3[NOP];
   double od[NOP];
   if constexpr (STG) {
@@ -233,10 +234,10 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
       p3 = term > 1 ? a.lam : nullptr;
       pd = term != a.T ? a.acc : nullptr;
     }
-    // columns 2(t + P j) for j >= 8 are >= H >= n1: zero padding
+    // columns 2(t + P j) for j >= E/2 are >= H >= n1: zero padding
     if ((a.n1 & 1) == 0) {  // column pairs are aligned: vector loads
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
+      for (int j = 0; j < E / 2; ++j) {
         const int c0 = 2 * (t + P * j);
         const bool ok = col_ok(c0);
         using V = cplx<R>;  // a pair of R
@@ -261,7 +262,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
+      for (int q = 0; q < E; ++q) {
         const int cc = 2 * (t + P * (q >> 1)) + (q & 1);
         const bool ok = col_ok(cc);
         o1[q] = (ok && p1) ? p1[rowoff + cc] : (R)0;
@@ -325,23 +326,23 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   }
 
   // exponents: forward phi_i = 2^E_i m_i; adjoint a_i = 2^e_lam (mantissa)
-  int dstep = 0, E = 0, elam = 0;
+  int dstep = 0, Ei = 0, elam = 0;
   if (MODE == ROW_TERM) {
     double mu = 0.0;
-    for (int i = tid; i < a.nbr; i += kThreads) mu = fmax(mu, a.mu[(size_t)(term - 1) * a.nbr + i]);
+    for (int i = tid; i < a.nbr; i += NT) mu = fmax(mu, a.mu[(size_t)(term - 1) * a.nbr + i]);
     mu = block_max(mu);
     dstep = exp_step(mu);
-    E = a.expo[term - 1] + dstep;
+    Ei = a.expo[term - 1] + dstep;
   }
   if ((MODE == ROW_TERM || MODE == ROW_PHI0) && bid == 0 && tid == 0) {
     const int slot = MODE == ROW_TERM ? term : 0;
-    a.expo[slot] = E;
-    if (a.info) a.info->scale_exp[slot] = E;
-    if (a.ck_expo) a.ck_expo[slot] = E;
+    a.expo[slot] = Ei;
+    if (a.info) a.info->scale_exp[slot] = Ei;
+    if (a.ck_expo) a.ck_expo[slot] = Ei;
   }
   if (MODE == ROW_ADJ0) {
     double mx = 0.0;
-    for (int i = tid; i < kRedBlocks; i += kThreads) mx = fmax(mx, a.red[i]);
+    for (int i = tid; i < kRedBlocks; i += NT) mx = fmax(mx, a.red[i]);
     mx = block_max(mx);
     elam = exp_step(mx);
     if (bid == 0 && tid == 0) a.expo[0] = elam;
@@ -354,25 +355,25 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     }
     __syncthreads();
     elam = s_e[0];
-    E = s_e[1];
+    Ei = s_e[1];
   }
 
   // sources of phi_0 (the first kSrcLds of them through LDS)
   constexpr int kSrcLds = MODE == ROW_PHI0 ? 512 : 1;
   __shared__ int s_src[2 * kSrcLds];
   if (MODE == ROW_PHI0)
-    for (int i = tid; i < 2 * min(a.n_src, kSrcLds); i += kThreads) s_src[i] = a.src[i];
+    for (int i = tid; i < 2 * min(a.n_src, kSrcLds); i += NT) s_src[i] = a.src[i];
 
   // ---- 3. operands into LDS -------------------------------------------------
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
-    const int k = tid + u * kThreads;
+    const int k = tid + u * NT;
     if (k < 2 * H) twl[k] = twr[u];
   }
   if constexpr (LOADS_TILE) tile_to_lds<FULL>(tile, tid, tl, lines);
   if constexpr (STG) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
+    for (int q = 0; q < E; ++q) {
       // a staging row holds H >= n1 entries
       const int cc = 2 * (t + P * (q >> 1)) + (q & 1);
       if (FULL || cc < a.n1) {
@@ -393,7 +394,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   auto op3 = [&](int cc, const R *g) -> R { return STG ? sR[(size_t)2 * RPW * H + cc] : g[rowoff + cc]; };
   auto opd = [&](int cc, const double *g) -> double { return STG ? sD[cc] : g[rowoff + cc]; };
 
-  C v[16];
+  C v[E];
 
   // ---- 4. kernel table ------------------------------------------------------
   if constexpr (MODE == ROW_GHAT) {
@@ -403,7 +404,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     R *xl = reinterpret_cast<R *>(line);
     const double k0v = s_par[0];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < E / 2; ++j) {
       const int c0 = 2 * (t + P * j);
       R z0 = 0, z1 = 0;
       if (row_ok) {
@@ -418,30 +419,30 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     if (t == 0) xl[H] = (R)0;  // offset H >= n1 is never used
     __syncthreads();
 #pragma unroll
-    for (int j = 8; j < 16; ++j) {
+    for (int j = E / 2; j < E; ++j) {
       const int c0 = 2 * (t + P * j);
       v[j] = cmake<C>(xl[2 * H - c0], xl[2 * H - c0 - 1]);
     }
-    row_r2c_store<FULL, R, H>(v, t, tid, line, lines, twl, tile);
+    row_r2c_store<FULL, R, H, E>(v, t, tid, line, lines, twl, tile);
     return;
   }
 
-  if constexpr (LOADS_TILE) row_c2r<R, H>(v, t, line, twl);
+  if constexpr (LOADS_TILE) row_c2r<R, H, E>(v, t, line, twl);
   // the forcing of the next FFT is zero in the padding half (columns >= H)
 #pragma unroll
-  for (int j = 8; j < 16; ++j) v[j] = cmake<C>((R)0, (R)0);
+  for (int j = E / 2; j < E; ++j) v[j] = cmake<C>((R)0, (R)0);
 
-  // ---- 5. pointwise step over columns 2k, 2k+1 (k = t + P j) --------------
+  // ---- 5. pointwise step over columns 2k, 2k+1 (k = t + P j, j < E/2) -----
   long long nbad = 0;
   if constexpr (MODE == ROW_PHI0 || MODE == ROW_TERM) {
     const bool even_n1 = FULL || (a.n1 & 1) == 0;
     const R sm = (R)ldexp(1.0, -dstep);
-    const double sE = ((MODE == ROW_TERM && (term & 1)) ? -1.0 : 1.0) * ldexp(1.0, E);
+    const double sE = ((MODE == ROW_TERM && (term & 1)) ? -1.0 : 1.0) * ldexp(1.0, Ei);
     R mlr = (R)0;
     const int slot = MODE == ROW_TERM ? term : 0;
     R *ckt = a.ck_terms ? a.ck_terms + (size_t)slot * N + rowoff : nullptr;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < E / 2; ++j) {
       const int c0 = 2 * (t + P * j);
       R z0 = 0, z1 = 0;
       if (col_ok(c0)) {
@@ -542,7 +543,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     const double lam_scale = ldexp(1.0, -elam);
     const double sgnT = (a.T & 1) ? -1.0 : 1.0;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < E / 2; ++j) {
       R zz[2] = {(R)0, (R)0};
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
@@ -563,11 +564,11 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   }
 
   if constexpr (MODE == ROW_ADJ) {
-    const double gscale = ldexp(1.0, E + elam);
+    const double gscale = ldexp(1.0, Ei + elam);
     const double sgn_prev = ((term - 1) & 1) ? -1.0 : 1.0;  // (-1)^(i-1)
     const R *mprev = a.ck_terms + (size_t)(term - 1) * N;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
+    for (int j = 0; j < E / 2; ++j) {
       R zz[2] = {(R)0, (R)0};
       const double bb[2] = {(double)v[j].x, (double)v[j].y};
 #pragma unroll
@@ -594,33 +595,33 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   }
 
   // ---- 6. forward real FFT of the new forcing, store the tile --------------
-  row_r2c_store<FULL, R, H>(v, t, tid, line, lines, twl, tile);
+  row_r2c_store<FULL, R, H, E>(v, t, tid, line, lines, twl, tile);
 }
 
-template <typename R, int MODE, int H>
+template <typename R, int MODE, int H, int E>
 __device__ __forceinline__ void row_block(const Args2<R> &a, int term, unsigned char *smem_raw,
                                           int bid) {
   const int row0 = bid * row_rpw(H);
   if (row0 + row_rpw(H) <= a.n0 && a.n1 == H)
-    row_pass<R, MODE, H, true>(a, term, smem_raw, bid);
+    row_pass<R, MODE, H, E, true>(a, term, smem_raw, bid);
   else
-    row_pass<R, MODE, H, false>(a, term, smem_raw, bid);
+    row_pass<R, MODE, H, E, false>(a, term, smem_raw, bid);
 }
 
-template <typename R, int MODE, int H>
-__global__ void __launch_bounds__(kThreads) k_row2(Args2<R> a, int term) {
+template <typename R, int MODE, int H, int E>
+__global__ void __launch_bounds__(team_threads(E)) k_row2(Args2<R> a, int term) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  row_block<R, MODE, H>(a, term, smem_raw, blockIdx.x);
+  row_block<R, MODE, H, E>(a, term, smem_raw, blockIdx.x);
 }
 
 // Uneven batch: one launch over the row work-groups of every instance of a
 // size class; items[i].begin is the first work-group of instance i.
-template <typename R, int MODE, int H>
-__global__ void __launch_bounds__(kThreads) k_row2_batch(const BatchItem<R> *__restrict__ items,
+template <typename R, int MODE, int H, int E>
+__global__ void __launch_bounds__(team_threads(E)) k_row2_batch(const BatchItem<R> *__restrict__ items,
                                                          int nitems, int term) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = find_item(items, nitems, (int)blockIdx.x);
-  row_block<R, MODE, H>(items[i].a, term, smem_raw, (int)blockIdx.x - items[i].begin);
+  row_block<R, MODE, H, E>(items[i].a, term, smem_raw, (int)blockIdx.x - items[i].begin);
 }
 
 // Adjoint start: max |lambda| partials (with the twiddle table).

@@ -122,3 +122,30 @@ def test_autograd_function(prec):
     g = pk.solve_adjoint(ft.detach(), src, 1 / 80, hbar, T, dLdS)
     torch.cuda.synchronize()
     assert torch.allclose(ft.grad, g, rtol=1e-6 if prec == "fp32" else 1e-12, atol=0)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-3)])
+def test_adjoint_radix8_schedule(prec, tol):
+    """The adjoint sweep with radix-8 team FFTs (512-thread work-groups)."""
+    import paper_1403_1937_amd as pk
+    dims, T, hbar = (100, 76), 8, 0.08
+    f, src, rec, w = _setup(dims, 3, 32, 91, hbar)
+    h = 1.0 / max(dims)
+    o = oracle.solve(f.astype(np.float64), src, h, hbar, T)
+    target = np.array([o["S"][i, j] for i, j in rec]) * 0.97
+    dLdS = _dLdS_dense(dims, rec, w, o["S"], target)
+    g_o, _ = oracle.adjoint(f.astype(np.float64), src, h, hbar, T, dLdS)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    pl = pk.Plan(dims, h, hbar, T, len(src), prec)
+    pl.set_schedule(8, 8)
+    ft = torch.as_tensor(f.astype(np.float64)).to("cuda", dt)
+    d_src = torch.as_tensor(np.ascontiguousarray(src, np.int32)).cuda()
+    S, ws, ck = torch.empty_like(ft), pl.workspace("cuda"), pl.checkpoint("cuda")
+    g = torch.empty_like(ft)
+    pl.solve(ft, d_src, S, ws, ck)
+    pl.adjoint(ft, d_src, ck, torch.as_tensor(dLdS).to("cuda", dt), g, ws)
+    torch.cuda.synchronize()
+    g = g.double().cpu().numpy()
+    err = np.linalg.norm(g - g_o) / np.linalg.norm(g_o)
+    print(f"adjoint radix-8 {prec}: normwise rel {err:.3e}", flush=True)
+    assert err <= tol

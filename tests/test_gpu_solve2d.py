@@ -135,3 +135,69 @@ def test_scale_exponents_track_decay():
     assert info["scale_exp"][-1] < -150  # far below float32's range
     worst, frac, _ = report(S, o, 0.05, "fp32")
     assert worst <= TOL["fp32"]
+
+
+def _run_sched(f32, src, h, hbar, T, prec, sched):
+    """Solve through an explicit plan with schedule (row_e, col_e)."""
+    import paper_1403_1937_amd as pk
+    from paper_1403_1937_amd._native import _read_info, info_struct_size
+    dims = f32.shape
+    pl = pk.Plan(dims, h, hbar, T, len(src), prec)
+    pl.set_schedule(*sched)
+    assert pl.schedule == {"row_e": sched[0], "col_e": sched[1]}
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    f = torch.as_tensor(f32.astype(np.float64)).to("cuda", dt)
+    d_src = torch.as_tensor(np.ascontiguousarray(src, np.int32)).to("cuda")
+    S = torch.empty_like(f)
+    info = torch.zeros(info_struct_size(), dtype=torch.uint8, device="cuda")
+    pl.solve(f, d_src, S, pl.workspace("cuda"), None, info)
+    torch.cuda.synchronize()
+    return S.double().cpu().numpy(), _read_info(info)
+
+
+SCHED_CASES = [c for c in CASES if c[0] in ("ragged100x76", "tall257x20", "thin7x300",
+                                                "square256", "rect200x513")]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("sched", [(8, 8), (16, 8), (8, 16)], ids=["r8c8", "r16c8", "r8c16"])
+@pytest.mark.parametrize("case", SCHED_CASES, ids=[c[0] for c in SCHED_CASES])
+def test_schedules_parity_2d(case, sched, prec):
+    """Radix-8 team FFTs with 512-thread work-groups, against the oracle."""
+    name, dims, h, hbar, T, n_src, seed = case
+    rng = np.random.default_rng(seed)
+    f = workloads.smoothed_noise(dims, 4.0, 1.0, 3.0, rng).astype(np.float32)
+    src = workloads.distinct_sources(dims, n_src, rng)
+    print(f"case {name} sched {sched} prec {prec}", flush=True)
+    S, info = _run_sched(f, src, h, hbar, T, prec, sched)
+    o = _oracle(f, src, h, hbar, T)
+    assert info["flags"] == 0
+    worst, frac, _ = report(S, o, hbar, prec)
+    print(f"  max rel {worst:.3e} on {frac:.3f}", flush=True)
+    assert worst <= TOL[prec]
+    assert envelope_violations(S, o, hbar, prec) == 0
+
+
+def test_autotune_picks_a_schedule_and_stays_correct():
+    import paper_1403_1937_amd as pk
+    # lengths no other test uses: the tuned entries go to the process table
+    dims, h, hbar, T = (150, 2000), 1 / 2000, 0.05, 6
+    rng = np.random.default_rng(41)
+    f32 = workloads.smoothed_noise(dims, 4.0, 1.0, 3.0, rng).astype(np.float32)
+    src = workloads.distinct_sources(dims, 3, rng)
+    pl = pk.Plan(dims, h, hbar, T, len(src), "fp32")
+    ws = pl.workspace("cuda")
+    n = pl.autotune(ws)
+    print(f"autotune timed {n} schedules -> {pl.schedule}", flush=True)
+    assert n == 4
+    assert pl.schedule["row_e"] in (8, 16) and pl.schedule["col_e"] in (8, 16)
+    # later plans of the same lengths start from the tuned entries
+    assert pk.Plan(dims, h, hbar, T, len(src), "fp32").schedule == pl.schedule
+    f = torch.as_tensor(f32).cuda()
+    d_src = torch.as_tensor(src).cuda()
+    S = torch.empty_like(f)
+    pl.solve(f, d_src, S, ws)  # the workspace was overwritten by the tuner
+    torch.cuda.synchronize()
+    o = _oracle(f32, src, h, hbar, T)
+    worst, _, _ = report(S.double().cpu().numpy(), o, hbar, "fp32")
+    assert worst <= TOL["fp32"]
