@@ -220,14 +220,16 @@ sweik_status sweik_plan_get_schedule(sweik_plan plan, sweik_schedule *out);
  * solve with this plan is being enqueued on another thread. */
 sweik_status sweik_plan_set_schedule(sweik_plan plan, const sweik_schedule *s);
 
-/* Times every candidate schedule of the 2D per-term passes (the column
- * convolution and, when T >= 2, the row pass) with HIP events on `stream`,
- * five launches each, on the workspace `ws` (its contents are overwritten:
- * run it before a solve, not between a solve and its adjoint).  Keeps the
- * fastest in the plan and in the process-wide table keyed by (pass, length,
- * precision) that later plans start from.  Synchronises the stream.  Returns
- * the number of schedules timed (0 for 3D plans, negative on a HIP error or
- * a too-small workspace). */
+/* Times every candidate schedule of the 2D per-term passes with HIP events
+ * on `stream`: each (col_e, row_e) pair as 4 back-to-back [column
+ * convolution; row pass] launches, 3 times, keeping the median (with T < 2
+ * only the column pass is timed).  Works on the workspace `ws`, whose
+ * contents are overwritten: run it before a solve, not between a solve and
+ * its adjoint.  Keeps the fastest in the plan and in the process-wide table
+ * keyed by (pass, length, precision) that later plans start from.
+ * Synchronises the stream.  Returns the number of schedules timed (4, or 2
+ * when T < 2; 0 for 3D plans; negative on a HIP error or a too-small
+ * workspace). */
 int32_t sweik_autotune(sweik_plan plan, void *ws, size_t ws_bytes,
                        void *stream);
 

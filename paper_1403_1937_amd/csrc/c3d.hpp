@@ -28,9 +28,8 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
                                         const int g) {
   using C = cplx<R>;
   constexpr int P = M / 16, CPW = c3_cpw(M), NT = c3_threads(M), LL = lds_line_len(M);
-  constexpr int HM = M / 2, TWLOG = ilog2c(M);
-  constexpr int NTW = (M + NT - 1) / NT;
-  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / M), k < M
+  constexpr int HM = M / 2;
+  C *twl = reinterpret_cast<C *>(smem_raw);  // stage twiddle tables (< M entries)
   C *lines = twl + M;
 
   const int tid = threadIdx.x, c = tid % CPW, t = tid / CPW;
@@ -47,12 +46,9 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
   }
 
   // ---- issue the global reads -------------------------------------------------
-  C twr[NTW];
-#pragma unroll
-  for (int u = 0; u < NTW; ++u) {
-    const int k = tid + u * NT;
-    if (k < M) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
-  }
+  constexpr int NSR = (stage_tw_len(M, 16) + NT - 1) / NT;
+  C twr[NSR > 0 ? NSR : 1];
+  stage_tw_issue<M, 16>(twr, a.tw, a.lmax_log, tid, NT);
   C v[16];
   R gv[16];
   const C zero = cmake<C>((R)0, (R)0);
@@ -98,18 +94,14 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
       v[j] = s < a.n0 ? in[(size_t)s * st] : zero;
     }
   }
-#pragma unroll
-  for (int u = 0; u < NTW; ++u) {
-    const int k = tid + u * NT;
-    if (k < M) twl[k] = twr[u];
-  }
+  stage_tw_store<M, 16>(twr, twl, tid, NT);
   __syncthreads();
 
   // ---- transforms and stores ----------------------------------------------------
   if constexpr (MODE == C3_YI) {
-    team_fft<M, TWLOG, true>(v, t, line, twl, false);
+    team_fft<M, true>(v, t, line, twl, false);
   } else {
-    team_fft<M, TWLOG, false>(v, t, line, twl, false);
+    team_fft<M, false>(v, t, line, twl, false);
   }
   if constexpr (MODE == C3_YF) {
     C *out = a.s2 + (size_t)plane * M * H2 + k2;
@@ -118,7 +110,7 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
   } else if constexpr (MODE == C3_Z) {
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = cscale(v[j], gv[j]);
-    team_fft<M, TWLOG, true>(v, t, line, twl, true);
+    team_fft<M, true>(v, t, line, twl, true);
     C *io = a.s2 + (size_t)plane * H2 + k2;
     const size_t st = (size_t)a.M1 * H2;
 #pragma unroll

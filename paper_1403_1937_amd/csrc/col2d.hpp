@@ -28,10 +28,9 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
   using C = cplx<R>;
   constexpr int P = M0 / E, CPW = col_cpw(M0), RB = spec_rb<R>(), LL = lds_line_len(M0);
   constexpr int NT = team_threads(E);
-  constexpr int H0 = M0 / 2, TWLOG = ilog2c(M0);
-  constexpr int NTW = (M0 + NT - 1) / NT;
+  constexpr int H0 = M0 / 2;
   static_assert(P % RB == 0, "column team must cover whole row blocks");
-  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / M0), k < M0
+  C *twl = reinterpret_cast<C *>(smem_raw);  // stage twiddle tables (< M0 entries)
   C *lines = twl + M0;
 
   const int tid = threadIdx.x;
@@ -47,12 +46,9 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
   C *col = a.spec + (size_t)(active ? k1 : 0) * RB;
 
   // ---- issue the global reads -----------------------------------------------
-  C twr[NTW];
-#pragma unroll
-  for (int u = 0; u < NTW; ++u) {
-    const int k = tid + u * NT;
-    if (k < M0) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
-  }
+  constexpr int NSR = (stage_tw_len(M0, E) + NT - 1) / NT;
+  C twr[NSR > 0 ? NSR : 1];
+  stage_tw_issue<M0, E>(twr, a.tw, a.lmax_log, tid, NT);
   C v[E];
   R gv[E], gb[E];
   if constexpr (MODE == COL_CONV) {
@@ -94,14 +90,10 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
       v[j] = x;
     }
   }
-#pragma unroll
-  for (int u = 0; u < NTW; ++u) {
-    const int k = tid + u * NT;
-    if (k < M0) twl[k] = twr[u];
-  }
+  stage_tw_store<M0, E>(twr, twl, tid, NT);
   __syncthreads();
 
-  team_fft<M0, TWLOG, false>(v, t, line, twl, false);
+  team_fft<M0, false>(v, t, line, twl, false);
   if constexpr (MODE == COL_CONV) {
     if (packed_wg) {
       C pv[E];
@@ -125,7 +117,7 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
 #pragma unroll
       for (int j = 0; j < E; ++j) v[j] = cscale(v[j], gv[j]);
     }
-    team_fft<M0, TWLOG, true>(v, t, line, twl, true);
+    team_fft<M0, true>(v, t, line, twl, true);
     if (active) {
 #pragma unroll
       for (int j = 0; j < E / 2; ++j) {

@@ -13,8 +13,8 @@
 // transform, a pointwise spectral product and an inverse transform chain
 // without any extra exchange.
 //
-// Twiddles come from a table in LDS, twl[k] = exp(-2 pi i k / 2^TWLOG) for
-// k < 2^TWLOG, which the kernel copies once from the solve's global table.
+// Twiddles come from per-stage tables in LDS (see stage_tw_len), which the
+// kernel copies once from the solve's global table.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -140,15 +140,41 @@ __host__ __device__ constexpr int lpad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lds_line_len(int L) { return L + (L >> 4) + 1; }
 __host__ __device__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
 
+// Stage twiddle tables: for every stage of span p > 1 (p = E, E^2, ... < L)
+// the p entries exp(-2 pi i k / (p R)), k < p, stored contiguously in LDS one
+// stage after the other, so that the butterflies of consecutive k read
+// consecutive entries (no bank conflicts from strided table reads).
+constexpr int stage_tw_len(int L, int E) {
+  int n = 0;
+  for (int p = E; p < L; p *= E) n += p;
+  return n;
+}
+constexpr int stage_tw_off(int p, int E) {
+  int n = 0;
+  for (int q = E; q < p; q *= E) n += q;
+  return n;
+}
+// index into a global table of 2^lmax_log entries exp(-2 pi i j / 2^lmax_log)
+// of entry e of the concatenated stage tables of a length-L line
+template <int L, int E> __device__ __forceinline__ int stage_tw_index(int e, int lmax_log) {
+  int off = 0;
+#pragma unroll
+  for (int p = E; p < L; p *= E) {
+    const int R = L / p < E ? L / p : E;
+    if (e < off + p) return (e - off) << (lmax_log - ilog2c(p * R));
+    off += p;
+  }
+  return 0;
+}
+
 // One Stockham stage of radix R and span p on a team line (compile-time L,
-// E elements per thread).  Twiddles exp(-2 pi i q k / (p R)) come from the
-// LDS table (base length 2^TWLOG); LAST: results stay in registers (index
-// t + P j), else they go to LDS at the autosort position.
-template <int L, int R, int p, int TWLOG, bool INV, bool LAST, int E, typename C>
-__device__ __forceinline__ void stage(C (&v)[E], int t, C *lds, const C *twl) {
+// E elements per thread).  Twiddles exp(-2 pi i q k / (p R)) are powers of
+// the stage table's entry k; LAST: results stay in registers (index t + P j),
+// else they go to LDS at the autosort position.
+template <int L, int R, int p, bool INV, bool LAST, int E, typename C>
+__device__ __forceinline__ void stage(C (&v)[E], int t, C *lds, const C *tws) {
   constexpr int P = L / E;
   constexpr int NB = E / R;  // butterflies per thread
-  constexpr int SH = TWLOG - ilog2c(p * R);
   static_assert(R >= 2 && R <= E && E % R == 0, "stage radix");
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
@@ -160,7 +186,7 @@ __device__ __forceinline__ void stage(C (&v)[E], int t, C *lds, const C *twl) {
     if constexpr (p > 1) {
       // one table read per butterfly; the other twiddles are its powers
       C w[R];
-      w[1] = twl[k << SH];
+      w[1] = tws[stage_tw_off(p, E) + k];
       if (INV) w[1] = cconj(w[1]);
 #pragma unroll
       for (int q = 2; q < R; ++q) w[q] = cmul(w[q / 2], w[q - q / 2]);
@@ -189,29 +215,52 @@ __device__ __forceinline__ void lds_gather(C (&v)[E], int t, const C *lds) {
 }
 
 // Stages of span p, p E, p E^2, ... (radix E), the last of radix L / p.
-template <int L, int TWLOG, bool INV, int E, int p, typename C>
-__device__ __forceinline__ void team_stages(C (&v)[E], int t, C *lds, const C *twl) {
+template <int L, bool INV, int E, int p, typename C>
+__device__ __forceinline__ void team_stages(C (&v)[E], int t, C *lds, const C *tws) {
   if constexpr (p * E >= L) {
-    stage<L, L / p, p, TWLOG, INV, true, E>(v, t, lds, twl);
+    stage<L, L / p, p, INV, true, E>(v, t, lds, tws);
   } else {
-    stage<L, E, p, TWLOG, INV, false, E>(v, t, lds, twl);
+    stage<L, E, p, INV, false, E>(v, t, lds, tws);
     lds_gather<L, E>(v, t, lds);
-    team_stages<L, TWLOG, INV, E, p * E>(v, t, lds, twl);
+    team_stages<L, INV, E, p * E>(v, t, lds, tws);
   }
 }
 
 // Complex FFT of length L held by a team of L/E threads (E = 16: radix-16
-// stages; E = 8: radix-8 stages); twl: LDS twiddle table with all 2^TWLOG
-// >= L entries.  Barriers are block-wide: every thread of the block calls
-// this.  With lead_sync a barrier first protects LDS data still being read
-// from earlier work.
-template <int L, int TWLOG, bool INV, int E, typename C>
-__device__ __forceinline__ void team_fft(C (&v)[E], int t, C *lds, const C *twl,
+// stages; E = 8: radix-8 stages); tws: the LDS stage twiddle tables of a
+// length-L line (stage_tw_len(L, E) entries).  Barriers are block-wide:
+// every thread of the block calls this.  With lead_sync a barrier first
+// protects LDS data still being read from earlier work.
+template <int L, bool INV, int E, typename C>
+__device__ __forceinline__ void team_fft(C (&v)[E], int t, C *lds, const C *tws,
                                          bool lead_sync = true) {
   static_assert(L >= E && L <= 4096 && (L & (L - 1)) == 0, "line length");
   static_assert(E == 8 || E == 16, "elements per thread");
   if (lead_sync) __syncthreads();
-  team_stages<L, TWLOG, INV, E, 1>(v, t, lds, twl);
+  team_stages<L, INV, E, 1>(v, t, lds, tws);
+}
+
+// The stage tables of a length-L line: issue the global reads into
+// registers (tr, NR = ceil(stage_tw_len / nthreads) per thread) ...
+template <int L, int E, int NR, typename C>
+__device__ __forceinline__ void stage_tw_issue(C (&tr)[NR], const C *tw, int lmax_log, int tid,
+                                               int nthreads) {
+  constexpr int NC = stage_tw_len(L, E);
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const int e = tid + u * nthreads;
+    if (e < NC) tr[u] = tw[stage_tw_index<L, E>(e, lmax_log)];
+  }
+}
+// ... and store them to LDS (before the barrier that precedes the FFT)
+template <int L, int E, int NR, typename C>
+__device__ __forceinline__ void stage_tw_store(const C (&tr)[NR], C *tws, int tid, int nthreads) {
+  constexpr int NC = stage_tw_len(L, E);
+#pragma unroll
+  for (int u = 0; u < NR; ++u) {
+    const int e = tid + u * nthreads;
+    if (e < NC) tws[e] = tr[u];
+  }
 }
 
 // ---- block reductions ----------------------------------------------------

@@ -28,11 +28,16 @@ constexpr int row_rpw(int H) { return H / 16 >= kThreads ? 1 : kThreads / (H / 1
 constexpr int col_cpw(int M0) { return M0 / 16 >= kThreads ? 1 : kThreads / (M0 / 16); }
 constexpr size_t kLdsDevice = 163840;  // gfx950 limit per work-group
 
-// Row pass LDS: twiddle table (2H entries of exp(-2 pi i k / 2H)), one padded
-// line per row, and (when it fits) staging rows for the pointwise operands
-// so that their loads are issued with the spectrum's.
+// Row pass LDS: twiddle table (2H entries of exp(-2 pi i k / 2H)), the stage
+// tables of the length-H FFT (room for either schedule), one padded line per
+// row, and (when it fits) staging rows for the pointwise operands so that
+// their loads are issued with the spectrum's.
+constexpr int row_stage_tw(int H) {
+  return stage_tw_len(H, 8) > stage_tw_len(H, 16) ? stage_tw_len(H, 8) : stage_tw_len(H, 16);
+}
 template <typename R> constexpr size_t row_lds_core(int H) {
-  return sizeof(R) * 2 * ((size_t)2 * H + (size_t)row_rpw(H) * lds_line_len(H));
+  return sizeof(R) * 2 *
+         ((size_t)2 * H + (size_t)row_stage_tw(H) + (size_t)row_rpw(H) * lds_line_len(H));
 }
 template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
   // per staged row: gamma (R) + accumulator (double) for the forward terms;

@@ -108,7 +108,7 @@ __device__ __forceinline__ void tile_store(const RowTile<R, H, E> &tile, int tid
 // v[j] = (x[2k], x[2k+1]) * 2 M1, k = t + P j, x the real row (M1 = 2H).
 template <typename R, int H, int E>
 __device__ __forceinline__ void row_c2r(cplx<R> (&v)[E], int t, cplx<R> *line,
-                                        const cplx<R> *twl) {
+                                        const cplx<R> *twl, const cplx<R> *tws) {
   using C = cplx<R>;
   constexpr int P = H / E;
   // split step: Z = (X_k + conj X_{H-k}) + i (X_k - conj X_{H-k}) conj(w^k);
@@ -123,7 +123,7 @@ __device__ __forceinline__ void row_c2r(cplx<R> (&v)[E], int t, cplx<R> *line,
     v[j] = cmake<C>(e.x - o.y, e.y + o.x);
     if (k == 0) v[j] = cmake<C>(xk.x + xk.y, xk.x - xk.y);
   }
-  team_fft<H, ilog2c(2 * H), true>(v, t, line, twl, true);
+  team_fft<H, true>(v, t, line, tws, true);
 }
 
 // Forward real FFT of this team's row (v[j] = (x[2k], x[2k+1]), k = t + P j)
@@ -132,10 +132,11 @@ __device__ __forceinline__ void row_c2r(cplx<R> (&v)[E], int t, cplx<R> *line,
 template <bool FULL, typename R, int H, int E>
 __device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[E], int t, int tid,
                                               cplx<R> *line, const cplx<R> *lines,
-                                              const cplx<R> *twl, const RowTile<R, H, E> &tile) {
+                                              const cplx<R> *twl, const cplx<R> *tws,
+                                              const RowTile<R, H, E> &tile) {
   using C = cplx<R>;
   constexpr int P = H / E;
-  team_fft<H, ilog2c(2 * H), false>(v, t, line, twl, true);
+  team_fft<H, false>(v, t, line, tws, true);
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < E; ++j) line[lpad(t + P * j)] = v[j];
@@ -185,7 +186,8 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   constexpr int NTW = (2 * H + NT - 1) / NT;
   constexpr bool LOADS_TILE = MODE == ROW_TERM || MODE == ROW_ADJ;
   C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / 2H), k < 2H
-  C *lines = twl + 2 * H;
+  C *tws = twl + 2 * H;                      // stage tables of the length-H FFT
+  C *lines = tws + row_stage_tw(H);
   unsigned char *stg = reinterpret_cast<unsigned char *>(lines + RPW * LL);
   __shared__ double s_par[2];
 
@@ -214,6 +216,9 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     const int k = tid + u * NT;
     if (k < 2 * H) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
   }
+  constexpr int NSR = (stage_tw_len(H, E) + NT - 1) / NT;
+  C tsr[NSR > 0 ? NSR : 1];
+  stage_tw_issue<H, E>(tsr, a.tw, a.lmax_log, tid, NT);
   C tl[Tile::NREG];
   if constexpr (LOADS_TILE) tile_issue<FULL>(tile, tid, tl);
   // pointwise operands of this thread's columns c = 2(t + P j) + e
@@ -370,6 +375,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     const int k = tid + u * NT;
     if (k < 2 * H) twl[k] = twr[u];
   }
+  stage_tw_store<H, E>(tsr, tws, tid, NT);
   if constexpr (LOADS_TILE) tile_to_lds<FULL>(tile, tid, tl, lines);
   if constexpr (STG) {
 #pragma unroll
@@ -423,11 +429,11 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
       const int c0 = 2 * (t + P * j);
       v[j] = cmake<C>(xl[2 * H - c0], xl[2 * H - c0 - 1]);
     }
-    row_r2c_store<FULL, R, H, E>(v, t, tid, line, lines, twl, tile);
+    row_r2c_store<FULL, R, H, E>(v, t, tid, line, lines, twl, tws, tile);
     return;
   }
 
-  if constexpr (LOADS_TILE) row_c2r<R, H, E>(v, t, line, twl);
+  if constexpr (LOADS_TILE) row_c2r<R, H, E>(v, t, line, twl, tws);
   // the forcing of the next FFT is zero in the padding half (columns >= H)
 #pragma unroll
   for (int j = E / 2; j < E; ++j) v[j] = cmake<C>((R)0, (R)0);
@@ -595,7 +601,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   }
 
   // ---- 6. forward real FFT of the new forcing, store the tile --------------
-  row_r2c_store<FULL, R, H, E>(v, t, tid, line, lines, twl, tile);
+  row_r2c_store<FULL, R, H, E>(v, t, tid, line, lines, twl, tws, tile);
 }
 
 template <typename R, int MODE, int H, int E>

@@ -18,14 +18,14 @@ namespace sweik {
 //            2E = U(k) + conj U(H-1-k), 2iO = U(k) - conj U(H-1-k)
 //            -> returns 2 X(k) = sum_j x(j) exp(-2 pi i j (k + 1/2) / M)
 //   inverse  the same steps backwards; returns 2M times the real line.
-template <typename R, int H, int TWLOG>
+template <typename R, int H>
 __device__ __forceinline__ void odd_r2c(cplx<R> (&v)[16], int t, cplx<R> *line,
-                                        const cplx<R> *twl) {
+                                        const cplx<R> *twl, const cplx<R> *tws) {
   using C = cplx<R>;
   constexpr int P = H / 16;
 #pragma unroll
   for (int j = 0; j < 16; ++j) v[j] = cmul(v[j], twl[2 * (t + P * j)]);
-  team_fft<H, TWLOG, false>(v, t, line, twl, true);
+  team_fft<H, false>(v, t, line, tws, true);
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < 16; ++j) line[lpad(t + P * j)] = v[j];
@@ -41,9 +41,9 @@ __device__ __forceinline__ void odd_r2c(cplx<R> (&v)[16], int t, cplx<R> *line,
   }
 }
 
-template <typename R, int H, int TWLOG>
+template <typename R, int H>
 __device__ __forceinline__ void odd_c2r(cplx<R> (&v)[16], int t, cplx<R> *line,
-                                        const cplx<R> *twl) {
+                                        const cplx<R> *twl, const cplx<R> *tws) {
   using C = cplx<R>;
   constexpr int P = H / 16;
   __syncthreads();
@@ -58,7 +58,7 @@ __device__ __forceinline__ void odd_c2r(cplx<R> (&v)[16], int t, cplx<R> *line,
     const C o = cmulc(csub(v[j], xp), twl[2 * k + 1]);  // 2O
     v[j] = cmake<C>(e.x - o.y, e.y + o.x);              // 2(E + iO)
   }
-  team_fft<H, TWLOG, true>(v, t, line, twl, true);
+  team_fft<H, true>(v, t, line, tws, true);
 #pragma unroll
   for (int j = 0; j < 16; ++j) v[j] = cmulc(v[j], twl[2 * (t + P * j)]);
 }
@@ -71,8 +71,9 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   constexpr int P = H / 16, LPW = x_lpw(H), LL = lds_line_len(H);
   constexpr int TWLOG = ilog2c(4 * H);
   constexpr int NTW = (4 * H + kThreads - 1) / kThreads;
-  C *twl = reinterpret_cast<C *>(smem_raw);
-  C *lines = twl + 4 * H;
+  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i q / 4H), q < 4H
+  C *tws = twl + 4 * H;                      // stage tables of the length-H FFT
+  C *lines = tws + stage_tw_len(H, 16);
   __shared__ double s_par[1];
 
   const int tid = threadIdx.x, team = tid / P, t = tid - team * P;
@@ -93,6 +94,9 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     const int k = tid + u * kThreads;
     if (k < 4 * H) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
   }
+  constexpr int NSR = (stage_tw_len(H, 16) + kThreads - 1) / kThreads;
+  C tsr[NSR > 0 ? NSR : 1];
+  stage_tw_issue<H, 16>(tsr, a.tw, a.lmax_log, tid, kThreads);
   C v[16];
   if constexpr (MODE == X_TERM) {
     const C *sl = a.s1 + (size_t)rs * H;
@@ -202,6 +206,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     const int k = tid + u * kThreads;
     if (k < 4 * H) twl[k] = twr[u];
   }
+  stage_tw_store<H, 16>(tsr, tws, tid, kThreads);
   __syncthreads();
 
   // ---- 3. kernel table -------------------------------------------------------
@@ -225,7 +230,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     }
   }
 
-  if constexpr (MODE == X_TERM) odd_c2r<R, H, TWLOG>(v, t, line, twl);
+  if constexpr (MODE == X_TERM) odd_c2r<R, H>(v, t, line, twl, tws);
 
   // ---- 4. pointwise step -------------------------------------------------------
   if constexpr (MODE == X_PHI0 || MODE == X_TERM) {
@@ -322,7 +327,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   }
 
   // ---- 5. forward real FFT, store the line's spectrum ------------------------
-  odd_r2c<R, H, TWLOG>(v, t, line, twl);
+  odd_r2c<R, H>(v, t, line, twl, tws);
   if (line_ok) {
     C *sl = a.s1 + (size_t)rs * H;
 #pragma unroll
