@@ -205,8 +205,8 @@ sweik_status sweik_batch_solve_graph(sweik_batch batch, const void *const *f,
  * A schedule fixes, per pass family, the FFT radix and the work-group shape:
  * E elements per team thread, i.e. radix-E Stockham stages and 4096/E
  * threads per work-group (the rows or columns per work-group do not change).
- *   row_e  2D row passes (all modes): 16 or 8
- *   col_e  2D column passes (all modes): 16 or 8
+ *   row_e  2D row passes (all modes): 16, 8, or 4 (float32 only)
+ *   col_e  2D column passes (all modes): 16, 8, or 4 (float32 only)
  * 3D plans have the single schedule {16, 16}.  New plans take the entries of
  * the process-wide table filled by sweik_autotune (default 16). */
 typedef struct {
@@ -215,21 +215,22 @@ typedef struct {
 } sweik_schedule;
 
 sweik_status sweik_plan_get_schedule(sweik_plan plan, sweik_schedule *out);
-/* SWEIK_EINVAL for a value other than 16 or 8; SWEIK_EUNSUPPORTED for a 3D
- * plan with a value other than 16.  Host only.  Not to be called while a
+/* SWEIK_EINVAL for a value other than 16, 8 or 4; SWEIK_EUNSUPPORTED for 4
+ * in a float64 plan or a 3D plan with a value other than 16.  Host only.  Not to be called while a
  * solve with this plan is being enqueued on another thread. */
 sweik_status sweik_plan_set_schedule(sweik_plan plan, const sweik_schedule *s);
 
 /* Times every candidate schedule of the 2D per-term passes with HIP events
- * on `stream`: each (col_e, row_e) pair as 4 back-to-back [column
+ * on `stream` (radix 16, 8 and, in float32, 4): each (col_e, row_e) pair
+ * as 4 back-to-back [column
  * convolution; row pass] launches, 3 times, keeping the median (with T < 2
  * only the column pass is timed).  Works on the workspace `ws`, whose
  * contents are overwritten: run it before a solve, not between a solve and
  * its adjoint.  Keeps the fastest in the plan and in the process-wide table
  * keyed by (pass, length, precision) that later plans start from.
- * Synchronises the stream.  Returns the number of schedules timed (4, or 2
- * when T < 2; 0 for 3D plans; negative on a HIP error or a too-small
- * workspace). */
+ * Synchronises the stream.  Returns the number of schedules timed (9 in
+ * float32, 4 in float64; 3 or 2 when T < 2; 0 for 3D plans; negative on a
+ * HIP error or a too-small workspace). */
 int32_t sweik_autotune(sweik_plan plan, void *ws, size_t ws_bytes,
                        void *stream);
 

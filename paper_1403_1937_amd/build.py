@@ -9,7 +9,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libsweik.so")
 SOURCES = [os.path.join(HERE, "csrc", n) for n in (
-    "api.hip", "k2d_row16_f32.hip", "k2d_row8_f32.hip", "k2d_col_f32.hip",
+    "api.hip", "k2d_row16_f32.hip", "k2d_row8_f32.hip", "k2d_row4_f32.hip", "k2d_col_f32.hip",
+    "k2d_col4_f32.hip",
     "k2d_row16_f64.hip", "k2d_row8_f64.hip", "k2d_col_f64.hip", "k3d_f32.hip", "k3d_f64.hip")]
 
 HIPCC_FLAGS = [

@@ -664,12 +664,14 @@ template <typename R> int32_t autotune2d(sweik_plan_s *pl, void *ws, hipStream_t
   // it runs in a solve (row pass of term 1, which is not the last term and so
   // writes no output; without two terms only the column pass is timed)
   const bool rows = pl->p.T >= 2;
-  const int cand[2] = {16, 8};
+  const int cand[3] = {16, 8, 4};
+  const int ncand = pl->p.prec == SWEIK_F64 ? 2 : 3;  // radix 4: float32 only
   int timed = 0, bc = g.ecol, br = g.erow;
   float best = 0.0f;
-  for (int ec : cand) {
-    for (int er : cand) {
-      if (!rows && er != cand[0]) continue;
+  for (int ic = 0; ic < ncand; ++ic) {
+    for (int ir = 0; ir < ncand; ++ir) {
+      const int ec = cand[ic], er = cand[ir];
+      if (!rows && ir != 0) continue;
       if (rows && g.H1 < er) continue;
       bool ok = true;
       float t[3];
@@ -953,8 +955,9 @@ sweik_status sweik_plan_get_schedule(sweik_plan plan, sweik_schedule *out) {
 
 sweik_status sweik_plan_set_schedule(sweik_plan plan, const sweik_schedule *sc) {
   if (!plan || !sc) return SWEIK_EINVAL;
-  auto ok = [](int e) { return e == 16 || e == 8; };
+  auto ok = [](int e) { return e == 16 || e == 8 || e == 4; };
   if (!ok(sc->row_e) || !ok(sc->col_e)) return SWEIK_EINVAL;
+  if (plan->p.prec == SWEIK_F64 && (sc->row_e == 4 || sc->col_e == 4)) return SWEIK_EUNSUPPORTED;
   if (plan->p.ndim == 3 && (sc->row_e != 16 || sc->col_e != 16)) return SWEIK_EUNSUPPORTED;
   if (plan->p.ndim == 2) {
     const int H = plan->g2.H1;

@@ -235,7 +235,7 @@ template <int L, bool INV, int E, typename C>
 __device__ __forceinline__ void team_fft(C (&v)[E], int t, C *lds, const C *tws,
                                          bool lead_sync = true) {
   static_assert(L >= E && L <= 4096 && (L & (L - 1)) == 0, "line length");
-  static_assert(E == 8 || E == 16, "elements per thread");
+  static_assert(E == 4 || E == 8 || E == 16, "elements per thread");
   if (lead_sync) __syncthreads();
   team_stages<L, INV, E, 1>(v, t, lds, tws);
 }

@@ -33,7 +33,9 @@ constexpr size_t kLdsDevice = 163840;  // gfx950 limit per work-group
 // row, and (when it fits) staging rows for the pointwise operands so that
 // their loads are issued with the spectrum's.
 constexpr int row_stage_tw(int H) {
-  return stage_tw_len(H, 8) > stage_tw_len(H, 16) ? stage_tw_len(H, 8) : stage_tw_len(H, 16);
+  int n = stage_tw_len(H, 16);
+  n = stage_tw_len(H, 8) > n ? stage_tw_len(H, 8) : n;
+  return stage_tw_len(H, 4) > n ? stage_tw_len(H, 4) : n;
 }
 template <typename R> constexpr size_t row_lds_core(int H) {
   return sizeof(R) * 2 *

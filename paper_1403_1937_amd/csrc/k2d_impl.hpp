@@ -182,6 +182,11 @@ template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream
   template hipError_t launch_row2_batch_e<R, E>(int, int, int, hipStream_t,                 \
                                                 const BatchItem<R> *, int, int);
 
+#define SWEIK_INSTANTIATE_2D_COLS_E(R, E)                                                   \
+  template hipError_t launch_col2_e<R, E>(int, int, dim3, hipStream_t, const Args2<R> &);   \
+  template hipError_t launch_col2_batch_e<R, E>(int, int, int, hipStream_t,                 \
+                                                const BatchItem<R> *, int);
+
 #define SWEIK_INSTANTIATE_2D_COLS(R)                                                        \
   template hipError_t launch_col2_e<R, 16>(int, int, dim3, hipStream_t, const Args2<R> &);  \
   template hipError_t launch_col2_e<R, 8>(int, int, dim3, hipStream_t, const Args2<R> &);   \

@@ -30,13 +30,46 @@ template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream
 template <typename R>
 hipError_t launch_prep_batch(int nitems, hipStream_t st, const BatchItem<R> *items);
 
-// schedule dispatch: E = 16 (radix-16 stages, 256 threads per work-group)
-// or 8 (radix-8 stages, 512 threads)
+// schedule dispatch: E = 16 (radix-16 stages, 256 threads per work-group),
+// 8 (radix-8 stages, 512 threads) or, in float32 only, 4 (radix-4 stages,
+// 1024 threads)
+template <typename R> struct RadixFour {
+  static hipError_t row(int, int, dim3, hipStream_t, const Args2<R> &, int) {
+    return hipErrorInvalidValue;
+  }
+  static hipError_t col(int, int, dim3, hipStream_t, const Args2<R> &) {
+    return hipErrorInvalidValue;
+  }
+  static hipError_t row_batch(int, int, int, hipStream_t, const BatchItem<R> *, int, int) {
+    return hipErrorInvalidValue;
+  }
+  static hipError_t col_batch(int, int, int, hipStream_t, const BatchItem<R> *, int) {
+    return hipErrorInvalidValue;
+  }
+};
+template <> struct RadixFour<float> {
+  static hipError_t row(int mode, int H, dim3 g, hipStream_t st, const Args2<float> &a, int term) {
+    return launch_row2_e<float, 4>(mode, H, g, st, a, term);
+  }
+  static hipError_t col(int mode, int M0, dim3 g, hipStream_t st, const Args2<float> &a) {
+    return launch_col2_e<float, 4>(mode, M0, g, st, a);
+  }
+  static hipError_t row_batch(int mode, int H, int nb, hipStream_t st,
+                              const BatchItem<float> *items, int n, int term) {
+    return launch_row2_batch_e<float, 4>(mode, H, nb, st, items, n, term);
+  }
+  static hipError_t col_batch(int mode, int M0, int nb, hipStream_t st,
+                              const BatchItem<float> *items, int n) {
+    return launch_col2_batch_e<float, 4>(mode, M0, nb, st, items, n);
+  }
+};
+
 template <typename R>
 inline hipError_t launch_row2(int mode, int H, int E, dim3 grid, hipStream_t st,
                               const Args2<R> &a, int term) {
   return E == 16  ? launch_row2_e<R, 16>(mode, H, grid, st, a, term)
          : E == 8 ? launch_row2_e<R, 8>(mode, H, grid, st, a, term)
+         : E == 4 ? RadixFour<R>::row(mode, H, grid, st, a, term)
                   : hipErrorInvalidValue;
 }
 template <typename R>
@@ -44,6 +77,7 @@ inline hipError_t launch_col2(int mode, int M0, int E, dim3 grid, hipStream_t st
                               const Args2<R> &a) {
   return E == 16  ? launch_col2_e<R, 16>(mode, M0, grid, st, a)
          : E == 8 ? launch_col2_e<R, 8>(mode, M0, grid, st, a)
+         : E == 4 ? RadixFour<R>::col(mode, M0, grid, st, a)
                   : hipErrorInvalidValue;
 }
 template <typename R>
@@ -51,6 +85,7 @@ inline hipError_t launch_row2_batch(int mode, int H, int E, int nblocks, hipStre
                                     const BatchItem<R> *items, int nitems, int term) {
   return E == 16  ? launch_row2_batch_e<R, 16>(mode, H, nblocks, st, items, nitems, term)
          : E == 8 ? launch_row2_batch_e<R, 8>(mode, H, nblocks, st, items, nitems, term)
+         : E == 4 ? RadixFour<R>::row_batch(mode, H, nblocks, st, items, nitems, term)
                   : hipErrorInvalidValue;
 }
 template <typename R>
@@ -58,6 +93,7 @@ inline hipError_t launch_col2_batch(int mode, int M0, int E, int nblocks, hipStr
                                     const BatchItem<R> *items, int nitems) {
   return E == 16  ? launch_col2_batch_e<R, 16>(mode, M0, nblocks, st, items, nitems)
          : E == 8 ? launch_col2_batch_e<R, 8>(mode, M0, nblocks, st, items, nitems)
+         : E == 4 ? RadixFour<R>::col_batch(mode, M0, nblocks, st, items, nitems)
                   : hipErrorInvalidValue;
 }
 
