@@ -40,7 +40,7 @@
 
 namespace sweik {
 
-constexpr int kRedBlocks = 256;  // partial reductions of f
+constexpr int kRedBlocks = 1024;  // partial reductions of f (work-groups of the prep)
 
 struct Params {      // device-side scalars shared by the kernels of a solve
   double ftilde, beta, hbar, inv_ft2, kappa0, fmin, fmax, c0;
@@ -88,6 +88,17 @@ template <typename R> struct Args2 {
 // prep: partial min / max / validity of f, and the twiddle table
 // ---------------------------------------------------------------------------
 template <typename R>
+__device__ __forceinline__ void prep_fold(double v, double &lo, double &hi, int &fl) {
+  if (!isfinite(v)) {
+    fl |= SWEIK_FLAG_F_NONFINITE;
+    return;
+  }
+  if (!(v > 0.0)) fl |= SWEIK_FLAG_F_NONPOSITIVE;
+  lo = v < lo ? v : lo;
+  hi = v > hi ? v : hi;
+}
+
+template <typename R>
 __device__ __forceinline__ void prep_block(const R *__restrict__ f, long long N,
                                            double *__restrict__ red, cplx<R> *__restrict__ tw,
                                            int lmax, int bid, int nblk) {
@@ -96,16 +107,29 @@ __device__ __forceinline__ void prep_block(const R *__restrict__ f, long long N,
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
   int fl = 0;
-  for (long long i = (long long)bid * blockDim.x + threadIdx.x; i < N;
-       i += (long long)nblk * blockDim.x) {
-    const double v = (double)f[i];
-    if (!isfinite(v)) {
-      fl |= SWEIK_FLAG_F_NONFINITE;
-      continue;
+  // pairs of consecutive values (vector loads when f is aligned to a pair),
+  // four pairs in flight per thread and iteration; then the tail
+  using V = cplx<R>;  // two R
+  const long long G = N / 2, stride = (long long)nblk * blockDim.x;
+  const long long g0 = (long long)bid * blockDim.x + threadIdx.x;
+  if ((reinterpret_cast<uintptr_t>(f) & (sizeof(V) - 1)) == 0) {
+    const V *f2 = reinterpret_cast<const V *>(f);
+    for (long long g = g0; g < G; g += 4 * stride) {
+      V x[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long long gu = g + u * stride;
+        x[u] = f2[gu < G ? gu : g];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        prep_fold<R>((double)x[u].x, lo, hi, fl);
+        prep_fold<R>((double)x[u].y, lo, hi, fl);
+      }
     }
-    if (!(v > 0.0)) fl |= SWEIK_FLAG_F_NONPOSITIVE;
-    lo = v < lo ? v : lo;
-    hi = v > hi ? v : hi;
+    for (long long i = 2 * G + g0; i < N; i += stride) prep_fold<R>((double)f[i], lo, hi, fl);
+  } else {
+    for (long long i = g0; i < N; i += stride) prep_fold<R>((double)f[i], lo, hi, fl);
   }
   lo = wave_min(lo);
   hi = wave_max(hi);

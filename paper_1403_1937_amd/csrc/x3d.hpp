@@ -218,9 +218,9 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     const int M2 = 2 * H;
     auto tab = [&](int c) -> R {
       if (!line_ok) return (R)0;
-      if (c < a.n2) return (R)kappa_3d(beta, r01 + (long long)c * c, k0v);
+      if (c < a.n2) return kappa_3d_t<R>(beta, r01 + (long long)c * c, k0v);
       const int d = M2 - c;
-      if (d < a.n2) return (R)(-kappa_3d(beta, r01 + (long long)d * d, k0v));
+      if (d < a.n2) return -kappa_3d_t<R>(beta, r01 + (long long)d * d, k0v);
       return (R)0;
     };
 #pragma unroll
