@@ -71,29 +71,29 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def alg_bytes_2d(n0, n1, H1, H0, esz, ckpt=False):
+def alg_bytes_2d(n0, n1, H1, H0, esz, T, ckpt=False):
     """Algorithmic HBM bytes per kernel class of a 2D forward solve: every
     pass reads its inputs once and writes its outputs once at the stored
     precision; the spectrum is the n0 x H1 half spectrum (the real DC and
     Nyquist bins share a column), the kernel spectrum the (H1+1) x (H0+1)
-    orthant.  With checkpoints the forward also stores phi_0..phi_{T-1}
-    (esz N each) and phi (8 N)."""
+    orthant.  Each term's mantissas are stored once (into the checkpoint when
+    one is kept) and the last pass sums the T stored terms in float64; with a
+    checkpoint it also writes phi (8 N)."""
     N = n0 * n1
     spec = 2 * esz * n0 * H1
     ghat = esz * (H1 + 1) * (H0 + 1)
-    ck = esz * N if ckpt else 0
     return {
         "prep": esz * N,
         "ghat_row": spec,
         "ghat_col": spec + ghat,
-        "phi0_row": 2 * esz * N + 8 * N + spec + ck,        # f in; acc, gamma, spectrum out
+        "phi0_row": 3 * esz * N + spec,                      # f in; gamma, phi_0, spectrum out
         "conv_col": 2 * spec + ghat,
-        "term_row": 2 * spec + esz * N + 16 * N + ck,        # spec in/out, gamma, acc RMW
-        "last_row": spec + 8 * N + esz * N + (8 * N if ckpt else 0),
+        "term_row": 2 * spec + 2 * esz * N,                  # spectrum in/out, gamma, term out
+        "last_row": spec + T * esz * N + esz * N + (8 * N if ckpt else 0),
     }
 
 
-def alg_bytes_3d(dims, padded, esz):
+def alg_bytes_3d(dims, padded, esz, T):
     """Algorithmic bytes per kernel class of a 3D forward solve (same rule):
     s1 = n0 n1 H2 and s2 = n0 M1 H2 complex spectra, the kernel spectrum
     (H1+1)(H0+1)H2 real."""
@@ -111,12 +111,12 @@ def alg_bytes_3d(dims, padded, esz):
         "ghat_row": s1,
         "ghat_col": s1 + s2g,
         "ghat_z": s2g + g,
-        "phi0_row": 2 * esz * N + 8 * N + s1,
+        "phi0_row": 3 * esz * N + s1,
         "y_fwd": s1 + s2,
         "conv_col": 2 * s2 + g,
         "y_inv": s2 + s1,
-        "term_row": 2 * s1 + esz * N + 16 * N,
-        "last_row": s1 + 8 * N + esz * N,
+        "term_row": 2 * s1 + 2 * esz * N,
+        "last_row": s1 + T * esz * N + esz * N,
     }
 
 
@@ -193,10 +193,10 @@ def run_main(pk, torch, dev, p, precision, steps, warmup):
             a[1] += c
     esz = 4 if precision == "fp32" else 8
     if len(p.dims) == 3:
-        ab = alg_bytes_3d(p.dims, plan.padded, esz)
+        ab = alg_bytes_3d(p.dims, plan.padded, esz, p.T)
     else:
         H1, H0 = plan.padded[1] // 2, plan.padded[0] // 2
-        ab = alg_bytes_2d(n0, n1, H1, H0, esz)
+        ab = alg_bytes_2d(n0, n1, H1, H0, esz, p.T)
     kern = {}
     for k, (m, c) in acc.items():
         if c == 0:
@@ -276,7 +276,7 @@ def run_fwd_bwd(pk, torch, dev, steps, warmup):
     torch.cuda.synchronize()
     ms_fwd = e0.elapsed_time(e1) / steps
     H1, H0 = plan.padded[1] // 2, plan.padded[0] // 2
-    ab = alg_bytes_2d(n0, n1, H1, H0, 4, ckpt=True)
+    ab = alg_bytes_2d(n0, n1, H1, H0, 4, p.T, ckpt=True)
     fwd_bytes = (ab["prep"] + ab["ghat_row"] + ab["ghat_col"] + ab["phi0_row"]
                  + p.T * ab["conv_col"] + (p.T - 1) * ab["term_row"] + ab["last_row"])
     bwd_bytes = alg_bytes_adjoint_2d(n0, n1, H1, H0, 4, p.T)
@@ -330,7 +330,7 @@ def run_batched(pk, torch, dev, steps, warmup):
         n0, n1 = q.dims
         M0 = max(64, 1 << int(np.ceil(np.log2(2 * n0 - 1))))
         M1 = max(64, 1 << int(np.ceil(np.log2(2 * n1 - 1))))
-        ab = alg_bytes_2d(n0, n1, M1 // 2, M0 // 2, 4)
+        ab = alg_bytes_2d(n0, n1, M1 // 2, M0 // 2, 4, T)
         total += (ab["prep"] + ab["ghat_row"] + ab["ghat_col"] + ab["phi0_row"]
                   + T * ab["conv_col"] + (T - 1) * ab["term_row"] + ab["last_row"])
     sizes = {}

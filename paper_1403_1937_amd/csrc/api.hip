@@ -178,6 +178,7 @@ sweik_status plan2d(sweik_plan_s *pl) {
   L.g = take((size_t)esz * (g.ldk + 1) * g.ldg);
   L.spec = take((size_t)csz * g.nb * g.ldk * g.RB);
   L.acc = take(sizeof(double) * N);
+  L.terms = take((size_t)esz * N * (size_t)p.T);
   L.lam = take((size_t)esz * N);
   L.gam = take((size_t)esz * N);
   L.total = off;
@@ -241,6 +242,8 @@ Args2<R> make_args2(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.ck_expo = c ? (int *)(c + L.ck_expo) : nullptr;
   a.ck_phi = c ? (double *)(c + L.ck_phi) : nullptr;
   a.ck_terms = c ? (R *)(c + L.ck_terms) : nullptr;
+  // the forward stores its terms in the checkpoint when one is kept
+  a.terms = c ? a.ck_terms : (R *)(w + L.terms);
   return a;
 }
 
@@ -368,7 +371,8 @@ sweik_status plan3d(sweik_plan_s *pl) {
   L.g = take((size_t)esz * (g.H1 + 1) * (g.H0 + 1) * g.H2);
   L.spec = take((size_t)csz * g.nlines * g.H2);
   L.s2 = take((size_t)csz * g.n0 * g.M1 * g.H2);
-  L.acc = take(sizeof(double) * N);
+  L.acc = 0;
+  L.terms = take((size_t)esz * N * (size_t)p.T);
   L.gam = take((size_t)esz * N);
   L.lam = 0;
   L.total = off;
@@ -414,7 +418,7 @@ Args3<R> make_args3(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.s1 = (cplx<R> *)(w + L.spec);
   a.s2 = (cplx<R> *)(w + L.s2);
   a.g = (R *)(w + L.g);
-  a.acc = (double *)(w + L.acc);
+  a.terms = (R *)(w + L.terms);
   a.gam = (R *)(w + L.gam);
   a.info = info;
   return a;

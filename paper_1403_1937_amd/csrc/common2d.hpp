@@ -70,7 +70,8 @@ template <typename R> struct Args2 {
   const cplx<R> *tw;
   cplx<R> *spec;
   R *g;          // (H1+1) x (H0+1) kernel spectrum orthant, pre-scaled
-  double *acc;   // n0 x n1
+  double *acc;   // n0 x n1 adjoint accumulator of dL/dgamma
+  R *terms;      // T x n0 x n1 mantissas of phi_0..phi_{T-1} (the checkpoint's when kept)
   R *gam;        // n0 x n1 gamma = f^2/ftilde^2 - 1
   ChebK0 k0tab;  // K0 for x > 2
   // adjoint
@@ -81,7 +82,7 @@ template <typename R> struct Args2 {
   sweik_info *info;
   int *ck_expo;  // T+1
   double *ck_phi;// n0 x n1
-  R *ck_terms;   // T x n0 x n1 series-term mantissas
+  R *ck_terms;   // T x n0 x n1 series-term mantissas (read by the adjoint)
 };
 
 // ---------------------------------------------------------------------------

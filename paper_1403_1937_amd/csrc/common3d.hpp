@@ -4,8 +4,9 @@
 // powers of two, Hd = Md / 2).  One correction term (Table 1, steps 9-13)
 // is four passes over two spectra:
 //   x pass   (axis 2, contiguous) per grid line (i0, i1): inverse real FFT
-//            of the previous term, crop, rescale, accumulate, form gamma *
-//            phi_i, forward real FFT -> s1[i0][i1][k2]      (n0 n1 H2 complex)
+//            of the previous term, crop, rescale, store the term, form
+//            gamma * phi_i, forward real FFT -> s1[i0][i1][k2] (n0 n1 H2
+//            complex); the last one sums the stored terms in float64
 //   y fwd    (axis 1) per (i0, k2): FFT of the n1 rows zero-padded to M1
 //            -> s2[i0][k1][k2]                              (n0 M1 H2 complex)
 //   z conv   (axis 0) per (k1, k2): FFT of the n0 rows zero-padded to M0,
@@ -67,7 +68,7 @@ template <typename R> struct Args3 {
   const cplx<R> *tw;
   cplx<R> *s1, *s2;
   R *g;            // kernel spectrum orthant
-  double *acc;     // N
+  R *terms;        // T x N mantissas of phi_0..phi_{T-1}
   R *gam;          // N
   sweik_info *info;
 };

@@ -42,11 +42,11 @@ template <typename R> constexpr size_t row_lds_core(int H) {
          ((size_t)2 * H + (size_t)row_stage_tw(H) + (size_t)row_rpw(H) * lds_line_len(H));
 }
 template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
-  // per staged row: gamma (R) + accumulator (double) for the forward terms;
-  // previous term, gamma or f, lambda (R) + gradient (double) for the adjoint
+  // per staged row: gamma (R) for the forward terms (f for phi_0); previous
+  // term, gamma or f, lambda (R) + gradient (double) for the adjoint
   return (size_t)row_rpw(H) * H *
-         (mode == ROW_TERM ? sizeof(R) + 8 : mode == ROW_PHI0 ? sizeof(R)
-                                           : mode == ROW_ADJ ? 3 * sizeof(R) + 8 : 0);
+         (mode == ROW_TERM || mode == ROW_PHI0 ? sizeof(R)
+                                               : mode == ROW_ADJ ? 3 * sizeof(R) + 8 : 0);
 }
 template <typename R> constexpr bool row_staged(int H, int mode) {
   return row_stage_bytes<R>(H, mode) > 0 &&

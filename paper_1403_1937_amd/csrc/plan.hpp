@@ -30,7 +30,7 @@ struct Geo3 {
 };
 
 struct Layout {      // byte offsets into the workspace / checkpoint
-  size_t par, red, expo, mu, mu_red, tw, g, spec, s2, acc, lam, gam, total;
+  size_t par, red, expo, mu, mu_red, tw, g, spec, s2, acc, terms, lam, gam, total;
   size_t ck_expo, ck_par, ck_g, ck_phi, ck_terms, ck_total;
 };
 

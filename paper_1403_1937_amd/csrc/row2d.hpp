@@ -165,8 +165,9 @@ __device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[E], int t, int tid,
 // Row pass, all modes.
 //   ROW_GHAT  kernel table rows (evenly extended), forward real FFT
 //   ROW_PHI0  phi_0 from the sources, first forcing term, forward real FFT
-//   ROW_TERM  term `term`: inverse FFT, rescale, accumulate; then either the
-//             next forcing term and its FFT, or (term == T) S = -hbar ln phi
+//   ROW_TERM  term `term`: inverse FFT, rescale, store the term; then either
+//             the next forcing term and its FFT, or (term == T) the sum of
+//             all terms in float64 and S = -hbar ln phi
 //   ROW_ADJ0  adjoint start: lambda = -hbar dL/dS / phi, a_T = (-1)^T lambda
 //   ROW_ADJ   adjoint step `term` = i: b_i = kappa (*) a_i, dL/dgamma +=
 //             phi_{i-1} b_i, a_{i-1} = (-1)^{i-1} lambda + gamma b_i; at
@@ -229,10 +230,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     const R *p1 = nullptr, *p2 = nullptr, *p3 = nullptr;
     const double *pd = nullptr;
     if (MODE == ROW_PHI0) p1 = last ? nullptr : a.f;
-    if (MODE == ROW_TERM) {
-      p1 = last ? nullptr : a.gam;
-      pd = a.acc;
-    }
+    if (MODE == ROW_TERM) p1 = last ? nullptr : a.gam;
     if (MODE == ROW_ADJ) {
       p1 = a.ck_terms + (size_t)(term - 1) * N;
       p2 = term > 1 ? a.gam : a.f;
@@ -345,6 +343,11 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     if (a.info) a.info->scale_exp[slot] = Ei;
     if (a.ck_expo) a.ck_expo[slot] = Ei;
   }
+  // last term: signed scales (-1)^i 2^E_i of the stored terms (read after
+  // the barrier below)
+  __shared__ double s_sE[MODE == ROW_TERM ? SWEIK_MAX_TERMS + 1 : 1];
+  if (MODE == ROW_TERM && term == a.T)
+    for (int i = tid; i < a.T; i += NT) s_sE[i] = ((i & 1) ? -1.0 : 1.0) * ldexp(1.0, a.expo[i]);
   if (MODE == ROW_ADJ0) {
     double mx = 0.0;
     for (int i = tid; i < kRedBlocks; i += NT) mx = fmax(mx, a.red[i]);
@@ -446,7 +449,48 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     const double sE = ((MODE == ROW_TERM && (term & 1)) ? -1.0 : 1.0) * ldexp(1.0, Ei);
     R mlr = (R)0;
     const int slot = MODE == ROW_TERM ? term : 0;
-    R *ckt = a.ck_terms ? a.ck_terms + (size_t)slot * N + rowoff : nullptr;
+    R *tout = a.terms + (size_t)slot * N + rowoff;  // this term's mantissas
+    // last term: the float64 sum of the stored terms 0..T-1 at this thread's
+    // columns, in the order of the terms (as a running accumulation would)
+    double ps[E];
+    if (MODE == ROW_TERM && last) {
+      using V = cplx<R>;
+      auto pair = [&](const R *q, int c0) -> V {
+        V x = cmake<V>((R)0, (R)0);
+        if (!col_ok(c0)) return x;
+        if (even_n1) return *reinterpret_cast<const V *>(q + c0);
+        x.x = q[c0];
+        if (FULL || c0 + 1 < a.n1) x.y = q[c0 + 1];
+        return x;
+      };
+      const R *t0 = a.terms + rowoff;
+#pragma unroll
+      for (int j = 0; j < E / 2; ++j) {
+        const V x = pair(t0, 2 * (t + P * j));
+        ps[2 * j] = (double)x.x;
+        ps[2 * j + 1] = (double)x.y;
+      }
+      for (int i0 = 1; i0 < a.T; i0 += 4) {  // four terms of loads in flight
+        V q[4][E / 2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i0 + u < a.T) {
+#pragma unroll
+            for (int j = 0; j < E / 2; ++j)
+              q[u][j] = pair(a.terms + (size_t)(i0 + u) * N + rowoff, 2 * (t + P * j));
+          }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i0 + u < a.T) {
+            const double sc = s_sE[i0 + u];
+#pragma unroll
+            for (int j = 0; j < E / 2; ++j) {
+              ps[2 * j] = fma((double)q[u][j].x, sc, ps[2 * j]);
+              ps[2 * j + 1] = fma((double)q[u][j].y, sc, ps[2 * j + 1]);
+            }
+          }
+      }
+    }
 #pragma unroll
     for (int j = 0; j < E / 2; ++j) {
       const int c0 = 2 * (t + P * j);
@@ -489,8 +533,8 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
         } else {
           m0 = v[j].x * sm;  // power-of-two rescale: exact
           m1 = v[j].y * sm;
-          p0 = fma((double)m0, sE, opd(c0, a.acc));
-          p1 = ok1 ? fma((double)m1, sE, opd(c0 + 1, a.acc)) : 0.0;
+          p0 = last ? fma((double)m0, sE, ps[2 * j]) : 0.0;
+          p1 = (last && ok1) ? fma((double)m1, sE, ps[2 * j + 1]) : 0.0;
         }
         if (last) {
           nbad += write_S(a, rowoff + c0, p0);
@@ -500,15 +544,13 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
             if (a.ck_phi) a.ck_phi[rowoff + c0 + 1] = p1;
           }
         } else {
+          (void)p0;
+          (void)p1;
           if (even_n1)
-            *reinterpret_cast<double2 *>(a.acc + rowoff + c0) = make_double2(p0, p1);
+            *reinterpret_cast<cplx<R> *>(tout + c0) = cmake<cplx<R>>(m0, m1);
           else {
-            a.acc[rowoff + c0] = p0;
-            if (ok1) a.acc[rowoff + c0 + 1] = p1;
-          }
-          if (ckt) {
-            ckt[c0] = m0;
-            if (ok1) ckt[c0 + 1] = m1;
+            tout[c0] = m0;
+            if (ok1) tout[c0 + 1] = m1;
           }
           // gamma = f^2/ftilde^2 - 1 (exactly 0 where f = ftilde); the
           // first pass forms it from f and keeps it for the later ones

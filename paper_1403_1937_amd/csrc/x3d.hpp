@@ -3,8 +3,9 @@
 //           also reduces f into the reference forcing and publishes it
 //   X_PHI0  phi_0 from the sources (eq. phi_0Solution), first forcing term,
 //           forward real FFT
-//   X_TERM  term `term`: inverse real FFT, rescale, accumulate; then the next
-//           forcing term and its FFT, or (term == T) S = -hbar ln phi
+//   X_TERM  term `term`: inverse real FFT, rescale, store the term; then the
+//           next forcing term and its FFT, or (term == T) the float64 sum of
+//           all terms and S = -hbar ln phi
 #pragma once
 
 #include "common3d.hpp"
@@ -109,7 +110,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   double od[16];
   if constexpr (MODE == X_TERM || MODE == X_PHI0) {
     const R *p1 = last ? nullptr : (MODE == X_PHI0 ? a.f : a.gam);
-    const double *pd = MODE == X_TERM ? a.acc : nullptr;
+    const double *pd = nullptr;  // no operand in float64
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int c0 = 2 * (t + P * j);
@@ -196,6 +197,10 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     a.expo[slot] = E;
     if (a.info) a.info->scale_exp[slot] = E;
   }
+  // last term: signed scales (-1)^i 2^E_i of the stored terms
+  __shared__ double s_sE[MODE == X_TERM ? SWEIK_MAX_TERMS + 1 : 1];
+  if (MODE == X_TERM && term == a.T)
+    for (int i = tid; i < a.T; i += kThreads) s_sE[i] = ((i & 1) ? -1.0 : 1.0) * ldexp(1.0, a.expo[i]);
   constexpr int kSrcLds = MODE == X_PHI0 ? 512 : 1;
   __shared__ int s_src[3 * kSrcLds];
   if (MODE == X_PHI0)
@@ -238,6 +243,48 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     const R sm = (R)ldexp(1.0, -dstep);
     const double sE = ((MODE == X_TERM && (term & 1)) ? -1.0 : 1.0) * ldexp(1.0, E);
     R mlr = (R)0;
+    R *tout = a.terms + (size_t)(MODE == X_TERM ? term : 0) * ((size_t)a.nlines * a.n2) + rowoff;
+    // last term: the float64 sum of the stored terms 0..T-1 at this thread's
+    // columns, in the order of the terms
+    double ps[16];
+    if (MODE == X_TERM && last) {
+      using V = cplx<R>;
+      const size_t NN = (size_t)a.nlines * a.n2;
+      auto pair = [&](const R *q, int c0) -> V {
+        V x = cmake<V>((R)0, (R)0);
+        if (!col_ok(c0)) return x;
+        if (vec) return *reinterpret_cast<const V *>(q + c0);
+        x.x = q[c0];
+        if (FULL || c0 + 1 < a.n2) x.y = q[c0 + 1];
+        return x;
+      };
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const V x = pair(a.terms + rowoff, 2 * (t + P * j));
+        ps[2 * j] = (double)x.x;
+        ps[2 * j + 1] = (double)x.y;
+      }
+      for (int i0 = 1; i0 < a.T; i0 += 4) {  // four terms of loads in flight
+        V q[4][8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i0 + u < a.T) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+              q[u][j] = pair(a.terms + (size_t)(i0 + u) * NN + rowoff, 2 * (t + P * j));
+          }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (i0 + u < a.T) {
+            const double sc = s_sE[i0 + u];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              ps[2 * j] = fma((double)q[u][j].x, sc, ps[2 * j]);
+              ps[2 * j + 1] = fma((double)q[u][j].y, sc, ps[2 * j + 1]);
+            }
+          }
+      }
+    }
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int c0 = 2 * (t + P * j);
@@ -279,18 +326,18 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
         } else {
           m0 = v[j].x * sm;  // power-of-two rescale: exact
           m1 = v[j].y * sm;
-          p0 = fma((double)m0, sE, od[2 * j]);
-          p1 = ok1 ? fma((double)m1, sE, od[2 * j + 1]) : 0.0;
+          p0 = last ? fma((double)m0, sE, ps[2 * j]) : 0.0;
+          p1 = (last && ok1) ? fma((double)m1, sE, ps[2 * j + 1]) : 0.0;
         }
         if (last) {
           nbad += write_S(a, rowoff + c0, p0);
           if (ok1) nbad += write_S(a, rowoff + c0 + 1, p1);
         } else {
           if (vec)
-            *reinterpret_cast<double2 *>(a.acc + rowoff + c0) = make_double2(p0, p1);
+            *reinterpret_cast<cplx<R> *>(tout + c0) = cmake<cplx<R>>(m0, m1);
           else {
-            a.acc[rowoff + c0] = p0;
-            if (ok1) a.acc[rowoff + c0 + 1] = p1;
+            tout[c0] = m0;
+            if (ok1) tout[c0 + 1] = m1;
           }
           R g0, g1 = (R)0;
           if constexpr (MODE == X_PHI0) {
