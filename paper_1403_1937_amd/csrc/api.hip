@@ -143,11 +143,10 @@ sweik_status plan2d(sweik_plan_s *pl) {
   // every pass must fit the work-group LDS limit
   const bool f64 = p.prec == SWEIK_F64;
   for (int mode = ROW_GHAT; mode <= ROW_ADJ; ++mode) {
-    const size_t b = f64 ? row_lds_bytes<double>(g.H1, mode) : row_lds_bytes<float>(g.H1, mode);
-    if (b > kLdsDevice) return SWEIK_EUNSUPPORTED;
+    if (!(f64 ? row_fits<double>(g.H1, mode) : row_fits<float>(g.H1, mode)))
+      return SWEIK_EUNSUPPORTED;
   }
-  if ((f64 ? col_lds_bytes<double>(g.M0) : col_lds_bytes<float>(g.M0)) > kLdsDevice)
-    return SWEIK_EUNSUPPORTED;
+  if (!(f64 ? col_fits<double>(g.M0) : col_fits<float>(g.M0))) return SWEIK_EUNSUPPORTED;
   g.rpw = row_rpw(g.H1);
   g.cpw = col_cpw(g.M0);
   const int spec_rows = g.nb * g.RB;
@@ -344,7 +343,9 @@ sweik_status plan3d(sweik_plan_s *pl) {
   const size_t xl = f64 ? x_lds_bytes<double>(g.H2) : x_lds_bytes<float>(g.H2);
   const size_t c0 = f64 ? c3_lds_bytes<double>(g.M0) : c3_lds_bytes<float>(g.M0);
   const size_t c1 = f64 ? c3_lds_bytes<double>(g.M1) : c3_lds_bytes<float>(g.M1);
-  if (xl > kLdsDevice || c0 > kLdsDevice || c1 > kLdsDevice) return SWEIK_EUNSUPPORTED;
+  if (xl + x_lds_static(X_PHI0) > kLdsDevice || c0 + kC3LdsStatic > kLdsDevice ||
+      c1 + kC3LdsStatic > kLdsDevice)
+    return SWEIK_EUNSUPPORTED;
   g.nlines = g.n0 * g.n1;
   g.nbx = (g.nlines + x_lpw(g.H2) - 1) / x_lpw(g.H2);
   g.ncb0 = g.H2 / c3_cpw(g.M0);

@@ -45,6 +45,10 @@ template <typename R> constexpr size_t x_lds_bytes(int H) {
 // CPW contiguous spectrum entries per row
 constexpr int c3_cpw(int M) { return 8192 / M < 32 ? 8192 / M : 32; }
 constexpr int c3_threads(int M) { return c3_cpw(M) * (M / 16); }
+// static shared memory of an x pass (reductions, scalars, term scales; phi_0
+// also holds up to 512 sources) and of a column pass
+constexpr size_t x_lds_static(int mode) { return 1536 + (mode == X_PHI0 ? 6144 : 0); }
+constexpr size_t kC3LdsStatic = 512;
 template <typename R> constexpr size_t c3_lds_bytes(int M) {
   return sizeof(R) * 2 * ((size_t)M + (size_t)c3_cpw(M) * lds_line_len(M));
 }

@@ -32,15 +32,19 @@ constexpr size_t kLdsDevice = 163840;  // gfx950 limit per work-group
 // tables of the length-H FFT (room for either schedule), one padded line per
 // row, and (when it fits) staging rows for the pointwise operands so that
 // their loads are issued with the spectrum's.
-constexpr int row_stage_tw(int H) {
+template <typename R> constexpr int row_stage_tw(int H) {
   int n = stage_tw_len(H, 16);
   n = stage_tw_len(H, 8) > n ? stage_tw_len(H, 8) : n;
-  return stage_tw_len(H, 4) > n ? stage_tw_len(H, 4) : n;
+  if (sizeof(R) == 4) n = stage_tw_len(H, 4) > n ? stage_tw_len(H, 4) : n;  // radix 4: float only
+  return n;
 }
 template <typename R> constexpr size_t row_lds_core(int H) {
   return sizeof(R) * 2 *
-         ((size_t)2 * H + (size_t)row_stage_tw(H) + (size_t)row_rpw(H) * lds_line_len(H));
+         ((size_t)2 * H + (size_t)row_stage_tw<R>(H) + (size_t)row_rpw(H) * lds_line_len(H));
 }
+// static shared memory of a row pass (block reductions, scalars, the term
+// scales; phi_0 also holds up to 512 sources)
+constexpr size_t row_lds_static(int mode) { return 1536 + (mode == ROW_PHI0 ? 4096 : 0); }
 template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
   // per staged row: gamma (R) for the forward terms (f for phi_0); previous
   // term, gamma or f, lambda (R) + gradient (double) for the adjoint
@@ -50,15 +54,23 @@ template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
 }
 template <typename R> constexpr bool row_staged(int H, int mode) {
   return row_stage_bytes<R>(H, mode) > 0 &&
-         row_lds_core<R>(H) + row_stage_bytes<R>(H, mode) <= kLdsDevice;
+         row_lds_core<R>(H) + row_stage_bytes<R>(H, mode) + row_lds_static(mode) <= kLdsDevice;
 }
 template <typename R> constexpr size_t row_lds_bytes(int H, int mode) {
   return row_lds_core<R>(H) + (row_staged<R>(H, mode) ? row_stage_bytes<R>(H, mode) : 0);
+}
+// dynamic + static shared memory of a row pass fits a work-group
+template <typename R> constexpr bool row_fits(int H, int mode) {
+  return row_lds_bytes<R>(H, mode) + row_lds_static(mode) <= kLdsDevice;
 }
 // Column pass LDS: twiddle table (M0 entries of exp(-2 pi i k / M0)) and
 // one padded line per column.
 template <typename R> constexpr size_t col_lds_bytes(int M0) {
   return sizeof(R) * 2 * ((size_t)M0 + (size_t)col_cpw(M0) * lds_line_len(M0));
+}
+constexpr size_t kColLdsStatic = 512;  // static shared memory of a column pass
+template <typename R> constexpr bool col_fits(int M0) {
+  return col_lds_bytes<R>(M0) + kColLdsStatic <= kLdsDevice;
 }
 
 }  // namespace sweik

@@ -47,7 +47,7 @@ template <typename K> static hipError_t set_lds(K kernel, size_t bytes) {
 template <typename R, int E, int MODE> struct RowLaunch {
   template <int H> static hipError_t one(dim3 grid, hipStream_t st, const Args2<R> &a, int term) {
     constexpr size_t lds = row_lds_bytes<R>(H, MODE);
-    if constexpr (lds > kLdsDevice || H < E) {  // rejected by the planner
+    if constexpr (!row_fits<R>(H, MODE) || H < E) {  // rejected by the planner
       return hipErrorInvalidValue;
     } else {
       static const hipError_t attr = set_lds(k_row2<R, MODE, H, E>, lds);
@@ -60,7 +60,7 @@ template <typename R, int E, int MODE> struct RowLaunch {
   static hipError_t batch(int nblocks, hipStream_t st, const BatchItem<R> *items, int nitems,
                           int term) {
     constexpr size_t lds = row_lds_bytes<R>(H, MODE);
-    if constexpr (lds > kLdsDevice || H < E) {
+    if constexpr (!row_fits<R>(H, MODE) || H < E) {
       return hipErrorInvalidValue;
     } else {
       static const hipError_t attr = set_lds(k_row2_batch<R, MODE, H, E>, lds);
@@ -105,7 +105,7 @@ hipError_t launch_row2_batch_e(int mode, int H, int nblocks, hipStream_t st,
 template <typename R, int E, int MODE> struct ColLaunch {
   template <int M0> static hipError_t one(dim3 grid, hipStream_t st, const Args2<R> &a) {
     constexpr size_t lds = col_lds_bytes<R>(M0);
-    if constexpr (lds > kLdsDevice) {  // rejected by the planner
+    if constexpr (!col_fits<R>(M0)) {  // rejected by the planner
       return hipErrorInvalidValue;
     } else {
       static const hipError_t attr = set_lds(k_col2<R, MODE, M0, E>, lds);
@@ -117,7 +117,7 @@ template <typename R, int E, int MODE> struct ColLaunch {
   template <int M0>
   static hipError_t batch(int nblocks, hipStream_t st, const BatchItem<R> *items, int nitems) {
     constexpr size_t lds = col_lds_bytes<R>(M0);
-    if constexpr (lds > kLdsDevice) {
+    if constexpr (!col_fits<R>(M0)) {
       return hipErrorInvalidValue;
     } else {
       static const hipError_t attr = set_lds(k_col2_batch<R, MODE, M0, E>, lds);

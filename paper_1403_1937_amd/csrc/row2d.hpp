@@ -188,7 +188,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   constexpr bool LOADS_TILE = MODE == ROW_TERM || MODE == ROW_ADJ;
   C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / 2H), k < 2H
   C *tws = twl + 2 * H;                      // stage tables of the length-H FFT
-  C *lines = tws + row_stage_tw(H);
+  C *lines = tws + row_stage_tw<R>(H);
   unsigned char *stg = reinterpret_cast<unsigned char *>(lines + RPW * LL);
   __shared__ double s_par[2];
 

@@ -68,6 +68,13 @@ def test_unsupported_sizes(lib):
     with pytest.raises(ValueError, match="unsupported"):
         _plan(dims=(64, 8192))      # row FFT length 16384
     _plan(dims=(2048, 4096))        # largest 2D grid
+    _plan(dims=(2048, 2048), precision="fp64")  # largest float64 row length
+    with pytest.raises(ValueError, match="unsupported"):
+        _plan(dims=(64, 2049), precision="fp64")  # float64 row FFT length 8192
+    for prec in ("fp32", "fp64"):
+        _plan(dims=(512, 512, 512), precision=prec)  # largest 3D grid
+        with pytest.raises(ValueError, match="unsupported"):
+            _plan(dims=(513, 8, 8), precision=prec)
 
 
 def test_workspace_sizes_scale_with_grid(lib):

@@ -149,3 +149,45 @@ def test_adjoint_radix8_schedule(prec, tol):
     err = np.linalg.norm(g - g_o) / np.linalg.norm(g_o)
     print(f"adjoint radix-8 {prec}: normwise rel {err:.3e}", flush=True)
     assert err <= tol
+
+
+def test_differentiation_workload_full_size():
+    """The 2048^2 differentiation workload at full size (T = 12, 4 sources,
+    256 receivers near the sources, target from the perturbed forcing).  The
+    FP64 oracle is too slow at this size, so the checks are properties: the
+    FP32-scaled gradient against the FP64 GPU gradient (normwise rel <=
+    1e-3), and the FP64 gradient against central differences of the FP64
+    GPU loss along two smooth directions (ftilde given, rel <= 1e-5)."""
+    import paper_1403_1937_amd as pk
+    p = workloads.problem(5)
+    rec, f_t = workloads.loss_setup(p)
+    f64 = p.f.astype(np.float64)
+    ftil = float(np.sqrt(0.5 * (f64.min() ** 2 + f64.max() ** 2)))
+    kw = dict(ftilde_mode="given", ftilde=ftil)
+    print("2048^2: target and forward solves", flush=True)
+    tgt = pk.solve(torch.as_tensor(f_t.astype(np.float64)).cuda(), p.src, p.h, p.hbar, p.T,
+                   **kw).cpu().numpy()[rec[:, 0], rec[:, 1]]
+    S64 = pk.solve(torch.as_tensor(f64).cuda(), p.src, p.h, p.hbar, p.T, **kw).cpu().numpy()
+    dLdS = np.zeros(p.dims)
+    dLdS[rec[:, 0], rec[:, 1]] = 2.0 * (S64[rec[:, 0], rec[:, 1]] - tgt)
+    g64 = pk.solve_adjoint(torch.as_tensor(f64).cuda(), p.src, p.h, p.hbar, p.T,
+                           torch.as_tensor(dLdS).cuda(), **kw).cpu().numpy()
+    g32 = pk.solve_adjoint(torch.as_tensor(p.f).cuda(), p.src, p.h, p.hbar, p.T,
+                           torch.as_tensor(dLdS.astype(np.float32)).cuda(),
+                           **kw).double().cpu().numpy()
+    err = np.linalg.norm(g32 - g64) / np.linalg.norm(g64)
+    print(f"  fp32 vs fp64 gradient: normwise rel {err:.3e}", flush=True)
+    assert np.isfinite(g64).all() and err <= 1e-3
+
+    def loss(ff):
+        S = pk.solve(torch.as_tensor(ff).cuda(), p.src, p.h, p.hbar, p.T, **kw).cpu().numpy()
+        return float(np.sum((S[rec[:, 0], rec[:, 1]] - tgt) ** 2))
+
+    rng = np.random.default_rng(17)
+    for k in range(2):
+        d = workloads.smoothed_noise(p.dims, 32.0, -1.0, 1.0, rng)
+        eps = 1e-5
+        fd = (loss(f64 + eps * d) - loss(f64 - eps * d)) / (2 * eps)
+        an = float(np.sum(g64 * d))
+        print(f"  direction {k}: fd {fd:.9e} adjoint {an:.9e}", flush=True)
+        assert abs(fd - an) <= 1e-5 * abs(an)

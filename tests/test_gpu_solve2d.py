@@ -205,3 +205,38 @@ def test_autotune_picks_a_schedule_and_stays_correct():
     o = _oracle(f32, src, h, hbar, T)
     worst, _, _ = report(S.double().cpu().numpy(), o, hbar, "fp32")
     assert worst <= TOL["fp32"]
+
+
+def test_data_flags_reported():
+    """Errors in the data are reported in sweik_info.flags (asynchronously):
+    a non-finite f, f <= 0, and sup|gamma| >= 1 with a given ftilde; a
+    valid problem reports none."""
+    import paper_1403_1937_amd as pk
+    from paper_1403_1937_amd import INFO_FLAGS
+    dims = (40, 48)
+    src = np.array([[10, 12]], np.int32)
+    base = np.full(dims, 1.5, np.float64)
+
+    def flags(f, **kw):
+        _, info = pk.solve(torch.as_tensor(f).cuda(), src, 0.02, 0.1, 3, return_info=True, **kw)
+        return info["flags"]
+
+    assert flags(base) == 0
+    f = base.copy()
+    f[3, 4] = np.nan
+    assert flags(f) & INFO_FLAGS["f_nonfinite"]
+    f = base.copy()
+    f[5, 6] = -1.0
+    assert flags(f) & INFO_FLAGS["f_nonpositive"]
+    f = base.copy()
+    f[7, 8] = 3.0  # gamma = (3/1.5)^2 - 1 = 3 with ftilde given as 1.5
+    assert flags(f, ftilde_mode="given", ftilde=1.5) & INFO_FLAGS["c0_ge_1"]
+
+
+def test_sources_validated_on_the_host():
+    import paper_1403_1937_amd as pk
+    f = torch.full((30, 30), 1.2, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        pk.solve(f, np.array([[30, 0]], np.int32), 0.1, 0.1, 2)
+    with pytest.raises(ValueError):
+        pk.solve(f, np.array([[1, 1], [1, 1]], np.int32), 0.1, 0.1, 2)
