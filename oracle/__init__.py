@@ -45,7 +45,7 @@ class _Problem(C.Structure):
     _fields_ = [("ndim", C.c_int32), ("dims", C.c_int64 * 3), ("h", C.c_double),
                 ("hbar", C.c_double), ("T", C.c_int32), ("ft_mode", C.c_int32),
                 ("ftilde_given", C.c_double), ("conv", C.c_int32),
-                ("nthreads", C.c_int32)]
+                ("nthreads", C.c_int32), ("src_s", C.c_void_p)]
 
 
 def _load():
@@ -69,6 +69,7 @@ def _load():
     lib.orc_ghat.argtypes = [C.c_int, lp, C.c_double, dp]
     lib.orc_ghat.restype = C.c_int64
     lib.orc_phi0.argtypes = [C.c_int, lp, C.c_double, C.c_int32, ip, dp]
+    lib.orc_phi0_weighted.argtypes = [C.c_int, lp, C.c_double, C.c_int32, ip, dp, dp]
     lib.orc_conv.argtypes = [C.c_int, lp, C.c_double, dp, dp, C.c_int32,
                              C.c_int32]
     lib.orc_solve.argtypes = [C.POINTER(_Problem), dp, C.c_int32, ip, dp, dp,
@@ -144,12 +145,18 @@ def ghat(dims, beta: float) -> np.ndarray:
     return out
 
 
-def phi0(dims, beta: float, src: np.ndarray) -> np.ndarray:
+def phi0(dims, beta: float, src: np.ndarray, weights: Optional[np.ndarray] = None) -> np.ndarray:
+    """sum_k w_k exp(-beta |m - y_k|) (eq. phi_0Solution; w_k = 1 by default)."""
     lib = _load()
     src = np.ascontiguousarray(np.asarray(src, np.int32))
     out = np.empty(tuple(int(d) for d in dims), np.float64)
-    _check(lib.orc_phi0(len(dims), _dims(dims), float(beta), len(src), _ip(src),
-                        _dp(out)), "phi0")
+    if weights is None:
+        rc = lib.orc_phi0(len(dims), _dims(dims), float(beta), len(src), _ip(src), _dp(out))
+    else:
+        w = np.ascontiguousarray(np.asarray(weights, np.float64))
+        rc = lib.orc_phi0_weighted(len(dims), _dims(dims), float(beta), len(src), _ip(src),
+                                   _dp(w), _dp(out))
+    _check(rc, "phi0")
     return out
 
 
@@ -164,7 +171,7 @@ def conv(x: np.ndarray, beta: float, method: str = "fft",
     return out
 
 
-def _problem(f, h, hbar, T, ft_mode, ftilde, method, nthreads) -> _Problem:
+def _problem(f, h, hbar, T, ft_mode, ftilde, method, nthreads, src_s=None) -> _Problem:
     p = _Problem()
     p.ndim = f.ndim
     p.dims = _dims(f.shape)
@@ -175,6 +182,9 @@ def _problem(f, h, hbar, T, ft_mode, ftilde, method, nthreads) -> _Problem:
     p.ftilde_given = float(ftilde) if ftilde is not None else 0.0
     p.conv = CONV[method]
     p.nthreads = int(nthreads)
+    if src_s is not None:
+        p._src_s = np.ascontiguousarray(np.asarray(src_s, np.float64))  # kept alive with p
+        p.src_s = p._src_s.ctypes.data
     return p
 
 
@@ -186,12 +196,14 @@ def _info(v) -> dict:
 
 def solve(f: np.ndarray, src: np.ndarray, h: float, hbar: float, T: int,
           ft_mode: str = "nu", ftilde: Optional[float] = None,
-          method: str = "fft", nthreads: int = 0, want_terms: bool = False):
-    """Full T-term solve.  Returns dict(S, phi, terms?, info)."""
+          method: str = "fft", nthreads: int = 0, want_terms: bool = False,
+          src_s: Optional[np.ndarray] = None):
+    """Full T-term solve.  Returns dict(S, phi, terms?, info).  src_s: values
+    of S at the sources (default 0)."""
     lib = _load()
     f = np.ascontiguousarray(np.asarray(f, np.float64))
     src = np.ascontiguousarray(np.asarray(src, np.int32))
-    p = _problem(f, h, hbar, T, ft_mode, ftilde, method, nthreads)
+    p = _problem(f, h, hbar, T, ft_mode, ftilde, method, nthreads, src_s)
     S = np.empty_like(f)
     phi = np.empty_like(f)
     terms = np.empty((int(T) + 1,) + f.shape, np.float64) if want_terms else None

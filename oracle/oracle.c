@@ -368,6 +368,15 @@ int64_t orc_ghat(int ndim, const int64_t *dims, double beta, double *ghat) {
 
 int orc_phi0(int ndim, const int64_t *dims, double beta, int32_t n_src,
              const int32_t *src, double *phi0) {
+  return orc_phi0_weighted(ndim, dims, beta, n_src, src, NULL, phi0);
+}
+
+/* Sources with prescribed values S(y_k) = s_k: the source term of the
+ * screened Poisson problem for a point whose wave function is exp(-s_k/hbar)
+ * there is that multiple of the unit one, so each exponential of eq.
+ * phi_0Solution carries the weight w_k = exp(-s_k / hbar) (superposition). */
+int orc_phi0_weighted(int ndim, const int64_t *dims, double beta, int32_t n_src,
+                      const int32_t *src, const double *w, double *phi0) {
   if ((ndim != 2 && ndim != 3) || !dims || !phi0 || n_src < 1 || !src)
     return -1;
   int64_t n0 = dims[0], n1 = dims[1], n2 = ndim == 3 ? dims[2] : 1;
@@ -382,7 +391,7 @@ int orc_phi0(int ndim, const int64_t *dims, double beta, int32_t n_src,
         double dd = (double)(c[d] - src[k * ndim + d]);
         r2 += dd * dd;
       }
-      s += exp(-beta * sqrt(r2));
+      s += (w ? w[k] : 1.0) * exp(-beta * sqrt(r2));
     }
     phi0[x] = s;
   }
@@ -479,7 +488,19 @@ static int forward(const orc_problem *p, const double *f, int32_t n_src,
     free(psi);
     return -2;
   }
-  orc_phi0(p->ndim, p->dims, beta, n_src, src, prev);
+  double *w = NULL;
+  if (p->src_s) {
+    w = (double *)malloc(sizeof(double) * n_src);
+    if (!w) {
+      free(prev);
+      free(cur);
+      free(psi);
+      return -2;
+    }
+    for (int k = 0; k < n_src; ++k) w[k] = exp(-p->src_s[k] / p->hbar);
+  }
+  orc_phi0_weighted(p->ndim, p->dims, beta, n_src, src, w, prev);
+  free(w);
   memcpy(phi, prev, sizeof(double) * N);
   if (terms) memcpy(terms, prev, sizeof(double) * N);
   for (int i = 1; i <= p->T; ++i) {

@@ -43,6 +43,7 @@ typedef struct {
   double ftilde_given;   /* used when ft_mode == ORC_FT_GIVEN */
   int32_t conv;          /* ORC_CONV_FFT or ORC_CONV_DIRECT */
   int32_t nthreads;      /* OpenMP threads for FFT lines; <= 0: leave as is */
+  const double *src_s;   /* nullable: S at the sources (default 0), n_src values */
 } orc_problem;
 
 /* info[0..7] = ftilde, beta, fmin, fmax, c0_bound = max|gamma|,
@@ -70,6 +71,10 @@ int64_t orc_ghat(int ndim, const int64_t *dims, double beta, double *ghat);
 /* phi_0 on the grid. */
 int orc_phi0(int ndim, const int64_t *dims, double beta, int32_t n_src,
              const int32_t *src, double *phi0);
+/* phi_0 with a weight per source: sum_k w_k exp(-beta |m - y_k|); w_k =
+ * exp(-s_k / hbar) gives sources with S(y_k) = s_k (w NULL: all 1). */
+int orc_phi0_weighted(int ndim, const int64_t *dims, double beta, int32_t n_src,
+                      const int32_t *src, const double *w, double *phi0);
 
 /* out = kappa (*) in (linear convolution over the grid). */
 int orc_conv(int ndim, const int64_t *dims, double beta, const double *in,

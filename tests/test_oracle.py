@@ -414,3 +414,47 @@ def test_invalid_arguments_rejected():
         oracle.solve(f, np.array([[0, 0]], np.int32), -0.1, 0.1, 2)
     with pytest.raises(ValueError):
         oracle.solve(-f, np.array([[0, 0]], np.int32), 0.1, 0.1, 2)
+
+
+# ---- sources with prescribed values S(y_k) = s_k (weights exp(-s_k/hbar)) ----
+
+def test_seed_values_constant_forcing_soft_min():
+    """f = c: phi = phi_0 = sum_k exp(-(s_k + c|x - y_k|)/hbar) exactly, so S
+    is the soft minimum of s_k + c |x - y_k| (eqs. STilde, SfromPhi)."""
+    dims, h, hbar, c = (24, 30), 0.05, 0.08, 1.7
+    src = np.array([[3, 4], [20, 25], [10, 2]], np.int32)
+    s = np.array([0.0, 0.3, -0.2])
+    out = oracle.solve(np.full(dims, c), src, h, hbar, 5, src_s=s)
+    g = np.stack(np.meshgrid(np.arange(dims[0]), np.arange(dims[1]), indexing="ij"), -1)
+    d = np.stack([np.linalg.norm(g - y, axis=-1) * h for y in src])
+    ref = -hbar * np.log(np.exp(-(s[:, None, None] + c * d) / hbar).sum(0))
+    assert np.max(np.abs(out["S"] - ref)) < 1e-12
+
+
+def test_seed_values_uniform_shift():
+    """Adding a constant to every seed value multiplies every term of the
+    series by exp(-shift/hbar), so S shifts by exactly that constant."""
+    rng = np.random.default_rng(71)
+    dims, h, hbar, T = (20, 26), 1 / 26, 0.1, 6
+    f = 1.0 + rng.uniform(0, 1, dims)
+    src = np.array([[4, 5], [15, 20]], np.int32)
+    s = np.array([0.05, 0.2])
+    a = oracle.solve(f, src, h, hbar, T, src_s=s)["S"]
+    b = oracle.solve(f, src, h, hbar, T, src_s=s + 0.37)["S"]
+    assert np.max(np.abs(b - a - 0.37)) < 1e-12
+
+
+def test_seed_value_far_above_removes_the_source():
+    """A seed value thousands of hbar above the rest contributes exp(-s/hbar)
+    = 0: the solve equals the one without that source."""
+    rng = np.random.default_rng(72)
+    dims, h, hbar, T = (18, 22), 1 / 22, 0.1, 5
+    f = 1.0 + rng.uniform(0, 1, dims)
+    src = np.array([[3, 3], [12, 17]], np.int32)
+    a = oracle.solve(f, src, h, hbar, T, src_s=np.array([0.0, 1e3]))["S"]
+    b = oracle.solve(f, src[:1], h, hbar, T)["S"]
+    assert np.array_equal(a, b)
+    # and zero seed values reproduce the default
+    c = oracle.solve(f, src, h, hbar, T, src_s=np.zeros(2))["S"]
+    d = oracle.solve(f, src, h, hbar, T)["S"]
+    assert np.array_equal(c, d)
