@@ -138,6 +138,17 @@ sweik_status sweik_solve(sweik_plan plan, const void *f, const int32_t *src,
                          void *S, void *ws, size_t ws_bytes, void *ckpt,
                          void *stream, sweik_info *info);
 
+/* Forward solve with prescribed values S(y_k) = s_k at the sources: each
+ * source's exponential in phi_0 (eq. phi_0Solution) carries the weight
+ * exp(-s_k / hbar), so that S is a smooth minimum of s_k + distance.
+ *   src_s  device, n_src values of the type of f (nullable: all 0, which is
+ *          sweik_solve).  Other arguments as sweik_solve.  An adjoint taken
+ *          from this solve's checkpoint holds the seed values fixed. */
+sweik_status sweik_solve_seeded(sweik_plan plan, const void *f,
+                                const int32_t *src, const void *src_s, void *S,
+                                void *ws, size_t ws_bytes, void *ckpt,
+                                void *stream, sweik_info *info);
+
 /* Adjoint (2D) of the solve with ftilde held fixed (reverse sweep of the
  * recurrence eq. phiRecRelation; the kernel is even, so the transposed
  * convolution is the convolution itself).

@@ -72,6 +72,7 @@ def load_library():
     lib.sweik_plan_padded_dims.argtypes = [vp, C.POINTER(C.c_int64)]
     lib.sweik_check_sources.argtypes = [vp, C.POINTER(C.c_int32)]
     lib.sweik_solve.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp, vp]
+    lib.sweik_solve_seeded.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
     lib.sweik_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.sweik_solve_timed.argtypes = [vp, vp, vp, vp, vp, sz, vp, C.POINTER(C.c_float),
                                       C.POINTER(C.c_int32)]
@@ -187,10 +188,15 @@ class Plan:
 
     def solve(self, f: torch.Tensor, src: torch.Tensor, S: torch.Tensor, ws: torch.Tensor,
               ckpt: Optional[torch.Tensor] = None, info: Optional[torch.Tensor] = None,
-              stream=None):
-        """Enqueue a solve with caller-owned buffers (no allocation)."""
-        _check(self._lib.sweik_solve(
-            self._h, f.data_ptr(), src.data_ptr(), S.data_ptr(), ws.data_ptr(),
+              stream=None, src_s: Optional[torch.Tensor] = None):
+        """Enqueue a solve with caller-owned buffers (no allocation).  src_s:
+        device values of S at the sources (dtype of f), default 0."""
+        if src_s is not None and (src_s.dtype != f.dtype or src_s.numel() != self.n_src
+                                  or not src_s.is_contiguous()):
+            raise ValueError("src_s must be a contiguous tensor of n_src values of f's dtype")
+        _check(self._lib.sweik_solve_seeded(
+            self._h, f.data_ptr(), src.data_ptr(),
+            src_s.data_ptr() if src_s is not None else None, S.data_ptr(), ws.data_ptr(),
             ws.numel(), ckpt.data_ptr() if ckpt is not None else None,
             _stream_ptr(stream), info.data_ptr() if info is not None else None),
             "sweik_solve")
@@ -266,17 +272,22 @@ def _check_f(f: torch.Tensor):
 
 
 def solve(f: torch.Tensor, src, h: float, hbar: float, T: int, ftilde_mode: str = "nu",
-          ftilde: Optional[float] = None, return_info: bool = False, stream=None):
+          ftilde: Optional[float] = None, return_info: bool = False, stream=None,
+          src_s=None):
     """S = -hbar ln phi of the T-term series for forcing f (float32 or
-    float64 CUDA tensor, 2D or 3D) and point sources src (int [n_src, ndim])."""
+    float64 CUDA tensor, 2D or 3D) and point sources src (int [n_src, ndim])
+    with values src_s there (default 0)."""
     _check_f(f)
     n_src = len(src)
     pl = _plan_for(f, n_src, h, hbar, T, ftilde_mode, ftilde)
     d_src = _src_to_device(src, pl, f.device)
+    d_s = None
+    if src_s is not None:
+        d_s = torch.as_tensor(np.asarray(src_s, np.float64)).to(f.device, f.dtype).contiguous()
     S = torch.empty_like(f)
     ws = pl.workspace(f.device)
     info = torch.zeros(C.sizeof(_Info), dtype=torch.uint8, device=f.device) if return_info else None
-    pl.solve(f, d_src, S, ws, None, info, stream)
+    pl.solve(f, d_src, S, ws, None, info, stream, src_s=d_s)
     if return_info:
         return S, _read_info(info)
     return S

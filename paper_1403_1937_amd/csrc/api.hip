@@ -218,6 +218,7 @@ Args2<R> make_args2(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.hbar = p.hbar;
   a.f = (const R *)f;
   a.src = src;
+  a.src_s = nullptr;
   a.S = (R *)S;
   a.par = (Params *)(w + L.par);
   a.red = (double *)(w + L.red);
@@ -267,9 +268,10 @@ struct KernelTimer {
 template <typename R>
 sweik_status enqueue2d(const sweik_plan_s *pl, const void *f, const int32_t *src, void *S,
                        void *ws, void *ckpt, hipStream_t st, sweik_info *info,
-                       KernelTimer *tm = nullptr) {
+                       KernelTimer *tm = nullptr, const void *src_s = nullptr) {
   const Geo2 &g = pl->g2;
   Args2<R> a = make_args2<R>(pl, f, src, S, ws, ckpt, info);
+  a.src_s = (const R *)src_s;
   const long long N = (long long)g.n0 * g.n1;
   hipError_t err = hipSuccess;
   auto launch = [&](int cls, auto &&fn) {
@@ -409,6 +411,7 @@ Args3<R> make_args3(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.hbar = p.hbar;
   a.f = (const R *)f;
   a.src = src;
+  a.src_s = nullptr;
   a.S = (R *)S;
   a.par = (Params *)(w + L.par);
   a.red = (double *)(w + L.red);
@@ -429,9 +432,11 @@ Args3<R> make_args3(const sweik_plan_s *pl, const void *f, const int32_t *src, v
 // then per term y forward, z convolution, y inverse and the x pass.
 template <typename R>
 sweik_status enqueue3d(const sweik_plan_s *pl, const void *f, const int32_t *src, void *S,
-                       void *ws, hipStream_t st, sweik_info *info, KernelTimer *tm = nullptr) {
+                       void *ws, hipStream_t st, sweik_info *info, KernelTimer *tm = nullptr,
+                       const void *src_s = nullptr) {
   const Geo3 &g = pl->g3;
   Args3<R> a = make_args3<R>(pl, f, src, S, ws, info);
+  a.src_s = (const R *)src_s;
   const long long N = (long long)g.n0 * g.n1 * g.n2;
   hipError_t err = hipSuccess;
   auto launch = [&](int cls, auto &&fn) {
@@ -755,19 +760,25 @@ sweik_status sweik_check_sources(sweik_plan plan, const int32_t *src) {
   return SWEIK_OK;
 }
 
-sweik_status sweik_solve(sweik_plan plan, const void *f, const int32_t *src, void *S, void *ws,
-                         size_t ws_bytes, void *ckpt, void *stream, sweik_info *info) {
+sweik_status sweik_solve_seeded(sweik_plan plan, const void *f, const int32_t *src,
+                                const void *src_s, void *S, void *ws, size_t ws_bytes,
+                                void *ckpt, void *stream, sweik_info *info) {
   if (!plan || !f || !src || !S || !ws) return SWEIK_EINVAL;
   if (ws_bytes < plan->ws.total) return SWEIK_EWORKSPACE;
   hipStream_t st = (hipStream_t)stream;
+  const bool f64 = plan->p.prec == SWEIK_F64;
   if (plan->p.ndim == 2) {
-    return plan->p.prec == SWEIK_F64
-               ? enqueue2d<double>(plan, f, src, S, ws, ckpt, st, info)
-               : enqueue2d<float>(plan, f, src, S, ws, ckpt, st, info);
+    return f64 ? enqueue2d<double>(plan, f, src, S, ws, ckpt, st, info, nullptr, src_s)
+               : enqueue2d<float>(plan, f, src, S, ws, ckpt, st, info, nullptr, src_s);
   }
   if (ckpt) return SWEIK_EUNSUPPORTED;  // the adjoint is 2D only
-  return plan->p.prec == SWEIK_F64 ? enqueue3d<double>(plan, f, src, S, ws, st, info)
-                                   : enqueue3d<float>(plan, f, src, S, ws, st, info);
+  return f64 ? enqueue3d<double>(plan, f, src, S, ws, st, info, nullptr, src_s)
+             : enqueue3d<float>(plan, f, src, S, ws, st, info, nullptr, src_s);
+}
+
+sweik_status sweik_solve(sweik_plan plan, const void *f, const int32_t *src, void *S, void *ws,
+                         size_t ws_bytes, void *ckpt, void *stream, sweik_info *info) {
+  return sweik_solve_seeded(plan, f, src, nullptr, S, ws, ws_bytes, ckpt, stream, info);
 }
 
 sweik_status sweik_solve_timed(sweik_plan plan, const void *f, const int32_t *src, void *S,

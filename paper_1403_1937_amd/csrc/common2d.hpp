@@ -61,6 +61,7 @@ template <typename R> struct Args2 {
   // data
   const R *f;
   const int *src;
+  const R *src_s;  // nullable: S at the sources
   R *S;
   // workspace
   Params *par;

@@ -46,8 +46,8 @@ template <typename R> constexpr size_t x_lds_bytes(int H) {
 constexpr int c3_cpw(int M) { return 8192 / M < 32 ? 8192 / M : 32; }
 constexpr int c3_threads(int M) { return c3_cpw(M) * (M / 16); }
 // static shared memory of an x pass (reductions, scalars, term scales; phi_0
-// also holds up to 512 sources) and of a column pass
-constexpr size_t x_lds_static(int mode) { return 1536 + (mode == X_PHI0 ? 6144 : 0); }
+// also holds up to 512 sources and their weights) and of a column pass
+constexpr size_t x_lds_static(int mode) { return 1536 + (mode == X_PHI0 ? 6144 + 4096 : 0); }
 constexpr size_t kC3LdsStatic = 512;
 template <typename R> constexpr size_t c3_lds_bytes(int M) {
   return sizeof(R) * 2 * ((size_t)M + (size_t)c3_cpw(M) * lds_line_len(M));
@@ -63,6 +63,7 @@ template <typename R> struct Args3 {
   double ftilde_given, h, hbar;
   const R *f;
   const int *src;
+  const R *src_s;  // nullable: S at the sources
   R *S;
   Params *par;
   double *red;     // kRedBlocks x 3

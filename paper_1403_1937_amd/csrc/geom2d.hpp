@@ -43,8 +43,8 @@ template <typename R> constexpr size_t row_lds_core(int H) {
          ((size_t)2 * H + (size_t)row_stage_tw<R>(H) + (size_t)row_rpw(H) * lds_line_len(H));
 }
 // static shared memory of a row pass (block reductions, scalars, the term
-// scales; phi_0 also holds up to 512 sources)
-constexpr size_t row_lds_static(int mode) { return 1536 + (mode == ROW_PHI0 ? 4096 : 0); }
+// scales; phi_0 also holds up to 512 sources and their weights)
+constexpr size_t row_lds_static(int mode) { return 1536 + (mode == ROW_PHI0 ? 4096 + 4096 : 0); }
 template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
   // per staged row: gamma (R) for the forward terms (f for phi_0); previous
   // term, gamma or f, lambda (R) + gradient (double) for the adjoint

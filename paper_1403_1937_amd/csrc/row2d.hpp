@@ -366,11 +366,19 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     Ei = s_e[1];
   }
 
-  // sources of phi_0 (the first kSrcLds of them through LDS)
+  // sources of phi_0 and their log-weights -s_k/hbar (the first kSrcLds of
+  // them through LDS)
   constexpr int kSrcLds = MODE == ROW_PHI0 ? 512 : 1;
   __shared__ int s_src[2 * kSrcLds];
-  if (MODE == ROW_PHI0)
+  __shared__ R s_lw[kSrcLds];
+  auto logw = [&](int k) -> double {  // -s_k / hbar (log2 e times that in float32)
+    const double l = a.src_s ? -(double)a.src_s[k] / a.hbar : 0.0;
+    return sizeof(R) == 4 ? l * 1.4426950408889634 : l;
+  };
+  if (MODE == ROW_PHI0) {
     for (int i = tid; i < 2 * min(a.n_src, kSrcLds); i += NT) s_src[i] = a.src[i];
+    for (int i = tid; i < min(a.n_src, kSrcLds); i += NT) s_lw[i] = (R)logw(i);
+  }
 
   // ---- 3. operands into LDS -------------------------------------------------
 #pragma unroll
@@ -508,11 +516,12 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
             for (int k = 0; k < a.n_src; ++k) {
               const int y0 = k < kSrcLds ? s_src[2 * k] : a.src[2 * k];
               const int y1 = k < kSrcLds ? s_src[2 * k + 1] : a.src[2 * k + 1];
+              const float lw = k < kSrcLds ? (float)s_lw[k] : (float)logw(k);
               const float d0 = (float)(r - y0);
               const float d1 = (float)(c0 - y1);
               const float q0 = d0 * d0;
-              f0 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + d1 * d1));
-              f1 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + (d1 + 1.0f) * (d1 + 1.0f)));
+              f0 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + d1 * d1) + lw);
+              f1 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + (d1 + 1.0f) * (d1 + 1.0f)) + lw);
             }
             s0 = f0;
             s1 = f1;
@@ -520,10 +529,11 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
             for (int k = 0; k < a.n_src; ++k) {
               const int y0 = k < kSrcLds ? s_src[2 * k] : a.src[2 * k];
               const int y1 = k < kSrcLds ? s_src[2 * k + 1] : a.src[2 * k + 1];
+              const double lw = k < kSrcLds ? (double)s_lw[k] : logw(k);
               const double d0 = (double)(r - y0);
               const double d1 = (double)(c0 - y1);
-              s0 += exp(-beta * sqrt(d0 * d0 + d1 * d1));
-              s1 += exp(-beta * sqrt(d0 * d0 + (d1 + 1) * (d1 + 1)));
+              s0 += exp(lw - beta * sqrt(d0 * d0 + d1 * d1));
+              s1 += exp(lw - beta * sqrt(d0 * d0 + (d1 + 1) * (d1 + 1)));
             }
           }
           m0 = (R)s0;

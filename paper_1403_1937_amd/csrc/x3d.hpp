@@ -203,8 +203,15 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     for (int i = tid; i < a.T; i += kThreads) s_sE[i] = ((i & 1) ? -1.0 : 1.0) * ldexp(1.0, a.expo[i]);
   constexpr int kSrcLds = MODE == X_PHI0 ? 512 : 1;
   __shared__ int s_src[3 * kSrcLds];
-  if (MODE == X_PHI0)
+  __shared__ R s_lw[kSrcLds];
+  auto logw = [&](int k) -> double {  // -s_k / hbar (log2 e times that in float32)
+    const double l = a.src_s ? -(double)a.src_s[k] / a.hbar : 0.0;
+    return sizeof(R) == 4 ? l * 1.4426950408889634 : l;
+  };
+  if (MODE == X_PHI0) {
     for (int i = tid; i < 3 * min(a.n_src, kSrcLds); i += kThreads) s_src[i] = a.src[i];
+    for (int i = tid; i < min(a.n_src, kSrcLds); i += kThreads) s_lw[i] = (R)logw(i);
+  }
 
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
@@ -301,22 +308,24 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
             float f0 = 0.0f, f1 = 0.0f;
             for (int k = 0; k < a.n_src; ++k) {
               const int *y = k < kSrcLds ? s_src + 3 * k : a.src + 3 * k;
+              const float lw = k < kSrcLds ? (float)s_lw[k] : (float)logw(k);
               const float d0 = (float)(i0 - y[0]), d1 = (float)(i1 - y[1]);
               const float d2 = (float)(c0 - y[2]);
               const float q = d0 * d0 + d1 * d1;
-              f0 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q + d2 * d2));
-              f1 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q + (d2 + 1.0f) * (d2 + 1.0f)));
+              f0 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q + d2 * d2) + lw);
+              f1 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q + (d2 + 1.0f) * (d2 + 1.0f)) + lw);
             }
             s0 = f0;
             s1 = f1;
           } else {
             for (int k = 0; k < a.n_src; ++k) {
               const int *y = k < kSrcLds ? s_src + 3 * k : a.src + 3 * k;
+              const double lw = k < kSrcLds ? (double)s_lw[k] : logw(k);
               const double d0 = (double)(i0 - y[0]), d1 = (double)(i1 - y[1]);
               const double d2 = (double)(c0 - y[2]);
               const double q = d0 * d0 + d1 * d1;
-              s0 += exp(-beta * sqrt(q + d2 * d2));
-              s1 += exp(-beta * sqrt(q + (d2 + 1) * (d2 + 1)));
+              s0 += exp(lw - beta * sqrt(q + d2 * d2));
+              s1 += exp(lw - beta * sqrt(q + (d2 + 1) * (d2 + 1)));
             }
           }
           m0 = (R)s0;

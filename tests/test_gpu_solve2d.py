@@ -240,3 +240,23 @@ def test_sources_validated_on_the_host():
         pk.solve(f, np.array([[30, 0]], np.int32), 0.1, 0.1, 2)
     with pytest.raises(ValueError):
         pk.solve(f, np.array([[1, 1], [1, 1]], np.int32), 0.1, 0.1, 2)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_seed_values_parity(prec):
+    """Sources with prescribed values S(y_k) = s_k against the oracle."""
+    import paper_1403_1937_amd as pk
+    rng = np.random.default_rng(81)
+    dims, h, hbar, T = (90, 70), 1 / 90, 0.08, 6
+    f = workloads.smoothed_noise(dims, 4.0, 1.0, 3.0, rng).astype(np.float32)
+    src = workloads.distinct_sources(dims, 5, rng)
+    s = rng.uniform(0.0, 0.3, len(src))
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    S = pk.solve(torch.as_tensor(f.astype(np.float64)).to("cuda", dt), src, h, hbar, T,
+                 src_s=s).double().cpu().numpy()
+    o = oracle.solve(f.astype(np.float64), src, h, hbar, T,
+                     src_s=np.asarray(s, np.float32 if prec == "fp32" else np.float64))
+    worst, frac, _ = report(S, o, hbar, prec)
+    print(f"seeded {prec}: max rel {worst:.3e} on {frac:.3f}", flush=True)
+    assert frac > 0.1 and worst <= TOL[prec]
+    assert envelope_violations(S, o, hbar, prec) == 0

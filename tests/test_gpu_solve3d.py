@@ -132,3 +132,20 @@ def test_zero_terms_3d():
     S, _ = _run(f, src, 0.1, 0.2, 0, "fp64")
     o = oracle.solve(f.astype(np.float64), src, 0.1, 0.2, 0)
     assert np.max(rel_err(S, o["S"], 0.2)) < 1e-13
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_seed_values_parity_3d(prec):
+    import paper_1403_1937_amd as pk
+    rng = np.random.default_rng(82)
+    dims, h, hbar, T = (20, 24, 28), 1 / 28, 0.1, 5
+    f = workloads.smoothed_noise(dims, 3.0, 0.5, 2.0, rng).astype(np.float32)
+    src = workloads.distinct_sources(dims, 3, rng)
+    s = rng.uniform(0.0, 0.2, len(src))
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    S = pk.solve(torch.as_tensor(f.astype(np.float64)).to("cuda", dt), src, h, hbar, T,
+                 src_s=s).double().cpu().numpy()
+    o = oracle.solve(f.astype(np.float64), src, h, hbar, T,
+                     src_s=np.asarray(s, np.float32 if prec == "fp32" else np.float64))
+    worst, frac, _ = report(S, o, hbar, prec)
+    assert frac > 0.1 and worst <= TOL[prec]
