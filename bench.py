@@ -90,6 +90,9 @@ def alg_bytes_2d(n0, n1, H1, H0, esz, T, ckpt=False):
         "conv_col": 2 * spec + ghat,
         "term_row": 2 * spec + 2 * esz * N,                  # spectrum in/out, gamma, term out
         "last_row": spec + T * esz * N + esz * N + (8 * N if ckpt else 0),
+        # phi_0 by FFT (many sources): kernel table and spectrum, zeroed
+        # source grid, its transform and the product with the spectrum
+        "phi0_fft": spec + (spec + ghat) + esz * N + (esz * N + spec) + (2 * spec + ghat),
     }
 
 

@@ -35,7 +35,8 @@ class _Problem(C.Structure):
 
 
 class _Schedule(C.Structure):
-    _fields_ = [("row_e", C.c_int32), ("col_e", C.c_int32), ("reserved", C.c_int32 * 6)]
+    _fields_ = [("row_e", C.c_int32), ("col_e", C.c_int32), ("phi0_fft", C.c_int32),
+                ("reserved", C.c_int32 * 5)]
 
 
 class _Info(C.Structure):
@@ -202,7 +203,7 @@ class Plan:
             "sweik_solve")
 
     KERNEL_CLASSES = ("prep", "ghat_row", "ghat_col", "phi0_row", "conv_col", "term_row",
-                      "last_row", "y_fwd", "y_inv", "ghat_z")
+                      "last_row", "y_fwd", "y_inv", "ghat_z", "phi0_fft")
 
     def solve_timed(self, f, src, S, ws, stream=None) -> dict:
         """Solve with HIP events around every kernel (synchronises); returns
@@ -234,11 +235,13 @@ class Plan:
     def schedule(self) -> dict:
         sc = _Schedule()
         _check(self._lib.sweik_plan_get_schedule(self._h, C.byref(sc)), "schedule")
-        return {"row_e": int(sc.row_e), "col_e": int(sc.col_e)}
+        return {"row_e": int(sc.row_e), "col_e": int(sc.col_e), "phi0_fft": int(sc.phi0_fft)}
 
-    def set_schedule(self, row_e: int = 16, col_e: int = 16):
+    def set_schedule(self, row_e: int = 16, col_e: int = 16, phi0_fft: Optional[int] = None):
+        """Set the schedule; phi0_fft None keeps the plan's phi_0 route."""
         sc = _Schedule()
         sc.row_e, sc.col_e = int(row_e), int(col_e)
+        sc.phi0_fft = self.schedule["phi0_fft"] if phi0_fft is None else int(phi0_fft)
         _check(self._lib.sweik_plan_set_schedule(self._h, C.byref(sc)), "set_schedule")
 
 

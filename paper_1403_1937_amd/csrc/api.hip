@@ -121,6 +121,10 @@ void sched_store(int fam, int len, int prec, int e) {
   g_sched[std::make_tuple(fam, len, prec)] = e;
 }
 
+// Sources beyond which a 2D plan takes the FFT route of phi_0: at 1024^2 the
+// direct sum costs about 1.4 us per source, the route about 80 us.
+constexpr int kPhi0FftSources = 64;
+
 // Schedule and workspace layout of a 2D problem.
 sweik_status plan2d(sweik_plan_s *pl) {
   const sweik_problem &p = pl->p;
@@ -156,6 +160,9 @@ sweik_status plan2d(sweik_plan_s *pl) {
   g.lmax_log = ilog2(g.lmax);
   g.erow = sched_lookup(SCHED_ROW2, g.H1, p.prec, 16);
   g.ecol = sched_lookup(SCHED_COL2, g.M0, p.prec, 16);
+  // phi_0 by FFT (Table 1 steps 1-5) when the direct sum over the sources
+  // costs more than the extra kernel spectrum and convolution
+  g.phi0_fft = p.n_src > kPhi0FftSources ? 1 : 0;
   pl->padded[0] = M0;
   pl->padded[1] = M1;
   pl->padded[2] = 1;
@@ -175,6 +182,7 @@ sweik_status plan2d(sweik_plan_s *pl) {
   L.mu = take(sizeof(double) * (size_t)(p.T + 1) * g.nbr);
   L.tw = take((size_t)csz * g.lmax);
   L.g = take((size_t)esz * (g.ldk + 1) * g.ldg);
+  L.g0 = take((size_t)esz * (g.ldk + 1) * g.ldg);  // spectrum of exp(-beta |m|) (phi_0 by FFT)
   L.spec = take((size_t)csz * g.nb * g.ldk * g.RB);
   L.acc = take(sizeof(double) * N);
   L.terms = take((size_t)esz * N * (size_t)p.T);
@@ -213,6 +221,8 @@ Args2<R> make_args2(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.T = p.T;
   a.n_src = p.n_src;
   a.ft_mode = p.ft_mode;
+  a.table = 0;
+  a.phi0_fft = 0;
   a.ftilde_given = p.ftilde;
   a.h = p.h;
   a.hbar = p.hbar;
@@ -289,6 +299,24 @@ sweik_status enqueue2d(const sweik_plan_s *pl, const void *f, const int32_t *src
   launch(SWEIK_KC_PREP, [&] { return launch_prep<R>((const R *)f, N, a.red, (cplx<R> *)a.tw, g.lmax, st); });
   launch(SWEIK_KC_GHAT_ROW, [&] { return launch_row2<R>(ROW_GHAT, g.H1, g.erow, grow, st, a, 0); });
   launch(SWEIK_KC_GHAT_COL, [&] { return launch_col2<R>(COL_GHAT, g.M0, g.ecol, gcol, st, a); });
+  if (g.phi0_fft) {
+    // Table 1 steps 1-5: spectrum of exp(-beta |m|), transform of the source
+    // grid (weights exp(-s_k/hbar)), product, inverse in the phi_0 pass
+    Args2<R> a0 = a;
+    a0.table = 1;
+    a0.g = (R *)((char *)ws + pl->ws.g0);
+    const long long N2 = (long long)g.n0 * g.n1;
+    launch(SWEIK_KC_PHI0_FFT, [&] { return launch_row2<R>(ROW_GHAT, g.H1, g.erow, grow, st, a0, 0); });
+    launch(SWEIK_KC_PHI0_FFT, [&] { return launch_col2<R>(COL_GHAT, g.M0, g.ecol, gcol, st, a0); });
+    launch(SWEIK_KC_PHI0_FFT, [&] { return launch_fill<R>(a.gam, N2, (R)0, st); });
+    launch(SWEIK_KC_PHI0_FFT, [&] {
+      return launch_seed_scatter<R>(a.gam, src, (const R *)src_s, pl->p.n_src, pl->p.hbar, g.n0,
+                                    g.n1, st);
+    });
+    launch(SWEIK_KC_PHI0_FFT, [&] { return launch_row2<R>(ROW_SEED, g.H1, g.erow, grow, st, a0, 0); });
+    launch(SWEIK_KC_PHI0_FFT, [&] { return launch_col2<R>(COL_CONV, g.M0, g.ecol, gcol, st, a0); });
+    a.phi0_fft = 1;
+  }
   launch(SWEIK_KC_PHI0_ROW, [&] { return launch_row2<R>(ROW_PHI0, g.H1, g.erow, grow, st, a, 0); });
   for (int i = 1; i <= pl->p.T; ++i) {
     launch(SWEIK_KC_CONV_COL, [&] { return launch_col2<R>(COL_CONV, g.M0, g.ecol, gcol, st, a); });
@@ -353,6 +381,7 @@ sweik_status plan3d(sweik_plan_s *pl) {
   g.ncb0 = g.H2 / c3_cpw(g.M0);
   g.ncb1 = g.H2 / c3_cpw(g.M1);
   pl->g2.erow = pl->g2.ecol = 16;  // the 3D passes have one schedule
+  pl->g2.phi0_fft = 0;
   g.lmax = std::max(2 * g.M2, std::max(g.M0, g.M1));
   g.lmax_log = ilog2(g.lmax);
   for (int d = 0; d < 3; ++d) pl->padded[d] = M[d];
@@ -852,6 +881,7 @@ sweik_status sweik_batch_create(const sweik_problem *problems, int32_t count, sw
       delete b;
       return st;
     }
+    pl.g2.phi0_fft = 0;  // batched phi_0 passes sum over the sources directly
   }
   // size classes, largest total work first (it runs on the caller's stream)
   for (int i = 0; i < count; ++i) {
@@ -966,6 +996,7 @@ sweik_status sweik_plan_get_schedule(sweik_plan plan, sweik_schedule *out) {
   std::memset(out, 0, sizeof(*out));
   out->row_e = plan->g2.erow;
   out->col_e = plan->g2.ecol;
+  out->phi0_fft = plan->p.ndim == 2 ? plan->g2.phi0_fft : 0;
   return SWEIK_OK;
 }
 
@@ -974,13 +1005,16 @@ sweik_status sweik_plan_set_schedule(sweik_plan plan, const sweik_schedule *sc) 
   auto ok = [](int e) { return e == 16 || e == 8 || e == 4; };
   if (!ok(sc->row_e) || !ok(sc->col_e)) return SWEIK_EINVAL;
   if (plan->p.prec == SWEIK_F64 && (sc->row_e == 4 || sc->col_e == 4)) return SWEIK_EUNSUPPORTED;
-  if (plan->p.ndim == 3 && (sc->row_e != 16 || sc->col_e != 16)) return SWEIK_EUNSUPPORTED;
+  if (sc->phi0_fft != 0 && sc->phi0_fft != 1) return SWEIK_EINVAL;
+  if (plan->p.ndim == 3 && (sc->row_e != 16 || sc->col_e != 16 || sc->phi0_fft))
+    return SWEIK_EUNSUPPORTED;
   if (plan->p.ndim == 2) {
     const int H = plan->g2.H1;
     if (H < sc->row_e) return SWEIK_EUNSUPPORTED;
   }
   plan->g2.erow = sc->row_e;
   plan->g2.ecol = sc->col_e;
+  if (plan->p.ndim == 2) plan->g2.phi0_fft = sc->phi0_fft;
   return SWEIK_OK;
 }
 

@@ -57,6 +57,8 @@ template <typename R> struct Args2 {
   int ncw;         // number of column-pass WGs
   int lmax_log;    // log2 of the twiddle table length
   int T, n_src, ft_mode;
+  int table;     // kernel table of the ROW_GHAT pass: 0 kappa, 1 exp(-beta |m|)
+  int phi0_fft;  // phi_0 from the transform of the source grid (in the spectrum)
   double ftilde_given, h, hbar;
   // data
   const R *f;
@@ -278,6 +280,19 @@ __global__ void __launch_bounds__(256) k_prep_batch(const BatchItem<R> *__restri
   const Args2<R> &a = items[i].a;
   prep_block(a.f, (long long)a.n0 * a.n1, a.red, const_cast<cplx<R> *>(a.tw),
              1 << a.lmax_log, bid, kRedBlocks);
+}
+
+// Source grid of phi_0 by FFT: the weight exp(-s_k/hbar) (1 without values)
+// at every source of a zeroed grid.
+template <typename R>
+__global__ void __launch_bounds__(256) k_seed_scatter(R *__restrict__ grid, const int *__restrict__ src,
+                                                      const R *__restrict__ src_s, int n_src,
+                                                      double hbar, int n0, int n1) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_src; k += gridDim.x * blockDim.x) {
+    const int y0 = src[2 * k], y1 = src[2 * k + 1];
+    if (y0 < 0 || y0 >= n0 || y1 < 0 || y1 >= n1) continue;  // flagged by the kernel-table pass
+    grid[(size_t)y0 * n1 + y1] = src_s ? (R)exp(-(double)src_s[k] / hbar) : (R)1;
+  }
 }
 
 // Work-group index -> tile index such that consecutive tiles run on the same

@@ -17,7 +17,7 @@
 
 namespace sweik {
 
-enum RowMode { ROW_GHAT = 0, ROW_PHI0 = 1, ROW_TERM = 2, ROW_ADJ0 = 3, ROW_ADJ = 4 };
+enum RowMode { ROW_GHAT = 0, ROW_PHI0 = 1, ROW_TERM = 2, ROW_ADJ0 = 3, ROW_ADJ = 4, ROW_SEED = 5 };
 enum ColMode { COL_GHAT = 0, COL_CONV = 1 };
 
 template <typename R> constexpr int spec_rb() { return sizeof(R) == 4 ? 4 : 2; }
@@ -46,11 +46,13 @@ template <typename R> constexpr size_t row_lds_core(int H) {
 // scales; phi_0 also holds up to 512 sources and their weights)
 constexpr size_t row_lds_static(int mode) { return 1536 + (mode == ROW_PHI0 ? 4096 + 4096 : 0); }
 template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
-  // per staged row: gamma (R) for the forward terms (f for phi_0); previous
-  // term, gamma or f, lambda (R) + gradient (double) for the adjoint
+  // per staged row: gamma (R) for the forward terms (f for phi_0, the source
+  // grid for its transform); previous term, gamma or f, lambda (R) +
+  // gradient (double) for the adjoint
   return (size_t)row_rpw(H) * H *
-         (mode == ROW_TERM || mode == ROW_PHI0 ? sizeof(R)
-                                               : mode == ROW_ADJ ? 3 * sizeof(R) + 8 : 0);
+         (mode == ROW_TERM || mode == ROW_PHI0 || mode == ROW_SEED
+              ? sizeof(R)
+              : mode == ROW_ADJ ? 3 * sizeof(R) + 8 : 0);
 }
 template <typename R> constexpr bool row_staged(int H, int mode) {
   return row_stage_bytes<R>(H, mode) > 0 &&

@@ -185,6 +185,17 @@ __device__ inline float kappa_2d_t<float>(double beta, int r2, double k0v, const
   return b * b * (float)(0.5 / kPi) * bessel_k0_f32(b * sqrtf((float)r2), tab);
 }
 
+// the kernel exp(-beta |m|) of phi_0 (eq. phi_0Solution with C = 1), for the
+// FFT route of phi_0 (Table 1, steps 1-5)
+template <typename R> __device__ inline R exp_kernel_t(double beta, int r2);
+template <> __device__ inline double exp_kernel_t<double>(double beta, int r2) {
+  return exp(-beta * sqrt((double)r2));
+}
+template <> __device__ inline float exp_kernel_t<float>(double beta, int r2) {
+  return __builtin_amdgcn_exp2f(-(float)(beta * 1.4426950408889634) *
+                                __builtin_amdgcn_sqrtf((float)r2));
+}
+
 __device__ inline double kappa_3d(double beta, long long r2, double k0v) {
   if (r2 == 0) return k0v;
   const double r = sqrt((double)r2);

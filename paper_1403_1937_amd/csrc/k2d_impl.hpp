@@ -87,6 +87,7 @@ hipError_t launch_row2_e(int mode, int H, dim3 grid, hipStream_t st, const Args2
     case ROW_TERM: return RowLaunch<R, E, ROW_TERM>::run(H, grid, st, a, term);
     case ROW_ADJ0: return RowLaunch<R, E, ROW_ADJ0>::run(H, grid, st, a, term);
     case ROW_ADJ: return RowLaunch<R, E, ROW_ADJ>::run(H, grid, st, a, term);
+    case ROW_SEED: return RowLaunch<R, E, ROW_SEED>::run(H, grid, st, a, term);
   }
   return hipErrorInvalidValue;
 }
@@ -170,6 +171,15 @@ hipError_t launch_adj_prep(const R *dLdS, const double *phi, long long N, double
   return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_seed_scatter(R *grid, const int *src, const R *src_s, int n_src, double hbar,
+                               int n0, int n1, hipStream_t st) {
+  const int nb = std::max(1, std::min((n_src + 255) / 256, 1024));
+  hipLaunchKernelGGL(k_seed_scatter<R>, dim3(nb), dim3(256), 0, st, grid, src, src_s, n_src, hbar,
+                     n0, n1);
+  return hipGetLastError();
+}
+
 template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream_t st) {
   const long long nb = std::min<long long>((N + 255) / 256, 4096);
   hipLaunchKernelGGL(k_fill<R>, dim3((unsigned)std::max<long long>(nb, 1)), dim3(256), 0, st, out,
@@ -199,6 +209,8 @@ template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream
   template hipError_t launch_adj_prep<R>(const R *, const double *, long long, double,      \
                                          double *, cplx<R> *, int, hipStream_t);            \
   template hipError_t launch_fill<R>(R *, long long, R, hipStream_t);                       \
+  template hipError_t launch_seed_scatter<R>(R *, const int *, const R *, int, double, int, int, \
+                                             hipStream_t);                                  \
   template hipError_t launch_prep_batch<R>(int, hipStream_t, const BatchItem<R> *);
 
 }  // namespace sweik

@@ -28,6 +28,9 @@ hipError_t launch_adj_prep(const R *dLdS, const double *phi, long long N, double
                            double *red, cplx<R> *tw, int lmax, hipStream_t st);
 template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream_t st);
 template <typename R>
+hipError_t launch_seed_scatter(R *grid, const int *src, const R *src_s, int n_src, double hbar,
+                               int n0, int n1, hipStream_t st);
+template <typename R>
 hipError_t launch_prep_batch(int nitems, hipStream_t st, const BatchItem<R> *items);
 
 // schedule dispatch: E = 16 (radix-16 stages, 256 threads per work-group),

@@ -19,6 +19,7 @@ struct Geo2 {
   int nbr, ncw;      // row WGs, column WGs
   int lmax, lmax_log;
   int erow, ecol;    // schedule: elements per team thread of the row / column passes
+  int phi0_fft;      // phi_0 by FFT of the source grid (Table 1 steps 1-5)
 };
 
 struct Geo3 {
@@ -30,7 +31,7 @@ struct Geo3 {
 };
 
 struct Layout {      // byte offsets into the workspace / checkpoint
-  size_t par, red, expo, mu, mu_red, tw, g, spec, s2, acc, terms, lam, gam, total;
+  size_t par, red, expo, mu, mu_red, tw, g, g0, spec, s2, acc, terms, lam, gam, total;
   size_t ck_expo, ck_par, ck_g, ck_phi, ck_terms, ck_total;
 };
 

@@ -185,7 +185,9 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   constexpr int TWLOG = ilog2c(2 * H);
   constexpr bool STG = row_staged<R>(H, MODE);
   constexpr int NTW = (2 * H + NT - 1) / NT;
-  constexpr bool LOADS_TILE = MODE == ROW_TERM || MODE == ROW_ADJ;
+  constexpr bool LOADS_TILE = MODE == ROW_TERM || MODE == ROW_ADJ || MODE == ROW_PHI0;
+  // phi_0 reads the spectrum only on its FFT route
+  const bool tile_in = MODE != ROW_PHI0 || a.phi0_fft;
   C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / 2H), k < 2H
   C *tws = twl + 2 * H;                      // stage tables of the length-H FFT
   C *lines = tws + row_stage_tw<R>(H);
@@ -221,7 +223,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   C tsr[NSR > 0 ? NSR : 1];
   stage_tw_issue<H, E>(tsr, a.tw, a.lmax_log, tid, NT);
   C tl[Tile::NREG];
-  if constexpr (LOADS_TILE) tile_issue<FULL>(tile, tid, tl);
+  if (LOADS_TILE && tile_in) tile_issue<FULL>(tile, tid, tl);
   // pointwise operands of this thread's columns c = 2(t + P j) + e
   constexpr int NOP = STG ? E : 1;
   R o1[NOP], o2[NOP], o3[NOP];
@@ -230,6 +232,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     const R *p1 = nullptr, *p2 = nullptr, *p3 = nullptr;
     const double *pd = nullptr;
     if (MODE == ROW_PHI0) p1 = last ? nullptr : a.f;
+    if (MODE == ROW_SEED) p1 = a.gam;  // the source grid
     if (MODE == ROW_TERM) p1 = last ? nullptr : a.gam;
     if (MODE == ROW_ADJ) {
       p1 = a.ck_terms + (size_t)(term - 1) * N;
@@ -387,7 +390,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     if (k < 2 * H) twl[k] = twr[u];
   }
   stage_tw_store<H, E>(tsr, tws, tid, NT);
-  if constexpr (LOADS_TILE) tile_to_lds<FULL>(tile, tid, tl, lines);
+  if (LOADS_TILE && tile_in) tile_to_lds<FULL>(tile, tid, tl, lines);
   if constexpr (STG) {
 #pragma unroll
     for (int q = 0; q < E; ++q) {
@@ -426,8 +429,11 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
       R z0 = 0, z1 = 0;
       if (row_ok) {
         const int rr = r * r;
-        if (c0 < a.n1) z0 = kappa_2d_t<R>(beta, rr + c0 * c0, k0v, a.k0tab);
-        if (c0 + 1 < a.n1) z1 = kappa_2d_t<R>(beta, rr + (c0 + 1) * (c0 + 1), k0v, a.k0tab);
+        auto tab = [&](int q) -> R {
+          return a.table ? exp_kernel_t<R>(beta, q) : kappa_2d_t<R>(beta, q, k0v, a.k0tab);
+        };
+        if (c0 < a.n1) z0 = tab(rr + c0 * c0);
+        if (c0 + 1 < a.n1) z1 = tab(rr + (c0 + 1) * (c0 + 1));
       }
       xl[c0] = z0;
       xl[c0 + 1] = z1;
@@ -444,7 +450,25 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     return;
   }
 
-  if constexpr (LOADS_TILE) row_c2r<R, H, E>(v, t, line, twl, tws);
+  // ---- 4b. transform of the source grid (phi_0 by FFT, Table 1 steps 1-3) ---
+  if constexpr (MODE == ROW_SEED) {
+#pragma unroll
+    for (int j = 0; j < E / 2; ++j) {
+      const int c0 = 2 * (t + P * j);
+      R z0 = 0, z1 = 0;
+      if (col_ok(c0)) {
+        z0 = op1(c0, a.gam);
+        if (FULL || c0 + 1 < a.n1) z1 = op1(c0 + 1, a.gam);
+      }
+      v[j] = cmake<C>(z0, z1);
+    }
+#pragma unroll
+    for (int j = E / 2; j < E; ++j) v[j] = cmake<C>((R)0, (R)0);
+    row_r2c_store<FULL, R, H, E>(v, t, tid, line, lines, twl, tws, tile);
+    return;
+  }
+
+  if (LOADS_TILE && tile_in) row_c2r<R, H, E>(v, t, line, twl, tws);
   // the forcing of the next FFT is zero in the padding half (columns >= H)
 #pragma unroll
   for (int j = E / 2; j < E; ++j) v[j] = cmake<C>((R)0, (R)0);
@@ -508,9 +532,13 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
         double p0, p1;  // phi after this term
         R m0, m1;       // stored mantissas of this term
         if constexpr (MODE == ROW_PHI0) {
-          // phi_0 = sum_k exp(-beta |m - y_k|)  (eq. phi_0Solution, C = 1)
+          // phi_0 = sum_k exp(-beta |m - y_k|)  (eq. phi_0Solution, C = 1),
+          // or on the FFT route the inverse transform of its spectrum
           double s0 = 0.0, s1 = 0.0;
-          if constexpr (sizeof(R) == 4) {
+          if (a.phi0_fft) {
+            s0 = (double)v[j].x;
+            s1 = (double)v[j].y;
+          } else if constexpr (sizeof(R) == 4) {
             const float nb = (float)(-beta * 1.4426950408889634);  // exp(x) = 2^(x log2 e)
             float f0 = 0.0f, f1 = 0.0f;
             for (int k = 0; k < a.n_src; ++k) {

@@ -127,3 +127,18 @@ def test_batch_create_checks_and_layout(lib):
     singles = sum(_plan(dims=q["dims"], T=4).workspace_bytes for q in probs)
     # per-instance regions plus the work lists at the head
     assert singles < b.workspace_bytes < singles + 64 * 1024
+
+
+def test_phi0_route_defaults_and_checks(lib):
+    few = _plan(n_src=8)
+    assert few.schedule["phi0_fft"] == 0
+    many = _plan(n_src=100)
+    assert many.schedule["phi0_fft"] == 1
+    many.set_schedule(16, 16, phi0_fft=0)
+    assert many.schedule["phi0_fft"] == 0
+    with pytest.raises(ValueError):
+        many.set_schedule(16, 16, phi0_fft=2)
+    cube = _plan(dims=(16, 16, 16), n_src=100)
+    assert cube.schedule["phi0_fft"] == 0
+    with pytest.raises(ValueError, match="unsupported"):
+        cube.set_schedule(16, 16, phi0_fft=1)

@@ -144,7 +144,7 @@ def _run_sched(f32, src, h, hbar, T, prec, sched):
     dims = f32.shape
     pl = pk.Plan(dims, h, hbar, T, len(src), prec)
     pl.set_schedule(*sched)
-    assert pl.schedule == {"row_e": sched[0], "col_e": sched[1]}
+    assert pl.schedule["row_e"] == sched[0] and pl.schedule["col_e"] == sched[1]
     dt = torch.float32 if prec == "fp32" else torch.float64
     f = torch.as_tensor(f32.astype(np.float64)).to("cuda", dt)
     d_src = torch.as_tensor(np.ascontiguousarray(src, np.int32)).to("cuda")
@@ -196,7 +196,7 @@ def test_autotune_picks_a_schedule_and_stays_correct():
     assert n == 9
     assert pl.schedule["row_e"] in (4, 8, 16) and pl.schedule["col_e"] in (4, 8, 16)
     # later plans of the same lengths start from the tuned entries
-    assert pk.Plan(dims, h, hbar, T, len(src), "fp32").schedule == pl.schedule
+    assert pk.Plan(dims, h, hbar, T, len(src), "fp32").schedule == pl.schedule  # same lengths
     f = torch.as_tensor(f32).cuda()
     d_src = torch.as_tensor(src).cuda()
     S = torch.empty_like(f)
@@ -260,3 +260,64 @@ def test_seed_values_parity(prec):
     print(f"seeded {prec}: max rel {worst:.3e} on {frac:.3f}", flush=True)
     assert frac > 0.1 and worst <= TOL[prec]
     assert envelope_violations(S, o, hbar, prec) == 0
+
+
+def _circle_sources(dims, count, rng):
+    """`count` distinct grid points on a circle (a dense seed curve)."""
+    c0, c1, rad = dims[0] / 2, dims[1] / 2, 0.35 * min(dims)
+    th = np.sort(rng.uniform(0, 2 * np.pi, 4 * count))
+    pts = np.stack([np.round(c0 + rad * np.cos(th)), np.round(c1 + rad * np.sin(th))], 1)
+    pts = np.unique(pts.astype(np.int32), axis=0)
+    return np.ascontiguousarray(pts[rng.permutation(len(pts))[:count]])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("seeded", [False, True], ids=["plain", "seed_values"])
+def test_phi0_by_fft_many_sources(prec, seeded):
+    """200 sources on a circle: the plan takes the FFT route of phi_0
+    (Table 1 steps 1-5), checked against the oracle's direct sum."""
+    import paper_1403_1937_amd as pk
+    rng = np.random.default_rng(91)
+    dims, h, hbar, T = (128, 160), 1 / 160, 0.05, 6
+    f = workloads.smoothed_noise(dims, 6.0, 1.0, 2.0, rng).astype(np.float32)
+    src = _circle_sources(dims, 200, rng)
+    s = rng.uniform(0.0, 0.05, len(src)) if seeded else None
+    pl = pk.Plan(dims, h, hbar, T, len(src), prec)
+    assert pl.schedule["phi0_fft"] == 1
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    S = pk.solve(torch.as_tensor(f.astype(np.float64)).to("cuda", dt), src, h, hbar, T,
+                 src_s=s).double().cpu().numpy()
+    o = oracle.solve(f.astype(np.float64), src, h, hbar, T,
+                     src_s=None if s is None else
+                     np.asarray(s, np.float32 if prec == "fp32" else np.float64))
+    worst, frac, _ = report(S, o, hbar, prec)
+    print(f"phi0 by FFT {prec} {'seeded' if seeded else 'plain'}: max rel {worst:.3e} "
+          f"on {frac:.3f}", flush=True)
+    assert frac > 0.1 and worst <= TOL[prec]
+    assert envelope_violations(S, o, hbar, prec) == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_phi0_routes_agree(prec):
+    """Few sources, the FFT route forced: against the oracle like the
+    direct route (ragged grid, partial tiles)."""
+    import paper_1403_1937_amd as pk
+    from paper_1403_1937_amd._native import _read_info, info_struct_size
+    rng = np.random.default_rng(92)
+    dims, h, hbar, T = (100, 76), 1 / 100, 0.1, 5
+    f = workloads.smoothed_noise(dims, 4.0, 1.0, 3.0, rng).astype(np.float32)
+    src = workloads.distinct_sources(dims, 4, rng)
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    o = oracle.solve(f.astype(np.float64), src, h, hbar, T)
+    for route in (0, 1):
+        pl = pk.Plan(dims, h, hbar, T, len(src), prec)
+        pl.set_schedule(16, 16, phi0_fft=route)
+        ft = torch.as_tensor(f.astype(np.float64)).to("cuda", dt)
+        S = torch.empty_like(ft)
+        info = torch.zeros(info_struct_size(), dtype=torch.uint8, device="cuda")
+        pl.solve(ft, torch.as_tensor(src).cuda(), S, pl.workspace("cuda"), None, info)
+        torch.cuda.synchronize()
+        worst, frac, _ = report(S.double().cpu().numpy(), o, hbar, prec)
+        print(f"route {route} {prec}: max rel {worst:.3e} on {frac:.3f}", flush=True)
+        assert _read_info(info)["flags"] == 0
+        assert worst <= TOL[prec]
