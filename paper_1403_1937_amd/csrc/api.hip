@@ -349,6 +349,9 @@ sweik_status enqueue2d_adjoint(const sweik_plan_s *pl, const void *f, const int3
 }
 
 
+// Extra complex elements between the planes of the 3D spectrum s2.
+constexpr long long kS2PlanePad = 16;
+
 // Schedule and workspace layout of a 3D problem.
 sweik_status plan3d(sweik_plan_s *pl) {
   const sweik_problem &p = pl->p;
@@ -402,7 +405,8 @@ sweik_status plan3d(sweik_plan_s *pl) {
   L.tw = take((size_t)csz * g.lmax);
   L.g = take((size_t)esz * (g.H1 + 1) * (g.H0 + 1) * g.H2);
   L.spec = take((size_t)csz * g.nlines * g.H2);
-  L.s2 = take((size_t)csz * g.n0 * g.M1 * g.H2);
+  g.ld2 = (long long)g.M1 * g.H2 + kS2PlanePad;
+  L.s2 = take((size_t)csz * g.n0 * (size_t)g.ld2);
   L.acc = 0;
   L.terms = take((size_t)esz * N * (size_t)p.T);
   L.gam = take((size_t)esz * N);
@@ -430,6 +434,7 @@ Args3<R> make_args3(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.H1 = g.H1;
   a.H2 = g.H2;
   a.nlines = g.nlines;
+  a.ld2 = g.ld2;
   a.nbx = g.nbx;
   a.lmax_log = g.lmax_log;
   a.T = p.T;

@@ -61,7 +61,7 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
     }
   } else if constexpr (MODE == C3_Z) {
     C *io = a.s2 + (size_t)plane * H2 + k2;
-    const size_t st = (size_t)a.M1 * H2;
+    const size_t st = (size_t)a.ld2;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int p = t + P * j;
@@ -75,7 +75,7 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
       gv[j] = gc[(size_t)(k0 <= HM ? k0 : M - k0) * H2];
     }
   } else if constexpr (MODE == C3_YI) {
-    const C *in = a.s2 + (size_t)plane * M * H2 + k2;
+    const C *in = a.s2 + (size_t)plane * a.ld2 + k2;
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = in[(size_t)(t + P * j) * H2];
   } else if constexpr (MODE == C3_GY) {
@@ -87,7 +87,7 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
     }
   } else {  // C3_GZ
     const C *in = a.s2 + (size_t)plane * H2 + k2;
-    const size_t st = (size_t)a.M1 * H2;
+    const size_t st = (size_t)a.ld2;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int p = t + P * j, s = p <= HM ? p : M - p;
@@ -104,7 +104,7 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
     team_fft<M, false>(v, t, line, twl, false);
   }
   if constexpr (MODE == C3_YF) {
-    C *out = a.s2 + (size_t)plane * M * H2 + k2;
+    C *out = a.s2 + (size_t)plane * a.ld2 + k2;
 #pragma unroll
     for (int j = 0; j < 16; ++j) out[(size_t)(t + P * j) * H2] = v[j];
   } else if constexpr (MODE == C3_Z) {
@@ -112,7 +112,7 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
     for (int j = 0; j < 16; ++j) v[j] = cscale(v[j], gv[j]);
     team_fft<M, true>(v, t, line, twl, true);
     C *io = a.s2 + (size_t)plane * H2 + k2;
-    const size_t st = (size_t)a.M1 * H2;
+    const size_t st = (size_t)a.ld2;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int p = t + P * j;
@@ -126,7 +126,7 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
       if (FULL || p < a.n1) out[(size_t)p * H2] = v[j];
     }
   } else if constexpr (MODE == C3_GY) {
-    C *out = a.s2 + (size_t)plane * M * H2 + k2;
+    C *out = a.s2 + (size_t)plane * a.ld2 + k2;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int k = t + P * j;

@@ -8,7 +8,9 @@
 //            gamma * phi_i, forward real FFT -> s1[i0][i1][k2] (n0 n1 H2
 //            complex); the last one sums the stored terms in float64
 //   y fwd    (axis 1) per (i0, k2): FFT of the n1 rows zero-padded to M1
-//            -> s2[i0][k1][k2]                              (n0 M1 H2 complex)
+//            -> s2[i0][k1][k2]                              (n0 M1 H2 complex;
+//            planes i0 are ld2 = M1 H2 + pad apart, so that the axis-0 pass
+//            does not step through memory by a large power of two)
 //   z conv   (axis 0) per (k1, k2): FFT of the n0 rows zero-padded to M0,
 //            product with the kernel spectrum, inverse FFT, first n0 rows
 //            back into s2
@@ -57,6 +59,7 @@ template <typename R> struct Args3 {
   int n0, n1, n2;
   int M0, M1, M2, H0, H1, H2;
   int nlines;    // n0 n1 grid lines along axis 2
+  long long ld2; // plane stride of s2 (M1 H2 plus a pad that breaks the power-of-two stride)
   int nbx;       // x-pass work-groups
   int lmax_log;  // log2 of the twiddle table length
   int T, n_src, ft_mode;

@@ -27,6 +27,7 @@ struct Geo3 {
   int M0, M1, M2, H0, H1, H2;
   int nlines, nbx;     // x-pass lines and work-groups
   int ncb0, ncb1;      // column blocks per plane of the z and y passes
+  long long ld2;       // plane stride of s2 (complex elements)
   int lmax, lmax_log;
 };
 
