@@ -26,7 +26,8 @@ Also reported on the same JSON line:
 
 Other modes (for profiling runs):
   --pmc-run                 a copy-calibration kernel, then a few solves of
-                            the main workload (run under rocprofv3 --pmc)
+                            the main workload with row schedules 8 and 16
+                            (run under rocprofv3 --pmc)
   --traffic-summary F W     turn the counter CSVs of a FETCH_SIZE run (F) and
                             a WRITE_SIZE run (W) into the traffic summary
   --stats-summary CSV       turn a rocprofv3 kernel_stats.csv into a short
@@ -145,9 +146,9 @@ def alg_bytes_adjoint_2d(n0, n1, H1, H0, esz, T):
     return total
 
 
-def read_traffic(kernel_hash: str):
-    """Per-launch HBM bytes of the dominant kernel from the committed
-    counter summary, or None when it is missing or stale."""
+def read_traffic(kernel_hash: str, row_e: int):
+    """Per-launch HBM bytes of the term-row kernel of schedule row_e from the
+    committed counter summary, or None when it is missing or stale."""
     try:
         with open(TRAFFIC_FILE) as fh:
             d = json.loads(fh.read().split("\n---\n", 1)[1])
@@ -155,7 +156,8 @@ def read_traffic(kernel_hash: str):
         return None
     if d.get("source_hash") != kernel_hash:
         return None
-    return d.get("traffic_bytes_per_launch")
+    e = d.get("per_schedule", {}).get(str(row_e))
+    return None if e is None else e.get("traffic_bytes_per_launch")
 
 
 def _events(torch, stream):
@@ -164,7 +166,7 @@ def _events(torch, stream):
     return e0, e1
 
 
-def run_main(pk, torch, dev, p, precision, steps, warmup):
+def run_main(pk, torch, dev, p, precision, steps, warmup, schedule=None):
     n0, n1 = p.dims[:2]
     dt = torch.float32 if precision == "fp32" else torch.float64
     f = torch.as_tensor(p.f.astype(np.float32 if precision == "fp32" else np.float64)).to(dev, dt)
@@ -172,7 +174,10 @@ def run_main(pk, torch, dev, p, precision, steps, warmup):
     plan = pk.Plan(p.dims, p.h, p.hbar, p.T, len(p.src), precision)
     plan.check_sources(p.src)
     ws = plan.workspace(dev)
-    plan.autotune(ws)  # schedule choice (radix / work-group shape), untimed
+    if schedule is None:
+        plan.autotune(ws)  # schedule choice (radix / work-group shape), untimed
+    else:
+        plan.set_schedule(*schedule)
     S = torch.empty_like(f)
     for _ in range(warmup):
         plan.solve(f, src, S, ws)
@@ -400,54 +405,49 @@ def _per_dispatch(rows, counter):
 
 def traffic_summary(fetch_path, write_path, command):
     """Average FETCH_SIZE / WRITE_SIZE (KiB per dispatch) of the term-row
-    kernel and of the calibration copy; the copy's reading over its known
-    byte count is the factor that turns counter KiB into HBM bytes."""
+    kernel of every schedule in the runs, and of the calibration copy; the
+    copy's reading over its known byte count is the factor that turns counter
+    KiB into HBM bytes."""
     res = {}
     for counter, path in (("FETCH_SIZE", fetch_path), ("WRITE_SIZE", write_path)):
         disp = _per_dispatch(_counter_rows(path), counter)
         ids = sorted(disp)
-        # the solves' term-row kernel: the schedule with the most dispatches
-        # (the tuner also launches the other candidate a few times)
-        names = {}
-        for d in ids:
-            name = disp[d][0]
-            if "k_row2<float, 2, 1024," in name:
-                names[name] = names.get(name, 0) + 1
-        if not names:
-            raise SystemExit(f"{counter}: no term-row dispatches in {path}")
-        row_name = max(names, key=names.get)
-        term, copy = [], []
+        term, copy = {}, []
         for j, d in enumerate(ids):
             name, v = disp[d]
             if "neg" in name.lower():
                 copy.append(v)
-            elif name == row_name:
-                # the last term-row dispatch of a solve is the log pass:
-                # it is followed by the next solve's prep (or nothing)
+            elif "k_row2<float, 2, 1024," in name:
+                # term-row dispatches of a solve are followed by a column
+                # pass (the last one, the log pass, by the next solve's prep)
                 nxt = disp[ids[j + 1]][0] if j + 1 < len(ids) else ""
                 if "k_col2" in nxt:
-                    term.append(v)
+                    e = name.split("k_row2<float, 2, 1024,")[1].split(">")[0].strip()
+                    term.setdefault(e, []).append(v)
         if not term or not copy:
             raise SystemExit(f"{counter}: no term-row or copy dispatches in {path}")
-        res[counter] = {"kernel_name": row_name,
-                        "term_row_kib": float(np.mean(term)), "term_row_dispatches": len(term),
-                        "copy_kib": float(np.mean(copy)), "copy_dispatches": len(copy)}
+        res[counter] = {"copy_kib": float(np.mean(copy)), "copy_dispatches": len(copy),
+                        "term_row_kib": {e: float(np.mean(x)) for e, x in term.items()},
+                        "term_row_dispatches": {e: len(x) for e, x in term.items()}}
     copy_bytes = 4.0 * COPY_ELEMS
     f_fac = res["FETCH_SIZE"]["copy_kib"] * 1024.0 / copy_bytes
     w_fac = res["WRITE_SIZE"]["copy_kib"] * 1024.0 / copy_bytes
-    fetch_b = res["FETCH_SIZE"]["term_row_kib"] * 1024.0 / f_fac
-    write_b = res["WRITE_SIZE"]["term_row_kib"] * 1024.0 / w_fac
-    d = {"kernel": "term_row (k_row2<float, ROW_TERM, 1024, E>)",
+    per = {}
+    for e in sorted(set(res["FETCH_SIZE"]["term_row_kib"]) & set(res["WRITE_SIZE"]["term_row_kib"])):
+        fb = res["FETCH_SIZE"]["term_row_kib"][e] * 1024.0 / f_fac
+        wb = res["WRITE_SIZE"]["term_row_kib"][e] * 1024.0 / w_fac
+        per[e] = {"kernel": f"k_row2<float, ROW_TERM, 1024, {e}>", "fetch_bytes_per_launch": fb,
+                  "write_bytes_per_launch": wb, "traffic_bytes_per_launch": fb + wb}
+    d = {"kernel": "term_row (k_row2<float, ROW_TERM, 1024, E> for each schedule E)",
          "workload": "noise2d_1024x1024_T16_src16 fp32-scaled",
          "counters": res,
          "copy_bytes_each_way": copy_bytes,
          "fetch_factor": f_fac, "write_factor": w_fac,
-         "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
-         "traffic_bytes_per_launch": fetch_b + write_b,
+         "per_schedule": per,
          "source_hash": source_hash()}
     head = ("HBM traffic of the term-row kernel (FETCH_SIZE and WRITE_SIZE, one rocprofv3\n"
-            "--pmc run each), scaled by the same counters' reading for a plain float32\n"
-            "elementwise copy (torch.neg) of known size.\n"
+            "--pmc run each, solves with row schedules 8 and 16), scaled by the same\n"
+            "counters' reading for a plain float32 elementwise copy (torch.neg) of known size.\n"
             f"command: {command}\n")
     return head + "\n---\n" + json.dumps(d, indent=1) + "\n"
 
@@ -525,8 +525,9 @@ def main():
             torch.neg(a, out=b)
         torch.cuda.synchronize()
         del a, b
-        ms, _, _ = run_main(pk, torch, dev, p, "fp32", args.steps, args.warmup)
-        print(f"pmc run done: {ms:.3f} ms per solve", flush=True)
+        for sched in ((8, 16), (16, 16)):  # the two row schedules the tuner picks at 1024^2
+            ms, _, _ = run_main(pk, torch, dev, p, "fp32", args.steps, args.warmup, sched)
+            print(f"pmc run, schedule {sched}: {ms:.3f} ms per solve", flush=True)
         return
 
     ms, kern, total_bytes = run_main(pk, torch, dev, p, args.precision, args.steps, args.warmup)
@@ -534,8 +535,8 @@ def main():
     sched = kern.pop("schedule")
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches_per_step"])
     d = kern[dom]
-    traffic = read_traffic(source_hash()) if (dom == "term_row" and args.precision == "fp32"
-                                              and args.n == 1024) else None
+    traffic = read_traffic(source_hash(), sched["row_e"]) if (
+        dom == "term_row" and args.precision == "fp32" and args.n == 1024) else None
     out = {
         "metric": METRIC,
         "value": value,
