@@ -146,7 +146,7 @@ sweik_status plan2d(sweik_plan_s *pl) {
   g.nb = (g.n0 + g.RB - 1) / g.RB;
   // every pass must fit the work-group LDS limit
   const bool f64 = p.prec == SWEIK_F64;
-  for (int mode = ROW_GHAT; mode <= ROW_ADJ; ++mode) {
+  for (int mode = ROW_GHAT; mode <= ROW_LAST; ++mode) {
     if (!(f64 ? row_fits<double>(g.H1, mode) : row_fits<float>(g.H1, mode)))
       return SWEIK_EUNSUPPORTED;
   }
@@ -320,8 +320,10 @@ sweik_status enqueue2d(const sweik_plan_s *pl, const void *f, const int32_t *src
   launch(SWEIK_KC_PHI0_ROW, [&] { return launch_row2<R>(ROW_PHI0, g.H1, g.erow, grow, st, a, 0); });
   for (int i = 1; i <= pl->p.T; ++i) {
     launch(SWEIK_KC_CONV_COL, [&] { return launch_col2<R>(COL_CONV, g.M0, g.ecol, gcol, st, a); });
-    launch(i == pl->p.T ? SWEIK_KC_LAST_ROW : SWEIK_KC_TERM_ROW,
-           [&] { return launch_row2<R>(ROW_TERM, g.H1, g.erow, grow, st, a, i); });
+    const bool lastp = i == pl->p.T;
+    launch(lastp ? SWEIK_KC_LAST_ROW : SWEIK_KC_TERM_ROW, [&] {
+      return launch_row2<R>(lastp ? ROW_LAST : ROW_TERM, g.H1, g.erow, grow, st, a, i);
+    });
   }
   return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
@@ -498,7 +500,7 @@ sweik_status enqueue3d(const sweik_plan_s *pl, const void *f, const int32_t *src
     launch(SWEIK_KC_CONV_COL, [&] { return launch_c3<R>(C3_Z, g.M0, g.M1 * g.ncb0, st, a, -1); });
     launch(SWEIK_KC_Y_INV, [&] { return launch_c3<R>(C3_YI, g.M1, ny, st, a, -1); });
     launch(i == T ? SWEIK_KC_LAST_ROW : SWEIK_KC_TERM_ROW,
-           [&] { return launch_x3<R>(X_TERM, g.H2, g.nbx, st, a, i); });
+           [&] { return launch_x3<R>(i == T ? X_LAST : X_TERM, g.H2, g.nbx, st, a, i); });
   }
   return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
@@ -637,7 +639,9 @@ hipError_t batch_class_chain(const sweik_batch_s *b, const BatchClass &c, char *
   if (err == hipSuccess) err = launch_row2_batch<R>(ROW_PHI0, c.H1, c.erow, c.row_blocks, st, ri, n, 0);
   for (int i = 1; i <= b->T && err == hipSuccess; ++i) {
     err = launch_col2_batch<R>(COL_CONV, c.M0, c.ecol, c.col_blocks, st, ci, n);
-    if (err == hipSuccess) err = launch_row2_batch<R>(ROW_TERM, c.H1, c.erow, c.row_blocks, st, ri, n, i);
+    if (err == hipSuccess)
+      err = launch_row2_batch<R>(i == b->T ? ROW_LAST : ROW_TERM, c.H1, c.erow, c.row_blocks, st,
+                                 ri, n, i);
   }
   return err;
 }

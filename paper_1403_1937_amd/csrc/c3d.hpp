@@ -51,13 +51,12 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
   stage_tw_issue<M, 16>(twr, a.tw, a.lmax_log, tid, NT);
   C v[16];
   R gv[16];
-  const C zero = cmake<C>((R)0, (R)0);
   if constexpr (MODE == C3_YF) {
     const C *in = a.s1 + (size_t)plane * a.n1 * H2 + k2;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int p = t + P * j;
-      v[j] = (j < 8 && (FULL || p < a.n1)) ? in[(size_t)p * H2] : zero;
+      v[j] = (j < 8 && (FULL || p < a.n1)) ? in[(size_t)p * H2] : cmake<C>((R)0, (R)0);
     }
   } else if constexpr (MODE == C3_Z) {
     C *io = a.s2 + (size_t)plane * H2 + k2;
@@ -65,7 +64,7 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int p = t + P * j;
-      v[j] = (j < 8 && (FULL || p < a.n0)) ? io[(size_t)p * st] : zero;
+      v[j] = (j < 8 && (FULL || p < a.n0)) ? io[(size_t)p * st] : cmake<C>((R)0, (R)0);
     }
     const int k1 = plane <= a.H1 ? plane : a.M1 - plane;
     const R *gc = a.g + (size_t)k1 * (HM + 1) * H2 + k2;
@@ -83,7 +82,7 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int p = t + P * j, s = p <= HM ? p : M - p;
-      v[j] = s < a.n1 ? in[(size_t)s * H2] : zero;
+      v[j] = s < a.n1 ? in[(size_t)s * H2] : cmake<C>((R)0, (R)0);
     }
   } else {  // C3_GZ
     const C *in = a.s2 + (size_t)plane * H2 + k2;
@@ -91,7 +90,7 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
       const int p = t + P * j, s = p <= HM ? p : M - p;
-      v[j] = s < a.n0 ? in[(size_t)s * st] : zero;
+      v[j] = s < a.n0 ? in[(size_t)s * st] : cmake<C>((R)0, (R)0);
     }
   }
   stage_tw_store<M, 16>(twr, twl, tid, NT);

@@ -169,7 +169,8 @@ __global__ void __launch_bounds__(team_threads(E)) k_col2_batch(const BatchItem<
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int g = xcd_tile(blockIdx.x, gridDim.x);
   const int i = find_item(items, nitems, g);
-  col_block<R, MODE, M0, E>(items[i].a, g - items[i].begin, smem_raw);
+  const Args2<R> a = item_args(items[i]);
+  col_block<R, MODE, M0, E>(a, g - items[i].begin, smem_raw);
 }
 
 }  // namespace sweik

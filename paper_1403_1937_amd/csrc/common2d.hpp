@@ -262,6 +262,40 @@ template <typename R> struct BatchItem {
   int pad_;
 };
 
+// Pointers read from a work list in memory are generic to the compiler (flat
+// loads and stores).  Rebuilding each one as a global-address-space pointer
+// from its integer value lets it use global memory instructions (a plain
+// generic -> global -> generic cast is folded away).
+template <typename T> __device__ __forceinline__ T *as_global(T *p) {
+  using G = __attribute__((address_space(1))) T;
+  return (T *)(G *)(unsigned long)p;
+}
+template <typename R> __device__ __forceinline__ Args2<R> item_args(const BatchItem<R> &it) {
+  Args2<R> a = it.a;
+  a.f = as_global(a.f);
+  a.src = as_global(a.src);
+  a.src_s = as_global(a.src_s);
+  a.S = as_global(a.S);
+  a.par = as_global(a.par);
+  a.red = as_global(a.red);
+  a.mu = as_global(a.mu);
+  a.expo = as_global(a.expo);
+  a.tw = as_global(a.tw);
+  a.spec = as_global(a.spec);
+  a.g = as_global(a.g);
+  a.acc = as_global(a.acc);
+  a.terms = as_global(a.terms);
+  a.gam = as_global(a.gam);
+  a.dLdS = as_global(a.dLdS);
+  a.dLdf = as_global(a.dLdf);
+  a.lam = as_global(a.lam);
+  a.info = as_global(a.info);
+  a.ck_expo = as_global(a.ck_expo);
+  a.ck_phi = as_global(a.ck_phi);
+  a.ck_terms = as_global(a.ck_terms);
+  return a;
+}
+
 // Instance owning work-group g (items sorted by begin; small lists).
 template <typename R>
 __device__ __forceinline__ int find_item(const BatchItem<R> *items, int n, int g) {
@@ -277,7 +311,7 @@ __device__ __forceinline__ int find_item(const BatchItem<R> *items, int n, int g
 template <typename R>
 __global__ void __launch_bounds__(256) k_prep_batch(const BatchItem<R> *__restrict__ items) {
   const int i = blockIdx.x / kRedBlocks, bid = blockIdx.x % kRedBlocks;
-  const Args2<R> &a = items[i].a;
+  const Args2<R> a = item_args(items[i]);
   prep_block(a.f, (long long)a.n0 * a.n1, a.red, const_cast<cplx<R> *>(a.tw),
              1 << a.lmax_log, bid, kRedBlocks);
 }

@@ -31,7 +31,9 @@
 
 namespace sweik {
 
-enum XMode { X_GHAT = 0, X_PHI0 = 1, X_TERM = 2 };
+// X_LAST: the pass after the last convolution (float64 sum of the stored
+// terms and the log), its own kernel so that X_TERM is not sized for it
+enum XMode { X_GHAT = 0, X_PHI0 = 1, X_TERM = 2, X_LAST = 3 };
 enum C3Mode { C3_YF = 0, C3_Z = 1, C3_YI = 2, C3_GY = 3, C3_GZ = 4 };
 
 // x pass: one team of P = H2/16 threads per line, 256 threads per group

@@ -246,10 +246,15 @@ template <int L, int E, int NR, typename C>
 __device__ __forceinline__ void stage_tw_issue(C (&tr)[NR], const C *tw, int lmax_log, int tid,
                                                int nthreads) {
   constexpr int NC = stage_tw_len(L, E);
+  if constexpr (NC > 0) {
+    // every register is loaded (threads past the end re-read the last entry
+    // and do not store it): a conditionally written register array would be
+    // kept in scratch memory
 #pragma unroll
-  for (int u = 0; u < NR; ++u) {
-    const int e = tid + u * nthreads;
-    if (e < NC) tr[u] = tw[stage_tw_index<L, E>(e, lmax_log)];
+    for (int u = 0; u < NR; ++u) {
+      const int e = min(tid + u * nthreads, NC - 1);
+      tr[u] = tw[stage_tw_index<L, E>(e, lmax_log)];
+    }
   }
 }
 // ... and store them to LDS (before the barrier that precedes the FFT)

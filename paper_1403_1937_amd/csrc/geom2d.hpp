@@ -17,7 +17,12 @@
 
 namespace sweik {
 
-enum RowMode { ROW_GHAT = 0, ROW_PHI0 = 1, ROW_TERM = 2, ROW_ADJ0 = 3, ROW_ADJ = 4, ROW_SEED = 5 };
+// ROW_LAST is the pass after the last convolution (no forcing, no forward
+// transform: the float64 sum of the stored terms and the log); it is its own
+// kernel so that the term passes are not sized for its registers.
+enum RowMode {
+  ROW_GHAT = 0, ROW_PHI0 = 1, ROW_TERM = 2, ROW_ADJ0 = 3, ROW_ADJ = 4, ROW_SEED = 5, ROW_LAST = 6
+};
 enum ColMode { COL_GHAT = 0, COL_CONV = 1 };
 
 template <typename R> constexpr int spec_rb() { return sizeof(R) == 4 ? 4 : 2; }

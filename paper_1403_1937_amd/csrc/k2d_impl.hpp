@@ -88,6 +88,7 @@ hipError_t launch_row2_e(int mode, int H, dim3 grid, hipStream_t st, const Args2
     case ROW_ADJ0: return RowLaunch<R, E, ROW_ADJ0>::run(H, grid, st, a, term);
     case ROW_ADJ: return RowLaunch<R, E, ROW_ADJ>::run(H, grid, st, a, term);
     case ROW_SEED: return RowLaunch<R, E, ROW_SEED>::run(H, grid, st, a, term);
+    case ROW_LAST: return RowLaunch<R, E, ROW_LAST>::run(H, grid, st, a, term);
   }
   return hipErrorInvalidValue;
 }
@@ -99,6 +100,7 @@ hipError_t launch_row2_batch_e(int mode, int H, int nblocks, hipStream_t st,
     case ROW_GHAT: return RowLaunch<R, E, ROW_GHAT>::run_batch(H, nblocks, st, items, nitems, term);
     case ROW_PHI0: return RowLaunch<R, E, ROW_PHI0>::run_batch(H, nblocks, st, items, nitems, term);
     case ROW_TERM: return RowLaunch<R, E, ROW_TERM>::run_batch(H, nblocks, st, items, nitems, term);
+    case ROW_LAST: return RowLaunch<R, E, ROW_LAST>::run_batch(H, nblocks, st, items, nitems, term);
   }
   return hipErrorInvalidValue;
 }

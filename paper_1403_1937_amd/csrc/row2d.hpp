@@ -7,6 +7,8 @@
 // (ii) takes the inverse real FFT of each row (complex FFT of length H
 // plus a split step), (iii) applies the pointwise step of its mode, and
 // (iv) takes the forward real FFT of the new forcing and stores the tile.
+// The pass after the last convolution (ROW_LAST) stops after (iii): it sums
+// the stored terms in float64 and writes S.
 #pragma once
 
 #include "common2d.hpp"
@@ -185,7 +187,8 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   constexpr int TWLOG = ilog2c(2 * H);
   constexpr bool STG = row_staged<R>(H, MODE);
   constexpr int NTW = (2 * H + NT - 1) / NT;
-  constexpr bool LOADS_TILE = MODE == ROW_TERM || MODE == ROW_ADJ || MODE == ROW_PHI0;
+  constexpr bool TERMLIKE = MODE == ROW_TERM || MODE == ROW_LAST;
+  constexpr bool LOADS_TILE = TERMLIKE || MODE == ROW_ADJ || MODE == ROW_PHI0;
   // phi_0 reads the spectrum only on its FFT route
   const bool tile_in = MODE != ROW_PHI0 || a.phi0_fft;
   C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / 2H), k < 2H
@@ -200,7 +203,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   const bool row_ok = FULL || r < a.n0;
   const size_t rowoff = (size_t)r * a.n1;
   const size_t N = (size_t)a.n0 * a.n1;
-  const bool last = (MODE == ROW_TERM && term == a.T) || (MODE == ROW_PHI0 && a.T == 0);
+  const bool last = MODE == ROW_LAST || (MODE == ROW_PHI0 && a.T == 0);
   // column c of this thread's pair j (c = 2(t + P j) + e) lies in the grid
   auto col_ok = [&](int c) { return FULL ? true : (row_ok && c < a.n1); };
   Tile tile;
@@ -217,7 +220,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int k = tid + u * NT;
-    if (k < 2 * H) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
+    twr[u] = a.tw[min(k, 2 * H - 1) << (a.lmax_log - TWLOG)];  // stored only if k < 2 * H
   }
   constexpr int NSR = (stage_tw_len(H, E) + NT - 1) / NT;
   C tsr[NSR > 0 ? NSR : 1];
@@ -233,7 +236,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     const double *pd = nullptr;
     if (MODE == ROW_PHI0) p1 = last ? nullptr : a.f;
     if (MODE == ROW_SEED) p1 = a.gam;  // the source grid
-    if (MODE == ROW_TERM) p1 = last ? nullptr : a.gam;
+    if (MODE == ROW_TERM) p1 = a.gam;
     if (MODE == ROW_ADJ) {
       p1 = a.ck_terms + (size_t)(term - 1) * N;
       p2 = term > 1 ? a.gam : a.f;
@@ -333,23 +336,23 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
 
   // exponents: forward phi_i = 2^E_i m_i; adjoint a_i = 2^e_lam (mantissa)
   int dstep = 0, Ei = 0, elam = 0;
-  if (MODE == ROW_TERM) {
+  if (TERMLIKE) {
     double mu = 0.0;
     for (int i = tid; i < a.nbr; i += NT) mu = fmax(mu, a.mu[(size_t)(term - 1) * a.nbr + i]);
     mu = block_max(mu);
     dstep = exp_step(mu);
     Ei = a.expo[term - 1] + dstep;
   }
-  if ((MODE == ROW_TERM || MODE == ROW_PHI0) && bid == 0 && tid == 0) {
-    const int slot = MODE == ROW_TERM ? term : 0;
+  if ((TERMLIKE || MODE == ROW_PHI0) && bid == 0 && tid == 0) {
+    const int slot = TERMLIKE ? term : 0;
     a.expo[slot] = Ei;
     if (a.info) a.info->scale_exp[slot] = Ei;
     if (a.ck_expo) a.ck_expo[slot] = Ei;
   }
   // last term: signed scales (-1)^i 2^E_i of the stored terms (read after
   // the barrier below)
-  __shared__ double s_sE[MODE == ROW_TERM ? SWEIK_MAX_TERMS + 1 : 1];
-  if (MODE == ROW_TERM && term == a.T)
+  __shared__ double s_sE[MODE == ROW_LAST ? SWEIK_MAX_TERMS + 1 : 1];
+  if (MODE == ROW_LAST)
     for (int i = tid; i < a.T; i += NT) s_sE[i] = ((i & 1) ? -1.0 : 1.0) * ldexp(1.0, a.expo[i]);
   if (MODE == ROW_ADJ0) {
     double mx = 0.0;
@@ -402,7 +405,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
           sR[(size_t)RPW * H + cc] = o2[q];
           sR[(size_t)2 * RPW * H + cc] = o3[q];
         }
-        if (MODE == ROW_TERM || MODE == ROW_ADJ) sD[cc] = od[q];
+        if (MODE == ROW_ADJ) sD[cc] = od[q];
       }
     }
   }
@@ -475,17 +478,17 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
 
   // ---- 5. pointwise step over columns 2k, 2k+1 (k = t + P j, j < E/2) -----
   long long nbad = 0;
-  if constexpr (MODE == ROW_PHI0 || MODE == ROW_TERM) {
+  if constexpr (MODE == ROW_PHI0 || TERMLIKE) {
     const bool even_n1 = FULL || (a.n1 & 1) == 0;
     const R sm = (R)ldexp(1.0, -dstep);
-    const double sE = ((MODE == ROW_TERM && (term & 1)) ? -1.0 : 1.0) * ldexp(1.0, Ei);
+    const double sE = ((TERMLIKE && (term & 1)) ? -1.0 : 1.0) * ldexp(1.0, Ei);
     R mlr = (R)0;
-    const int slot = MODE == ROW_TERM ? term : 0;
+    const int slot = TERMLIKE ? term : 0;
     R *tout = a.terms + (size_t)slot * N + rowoff;  // this term's mantissas
     // last term: the float64 sum of the stored terms 0..T-1 at this thread's
     // columns, in the order of the terms (as a running accumulation would)
     double ps[E];
-    if (MODE == ROW_TERM && last) {
+    if constexpr (MODE == ROW_LAST) {
       using V = cplx<R>;
       auto pair = [&](const R *q, int c0) -> V {
         V x = cmake<V>((R)0, (R)0);
@@ -541,28 +544,30 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
           } else if constexpr (sizeof(R) == 4) {
             const float nb = (float)(-beta * 1.4426950408889634);  // exp(x) = 2^(x log2 e)
             float f0 = 0.0f, f1 = 0.0f;
-            for (int k = 0; k < a.n_src; ++k) {
-              const int y0 = k < kSrcLds ? s_src[2 * k] : a.src[2 * k];
-              const int y1 = k < kSrcLds ? s_src[2 * k + 1] : a.src[2 * k + 1];
-              const float lw = k < kSrcLds ? (float)s_lw[k] : (float)logw(k);
+            auto add = [&](int y0, int y1, float lw) {
               const float d0 = (float)(r - y0);
               const float d1 = (float)(c0 - y1);
               const float q0 = d0 * d0;
               f0 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + d1 * d1) + lw);
               f1 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + (d1 + 1.0f) * (d1 + 1.0f)) + lw);
-            }
+            };
+            // the first kSrcLds sources from LDS, the rest from global memory
+            // (two loops, so that no load picks its address space at run time)
+            const int nl = min(a.n_src, kSrcLds);
+            for (int k = 0; k < nl; ++k) add(s_src[2 * k], s_src[2 * k + 1], (float)s_lw[k]);
+            for (int k = nl; k < a.n_src; ++k) add(a.src[2 * k], a.src[2 * k + 1], (float)logw(k));
             s0 = f0;
             s1 = f1;
           } else {
-            for (int k = 0; k < a.n_src; ++k) {
-              const int y0 = k < kSrcLds ? s_src[2 * k] : a.src[2 * k];
-              const int y1 = k < kSrcLds ? s_src[2 * k + 1] : a.src[2 * k + 1];
-              const double lw = k < kSrcLds ? (double)s_lw[k] : logw(k);
+            auto add = [&](int y0, int y1, double lw) {
               const double d0 = (double)(r - y0);
               const double d1 = (double)(c0 - y1);
               s0 += exp(lw - beta * sqrt(d0 * d0 + d1 * d1));
               s1 += exp(lw - beta * sqrt(d0 * d0 + (d1 + 1) * (d1 + 1)));
-            }
+            };
+            const int nl = min(a.n_src, kSrcLds);
+            for (int k = 0; k < nl; ++k) add(s_src[2 * k], s_src[2 * k + 1], (double)s_lw[k]);
+            for (int k = nl; k < a.n_src; ++k) add(a.src[2 * k], a.src[2 * k + 1], logw(k));
           }
           m0 = (R)s0;
           m1 = (R)s1;
@@ -707,7 +712,8 @@ __global__ void __launch_bounds__(team_threads(E)) k_row2_batch(const BatchItem<
                                                          int nitems, int term) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = find_item(items, nitems, (int)blockIdx.x);
-  row_block<R, MODE, H, E>(items[i].a, term, smem_raw, (int)blockIdx.x - items[i].begin);
+  const Args2<R> a = item_args(items[i]);
+  row_block<R, MODE, H, E>(a, term, smem_raw, (int)blockIdx.x - items[i].begin);
 }
 
 // Adjoint start: max |lambda| partials (with the twiddle table).

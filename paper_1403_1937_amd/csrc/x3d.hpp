@@ -3,9 +3,10 @@
 //           also reduces f into the reference forcing and publishes it
 //   X_PHI0  phi_0 from the sources (eq. phi_0Solution), first forcing term,
 //           forward real FFT
-//   X_TERM  term `term`: inverse real FFT, rescale, store the term; then the
-//           next forcing term and its FFT, or (term == T) the float64 sum of
-//           all terms and S = -hbar ln phi
+//   X_TERM  term `term` < T: inverse real FFT, rescale, store the term; then
+//           the next forcing term and its FFT
+//   X_LAST  term T: inverse real FFT, the float64 sum of all terms and
+//           S = -hbar ln phi
 #pragma once
 
 #include "common3d.hpp"
@@ -84,7 +85,8 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   const int i0 = rs / a.n1, i1 = rs - i0 * a.n1;
   C *line = lines + team * LL;
   const size_t rowoff = (size_t)rs * a.n2;
-  const bool last = (MODE == X_TERM && term == a.T) || (MODE == X_PHI0 && a.T == 0);
+  constexpr bool TERMLIKE = MODE == X_TERM || MODE == X_LAST;
+  const bool last = MODE == X_LAST || (MODE == X_PHI0 && a.T == 0);
   auto col_ok = [&](int c) { return FULL ? true : (line_ok && c < a.n2); };
   const bool vec = FULL || (a.n2 & 1) == 0;  // column pairs aligned: vector access
 
@@ -93,13 +95,13 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int k = tid + u * kThreads;
-    if (k < 4 * H) twr[u] = a.tw[k << (a.lmax_log - TWLOG)];
+    twr[u] = a.tw[min(k, 4 * H - 1) << (a.lmax_log - TWLOG)];  // stored only if k < 4 * H
   }
   constexpr int NSR = (stage_tw_len(H, 16) + kThreads - 1) / kThreads;
   C tsr[NSR > 0 ? NSR : 1];
   stage_tw_issue<H, 16>(tsr, a.tw, a.lmax_log, tid, kThreads);
   C v[16];
-  if constexpr (MODE == X_TERM) {
+  if constexpr (TERMLIKE) {
     const C *sl = a.s1 + (size_t)rs * H;
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = line_ok ? sl[t + P * j] : cmake<C>((R)0, (R)0);
@@ -108,7 +110,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   // can lie in the grid since n2 <= H)
   R o1[16];
   double od[16];
-  if constexpr (MODE == X_TERM || MODE == X_PHI0) {
+  if constexpr (TERMLIKE || MODE == X_PHI0) {
     const R *p1 = last ? nullptr : (MODE == X_PHI0 ? a.f : a.gam);
     const double *pd = nullptr;  // no operand in float64
 #pragma unroll
@@ -188,18 +190,18 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     ft = a.par->ftilde;
   }
   int dstep = 0, E = 0;
-  if (MODE == X_TERM) {
+  if (TERMLIKE) {
     dstep = exp_step(a.mu_red[term - 1]);
     E = a.expo[term - 1] + dstep;
   }
-  if ((MODE == X_TERM || MODE == X_PHI0) && bid == 0 && tid == 0) {
-    const int slot = MODE == X_TERM ? term : 0;
+  if ((TERMLIKE || MODE == X_PHI0) && bid == 0 && tid == 0) {
+    const int slot = TERMLIKE ? term : 0;
     a.expo[slot] = E;
     if (a.info) a.info->scale_exp[slot] = E;
   }
   // last term: signed scales (-1)^i 2^E_i of the stored terms
-  __shared__ double s_sE[MODE == X_TERM ? SWEIK_MAX_TERMS + 1 : 1];
-  if (MODE == X_TERM && term == a.T)
+  __shared__ double s_sE[MODE == X_LAST ? SWEIK_MAX_TERMS + 1 : 1];
+  if (MODE == X_LAST)
     for (int i = tid; i < a.T; i += kThreads) s_sE[i] = ((i & 1) ? -1.0 : 1.0) * ldexp(1.0, a.expo[i]);
   constexpr int kSrcLds = MODE == X_PHI0 ? 512 : 1;
   __shared__ int s_src[3 * kSrcLds];
@@ -242,19 +244,19 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     }
   }
 
-  if constexpr (MODE == X_TERM) odd_c2r<R, H>(v, t, line, twl, tws);
+  if constexpr (TERMLIKE) odd_c2r<R, H>(v, t, line, twl, tws);
 
   // ---- 4. pointwise step -------------------------------------------------------
-  if constexpr (MODE == X_PHI0 || MODE == X_TERM) {
+  if constexpr (MODE == X_PHI0 || TERMLIKE) {
     long long nbad = 0;
     const R sm = (R)ldexp(1.0, -dstep);
-    const double sE = ((MODE == X_TERM && (term & 1)) ? -1.0 : 1.0) * ldexp(1.0, E);
+    const double sE = ((TERMLIKE && (term & 1)) ? -1.0 : 1.0) * ldexp(1.0, E);
     R mlr = (R)0;
-    R *tout = a.terms + (size_t)(MODE == X_TERM ? term : 0) * ((size_t)a.nlines * a.n2) + rowoff;
+    R *tout = a.terms + (size_t)(TERMLIKE ? term : 0) * ((size_t)a.nlines * a.n2) + rowoff;
     // last term: the float64 sum of the stored terms 0..T-1 at this thread's
     // columns, in the order of the terms
     double ps[16];
-    if (MODE == X_TERM && last) {
+    if constexpr (MODE == X_LAST) {
       using V = cplx<R>;
       const size_t NN = (size_t)a.nlines * a.n2;
       auto pair = [&](const R *q, int c0) -> V {
@@ -303,30 +305,34 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
         if constexpr (MODE == X_PHI0) {
           // phi_0 = sum_k exp(-beta |m - y_k|)  (eq. phi_0Solution, C = 1)
           double s0 = 0.0, s1 = 0.0;
+          // the first kSrcLds sources from LDS, the rest from global memory
+          // (two loops, so that no load picks its address space at run time)
+          const int nl = min(a.n_src, kSrcLds);
           if constexpr (sizeof(R) == 4) {
             const float nb = (float)(-beta * 1.4426950408889634);  // exp(x) = 2^(x log2 e)
             float f0 = 0.0f, f1 = 0.0f;
-            for (int k = 0; k < a.n_src; ++k) {
-              const int *y = k < kSrcLds ? s_src + 3 * k : a.src + 3 * k;
-              const float lw = k < kSrcLds ? (float)s_lw[k] : (float)logw(k);
-              const float d0 = (float)(i0 - y[0]), d1 = (float)(i1 - y[1]);
-              const float d2 = (float)(c0 - y[2]);
+            auto add = [&](int y0, int y1, int y2, float lw) {
+              const float d0 = (float)(i0 - y0), d1 = (float)(i1 - y1);
+              const float d2 = (float)(c0 - y2);
               const float q = d0 * d0 + d1 * d1;
               f0 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q + d2 * d2) + lw);
               f1 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q + (d2 + 1.0f) * (d2 + 1.0f)) + lw);
-            }
+            };
+            for (int k = 0; k < nl; ++k) add(s_src[3 * k], s_src[3 * k + 1], s_src[3 * k + 2], (float)s_lw[k]);
+            for (int k = nl; k < a.n_src; ++k)
+              add(a.src[3 * k], a.src[3 * k + 1], a.src[3 * k + 2], (float)logw(k));
             s0 = f0;
             s1 = f1;
           } else {
-            for (int k = 0; k < a.n_src; ++k) {
-              const int *y = k < kSrcLds ? s_src + 3 * k : a.src + 3 * k;
-              const double lw = k < kSrcLds ? (double)s_lw[k] : logw(k);
-              const double d0 = (double)(i0 - y[0]), d1 = (double)(i1 - y[1]);
-              const double d2 = (double)(c0 - y[2]);
+            auto add = [&](int y0, int y1, int y2, double lw) {
+              const double d0 = (double)(i0 - y0), d1 = (double)(i1 - y1);
+              const double d2 = (double)(c0 - y2);
               const double q = d0 * d0 + d1 * d1;
               s0 += exp(lw - beta * sqrt(q + d2 * d2));
               s1 += exp(lw - beta * sqrt(q + (d2 + 1) * (d2 + 1)));
-            }
+            };
+            for (int k = 0; k < nl; ++k) add(s_src[3 * k], s_src[3 * k + 1], s_src[3 * k + 2], (double)s_lw[k]);
+            for (int k = nl; k < a.n_src; ++k) add(a.src[3 * k], a.src[3 * k + 1], a.src[3 * k + 2], logw(k));
           }
           m0 = (R)s0;
           m1 = (R)s1;
@@ -377,7 +383,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
       return;
     }
     const double bm = block_max((double)mlr);
-    if (tid == 0) a.mu[(size_t)(MODE == X_TERM ? term : 0) * a.nbx + bid] = bm;
+    if (tid == 0) a.mu[(size_t)(TERMLIKE ? term : 0) * a.nbx + bid] = bm;
 #pragma unroll
     for (int j = 8; j < 16; ++j) v[j] = cmake<C>((R)0, (R)0);
   }
