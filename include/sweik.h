@@ -160,6 +160,41 @@ sweik_status sweik_solve_adjoint(sweik_plan plan, const void *f,
                                  const void *dLdS, void *dLdf, void *ws,
                                  size_t ws_bytes, void *stream);
 
+/* ---- path backtracking (Section 6, path planning) -------------------------
+ * From each start point, integrate dx/dt = -grad S / |grad S| (eq.
+ * PathPlanning-backTrackOnS) on a computed S, in grid units (position x_d
+ * is grid index x_d along axis d, C order):
+ *   - the node gradient of S is its central difference along each axis
+ *     (one-sided at the first and last node); the gradient at x is the
+ *     multilinear interpolation of the node gradients of x's cell;
+ *   - each step is a classical fourth-order Runge-Kutta step of length
+ *     `step` on the unit field -g/|g|; stage positions and new points are
+ *     clamped to the box [0, dims[d] - 1];
+ *   - a path stops when it comes within `radius` of a source (status 0),
+ *     after max_steps steps (1), or where the gradient vanishes or is not
+ *     finite, e.g. where S = +inf (2).  A start outside the box or not
+ *     finite records no point (status 3).
+ * Arguments:
+ *   ndim, dims  host: 2 or 3 axes, each 2 .. 2^20 points
+ *   prec        type of S: float32 (SWEIK_F32_SCALED) or float64
+ *   S           device, dims (as written by a solve)
+ *   src         device, int32 [n_src][ndim] (n_src >= 0)
+ *   start       device, float64 [n_paths][ndim]
+ *   max_steps   0 .. 2^20; step > 0 and radius >= 0, finite
+ *   path        device, float64 [n_paths][max_steps + 1][ndim] (output; the
+ *               first n_points[p] points of path p are written)
+ *   n_points    device, int32 [n_paths] (output)
+ *   status      device, int32 [n_paths] (output)
+ *   stream      hipStream_t
+ * Argument errors return SWEIK_EINVAL before anything is enqueued; nothing
+ * is allocated and the stream is not synchronised.  All arithmetic is
+ * float64.  n_paths = 0 is a no-op. */
+sweik_status sweik_backtrack(int32_t ndim, const int64_t *dims, sweik_precision prec,
+                             const void *S, const int32_t *src, int32_t n_src,
+                             const double *start, int32_t n_paths, int32_t max_steps,
+                             double step, double radius, double *path, int32_t *n_points,
+                             int32_t *status, void *stream);
+
 /* ---- measurement ---------------------------------------------------------
  * Kernel classes of a solve, for sweik_solve_timed. */
 enum {

@@ -7,14 +7,15 @@ built, importing the solver functions raises.
 
     S = solve(f, src, h, hbar, T)                 # f: cuda float32/float64
     S, info = solve(..., return_info=True)
+    path, n_points, status = backtrack(S, src, start)   # Section 6 paths
 """
 from __future__ import annotations
 
 from ._native import (  # noqa: F401
     SweikError, Plan, Batch, solve, solve_adjoint, solve_with_checkpoint,
-    EikonalFn, eikonal, batch_solve, lib_path, load_library, INFO_FLAGS,
+    EikonalFn, eikonal, batch_solve, lib_path, load_library, INFO_FLAGS, backtrack, TRACE_STATUS,
 )
 
 __all__ = ["SweikError", "Plan", "Batch", "solve", "solve_adjoint",
            "solve_with_checkpoint", "EikonalFn", "eikonal", "batch_solve",
-           "lib_path", "load_library", "INFO_FLAGS"]
+           "lib_path", "load_library", "INFO_FLAGS", "backtrack", "TRACE_STATUS"]

@@ -88,6 +88,9 @@ def load_library():
     lib.sweik_autotune.argtypes = [vp, vp, sz, vp]
     lib.sweik_plan_get_schedule.argtypes = [vp, C.POINTER(_Schedule)]
     lib.sweik_plan_set_schedule.argtypes = [vp, C.POINTER(_Schedule)]
+    lib.sweik_backtrack.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.c_int, vp, vp, C.c_int32,
+                                    vp, C.c_int32, C.c_int32, C.c_double, C.c_double, vp, vp,
+                                    vp, vp]
     lib.sweik_status_string.argtypes = [C.c_int]
     lib.sweik_status_string.restype = C.c_char_p
     lib.sweik_abi_version.restype = C.c_int32
@@ -294,6 +297,38 @@ def solve(f: torch.Tensor, src, h: float, hbar: float, T: int, ftilde_mode: str 
     if return_info:
         return S, _read_info(info)
     return S
+
+
+TRACE_STATUS = {0: "reached a source", 1: "max_steps", 2: "no gradient", 3: "start outside"}
+
+
+def backtrack(S: torch.Tensor, src, start, step: float = 0.5, radius: float = 1.0,
+              max_steps: int = 4096, stream=None):
+    """Paths of steepest descent on S (Section 6, path planning) from each
+    start point (grid coordinates, [n_paths, ndim]) to the sources (int
+    [n_src, ndim]).  Returns (path [n_paths, max_steps+1, ndim] float64,
+    n_points [n_paths] int32, status [n_paths] int32) on S's device; path p
+    holds n_points[p] valid points (status codes: TRACE_STATUS)."""
+    lib = load_library()
+    _check_f(S)
+    if S.dtype not in (torch.float32, torch.float64):
+        raise ValueError("S must be float32 or float64")
+    dev = S.device
+    ndim = S.dim()
+    d_src = torch.as_tensor(np.ascontiguousarray(np.asarray(src, np.int32).reshape(-1, ndim))).to(dev)
+    d_start = torch.as_tensor(np.asarray(start, np.float64).reshape(-1, ndim)).to(dev).contiguous()
+    n_paths = d_start.shape[0]
+    path = torch.empty((n_paths, max_steps + 1, ndim), dtype=torch.float64, device=dev)
+    n_points = torch.empty(n_paths, dtype=torch.int32, device=dev)
+    status = torch.empty(n_paths, dtype=torch.int32, device=dev)
+    dims = (C.c_int64 * 3)(*S.shape, *([0] * (3 - ndim)))
+    prec = 1 if S.dtype == torch.float64 else 0
+    rc = lib.sweik_backtrack(ndim, dims, prec, S.data_ptr(), d_src.data_ptr(), d_src.shape[0],
+                             d_start.data_ptr(), n_paths, int(max_steps), float(step),
+                             float(radius), path.data_ptr(), n_points.data_ptr(),
+                             status.data_ptr(), _stream_ptr(stream))
+    _check(rc, "sweik_backtrack")
+    return path, n_points, status
 
 
 def solve_with_checkpoint(f: torch.Tensor, src, h, hbar, T, ftilde_mode="nu", ftilde=None,

@@ -11,7 +11,8 @@ LIB = os.path.join(HERE, "libsweik.so")
 SOURCES = [os.path.join(HERE, "csrc", n) for n in (
     "api.hip", "k2d_row16_f32.hip", "k2d_row8_f32.hip", "k2d_row4_f32.hip", "k2d_col_f32.hip",
     "k2d_col4_f32.hip",
-    "k2d_row16_f64.hip", "k2d_row8_f64.hip", "k2d_col_f64.hip", "k3d_f32.hip", "k3d_f64.hip")]
+    "k2d_row16_f64.hip", "k2d_row8_f64.hip", "k2d_col_f64.hip", "k3d_f32.hip", "k3d_f64.hip",
+    "trace.hip")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -167,9 +167,11 @@ __device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[E], int t, int tid,
 // Row pass, all modes.
 //   ROW_GHAT  kernel table rows (evenly extended), forward real FFT
 //   ROW_PHI0  phi_0 from the sources, first forcing term, forward real FFT
-//   ROW_TERM  term `term`: inverse FFT, rescale, store the term; then either
-//             the next forcing term and its FFT, or (term == T) the sum of
-//             all terms in float64 and S = -hbar ln phi
+//   ROW_TERM  term `term` < T: inverse FFT, rescale, store the term, the
+//             next forcing term and its FFT
+//   ROW_LAST  term T: inverse FFT, the sum of all terms in float64 and
+//             S = -hbar ln phi
+//   ROW_SEED  transform of the source grid (phi_0 by FFT)
 //   ROW_ADJ0  adjoint start: lambda = -hbar dL/dS / phi, a_T = (-1)^T lambda
 //   ROW_ADJ   adjoint step `term` = i: b_i = kappa (*) a_i, dL/dgamma +=
 //             phi_{i-1} b_i, a_{i-1} = (-1)^{i-1} lambda + gamma b_i; at

@@ -142,3 +142,29 @@ def test_phi0_route_defaults_and_checks(lib):
     assert cube.schedule["phi0_fft"] == 0
     with pytest.raises(ValueError, match="unsupported"):
         cube.set_schedule(16, 16, phi0_fft=1)
+
+
+def test_backtrack_rejects_invalid_arguments(lib):
+    # every argument error returns SWEIK_EINVAL before any HIP call; a
+    # zero-path call is a no-op
+    vp = C.c_void_p
+    dims = (C.c_int64 * 3)(64, 64, 0)
+    ok = dict(ndim=2, dims=dims, prec=0, S=vp(16), src=vp(16), n_src=1, start=vp(16),
+              n_paths=4, max_steps=10, step=0.5, radius=1.0, path=vp(16), n_points=vp(16),
+              status=vp(16), stream=None)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return lib.sweik_backtrack(a["ndim"], a["dims"], a["prec"], a["S"], a["src"], a["n_src"],
+                                   a["start"], a["n_paths"], a["max_steps"], a["step"],
+                                   a["radius"], a["path"], a["n_points"], a["status"],
+                                   a["stream"])
+    bad = [dict(ndim=1), dict(ndim=4), dict(dims=None), dict(prec=7),
+           dict(dims=(C.c_int64 * 3)(1, 64, 0)), dict(n_src=-1), dict(n_paths=-1),
+           dict(max_steps=-1), dict(max_steps=(1 << 20) + 1), dict(step=0.0),
+           dict(step=float("nan")), dict(radius=-1.0), dict(radius=float("inf")),
+           dict(S=None), dict(src=None), dict(start=None), dict(path=None),
+           dict(n_points=None), dict(status=None)]
+    for kw in bad:
+        assert call(**kw) == 1, kw
+    assert call(n_paths=0, S=None, start=None, path=None) == 0
