@@ -18,6 +18,8 @@ Also reported on the same JSON line:
   solve3d          256^3 grid, f from 32 Gaussian blobs in [0.5, 2], one
                    source at the centre, hbar = 0.1, T = 16; FP32-scaled and
                    FP64, per-kernel classes and the dominant kernel's roofline
+  backtrack        256 descent paths on the main workload's S (Section 6),
+                   path points per second
   roofline         of the dominant kernel: algorithmic bytes per launch over
                    its HIP-event-timed duration; `traffic` from the committed
                    FETCH_SIZE / WRITE_SIZE counter summary when it was taken
@@ -297,6 +299,38 @@ def run_fwd_bwd(pk, torch, dev, steps, warmup):
             "precision": "fp32-scaled", "gradient_finite": ok, "schedule": plan.schedule}
 
 
+def run_backtrack(pk, torch, dev, steps, warmup):
+    """Backtracking (Section 6) of 256 paths from seeded start points on the
+    S of the 1024^2 main workload (step 0.5 cell, stop within 1 cell of a
+    source): one thread per path, so the figure of merit is path points per
+    second."""
+    import workloads
+    p = workloads.problem(2, 1024)
+    f = torch.as_tensor(p.f).to(dev)
+    S = pk.solve(f, p.src, p.h, p.hbar, p.T)
+    rng = np.random.default_rng(2024)
+    start = rng.uniform(0, 1023, size=(256, 2))
+    args = dict(step=0.5, radius=1.0, max_steps=8192)
+    for _ in range(max(1, warmup)):
+        path, npts, st = pk.backtrack(S, p.src, start, **args)
+    torch.cuda.synchronize()
+    s_ = torch.cuda.current_stream()
+    e0, e1 = _events(torch, s_)
+    e0.record(s_)
+    for _ in range(steps):
+        path, npts, st = pk.backtrack(S, p.src, start, **args)
+    e1.record(s_)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    npts = npts.cpu().numpy()
+    st = st.cpu().numpy()
+    return {"workload": "backtrack_noise2d_1024x1024_256paths", "paths": 256,
+            "path_points": int(npts.sum()), "max_points": int(npts.max()),
+            "reached_source": int((st == 0).sum()), "ms_per_call": ms,
+            "value": float(npts.sum()) / (ms * 1e-3), "unit": "path points/s",
+            "bound": "latency (one thread per path, dependent reads of S)"}
+
+
 def run_batched(pk, torch, dev, steps, warmup):
     """64 uneven instances, one HIP graph replay per step."""
     import workloads
@@ -478,7 +512,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip fwd+bwd and batched")
-    ap.add_argument("--only", choices=["fwd_bwd", "batched", "solve3d"],
+    ap.add_argument("--only", choices=["fwd_bwd", "batched", "solve3d", "backtrack"],
                     help="run one extra section alone and print its JSON (profiling runs)")
     ap.add_argument("--pmc-run", action="store_true")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH", "WRITE"))
@@ -514,7 +548,8 @@ def main():
     N = n0 * n1
 
     if args.only:
-        fn = {"fwd_bwd": run_fwd_bwd, "batched": run_batched, "solve3d": run_3d}[args.only]
+        fn = {"fwd_bwd": run_fwd_bwd, "batched": run_batched, "solve3d": run_3d,
+              "backtrack": run_backtrack}[args.only]
         print(json.dumps(fn(pk, torch, dev, args.steps, args.warmup)))
         return
 
@@ -572,6 +607,7 @@ def main():
         out["fwd_bwd"] = run_fwd_bwd(pk, torch, dev, max(3, args.steps // 2), 2)
         out["batched"] = run_batched(pk, torch, dev, max(3, args.steps // 4), 1)
         out["solve3d"] = run_3d(pk, torch, dev, max(3, args.steps // 4), 1)
+        out["backtrack"] = run_backtrack(pk, torch, dev, max(3, args.steps // 4), 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out))
