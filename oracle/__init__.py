@@ -10,6 +10,10 @@ What is computed, and which passage each step follows, is listed in
 functions (Section 3.2), phi_0 (eq. phi_0Solution), the recurrence
 (eqs. phiRecRelation / phi_i_Solution), the alternating sum (eq.
 phiSolution) and the logarithm (eq. SfromPhi); steps as in Table 1.
+
+Two numpy modules cover Section 6: ``oracle.trace`` (path backtracking on S)
+and ``oracle.fd`` (the finite-difference screened Poisson system, solved by a
+sparse direct factorisation).
 """
 from __future__ import annotations
 
