@@ -160,6 +160,43 @@ sweik_status sweik_solve_adjoint(sweik_plan plan, const void *f,
                                  const void *dLdS, void *dLdf, void *ws,
                                  size_t ws_bytes, void *stream);
 
+/* ---- finite-difference screened Poisson solve (Section 6) ----------------
+ * The paper's second method: eq. phiEquation discretised with the standard
+ * Laplacian (five-point in 2D, seven-point in 3D; phi = 0 outside the grid),
+ * the sparse system of eq. sparse-system,
+ *   (2D + (h f_m / hbar)^2) phi_m - sum_{grid neighbours n} phi_n = b_m,
+ * b = 1 at the sources and 0 elsewhere (eq. deltakron), then
+ * S = -hbar ln phi (eq. SfromPhi).  (The printed diagonal term f(X_i) is read
+ * as (h f / hbar)^2; with the printed right-hand side, phi at a source is a
+ * value of the discrete Green's function, so S there is O(hbar), not 0.)
+ * Solved matrix-free by conjugate gradients preconditioned with the
+ * diagonal, in float64 for either precision of f and S, until
+ * ||r|| <= rtol ||b|| or max_iter iterations.
+ *   plan      any plan (uses ndim, dims, h, hbar, n_src and the precision of
+ *             f and S; T and the reference forcing are not used)
+ *   f, src, S as sweik_solve (device)
+ *   ws        device workspace of ws_bytes >= sweik_fd_workspace_bytes(plan)
+ *             (about 56 bytes per grid point)
+ *   max_iter  0 .. 2^24; rtol >= 0, finite
+ *   info      HOST, nullable
+ * Unlike the FFT solve this call synchronises the stream: it reads a
+ * convergence flag from the device after every 64 iterations (so it cannot
+ * be captured into a graph).  Sources are distinct grid points; a source
+ * outside the grid sets SWEIK_FLAG_BAD_SOURCE and is ignored. */
+typedef struct {
+  int32_t iterations;   /* CG iterations taken */
+  int32_t converged;    /* 1 when ||r|| <= rtol ||b|| was reached */
+  double rel_residual;  /* ||r|| / ||b|| of the recursively updated residual */
+  int64_t n_nonpositive_phi; /* points with phi <= 0 (S = +inf) */
+  int32_t flags;        /* SWEIK_FLAG_* for f and the sources */
+  int32_t n_sources;    /* distinct sources inside the grid */
+} sweik_fd_info;
+
+size_t sweik_fd_workspace_bytes(sweik_plan plan);
+sweik_status sweik_fd_solve(sweik_plan plan, const void *f, const int32_t *src, void *S,
+                            void *ws, size_t ws_bytes, int32_t max_iter, double rtol,
+                            void *stream, sweik_fd_info *info);
+
 /* ---- path backtracking (Section 6, path planning) -------------------------
  * From each start point, integrate dx/dt = -grad S / |grad S| (eq.
  * PathPlanning-backTrackOnS) on a computed S, in grid units (position x_d

@@ -8,14 +8,16 @@ built, importing the solver functions raises.
     S = solve(f, src, h, hbar, T)                 # f: cuda float32/float64
     S, info = solve(..., return_info=True)
     path, n_points, status = backtrack(S, src, start)   # Section 6 paths
+    S_fd = fd_solve(f, src, h, hbar)                    # Section 6 FD system
 """
 from __future__ import annotations
 
 from ._native import (  # noqa: F401
     SweikError, Plan, Batch, solve, solve_adjoint, solve_with_checkpoint,
     EikonalFn, eikonal, batch_solve, lib_path, load_library, INFO_FLAGS, backtrack, TRACE_STATUS,
+    fd_solve,
 )
 
 __all__ = ["SweikError", "Plan", "Batch", "solve", "solve_adjoint",
            "solve_with_checkpoint", "EikonalFn", "eikonal", "batch_solve",
-           "lib_path", "load_library", "INFO_FLAGS", "backtrack", "TRACE_STATUS"]
+           "lib_path", "load_library", "INFO_FLAGS", "backtrack", "TRACE_STATUS", "fd_solve"]

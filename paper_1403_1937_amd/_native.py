@@ -46,6 +46,12 @@ class _Info(C.Structure):
                 ("scale_exp", C.c_int32 * (MAX_TERMS + 1))]
 
 
+class _FdInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("converged", C.c_int32),
+                ("rel_residual", C.c_double), ("n_nonpositive_phi", C.c_int64),
+                ("flags", C.c_int32), ("n_sources", C.c_int32)]
+
+
 _lib = None
 
 
@@ -91,6 +97,10 @@ def load_library():
     lib.sweik_backtrack.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.c_int, vp, vp, C.c_int32,
                                     vp, C.c_int32, C.c_int32, C.c_double, C.c_double, vp, vp,
                                     vp, vp]
+    lib.sweik_fd_workspace_bytes.argtypes = [vp]
+    lib.sweik_fd_workspace_bytes.restype = sz
+    lib.sweik_fd_solve.argtypes = [vp, vp, vp, vp, vp, sz, C.c_int32, C.c_double, vp,
+                                   C.POINTER(_FdInfo)]
     lib.sweik_status_string.argtypes = [C.c_int]
     lib.sweik_status_string.restype = C.c_char_p
     lib.sweik_abi_version.restype = C.c_int32
@@ -296,6 +306,31 @@ def solve(f: torch.Tensor, src, h: float, hbar: float, T: int, ftilde_mode: str 
     pl.solve(f, d_src, S, ws, None, info, stream, src_s=d_s)
     if return_info:
         return S, _read_info(info)
+    return S
+
+
+def fd_solve(f: torch.Tensor, src, h: float, hbar: float, max_iter: int = 50000,
+             rtol: float = 1e-12, return_info: bool = False, stream=None):
+    """The paper's second method (Section 6): S = -hbar ln phi with phi from
+    the finite-difference screened Poisson system (eq. sparse-system), solved
+    by diagonally preconditioned conjugate gradients on the GPU in float64.
+    Synchronises the stream.  With return_info, also a dict with the
+    iteration count, convergence and the final relative residual."""
+    lib = load_library()
+    _check_f(f)
+    n_src = len(src)
+    pl = _plan_for(f, n_src, h, hbar, 0, "nu", None)
+    d_src = _src_to_device(src, pl, f.device)
+    S = torch.empty_like(f)
+    nb = int(lib.sweik_fd_workspace_bytes(pl.handle))
+    ws = torch.empty(nb, dtype=torch.uint8, device=f.device)
+    info = _FdInfo()
+    rc = lib.sweik_fd_solve(pl.handle, f.data_ptr(), d_src.data_ptr(), S.data_ptr(),
+                            ws.data_ptr(), nb, int(max_iter), float(rtol), _stream_ptr(stream),
+                            C.byref(info))
+    _check(rc, "sweik_fd_solve")
+    if return_info:
+        return S, {k: getattr(info, k) for k, _ in _FdInfo._fields_}
     return S
 
 

@@ -12,7 +12,7 @@ SOURCES = [os.path.join(HERE, "csrc", n) for n in (
     "api.hip", "k2d_row16_f32.hip", "k2d_row8_f32.hip", "k2d_row4_f32.hip", "k2d_col_f32.hip",
     "k2d_col4_f32.hip",
     "k2d_row16_f64.hip", "k2d_row8_f64.hip", "k2d_col_f64.hip", "k3d_f32.hip", "k3d_f64.hip",
-    "trace.hip")]
+    "trace.hip", "fd.hip")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
