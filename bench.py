@@ -20,6 +20,9 @@ Also reported on the same JSON line:
                    FP64, per-kernel classes and the dominant kernel's roofline
   backtrack        256 descent paths on the main workload's S (Section 6),
                    path points per second
+  fd               the finite-difference screened Poisson system of the main
+                   workload (Section 6, the paper's second method) by CG in
+                   float64
   roofline         of the dominant kernel: algorithmic bytes per launch over
                    its HIP-event-timed duration; `traffic` from the committed
                    FETCH_SIZE / WRITE_SIZE counter summary when it was taken
@@ -331,6 +334,33 @@ def run_backtrack(pk, torch, dev, steps, warmup):
             "bound": "latency (one thread per path, dependent reads of S)"}
 
 
+def run_fd(pk, torch, dev, steps, warmup):
+    """The paper's second method (Section 6): the finite-difference screened
+    Poisson system of the 1024^2 main workload, CG in float64 to
+    ||r|| <= 1e-10 ||b||.  Bytes per CG iteration (float64 vectors of N):
+    apply reads z, p_prev, diag and writes p, q (40 N); update reads x, p,
+    r, q, diag and writes x, r, z (64 N)."""
+    import workloads
+    p = workloads.problem(2, 1024)
+    N = p.dims[0] * p.dims[1]
+    f = torch.as_tensor(p.f).to(dev, torch.float64)
+    for _ in range(max(1, warmup)):
+        S, info = pk.fd_solve(f, p.src, p.h, p.hbar, rtol=1e-10, return_info=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        S, info = pk.fd_solve(f, p.src, p.h, p.hbar, rtol=1e-10, return_info=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps  # the call synchronises: host clock
+    it = info["iterations"]
+    per_it = ms / max(it, 1)
+    return {"workload": "fd_noise2d_1024x1024_src16", "value": N / (ms * 1e-3),
+            "unit": "grid pts/s", "ms_per_step": ms, "iterations": it,
+            "rel_residual": info["rel_residual"], "us_per_iteration": per_it * 1e3,
+            "iteration_alg_bytes": 104 * N,
+            "iteration_GBps": 104 * N / (per_it * 1e-3) / 1e9, "precision": "fp64"}
+
+
 def run_batched(pk, torch, dev, steps, warmup):
     """64 uneven instances, one HIP graph replay per step."""
     import workloads
@@ -512,7 +542,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip fwd+bwd and batched")
-    ap.add_argument("--only", choices=["fwd_bwd", "batched", "solve3d", "backtrack"],
+    ap.add_argument("--only", choices=["fwd_bwd", "batched", "solve3d", "backtrack", "fd"],
                     help="run one extra section alone and print its JSON (profiling runs)")
     ap.add_argument("--pmc-run", action="store_true")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH", "WRITE"))
@@ -549,7 +579,7 @@ def main():
 
     if args.only:
         fn = {"fwd_bwd": run_fwd_bwd, "batched": run_batched, "solve3d": run_3d,
-              "backtrack": run_backtrack}[args.only]
+              "backtrack": run_backtrack, "fd": run_fd}[args.only]
         print(json.dumps(fn(pk, torch, dev, args.steps, args.warmup)))
         return
 
@@ -608,6 +638,7 @@ def main():
         out["batched"] = run_batched(pk, torch, dev, max(3, args.steps // 4), 1)
         out["solve3d"] = run_3d(pk, torch, dev, max(3, args.steps // 4), 1)
         out["backtrack"] = run_backtrack(pk, torch, dev, max(3, args.steps // 4), 1)
+        out["fd"] = run_fd(pk, torch, dev, 3, 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p)
     print(json.dumps(out))

@@ -166,27 +166,35 @@ __global__ void __launch_bounds__(kFdThreads) k_fd_apply(FdArgs a, int k) {
   double *__restrict__ pout = a.p[(k + 1) & 1];
   const double *__restrict__ z = a.z;
   auto dirv = [&](long long j) { return z[j] + beta * pin[j]; };
+  // one grid line (along the last axis) per block at a time: the line's
+  // coordinates on the other axes cost one division per line, not per point
+  const int nl = a.n[D - 1];
+  const long long lines = a.N / nl;
   double acc = 0.0;
-  for (long long i = (long long)blockIdx.x * kFdThreads + threadIdx.x; i < a.N;
-       i += (long long)kFdBlocks * kFdThreads) {
+  for (long long line = blockIdx.x; line < lines; line += kFdBlocks) {
     int m[D];
-    long long rem = i;
+    long long rem = line;
 #pragma unroll
-    for (int e = 0; e < D - 1; ++e) {
-      m[e] = (int)(rem / a.st[e]);
-      rem -= (long long)m[e] * a.st[e];
+    for (int e = D - 2; e >= 0; --e) {
+      const long long qd = rem / a.n[e];
+      m[e] = (int)(rem - qd * a.n[e]);
+      rem = qd;
     }
-    m[D - 1] = (int)rem;
-    const double pc = dirv(i);
-    double v = a.d[i] * pc;
+    const long long base = line * nl;
+    for (int c = threadIdx.x; c < nl; c += kFdThreads) {
+      const long long i = base + c;
+      m[D - 1] = c;
+      const double pc = dirv(i);
+      double v = a.d[i] * pc;
 #pragma unroll
-    for (int e = 0; e < D; ++e) {
-      if (m[e] > 0) v -= dirv(i - a.st[e]);
-      if (m[e] < a.n[e] - 1) v -= dirv(i + a.st[e]);
+      for (int e = 0; e < D; ++e) {
+        if (m[e] > 0) v -= dirv(i - a.st[e]);
+        if (m[e] < a.n[e] - 1) v -= dirv(i + a.st[e]);
+      }
+      pout[i] = pc;
+      a.q[i] = v;
+      acc += pc * v;
     }
-    pout[i] = pc;
-    a.q[i] = v;
-    acc += pc * v;
   }
   double t[1] = {acc};
   block_sums(t);
