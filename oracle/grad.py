@@ -1,0 +1,124 @@
+"""Plain FP64 oracle of the full gradient of a loss L(S) of the 2D solve.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).  Not in the paper: the
+derivative of the steps of Table 1 with respect to all of their inputs,
+
+  beta = ftilde h / hbar,  gamma = f^2 / ftilde^2 - 1,  w_k = exp(-s_k / hbar),
+  phi_0 = sum_k w_k exp(-beta |m - y_k|)                 (eq. phi_0Solution)
+  phi_i = kappa_beta (*) (gamma phi_{i-1})               (eq. phiRecRelation)
+  phi = sum_i (-1)^i phi_i,  S = -hbar ln phi            (eqs. phiSolution, SfromPhi)
+
+with ftilde a function of f (nu = sqrt((fmin^2 + fmax^2)/2), or sup f, or a
+constant: Section 5.1).  dL/df is the adjoint with ftilde fixed plus
+dL/dftilde times a subgradient of ftilde(f): the derivative with respect to
+fmin (fmax) goes to the first grid point, in C order, where f attains it.
+
+The three scalar paths (beta through the kernel and phi_0, ftilde through
+gamma, hbar through the weights) are propagated forward: one tangent series
+per path, each convolution done by the oracle's convolution (own FFT) or, for
+the kernel's beta-derivative, by a numpy FFT of its even extension.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+
+import oracle
+
+
+def kappa_dbeta(dims, beta: float) -> np.ndarray:
+    """d kappa / d beta on the orthant 0 <= m_d < n_d (2D):
+    (beta/pi) K0(beta r) - (beta^2 r / 2 pi) K1(beta r) off the origin; at
+    the origin the beta-derivative of the ball average 1 - a K1(a),
+    a = beta/sqrt(pi), which is (beta/pi) K0(beta/sqrt(pi))."""
+    n0, n1 = (int(d) for d in dims)
+    m0, m1 = np.meshgrid(np.arange(n0, dtype=np.float64), np.arange(n1, dtype=np.float64),
+                         indexing="ij")
+    r = np.hypot(m0, m1)
+    out = np.zeros((n0, n1))
+    nz = r > 0
+    x = beta * r[nz]
+    out[nz] = beta / np.pi * oracle.k0(x) - beta * beta * r[nz] / (2 * np.pi) * oracle.k1(x)
+    out[0, 0] = beta / np.pi * float(oracle.k0(beta / np.sqrt(np.pi)))
+    return out
+
+
+def conv_table(x: np.ndarray, table: np.ndarray) -> np.ndarray:
+    """Linear convolution of x with the even extension of an orthant table,
+    by numpy FFTs on the zero-padded grid."""
+    dims = x.shape
+    M = oracle.pad_sizes(dims)
+    K = np.zeros(M)
+    n0, n1 = dims
+    for s0 in (1, -1):
+        for s1 in (1, -1):
+            i0 = (s0 * np.arange(n0)) % M[0]
+            i1 = (s1 * np.arange(n1)) % M[1]
+            K[np.ix_(i0, i1)] = table
+    X = np.zeros(M)
+    X[:n0, :n1] = x
+    y = np.fft.ifft2(np.fft.fft2(X) * np.fft.fft2(K)).real
+    return y[:n0, :n1]
+
+
+def full_gradient(f: np.ndarray, src: np.ndarray, h: float, hbar: float, T: int,
+                  dLdS: np.ndarray, ft_mode: str = "nu", ftilde: Optional[float] = None,
+                  src_s: Optional[np.ndarray] = None) -> dict:
+    f = np.asarray(f, np.float64)
+    dims = f.shape
+    src = np.asarray(src, np.int32).reshape(-1, 2)
+    dLdS = np.asarray(dLdS, np.float64)
+    lo, hi = float(f.min()), float(f.max())
+    ft = {"nu": np.sqrt(0.5 * (lo * lo + hi * hi)), "fmax": hi, "given": ftilde}[ft_mode]
+    beta = ft * h / hbar
+    gam = (f - ft) * (f + ft) / (ft * ft)
+    s = np.zeros(len(src)) if src_s is None else np.asarray(src_s, np.float64)
+    w = np.exp(-s / hbar)
+
+    # forward series
+    phis = [oracle.phi0(dims, beta, src, w)]
+    for _ in range(T):
+        phis.append(oracle.conv(gam * phis[-1], beta))
+    sgn = [(-1.0) ** i for i in range(T + 1)]
+    phi = sum(sg * p for sg, p in zip(sgn, phis))
+    S = -hbar * np.log(phi)
+    lam = -hbar * dLdS / phi
+
+    # reverse sweep with ftilde fixed: a_i = dL/dphi_i
+    a = sgn[T] * lam
+    dLdg = np.zeros(dims)
+    for i in range(T, 0, -1):
+        b = oracle.conv(a, beta)
+        dLdg += phis[i - 1] * b
+        a = sgn[i - 1] * lam + gam * b
+    dLdf = dLdg * 2.0 * f / (ft * ft)
+
+    # forward tangents of the three scalar paths
+    m0, m1 = np.meshgrid(np.arange(dims[0], dtype=np.float64),
+                         np.arange(dims[1], dtype=np.float64), indexing="ij")
+    dist = [np.hypot(m0 - y[0], m1 - y[1]) for y in src]
+    ex = [np.exp(-beta * d) for d in dist]
+    dkap = kappa_dbeta(dims, beta)
+    dgam = -2.0 * f * f / ft ** 3
+    t = [-sum(wk * d * e for wk, d, e in zip(w, dist, ex))]            # d phi_i / d beta
+    u = [np.zeros(dims)]                                                # d phi_i / d ftilde (gamma)
+    v = [sum(wk * sk / hbar ** 2 * e for wk, sk, e in zip(w, s, ex))]  # d phi_i / d hbar (weights)
+    for i in range(1, T + 1):
+        t.append(conv_table(gam * phis[i - 1], dkap) + oracle.conv(gam * t[-1], beta))
+        u.append(oracle.conv(dgam * phis[i - 1] + gam * u[-1], beta))
+        v.append(oracle.conv(gam * v[-1], beta))
+    dLdbeta = float(np.sum(lam * sum(sg * x for sg, x in zip(sgn, t))))
+    dLdft_gamma = float(np.sum(lam * sum(sg * x for sg, x in zip(sgn, u))))
+    dLdhbar_w = float(np.sum(lam * sum(sg * x for sg, x in zip(sgn, v))))
+
+    dLdhbar = float(np.sum(dLdS * S / hbar)) - beta / hbar * dLdbeta + dLdhbar_w
+    dLdft = h / hbar * dLdbeta + dLdft_gamma
+    flat = dLdf.reshape(-1)
+    if ft_mode == "nu":
+        flat[int(np.argmin(f))] += dLdft * lo / (2.0 * ft)
+        flat[int(np.argmax(f))] += dLdft * hi / (2.0 * ft)
+    elif ft_mode == "fmax":
+        flat[int(np.argmax(f))] += dLdft
+    return {"dLdf": dLdf, "dLdhbar": dLdhbar, "dLdftilde": dLdft, "dLdbeta": dLdbeta,
+            "S": S, "ftilde": ft, "beta": beta}
