@@ -160,6 +160,30 @@ sweik_status sweik_solve_adjoint(sweik_plan plan, const void *f,
                                  const void *dLdS, void *dLdf, void *ws,
                                  size_t ws_bytes, void *stream);
 
+/* Full gradient (2D) of a loss L(S) of a solve: not in the paper, the
+ * derivative of all of its steps.  With beta = ftilde h / hbar,
+ * gamma = f^2/ftilde^2 - 1 and w_k = exp(-s_k / hbar):
+ *   dLdf   device, dims, type of f (output): dL/df including the dependence
+ *          of ftilde on f (Section 5.1): the adjoint of sweik_solve_adjoint
+ *          plus dL/dftilde times a subgradient of ftilde(f), which for nu
+ *          puts fmin/(2 ftilde) on the first grid point (C order) where f is
+ *          smallest and fmax/(2 ftilde) on the first where it is largest; for
+ *          sup f, 1 on the first maximum; nothing for a given ftilde
+ *   grads  device, 4 doubles, nullable (output): dL/dhbar (through beta, the
+ *          weights and the logarithm), dL/dftilde, dL/dbeta, 0
+ *   src_s  device, nullable: the source values of the forward solve
+ *          (sweik_solve_seeded); ckpt its checkpoint
+ *   ws     device workspace of ws_bytes >= sweik_adjoint_full_workspace_bytes
+ * The beta-derivative of the kernel (2D: (beta/pi) K0(x) - (beta/2pi) x
+ * K1(x), x = beta|m|; at the origin that of the ball average) is convolved
+ * with every adjoint term, so the sweep costs about 1.7 adjoints.
+ * SWEIK_EUNSUPPORTED in 3D. */
+size_t sweik_adjoint_full_workspace_bytes(sweik_plan plan);
+sweik_status sweik_solve_adjoint_full(sweik_plan plan, const void *f, const int32_t *src,
+                                      const void *src_s, const void *ckpt, const void *dLdS,
+                                      void *dLdf, double *grads, void *ws, size_t ws_bytes,
+                                      void *stream);
+
 /* ---- finite-difference screened Poisson solve (Section 6) ----------------
  * The paper's second method: eq. phiEquation discretised with the standard
  * Laplacian (five-point in 2D, seven-point in 3D; phi = 0 outside the grid),

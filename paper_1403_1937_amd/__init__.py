@@ -15,9 +15,9 @@ from __future__ import annotations
 from ._native import (  # noqa: F401
     SweikError, Plan, Batch, solve, solve_adjoint, solve_with_checkpoint,
     EikonalFn, eikonal, batch_solve, lib_path, load_library, INFO_FLAGS, backtrack, TRACE_STATUS,
-    fd_solve,
+    fd_solve, solve_gradient,
 )
 
 __all__ = ["SweikError", "Plan", "Batch", "solve", "solve_adjoint",
            "solve_with_checkpoint", "EikonalFn", "eikonal", "batch_solve",
-           "lib_path", "load_library", "INFO_FLAGS", "backtrack", "TRACE_STATUS", "fd_solve"]
+           "lib_path", "load_library", "INFO_FLAGS", "backtrack", "TRACE_STATUS", "fd_solve", "solve_gradient"]

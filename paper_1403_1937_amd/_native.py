@@ -97,6 +97,9 @@ def load_library():
     lib.sweik_backtrack.argtypes = [C.c_int32, C.POINTER(C.c_int64), C.c_int, vp, vp, C.c_int32,
                                     vp, C.c_int32, C.c_int32, C.c_double, C.c_double, vp, vp,
                                     vp, vp]
+    lib.sweik_adjoint_full_workspace_bytes.argtypes = [vp]
+    lib.sweik_adjoint_full_workspace_bytes.restype = sz
+    lib.sweik_solve_adjoint_full.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.sweik_fd_workspace_bytes.argtypes = [vp]
     lib.sweik_fd_workspace_bytes.restype = sz
     lib.sweik_fd_solve.argtypes = [vp, vp, vp, vp, vp, sz, C.c_int32, C.c_double, vp,
@@ -234,6 +237,20 @@ class Plan:
             self._h, f.data_ptr(), src.data_ptr(), ckpt.data_ptr(), dLdS.data_ptr(),
             dLdf.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(stream)),
             "sweik_solve_adjoint")
+
+    def adjoint_full(self, f, src, ckpt, dLdS, dLdf, grads, ws, src_s=None, stream=None):
+        """Full gradient (dLdf with the ftilde path; grads: 4 float64 device
+        values dL/dhbar, dL/dftilde, dL/dbeta, 0) into caller buffers; ws
+        must hold adjoint_full_workspace_bytes."""
+        _check(self._lib.sweik_solve_adjoint_full(
+            self._h, f.data_ptr(), src.data_ptr(),
+            src_s.data_ptr() if src_s is not None else None, ckpt.data_ptr(), dLdS.data_ptr(),
+            dLdf.data_ptr(), grads.data_ptr() if grads is not None else None, ws.data_ptr(),
+            ws.numel(), _stream_ptr(stream)), "sweik_solve_adjoint_full")
+
+    @property
+    def adjoint_full_workspace_bytes(self) -> int:
+        return int(self._lib.sweik_adjoint_full_workspace_bytes(self._h))
 
     def autotune(self, ws: torch.Tensor, stream=None) -> int:
         """Time the candidate schedules on `ws` (overwritten) and keep the
@@ -389,6 +406,28 @@ def solve_adjoint(f: torch.Tensor, src, h, hbar, T, dLdS: torch.Tensor, ftilde_m
     g = torch.empty_like(f)
     pl.adjoint(f, d_src, ck, dLdS.contiguous(), g, ws, stream)
     return g
+
+
+def solve_gradient(f: torch.Tensor, src, h, hbar, T, dLdS: torch.Tensor, ftilde_mode="nu",
+                   ftilde=None, src_s=None, stream=None):
+    """Full gradient of a loss with gradient dLdS w.r.t. S (2D): returns
+    (dL/df including the dependence of ftilde on f, {"dLdhbar", "dLdftilde",
+    "dLdbeta"}).  src_s: values of S at the sources (default 0)."""
+    _check_f(f)
+    pl = _plan_for(f, len(src), h, hbar, T, ftilde_mode, ftilde)
+    d_src = _src_to_device(src, pl, f.device)
+    d_s = None
+    if src_s is not None:
+        d_s = torch.as_tensor(np.asarray(src_s, np.float64)).to(f.device, f.dtype).contiguous()
+    S = torch.empty_like(f)
+    ws = torch.empty(pl.adjoint_full_workspace_bytes, dtype=torch.uint8, device=f.device)
+    ck = pl.checkpoint(f.device)
+    pl.solve(f, d_src, S, ws, ck, None, stream, src_s=d_s)
+    g = torch.empty_like(f)
+    grads = torch.zeros(4, dtype=torch.float64, device=f.device)
+    pl.adjoint_full(f, d_src, ck, dLdS.contiguous(), g, grads, ws, d_s, stream)
+    v = grads.cpu().tolist()
+    return g, {"dLdhbar": v[0], "dLdftilde": v[1], "dLdbeta": v[2]}
 
 
 class EikonalFn(torch.autograd.Function):

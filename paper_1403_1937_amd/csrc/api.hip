@@ -146,7 +146,7 @@ sweik_status plan2d(sweik_plan_s *pl) {
   g.nb = (g.n0 + g.RB - 1) / g.RB;
   // every pass must fit the work-group LDS limit
   const bool f64 = p.prec == SWEIK_F64;
-  for (int mode = ROW_GHAT; mode <= ROW_LAST; ++mode) {
+  for (int mode = ROW_GHAT; mode <= ROW_ADJ_B; ++mode) {
     if (!(f64 ? row_fits<double>(g.H1, mode) : row_fits<float>(g.H1, mode)))
       return SWEIK_EUNSUPPORTED;
   }
@@ -189,6 +189,10 @@ sweik_status plan2d(sweik_plan_s *pl) {
   L.lam = take((size_t)esz * N);
   L.gam = take((size_t)esz * N);
   L.total = off;
+  L.fg_spec2 = take((size_t)csz * g.nb * g.ldk * g.RB);
+  L.fg_part = take(sizeof(double) * kGradSlots * g.nbr);
+  L.fg_ext = take(sizeof(long long) * 2 * kRedBlocks);
+  L.fg_total = off;
   off = 0;
   L.ck_expo = take(sizeof(int) * (SWEIK_MAX_TERMS + 1));
   L.ck_par = take(sizeof(Params));
@@ -243,6 +247,8 @@ Args2<R> make_args2(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.k0tab = bessel_cheb_k0();
   a.dLdS = nullptr;
   a.dLdf = nullptr;
+  a.spec2 = nullptr;
+  a.gpart = nullptr;
   a.info = info;
   char *c = (char *)ckpt;
   if (c) {  // the kernel spectrum and scalars live in the checkpoint
@@ -350,6 +356,52 @@ sweik_status enqueue2d_adjoint(const sweik_plan_s *pl, const void *f, const int3
   return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
 
+
+// Full gradient (2D): the adjoint sweep of enqueue2d_adjoint, with every
+// convolution of a_i done twice (with the kernel and with its
+// beta-derivative), the scalar partial sums in the row passes, then the
+// argmin / argmax of f and the scalar derivatives.
+template <typename R>
+sweik_status enqueue2d_adjoint_full(const sweik_plan_s *pl, const void *f, const int32_t *src,
+                                    const void *src_s, const void *ckpt, const void *dLdS,
+                                    void *dLdf, double *grads, void *ws, hipStream_t st) {
+  const Geo2 &g = pl->g2;
+  const Layout &L = pl->ws;
+  char *w = (char *)ws;
+  Args2<R> a = make_args2<R>(pl, f, src, nullptr, ws, const_cast<void *>(ckpt), nullptr);
+  a.src_s = (const R *)src_s;
+  a.dLdS = (const R *)dLdS;
+  a.dLdf = (R *)dLdf;
+  a.spec2 = (cplx<R> *)(w + L.fg_spec2);
+  a.gpart = (double *)(w + L.fg_part);
+  const long long N = (long long)g.n0 * g.n1;
+  const dim3 grow(g.nbr), gcol(g.ncw);
+  // the same arguments with the beta-derivative convolution's spectra
+  Args2<R> ab = a;
+  ab.spec = a.spec2;
+  ab.g = (R *)(w + L.g0);
+  hipError_t err = launch_adj_prep<R>((const R *)dLdS, (const double *)a.ck_phi, N,
+                                      pl->p.hbar, a.red, (cplx<R> *)a.tw, g.lmax, st);
+  if (pl->p.T == 0) {
+    if (err == hipSuccess) err = launch_fill<R>((R *)dLdf, N, (R)0, st);
+    if (err == hipSuccess) err = launch_row2<R>(ROW_ADJ0_B, g.H1, g.erow, grow, st, a, 0);
+  } else {
+    // spectrum of dkappa/dbeta (rows into spec2, columns into g0)
+    if (err == hipSuccess) err = launch_row2<R>(ROW_DGHAT, g.H1, g.erow, grow, st, ab, 0);
+    if (err == hipSuccess) err = launch_col2<R>(COL_GHAT, g.M0, g.ecol, gcol, st, ab);
+    if (err == hipSuccess) err = launch_row2<R>(ROW_ADJ0_B, g.H1, g.erow, grow, st, a, pl->p.T);
+    for (int i = pl->p.T; i >= 1 && err == hipSuccess; --i) {
+      err = launch_col2<R>(COL_CONV, g.M0, g.ecol, gcol, st, a);
+      if (err == hipSuccess) err = launch_col2<R>(COL_CONV, g.M0, g.ecol, gcol, st, ab);
+      if (err == hipSuccess) err = launch_row2<R>(ROW_ADJ_B, g.H1, g.erow, grow, st, a, i);
+    }
+  }
+  if (err == hipSuccess)
+    err = launch_adj_full_finish<R>((const R *)f, N, a.par, a.gpart, g.nbr,
+                                    (long long *)(w + L.fg_ext), pl->p.ft_mode, pl->p.h,
+                                    pl->p.hbar, (R *)dLdf, grads, st);
+  return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
+}
 
 // Extra complex elements between the planes of the 3D spectrum s2.
 constexpr long long kS2PlanePad = 16;
@@ -862,6 +914,24 @@ sweik_status sweik_solve_adjoint(sweik_plan plan, const void *f, const int32_t *
                : enqueue2d_adjoint<float>(plan, f, src, ckpt, dLdS, dLdf, ws, st);
   }
   return SWEIK_EUNSUPPORTED;
+}
+
+size_t sweik_adjoint_full_workspace_bytes(sweik_plan plan) {
+  if (!plan || plan->p.ndim != 2) return 0;
+  return plan->ws.fg_total;
+}
+
+sweik_status sweik_solve_adjoint_full(sweik_plan plan, const void *f, const int32_t *src,
+                                      const void *src_s, const void *ckpt, const void *dLdS,
+                                      void *dLdf, double *grads, void *ws, size_t ws_bytes,
+                                      void *stream) {
+  if (!plan || !f || !src || !ckpt || !dLdS || !dLdf || !ws) return SWEIK_EINVAL;
+  if (plan->p.ndim != 2) return SWEIK_EUNSUPPORTED;
+  if (ws_bytes < plan->ws.fg_total) return SWEIK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  return plan->p.prec == SWEIK_F64
+             ? enqueue2d_adjoint_full<double>(plan, f, src, src_s, ckpt, dLdS, dLdf, grads, ws, st)
+             : enqueue2d_adjoint_full<float>(plan, f, src, src_s, ckpt, dLdS, dLdf, grads, ws, st);
 }
 
 sweik_status sweik_batch_create(const sweik_problem *problems, int32_t count, sweik_batch *out) {

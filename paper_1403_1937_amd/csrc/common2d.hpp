@@ -36,6 +36,7 @@
 #include "green.hpp"
 #include "sweik.h"
 
+#include <climits>
 #include <type_traits>
 
 namespace sweik {
@@ -86,7 +87,18 @@ template <typename R> struct Args2 {
   int *ck_expo;  // T+1
   double *ck_phi;// n0 x n1
   R *ck_terms;   // T x n0 x n1 series-term mantissas (read by the adjoint)
+  // full gradient
+  cplx<R> *spec2;  // spectrum convolved with the kernel's beta-derivative
+  double *gpart;   // kGradSlots x nbr per-work-group partial sums
 };
+
+// Per-work-group partial sums of the full gradient (each slot nbr long):
+//   G_S   sum dL/dS * S / hbar                  (hbar in S = -hbar ln phi)
+//   G_C   sum over terms of <c_i, gamma phi_{i-1}>, c_i = dkappa/dbeta (*) a_i
+//   G_B0  <a_0, d phi_0 / d beta>
+//   G_H0  <a_0, d phi_0 / d hbar> through the weights exp(-s_k / hbar)
+//   G_GF  sum dL/dgamma * f^2                   (gamma = f^2 / ftilde^2 - 1)
+enum { G_S = 0, G_C = 1, G_B0 = 2, G_H0 = 3, G_GF = 4, kGradSlots = 5 };
 
 // ---------------------------------------------------------------------------
 // prep: partial min / max / validity of f, and the twiddle table
@@ -226,6 +238,25 @@ __device__ inline double block_max(double x) {
   return x;
 }
 
+// sums of K doubles over the block (every thread gets them)
+template <int K> __device__ inline void block_sums_d(double (&v)[K]) {
+  __shared__ double s[K][16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) s[k][wid] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double x = s[k][0];
+    for (int w = 1; w < nw; ++w) x += s[k][w];
+    v[k] = x;
+  }
+}
+
 __device__ inline long long block_sum_ll(long long x) {
   __shared__ long long s[16];
   x = wave_sum(x);
@@ -293,6 +324,8 @@ template <typename R> __device__ __forceinline__ Args2<R> item_args(const BatchI
   a.ck_expo = as_global(a.ck_expo);
   a.ck_phi = as_global(a.ck_phi);
   a.ck_terms = as_global(a.ck_terms);
+  a.spec2 = as_global(a.spec2);
+  a.gpart = as_global(a.gpart);
   return a;
 }
 

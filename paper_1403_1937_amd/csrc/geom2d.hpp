@@ -20,8 +20,12 @@ namespace sweik {
 // ROW_LAST is the pass after the last convolution (no forcing, no forward
 // transform: the float64 sum of the stored terms and the log); it is its own
 // kernel so that the term passes are not sized for its registers.
+// ROW_DGHAT, ROW_ADJ0_B and ROW_ADJ_B serve the full gradient: the kernel
+// table's beta-derivative, and the adjoint passes that also carry the
+// convolutions with it and the scalar partial sums.
 enum RowMode {
-  ROW_GHAT = 0, ROW_PHI0 = 1, ROW_TERM = 2, ROW_ADJ0 = 3, ROW_ADJ = 4, ROW_SEED = 5, ROW_LAST = 6
+  ROW_GHAT = 0, ROW_PHI0 = 1, ROW_TERM = 2, ROW_ADJ0 = 3, ROW_ADJ = 4, ROW_SEED = 5, ROW_LAST = 6,
+  ROW_DGHAT = 7, ROW_ADJ0_B = 8, ROW_ADJ_B = 9
 };
 enum ColMode { COL_GHAT = 0, COL_CONV = 1 };
 
@@ -57,7 +61,7 @@ template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
   return (size_t)row_rpw(H) * H *
          (mode == ROW_TERM || mode == ROW_PHI0 || mode == ROW_SEED
               ? sizeof(R)
-              : mode == ROW_ADJ ? 3 * sizeof(R) + 8 : 0);
+              : (mode == ROW_ADJ || mode == ROW_ADJ_B) ? 3 * sizeof(R) + 8 : 0);
 }
 template <typename R> constexpr bool row_staged(int H, int mode) {
   return row_stage_bytes<R>(H, mode) > 0 &&

@@ -185,6 +185,20 @@ __device__ inline float kappa_2d_t<float>(double beta, int r2, double k0v, const
   return b * b * (float)(0.5 / kPi) * bessel_k0_f32(b * sqrtf((float)r2), tab);
 }
 
+// d kappa / d beta at an integer offset (2D), for the gradient with respect
+// to beta: off the origin (beta/pi) K0(x) - (beta/2pi) x K1(x), x = beta |m|;
+// at the origin the beta-derivative of the ball average 1 - a K1(a),
+// a = beta/sqrt(pi), which is (beta/pi) K0(a) (d/da of a K1(a) is -a K0(a)).
+// Float64 for either precision (evaluated once per gradient).
+__device__ inline double dkappa_2d(double beta, long long r2, const ChebK0 &tab) {
+  if (r2 == 0) return beta / kPi * bessel_k0_fast(beta / sqrt(kPi), tab);
+  const double x = beta * sqrt((double)r2);
+  double xk1;  // x K1(x)
+  if (x <= 2.0) xk1 = 1.0 - one_minus_aK1(x);
+  else xk1 = x * exp(-x) * (x < 25.0 ? k_trapezoid_scaled(x, 1) : k_hankel_scaled(x, 1));
+  return beta / kPi * bessel_k0_fast(x, tab) - beta / (2.0 * kPi) * xk1;
+}
+
 // the kernel exp(-beta |m|) of phi_0 (eq. phi_0Solution with C = 1), for the
 // FFT route of phi_0 (Table 1, steps 1-5)
 template <typename R> __device__ inline R exp_kernel_t(double beta, int r2);

@@ -89,6 +89,9 @@ hipError_t launch_row2_e(int mode, int H, dim3 grid, hipStream_t st, const Args2
     case ROW_ADJ: return RowLaunch<R, E, ROW_ADJ>::run(H, grid, st, a, term);
     case ROW_SEED: return RowLaunch<R, E, ROW_SEED>::run(H, grid, st, a, term);
     case ROW_LAST: return RowLaunch<R, E, ROW_LAST>::run(H, grid, st, a, term);
+    case ROW_DGHAT: return RowLaunch<R, E, ROW_DGHAT>::run(H, grid, st, a, term);
+    case ROW_ADJ0_B: return RowLaunch<R, E, ROW_ADJ0_B>::run(H, grid, st, a, term);
+    case ROW_ADJ_B: return RowLaunch<R, E, ROW_ADJ_B>::run(H, grid, st, a, term);
   }
   return hipErrorInvalidValue;
 }
@@ -182,6 +185,16 @@ hipError_t launch_seed_scatter(R *grid, const int *src, const R *src_s, int n_sr
   return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_adj_full_finish(const R *f, long long N, const Params *par, const double *gpart,
+                                  int nbr, long long *ext, int ft_mode, double h, double hbar,
+                                  R *dLdf, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(k_argext<R>, dim3(kRedBlocks), dim3(256), 0, st, f, N, par, ext);
+  hipLaunchKernelGGL(k_adj_full_finish<R>, dim3(1), dim3(256), 0, st, gpart, nbr,
+                     (const long long *)ext, (int)kRedBlocks, par, ft_mode, h, hbar, dLdf, out);
+  return hipGetLastError();
+}
+
 template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream_t st) {
   const long long nb = std::min<long long>((N + 255) / 256, 4096);
   hipLaunchKernelGGL(k_fill<R>, dim3((unsigned)std::max<long long>(nb, 1)), dim3(256), 0, st, out,
@@ -211,6 +224,9 @@ template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream
   template hipError_t launch_adj_prep<R>(const R *, const double *, long long, double,      \
                                          double *, cplx<R> *, int, hipStream_t);            \
   template hipError_t launch_fill<R>(R *, long long, R, hipStream_t);                       \
+  template hipError_t launch_adj_full_finish<R>(const R *, long long, const Params *,         \
+                                                const double *, int, long long *, int, double, \
+                                                double, R *, double *, hipStream_t);           \
   template hipError_t launch_seed_scatter<R>(R *, const int *, const R *, int, double, int, int, \
                                              hipStream_t);                                  \
   template hipError_t launch_prep_batch<R>(int, hipStream_t, const BatchItem<R> *);

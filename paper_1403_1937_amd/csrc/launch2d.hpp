@@ -27,6 +27,12 @@ template <typename R>
 hipError_t launch_adj_prep(const R *dLdS, const double *phi, long long N, double hbar,
                            double *red, cplx<R> *tw, int lmax, hipStream_t st);
 template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream_t st);
+// full gradient: argmin / argmax of f (kRedBlocks partials in ext, 2 x
+// kRedBlocks long long) and the scalar derivatives (see k_adj_full_finish)
+template <typename R>
+hipError_t launch_adj_full_finish(const R *f, long long N, const Params *par, const double *gpart,
+                                  int nbr, long long *ext, int ft_mode, double h, double hbar,
+                                  R *dLdf, double *out, hipStream_t st);
 template <typename R>
 hipError_t launch_seed_scatter(R *grid, const int *src, const R *src_s, int n_src, double hbar,
                                int n0, int n1, hipStream_t st);

@@ -34,6 +34,10 @@ struct Geo3 {
 struct Layout {      // byte offsets into the workspace / checkpoint
   size_t par, red, expo, mu, mu_red, tw, g, g0, spec, s2, acc, terms, lam, gam, total;
   size_t ck_expo, ck_par, ck_g, ck_phi, ck_terms, ck_total;
+  // full gradient: after `total`, a second spectrum, the per-work-group
+  // partial sums and the argmin / argmax partials (the kernel table's
+  // beta-derivative spectrum reuses g0)
+  size_t fg_spec2, fg_part, fg_ext, fg_total;
 };
 
 }  // namespace sweik

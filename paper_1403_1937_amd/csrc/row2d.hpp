@@ -190,7 +190,11 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   constexpr bool STG = row_staged<R>(H, MODE);
   constexpr int NTW = (2 * H + NT - 1) / NT;
   constexpr bool TERMLIKE = MODE == ROW_TERM || MODE == ROW_LAST;
-  constexpr bool LOADS_TILE = TERMLIKE || MODE == ROW_ADJ || MODE == ROW_PHI0;
+  constexpr bool ADJ = MODE == ROW_ADJ || MODE == ROW_ADJ_B;
+  constexpr bool ADJ0 = MODE == ROW_ADJ0 || MODE == ROW_ADJ0_B;
+  constexpr bool FULLG = MODE == ROW_ADJ_B || MODE == ROW_ADJ0_B;  // full gradient
+  constexpr bool GHATLIKE = MODE == ROW_GHAT || MODE == ROW_DGHAT;
+  constexpr bool LOADS_TILE = TERMLIKE || ADJ || MODE == ROW_PHI0;
   // phi_0 reads the spectrum only on its FFT route
   const bool tile_in = MODE != ROW_PHI0 || a.phi0_fft;
   C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / 2H), k < 2H
@@ -213,7 +217,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
 
   // staging rows of this team (written and read by the same thread)
   R *sR = reinterpret_cast<R *>(stg) + (size_t)team * H;                   // first R row
-  constexpr int NRSTG = MODE == ROW_ADJ ? 3 : 1;
+  constexpr int NRSTG = ADJ ? 3 : 1;
   double *sD = reinterpret_cast<double *>(reinterpret_cast<R *>(stg) + (size_t)RPW * H * NRSTG) +
                (size_t)team * H;
 
@@ -229,6 +233,13 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   stage_tw_issue<H, E>(tsr, a.tw, a.lmax_log, tid, NT);
   C tl[Tile::NREG];
   if (LOADS_TILE && tile_in) tile_issue<FULL>(tile, tid, tl);
+  // full gradient: the tile of c_i = dkappa/dbeta (*) a_i
+  Tile tile2;
+  C tl2[MODE == ROW_ADJ_B ? Tile::NREG : 1];
+  if constexpr (MODE == ROW_ADJ_B) {
+    tile2.init(a.spec2, row0, a.nb * spec_rb<R>());
+    tile_issue<FULL>(tile2, tid, tl2);
+  }
   // pointwise operands of this thread's columns c = 2(t + P j) + e
   constexpr int NOP = STG ? E : 1;
   R o1[NOP], o2[NOP], o3[NOP];
@@ -239,10 +250,10 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     if (MODE == ROW_PHI0) p1 = last ? nullptr : a.f;
     if (MODE == ROW_SEED) p1 = a.gam;  // the source grid
     if (MODE == ROW_TERM) p1 = a.gam;
-    if (MODE == ROW_ADJ) {
+    if (ADJ) {
       p1 = a.ck_terms + (size_t)(term - 1) * N;
       p2 = term > 1 ? a.gam : a.f;
-      p3 = term > 1 ? a.lam : nullptr;
+      p3 = (term > 1 || FULLG) ? a.lam : nullptr;  // the full gradient also needs a_0
       pd = term != a.T ? a.acc : nullptr;
     }
     // columns 2(t + P j) for j >= E/2 are >= H >= n1: zero padding
@@ -255,14 +266,14 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
         V x1 = cmake<V>((R)0, (R)0), x2 = x1, x3 = x1;
         double2 xd = make_double2(0.0, 0.0);
         if (ok && p1) x1 = *reinterpret_cast<const V *>(p1 + rowoff + c0);
-        if (MODE == ROW_ADJ) {
+        if (ADJ) {
           if (ok && p2) x2 = *reinterpret_cast<const V *>(p2 + rowoff + c0);
           if (ok && p3) x3 = *reinterpret_cast<const V *>(p3 + rowoff + c0);
         }
         if (ok && pd) xd = *reinterpret_cast<const double2 *>(pd + rowoff + c0);
         o1[2 * j] = x1.x;
         o1[2 * j + 1] = x1.y;
-        if (MODE == ROW_ADJ) {
+        if (ADJ) {
           o2[2 * j] = x2.x;
           o2[2 * j + 1] = x2.y;
           o3[2 * j] = x3.x;
@@ -277,7 +288,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
         const int cc = 2 * (t + P * (q >> 1)) + (q & 1);
         const bool ok = col_ok(cc);
         o1[q] = (ok && p1) ? p1[rowoff + cc] : (R)0;
-        if (MODE == ROW_ADJ) {
+        if (ADJ) {
           o2[q] = (ok && p2) ? p2[rowoff + cc] : (R)0;
           o3[q] = (ok && p3) ? p3[rowoff + cc] : (R)0;
         }
@@ -356,14 +367,14 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   __shared__ double s_sE[MODE == ROW_LAST ? SWEIK_MAX_TERMS + 1 : 1];
   if (MODE == ROW_LAST)
     for (int i = tid; i < a.T; i += NT) s_sE[i] = ((i & 1) ? -1.0 : 1.0) * ldexp(1.0, a.expo[i]);
-  if (MODE == ROW_ADJ0) {
+  if (ADJ0) {
     double mx = 0.0;
     for (int i = tid; i < kRedBlocks; i += NT) mx = fmax(mx, a.red[i]);
     mx = block_max(mx);
     elam = exp_step(mx);
     if (bid == 0 && tid == 0) a.expo[0] = elam;
   }
-  if (MODE == ROW_ADJ) {
+  if (ADJ) {
     __shared__ int s_e[2];
     if (tid == 0) {
       s_e[0] = a.expo[0];
@@ -403,11 +414,11 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
       const int cc = 2 * (t + P * (q >> 1)) + (q & 1);
       if (FULL || cc < a.n1) {
         sR[cc] = o1[q];
-        if (MODE == ROW_ADJ) {
+        if (ADJ) {
           sR[(size_t)RPW * H + cc] = o2[q];
           sR[(size_t)2 * RPW * H + cc] = o3[q];
         }
-        if (MODE == ROW_ADJ) sD[cc] = od[q];
+        if (ADJ) sD[cc] = od[q];
       }
     }
   }
@@ -422,12 +433,12 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   C v[E];
 
   // ---- 4. kernel table ------------------------------------------------------
-  if constexpr (MODE == ROW_GHAT) {
+  if constexpr (GHATLIKE) {
     // Row r of the evenly extended kernel table, x[m] = kappa(r, min(m,
     // 2H - m)) (zero for offsets >= n1): the first half is evaluated, the
     // mirrored half is read back through LDS.
     R *xl = reinterpret_cast<R *>(line);
-    const double k0v = s_par[0];
+    const double k0v = MODE == ROW_GHAT ? s_par[0] : 0.0;
 #pragma unroll
     for (int j = 0; j < E / 2; ++j) {
       const int c0 = 2 * (t + P * j);
@@ -435,7 +446,8 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
       if (row_ok) {
         const int rr = r * r;
         auto tab = [&](int q) -> R {
-          return a.table ? exp_kernel_t<R>(beta, q) : kappa_2d_t<R>(beta, q, k0v, a.k0tab);
+          if constexpr (MODE == ROW_DGHAT) return (R)dkappa_2d(beta, q, a.k0tab);
+          else return a.table ? exp_kernel_t<R>(beta, q) : kappa_2d_t<R>(beta, q, k0v, a.k0tab);
         };
         if (c0 < a.n1) z0 = tab(rr + c0 * c0);
         if (c0 + 1 < a.n1) z1 = tab(rr + (c0 + 1) * (c0 + 1));
@@ -474,6 +486,14 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   }
 
   if (LOADS_TILE && tile_in) row_c2r<R, H, E>(v, t, line, twl, tws);
+  // full gradient: the inverse transform of c_i's tile through the same lines
+  C vc[MODE == ROW_ADJ_B ? E : 1];
+  if constexpr (MODE == ROW_ADJ_B) {
+    __syncthreads();  // every team is done with its line
+    tile_to_lds<FULL>(tile2, tid, tl2, lines);
+    __syncthreads();
+    row_c2r<R, H, E>(vc, t, line, twl, tws);
+  }
   // the forcing of the next FFT is zero in the padding half (columns >= H)
 #pragma unroll
   for (int j = E / 2; j < E; ++j) v[j] = cmake<C>((R)0, (R)0);
@@ -631,10 +651,28 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     if (tid == 0) a.mu[(size_t)slot * a.nbr + bid] = bm;
   }
 
-  if constexpr (MODE == ROW_ADJ0) {
+  // full gradient: d phi_0 / d beta and d phi_0 / d hbar (through the
+  // weights w_k = exp(-s_k / hbar)) at column cc of this row, in float64
+  auto dphi0 = [&](int cc, double &dbeta, double &dhbar) {
+    dbeta = 0.0;
+    dhbar = 0.0;
+    for (int k = 0; k < a.n_src; ++k) {
+      const double d0 = (double)(r - a.src[2 * k]), d1 = (double)(cc - a.src[2 * k + 1]);
+      const double dist = sqrt(d0 * d0 + d1 * d1);
+      const double sk = a.src_s ? (double)a.src_s[k] : 0.0;
+      const double e = exp(-sk / a.hbar - beta * dist);
+      dbeta -= dist * e;
+      dhbar += e * sk / (a.hbar * a.hbar);
+    }
+  };
+  // per-work-group slot of the full gradient's partial sums
+  auto gslot = [&](int slot) -> double & { return a.gpart[(size_t)slot * a.nbr + bid]; };
+
+  if constexpr (ADJ0) {
     // lambda mantissa (scale 2^-e_lam); a_T = (-1)^T lambda
     const double lam_scale = ldexp(1.0, -elam);
     const double sgnT = (a.T & 1) ? -1.0 : 1.0;
+    double ps[FULLG ? 3 : 1] = {};  // S/hbar, a_0 d phi_0/d beta, a_0 d phi_0/d hbar
 #pragma unroll
     for (int j = 0; j < E / 2; ++j) {
       R zz[2] = {(R)0, (R)0};
@@ -650,14 +688,38 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
           const R q = (R)l;
           a.lam[rowoff + cc] = q;
           zz[e] = (R)(sgnT * (double)q);
+          if constexpr (FULLG) {
+            if (ph > 0.0 && isfinite(ph)) ps[0] += (double)a.dLdS[rowoff + cc] * -log(ph);
+            if (a.T == 0) {  // phi = phi_0: a_0 = lambda
+              double db, dh;
+              dphi0(cc, db, dh);
+              ps[1] += (double)q * db;
+              ps[2] += (double)q * dh;
+            }
+          }
         }
       }
       v[j] = cmake<C>(zz[0], zz[1]);
     }
+    if constexpr (FULLG) {
+      block_sums_d(ps);
+      if (tid == 0) {
+        const double sl = ldexp(1.0, elam);
+        gslot(G_S) = ps[0];
+        gslot(G_C) = 0.0;
+        gslot(G_B0) = ps[1] * sl;
+        gslot(G_H0) = ps[2] * sl;
+        gslot(G_GF) = 0.0;
+      }
+      if (a.T == 0) return;
+    }
   }
 
-  if constexpr (MODE == ROW_ADJ) {
+  if constexpr (ADJ) {
     const double gscale = ldexp(1.0, Ei + elam);
+    // full gradient: <c_i, gamma phi_{i-1}>, and at term 1 a_0 d phi_0 and
+    // dL/dgamma f^2 (mantissa sums; scales applied per work-group)
+    double ps[FULLG ? 4 : 1] = {};
     const double sgn_prev = ((term - 1) & 1) ? -1.0 : 1.0;  // (-1)^(i-1)
     const R *mprev = a.ck_terms + (size_t)(term - 1) * N;
 #pragma unroll
@@ -680,15 +742,49 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
             const double fa = (double)op2(cc, a.f);
             a.dLdf[rowoff + cc] = (R)(g * 2.0 * fa * inv_ft2);
           }
+          if constexpr (MODE == ROW_ADJ_B) {
+            const double mp = (double)op1(cc, mprev);
+            double ga;
+            if (term > 1) {
+              ga = (double)op2(cc, a.gam);
+            } else {
+              const double fa = (double)op2(cc, a.f);
+              ga = (fa - ft) * (fa + ft) * inv_ft2;
+              const double a0 = (double)op3(cc, a.lam) + ga * bb[e];  // a_0 = lambda + gamma b_1
+              double db, dh;
+              dphi0(cc, db, dh);
+              ps[1] += a0 * db;
+              ps[2] += a0 * dh;
+              ps[3] += g * fa * fa;
+            }
+            ps[0] += (double)(e ? vc[j].y : vc[j].x) * ga * mp;
+          }
         }
       }
       v[j] = cmake<C>(zz[0], zz[1]);
+    }
+    if constexpr (MODE == ROW_ADJ_B) {
+      block_sums_d(ps);
+      if (tid == 0) {
+        gslot(G_C) += ps[0] * gscale;
+        if (term == 1) {
+          const double sl = ldexp(1.0, elam);
+          gslot(G_B0) = ps[1] * sl;
+          gslot(G_H0) = ps[2] * sl;
+          gslot(G_GF) = ps[3];
+        }
+      }
     }
     if (term == 1) return;
   }
 
   // ---- 6. forward real FFT of the new forcing, store the tile --------------
   row_r2c_store<FULL, R, H, E>(v, t, tid, line, lines, twl, tws, tile);
+  if constexpr (FULLG) {  // the same spectrum again, for the convolution with dkappa/dbeta
+    Tile t2;
+    t2.init(a.spec2, row0, a.nb * spec_rb<R>());
+    tile_store<FULL>(t2, tid, lines);
+  }
 }
 
 template <typename R, int MODE, int H, int E>
@@ -742,6 +838,105 @@ __global__ void __launch_bounds__(256) k_adj_prep(const R *__restrict__ dLdS,
     w.x = (R)cs;
     w.y = (R)(-s);
     tw[j] = w;
+  }
+}
+
+// Full gradient: the first grid point (C order) where f equals its minimum
+// and its maximum (from the checkpointed scalars), per work-group.
+template <typename R>
+__global__ void __launch_bounds__(256) k_argext(const R *__restrict__ f, long long N,
+                                                const Params *__restrict__ par,
+                                                long long *__restrict__ ext) {
+  const double lo = par->fmin, hi = par->fmax;
+  long long imin = LLONG_MAX, imax = LLONG_MAX;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double v = (double)f[i];
+    if (v == lo && i < imin) imin = i;
+    if (v == hi && i < imax) imax = i;
+  }
+  __shared__ long long s[2][4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const long long a = __shfl_xor(imin, o, 64), b = __shfl_xor(imax, o, 64);
+    imin = a < imin ? a : imin;
+    imax = b < imax ? b : imax;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s[0][threadIdx.x >> 6] = imin;
+    s[1][threadIdx.x >> 6] = imax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 4; ++w) {
+      imin = s[0][w] < imin ? s[0][w] : imin;
+      imax = s[1][w] < imax ? s[1][w] : imax;
+    }
+    ext[blockIdx.x] = s[0][0] < imin ? s[0][0] : imin;
+    ext[gridDim.x + blockIdx.x] = s[1][0] < imax ? s[1][0] : imax;
+  }
+}
+
+// Full gradient, last step (one work-group): the scalar derivatives
+//   dL/dbeta   = G_C + G_B0
+//   dL/dhbar   = G_S - (beta / hbar) dL/dbeta + G_H0
+//   dL/dftilde = (h / hbar) dL/dbeta - (2 / ftilde^3) G_GF
+// and dL/dftilde times a subgradient of ftilde(f) added to dL/df at the
+// first minimum and maximum of f (nu: fmin / 2 ftilde and fmax / 2 ftilde;
+// sup f: 1 at the maximum; a given ftilde: nothing).  out[0..2] = dL/dhbar,
+// dL/dftilde, dL/dbeta (nullable).
+template <typename R>
+__global__ void __launch_bounds__(256) k_adj_full_finish(const double *__restrict__ gpart, int nbr,
+                                                         const long long *__restrict__ ext,
+                                                         int next, const Params *__restrict__ par,
+                                                         int ft_mode, double h, double hbar,
+                                                         R *__restrict__ dLdf,
+                                                         double *__restrict__ out) {
+  double v[kGradSlots];
+#pragma unroll
+  for (int k = 0; k < kGradSlots; ++k) {
+    double t = 0.0;
+    for (int i = threadIdx.x; i < nbr; i += blockDim.x) t += gpart[(size_t)k * nbr + i];
+    v[k] = t;
+  }
+  block_sums_d(v);
+  long long imin = LLONG_MAX, imax = LLONG_MAX;
+  for (int i = threadIdx.x; i < next; i += blockDim.x) {
+    imin = ext[i] < imin ? ext[i] : imin;
+    imax = ext[next + i] < imax ? ext[next + i] : imax;
+  }
+  __shared__ long long s[2][4];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const long long a = __shfl_xor(imin, o, 64), b = __shfl_xor(imax, o, 64);
+    imin = a < imin ? a : imin;
+    imax = b < imax ? b : imax;
+  }
+  if ((threadIdx.x & 63) == 0) {
+    s[0][threadIdx.x >> 6] = imin;
+    s[1][threadIdx.x >> 6] = imax;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int w = 0; w < 4; ++w) {
+    imin = s[0][w] < imin ? s[0][w] : imin;
+    imax = s[1][w] < imax ? s[1][w] : imax;
+  }
+  const double beta = par->beta, ft = par->ftilde;
+  const double dbeta = v[G_C] + v[G_B0];
+  const double dhbar = v[G_S] - beta / hbar * dbeta + v[G_H0];
+  const double dft = h / hbar * dbeta - 2.0 / (ft * ft * ft) * v[G_GF];
+  if (ft_mode == SWEIK_FT_NU) {
+    if (imin != LLONG_MAX) dLdf[imin] = (R)((double)dLdf[imin] + dft * par->fmin / (2.0 * ft));
+    if (imax != LLONG_MAX) dLdf[imax] = (R)((double)dLdf[imax] + dft * par->fmax / (2.0 * ft));
+  } else if (ft_mode == SWEIK_FT_FMAX) {
+    if (imax != LLONG_MAX) dLdf[imax] = (R)((double)dLdf[imax] + dft);
+  }
+  if (out) {
+    out[0] = dhbar;
+    out[1] = dft;
+    out[2] = dbeta;
+    out[3] = 0.0;
   }
 }
 

@@ -168,3 +168,18 @@ def test_backtrack_rejects_invalid_arguments(lib):
     for kw in bad:
         assert call(**kw) == 1, kw
     assert call(n_paths=0, S=None, start=None, path=None) == 0
+
+
+def test_full_gradient_entry_checks(lib):
+    # host-side rejections before any device call; the full gradient needs
+    # more workspace than a solve (a second spectrum and partial sums)
+    p = _plan()
+    vp = C.c_void_p
+    assert lib.sweik_adjoint_full_workspace_bytes(p.handle) > lib.sweik_workspace_bytes(p.handle)
+    rc = lib.sweik_solve_adjoint_full(p.handle, None, None, None, None, None, None, None, None,
+                                      0, None)
+    assert rc == 1
+    need = lib.sweik_adjoint_full_workspace_bytes(p.handle)
+    rc = lib.sweik_solve_adjoint_full(p.handle, vp(16), vp(16), None, vp(16), vp(16), vp(16),
+                                      None, vp(16), need - 1, None)
+    assert rc == 3  # SWEIK_EWORKSPACE
