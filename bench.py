@@ -12,7 +12,8 @@ Also reported on the same JSON line:
   fp64_comparator  the plain FP64 GPU solve of the same workload
   fwd_bwd          forward (with checkpoints) + adjoint dL/df on the 2048^2,
                    T = 12, 4-source differentiation workload, FP32-scaled,
-                   loss = sum over 256 receivers of (S - target)^2
+                   loss = sum over 256 receivers of (S - target)^2; also the
+                   full gradient (ftilde's dependence on f, dL/dhbar)
   batched          64 uneven instances (edges from {256, 512, 1024, 2048},
                    T = 12, FP32-scaled) solved by one replay of a HIP graph
   solve3d          256^3 grid, f from 32 Gaussian blobs in [0.5, 2], one
@@ -294,12 +295,35 @@ def run_fwd_bwd(pk, torch, dev, steps, warmup):
                  + p.T * ab["conv_col"] + (p.T - 1) * ab["term_row"] + ab["last_row"])
     bwd_bytes = alg_bytes_adjoint_2d(n0, n1, H1, H0, 4, p.T)
     ok = bool(torch.isfinite(dLdf).all().item())
+
+    # the full gradient (dL/df with ftilde's dependence on f, dL/dhbar): the
+    # same step with sweik_solve_adjoint_full on its larger workspace
+    wsf = torch.empty(plan.adjoint_full_workspace_bytes, dtype=torch.uint8, device=dev)
+    grads = torch.zeros(4, dtype=torch.float64, device=dev)
+
+    def step_full():
+        plan.solve(f, src, S, wsf, ck)
+        dLdS[ridx] = 2.0 * (S.view(-1)[ridx] - tgt.view(-1)[ridx])
+        plan.adjoint_full(f, src, ck, dLdS.view(n0, n1), dLdf, grads, wsf)
+
+    step_full()
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(steps):
+        step_full()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms_full = e0.elapsed_time(e1) / steps
     return {"workload": f"noise2d_{n0}x{n1}_T{p.T}_src{len(p.src)}_rec{len(rec)}",
             "value": N / (ms * 1e-3), "unit": "grid pts/s", "ms_per_step": ms,
             "ms_forward_with_checkpoints": ms_fwd, "ms_adjoint": ms - ms_fwd,
             "alg_bytes": fwd_bytes + bwd_bytes,
             "alg_GBps": (fwd_bytes + bwd_bytes) / (ms * 1e-3) / 1e9,
-            "precision": "fp32-scaled", "gradient_finite": ok, "schedule": plan.schedule}
+            "precision": "fp32-scaled", "gradient_finite": ok, "schedule": plan.schedule,
+            "full_gradient": {"value": N / (ms_full * 1e-3), "ms_per_step": ms_full,
+                              "ms_adjoint_full": ms_full - ms_fwd,
+                              "dLdhbar": float(grads[0].item()),
+                              "note": "dL/df with the ftilde(f) subgradient, and dL/dhbar"}}
 
 
 def run_backtrack(pk, torch, dev, steps, warmup):
