@@ -361,9 +361,9 @@ def run_backtrack(pk, torch, dev, steps, warmup):
 def run_fd(pk, torch, dev, steps, warmup):
     """The paper's second method (Section 6): the finite-difference screened
     Poisson system of the 1024^2 main workload, CG in float64 to
-    ||r|| <= 1e-10 ||b||.  Bytes per CG iteration (float64 vectors of N):
-    apply reads z, p_prev, diag and writes p, q (40 N); update reads x, p,
-    r, q, diag and writes x, r, z (64 N)."""
+    ||r|| <= 1e-10 ||b||.  Bytes per CG iteration (one kernel; float64
+    vectors of N): reads r, w, s_prev, p, x, 1/diag and writes p, s, x, r,
+    w (88 N; the neighbours' r, w, s, 1/diag come from cache)."""
     import workloads
     p = workloads.problem(2, 1024)
     N = p.dims[0] * p.dims[1]
@@ -381,8 +381,8 @@ def run_fd(pk, torch, dev, steps, warmup):
     return {"workload": "fd_noise2d_1024x1024_src16", "value": N / (ms * 1e-3),
             "unit": "grid pts/s", "ms_per_step": ms, "iterations": it,
             "rel_residual": info["rel_residual"], "us_per_iteration": per_it * 1e3,
-            "iteration_alg_bytes": 104 * N,
-            "iteration_GBps": 104 * N / (per_it * 1e-3) / 1e9, "precision": "fp64"}
+            "iteration_alg_bytes": 88 * N,
+            "iteration_GBps": 88 * N / (per_it * 1e-3) / 1e9, "precision": "fp64"}
 
 
 def run_batched(pk, torch, dev, steps, warmup):

@@ -200,7 +200,7 @@ sweik_status sweik_solve_adjoint_full(sweik_plan plan, const void *f, const int3
  *             f and S; T and the reference forcing are not used)
  *   f, src, S as sweik_solve (device)
  *   ws        device workspace of ws_bytes >= sweik_fd_workspace_bytes(plan)
- *             (about 56 bytes per grid point)
+ *             (about 72 bytes per grid point)
  *   max_iter  0 .. 2^24; rtol >= 0, finite
  *   info      HOST, nullable
  * Unlike the FFT solve this call synchronises the stream: it reads a

@@ -37,12 +37,16 @@ int ilog2(int64_t x) {
 }
 
 // e^x K0(x) for x >= 2 by the trapezoid rule on int_0^inf exp(-2x sinh^2(t/2)) dt
-double k0_scaled_host(double x) {
+// e^x K_nu(x), nu = 0 or 1: Hankel's expansion (terms (4nu^2 - (2j-1)^2) /
+// (8 j x)) for x > 60, else the trapezoid rule on the integral
+// int_0^inf exp(-2 x sinh^2(t/2)) cosh(nu t) dt
+double k_scaled_host(double x, int nu) {
   const double pi = 3.14159265358979323846;
-  if (x > 60.0) {  // Hankel expansion, terms (2j-1)^2 / (8 j x)
+  const double mu = 4.0 * nu * nu;
+  if (x > 60.0) {
     double term = 1.0, sum = 1.0;
     for (int j = 1; j < 40; ++j) {
-      const double nt = -term * (2.0 * j - 1.0) * (2.0 * j - 1.0) / (8.0 * j * x);
+      const double nt = term * (mu - (2.0 * j - 1.0) * (2.0 * j - 1.0)) / (8.0 * j * x);
       if (std::fabs(nt) >= std::fabs(term)) break;
       term = nt;
       sum += term;
@@ -53,7 +57,8 @@ double k0_scaled_host(double x) {
   double sum = 0.5;
   for (int j = 1; j < 10000; ++j) {
     const double sh = std::sinh(0.5 * eta * j);
-    const double g = std::exp(-2.0 * x * sh * sh);
+    double g = std::exp(-2.0 * x * sh * sh);
+    if (nu) g *= std::cosh(eta * j);
     sum += g;
     if (g < 1e-18 * sum) break;
   }
@@ -64,24 +69,31 @@ double k0_scaled_host(double x) {
 
 namespace sweik {
 
-// Chebyshev coefficients of sqrt(x) e^x K0(x) on x >= 2 in t = 4/x - 1,
+// Chebyshev coefficients of sqrt(x) e^x K0(x) and sqrt(x) e^x K1(x) on
+// x >= 2 in t = 4/x - 1,
 // from its values at the Chebyshev points (discrete cosine transform).
 const ChebK0 &bessel_cheb_k0() {
   static const ChebK0 tab = [] {
     ChebK0 t;
     const int n = 40;
     const double pi = 3.14159265358979323846;
-    double g[n];
+    double g0[n], g1[n];
     for (int j = 0; j < n; ++j) {
       const double tj = std::cos(pi * (j + 0.5) / n);
       const double x = 4.0 / (tj + 1.0);
-      g[j] = std::sqrt(x) * k0_scaled_host(x);
+      g0[j] = std::sqrt(x) * k_scaled_host(x, 0);
+      g1[j] = std::sqrt(x) * k_scaled_host(x, 1);
     }
     for (int k = 0; k < kChebK0; ++k) {
-      double s = 0.0;
-      for (int j = 0; j < n; ++j) s += g[j] * std::cos(pi * k * (j + 0.5) / n);
-      t.c[k] = (k == 0 ? 1.0 : 2.0) * s / n;
+      double s0 = 0.0, s1 = 0.0;
+      for (int j = 0; j < n; ++j) {
+        const double c = std::cos(pi * k * (j + 0.5) / n);
+        s0 += g0[j] * c;
+        s1 += g1[j] * c;
+      }
+      t.c[k] = (k == 0 ? 1.0 : 2.0) * s0 / n;
       t.c32[k] = (float)t.c[k];
+      t.c1[k] = (k == 0 ? 1.0 : 2.0) * s1 / n;
     }
     return t;
   }();

@@ -10,20 +10,21 @@
 // with the diagonal as preconditioner, in float64 whatever the type of f and
 // S.
 //
-// One CG iteration is two kernels over the grid:
-//   apply   p = z + beta p_prev (at the point and at its neighbours, read
-//           from the previous direction buffer) and q = A p; partial sums of
-//           p.q
-//   update  x += alpha p, r -= alpha q, z = r / diag; partial sums of r.z
-//           and r.r
-// Every block of a kernel first sums the per-block partials of the kernel
-// before it (a fixed number of blocks and a fixed order: deterministic), so
-// the scalars alpha and beta need no separate launch.  The partials of r.z
-// alternate between two buffers by iteration parity, and so do the search
-// directions, so that no kernel overwrites what another block of the same
-// kernel still reads.  The apply kernel also tests ||r|| <= rtol ||b|| and
-// raises a flag that makes every later kernel return at once; the host
-// checks the flag between chunks of iterations.
+// The iteration is the Chronopoulos-Gear form of preconditioned CG (one
+// pair of inner products per iteration, both formed after the update), so
+// that one iteration is one kernel over the grid:
+//   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
+//   u = r / diag,  w = A u,  gamma = (r, u),  delta = (w, u),  (r, r)
+// with beta = gamma / gamma_prev and alpha = gamma / (delta - beta gamma /
+// alpha_prev).  The stencil w = A u needs the new u at the neighbours; each
+// thread recomputes it there from the old r, w, s (read-only in the
+// kernel), so the old and new r, w and s live in two buffers each, by
+// iteration parity.  Every block first sums the per-block partials of the
+// kernel before it (a fixed number of blocks and a fixed order:
+// deterministic) and derives alpha and beta itself; block 0 keeps the
+// scalars the next iteration needs.  A convergence test on (r, r) raises a
+// flag that makes every later kernel return at once; the host checks the
+// flag between chunks of iterations.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -37,7 +38,8 @@ namespace {
 constexpr int kFdThreads = 256;
 constexpr int kFdBlocks = 1024;
 constexpr int kFdChunk = 64;  // iterations enqueued between two convergence checks
-enum { P_RZ0 = 0, P_RZ1 = 1, P_RR = 2, P_PQ = 3, P_COUNT = 4 };
+// partial-sum slots, two parities each: (r, u), (w, u), (r, r)
+enum { P_G = 0, P_D = 1, P_RR = 2, P_COUNT = 3 };
 
 struct FdArgs {
   int n[3];
@@ -46,8 +48,9 @@ struct FdArgs {
   int D;
   double c;        // (h / hbar)^2
   double tol2;     // rtol^2
-  double *d, *x, *r, *z, *q, *p[2];
-  double *part;    // [P_COUNT][kFdBlocks]
+  double *dinv, *x, *p, *r[2], *w[2], *s[2];
+  double *part;    // [2][P_COUNT][kFdBlocks]
+  double *hist;    // [2][2]: gamma and alpha of the last iterations, by parity
   double *scal;    // [0] ||b||^2, [1] r.r at exit
   int *state;      // [0] converged, [1] iterations, [2] flags
   unsigned long long *nbad;
@@ -79,13 +82,17 @@ template <int K> __device__ __forceinline__ void block_sums(double (&v)[K]) {
   __syncthreads();
 }
 
-// sums of the per-block partials of the listed slots
-template <int K> __device__ __forceinline__ void reduce_parts(const FdArgs &a, const int (&slot)[K],
-                                                             double (&out)[K]) {
+__device__ __forceinline__ double *part_of(const FdArgs &a, int parity, int slot) {
+  return a.part + ((size_t)parity * P_COUNT + slot) * kFdBlocks;
+}
+
+// the three partial sums of one parity
+__device__ __forceinline__ void reduce_parts(const FdArgs &a, int parity, double (&out)[3]) {
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
+  for (int k = 0; k < 3; ++k) {
+    const double *pp = part_of(a, parity, k);
     double t = 0.0;
-    for (int i = threadIdx.x; i < kFdBlocks; i += kFdThreads) t += a.part[slot[k] * kFdBlocks + i];
+    for (int i = threadIdx.x; i < kFdBlocks; i += kFdThreads) t += pp[i];
     out[k] = t;
   }
   block_sums(out);
@@ -94,6 +101,7 @@ template <int K> __device__ __forceinline__ void reduce_parts(const FdArgs &a, c
 __global__ void __launch_bounds__(kFdThreads) k_fd_init(FdArgs a) {
   if (threadIdx.x < 4) a.state[threadIdx.x] = 0;
   if (threadIdx.x < 2) a.scal[threadIdx.x] = 0.0;
+  if (threadIdx.x < 4) a.hist[threadIdx.x] = 0.0;
   if (threadIdx.x == 0) *a.nbad = 0ull;
 }
 
@@ -105,21 +113,19 @@ __global__ void __launch_bounds__(kFdThreads) k_fd_setup(FdArgs a, const R *__re
     const double fv = (double)f[i];
     if (!isfinite(fv)) fl |= SWEIK_FLAG_F_NONFINITE;
     else if (!(fv > 0.0)) fl |= SWEIK_FLAG_F_NONPOSITIVE;
-    a.d[i] = 2.0 * a.D + a.c * fv * fv;
+    a.dinv[i] = 1.0 / (2.0 * a.D + a.c * fv * fv);
     a.x[i] = 0.0;
-    a.r[i] = 0.0;
-    a.z[i] = 0.0;
-    a.p[0][i] = 0.0;
+    a.p[i] = 0.0;
+    a.r[0][i] = 0.0;
+    a.s[1][i] = 0.0;  // s of iteration -1
   }
-  if (threadIdx.x < P_COUNT) a.part[threadIdx.x * kFdBlocks + blockIdx.x] = 0.0;
   if (fl) atomicOr(&a.state[2], fl);
 }
 
-// b = delta at the sources: r = b, z = b / diag; the partials of r.z and r.r
-// of the first iteration (one thread: the list is short)
+// b = delta at the sources: r_0 = b (one thread: the list is short)
 __global__ void k_fd_seed(FdArgs a, const int32_t *__restrict__ src, int n_src) {
   if (threadIdx.x != 0) return;
-  double rz = 0.0, cnt = 0.0;
+  double cnt = 0.0;
   int fl = 0;
   for (int k = 0; k < n_src; ++k) {
     long long o = 0;
@@ -133,44 +139,21 @@ __global__ void k_fd_seed(FdArgs a, const int32_t *__restrict__ src, int n_src) 
       fl |= SWEIK_FLAG_BAD_SOURCE;
       continue;
     }
-    if (a.r[o] == 0.0) {  // a repeated source counts once (b is an indicator)
-      a.r[o] = 1.0;
-      a.z[o] = 1.0 / a.d[o];
-      rz += a.z[o];
+    if (a.r[0][o] == 0.0) {  // a repeated source counts once (b is an indicator)
+      a.r[0][o] = 1.0;
       cnt += 1.0;
     }
   }
-  a.part[P_RZ0 * kFdBlocks] = rz;
-  a.part[P_RR * kFdBlocks] = cnt;
   a.scal[0] = cnt;
   if (fl) atomicOr(&a.state[2], fl);
 }
 
-template <int D>
-__global__ void __launch_bounds__(kFdThreads) k_fd_apply(FdArgs a, int k) {
-  if (a.state[0]) return;
-  double s[3];
-  const int slots[3] = {(k & 1) ? P_RZ1 : P_RZ0, (k & 1) ? P_RZ0 : P_RZ1, P_RR};
-  reduce_parts(a, slots, s);
-  const double rz = s[0], rz_prev = s[1], rr = s[2], bb = a.scal[0];
-  if (rr <= a.tol2 * bb) {  // converged (also when there is no source: b = 0)
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      a.state[0] = 1;
-      a.state[1] = k;
-      a.scal[1] = rr;
-    }
-    return;
-  }
-  const double beta = k == 0 ? 0.0 : rz / rz_prev;
-  const double *__restrict__ pin = a.p[k & 1];
-  double *__restrict__ pout = a.p[(k + 1) & 1];
-  const double *__restrict__ z = a.z;
-  auto dirv = [&](long long j) { return z[j] + beta * pin[j]; };
-  // one grid line (along the last axis) per block at a time: the line's
-  // coordinates on the other axes cost one division per line, not per point
+// Grid lines along the last axis, one per block at a time: the line's
+// coordinates on the other axes cost one division per line.
+template <int D, typename F>
+__device__ __forceinline__ void for_points(const FdArgs &a, F &&fn) {
   const int nl = a.n[D - 1];
   const long long lines = a.N / nl;
-  double acc = 0.0;
   for (long long line = blockIdx.x; line < lines; line += kFdBlocks) {
     int m[D];
     long long rem = line;
@@ -182,61 +165,106 @@ __global__ void __launch_bounds__(kFdThreads) k_fd_apply(FdArgs a, int k) {
     }
     const long long base = line * nl;
     for (int c = threadIdx.x; c < nl; c += kFdThreads) {
-      const long long i = base + c;
       m[D - 1] = c;
-      const double pc = dirv(i);
-      double v = a.d[i] * pc;
-#pragma unroll
-      for (int e = 0; e < D; ++e) {
-        if (m[e] > 0) v -= dirv(i - a.st[e]);
-        if (m[e] < a.n[e] - 1) v -= dirv(i + a.st[e]);
-      }
-      pout[i] = pc;
-      a.q[i] = v;
-      acc += pc * v;
+      fn(base + c, m);
     }
   }
-  double t[1] = {acc};
-  block_sums(t);
-  if (threadIdx.x == 0) a.part[P_PQ * kFdBlocks + blockIdx.x] = t[0];
 }
 
-__global__ void __launch_bounds__(kFdThreads) k_fd_update(FdArgs a, int k) {
-  if (a.state[0]) return;
-  double s[2];
-  const int slots[2] = {(k & 1) ? P_RZ1 : P_RZ0, P_PQ};
-  reduce_parts(a, slots, s);
-  const double alpha = s[0] / s[1];
-  const double *__restrict__ p = a.p[(k + 1) & 1];
-  double rz = 0.0, rr = 0.0;
-  for (long long i = (long long)blockIdx.x * kFdThreads + threadIdx.x; i < a.N;
-       i += (long long)kFdBlocks * kFdThreads) {
-    a.x[i] += alpha * p[i];
-    const double r = a.r[i] - alpha * a.q[i];
-    const double z = r / a.d[i];
-    a.r[i] = r;
-    a.z[i] = z;
-    rz += r * z;
-    rr += r * r;
-  }
-  double t[2] = {rz, rr};
+// w_0 = A u_0 with u_0 = r_0 / diag, and the partials of iteration 0
+template <int D>
+__global__ void __launch_bounds__(kFdThreads) k_fd_start(FdArgs a) {
+  const double *__restrict__ r = a.r[0];
+  double g = 0.0, dl = 0.0, rr = 0.0;
+  for_points<D>(a, [&](long long i, const int (&m)[D]) {
+    const double u = r[i] * a.dinv[i];
+    double w = r[i];  // diag u
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      if (m[e] > 0) w -= r[i - a.st[e]] * a.dinv[i - a.st[e]];
+      if (m[e] < a.n[e] - 1) w -= r[i + a.st[e]] * a.dinv[i + a.st[e]];
+    }
+    a.w[0][i] = w;
+    g += r[i] * u;
+    dl += w * u;
+    rr += r[i] * r[i];
+  });
+  double t[3] = {g, dl, rr};
   block_sums(t);
-  if (threadIdx.x == 0) {
-    a.part[((k & 1) ? P_RZ0 : P_RZ1) * kFdBlocks + blockIdx.x] = t[0];
-    a.part[P_RR * kFdBlocks + blockIdx.x] = t[1];
+  if (threadIdx.x == 0)
+    for (int k = 0; k < 3; ++k) part_of(a, 0, k)[blockIdx.x] = t[k];
+}
+
+template <int D>
+__global__ void __launch_bounds__(kFdThreads) k_fd_iter(FdArgs a, int k) {
+  if (a.state[0]) return;
+  const int cur = k & 1, nxt = cur ^ 1;
+  double sc[3];
+  reduce_parts(a, cur, sc);
+  const double gam = sc[0], del = sc[1], rr = sc[2], bb = a.scal[0];
+  if (rr <= a.tol2 * bb) {  // converged (also when there is no source: b = 0)
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.state[0] = 1;
+      a.state[1] = k;
+      a.scal[1] = rr;
+    }
+    return;
   }
+  double beta = 0.0, alpha = gam / del;
+  if (k > 0) {
+    beta = gam / a.hist[2 * nxt];
+    alpha = gam / (del - beta * gam / a.hist[2 * nxt + 1]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {  // read by the next iteration only
+    a.hist[2 * cur] = gam;
+    a.hist[2 * cur + 1] = alpha;
+  }
+  const double *__restrict__ r0 = a.r[cur];
+  const double *__restrict__ w0 = a.w[cur];
+  const double *__restrict__ s0 = a.s[nxt];  // s of the previous iteration
+  double *__restrict__ r1 = a.r[nxt];
+  double *__restrict__ w1 = a.w[nxt];
+  double *__restrict__ s1 = a.s[cur];
+  const double *__restrict__ dinv = a.dinv;
+  // the new residual's preconditioned value at any point
+  auto unew = [&](long long j) { return (r0[j] - alpha * (w0[j] + beta * s0[j])) * dinv[j]; };
+  double g = 0.0, dl = 0.0, rs = 0.0;
+  for_points<D>(a, [&](long long i, const int (&m)[D]) {
+    const double di = dinv[i];
+    const double p = r0[i] * di + beta * a.p[i];
+    const double s = w0[i] + beta * s0[i];
+    a.p[i] = p;
+    s1[i] = s;
+    a.x[i] += alpha * p;
+    const double rn = r0[i] - alpha * s;
+    const double u = rn * di;
+    double w = rn;  // diag u
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      if (m[e] > 0) w -= unew(i - a.st[e]);
+      if (m[e] < a.n[e] - 1) w -= unew(i + a.st[e]);
+    }
+    r1[i] = rn;
+    w1[i] = w;
+    g += rn * u;
+    dl += w * u;
+    rs += rn * rn;
+  });
+  double t[3] = {g, dl, rs};
+  block_sums(t);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) part_of(a, nxt, q)[blockIdx.x] = t[q];
 }
 
 template <typename R>
 __global__ void __launch_bounds__(kFdThreads) k_fd_finish(FdArgs a, R *__restrict__ S, double hbar,
                                                           int iters_run) {
   if (blockIdx.x == 0) {
-    double s[1];
-    const int slots[1] = {P_RR};
-    reduce_parts(a, slots, s);
+    double s[3];
+    reduce_parts(a, iters_run & 1, s);
     if (threadIdx.x == 0 && !a.state[0]) {
       a.state[1] = iters_run;
-      a.scal[1] = s[0];
+      a.scal[1] = s[2];
     }
   }
   unsigned long long bad = 0;
@@ -258,7 +286,7 @@ __global__ void __launch_bounds__(kFdThreads) k_fd_finish(FdArgs a, R *__restric
 }
 
 struct FdLayout {
-  size_t vec, part, scal, state, nbad, total;
+  size_t vec, part, hist, scal, state, nbad, total;
 };
 
 FdLayout fd_layout(long long N) {
@@ -269,8 +297,9 @@ FdLayout fd_layout(long long N) {
     off += (bytes + 255) & ~(size_t)255;
     return o;
   };
-  L.vec = take((size_t)7 * N * sizeof(double));
-  L.part = take((size_t)P_COUNT * kFdBlocks * sizeof(double));
+  L.vec = take((size_t)9 * N * sizeof(double));
+  L.part = take((size_t)2 * P_COUNT * kFdBlocks * sizeof(double));
+  L.hist = take(4 * sizeof(double));
   L.scal = take(4 * sizeof(double));
   L.state = take(4 * sizeof(int));
   L.nbad = take(sizeof(unsigned long long));
@@ -301,14 +330,16 @@ sweik_status fd_run(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.c = (pl->p.h / pl->p.hbar) * (pl->p.h / pl->p.hbar);
   a.tol2 = rtol * rtol;
   double *v = (double *)(ws + L.vec);
-  a.d = v;
+  a.dinv = v;
   a.x = v + N;
-  a.r = v + 2 * N;
-  a.z = v + 3 * N;
-  a.q = v + 4 * N;
-  a.p[0] = v + 5 * N;
-  a.p[1] = v + 6 * N;
+  a.p = v + 2 * N;
+  for (int q = 0; q < 2; ++q) {
+    a.r[q] = v + (3 + q) * N;
+    a.w[q] = v + (5 + q) * N;
+    a.s[q] = v + (7 + q) * N;
+  }
   a.part = (double *)(ws + L.part);
+  a.hist = (double *)(ws + L.hist);
   a.scal = (double *)(ws + L.scal);
   a.state = (int *)(ws + L.state);
   a.nbad = (unsigned long long *)(ws + L.nbad);
@@ -317,14 +348,15 @@ sweik_status fd_run(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   hipLaunchKernelGGL(k_fd_init, dim3(1), blk, 0, st, a);
   hipLaunchKernelGGL((k_fd_setup<R>), grid, blk, 0, st, a, (const R *)f);
   hipLaunchKernelGGL(k_fd_seed, dim3(1), dim3(64), 0, st, a, src, pl->p.n_src);
+  if (a.D == 2) hipLaunchKernelGGL((k_fd_start<2>), grid, blk, 0, st, a);
+  else hipLaunchKernelGGL((k_fd_start<3>), grid, blk, 0, st, a);
   if (hipGetLastError() != hipSuccess) return SWEIK_EDEVICE;
   int it = 0;
   while (it < max_iter) {
     const int chunk = max_iter - it < kFdChunk ? max_iter - it : kFdChunk;
     for (int j = 0; j < chunk; ++j) {
-      if (a.D == 2) hipLaunchKernelGGL((k_fd_apply<2>), grid, blk, 0, st, a, it + j);
-      else hipLaunchKernelGGL((k_fd_apply<3>), grid, blk, 0, st, a, it + j);
-      hipLaunchKernelGGL(k_fd_update, grid, blk, 0, st, a, it + j);
+      if (a.D == 2) hipLaunchKernelGGL((k_fd_iter<2>), grid, blk, 0, st, a, it + j);
+      else hipLaunchKernelGGL((k_fd_iter<3>), grid, blk, 0, st, a, it + j);
     }
     it += chunk;
     int done = 0;

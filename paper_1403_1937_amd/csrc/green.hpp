@@ -65,6 +65,7 @@ constexpr int kChebK0 = 28;
 struct ChebK0 {
   double c[kChebK0];
   float c32[kChebK0];
+  double c1[kChebK0];  // the same for sqrt(x) e^x K1(x) (the gradient's kernel derivative)
 };
 
 __device__ __forceinline__ double k0_cheb(double x, const ChebK0 &tab) {
@@ -194,8 +195,19 @@ __device__ inline double dkappa_2d(double beta, long long r2, const ChebK0 &tab)
   if (r2 == 0) return beta / kPi * bessel_k0_fast(beta / sqrt(kPi), tab);
   const double x = beta * sqrt((double)r2);
   double xk1;  // x K1(x)
-  if (x <= 2.0) xk1 = 1.0 - one_minus_aK1(x);
-  else xk1 = x * exp(-x) * (x < 25.0 ? k_trapezoid_scaled(x, 1) : k_hankel_scaled(x, 1));
+  if (x <= 2.0) {
+    xk1 = 1.0 - one_minus_aK1(x);
+  } else {  // Chebyshev series of sqrt(x) e^x K1(x) in t = 4/x - 1
+    const double t = 4.0 / x - 1.0, t2 = 2.0 * t;
+    double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+    for (int k = kChebK0 - 1; k >= 1; --k) {
+      const double b0 = fma(t2, b1, tab.c1[k] - b2);
+      b2 = b1;
+      b1 = b0;
+    }
+    xk1 = sqrt(x) * exp(-x) * fma(t, b1, tab.c1[0] - b2);
+  }
   return beta / kPi * bessel_k0_fast(x, tab) - beta / (2.0 * kPi) * xk1;
 }
 
