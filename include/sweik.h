@@ -108,8 +108,8 @@ typedef struct sweik_plan_s *sweik_plan;
 /* Validate a problem and choose the kernel schedule.  Host only: makes no
  * HIP call.  Returns SWEIK_EINVAL for invalid fields, SWEIK_EUNSUPPORTED for
  * grids beyond the supported sizes.  Padded FFT lengths (the next power of
- * two >= 2n-1, at least 64): 2D axis 0 <= 4096 and axis 1 <= 8192 (FP64:
- * axis 1 <= 4096); 3D every axis <= 1024. */
+ * two >= 2n-1, at least 64): 2D axis 0 <= 4096 and axis 1 <= 8192; 3D
+ * every axis <= 1024. */
 sweik_status sweik_plan_create(const sweik_problem *problem, sweik_plan *out);
 void sweik_plan_destroy(sweik_plan plan);
 

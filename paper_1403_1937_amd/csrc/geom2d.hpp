@@ -37,7 +37,8 @@ constexpr int row_rpw(int H) { return H / 16 >= kThreads ? 1 : kThreads / (H / 1
 constexpr int col_cpw(int M0) { return M0 / 16 >= kThreads ? 1 : kThreads / (M0 / 16); }
 constexpr size_t kLdsDevice = 163840;  // gfx950 limit per work-group
 
-// Row pass LDS: twiddle table (2H entries of exp(-2 pi i k / 2H)), the stage
+// Row pass LDS: twiddle table of the split steps (H entries of
+// exp(-2 pi i k / 2H)), the stage
 // tables of the length-H FFT (room for either schedule), one padded line per
 // row, and (when it fits) staging rows for the pointwise operands so that
 // their loads are issued with the spectrum's.
@@ -49,7 +50,7 @@ template <typename R> constexpr int row_stage_tw(int H) {
 }
 template <typename R> constexpr size_t row_lds_core(int H) {
   return sizeof(R) * 2 *
-         ((size_t)2 * H + (size_t)row_stage_tw<R>(H) + (size_t)row_rpw(H) * lds_line_len(H));
+         ((size_t)H + (size_t)row_stage_tw<R>(H) + (size_t)row_rpw(H) * lds_line_len(H));
 }
 // static shared memory of a row pass (block reductions, scalars, the term
 // scales; phi_0 also holds up to 512 sources and their weights)

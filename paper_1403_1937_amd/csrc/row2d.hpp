@@ -188,7 +188,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   constexpr int P = H / E, RPW = row_rpw(H), LL = lds_line_len(H), NT = team_threads(E);
   constexpr int TWLOG = ilog2c(2 * H);
   constexpr bool STG = row_staged<R>(H, MODE);
-  constexpr int NTW = (2 * H + NT - 1) / NT;
+  constexpr int NTW = (H + NT - 1) / NT;
   constexpr bool TERMLIKE = MODE == ROW_TERM || MODE == ROW_LAST;
   constexpr bool ADJ = MODE == ROW_ADJ || MODE == ROW_ADJ_B;
   constexpr bool ADJ0 = MODE == ROW_ADJ0 || MODE == ROW_ADJ0_B;
@@ -197,8 +197,8 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   constexpr bool LOADS_TILE = TERMLIKE || ADJ || MODE == ROW_PHI0;
   // phi_0 reads the spectrum only on its FFT route
   const bool tile_in = MODE != ROW_PHI0 || a.phi0_fft;
-  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / 2H), k < 2H
-  C *tws = twl + 2 * H;                      // stage tables of the length-H FFT
+  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / 2H), k < H (split steps)
+  C *tws = twl + H;                          // stage tables of the length-H FFT
   C *lines = tws + row_stage_tw<R>(H);
   unsigned char *stg = reinterpret_cast<unsigned char *>(lines + RPW * LL);
   __shared__ double s_par[2];
@@ -226,7 +226,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int k = tid + u * NT;
-    twr[u] = a.tw[min(k, 2 * H - 1) << (a.lmax_log - TWLOG)];  // stored only if k < 2 * H
+    twr[u] = a.tw[min(k, H - 1) << (a.lmax_log - TWLOG)];  // stored only if k < H
   }
   constexpr int NSR = (stage_tw_len(H, E) + NT - 1) / NT;
   C tsr[NSR > 0 ? NSR : 1];
@@ -403,7 +403,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int k = tid + u * NT;
-    if (k < 2 * H) twl[k] = twr[u];
+    if (k < H) twl[k] = twr[u];
   }
   stage_tw_store<H, E>(tsr, tws, tid, NT);
   if (LOADS_TILE && tile_in) tile_to_lds<FULL>(tile, tid, tl, lines);

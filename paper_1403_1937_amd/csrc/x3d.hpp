@@ -15,7 +15,7 @@ namespace sweik {
 
 // Odd-frequency real transform of a line of M = 2H real samples held by a
 // team as u(m) = x(2m) + i x(2m+1), m = t + P j.  With w(q) = exp(-2 pi i q /
-// 2M) (the LDS table, 4H entries):
+// 2M) (the LDS table holds q < 2H, all that the twiddles below use):
 //   forward  U = FFT_H(u(m) w(2m));  X(k) = E(k) + w(2k+1) O(k) with
 //            2E = U(k) + conj U(H-1-k), 2iO = U(k) - conj U(H-1-k)
 //            -> returns 2 X(k) = sum_j x(j) exp(-2 pi i j (k + 1/2) / M)
@@ -72,9 +72,9 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   using C = cplx<R>;
   constexpr int P = H / 16, LPW = x_lpw(H), LL = lds_line_len(H);
   constexpr int TWLOG = ilog2c(4 * H);
-  constexpr int NTW = (4 * H + kThreads - 1) / kThreads;
-  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i q / 4H), q < 4H
-  C *tws = twl + 4 * H;                      // stage tables of the length-H FFT
+  constexpr int NTW = (2 * H + kThreads - 1) / kThreads;  // q < 2H are used
+  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i q / 4H), q < 2H
+  C *tws = twl + 2 * H;                      // stage tables of the length-H FFT
   C *lines = tws + stage_tw_len(H, 16);
   __shared__ double s_par[1];
 
@@ -95,7 +95,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int k = tid + u * kThreads;
-    twr[u] = a.tw[min(k, 4 * H - 1) << (a.lmax_log - TWLOG)];  // stored only if k < 4 * H
+    twr[u] = a.tw[min(k, 2 * H - 1) << (a.lmax_log - TWLOG)];  // stored only if k < 2 * H
   }
   constexpr int NSR = (stage_tw_len(H, 16) + kThreads - 1) / kThreads;
   C tsr[NSR > 0 ? NSR : 1];
@@ -218,7 +218,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int k = tid + u * kThreads;
-    if (k < 4 * H) twl[k] = twr[u];
+    if (k < 2 * H) twl[k] = twr[u];
   }
   stage_tw_store<H, 16>(tsr, tws, tid, kThreads);
   __syncthreads();

@@ -68,9 +68,9 @@ def test_unsupported_sizes(lib):
     with pytest.raises(ValueError, match="unsupported"):
         _plan(dims=(64, 8192))      # row FFT length 16384
     _plan(dims=(2048, 4096))        # largest 2D grid
-    _plan(dims=(2048, 2048), precision="fp64")  # largest float64 row length
+    _plan(dims=(2048, 4096), precision="fp64")  # largest float64 grid
     with pytest.raises(ValueError, match="unsupported"):
-        _plan(dims=(64, 2049), precision="fp64")  # float64 row FFT length 8192
+        _plan(dims=(64, 4097), precision="fp64")  # row FFT length 16384
     for prec in ("fp32", "fp64"):
         _plan(dims=(512, 512, 512), precision=prec)  # largest 3D grid
         with pytest.raises(ValueError, match="unsupported"):

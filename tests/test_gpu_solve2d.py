@@ -44,6 +44,7 @@ CASES = [
     ("tall257x20", (257, 20), 1 / 257, 0.25, 4, 2, 5),
     ("square256", (256, 256), 1 / 256, 0.05, 10, 16, 6),
     ("rect200x513", (200, 513), 1 / 513, 0.1, 7, 4, 7),
+    ("wide24x3000", (24, 3000), 1 / 3000, 0.3, 4, 2, 8),  # row FFT length 8192
 ]
 
 
