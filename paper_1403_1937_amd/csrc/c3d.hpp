@@ -29,8 +29,8 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
   using C = cplx<R>;
   constexpr int P = M / 16, CPW = c3_cpw(M), NT = c3_threads(M), LL = lds_line_len(M);
   constexpr int HM = M / 2;
-  C *twl = reinterpret_cast<C *>(smem_raw);  // stage twiddle tables (< M entries)
-  C *lines = twl + M;
+  C *twl = reinterpret_cast<C *>(smem_raw);  // stage twiddle tables
+  C *lines = twl + stage_tw_len(M, 16);
 
   const int tid = threadIdx.x, c = tid % CPW, t = tid / CPW;
   const int ncb = a.H2 / CPW;  // H2 is a multiple of CPW

@@ -30,8 +30,8 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
   constexpr int NT = team_threads(E);
   constexpr int H0 = M0 / 2;
   static_assert(P % RB == 0, "column team must cover whole row blocks");
-  C *twl = reinterpret_cast<C *>(smem_raw);  // stage twiddle tables (< M0 entries)
-  C *lines = twl + M0;
+  C *twl = reinterpret_cast<C *>(smem_raw);  // stage twiddle tables
+  C *lines = twl + col_stage_tw<R>(M0);
 
   const int tid = threadIdx.x;
   const int grp = tid / RB, rr = tid - grp * RB;

@@ -55,7 +55,8 @@ constexpr int c3_threads(int M) { return c3_cpw(M) * (M / 16); }
 constexpr size_t x_lds_static(int mode) { return 1536 + (mode == X_PHI0 ? 6144 + 4096 : 0); }
 constexpr size_t kC3LdsStatic = 512;
 template <typename R> constexpr size_t c3_lds_bytes(int M) {
-  return sizeof(R) * 2 * ((size_t)M + (size_t)c3_cpw(M) * lds_line_len(M));
+  // the FFT's stage tables and one padded line per column
+  return sizeof(R) * 2 * ((size_t)stage_tw_len(M, 16) + (size_t)c3_cpw(M) * lds_line_len(M));
 }
 
 template <typename R> struct Args3 {

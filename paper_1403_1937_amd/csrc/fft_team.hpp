@@ -24,10 +24,18 @@ namespace sweik {
 
 template <typename R> struct cplx_t;
 template <> struct cplx_t<float> { using type = float2; };
-template <> struct cplx_t<double> { using type = double2; };
+// float64 complex values are a native two-lane vector: register arrays of
+// them stay in registers, where arrays of HIP's double2 (or of a plain
+// struct of two doubles) were placed in scratch memory by the compiler
+typedef double double2v __attribute__((ext_vector_type(2)));
+template <> struct cplx_t<double> { using type = double2v; };
 template <typename R> using cplx = typename cplx_t<R>::type;
+template <typename C> struct real_of;
+template <> struct real_of<float2> { using type = float; };
+template <> struct real_of<double2v> { using type = double; };
+template <typename C> using real_t = typename real_of<C>::type;
 
-template <typename C> __device__ __forceinline__ C cmake(decltype(C::x) a, decltype(C::x) b) {
+template <typename C> __device__ __forceinline__ C cmake(real_t<C> a, real_t<C> b) {
   C c;
   c.x = a;
   c.y = b;
@@ -43,7 +51,7 @@ template <typename C> __device__ __forceinline__ C cmulc(C a, C b) {
   return cmake<C>(a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y);
 }
 template <typename C> __device__ __forceinline__ C cconj(C a) { return cmake<C>(a.x, -a.y); }
-template <typename C> __device__ __forceinline__ C cscale(C a, decltype(C::x) s) { return cmake<C>(a.x * s, a.y * s); }
+template <typename C> __device__ __forceinline__ C cscale(C a, real_t<C> s) { return cmake<C>(a.x * s, a.y * s); }
 // multiply by -i (forward) or +i (inverse)
 template <bool INV, typename C> __device__ __forceinline__ C cmul_mi(C a) {
   return INV ? cmake<C>(-a.y, a.x) : cmake<C>(a.y, -a.x);
@@ -63,7 +71,7 @@ __device__ constexpr double kSin16[16] = {
 
 // v *= exp(-+ 2 pi i m / R) with compile-time R, m  (sign: - forward, + inverse)
 template <int R, int M, bool INV, typename C> __device__ __forceinline__ C twc(C v) {
-  using T = decltype(C::x);
+  using T = real_t<C>;
   constexpr int m16 = (M * (16 / R)) & 15;
   if constexpr (m16 == 0) {
     return v;

@@ -33,7 +33,11 @@ template <typename R> constexpr int spec_rb() { return sizeof(R) == 4 ? 4 : 2; }
 constexpr int kThreads = 256;
 // threads of a 2D pass work-group with E elements per team thread
 constexpr int team_threads(int E) { return kThreads * 16 / E; }
-constexpr int row_rpw(int H) { return H / 16 >= kThreads ? 1 : kThreads / (H / 16); }
+// Row passes: rows per work-group (kRowThreads / (H/16) rows at radix 16;
+// one row when a row needs more threads) and threads per work-group.
+constexpr int kRowThreads = 256;
+constexpr int row_rpw(int H) { return H / 16 >= kRowThreads ? 1 : kRowThreads / (H / 16); }
+constexpr int row_threads(int H, int E) { return row_rpw(H) * (H / E); }
 constexpr int col_cpw(int M0) { return M0 / 16 >= kThreads ? 1 : kThreads / (M0 / 16); }
 constexpr size_t kLdsDevice = 163840;  // gfx950 limit per work-group
 
@@ -75,10 +79,16 @@ template <typename R> constexpr size_t row_lds_bytes(int H, int mode) {
 template <typename R> constexpr bool row_fits(int H, int mode) {
   return row_lds_bytes<R>(H, mode) + row_lds_static(mode) <= kLdsDevice;
 }
-// Column pass LDS: twiddle table (M0 entries of exp(-2 pi i k / M0)) and
-// one padded line per column.
+// Column pass LDS: the stage twiddle tables of the length-M0 FFT (room for
+// any schedule) and one padded line per column.
+template <typename R> constexpr int col_stage_tw(int M0) {
+  int n = stage_tw_len(M0, 16);
+  n = stage_tw_len(M0, 8) > n ? stage_tw_len(M0, 8) : n;
+  if (sizeof(R) == 4) n = stage_tw_len(M0, 4) > n ? stage_tw_len(M0, 4) : n;  // radix 4: float only
+  return n;
+}
 template <typename R> constexpr size_t col_lds_bytes(int M0) {
-  return sizeof(R) * 2 * ((size_t)M0 + (size_t)col_cpw(M0) * lds_line_len(M0));
+  return sizeof(R) * 2 * ((size_t)col_stage_tw<R>(M0) + (size_t)col_cpw(M0) * lds_line_len(M0));
 }
 constexpr size_t kColLdsStatic = 512;  // static shared memory of a column pass
 template <typename R> constexpr bool col_fits(int M0) {

@@ -52,7 +52,7 @@ template <typename R, int E, int MODE> struct RowLaunch {
     } else {
       static const hipError_t attr = set_lds(k_row2<R, MODE, H, E>, lds);
       if (attr != hipSuccess) return attr;
-      hipLaunchKernelGGL((k_row2<R, MODE, H, E>), grid, dim3(team_threads(E)), lds, st, a, term);
+      hipLaunchKernelGGL((k_row2<R, MODE, H, E>), grid, dim3(row_threads(H, E)), lds, st, a, term);
       return hipGetLastError();
     }
   }
@@ -65,7 +65,7 @@ template <typename R, int E, int MODE> struct RowLaunch {
     } else {
       static const hipError_t attr = set_lds(k_row2_batch<R, MODE, H, E>, lds);
       if (attr != hipSuccess) return attr;
-      hipLaunchKernelGGL((k_row2_batch<R, MODE, H, E>), dim3(nblocks), dim3(team_threads(E)),
+      hipLaunchKernelGGL((k_row2_batch<R, MODE, H, E>), dim3(nblocks), dim3(row_threads(H, E)),
                          lds, st, items, nitems, term);
       return hipGetLastError();
     }

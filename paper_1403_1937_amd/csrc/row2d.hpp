@@ -1,7 +1,7 @@
 // row2d.hpp -- row passes of the 2D solve (forward and adjoint).
 //
-// One team of P = H/E threads per grid row (E = 16 or 8 elements per
-// thread; 4096/E threads per work-group), RPW = 4096/H rows per work-group.  A
+// One team of P = H/E threads per grid row (E = 16, 8 or 4 elements per
+// thread), RPW = max(1, 4096/H) rows and RPW P threads per work-group.  A
 // pass (i) reads its spectral tile (RPW contiguous rows of the blocked
 // spectrum), the twiddle table and the pointwise operands of its rows,
 // (ii) takes the inverse real FFT of each row (complex FFT of length H
@@ -20,7 +20,7 @@ namespace sweik {
 // and Nyquist bins of the row as one complex number).  Element e <-> (local
 // row, column).
 template <typename R, int H, int E> struct RowTile {
-  static constexpr int RB = spec_rb<R>(), RPW = row_rpw(H), LDK = H, NT = team_threads(E);
+  static constexpr int RB = spec_rb<R>(), RPW = row_rpw(H), LDK = H, NT = row_threads(H, E);
   static constexpr int NREG = (RPW * LDK + NT - 1) / NT;  // per thread
   cplx<R> *base;
   int rows;
@@ -185,7 +185,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
                                          const int bid) {
   using C = cplx<R>;
   using Tile = RowTile<R, H, E>;
-  constexpr int P = H / E, RPW = row_rpw(H), LL = lds_line_len(H), NT = team_threads(E);
+  constexpr int P = H / E, RPW = row_rpw(H), LL = lds_line_len(H), NT = row_threads(H, E);
   constexpr int TWLOG = ilog2c(2 * H);
   constexpr bool STG = row_staged<R>(H, MODE);
   constexpr int NTW = (H + NT - 1) / NT;
@@ -798,7 +798,7 @@ __device__ __forceinline__ void row_block(const Args2<R> &a, int term, unsigned 
 }
 
 template <typename R, int MODE, int H, int E>
-__global__ void __launch_bounds__(team_threads(E)) k_row2(Args2<R> a, int term) {
+__global__ void __launch_bounds__(row_threads(H, E)) k_row2(Args2<R> a, int term) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   row_block<R, MODE, H, E>(a, term, smem_raw, blockIdx.x);
 }
@@ -806,7 +806,7 @@ __global__ void __launch_bounds__(team_threads(E)) k_row2(Args2<R> a, int term) 
 // Uneven batch: one launch over the row work-groups of every instance of a
 // size class; items[i].begin is the first work-group of instance i.
 template <typename R, int MODE, int H, int E>
-__global__ void __launch_bounds__(team_threads(E)) k_row2_batch(const BatchItem<R> *__restrict__ items,
+__global__ void __launch_bounds__(row_threads(H, E)) k_row2_batch(const BatchItem<R> *__restrict__ items,
                                                          int nitems, int term) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int i = find_item(items, nitems, (int)blockIdx.x);
