@@ -68,9 +68,16 @@ template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
               ? sizeof(R)
               : (mode == ROW_ADJ || mode == ROW_ADJ_B) ? 3 * sizeof(R) + 8 : 0);
 }
+// Staging is used when it fits, unless it would cost the second work-group
+// per CU that the pass has room for without it (the adjoint's 20 bytes per
+// point at 2048 columns): then the operands are read from memory where they
+// are used.  The full gradient's adjoint pass keeps its staging: its
+// registers allow one work-group per CU anyway.
 template <typename R> constexpr bool row_staged(int H, int mode) {
-  return row_stage_bytes<R>(H, mode) > 0 &&
-         row_lds_core<R>(H) + row_stage_bytes<R>(H, mode) + row_lds_static(mode) <= kLdsDevice;
+  const size_t plain = row_lds_core<R>(H) + row_lds_static(mode);
+  const size_t staged = plain + row_stage_bytes<R>(H, mode);
+  return row_stage_bytes<R>(H, mode) > 0 && staged <= kLdsDevice &&
+         (staged <= kLdsDevice / 2 || plain > kLdsDevice / 2 || mode == ROW_ADJ_B);
 }
 template <typename R> constexpr size_t row_lds_bytes(int H, int mode) {
   return row_lds_core<R>(H) + (row_staged<R>(H, mode) ? row_stage_bytes<R>(H, mode) : 0);
