@@ -15,18 +15,19 @@ namespace sweik {
 
 // Odd-frequency real transform of a line of M = 2H real samples held by a
 // team as u(m) = x(2m) + i x(2m+1), m = t + P j.  With w(q) = exp(-2 pi i q /
-// 2M) (the LDS table holds q < 2H, all that the twiddles below use):
+// 2M) (the LDS table holds the even ones, we[m] = w(2m) for m < H; an odd one
+// is w(2k+1) = we[k] w(1)):
 //   forward  U = FFT_H(u(m) w(2m));  X(k) = E(k) + w(2k+1) O(k) with
 //            2E = U(k) + conj U(H-1-k), 2iO = U(k) - conj U(H-1-k)
 //            -> returns 2 X(k) = sum_j x(j) exp(-2 pi i j (k + 1/2) / M)
 //   inverse  the same steps backwards; returns 2M times the real line.
 template <typename R, int H>
 __device__ __forceinline__ void odd_r2c(cplx<R> (&v)[16], int t, cplx<R> *line,
-                                        const cplx<R> *twl, const cplx<R> *tws) {
+                                        const cplx<R> *twl, const cplx<R> *tws, cplx<R> w1) {
   using C = cplx<R>;
   constexpr int P = H / 16;
 #pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = cmul(v[j], twl[2 * (t + P * j)]);
+  for (int j = 0; j < 16; ++j) v[j] = cmul(v[j], twl[t + P * j]);
   team_fft<H, false>(v, t, line, tws, true);
   __syncthreads();
 #pragma unroll
@@ -39,13 +40,13 @@ __device__ __forceinline__ void odd_r2c(cplx<R> (&v)[16], int t, cplx<R> *line,
     const C e = cadd(v[j], up);
     const C d = csub(v[j], up);
     const C o = cmake<C>(d.y, -d.x);  // -i d = 2 O
-    v[j] = cadd(e, cmul(o, twl[2 * k + 1]));
+    v[j] = cadd(e, cmul(o, cmul(twl[k], w1)));
   }
 }
 
 template <typename R, int H>
 __device__ __forceinline__ void odd_c2r(cplx<R> (&v)[16], int t, cplx<R> *line,
-                                        const cplx<R> *twl, const cplx<R> *tws) {
+                                        const cplx<R> *twl, const cplx<R> *tws, cplx<R> w1) {
   using C = cplx<R>;
   constexpr int P = H / 16;
   __syncthreads();
@@ -57,12 +58,12 @@ __device__ __forceinline__ void odd_c2r(cplx<R> (&v)[16], int t, cplx<R> *line,
     const int k = t + P * j;
     const C xp = cconj(line[lpad(H - 1 - k)]);
     const C e = cadd(v[j], xp);                         // 2E
-    const C o = cmulc(csub(v[j], xp), twl[2 * k + 1]);  // 2O
+    const C o = cmulc(csub(v[j], xp), cmul(twl[k], w1));  // 2O
     v[j] = cmake<C>(e.x - o.y, e.y + o.x);              // 2(E + iO)
   }
   team_fft<H, true>(v, t, line, tws, true);
 #pragma unroll
-  for (int j = 0; j < 16; ++j) v[j] = cmulc(v[j], twl[2 * (t + P * j)]);
+  for (int j = 0; j < 16; ++j) v[j] = cmulc(v[j], twl[t + P * j]);
 }
 
 // FULL: every line of the group exists and n2 == H2 (no bounds checks).
@@ -72,9 +73,9 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   using C = cplx<R>;
   constexpr int P = H / 16, LPW = x_lpw(H), LL = lds_line_len(H);
   constexpr int TWLOG = ilog2c(4 * H);
-  constexpr int NTW = (2 * H + kThreads - 1) / kThreads;  // q < 2H are used
-  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i q / 4H), q < 2H
-  C *tws = twl + 2 * H;                      // stage tables of the length-H FFT
+  constexpr int NTW = (H + kThreads - 1) / kThreads;
+  C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i 2m / 4H), m < H
+  C *tws = twl + H;                          // stage tables of the length-H FFT
   C *lines = tws + stage_tw_len(H, 16);
   __shared__ double s_par[1];
 
@@ -95,11 +96,12 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int k = tid + u * kThreads;
-    twr[u] = a.tw[min(k, 2 * H - 1) << (a.lmax_log - TWLOG)];  // stored only if k < 2 * H
+    twr[u] = a.tw[(2 * min(k, H - 1)) << (a.lmax_log - TWLOG)];  // stored only if k < H
   }
   constexpr int NSR = (stage_tw_len(H, 16) + kThreads - 1) / kThreads;
   C tsr[NSR > 0 ? NSR : 1];
   stage_tw_issue<H, 16>(tsr, a.tw, a.lmax_log, tid, kThreads);
+  const C w1 = a.tw[1 << (a.lmax_log - TWLOG)];  // w(1) = exp(-2 pi i / 4H)
   C v[16];
   if constexpr (TERMLIKE) {
     const C *sl = a.s1 + (size_t)rs * H;
@@ -218,7 +220,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
     const int k = tid + u * kThreads;
-    if (k < 2 * H) twl[k] = twr[u];
+    if (k < H) twl[k] = twr[u];
   }
   stage_tw_store<H, 16>(tsr, tws, tid, kThreads);
   __syncthreads();
@@ -244,7 +246,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     }
   }
 
-  if constexpr (TERMLIKE) odd_c2r<R, H>(v, t, line, twl, tws);
+  if constexpr (TERMLIKE) odd_c2r<R, H>(v, t, line, twl, tws, w1);
 
   // ---- 4. pointwise step -------------------------------------------------------
   if constexpr (MODE == X_PHI0 || TERMLIKE) {
@@ -389,7 +391,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   }
 
   // ---- 5. forward real FFT, store the line's spectrum ------------------------
-  odd_r2c<R, H>(v, t, line, twl, tws);
+  odd_r2c<R, H>(v, t, line, twl, tws, w1);
   if (line_ok) {
     C *sl = a.s1 + (size_t)rs * H;
 #pragma unroll
