@@ -319,6 +319,7 @@ def run_fwd_bwd(pk, torch, dev, steps, warmup):
             "ms_forward_with_checkpoints": ms_fwd, "ms_adjoint": ms - ms_fwd,
             "alg_bytes": fwd_bytes + bwd_bytes,
             "alg_GBps": (fwd_bytes + bwd_bytes) / (ms * 1e-3) / 1e9,
+            "hbm_frac": (fwd_bytes + bwd_bytes) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
             "precision": "fp32-scaled", "gradient_finite": ok, "schedule": plan.schedule,
             "full_gradient": {"value": N / (ms_full * 1e-3), "ms_per_step": ms_full,
                               "ms_adjoint_full": ms_full - ms_fwd,
@@ -435,7 +436,8 @@ def run_batched(pk, torch, dev, steps, warmup):
     return {"workload": f"batch64_uneven_T{T}", "instances_per_edge": sizes,
             "sum_grid_pts": sumN, "value": sumN / (ms * 1e-3), "unit": "grid pts/s",
             "ms_per_step": ms, "ms_per_step_eager": ms_eager, "alg_bytes": total,
-            "alg_GBps": total / (ms * 1e-3) / 1e9, "precision": "fp32-scaled",
+            "alg_GBps": total / (ms * 1e-3) / 1e9,
+            "hbm_frac": total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, "precision": "fp32-scaled",
             "execution": "one HIP graph replay per step", "schedules": sched}
 
 
