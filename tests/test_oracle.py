@@ -458,3 +458,31 @@ def test_seed_value_far_above_removes_the_source():
     c = oracle.solve(f, src, h, hbar, T, src_s=np.zeros(2))["S"]
     d = oracle.solve(f, src, h, hbar, T)["S"]
     assert np.array_equal(c, d)
+
+
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")
+def test_viscous_eikonal_residual():
+    # S = -hbar ln phi of the screened Poisson solution obeys
+    # |grad S|^2 - hbar lap S = f^2 (Section 4): by central differences the
+    # relative residual is small on the resolvable set away from the source,
+    # and shrinks with hbar
+    n = 96
+    h = 1.0 / n
+    m0, m1 = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    f = 1.0 + 0.4 * np.exp(-((m0 - 40) ** 2 + (m1 - 60) ** 2) / 300.0)
+    src = np.array([[48, 30]], np.int32)
+    med = []
+    for hbar in (0.08, 0.04, 0.02):
+        o = oracle.solve(f, src, h, hbar, 20)
+        S, phi = o["S"], o["phi"]
+        lam = np.log(phi.max() / np.where(phi > 0, phi, 1e-300))
+        c = (slice(1, -1), slice(1, -1))
+        gx = (S[2:, 1:-1] - S[:-2, 1:-1]) / (2 * h)
+        gy = (S[1:-1, 2:] - S[1:-1, :-2]) / (2 * h)
+        lap = (S[2:, 1:-1] + S[:-2, 1:-1] + S[1:-1, 2:] + S[1:-1, :-2] - 4 * S[c]) / h ** 2
+        r = np.abs(gx ** 2 + gy ** 2 - hbar * lap - f[c] ** 2) / f[c] ** 2
+        ok = (np.hypot(m0 - 48, m1 - 30)[c] > 8) & (lam[c] < 9)
+        med.append(float(np.median(r[ok])))
+    assert med[1] < 0.15 and med[2] < 0.1
+    assert med[0] > med[1] > med[2]
+

@@ -52,3 +52,27 @@ def test_m_matrix_properties():
     # the other sources only add positive terms)
     d = (h * f / hbar) ** 2
     assert np.all(phi[tuple(src.T)] >= 1.0 / (4.0 + d[tuple(src.T)]))
+
+
+@pytest.mark.filterwarnings("ignore::RuntimeWarning")
+def test_fd_and_series_agree_to_order_hbar():
+    # the FD system and the perturbation series discretise the same screened
+    # Poisson problem differently (and normalise phi differently at the
+    # source), so their S agree up to O(hbar): the gap divided by hbar stays
+    # bounded as hbar shrinks, on the set the FP64 series resolves
+    import oracle
+    n = 96
+    h = 1.0 / n
+    m0, m1 = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    f = 1.0 + 0.4 * np.exp(-((m0 - 40) ** 2 + (m1 - 60) ** 2) / 300.0)
+    src = np.array([[48, 30]], np.int32)
+    far = np.hypot(m0 - 48, m1 - 30) > 6
+    gaps = []
+    for hbar in (0.08, 0.04, 0.02):
+        o = oracle.solve(f, src, h, hbar, 20)
+        lam = np.log(o["phi"].max() / np.where(o["phi"] > 0, o["phi"], 1e-300))
+        mk = far & (lam < 9)
+        gap = np.abs(fd.solve(f, src, h, hbar)["S"] - o["S"])[mk].max() / hbar
+        gaps.append(gap)
+    assert max(gaps) < 8.0
+    assert gaps[-1] < gaps[0]
