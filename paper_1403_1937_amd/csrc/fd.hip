@@ -256,6 +256,107 @@ __global__ void __launch_bounds__(kFdThreads) k_fd_iter(FdArgs a, int k) {
     for (int q = 0; q < 3; ++q) part_of(a, nxt, q)[blockIdx.x] = t[q];
 }
 
+// 2D form of the same step on tiles of kFdTileRows x kFdThreads points: the
+// new preconditioned residual is formed once per point of the tile and its
+// one-point halo into LDS, and the stencil reads it there (a point's four
+// neighbours then cost no extra global reads).
+constexpr int kFdTileRows = 4;
+__global__ void __launch_bounds__(kFdThreads) k_fd_iter_2d(FdArgs a, int k) {
+  if (a.state[0]) return;
+  const int cur = k & 1, nxt = cur ^ 1;
+  double sc[3];
+  reduce_parts(a, cur, sc);
+  const double gam = sc[0], del = sc[1], rr = sc[2], bb = a.scal[0];
+  if (rr <= a.tol2 * bb) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      a.state[0] = 1;
+      a.state[1] = k;
+      a.scal[1] = rr;
+    }
+    return;
+  }
+  double beta = 0.0, alpha = gam / del;
+  if (k > 0) {
+    beta = gam / a.hist[2 * nxt];
+    alpha = gam / (del - beta * gam / a.hist[2 * nxt + 1]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.hist[2 * cur] = gam;
+    a.hist[2 * cur + 1] = alpha;
+  }
+  const double *__restrict__ r0 = a.r[cur];
+  const double *__restrict__ w0 = a.w[cur];
+  const double *__restrict__ s0 = a.s[nxt];
+  double *__restrict__ r1 = a.r[nxt];
+  double *__restrict__ w1 = a.w[nxt];
+  double *__restrict__ s1 = a.s[cur];
+  const double *__restrict__ dinv = a.dinv;
+  constexpr int TR = kFdTileRows;
+  __shared__ double su[TR + 2][kFdThreads + 2];  // new u on the tile and its halo (0 outside)
+  const int n0 = a.n[0], n1 = a.n[1];
+  const int tiles1 = (n1 + kFdThreads - 1) / kFdThreads;
+  const long long ntiles = (long long)((n0 + TR - 1) / TR) * tiles1;
+  const int t = threadIdx.x;
+  auto unew = [&](int row, int col) -> double {
+    if (row < 0 || row >= n0 || col < 0 || col >= n1) return 0.0;
+    const long long j = (long long)row * n1 + col;
+    return (r0[j] - alpha * (w0[j] + beta * s0[j])) * dinv[j];
+  };
+  double g = 0.0, dl = 0.0, rs = 0.0;
+  for (long long tile = blockIdx.x; tile < ntiles; tile += kFdBlocks) {
+    const int tr = (int)(tile / tiles1), tc = (int)(tile - (long long)tr * tiles1);
+    const int row0 = tr * TR, col0 = tc * kFdThreads, c = col0 + t;
+    double rv[TR], wv[TR], sv[TR], dv[TR];
+#pragma unroll
+    for (int q = 0; q < TR; ++q) {  // the tile's own points: keep the old values
+      const int row = row0 + q;
+      rv[q] = wv[q] = sv[q] = dv[q] = 0.0;
+      double u = 0.0;
+      if (row < n0 && c < n1) {
+        const long long i = (long long)row * n1 + c;
+        rv[q] = r0[i];
+        wv[q] = w0[i];
+        sv[q] = s0[i];
+        dv[q] = dinv[i];
+        u = (rv[q] - alpha * (wv[q] + beta * sv[q])) * dv[q];
+      }
+      su[q + 1][t + 1] = u;
+    }
+    su[0][t + 1] = unew(row0 - 1, c);
+    su[TR + 1][t + 1] = unew(row0 + TR, c);
+    if (t < 2 * (TR + 2)) {  // halo columns
+      const int side = t / (TR + 2), q = t - side * (TR + 2);
+      su[q][side ? kFdThreads + 1 : 0] = unew(row0 - 1 + q, side ? col0 + kFdThreads : col0 - 1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < TR; ++q) {
+      const int row = row0 + q;
+      if (row < n0 && c < n1) {
+        const long long i = (long long)row * n1 + c;
+        const double p = rv[q] * dv[q] + beta * a.p[i];
+        const double s = wv[q] + beta * sv[q];
+        a.p[i] = p;
+        s1[i] = s;
+        a.x[i] += alpha * p;
+        const double rn = rv[q] - alpha * s;
+        const double u = rn * dv[q];
+        const double w = rn - (su[q][t + 1] + su[q + 2][t + 1] + su[q + 1][t] + su[q + 1][t + 2]);
+        r1[i] = rn;
+        w1[i] = w;
+        g += rn * u;
+        dl += w * u;
+        rs += rn * rn;
+      }
+    }
+    __syncthreads();  // before the next tile overwrites su
+  }
+  double tt[3] = {g, dl, rs};
+  block_sums(tt);
+  if (threadIdx.x == 0)
+    for (int q = 0; q < 3; ++q) part_of(a, nxt, q)[blockIdx.x] = tt[q];
+}
+
 template <typename R>
 __global__ void __launch_bounds__(kFdThreads) k_fd_finish(FdArgs a, R *__restrict__ S, double hbar,
                                                           int iters_run) {
@@ -355,7 +456,7 @@ sweik_status fd_run(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   while (it < max_iter) {
     const int chunk = max_iter - it < kFdChunk ? max_iter - it : kFdChunk;
     for (int j = 0; j < chunk; ++j) {
-      if (a.D == 2) hipLaunchKernelGGL((k_fd_iter<2>), grid, blk, 0, st, a, it + j);
+      if (a.D == 2) hipLaunchKernelGGL(k_fd_iter_2d, grid, blk, 0, st, a, it + j);
       else hipLaunchKernelGGL((k_fd_iter<3>), grid, blk, 0, st, a, it + j);
     }
     it += chunk;
