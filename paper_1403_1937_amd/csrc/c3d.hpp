@@ -22,6 +22,16 @@
 
 namespace sweik {
 
+// C3_Z: planes k1 and M1 - k1 read the same kernel spectrum columns, so they
+// are visited one after the other (0, H1, 1, M1 - 1, 2, M1 - 2, ...): the
+// second read of a column block then hits in L2 instead of fetching the
+// kernel spectrum twice from memory.
+__device__ __forceinline__ int z_plane(int p, int M1) {
+  if (p < 2) return p * (M1 / 2);
+  const int i = (p - 2) / 2 + 1;
+  return (p & 1) ? M1 - i : i;
+}
+
 // FULL: the loaded axis is exactly half the padded length (no bounds checks).
 template <typename R, int MODE, int M, bool FULL>
 __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned char *smem_raw,
@@ -34,7 +44,8 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
 
   const int tid = threadIdx.x, c = tid % CPW, t = tid / CPW;
   const int ncb = a.H2 / CPW;  // H2 is a multiple of CPW
-  const int plane = g / ncb, k2 = (g - plane * ncb) * CPW + c;
+  const int pg = g / ncb, k2 = (g - pg * ncb) * CPW + c;
+  const int plane = MODE == C3_Z ? z_plane(pg, a.M1) : pg;
   C *line = lines + c * LL;
   const size_t H2 = (size_t)a.H2;
 

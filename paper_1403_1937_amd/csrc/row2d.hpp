@@ -797,10 +797,20 @@ __device__ __forceinline__ void row_block(const Args2<R> &a, int term, unsigned 
     row_pass<R, MODE, H, E, false>(a, term, smem_raw, bid);
 }
 
+// When a tile holds fewer rows than a spectrum block (RPW < RB), the tiles of
+// one block share its 32-byte entries: work-groups are then mapped so that
+// neighbouring tiles run on the same XCD, where the halves of an entry meet
+// in one L2 instead of being fetched, and written back as partial lines, once
+// per XCD (this doubled the row passes' traffic at 2048 columns).  Tiles of
+// whole blocks keep the dispatch order, which measures faster for them.
+template <typename R, int H> __device__ __forceinline__ int row_tile_id(int b, int nblocks) {
+  return row_rpw(H) < spec_rb<R>() ? xcd_tile(b, nblocks) : b;
+}
+
 template <typename R, int MODE, int H, int E>
 __global__ void __launch_bounds__(row_threads(H, E)) k_row2(Args2<R> a, int term) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  row_block<R, MODE, H, E>(a, term, smem_raw, blockIdx.x);
+  row_block<R, MODE, H, E>(a, term, smem_raw, row_tile_id<R, H>(blockIdx.x, gridDim.x));
 }
 
 // Uneven batch: one launch over the row work-groups of every instance of a
@@ -809,9 +819,10 @@ template <typename R, int MODE, int H, int E>
 __global__ void __launch_bounds__(row_threads(H, E)) k_row2_batch(const BatchItem<R> *__restrict__ items,
                                                          int nitems, int term) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int i = find_item(items, nitems, (int)blockIdx.x);
+  const int g = row_tile_id<R, H>(blockIdx.x, gridDim.x);
+  const int i = find_item(items, nitems, g);
   const Args2<R> a = item_args(items[i]);
-  row_block<R, MODE, H, E>(a, term, smem_raw, (int)blockIdx.x - items[i].begin);
+  row_block<R, MODE, H, E>(a, term, smem_raw, g - items[i].begin);
 }
 
 // Adjoint start: max |lambda| partials (with the twiddle table).
