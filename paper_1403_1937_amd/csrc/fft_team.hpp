@@ -142,11 +142,44 @@ template <int R, bool INV, typename C> struct Dft {
   }
 };
 
-// LDS index with one pad slot every 16 elements (breaks the stride-16
-// pattern of the first Stockham stage).
+__host__ __device__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
+
+// LDS layouts of a line.
+//   padded   one pad slot every 16 elements (breaks the stride-16 pattern of
+//            the first Stockham stage); lpad, lds_line_len
+//   packed   float2 lines only: unpadded, the exchanges inside the FFT
+//            XOR-swizzled per stage (stage_slot); lslot.  The LDS serves a
+//            wave's 8-byte accesses 32 lanes at a time over 64 four-byte
+//            banks, so 32 consecutive float2 elements fill the banks exactly
+//            once, and a pad slot inside such a run costs a second cycle.
+//            Used by the 2D row passes (one team per wave at the benchmark
+//            sizes).  The column passes (the 2048-point ones interleave two
+//            teams in a wave) and the 3D passes measured slower with it and
+//            keep the padded layout, as does every double2 line.
 __host__ __device__ constexpr int lpad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lds_line_len(int L) { return L + (L >> 4) + 1; }
-__host__ __device__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
+template <typename C> __host__ __device__ constexpr int lslot(int i) {
+  return sizeof(C) == 8 ? i : lpad(i);
+}
+
+// Slot of element x of the exchange after a Stockham stage of span p and
+// radix R (float2 lines).  The stage's writes are runs of p lanes at stride
+// p R elements (p = 1: single lanes at stride R); the swizzle moves run m of
+// a 32-lane group to its own bank range by XOR-ing the bits of x below 32
+// that vary inside a run with m.  The gather that follows reads 32 aligned
+// consecutive elements, which the swizzle only permutes.  Only the five
+// lowest bits of x change, so a slot stays inside its aligned run of 32.
+template <int p, int R, bool PACKED, typename C> __device__ __forceinline__ int stage_slot(int x) {
+  if constexpr (!PACKED || sizeof(C) != 8) {
+    return lpad(x);
+  } else if constexpr (p == 1) {
+    return x ^ ((x >> 5) & (R - 1));
+  } else if constexpr (p < 32 && p * R >= 64) {
+    return x ^ (((x >> ilog2c(p * R)) & (32 / p - 1)) << ilog2c(p));
+  } else {
+    return x;
+  }
+}
 
 // Stage twiddle tables: for every stage of span p > 1 (p = E, E^2, ... < L)
 // the p entries exp(-2 pi i k / (p R)), k < p, stored contiguously in LDS one
@@ -179,7 +212,7 @@ template <int L, int E> __device__ __forceinline__ int stage_tw_index(int e, int
 // E elements per thread).  Twiddles exp(-2 pi i q k / (p R)) are powers of
 // the stage table's entry k; LAST: results stay in registers (index t + P j),
 // else they go to LDS at the autosort position.
-template <int L, int R, int p, bool INV, bool LAST, int E, typename C>
+template <int L, int R, int p, bool INV, bool LAST, bool PACKED, int E, typename C>
 __device__ __forceinline__ void stage(C (&v)[E], int t, C *lds, const C *tws) {
   constexpr int P = L / E;
   constexpr int NB = E / R;  // butterflies per thread
@@ -208,29 +241,30 @@ __device__ __forceinline__ void stage(C (&v)[E], int t, C *lds, const C *tws) {
     } else {
       const int base = (i - k) * R + k;
 #pragma unroll
-      for (int q = 0; q < R; ++q) lds[lpad(base + q * p)] = u[q];
+      for (int q = 0; q < R; ++q) lds[stage_slot<p, R, PACKED, C>(base + q * p)] = u[q];
     }
   }
 }
 
-template <int L, int E, typename C>
+// the gather after the stage of span p (radix E)
+template <int L, int E, int p, bool PACKED, typename C>
 __device__ __forceinline__ void lds_gather(C (&v)[E], int t, const C *lds) {
   constexpr int P = L / E;
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < E; ++j) v[j] = lds[lpad(t + P * j)];
+  for (int j = 0; j < E; ++j) v[j] = lds[stage_slot<p, E, PACKED, C>(t + P * j)];
   __syncthreads();
 }
 
 // Stages of span p, p E, p E^2, ... (radix E), the last of radix L / p.
-template <int L, bool INV, int E, int p, typename C>
+template <int L, bool INV, bool PACKED, int E, int p, typename C>
 __device__ __forceinline__ void team_stages(C (&v)[E], int t, C *lds, const C *tws) {
   if constexpr (p * E >= L) {
-    stage<L, L / p, p, INV, true, E>(v, t, lds, tws);
+    stage<L, L / p, p, INV, true, PACKED, E>(v, t, lds, tws);
   } else {
-    stage<L, E, p, INV, false, E>(v, t, lds, tws);
-    lds_gather<L, E>(v, t, lds);
-    team_stages<L, INV, E, p * E>(v, t, lds, tws);
+    stage<L, E, p, INV, false, PACKED, E>(v, t, lds, tws);
+    lds_gather<L, E, p, PACKED>(v, t, lds);
+    team_stages<L, INV, PACKED, E, p * E>(v, t, lds, tws);
   }
 }
 
@@ -238,14 +272,15 @@ __device__ __forceinline__ void team_stages(C (&v)[E], int t, C *lds, const C *t
 // stages; E = 8: radix-8 stages); tws: the LDS stage twiddle tables of a
 // length-L line (stage_tw_len(L, E) entries).  Barriers are block-wide:
 // every thread of the block calls this.  With lead_sync a barrier first
-// protects LDS data still being read from earlier work.
-template <int L, bool INV, int E, typename C>
+// protects LDS data still being read from earlier work.  PACKED selects the
+// packed line layout (float2 only; see lslot).
+template <int L, bool INV, bool PACKED = false, int E, typename C>
 __device__ __forceinline__ void team_fft(C (&v)[E], int t, C *lds, const C *tws,
                                          bool lead_sync = true) {
   static_assert(L >= E && L <= 4096 && (L & (L - 1)) == 0, "line length");
   static_assert(E == 4 || E == 8 || E == 16, "elements per thread");
   if (lead_sync) __syncthreads();
-  team_stages<L, INV, E, 1>(v, t, lds, tws);
+  team_stages<L, INV, PACKED, E, 1>(v, t, lds, tws);
 }
 
 // The stage tables of a length-L line: issue the global reads into

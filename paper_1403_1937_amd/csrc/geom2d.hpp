@@ -52,9 +52,18 @@ template <typename R> constexpr int row_stage_tw(int H) {
   if (sizeof(R) == 4) n = stage_tw_len(H, 4) > n ? stage_tw_len(H, 4) : n;  // radix 4: float only
   return n;
 }
+// Line length of a row pass.  The tile transposes put Q = min(RPW, RB) rows
+// in a 32-lane group (row fastest): float2 lines start 32/Q elements apart
+// modulo 32, so the Q rows of a group fall on disjoint banks.
+template <typename R> constexpr int row_line_len(int H) {
+  return sizeof(R) != 4 ? lds_line_len(H)
+         : H + ((row_rpw(H) < spec_rb<R>() ? row_rpw(H) : spec_rb<R>()) > 1
+                    ? 32 / (row_rpw(H) < spec_rb<R>() ? row_rpw(H) : spec_rb<R>())
+                    : 0);
+}
 template <typename R> constexpr size_t row_lds_core(int H) {
   return sizeof(R) * 2 *
-         ((size_t)H + (size_t)row_stage_tw<R>(H) + (size_t)row_rpw(H) * lds_line_len(H));
+         ((size_t)H + (size_t)row_stage_tw<R>(H) + (size_t)row_rpw(H) * row_line_len<R>(H));
 }
 // static shared memory of a row pass (block reductions, scalars, the term
 // scales; phi_0 also holds up to 512 sources and their weights)

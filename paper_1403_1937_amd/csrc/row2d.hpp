@@ -67,7 +67,7 @@ template <bool FULL, typename R, int H, int E>
 __device__ __forceinline__ void tile_to_lds(const RowTile<R, H, E> &tile, int tid,
                                             const cplx<R> (&tl)[RowTile<R, H, E>::NREG],
                                             cplx<R> *lines) {
-  constexpr int LL = lds_line_len(H);
+  constexpr int LL = row_line_len<R>(H);
   const int total = tile.rows * H;
 #pragma unroll
   for (int u = 0; u < RowTile<R, H, E>::NREG; ++u) {
@@ -75,7 +75,7 @@ __device__ __forceinline__ void tile_to_lds(const RowTile<R, H, E> &tile, int ti
     if (FULL || e < total) {
       int rl, k1, off;
       tile.map(e, rl, k1, off);
-      lines[rl * LL + lpad(k1)] = tl[u];
+      lines[rl * LL + lslot<cplx<R>>(k1)] = tl[u];
     }
   }
 }
@@ -83,7 +83,7 @@ __device__ __forceinline__ void tile_to_lds(const RowTile<R, H, E> &tile, int ti
 template <bool FULL, typename R, int H, int E>
 __device__ __forceinline__ void tile_store(const RowTile<R, H, E> &tile, int tid,
                                            const cplx<R> *lines) {
-  constexpr int LL = lds_line_len(H);
+  constexpr int LL = row_line_len<R>(H);
   const int total = tile.rows * H;
   cplx<R> out[RowTile<R, H, E>::NREG];
 #pragma unroll
@@ -92,7 +92,7 @@ __device__ __forceinline__ void tile_store(const RowTile<R, H, E> &tile, int tid
     if (FULL || e < total) {
       int rl, k1, off;
       tile.map(e, rl, k1, off);
-      out[u] = lines[rl * LL + lpad(k1)];
+      out[u] = lines[rl * LL + lslot<cplx<R>>(k1)];
     }
   }
 #pragma unroll
@@ -118,14 +118,14 @@ __device__ __forceinline__ void row_c2r(cplx<R> (&v)[E], int t, cplx<R> *line,
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int k = t + P * j;
-    C xk = line[lpad(k)];
-    C xc = cconj(line[lpad((H - k) & (H - 1))]);
+    C xk = line[lslot<cplx<R>>(k)];
+    C xc = cconj(line[lslot<cplx<R>>((H - k) & (H - 1))]);
     C e = cadd(xk, xc);
     C o = cmulc(csub(xk, xc), twl[k]);
     v[j] = cmake<C>(e.x - o.y, e.y + o.x);
     if (k == 0) v[j] = cmake<C>(xk.x + xk.y, xk.x - xk.y);
   }
-  team_fft<H, true>(v, t, line, tws, true);
+  team_fft<H, true, true>(v, t, line, tws, true);
 }
 
 // Forward real FFT of this team's row (v[j] = (x[2k], x[2k+1]), k = t + P j)
@@ -138,17 +138,17 @@ __device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[E], int t, int tid,
                                               const RowTile<R, H, E> &tile) {
   using C = cplx<R>;
   constexpr int P = H / E;
-  team_fft<H, false>(v, t, line, tws, true);
+  team_fft<H, false, true>(v, t, line, tws, true);
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < E; ++j) line[lpad(t + P * j)] = v[j];
+  for (int j = 0; j < E; ++j) line[lslot<cplx<R>>(t + P * j)] = v[j];
   __syncthreads();
   C x[E];
 #pragma unroll
   for (int j = 0; j < E; ++j) {
     const int k = t + P * j;
-    C zk = line[lpad(k)];
-    C zc = cconj(line[lpad((H - k) & (H - 1))]);
+    C zk = line[lslot<cplx<R>>(k)];
+    C zc = cconj(line[lslot<cplx<R>>((H - k) & (H - 1))]);
     C e = cadd(zk, zc);
     C d = csub(zk, zc);
     C o = cmake<C>(d.y, -d.x);  // d / i
@@ -158,7 +158,7 @@ __device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[E], int t, int tid,
   }
   __syncthreads();
 #pragma unroll
-  for (int j = 0; j < E; ++j) line[lpad(t + P * j)] = x[j];
+  for (int j = 0; j < E; ++j) line[lslot<cplx<R>>(t + P * j)] = x[j];
   __syncthreads();
   tile_store<FULL>(tile, tid, lines);
 }
@@ -185,7 +185,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
                                          const int bid) {
   using C = cplx<R>;
   using Tile = RowTile<R, H, E>;
-  constexpr int P = H / E, RPW = row_rpw(H), LL = lds_line_len(H), NT = row_threads(H, E);
+  constexpr int P = H / E, RPW = row_rpw(H), LL = row_line_len<R>(H), NT = row_threads(H, E);
   constexpr int TWLOG = ilog2c(2 * H);
   constexpr bool STG = row_staged<R>(H, MODE);
   constexpr int NTW = (H + NT - 1) / NT;
