@@ -271,11 +271,29 @@ def run_fwd_bwd(pk, torch, dev, steps, warmup):
         dLdS[ridx] = 2.0 * (S.view(-1)[ridx] - tgt.view(-1)[ridx])
         plan.adjoint(f, src, ck, dLdS.view(n0, n1), dLdf, ws)
 
+    st = torch.cuda.current_stream()
+    e0, e1 = _events(torch, st)
+    # the library's tuner times the forward solve; the adjoint's row pass
+    # ranks the row schedules differently, so the row schedule of this step
+    # is picked by timing the whole step (untimed, before the warm-up)
+    col_e = plan.schedule["col_e"]
+    best = None
+    for row_e in (16, 8, 4):
+        plan.set_schedule(row_e, col_e)
+        step()
+        e0.record(st)
+        for _ in range(2):
+            step()
+        e1.record(st)
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1)
+        if best is None or t < best[0]:
+            best = (t, row_e)
+    plan.set_schedule(best[1], col_e)
+
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    st = torch.cuda.current_stream()
-    e0, e1 = _events(torch, st)
     e0.record(st)
     for _ in range(steps):
         step()

@@ -55,11 +55,11 @@ template <typename R> constexpr int row_stage_tw(int H) {
 // Line length of a row pass.  The tile transposes put Q = min(RPW, RB) rows
 // in a 32-lane group (row fastest): float2 lines start 32/Q elements apart
 // modulo 32, so the Q rows of a group fall on disjoint banks.
+template <typename R> constexpr int row_tile_q(int H) {
+  return row_rpw(H) < spec_rb<R>() ? row_rpw(H) : spec_rb<R>();
+}
 template <typename R> constexpr int row_line_len(int H) {
-  return sizeof(R) != 4 ? lds_line_len(H)
-         : H + ((row_rpw(H) < spec_rb<R>() ? row_rpw(H) : spec_rb<R>()) > 1
-                    ? 32 / (row_rpw(H) < spec_rb<R>() ? row_rpw(H) : spec_rb<R>())
-                    : 0);
+  return sizeof(R) != 4 ? lds_line_len(H) : H + (row_tile_q<R>(H) > 1 ? 32 / row_tile_q<R>(H) : 0);
 }
 template <typename R> constexpr size_t row_lds_core(int H) {
   return sizeof(R) * 2 *

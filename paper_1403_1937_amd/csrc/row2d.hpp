@@ -424,6 +424,12 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   }
   __syncthreads();
 
+  // Pointwise steps that store to global memory read their operands a chunk
+  // of kOpChunk column pairs at a time, all before the chunk's stores: the
+  // compiler cannot tell the stored arrays from the operand arrays, so a read
+  // placed after a store would wait for everything before it (one memory
+  // latency per column instead of one per chunk).
+  constexpr int kOpChunk = E >= 16 ? 4 : 1;
   // operand access: staged copy or direct global read
   auto op1 = [&](int cc, const R *g) -> R { return STG ? sR[cc] : g[rowoff + cc]; };
   auto op2 = [&](int cc, const R *g) -> R { return STG ? sR[(size_t)RPW * H + cc] : g[rowoff + cc]; };
@@ -674,32 +680,49 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     const double sgnT = (a.T & 1) ? -1.0 : 1.0;
     double ps[FULLG ? 3 : 1] = {};  // S/hbar, a_0 d phi_0/d beta, a_0 d phi_0/d hbar
 #pragma unroll
-    for (int j = 0; j < E / 2; ++j) {
-      R zz[2] = {(R)0, (R)0};
+    for (int j0 = 0; j0 < E / 2; j0 += kOpChunk) {
+      // the chunk's reads first (see kOpChunk)
+      R qf[kOpChunk][2], qs[kOpChunk][2];
+      double qp[kOpChunk][2];
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int cc = 2 * (t + P * j) + e;
-        if (col_ok(cc)) {
-          const double fa = (double)a.f[rowoff + cc];
-          a.gam[rowoff + cc] = (R)((fa - ft) * (fa + ft) * inv_ft2);
-          const double ph = a.ck_phi[rowoff + cc];
-          double l = 0.0;
-          if (ph > 0.0 && isfinite(ph)) l = -a.hbar * (double)a.dLdS[rowoff + cc] / ph * lam_scale;
-          const R q = (R)l;
-          a.lam[rowoff + cc] = q;
-          zz[e] = (R)(sgnT * (double)q);
-          if constexpr (FULLG) {
-            if (ph > 0.0 && isfinite(ph)) ps[0] += (double)a.dLdS[rowoff + cc] * -log(ph);
-            if (a.T == 0) {  // phi = phi_0: a_0 = lambda
-              double db, dh;
-              dphi0(cc, db, dh);
-              ps[1] += (double)q * db;
-              ps[2] += (double)q * dh;
+      for (int jj = 0; jj < kOpChunk; ++jj)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int cc = 2 * (t + P * (j0 + jj)) + e;
+          const bool ok = col_ok(cc);
+          qf[jj][e] = ok ? a.f[rowoff + cc] : (R)1;
+          qs[jj][e] = ok ? a.dLdS[rowoff + cc] : (R)0;
+          qp[jj][e] = ok ? a.ck_phi[rowoff + cc] : 1.0;
+        }
+#pragma unroll
+      for (int jj = 0; jj < kOpChunk; ++jj) {
+        const int j = j0 + jj;
+        R zz[2] = {(R)0, (R)0};
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int cc = 2 * (t + P * j) + e;
+          if (col_ok(cc)) {
+            const double fa = (double)qf[jj][e];
+            a.gam[rowoff + cc] = (R)((fa - ft) * (fa + ft) * inv_ft2);
+            const double ph = qp[jj][e];
+            double l = 0.0;
+            if (ph > 0.0 && isfinite(ph)) l = -a.hbar * (double)qs[jj][e] / ph * lam_scale;
+            const R q = (R)l;
+            a.lam[rowoff + cc] = q;
+            zz[e] = (R)(sgnT * (double)q);
+            if constexpr (FULLG) {
+              if (ph > 0.0 && isfinite(ph)) ps[0] += (double)qs[jj][e] * -log(ph);
+              if (a.T == 0) {  // phi = phi_0: a_0 = lambda
+                double db, dh;
+                dphi0(cc, db, dh);
+                ps[1] += (double)q * db;
+                ps[2] += (double)q * dh;
+              }
             }
           }
         }
+        v[j] = cmake<C>(zz[0], zz[1]);
       }
-      v[j] = cmake<C>(zz[0], zz[1]);
     }
     if constexpr (FULLG) {
       block_sums_d(ps);
@@ -722,46 +745,64 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     double ps[FULLG ? 4 : 1] = {};
     const double sgn_prev = ((term - 1) & 1) ? -1.0 : 1.0;  // (-1)^(i-1)
     const R *mprev = a.ck_terms + (size_t)(term - 1) * N;
+    const R *p2 = term > 1 ? a.gam : a.f;  // gamma, or f at the last step
+    const bool need3 = term > 1 || FULLG;   // lambda
 #pragma unroll
-    for (int j = 0; j < E / 2; ++j) {
-      R zz[2] = {(R)0, (R)0};
-      const double bb[2] = {(double)v[j].x, (double)v[j].y};
+    for (int j0 = 0; j0 < E / 2; j0 += kOpChunk) {
+      // the chunk's reads first (see kOpChunk): phi_{i-1}, gamma or f,
+      // lambda, the dL/dgamma accumulator
+      R q1[kOpChunk][2], q2[kOpChunk][2], q3[kOpChunk][2];
+      double qd[kOpChunk][2];
 #pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const int cc = 2 * (t + P * j) + e;
-        if (col_ok(cc)) {
-          // dL/dgamma += phi_{i-1} b_i  (true scale 2^(E_{i-1} + e_lam))
-          double g = (double)op1(cc, mprev) * bb[e] * gscale;
-          if (term != a.T) g += opd(cc, a.acc);
-          if (term > 1) {
-            a.acc[rowoff + cc] = g;
-            const double ga = (double)op2(cc, a.gam);
-            zz[e] = (R)(sgn_prev * (double)op3(cc, a.lam) + ga * bb[e]);
-          } else {
-            // dL/df = dL/dgamma * 2 f / ftilde^2
-            const double fa = (double)op2(cc, a.f);
-            a.dLdf[rowoff + cc] = (R)(g * 2.0 * fa * inv_ft2);
-          }
-          if constexpr (MODE == ROW_ADJ_B) {
-            const double mp = (double)op1(cc, mprev);
-            double ga;
+      for (int jj = 0; jj < kOpChunk; ++jj)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int cc = 2 * (t + P * (j0 + jj)) + e;
+          const bool ok = col_ok(cc);
+          q1[jj][e] = ok ? op1(cc, mprev) : (R)0;
+          q2[jj][e] = ok ? op2(cc, p2) : (R)0;
+          q3[jj][e] = (ok && need3) ? op3(cc, a.lam) : (R)0;
+          qd[jj][e] = (ok && term != a.T) ? opd(cc, a.acc) : 0.0;
+        }
+#pragma unroll
+      for (int jj = 0; jj < kOpChunk; ++jj) {
+        const int j = j0 + jj;
+        R zz[2] = {(R)0, (R)0};
+        const double bb[2] = {(double)v[j].x, (double)v[j].y};
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int cc = 2 * (t + P * j) + e;
+          if (col_ok(cc)) {
+            // dL/dgamma += phi_{i-1} b_i  (true scale 2^(E_{i-1} + e_lam))
+            const double mp = (double)q1[jj][e];
+            const double g = mp * bb[e] * gscale + qd[jj][e];
+            double ga;  // gamma at this point
             if (term > 1) {
-              ga = (double)op2(cc, a.gam);
+              a.acc[rowoff + cc] = g;
+              ga = (double)q2[jj][e];
+              zz[e] = (R)(sgn_prev * (double)q3[jj][e] + ga * bb[e]);
             } else {
-              const double fa = (double)op2(cc, a.f);
+              // dL/df = dL/dgamma * 2 f / ftilde^2
+              const double fa = (double)q2[jj][e];
+              a.dLdf[rowoff + cc] = (R)(g * 2.0 * fa * inv_ft2);
               ga = (fa - ft) * (fa + ft) * inv_ft2;
-              const double a0 = (double)op3(cc, a.lam) + ga * bb[e];  // a_0 = lambda + gamma b_1
-              double db, dh;
-              dphi0(cc, db, dh);
-              ps[1] += a0 * db;
-              ps[2] += a0 * dh;
-              ps[3] += g * fa * fa;
             }
-            ps[0] += (double)(e ? vc[j].y : vc[j].x) * ga * mp;
+            if constexpr (MODE == ROW_ADJ_B) {
+              if (term == 1) {
+                const double fa = (double)q2[jj][e];
+                const double a0 = (double)q3[jj][e] + ga * bb[e];  // a_0 = lambda + gamma b_1
+                double db, dh;
+                dphi0(cc, db, dh);
+                ps[1] += a0 * db;
+                ps[2] += a0 * dh;
+                ps[3] += g * fa * fa;
+              }
+              ps[0] += (double)(e ? vc[j].y : vc[j].x) * ga * mp;
+            }
           }
         }
+        v[j] = cmake<C>(zz[0], zz[1]);
       }
-      v[j] = cmake<C>(zz[0], zz[1]);
     }
     if constexpr (MODE == ROW_ADJ_B) {
       block_sums_d(ps);
