@@ -196,7 +196,26 @@ __device__ inline void reduce_forcing(const double *__restrict__ red, int ft_mod
   __shared__ int sfl[16];
   double lo = __builtin_huge_val(), hi = -__builtin_huge_val();
   int fl = 0;
-  for (int i = threadIdx.x; i < kRedBlocks; i += blockDim.x) {
+  // the partials of the first kIt rounds are all read before any is used
+  // (a loop that folds as it reads waits once per round); the tail loop
+  // serves work-groups of fewer than kRedBlocks / kIt threads
+  constexpr int kIt = 4;
+  double rl[kIt], rh[kIt], rf[kIt];
+#pragma unroll
+  for (int u = 0; u < kIt; ++u) {
+    const int i = (int)threadIdx.x + u * (int)blockDim.x;
+    const int k = i < kRedBlocks ? i : 0;
+    rl[u] = red[3 * k];
+    rh[u] = red[3 * k + 1];
+    rf[u] = i < kRedBlocks ? red[3 * k + 2] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < kIt; ++u) {
+    lo = rl[u] < lo ? rl[u] : lo;
+    hi = rh[u] > hi ? rh[u] : hi;
+    fl |= (int)rf[u];
+  }
+  for (int i = threadIdx.x + kIt * blockDim.x; i < kRedBlocks; i += blockDim.x) {
     lo = red[3 * i] < lo ? red[3 * i] : lo;
     hi = red[3 * i + 1] > hi ? red[3 * i + 1] : hi;
     fl |= (int)red[3 * i + 2];

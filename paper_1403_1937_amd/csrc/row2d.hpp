@@ -307,14 +307,22 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
          : a.ft_mode == SWEIK_FT_FMAX ? hi : a.ftilde_given;
     beta = ft * a.h / a.hbar;
     inv_ft2 = 1.0 / (ft * ft);
+    // the first work-group checks the sources, one per thread (a loop in one
+    // thread made every work-group wait for n_src dependent reads)
+    __shared__ int s_badsrc;
+    if (tid == 0) s_badsrc = 0;
+    __syncthreads();
+    if (bid == 0)
+      for (int k = tid; k < a.n_src; k += NT) {
+        const int y0 = a.src[2 * k], y1 = a.src[2 * k + 1];
+        if (y0 < 0 || y0 >= a.n0 || y1 < 0 || y1 >= a.n1) atomicOr(&s_badsrc, 1);
+      }
+    __syncthreads();
     if (tid == 0) {
       s_par[0] = kappa0_2d(beta);
       const double c0 = fmax((hi - ft) * (hi + ft), (ft - lo) * (ft + lo)) * inv_ft2;
       if (!(c0 < 1.0)) fl |= SWEIK_FLAG_C0_GE_1;
-      for (int k = 0; k < a.n_src; ++k) {
-        const int y0 = a.src[2 * k], y1 = a.src[2 * k + 1];
-        if (y0 < 0 || y0 >= a.n0 || y1 < 0 || y1 >= a.n1) fl |= SWEIK_FLAG_BAD_SOURCE;
-      }
+      if (s_badsrc) fl |= SWEIK_FLAG_BAD_SOURCE;
       if (bid == 0) {
         Params p;
         p.ftilde = ft;
@@ -350,8 +358,17 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   // exponents: forward phi_i = 2^E_i m_i; adjoint a_i = 2^e_lam (mantissa)
   int dstep = 0, Ei = 0, elam = 0;
   if (TERMLIKE) {
-    double mu = 0.0;
-    for (int i = tid; i < a.nbr; i += NT) mu = fmax(mu, a.mu[(size_t)(term - 1) * a.nbr + i]);
+    // the previous pass's per-work-group maxima: the first four rounds are
+    // read before any is folded (one wait instead of one per round)
+    const double *mp = a.mu + (size_t)(term - 1) * a.nbr;
+    double mr[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int i = tid + u * NT;
+      mr[u] = i < a.nbr ? mp[i] : 0.0;
+    }
+    double mu = fmax(fmax(mr[0], mr[1]), fmax(mr[2], mr[3]));
+    for (int i = tid + 4 * NT; i < a.nbr; i += NT) mu = fmax(mu, mp[i]);
     mu = block_max(mu);
     dstep = exp_step(mu);
     Ei = a.expo[term - 1] + dstep;
