@@ -26,7 +26,7 @@ namespace sweik {
 template <typename R, int MODE, int M0, int E, bool FULL>
 __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned char *smem_raw) {
   using C = cplx<R>;
-  constexpr int P = M0 / E, CPW = col_cpw(M0), RB = spec_rb<R>(), LL = lds_line_len(M0);
+  constexpr int P = M0 / E, CPW = col_cpw(M0), RB = spec_rb<R>(), LL = col_line_len<R>(M0);
   constexpr int NT = team_threads(E);
   constexpr int H0 = M0 / 2;
   static_assert(P % RB == 0, "column team must cover whole row blocks");

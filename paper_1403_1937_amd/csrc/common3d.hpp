@@ -38,12 +38,19 @@ enum C3Mode { C3_YF = 0, C3_Z = 1, C3_YI = 2, C3_GY = 3, C3_GZ = 4 };
 
 // x pass: one team of P = H2/16 threads per line, 256 threads per group
 constexpr int x_lpw(int H) { return kThreads / (H / 16); }
+// Line length of an x pass: a 32-lane group holds 32/P lines (P = H/16
+// threads per line); float2 lines are spread over the banks.  (The column
+// passes, whose 32-lane groups interleave 16 columns two lanes each,
+// measured twice the conflicts with spread lines and keep the padded length.)
+template <typename R> constexpr int x_line_len(int H) {
+  return sizeof(R) == 4 ? lds_line_len_spread(H, H / 16 < 32 ? 32 / (H / 16) : 1) : lds_line_len(H);
+}
 template <typename R> constexpr size_t x_lds_bytes(int H) {
   // twiddles exp(-2 pi i 2m / 4H), m < H (the odd-frequency transform's
   // even ones; it forms the odd ones from them), the FFT's stage tables and
   // one padded line per team
   return sizeof(R) * 2 *
-         ((size_t)H + (size_t)stage_tw_len(H, 16) + (size_t)x_lpw(H) * lds_line_len(H));
+         ((size_t)H + (size_t)stage_tw_len(H, 16) + (size_t)x_lpw(H) * x_line_len<R>(H));
 }
 // column passes: CPW neighbouring k2 columns per group, one team of M/16
 // threads per column, threads ordered column-fastest so that a wave reads

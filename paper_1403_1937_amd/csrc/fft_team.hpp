@@ -161,6 +161,14 @@ __host__ __device__ constexpr int lds_line_len(int L) { return L + (L >> 4) + 1;
 template <typename C> __host__ __device__ constexpr int lslot(int i) {
   return sizeof(C) == 8 ? i : lpad(i);
 }
+// Padded line length of a pass whose 32-lane groups hold G lines (teams):
+// the shortest length that holds lpad(L - 1) and starts the lines 32/G
+// float2 elements apart modulo 32 (64/G banks), so that the G lines of a
+// group fall on disjoint banks.
+__host__ __device__ constexpr int lds_line_len_spread(int L, int G) {
+  return G <= 1 ? lds_line_len(L)
+                : (L + L / 16 - 1) + ((32 / G - (L + L / 16 - 1) % 32) % 32 + 32) % 32;
+}
 
 // Slot of element x of the exchange after a Stockham stage of span p and
 // radix R (float2 lines).  The stage's writes are runs of p lanes at stride

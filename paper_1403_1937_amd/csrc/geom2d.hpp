@@ -103,8 +103,14 @@ template <typename R> constexpr int col_stage_tw(int M0) {
   if (sizeof(R) == 4) n = stage_tw_len(M0, 4) > n ? stage_tw_len(M0, 4) : n;  // radix 4: float only
   return n;
 }
+// Line length of a column pass: the CPW columns of a work-group interleave
+// their teams in a 32-lane group, so float2 lines are spread over the banks.
+template <typename R> constexpr int col_line_len(int M0) {
+  return sizeof(R) == 4 ? lds_line_len_spread(M0, col_cpw(M0) < 32 ? col_cpw(M0) : 32)
+                        : lds_line_len(M0);
+}
 template <typename R> constexpr size_t col_lds_bytes(int M0) {
-  return sizeof(R) * 2 * ((size_t)col_stage_tw<R>(M0) + (size_t)col_cpw(M0) * lds_line_len(M0));
+  return sizeof(R) * 2 * ((size_t)col_stage_tw<R>(M0) + (size_t)col_cpw(M0) * col_line_len<R>(M0));
 }
 constexpr size_t kColLdsStatic = 512;  // static shared memory of a column pass
 template <typename R> constexpr bool col_fits(int M0) {

@@ -71,7 +71,7 @@ template <typename R, int MODE, int H, bool FULL>
 __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned char *smem_raw,
                                        const int bid) {
   using C = cplx<R>;
-  constexpr int P = H / 16, LPW = x_lpw(H), LL = lds_line_len(H);
+  constexpr int P = H / 16, LPW = x_lpw(H), LL = x_line_len<R>(H);
   constexpr int TWLOG = ilog2c(4 * H);
   constexpr int NTW = (H + kThreads - 1) / kThreads;
   C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i 2m / 4H), m < H
