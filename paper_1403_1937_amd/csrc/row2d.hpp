@@ -530,6 +530,22 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     R mlr = (R)0;
     const int slot = TERMLIKE ? term : 0;
     R *tout = a.terms + (size_t)slot * N + rowoff;  // this term's mantissas
+    // unstaged operand (f for phi_0, else gamma) of this thread's columns,
+    // read before the loop's stores (see kOpChunk)
+    constexpr bool PRE = !STG && (MODE == ROW_PHI0 || MODE == ROW_TERM);
+    R opre[PRE ? E : 1];
+    if constexpr (PRE) {
+      const R *po = MODE == ROW_PHI0 ? a.f : a.gam;
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int cc = 2 * (t + P * (q >> 1)) + (q & 1);
+        opre[q] = (!last && col_ok(cc)) ? po[rowoff + cc] : (R)0;
+      }
+    }
+    auto opr = [&](int q, int cc, const R *g) -> R {
+      if constexpr (PRE) return opre[q];
+      else return op1(cc, g);
+    };
     // last term: the float64 sum of the stored terms 0..T-1 at this thread's
     // columns, in the order of the terms (as a running accumulation would)
     double ps[E];
@@ -644,17 +660,17 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
           // first pass forms it from f and keeps it for the later ones
           R g0, g1 = (R)0;
           if constexpr (MODE == ROW_PHI0) {
-            const double fa = (double)op1(c0, a.f);
+            const double fa = (double)opr(2 * j, c0, a.f);
             g0 = (R)((fa - ft) * (fa + ft) * inv_ft2);
             a.gam[rowoff + c0] = g0;
             if (ok1) {
-              const double fb = (double)op1(c0 + 1, a.f);
+              const double fb = (double)opr(2 * j + 1, c0 + 1, a.f);
               g1 = (R)((fb - ft) * (fb + ft) * inv_ft2);
               a.gam[rowoff + c0 + 1] = g1;
             }
           } else {
-            g0 = op1(c0, a.gam);
-            if (ok1) g1 = op1(c0 + 1, a.gam);
+            g0 = opr(2 * j, c0, a.gam);
+            if (ok1) g1 = opr(2 * j + 1, c0 + 1, a.gam);
           }
           z0 = g0 * m0;
           z1 = g1 * m1;
