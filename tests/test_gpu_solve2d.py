@@ -322,3 +322,33 @@ def test_phi0_routes_agree(prec):
         print(f"route {route} {prec}: max rel {worst:.3e} on {frac:.3f}", flush=True)
         assert _read_info(info)["flags"] == 0
         assert worst <= TOL[prec]
+
+
+@pytest.mark.parametrize("cfg", [2, 5], ids=["noise1024_T16_src16", "noise2048_T12_src4"])
+def test_benchmark_workloads_full_size(cfg):
+    """The 1024^2 workload the benchmark times (T = 16, 16 sources) and the
+    forward solve of the 2048^2 differentiation workload (T = 12, 4 sources),
+    at full size through a plan in the schedule the autotuner picks, against
+    the FP64 oracle over the whole grid: FP32-scaled and FP64 on their
+    resolvable sets, and no point outside the conditioning envelope."""
+    import paper_1403_1937_amd as pk
+    p = workloads.problem(cfg)
+    print(f"workload {cfg}: {p.dims} T={p.T} n_src={len(p.src)}: oracle", flush=True)
+    o = oracle.solve(p.f.astype(np.float64), p.src, p.h, p.hbar, p.T)
+    src = torch.as_tensor(np.ascontiguousarray(p.src, np.int32)).to("cuda")
+    for prec, dt in (("fp32", torch.float32), ("fp64", torch.float64)):
+        plan = pk.Plan(p.dims, p.h, p.hbar, p.T, len(p.src), prec)
+        ws = plan.workspace("cuda")
+        plan.autotune(ws)
+        f = torch.as_tensor(p.f.astype(np.float64)).to("cuda", dt)
+        S = torch.empty_like(f)
+        plan.solve(f, src, S, ws)
+        torch.cuda.synchronize()
+        Sh = S.double().cpu().numpy()
+        worst, frac, _ = report(Sh, o, p.hbar, prec)
+        nbad = envelope_violations(Sh, o, p.hbar, prec)
+        print(f"  {prec} schedule {plan.schedule}: max rel {worst:.3e} on {frac:.3f} of the grid; "
+              f"envelope violations {nbad}", flush=True)
+        assert frac > 0.4
+        assert worst <= TOL[prec]
+        assert nbad == 0
