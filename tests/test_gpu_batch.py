@@ -146,3 +146,36 @@ def test_batch_rejects_mixed_and_bad_args():
     small = torch.empty(b.workspace_bytes - 1, dtype=torch.uint8, device="cuda")
     with pytest.raises(ValueError):
         b.solve([f], [src], [S], small)
+
+
+def test_benchmark_batch_full_size_sampled():
+    """The 64-instance batch the benchmark times (edges 256..2048, T = 12,
+    FP32-scaled), solved by one graph replay at full size; one instance of
+    each edge length is checked against the FP64 oracle over its whole grid
+    (resolvable set and envelope)."""
+    import paper_1403_1937_amd as pk
+    probs = workloads.batch_problems()
+    b = pk.Batch([{"dims": q.dims, "h": q.h, "hbar": q.hbar, "T": q.T, "n_src": len(q.src)}
+                  for q in probs], "fp32")
+    fs = [torch.as_tensor(q.f).cuda() for q in probs]
+    srcs = [torch.as_tensor(q.src).cuda() for q in probs]
+    Ss = [torch.empty_like(f) for f in fs]
+    ws = torch.empty(b.workspace_bytes, dtype=torch.uint8, device="cuda")
+    print(f"batch of {len(probs)}, sum N = {sum(q.dims[0] * q.dims[1] for q in probs)}", flush=True)
+    b.solve(fs, srcs, Ss, ws, graph=True)
+    torch.cuda.synchronize()
+    seen = set()
+    for i, q in enumerate(probs):
+        if q.dims[0] in seen:
+            continue
+        seen.add(q.dims[0])
+        o = oracle.solve(q.f.astype(np.float64), q.src, q.h, q.hbar, q.T)
+        S = Ss[i].double().cpu().numpy()
+        worst, frac, _ = report(S, o, q.hbar, "fp32")
+        nbad = envelope_violations(S, o, q.hbar, "fp32")
+        print(f"  instance {i} {q.dims} hbar {q.hbar:.3f} n_src {len(q.src)}: max rel "
+              f"{worst:.3e} on {frac:.3f}; envelope violations {nbad}", flush=True)
+        assert frac > 0.05
+        assert worst <= TOL["fp32"]
+        assert nbad == 0
+    assert len(seen) >= 3
