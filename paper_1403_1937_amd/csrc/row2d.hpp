@@ -319,7 +319,9 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
       }
     __syncthreads();
     if (tid == 0) {
-      s_par[0] = kappa0_2d(beta);
+      // the origin value (one float64 Bessel evaluation in one thread) is
+      // used only by the tile of row 0
+      s_par[0] = bid == 0 ? kappa0_2d(beta) : 0.0;
       const double c0 = fmax((hi - ft) * (hi + ft), (ft - lo) * (ft + lo)) * inv_ft2;
       if (!(c0 < 1.0)) fl |= SWEIK_FLAG_C0_GE_1;
       if (s_badsrc) fl |= SWEIK_FLAG_BAD_SOURCE;

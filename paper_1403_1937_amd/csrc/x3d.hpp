@@ -152,7 +152,8 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     beta = ft * a.h / a.hbar;
     inv_ft2 = 1.0 / (ft * ft);
     if (tid == 0) {
-      s_par[0] = kappa0_3d(beta);
+      // the origin value is used only by the group of line 0
+      s_par[0] = bid == 0 ? kappa0_3d(beta) : 0.0;
       if (bid == 0) {
         const double c0 = fmax((hi - ft) * (hi + ft), (ft - lo) * (ft + lo)) * inv_ft2;
         if (!(c0 < 1.0)) fl |= SWEIK_FLAG_C0_GE_1;
