@@ -58,8 +58,14 @@ template <typename R> constexpr int row_stage_tw(int H) {
 template <typename R> constexpr int row_tile_q(int H) {
   return row_rpw(H) < spec_rb<R>() ? row_rpw(H) : spec_rb<R>();
 }
+// double2 lines keep the padded layout; with the two rows of a block in a
+// tile (16-byte accesses) they start 8 elements apart modulo 16, which the
+// bank probe measured conflict-free for that interleave.
 template <typename R> constexpr int row_line_len(int H) {
-  return sizeof(R) != 4 ? lds_line_len(H) : H + (row_tile_q<R>(H) > 1 ? 32 / row_tile_q<R>(H) : 0);
+  return sizeof(R) != 4
+             ? (row_tile_q<R>(H) > 1 ? (H + H / 16 - 1) + ((8 - (H + H / 16 - 1) % 16) % 16 + 16) % 16
+                                     : lds_line_len(H))
+             : H + (row_tile_q<R>(H) > 1 ? 32 / row_tile_q<R>(H) : 0);
 }
 template <typename R> constexpr size_t row_lds_core(int H) {
   return sizeof(R) * 2 *
