@@ -110,10 +110,12 @@ template <typename R> constexpr int col_stage_tw(int M0) {
   return n;
 }
 // Line length of a column pass: the CPW columns of a work-group interleave
-// their teams in a 32-lane group, so float2 lines are spread over the banks.
+// their teams in a 32-lane group, so float2 lines are spread over the banks;
+// double2 lines of two columns start 8 elements apart modulo 16.
 template <typename R> constexpr int col_line_len(int M0) {
   return sizeof(R) == 4 ? lds_line_len_spread(M0, col_cpw(M0) < 32 ? col_cpw(M0) : 32)
-                        : lds_line_len(M0);
+         : col_cpw(M0) == 2 ? (M0 + M0 / 16 - 1) + ((8 - (M0 + M0 / 16 - 1) % 16) % 16 + 16) % 16
+                            : lds_line_len(M0);
 }
 template <typename R> constexpr size_t col_lds_bytes(int M0) {
   return sizeof(R) * 2 * ((size_t)col_stage_tw<R>(M0) + (size_t)col_cpw(M0) * col_line_len<R>(M0));
