@@ -196,6 +196,7 @@ sweik_status plan2d(sweik_plan_s *pl) {
   L.g = take((size_t)esz * (g.ldk + 1) * g.ldg);
   L.g0 = take((size_t)esz * (g.ldk + 1) * g.ldg);  // spectrum of exp(-beta |m|) (phi_0 by FFT)
   L.spec = take((size_t)csz * g.nb * g.ldk * g.RB);
+  L.spec0 = take((size_t)csz * g.nb * g.ldk * g.RB);  // kernel-table rows of the paired pass
   L.acc = take(sizeof(double) * N);
   L.terms = take((size_t)esz * N * (size_t)p.T);
   L.lam = take((size_t)esz * N);
@@ -239,6 +240,7 @@ Args2<R> make_args2(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.ft_mode = p.ft_mode;
   a.table = 0;
   a.phi0_fft = 0;
+  a.own_par = 0;
   a.ftilde_given = p.ftilde;
   a.h = p.h;
   a.hbar = p.hbar;
@@ -315,8 +317,19 @@ sweik_status enqueue2d(const sweik_plan_s *pl, const void *f, const int32_t *src
   };
   const dim3 grow(g.nbr), gcol(g.ncw);
   launch(SWEIK_KC_PREP, [&] { return launch_prep<R>((const R *)f, N, a.red, (cplx<R> *)a.tw, g.lmax, st); });
-  launch(SWEIK_KC_GHAT_ROW, [&] { return launch_row2<R>(ROW_GHAT, g.H1, g.erow, grow, st, a, 0); });
-  launch(SWEIK_KC_GHAT_COL, [&] { return launch_col2<R>(COL_GHAT, g.M0, g.ecol, gcol, st, a); });
+  // the kernel-table and phi_0 row passes in one launch where two of its
+  // work-groups fit a CU (the timed variant keeps them apart, one class each)
+  const bool paired = tm == nullptr && !g.phi0_fft && pl->p.T > 0 && row_init_pairs<R>(g.H1);
+  if (paired) {
+    Args2<R> ag = a, ap = a;
+    ag.spec = (cplx<R> *)((char *)ws + pl->ws.spec0);
+    ap.own_par = 1;
+    launch(SWEIK_KC_GHAT_ROW, [&] { return launch_row2_init<R>(g.H1, g.erow, g.nbr, st, ag, ap); });
+    launch(SWEIK_KC_GHAT_COL, [&] { return launch_col2<R>(COL_GHAT, g.M0, g.ecol, gcol, st, ag); });
+  } else {
+    launch(SWEIK_KC_GHAT_ROW, [&] { return launch_row2<R>(ROW_GHAT, g.H1, g.erow, grow, st, a, 0); });
+    launch(SWEIK_KC_GHAT_COL, [&] { return launch_col2<R>(COL_GHAT, g.M0, g.ecol, gcol, st, a); });
+  }
   if (g.phi0_fft) {
     // Table 1 steps 1-5: spectrum of exp(-beta |m|), transform of the source
     // grid (weights exp(-s_k/hbar)), product, inverse in the phi_0 pass
@@ -335,7 +348,8 @@ sweik_status enqueue2d(const sweik_plan_s *pl, const void *f, const int32_t *src
     launch(SWEIK_KC_PHI0_FFT, [&] { return launch_col2<R>(COL_CONV, g.M0, g.ecol, gcol, st, a0); });
     a.phi0_fft = 1;
   }
-  launch(SWEIK_KC_PHI0_ROW, [&] { return launch_row2<R>(ROW_PHI0, g.H1, g.erow, grow, st, a, 0); });
+  if (!paired)
+    launch(SWEIK_KC_PHI0_ROW, [&] { return launch_row2<R>(ROW_PHI0, g.H1, g.erow, grow, st, a, 0); });
   for (int i = 1; i <= pl->p.T; ++i) {
     launch(SWEIK_KC_CONV_COL, [&] { return launch_col2<R>(COL_CONV, g.M0, g.ecol, gcol, st, a); });
     const bool lastp = i == pl->p.T;

@@ -60,6 +60,7 @@ template <typename R> struct Args2 {
   int T, n_src, ft_mode;
   int table;     // kernel table of the ROW_GHAT pass: 0 kappa, 1 exp(-beta |m|)
   int phi0_fft;  // phi_0 from the transform of the source grid (in the spectrum)
+  int own_par;   // ROW_PHI0 forms the reference forcing itself (paired with ROW_GHAT)
   double ftilde_given, h, hbar;
   // data
   const R *f;

@@ -101,6 +101,16 @@ template <typename R> constexpr size_t row_lds_bytes(int H, int mode) {
 template <typename R> constexpr bool row_fits(int H, int mode) {
   return row_lds_bytes<R>(H, mode) + row_lds_static(mode) <= kLdsDevice;
 }
+// the paired kernel-table + phi_0 pass (both passes' static shared memory,
+// the larger dynamic size) is used where two of its work-groups fit a CU
+template <typename R> constexpr size_t row_init_lds_bytes(int H) {
+  return row_lds_bytes<R>(H, ROW_GHAT) > row_lds_bytes<R>(H, ROW_PHI0) ? row_lds_bytes<R>(H, ROW_GHAT)
+                                                                       : row_lds_bytes<R>(H, ROW_PHI0);
+}
+template <typename R> constexpr bool row_init_pairs(int H) {
+  return row_init_lds_bytes<R>(H) + row_lds_static(ROW_GHAT) + row_lds_static(ROW_PHI0) <=
+         kLdsDevice / 2;
+}
 // Column pass LDS: the stage twiddle tables of the length-M0 FFT (room for
 // any schedule) and one padded line per column.
 template <typename R> constexpr int col_stage_tw(int M0) {

@@ -79,6 +79,31 @@ template <typename R, int E, int MODE> struct RowLaunch {
   }
 };
 
+template <typename R, int E> struct RowInitLaunch {
+  template <int H>
+  static hipError_t one(hipStream_t st, const Args2<R> &ag, const Args2<R> &ap, int nbr) {
+    if constexpr (!row_init_pairs<R>(H) || H < E) {  // not planned
+      return hipErrorInvalidValue;
+    } else {
+      constexpr size_t lds = row_init_lds_bytes<R>(H);
+      static const hipError_t attr = set_lds(k_row2_init<R, H, E>, lds);
+      if (attr != hipSuccess) return attr;
+      hipLaunchKernelGGL((k_row2_init<R, H, E>), dim3(2 * nbr), dim3(row_threads(H, E)), lds, st,
+                         ag, ap, nbr);
+      return hipGetLastError();
+    }
+  }
+  static hipError_t run(int H, hipStream_t st, const Args2<R> &ag, const Args2<R> &ap, int nbr) {
+    SWEIK_ROW_LENGTHS(one, st, ag, ap, nbr)
+  }
+};
+
+template <typename R, int E>
+hipError_t launch_row2_init_e(int H, int nbr, hipStream_t st, const Args2<R> &ag,
+                              const Args2<R> &ap) {
+  return RowInitLaunch<R, E>::run(H, st, ag, ap, nbr);
+}
+
 template <typename R, int E>
 hipError_t launch_row2_e(int mode, int H, dim3 grid, hipStream_t st, const Args2<R> &a, int term) {
   switch (mode) {
@@ -204,6 +229,8 @@ template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream
 
 #define SWEIK_INSTANTIATE_2D_ROWS(R, E)                                                     \
   template hipError_t launch_row2_e<R, E>(int, int, dim3, hipStream_t, const Args2<R> &, int); \
+  template hipError_t launch_row2_init_e<R, E>(int, int, hipStream_t, const Args2<R> &,      \
+                                               const Args2<R> &);                            \
   template hipError_t launch_row2_batch_e<R, E>(int, int, int, hipStream_t,                 \
                                                 const BatchItem<R> *, int, int);
 

@@ -15,6 +15,9 @@ hipError_t launch_row2_e(int mode, int H, dim3 grid, hipStream_t st, const Args2
 template <typename R, int E>
 hipError_t launch_col2_e(int mode, int M0, dim3 grid, hipStream_t st, const Args2<R> &a);
 template <typename R, int E>
+hipError_t launch_row2_init_e(int H, int nbr, hipStream_t st, const Args2<R> &ag,
+                              const Args2<R> &ap);
+template <typename R, int E>
 hipError_t launch_row2_batch_e(int mode, int H, int nblocks, hipStream_t st,
                                const BatchItem<R> *items, int nitems, int term);
 template <typename R, int E>
@@ -52,6 +55,9 @@ template <typename R> struct RadixFour {
   static hipError_t row_batch(int, int, int, hipStream_t, const BatchItem<R> *, int, int) {
     return hipErrorInvalidValue;
   }
+  static hipError_t row_init(int, int, hipStream_t, const Args2<R> &, const Args2<R> &) {
+    return hipErrorInvalidValue;
+  }
   static hipError_t col_batch(int, int, int, hipStream_t, const BatchItem<R> *, int) {
     return hipErrorInvalidValue;
   }
@@ -67,6 +73,10 @@ template <> struct RadixFour<float> {
                               const BatchItem<float> *items, int n, int term) {
     return launch_row2_batch_e<float, 4>(mode, H, nb, st, items, n, term);
   }
+  static hipError_t row_init(int H, int nbr, hipStream_t st, const Args2<float> &ag,
+                             const Args2<float> &ap) {
+    return launch_row2_init_e<float, 4>(H, nbr, st, ag, ap);
+  }
   static hipError_t col_batch(int mode, int M0, int nb, hipStream_t st,
                               const BatchItem<float> *items, int n) {
     return launch_col2_batch_e<float, 4>(mode, M0, nb, st, items, n);
@@ -79,6 +89,15 @@ inline hipError_t launch_row2(int mode, int H, int E, dim3 grid, hipStream_t st,
   return E == 16  ? launch_row2_e<R, 16>(mode, H, grid, st, a, term)
          : E == 8 ? launch_row2_e<R, 8>(mode, H, grid, st, a, term)
          : E == 4 ? RadixFour<R>::row(mode, H, grid, st, a, term)
+                  : hipErrorInvalidValue;
+}
+// the paired kernel-table + phi_0 row pass (2 nbr work-groups)
+template <typename R>
+inline hipError_t launch_row2_init(int H, int E, int nbr, hipStream_t st, const Args2<R> &ag,
+                                   const Args2<R> &ap) {
+  return E == 16  ? launch_row2_init_e<R, 16>(H, nbr, st, ag, ap)
+         : E == 8 ? launch_row2_init_e<R, 8>(H, nbr, st, ag, ap)
+         : E == 4 ? RadixFour<R>::row_init(H, nbr, st, ag, ap)
                   : hipErrorInvalidValue;
 }
 template <typename R>

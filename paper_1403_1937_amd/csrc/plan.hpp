@@ -32,7 +32,7 @@ struct Geo3 {
 };
 
 struct Layout {      // byte offsets into the workspace / checkpoint
-  size_t par, red, expo, mu, mu_red, tw, g, g0, spec, s2, acc, terms, lam, gam, total;
+  size_t par, red, expo, mu, mu_red, tw, g, g0, spec, spec0, s2, acc, terms, lam, gam, total;
   size_t ck_expo, ck_par, ck_g, ck_phi, ck_terms, ck_total;
   // full gradient: after `total`, a second spectrum, the per-work-group
   // partial sums and the argmin / argmax partials (the kernel table's

@@ -351,6 +351,16 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
       }
     }
     __syncthreads();
+  } else if (MODE == ROW_PHI0 && a.own_par) {
+    // running beside the kernel-table pass: the same reduction and formulas
+    // (bit-identical scalars), nothing published
+    double lo, hi;
+    int fl;
+    reduce_forcing(a.red, a.ft_mode, a.ftilde_given, &lo, &hi, &fl);
+    ft = a.ft_mode == SWEIK_FT_NU ? sqrt(0.5 * (lo * lo + hi * hi))
+         : a.ft_mode == SWEIK_FT_FMAX ? hi : a.ftilde_given;
+    beta = ft * a.h / a.hbar;
+    inv_ft2 = 1.0 / (ft * ft);
   } else {
     beta = a.par->beta;
     inv_ft2 = a.par->inv_ft2;
@@ -887,6 +897,20 @@ template <typename R, int MODE, int H, int E>
 __global__ void __launch_bounds__(row_threads(H, E)) k_row2(Args2<R> a, int term) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   row_block<R, MODE, H, E>(a, term, smem_raw, row_tile_id<R, H>(blockIdx.x, gridDim.x));
+}
+
+// The kernel-table row pass (work-groups [0, nbr), into ag's spectrum) and
+// the phi_0 row pass (work-groups [nbr, 2 nbr), into ap's) in one launch:
+// they depend only on the reduction of f, and side by side their load and
+// compute phases overlap on each CU.  ap.own_par is set.
+template <typename R, int H, int E>
+__global__ void __launch_bounds__(row_threads(H, E)) k_row2_init(Args2<R> ag, Args2<R> ap, int nbr) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int b = blockIdx.x;
+  if (b < nbr)
+    row_block<R, ROW_GHAT, H, E>(ag, 0, smem_raw, row_tile_id<R, H>(b, nbr));
+  else
+    row_block<R, ROW_PHI0, H, E>(ap, 0, smem_raw, row_tile_id<R, H>(b - nbr, nbr));
 }
 
 // Uneven batch: one launch over the row work-groups of every instance of a
