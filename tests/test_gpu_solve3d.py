@@ -3,10 +3,14 @@
 The 3D path uses an odd-frequency real transform along the last axis and
 full transforms along the other two; the oracle uses its own complex
 radix-2 FFT over the whole padded box.  Tolerances are claimed on the
-resolvable sets of tests/common.py.  At the full 256^3 size the oracle is
-too slow, so there the checks are properties that hold at any size: the
-constant-forcing closed form and agreement of the FP32-scaled path with the
-FP64 path on the resolvable set.
+resolvable sets of tests/common.py.
+
+Every compiled line length is compared element by element with the oracle:
+thin grids pad one or two axes to 512 or 1024 points (the x pass with 256
+or 512 odd-frequency bins, the axis-1 and axis-0 column passes of length
+512 and 1024) while the oracle's padded box stays small, and the 256^3
+blob workload itself (the benchmark's launch configuration, T = 16) is
+solved by the oracle at full size.
 """
 import numpy as np
 import pytest
@@ -26,6 +30,18 @@ def _lib():
         pytest.skip("no GPU")
 
 
+def _supported(dims, h, hbar, T, n_src, prec):
+    """The planner's verdict (host only): False when it rejects the sizes."""
+    import paper_1403_1937_amd as pk
+    try:
+        pk.Plan(dims, h, hbar, T, n_src, prec)
+    except ValueError as e:
+        if "unsupported" in str(e):
+            return False
+        raise
+    return True
+
+
 def _run(f32, src, h, hbar, T, prec, ft_mode="nu", ftilde=None):
     import paper_1403_1937_amd as pk
     dt = torch.float32 if prec == "fp32" else torch.float64
@@ -43,6 +59,13 @@ CASES = [
     ("full32", (32, 32, 32), 1 / 32, 0.1, 8, 2, 24),
     ("mixed16x48x64", (16, 48, 64), 1 / 64, 0.06, 6, 4, 25),
     ("rect40x33x65", (40, 33, 65), 1 / 65, 0.1, 5, 2, 26),
+    # thin grids whose padded lengths reach the benchmark's 512 and the
+    # largest supported 1024 along one or two axes
+    ("thin130x6x130", (130, 6, 130), 1 / 130, 0.1, 4, 2, 41),
+    ("thin6x130x6", (6, 130, 6), 1 / 130, 0.1, 4, 2, 42),
+    ("thin300x5x5", (300, 5, 5), 1 / 300, 0.1, 4, 2, 43),
+    ("thin5x300x5", (5, 300, 5), 1 / 300, 0.1, 4, 2, 44),
+    ("thin5x5x300", (5, 5, 300), 1 / 300, 0.1, 4, 2, 45),
 ]
 
 
@@ -50,6 +73,8 @@ CASES = [
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_forward_parity_3d(case, prec):
     name, dims, h, hbar, T, n_src, seed = case
+    if not _supported(dims, h, hbar, T, n_src, prec):
+        pytest.skip(f"{dims} {prec}: padded lengths beyond the planner's limits")
     rng = np.random.default_rng(seed)
     f = workloads.smoothed_noise(dims, 3.0, 0.5, 2.0, rng).astype(np.float32)
     src = workloads.distinct_sources(dims, n_src, rng)
@@ -98,9 +123,8 @@ def test_constant_forcing_closed_form_3d():
     assert np.max(np.abs(S - _closed_form(dims, src, 1.25, 0.05, 0.1))) < 1e-12
 
 
-def test_full_size_256_closed_form_and_fp32_vs_fp64():
-    """At 256^3 (the blob workload's size): the constant-forcing closed form
-    on a sample of points, and FP32-scaled vs FP64 on the blob forcing."""
+def test_full_size_256_closed_form():
+    """At 256^3: the constant-forcing closed form on a sample of points."""
     n = 256
     p = workloads.problem(3, n)
     f = np.full((n, n, n), 1.3, np.float32)
@@ -112,16 +136,32 @@ def test_full_size_256_closed_form_and_fp32_vs_fp64():
     ref = 1.3 * d  # one source: S = ftilde |x - y|
     got = S[idx[:, 0], idx[:, 1], idx[:, 2]]
     assert np.max(np.abs(got - ref) / np.maximum(ref, p.hbar)) < 1e-5
-    print("256^3 blobs, fp32 and fp64", flush=True)
-    S32, _ = _run(p.f, p.src, p.h, p.hbar, p.T, "fp32")
-    S64, _ = _run(p.f, p.src, p.h, p.hbar, p.T, "fp64")
-    # resolvable set of the FP32 path judged from the FP64 result
-    phi64 = np.exp(-(S64 - S64.min()) / p.hbar)
-    m = resolvable(phi64, "fp32")
-    e = rel_err(S32, S64, p.hbar)
-    print(f"  fp32 vs fp64: max rel {e[m].max():.3e} on {m.mean():.3f}", flush=True)
-    assert m.mean() > 0.1
-    assert e[m].max() <= TOL["fp32"]
+
+
+@pytest.mark.timeout(600)
+def test_blobs_workload_full_size_against_oracle():
+    """The 256^3 blob workload (h = 1/256, hbar = 0.1, centre source,
+    T = 16) in both precisions, element by element over the whole grid
+    against the FP64 oracle's full-size solve, in the plan the benchmark
+    times."""
+    p = workloads.problem(3)
+    print("256^3 blobs: oracle solve (T = 16)", flush=True)
+    o = oracle.solve(p.f.astype(np.float64), p.src, p.h, p.hbar, p.T)
+    for prec in ("fp32", "fp64"):
+        print(f"256^3 blobs: GPU {prec}", flush=True)
+        S, info = _run(p.f, p.src, p.h, p.hbar, p.T, prec)
+        assert info["flags"] == 0
+        assert abs(info["ftilde"] - o["info"]["ftilde"]) <= 1e-14 * o["info"]["ftilde"]
+        worst, frac, _ = report(S, o, p.hbar, prec)
+        nbad = envelope_violations(S, o, p.hbar, prec)
+        print(f"  max rel {worst:.3e} on {frac:.3f} of the grid; envelope violations {nbad}; "
+              f"+inf {info['n_nonpositive_phi']} (oracle {o['info']['n_nonpositive_phi']})",
+              flush=True)
+        assert frac > 0.9
+        assert worst <= TOL[prec]
+        assert nbad == 0
+        assert info["n_nonpositive_phi"] == int(np.isinf(S).sum())
+        del S
 
 
 def test_zero_terms_3d():
