@@ -220,7 +220,9 @@ def run_main(pk, torch, dev, p, precision, steps, warmup, schedule=None):
                    "alg_bytes": ab[k], "GBps": ab[k] / (avg_ms * 1e-3) / 1e9}
     total_bytes = sum(ab[k] * kern[k]["launches_per_step"] for k in kern)
     kern["schedule"] = plan.schedule
-    return ms, kern, total_bytes
+    plan.solve(f, src, S, ws)
+    torch.cuda.synchronize()
+    return ms, kern, total_bytes, S.double().cpu().numpy()
 
 
 def run_3d(pk, torch, dev, steps, warmup):
@@ -229,8 +231,9 @@ def run_3d(pk, torch, dev, steps, warmup):
     p = workloads.problem(3)
     N = int(np.prod(p.dims))
     out = {"workload": "blobs3d_256x256x256_T16_src1", "unit": "grid pts/s"}
+    results = {}
     for prec in ("fp32", "fp64"):
-        ms, kern, tb = run_main(pk, torch, dev, p, prec, steps, warmup)
+        ms, kern, tb, results[prec] = run_main(pk, torch, dev, p, prec, steps, warmup)
         kern.pop("schedule")
         dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches_per_step"])
         out[prec] = {"value": N / (ms * 1e-3), "ms_per_step": ms,
@@ -240,7 +243,7 @@ def run_3d(pk, torch, dev, steps, warmup):
                                   "frac": kern[dom]["GBps"] / HBM_PEAK_GBPS},
                      "kernels": kern}
     out["speedup_fp32_over_fp64"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
-    return out
+    return out, (p, results)
 
 
 def run_fwd_bwd(pk, torch, dev, steps, warmup):
@@ -332,7 +335,19 @@ def run_fwd_bwd(pk, torch, dev, steps, warmup):
     e1.record(st)
     torch.cuda.synchronize()
     ms_full = e0.elapsed_time(e1) / steps
-    return {"workload": f"noise2d_{n0}x{n1}_T{p.T}_src{len(p.src)}_rec{len(rec)}",
+
+    plan.solve(f, src, S, ws, ck)
+    torch.cuda.synchronize()
+    S_host = S.double().cpu().numpy()
+
+    def gradient(dLdS_host):
+        """dL/df of this plan's solve for a given dL/dS (host arrays)."""
+        plan.solve(f, src, S, ws, ck)
+        plan.adjoint(f, src, ck, torch.as_tensor(dLdS_host.astype(np.float32)).to(dev), dLdf, ws)
+        torch.cuda.synchronize()
+        return dLdf.double().cpu().numpy()
+
+    out = {"workload": f"noise2d_{n0}x{n1}_T{p.T}_src{len(p.src)}_rec{len(rec)}",
             "value": N / (ms * 1e-3), "unit": "grid pts/s", "ms_per_step": ms,
             "ms_forward_with_checkpoints": ms_fwd, "ms_adjoint": ms - ms_fwd,
             "alg_bytes": fwd_bytes + bwd_bytes,
@@ -343,6 +358,7 @@ def run_fwd_bwd(pk, torch, dev, steps, warmup):
                               "ms_adjoint_full": ms_full - ms_fwd,
                               "dLdhbar": float(grads[0].item()),
                               "note": "dL/df with the ftilde(f) subgradient, and dL/dhbar"}}
+    return out, (p, rec, f_t, S_host, gradient)
 
 
 def run_backtrack(pk, torch, dev, steps, warmup):
@@ -451,25 +467,127 @@ def run_batched(pk, torch, dev, steps, warmup):
     sizes = {}
     for q in probs:
         sizes[q.dims[0]] = sizes.get(q.dims[0], 0) + 1
-    return {"workload": f"batch64_uneven_T{T}", "instances_per_edge": sizes,
+    # one instance of each edge length (the first in the batch), for the
+    # accuracy figures
+    sample = {}
+    for j, q in enumerate(probs):
+        if q.dims[0] not in sample:
+            sample[q.dims[0]] = (j, q, Ss[j].double().cpu().numpy())
+    out = {"workload": f"batch64_uneven_T{T}", "instances_per_edge": sizes,
             "sum_grid_pts": sumN, "value": sumN / (ms * 1e-3), "unit": "grid pts/s",
             "ms_per_step": ms, "ms_per_step_eager": ms_eager, "alg_bytes": total,
             "alg_GBps": total / (ms * 1e-3) / 1e9,
             "hbm_frac": total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, "precision": "fp32-scaled",
             "execution": "one HIP graph replay per step", "schedules": sched}
+    return out, sample
 
 
-def cpu_baseline(p, budget_s=10.0):
+def run_config1(pk, torch, dev, steps, warmup):
+    """The plain method on the 64 x 64 bump workload (h = 1, hbar = 0.5,
+    one source at the centre, T = 8) in FP64: a few hundred kilobytes per
+    solve, so the figure is the latency of one solve (median of `steps`
+    event-timed solves after the warm-up)."""
+    import workloads
+    p = workloads.problem(1)
+    f = torch.as_tensor(p.f.astype(np.float64)).to(dev)
+    src = torch.as_tensor(p.src).to(dev)
+    plan = pk.Plan(p.dims, p.h, p.hbar, p.T, len(p.src), "fp64")
+    plan.check_sources(p.src)
+    ws = plan.workspace(dev)
+    S = torch.empty_like(f)
+    for _ in range(max(1, warmup)):
+        plan.solve(f, src, S, ws)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    times = []
+    for _ in range(steps):
+        e0, e1 = _events(torch, st)
+        e0.record(st)
+        plan.solve(f, src, S, ws)
+        e1.record(st)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    out = {"workload": "bumps2d_64x64_T8_src1_h1", "precision": "fp64",
+           "latency_ms_median": ms, "latency_ms_min": float(min(times)),
+           "value": p.dims[0] * p.dims[1] / (ms * 1e-3), "unit": "grid pts/s",
+           "launches_per_solve": 4 + 2 * p.T, "bound": "launch latency"}
+    return out, (p, S.double().cpu().numpy())
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ---- cpu_baseline leg ---------------------------------------------------------
+# The FP64 oracle on the host cores.  This leg is the only part of the
+# benchmark that runs the oracle: it times it (cpu_baseline) and computes the
+# reference results that the accuracy figures compare the GPU results with.
+
+# (resolvable set on which the tolerance is claimed, the wider set that the
+# conditioning law alone would suggest) per precision, in Lambda =
+# ln(max phi / phi(x)) of the oracle
+LAMBDA_SETS = {"fp32": (9.0, 12.0), "fp64": (16.0, 20.0)}
+TOLERANCE = {"fp32": 1e-4, "fp64": 1e-10}
+LAMBDA_BINS = (0.0, 4.0, 8.0, 12.0, 16.0, 20.0, 30.0, 40.0, np.inf)
+
+
+def accuracy(S, o, hbar, prec):
+    """|S - S_oracle| / max(|S_oracle|, hbar) of one GPU result: the maximum
+    on the resolvable set and on the wider set, full-grid percentiles, the
+    maximum per Lambda bin and the +inf counts."""
+    S = np.asarray(S, np.float64)
+    So, phi = o["S"], o["phi"]
+    pos = phi > 0
+    L = np.full(phi.shape, np.inf)
+    L[pos] = np.log(phi[pos].max() / phi[pos])
+    with np.errstate(invalid="ignore"):
+        rel = np.abs(S - So) / np.maximum(np.abs(So), hbar)
+    fin = np.isfinite(S) & np.isfinite(So)
+
+    def mx(m):
+        return float(np.nan_to_num(rel[m], nan=np.inf).max()) if m.any() else None
+
+    tight, wide = LAMBDA_SETS[prec]
+    bins = {}
+    for lo, hi in zip(LAMBDA_BINS[:-1], LAMBDA_BINS[1:]):
+        m = (L > lo) & (L <= hi) if lo > 0 else (L <= hi)
+        if m.any():
+            bins[f"{lo:g}-{hi:g}"] = {"max_rel": mx(m & fin) if (m & fin).any() else None,
+                                     "frac": float(m.mean()),
+                                     "n_inf_gpu": int((m & np.isinf(S)).sum())}
+    r_tight, r_wide = L <= tight, L <= wide
+    return {"tol": TOLERANCE[prec],
+            "set": f"Lambda<={tight:g}", "max_rel": mx(r_tight), "frac_set": float(r_tight.mean()),
+            "within_tol": bool(mx(r_tight) is not None and mx(r_tight) <= TOLERANCE[prec]),
+            "wide_set": f"Lambda<={wide:g}", "max_rel_wide": mx(r_wide),
+            "frac_wide": float(r_wide.mean()),
+            "p50_all": float(np.percentile(rel[fin], 50)) if fin.any() else None,
+            "p99_all": float(np.percentile(rel[fin], 99)) if fin.any() else None,
+            "max_rel_by_lambda": bins,
+            "n_inf_gpu": int(np.isinf(S).sum()), "n_nonpositive_oracle": int((~pos).sum())}
+
+
+def cpu_baseline(p, threads, budget_s=10.0):
     """The FP64 CPU oracle on the host cores: whole solves of the main
     workload, repeated until `budget_s` seconds have passed; plus one
-    single-thread solve."""
+    single-thread solve.  Also returns the oracle's result of the workload."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     n0, n1 = p.dims
     f64 = p.f.astype(np.float64)
     reps, t0 = 0, time.perf_counter()
+    first = None
     while True:
-        oracle.solve(f64, p.src, p.h, p.hbar, p.T, nthreads=threads)
+        o = oracle.solve(f64, p.src, p.h, p.hbar, p.T, nthreads=threads)
+        if first is None:
+            first = o
         reps += 1
         el = time.perf_counter() - t0
         if el >= budget_s:
@@ -478,10 +596,66 @@ def cpu_baseline(p, budget_s=10.0):
     oracle.solve(f64, p.src, p.h, p.hbar, p.T, nthreads=1)
     t1s = time.perf_counter() - t1
     return {"value": reps * n0 * n1 / el, "unit": "grid pts/s", "cores": threads,
-            "kind": "oracle",
+            "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"{reps} full {n0}x{n1} T={p.T} solves (FP64, own radix-2 FFT) in "
                       f"{el:.1f} s on {threads} threads",
-            "single_thread": {"value": n0 * n1 / t1s, "seconds_per_solve": t1s}}
+            "single_thread": {"value": n0 * n1 / t1s, "seconds_per_solve": t1s}}, first
+
+
+def reference_accuracy(gpu, o_main, threads):
+    """Accuracy of every GPU result against the FP64 oracle on the same
+    inputs.  `gpu` holds the host copies of the GPU results per section."""
+    import oracle
+    out = {"reference": "FP64 CPU oracle (own FFT) on the same inputs; rel = |S - S_oracle| / "
+                        "max(|S_oracle|, hbar); Lambda = ln(max phi / phi) of the oracle"}
+    p, S32, S64 = gpu["main"]
+    out["main"] = {"workload": f"noise2d_{p.dims[0]}x{p.dims[1]}_T{p.T}",
+                   "fp32": accuracy(S32, o_main, p.hbar, "fp32")}
+    if S64 is not None:
+        out["main"]["fp64"] = accuracy(S64, o_main, p.hbar, "fp64")
+    if "config1" in gpu:
+        p1, S1 = gpu["config1"]
+        f1 = p1.f.astype(np.float64)
+        od = oracle.solve(f1, p1.src, p1.h, p1.hbar, p1.T, method="direct", nthreads=threads)
+        of = oracle.solve(f1, p1.src, p1.h, p1.hbar, p1.T, nthreads=threads)
+        out["config1"] = {"workload": "bumps2d_64x64_T8_src1_h1",
+                          "fp64_vs_oracle_fft": accuracy(S1, of, p1.hbar, "fp64"),
+                          "fp64_vs_oracle_direct": accuracy(S1, od, p1.hbar, "fp64"),
+                          "note": "the direct sum is the ground truth where FFT noise dominates "
+                                  "(Lambda beyond ~30)"}
+    if "fwd_bwd" in gpu:
+        p5, rec, f_t, S5, gradient = gpu["fwd_bwd"]
+        f5 = p5.f.astype(np.float64)
+        o5 = oracle.solve(f5, p5.src, p5.h, p5.hbar, p5.T, nthreads=threads)
+        t5 = oracle.solve(f_t.astype(np.float64), p5.src, p5.h, p5.hbar, p5.T, nthreads=threads)
+        dLdS = np.zeros(p5.dims)
+        r0, r1 = rec[:, 0], rec[:, 1]
+        dLdS[r0, r1] = 2.0 * (o5["S"][r0, r1] - t5["S"][r0, r1])
+        g_o, _ = oracle.adjoint(f5, p5.src, p5.h, p5.hbar, p5.T, dLdS, nthreads=threads)
+        g = gradient(dLdS)
+        out["fwd_bwd"] = {"workload": f"noise2d_{p5.dims[0]}x{p5.dims[1]}_T{p5.T}",
+                          "forward_fp32": accuracy(S5, o5, p5.hbar, "fp32"),
+                          "gradient_fp32": {
+                              "normwise_rel": float(np.linalg.norm(g - g_o) / np.linalg.norm(g_o)),
+                              "tol": 1e-3,
+                              "dLdS": "2 (S - target) at 256 receivers, from the oracle's solves "
+                                      "of f and the perturbed forcing"}}
+    if "batched" in gpu:
+        res = {}
+        for n, (j, q, Sq) in sorted(gpu["batched"].items()):
+            oq = oracle.solve(q.f.astype(np.float64), q.src, q.h, q.hbar, q.T, nthreads=threads)
+            a = accuracy(Sq, oq, q.hbar, "fp32")
+            a["instance"] = j
+            a["hbar"] = q.hbar
+            a["n_src"] = int(len(q.src))
+            res[str(n)] = a
+        out["batched"] = {"sample": "the first instance of each edge length", "fp32": res}
+    if "solve3d" in gpu:
+        p3, r3 = gpu["solve3d"]
+        o3 = oracle.solve(p3.f.astype(np.float64), p3.src, p3.h, p3.hbar, p3.T, nthreads=threads)
+        out["solve3d"] = {"workload": "blobs3d_256x256x256_T16",
+                          **{k: accuracy(v, o3, p3.hbar, k) for k, v in r3.items()}}
+    return out
 
 
 # ---- counter and trace summaries --------------------------------------------
@@ -623,8 +797,9 @@ def main():
 
     if args.only:
         fn = {"fwd_bwd": run_fwd_bwd, "batched": run_batched, "solve3d": run_3d,
-              "backtrack": run_backtrack, "fd": run_fd}[args.only]
-        print(json.dumps(fn(pk, torch, dev, args.steps, args.warmup)))
+              "backtrack": run_backtrack, "fd": run_fd, "config1": run_config1}[args.only]
+        r = fn(pk, torch, dev, args.steps, args.warmup)
+        print(json.dumps(r[0] if isinstance(r, tuple) else r))
         return
 
     if args.pmc_run:
@@ -635,11 +810,13 @@ def main():
         torch.cuda.synchronize()
         del a, b
         for sched in ((8, 16), (16, 16)):  # the two row schedules the tuner picks at 1024^2
-            ms, _, _ = run_main(pk, torch, dev, p, "fp32", args.steps, args.warmup, sched)
+            ms, _, _, _ = run_main(pk, torch, dev, p, "fp32", args.steps, args.warmup, sched)
             print(f"pmc run, schedule {sched}: {ms:.3f} ms per solve", flush=True)
         return
 
-    ms, kern, total_bytes = run_main(pk, torch, dev, p, args.precision, args.steps, args.warmup)
+    ms, kern, total_bytes, S_main = run_main(pk, torch, dev, p, args.precision, args.steps,
+                                             args.warmup)
+    gpu = {}  # host copies of the GPU results, for the accuracy figures
     value = N / (ms * 1e-3)
     sched = kern.pop("schedule")
     dom = max(kern, key=lambda k: kern[k]["avg_us"] * kern[k]["launches_per_step"])
@@ -672,19 +849,25 @@ def main():
         "solve_alg_bytes": total_bytes,
         "kernels": kern,
     }
+    S64_main = None
     if not args.no_fp64 and args.precision == "fp32":
-        ms64, _, tb64 = run_main(pk, torch, dev, p, "fp64", max(5, args.steps // 2), 2)
+        ms64, _, tb64, S64_main = run_main(pk, torch, dev, p, "fp64", max(5, args.steps // 2), 2)
         out["fp64_comparator"] = {"value": N / (ms64 * 1e-3), "ms_per_step": ms64,
                                   "solve_alg_GBps": tb64 / (ms64 * 1e-3) / 1e9,
                                   "speedup_fp32_over_fp64": ms64 / ms}
+    gpu["main"] = (p, S_main, S64_main) if args.precision == "fp32" else (p, None, S_main)
     if not args.no_extra:
-        out["fwd_bwd"] = run_fwd_bwd(pk, torch, dev, max(3, args.steps // 2), 2)
-        out["batched"] = run_batched(pk, torch, dev, max(3, args.steps // 4), 1)
-        out["solve3d"] = run_3d(pk, torch, dev, max(3, args.steps // 4), 1)
+        out["config1"], gpu["config1"] = run_config1(pk, torch, dev, max(20, args.steps), 3)
+        out["fwd_bwd"], gpu["fwd_bwd"] = run_fwd_bwd(pk, torch, dev, max(3, args.steps // 2), 2)
+        out["batched"], gpu["batched"] = run_batched(pk, torch, dev, max(3, args.steps // 4), 1)
+        out["solve3d"], gpu["solve3d"] = run_3d(pk, torch, dev, max(3, args.steps // 4), 1)
         out["backtrack"] = run_backtrack(pk, torch, dev, max(3, args.steps // 4), 1)
         out["fd"] = run_fd(pk, torch, dev, 3, 1)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        out["cpu_baseline"], o_main = cpu_baseline(p, threads)
+        if args.precision == "fp32":
+            out["accuracy"] = reference_accuracy(gpu, o_main, threads)
     print(json.dumps(out))
 
 
