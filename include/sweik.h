@@ -287,22 +287,37 @@ sweik_status sweik_solve_timed(sweik_plan plan, const void *f, const int32_t *sr
 /* ---- uneven batches of independent 2D problems ------------------------ */
 typedef struct sweik_batch_s *sweik_batch;
 
-/* All problems must be 2D with the same precision and the same T. */
+/* All problems must be 2D with the same precision and the same T.  Host
+ * only: validates the problems and lays out the workspace (no HIP call). */
 sweik_status sweik_batch_create(const sweik_problem *problems, int32_t count,
                                 sweik_batch *out);
+/* Creates, on the calling thread's current device, the HIP resources the
+ * batch's solves use: one stream and one event per size class beyond the
+ * first (class chains run side by side), a capture stream, and a ring of
+ * pinned host staging buffers for the per-instance argument lists.  Call
+ * once before the first solve; the batch then runs on that device only.
+ * Returns SWEIK_EINVAL when called again from another device, SWEIK_EDEVICE
+ * when a HIP call fails.  The batch owns these until sweik_batch_destroy. */
+sweik_status sweik_batch_prepare(sweik_batch batch);
 void sweik_batch_destroy(sweik_batch batch);
 size_t sweik_batch_workspace_bytes(sweik_batch batch);
 
 /* f, src, S: HOST arrays of `count` device pointers.  infos: device array of
- * `count` sweik_info (nullable). */
+ * `count` sweik_info (nullable).  Creates no HIP resource and allocates
+ * nothing: SWEIK_EINVAL until sweik_batch_prepare has been called.  The
+ * argument lists are copied from the pinned ring; a slot is reused only
+ * after the copy issued from it four calls earlier has completed (the one
+ * host wait of this call). */
 sweik_status sweik_batch_solve(sweik_batch batch, const void *const *f,
                                const int32_t *const *src, void *const *S,
                                void *ws, size_t ws_bytes, void *stream,
                                sweik_info *infos);
 
 /* Same work, captured once into a HIP graph owned by the batch and replayed
- * on later calls with the same pointers (a call with other pointers
- * re-captures). */
+ * on later calls with the same pointers (a call with other pointers waits
+ * for the stream and re-captures).  Capturing instantiates a graph: the
+ * first call, and a call with new pointers, create one graph executable;
+ * replays create nothing.  SWEIK_EINVAL until sweik_batch_prepare. */
 sweik_status sweik_batch_solve_graph(sweik_batch batch, const void *const *f,
                                      const int32_t *const *src,
                                      void *const *S, void *ws,
@@ -351,6 +366,13 @@ int32_t sweik_autotune(sweik_plan plan, void *ws, size_t ws_bytes,
 
 const char *sweik_status_string(sweik_status s);
 int32_t sweik_abi_version(void);
+/* Number of HIP resources (streams, events, pinned host buffers, graph
+ * executables) the library has created in this process so far.  Solves,
+ * adjoints, batch solves and graph replays create none; plan and batch
+ * creation are host only; sweik_batch_prepare, the first capture of a batch
+ * graph, sweik_solve_timed and sweik_autotune do create some.  For tests
+ * and diagnostics. */
+int64_t sweik_resource_count(void);
 
 #ifdef __cplusplus
 }

@@ -84,8 +84,10 @@ def load_library():
     lib.sweik_solve_timed.argtypes = [vp, vp, vp, vp, vp, sz, vp, C.POINTER(C.c_float),
                                       C.POINTER(C.c_int32)]
     lib.sweik_batch_create.argtypes = [P, C.c_int32, C.POINTER(vp)]
+    lib.sweik_batch_prepare.argtypes = [vp]
     lib.sweik_batch_destroy.argtypes = [vp]
     lib.sweik_batch_destroy.restype = None
+    lib.sweik_resource_count.restype = C.c_int64
     lib.sweik_batch_workspace_bytes.argtypes = [vp]
     lib.sweik_batch_workspace_bytes.restype = sz
     PP = C.POINTER(vp)
@@ -458,7 +460,9 @@ def eikonal(f, src, h, hbar, T, ftilde_mode="nu", ftilde=None):
 class Batch:
     """Uneven batch of independent 2D problems (sweik_batch)."""
 
-    def __init__(self, problems: Sequence[dict], precision: str = "fp32"):
+    def __init__(self, problems: Sequence[dict], precision: str = "fp32", prepare: bool = True):
+        """prepare=False only validates and lays out the batch (host only):
+        such a batch cannot be solved."""
         lib = load_library()
         arr = (_Problem * len(problems))()
         for i, q in enumerate(problems):
@@ -474,6 +478,9 @@ class Batch:
         _check(lib.sweik_batch_create(arr, len(problems), C.byref(handle)), "sweik_batch_create")
         self._lib, self._h, self.count = lib, handle, len(problems)
         self.workspace_bytes = int(lib.sweik_batch_workspace_bytes(handle))
+        # streams, events and pinned staging on the current device, once
+        if prepare:
+            _check(lib.sweik_batch_prepare(handle), "sweik_batch_prepare")
 
     def __del__(self):
         try:
@@ -506,6 +513,11 @@ def batch_solve(fs: Sequence[torch.Tensor], srcs, hs, hbars, T: int, graph: bool
     ws = torch.empty(b.workspace_bytes, dtype=torch.uint8, device=fs[0].device)
     b.solve(fs, d_srcs, Ss, ws, graph=graph)
     return Ss
+
+
+def resource_count() -> int:
+    """HIP resources the library has created so far in this process."""
+    return int(load_library().sweik_resource_count())
 
 
 def info_struct_size() -> int:

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
@@ -21,6 +22,14 @@
 using namespace sweik;
 
 namespace {
+
+// HIP resources (streams, events, pinned host buffers, graph executables)
+// created by the library so far: solves and batch solves create none.
+std::atomic<long long> g_resources{0};
+template <typename T> T counted(T err) {
+  if (err == hipSuccess) g_resources.fetch_add(1, std::memory_order_relaxed);
+  return err;
+}
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -288,7 +297,8 @@ struct KernelTimer {
   bool ok = true;
   KernelTimer() {
     for (int i = 0; i <= kMax; ++i)
-      if (hipEventCreateWithFlags(&ev[i], hipEventDisableSystemFence) != hipSuccess) ok = false;
+      if (counted(hipEventCreateWithFlags(&ev[i], hipEventDisableSystemFence)) != hipSuccess)
+        ok = false;
   }
   ~KernelTimer() {
     for (int i = 0; i <= kMax; ++i) (void)hipEventDestroy(ev[i]);
@@ -615,8 +625,9 @@ struct sweik_batch_s {
   std::vector<size_t> inst_off;
   std::vector<sweik::BatchClass> classes;
   size_t items_bytes = 0, total = 0;
-  // created on the first solve (device of that call)
+  // created by sweik_batch_prepare (on its current device)
   bool rt = false;
+  int device = -1;
   std::vector<hipStream_t> side;
   hipEvent_t fork = nullptr;
   std::vector<hipEvent_t> join;
@@ -653,28 +664,34 @@ size_t batch_item_bytes(int prec) {
   return prec == SWEIK_F64 ? sizeof(BatchItem<double>) : sizeof(BatchItem<float>);
 }
 
+// Streams, events and pinned staging of a batch, on the current device
+// (sweik_batch_prepare): solves only use them.
 sweik_status batch_runtime(sweik_batch_s *b) {
   if (b->rt) return SWEIK_OK;
   const int nside = (int)b->classes.size() - 1;
   for (int c = 0; c < nside; ++c) {
     hipStream_t s;
-    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return SWEIK_EDEVICE;
+    if (counted(hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess)
+      return SWEIK_EDEVICE;
     b->side.push_back(s);
     hipEvent_t e;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return SWEIK_EDEVICE;
+    if (counted(hipEventCreateWithFlags(&e, hipEventDisableTiming)) != hipSuccess)
+      return SWEIK_EDEVICE;
     b->join.push_back(e);
   }
-  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess)
+  if (counted(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming)) != hipSuccess)
     return SWEIK_EDEVICE;
-  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) return SWEIK_EDEVICE;
+  if (counted(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking)) != hipSuccess)
+    return SWEIK_EDEVICE;
   for (int i = 0; i < sweik_batch_s::kRing; ++i) {
-    if (hipHostMalloc(&b->stage[i], b->items_bytes, hipHostMallocDefault) != hipSuccess)
+    if (counted(hipHostMalloc(&b->stage[i], b->items_bytes, hipHostMallocDefault)) != hipSuccess)
       return SWEIK_EDEVICE;
-    if (hipEventCreateWithFlags(&b->stage_ev[i], hipEventDisableTiming) != hipSuccess)
+    if (counted(hipEventCreateWithFlags(&b->stage_ev[i], hipEventDisableTiming)) != hipSuccess)
       return SWEIK_EDEVICE;
   }
-  if (hipHostMalloc(&b->gstage, b->items_bytes, hipHostMallocDefault) != hipSuccess)
+  if (counted(hipHostMalloc(&b->gstage, b->items_bytes, hipHostMallocDefault)) != hipSuccess)
     return SWEIK_EDEVICE;
+  if (hipGetDevice(&b->device) != hipSuccess) return SWEIK_EDEVICE;
   b->rt = true;
   return SWEIK_OK;
 }
@@ -750,7 +767,7 @@ sweik_status batch_enqueue(sweik_batch_s *b, void *host, char *ws, hipStream_t s
 sweik_status batch_args_ok(const sweik_batch_s *b, const void *const *f,
                            const int32_t *const *src, void *const *S, void *ws,
                            size_t ws_bytes) {
-  if (!b || !f || !src || !S || !ws) return SWEIK_EINVAL;
+  if (!b || !f || !src || !S || !ws || !b->rt) return SWEIK_EINVAL;
   if (ws_bytes < b->total) return SWEIK_EWORKSPACE;
   for (int i = 0; i < b->count; ++i)
     if (!f[i] || !src[i] || !S[i]) return SWEIK_EINVAL;
@@ -764,8 +781,8 @@ namespace {
 // Average milliseconds of `reps` launches of fn on st (events around all).
 template <typename F> float time_launches(hipStream_t st, int reps, F &&fn, bool *ok) {
   hipEvent_t e0, e1;
-  if (hipEventCreate(&e0) != hipSuccess) return *ok = false, 0.0f;
-  if (hipEventCreate(&e1) != hipSuccess) {
+  if (counted(hipEventCreate(&e0)) != hipSuccess) return *ok = false, 0.0f;
+  if (counted(hipEventCreate(&e1)) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return *ok = false, 0.0f;
   }
@@ -1024,6 +1041,16 @@ sweik_status sweik_batch_create(const sweik_problem *problems, int32_t count, sw
   return SWEIK_OK;
 }
 
+sweik_status sweik_batch_prepare(sweik_batch b) {
+  if (!b) return SWEIK_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SWEIK_EDEVICE;
+  if (b->rt) return dev == b->device ? SWEIK_OK : SWEIK_EINVAL;
+  return batch_runtime(b);
+}
+
+int64_t sweik_resource_count(void) { return g_resources.load(std::memory_order_relaxed); }
+
 void sweik_batch_destroy(sweik_batch batch) { delete batch; }
 
 size_t sweik_batch_workspace_bytes(sweik_batch batch) { return batch ? batch->total : 0; }
@@ -1033,7 +1060,6 @@ sweik_status sweik_batch_solve(sweik_batch b, const void *const *f, const int32_
                                sweik_info *infos) {
   sweik_status rc = batch_args_ok(b, f, src, S, ws, ws_bytes);
   if (rc != SWEIK_OK) return rc;
-  if ((rc = batch_runtime(b)) != SWEIK_OK) return rc;
   // staging slot: wait (host side) only for the copy issued kRing calls ago
   const int slot = b->ring;
   b->ring = (b->ring + 1) % sweik_batch_s::kRing;
@@ -1055,7 +1081,6 @@ sweik_status sweik_batch_solve_graph(sweik_batch b, const void *const *f,
                                      size_t ws_bytes, void *stream, sweik_info *infos) {
   sweik_status rc = batch_args_ok(b, f, src, S, ws, ws_bytes);
   if (rc != SWEIK_OK) return rc;
-  if ((rc = batch_runtime(b)) != SWEIK_OK) return rc;
   BatchKey key;
   for (int i = 0; i < b->count; ++i) {
     key.ptrs.push_back(f[i]);
@@ -1085,7 +1110,7 @@ sweik_status sweik_batch_solve_graph(sweik_batch b, const void *const *f,
       if (graph) (void)hipGraphDestroy(graph);
       return SWEIK_EDEVICE;
     }
-    const hipError_t ei = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    const hipError_t ei = counted(hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0));
     (void)hipGraphDestroy(graph);
     if (ei != hipSuccess) {
       b->exec = nullptr;

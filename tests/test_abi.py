@@ -115,15 +115,15 @@ def test_batch_create_checks_and_layout(lib):
     from paper_1403_1937_amd import Batch
     base = {"dims": (64, 64), "h": 1 / 64, "hbar": 0.1, "T": 4, "n_src": 1}
     with pytest.raises(ValueError):
-        Batch([], "fp32")
+        Batch([], "fp32", prepare=False)
     with pytest.raises(ValueError):
-        Batch([base, dict(base, T=5)], "fp32")          # T must agree
+        Batch([base, dict(base, T=5)], "fp32", prepare=False)          # T must agree
     with pytest.raises(ValueError):
-        Batch([base, dict(base, dims=(8, 8, 8))], "fp32")  # 2D only
+        Batch([base, dict(base, dims=(8, 8, 8))], "fp32", prepare=False)  # 2D only
     with pytest.raises(ValueError):
-        Batch([base, dict(base, hbar=-1.0)], "fp32")
+        Batch([base, dict(base, hbar=-1.0)], "fp32", prepare=False)
     probs = [base, dict(base, dims=(100, 76)), dict(base, dims=(7, 300)), base]
-    b = Batch(probs, "fp32")
+    b = Batch(probs, "fp32", prepare=False)
     singles = sum(_plan(dims=q["dims"], T=4).workspace_bytes for q in probs)
     # per-instance regions plus the work lists at the head
     assert singles < b.workspace_bytes < singles + 64 * 1024
@@ -183,3 +183,27 @@ def test_full_gradient_entry_checks(lib):
     rc = lib.sweik_solve_adjoint_full(p.handle, vp(16), vp(16), None, vp(16), vp(16), vp(16),
                                       None, vp(16), need - 1, None)
     assert rc == 3  # SWEIK_EWORKSPACE
+
+
+def test_batch_solve_before_prepare_is_rejected(lib):
+    # a batch that was only created (host only) has no streams or staging:
+    # its solves return SWEIK_EINVAL before any HIP call
+    from paper_1403_1937_amd import Batch
+    base = {"dims": (64, 64), "h": 1 / 64, "hbar": 0.1, "T": 4, "n_src": 1}
+    b = Batch([base, dict(base, dims=(40, 90))], "fp32", prepare=False)
+    vp = C.c_void_p
+    P = vp * 2
+    ptrs = P(vp(256), vp(512))
+    for fn in (lib.sweik_batch_solve, lib.sweik_batch_solve_graph):
+        assert fn(b._h, ptrs, ptrs, ptrs, vp(4096), b.workspace_bytes, None, None) == 1
+    assert lib.sweik_batch_prepare(None) == 1
+
+
+def test_host_only_calls_create_no_hip_resource(lib):
+    # plans, batches and argument checks make no HIP call
+    from paper_1403_1937_amd import Batch
+    n = lib.sweik_resource_count()
+    _plan()
+    Batch([{"dims": (64, 64), "h": 1 / 64, "hbar": 0.1, "T": 4, "n_src": 1}], "fp32",
+          prepare=False)
+    assert lib.sweik_resource_count() == n

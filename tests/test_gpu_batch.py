@@ -179,3 +179,63 @@ def test_benchmark_batch_full_size_sampled():
         assert worst <= TOL["fp32"]
         assert nbad == 0
     assert len(seen) >= 3
+
+
+def test_batch_solves_create_nothing():
+    """After sweik_batch_prepare, eager batch solves create no HIP resource
+    and allocate no device memory; the graph variant creates one graph
+    executable on its first call and nothing on replays."""
+    import paper_1403_1937_amd as pk
+    probs, fs, srcs, _ = _make("fp32", seed=12)
+    b = pk.Batch(probs, "fp32")  # prepares
+    Ss = [torch.empty_like(f) for f in fs]
+    ws = torch.empty(b.workspace_bytes, dtype=torch.uint8, device="cuda")
+    b.solve(fs, srcs, Ss, ws)
+    torch.cuda.synchronize()
+    ref = [S.clone() for S in Ss]
+    free0, _ = torch.cuda.mem_get_info()
+    n0 = pk._native.resource_count()
+    for _ in range(6):  # more calls than the staging ring has slots
+        b.solve(fs, srcs, Ss, ws)
+    torch.cuda.synchronize()
+    assert pk._native.resource_count() == n0
+    assert torch.cuda.mem_get_info()[0] == free0
+    assert all(torch.equal(S, R) for S, R in zip(Ss, ref))
+    b.solve(fs, srcs, Ss, ws, graph=True)
+    torch.cuda.synchronize()
+    assert pk._native.resource_count() == n0 + 1
+    n1 = pk._native.resource_count()
+    for _ in range(3):
+        b.solve(fs, srcs, Ss, ws, graph=True)
+    torch.cuda.synchronize()
+    assert pk._native.resource_count() == n1
+    assert all(torch.equal(S, R) for S, R in zip(Ss, ref))
+
+
+def test_batch_solve_needs_prepare():
+    """A batch that was not prepared is rejected before anything is
+    enqueued."""
+    import ctypes as C
+    import paper_1403_1937_amd as pk
+    probs, fs, srcs, _ = _make("fp32", seed=13)
+    lib = pk.load_library()
+    arr = (pk._native._Problem * len(probs))()
+    for i, q in enumerate(probs):
+        arr[i].ndim = 2
+        arr[i].dims = (C.c_int64 * 3)(q["dims"][0], q["dims"][1], 1)
+        arr[i].h, arr[i].hbar, arr[i].T, arr[i].n_src = q["h"], q["hbar"], q["T"], q["n_src"]
+        arr[i].prec, arr[i].ft_mode = 0, 0
+    h = C.c_void_p()
+    assert lib.sweik_batch_create(arr, len(probs), C.byref(h)) == 0
+    try:
+        Ss = [torch.empty_like(f) for f in fs]
+        ws = torch.empty(int(lib.sweik_batch_workspace_bytes(h)), dtype=torch.uint8,
+                         device="cuda")
+        P = C.c_void_p * len(fs)
+        rc = lib.sweik_batch_solve(h, P(*[f.data_ptr() for f in fs]),
+                                   P(*[s.data_ptr() for s in srcs]),
+                                   P(*[S.data_ptr() for S in Ss]), ws.data_ptr(), ws.numel(),
+                                   None, None)
+        assert rc == 1  # SWEIK_EINVAL
+    finally:
+        lib.sweik_batch_destroy(h)
