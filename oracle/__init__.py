@@ -80,6 +80,8 @@ def _load():
                               dp, dp]
     lib.orc_adjoint.argtypes = [C.POINTER(_Problem), dp, C.c_int32, ip, dp, dp,
                                 dp]
+    lib.orc_solve_logdirect.argtypes = [C.POINTER(_Problem), dp, C.c_int32, ip, dp, dp, dp]
+    lib.orc_log_kappa.argtypes = [C.c_int, lp, C.c_double, dp]
     _lib = lib
     return lib
 
@@ -218,6 +220,32 @@ def solve(f: np.ndarray, src: np.ndarray, h: float, hbar: float, T: int,
     out = {"S": S, "phi": phi, "info": _info(info)}
     if terms is not None:
         out["terms"] = terms
+    return out
+
+
+def solve_logdirect(f: np.ndarray, src: np.ndarray, h: float, hbar: float, T: int,
+                    nthreads: int = 0, src_s: Optional[np.ndarray] = None):
+    """The T-term series with ftilde = sup f by direct sums in the log
+    domain (every term is non-negative then): S with full relative accuracy
+    at any distance from the sources, where phi underflows double precision.
+    O(N^2) per term.  Returns dict(S, logphi, info)."""
+    lib = _load()
+    f = np.ascontiguousarray(np.asarray(f, np.float64))
+    src = np.ascontiguousarray(np.asarray(src, np.int32))
+    p = _problem(f, h, hbar, T, "fmax", None, "direct", nthreads, src_s)
+    S = np.empty_like(f)
+    lphi = np.empty_like(f)
+    info = np.zeros(8, np.float64)
+    _check(lib.orc_solve_logdirect(C.byref(p), _dp(f), len(src), _ip(src), _dp(S), _dp(lphi),
+                                   _dp(info)), "solve_logdirect")
+    return {"S": S, "logphi": lphi, "info": _info(info)}
+
+
+def log_kappa(dims, beta: float) -> np.ndarray:
+    """ln kappa on the orthant 0 <= m_d < n_d."""
+    lib = _load()
+    out = np.empty(tuple(dims), np.float64)
+    _check(lib.orc_log_kappa(len(dims), _dims(dims), float(beta), _dp(out)), "log_kappa")
     return out
 
 

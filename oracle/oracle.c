@@ -615,3 +615,142 @@ int orc_adjoint(const orc_problem *p, const double *f, int32_t n_src,
   free(g);
   return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Log-domain direct path (reference forcing sup f).                         */
+/* ------------------------------------------------------------------------ */
+/* With ftilde = sup f every gamma = f^2/ftilde^2 - 1 is <= 0 while kappa > 0,
+ * so t_i = (-1)^i phi_i = kappa (*) ((-gamma) t_{i-1}) is a sum of
+ * non-negative products for every i (the monotone case of Section 5.1), and
+ * phi = sum_i t_i.  Carried as logarithms, each sum is a log-sum-exp: every
+ * value keeps full relative accuracy at any distance from the sources,
+ * where exp(-S/hbar) underflows double precision and FFT rounding noise
+ * swamps the value.  O(N^2) per term: tiny grids only. */
+
+/* ln kappa at distance r (grid units) */
+static double log_kappa_at(int ndim, double beta, double r) {
+  if (r == 0.0) return log(orc_kappa0(ndim, beta));
+  double x = beta * r;
+  if (ndim == 2) {
+    double lk0 = x <= 2.0 ? log(orc_bessel_k0(x)) : -x + log(k_integral_scaled(x, 0));
+    return log(beta * beta / (2.0 * PI)) + lk0;
+  }
+  return log(beta * beta / (4.0 * PI * r)) - x;
+}
+
+/* ln(e^a + e^b) */
+static double log_add(double a, double b) {
+  if (a == -INFINITY) return b;
+  if (b == -INFINITY) return a;
+  double m = a > b ? a : b;
+  return m + log1p(exp(-fabs(a - b)));
+}
+
+int orc_solve_logdirect(const orc_problem *p, const double *f, int32_t n_src,
+                        const int32_t *src, double *S, double *logphi,
+                        double *info) {
+  if (check_problem(p, f, n_src, src) || !S || p->ft_mode != ORC_FT_FMAX) return -1;
+#ifdef _OPENMP
+  if (p->nthreads > 0) omp_set_num_threads(p->nthreads);
+#endif
+  int64_t N = grid_size(p);
+  double ft, lo, hi;
+  int rc = reference_forcing(p, f, N, &ft, &lo, &hi);
+  if (rc) return rc;
+  double beta = ft * p->h / p->hbar;
+  int64_t n0 = p->dims[0], n1 = p->dims[1], n2 = p->ndim == 3 ? p->dims[2] : 1;
+  double *lk = (double *)malloc(sizeof(double) * N);   /* ln kappa, orthant */
+  double *lg = (double *)malloc(sizeof(double) * N);   /* ln(-gamma) */
+  double *prev = (double *)malloc(sizeof(double) * N); /* ln t_{i-1} */
+  double *cur = (double *)malloc(sizeof(double) * N);
+  double *lphi = logphi ? logphi : (double *)malloc(sizeof(double) * N);
+  if (!lk || !lg || !prev || !cur || !lphi) {
+    free(lk);
+    free(lg);
+    free(prev);
+    free(cur);
+    if (!logphi) free(lphi);
+    return -2;
+  }
+  double c0 = 0.0;
+  for (int64_t a = 0; a < n0; ++a)
+    for (int64_t b = 0; b < n1; ++b)
+      for (int64_t e = 0; e < n2; ++e) {
+        int64_t i = (a * n1 + b) * n2 + e;
+        lk[i] = log_kappa_at(p->ndim, beta, sqrt((double)(a * a + b * b + e * e)));
+        double g = f[i] * f[i] / (ft * ft) - 1.0;  /* <= 0 */
+        if (fabs(g) > c0) c0 = fabs(g);
+        lg[i] = -g > 0.0 ? log(-g) : -INFINITY;
+      }
+  /* ln phi_0 = ln sum_k exp(-s_k/hbar - beta |x - y_k|) (eq. phi_0Solution) */
+#pragma omp parallel for schedule(static)
+  for (int64_t x = 0; x < N; ++x) {
+    int64_t xa = x / (n1 * n2), xb = (x / n2) % n1, xe = x % n2;
+    double acc = -INFINITY;
+    for (int k = 0; k < n_src; ++k) {
+      double d0 = (double)(xa - src[k * p->ndim]);
+      double d1 = (double)(xb - src[k * p->ndim + 1]);
+      double d2 = p->ndim == 3 ? (double)(xe - src[k * p->ndim + 2]) : 0.0;
+      double lw = p->src_s ? -p->src_s[k] / p->hbar : 0.0;
+      acc = log_add(acc, lw - beta * sqrt(d0 * d0 + d1 * d1 + d2 * d2));
+    }
+    prev[x] = acc;
+    lphi[x] = acc;
+  }
+  for (int i = 1; i <= p->T; ++i) {
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t x = 0; x < N; ++x) {
+      int64_t xa = x / (n1 * n2), xb = (x / n2) % n1, xe = x % n2;
+      /* ln t_i(x) = ln sum_y kappa(x-y) (-gamma(y)) t_{i-1}(y): the largest
+         summand first, then the sum of the others relative to it */
+      double m = -INFINITY;
+      for (int64_t y = 0; y < N; ++y) {
+        int64_t ya = y / (n1 * n2), yb = (y / n2) % n1, ye = y % n2;
+        int64_t k = (llabs(xa - ya) * n1 + llabs(xb - yb)) * n2 + llabs(xe - ye);
+        double v = lk[k] + lg[y] + prev[y];
+        if (v > m) m = v;
+      }
+      double sum = 0.0;
+      if (m > -INFINITY)
+        for (int64_t y = 0; y < N; ++y) {
+          int64_t ya = y / (n1 * n2), yb = (y / n2) % n1, ye = y % n2;
+          int64_t k = (llabs(xa - ya) * n1 + llabs(xb - yb)) * n2 + llabs(xe - ye);
+          sum += exp(lk[k] + lg[y] + prev[y] - m);
+        }
+      cur[x] = m > -INFINITY ? m + log(sum) : -INFINITY;
+      lphi[x] = log_add(lphi[x], cur[x]);
+    }
+    double *t = prev;
+    prev = cur;
+    cur = t;
+  }
+  for (int64_t x = 0; x < N; ++x) S[x] = -p->hbar * lphi[x];
+  if (info) {
+    info[0] = ft;
+    info[1] = beta;
+    info[2] = lo;
+    info[3] = hi;
+    info[4] = c0;
+    info[5] = 0.0;
+    info[6] = 0.0;
+    info[7] = 0.0;
+  }
+  free(lk);
+  free(lg);
+  free(prev);
+  free(cur);
+  if (!logphi) free(lphi);
+  return 0;
+}
+
+/* ln kappa on the orthant of offsets (for tests of the log-domain path) */
+int orc_log_kappa(int ndim, const int64_t *dims, double beta, double *out) {
+  if ((ndim != 2 && ndim != 3) || !dims || !out || !(beta > 0)) return -1;
+  int64_t n0 = dims[0], n1 = dims[1], n2 = ndim == 3 ? dims[2] : 1;
+  for (int64_t a = 0; a < n0; ++a)
+    for (int64_t b = 0; b < n1; ++b)
+      for (int64_t c = 0; c < n2; ++c)
+        out[(a * n1 + b) * n2 + c] =
+            log_kappa_at(ndim, beta, sqrt((double)(a * a + b * b + c * c)));
+  return 0;
+}

@@ -91,6 +91,16 @@ int orc_adjoint(const orc_problem *p, const double *f, int32_t n_src,
                 const int32_t *src, const double *dLdS, double *dLdf,
                 double *info);
 
+/* Log-domain direct path: the same series for ftilde = sup f (ft_mode must
+ * be ORC_FT_FMAX; every term is then non-negative), each term's O(N^2) sum
+ * as a log-sum-exp: S = -hbar ln phi with full relative accuracy at any
+ * distance.  logphi (N, nullable) receives ln phi.  info as orc_solve. */
+int orc_solve_logdirect(const orc_problem *p, const double *f, int32_t n_src,
+                        const int32_t *src, double *S, double *logphi,
+                        double *info);
+/* ln kappa on the orthant 0 <= m_d < n_d. */
+int orc_log_kappa(int ndim, const int64_t *dims, double beta, double *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -486,3 +486,102 @@ def test_viscous_eikonal_residual():
     assert med[1] < 0.15 and med[2] < 0.1
     assert med[0] > med[1] > med[2]
 
+
+
+# ---- log-domain direct path (ground truth beyond FFT noise and underflow) ----
+
+def test_log_kappa_against_scipy():
+    """ln kappa from the exponentially scaled K0 of scipy (2D) and the
+    closed form (3D), far beyond the range where kappa itself underflows."""
+    for beta in (0.05, 2.6, 40.0):
+        lk = oracle.log_kappa((30, 30), beta)
+        m = np.stack(np.meshgrid(np.arange(30), np.arange(30), indexing="ij"), -1)
+        r = np.linalg.norm(m, axis=-1)
+        x = beta * r[1:, :]
+        ref = np.log(beta * beta / (2 * np.pi)) + np.log(sp.k0e(x)) - x
+        assert np.max(np.abs(lk[1:, :] - ref) / np.maximum(np.abs(ref), 1.0)) < 1e-13
+        assert abs(lk[0, 0] - np.log(oracle.kappa0(2, beta))) < 1e-14
+        lk3 = oracle.log_kappa((6, 7, 8), beta)
+        m3 = np.stack(np.meshgrid(np.arange(6), np.arange(7), np.arange(8), indexing="ij"), -1)
+        r3 = np.linalg.norm(m3, axis=-1)
+        ref3 = np.log(beta * beta / (4 * np.pi * r3[1:])) - beta * r3[1:]
+        assert np.max(np.abs(lk3[1:] - ref3) / np.maximum(np.abs(ref3), 1.0)) < 1e-13
+
+
+def test_logdirect_equals_kahan_direct():
+    """Where phi stays a normal double (the 64^2 bump workload, Lambda up to
+    ~108), the log-domain path and the compensated direct sums agree to
+    rounding at every point (sup f reference forcing)."""
+    p = workloads.problem(1)
+    f = p.f.astype(np.float64)
+    L = oracle.solve_logdirect(f, p.src, p.h, p.hbar, p.T)
+    D = oracle.solve(f, p.src, p.h, p.hbar, p.T, ft_mode="fmax", method="direct")
+    assert np.isfinite(D["S"]).all()
+    rel = np.abs(L["S"] - D["S"]) / np.maximum(np.abs(D["S"]), p.hbar)
+    assert rel.max() < 1e-13
+    assert abs(L["info"]["ftilde"] - f.max()) == 0.0
+
+
+@pytest.mark.parametrize("dims,hbar", [((48, 40), 0.02), ((10, 12, 14), 0.005)])
+def test_logdirect_constant_forcing_beyond_underflow(dims, hbar):
+    """f = c: gamma = 0, phi = phi_0 (eq. STilde): S = -hbar ln sum_k
+    exp(-c |x - y_k| / hbar) exactly, here with c|x-y|/hbar up to ~4000,
+    where exp underflows double precision and the plain paths give +inf."""
+    rng = np.random.default_rng(5)
+    f = np.full(dims, 1.3)
+    src = workloads.distinct_sources(dims, 2, rng)
+    h, T = 1.0, 4
+    L = oracle.solve_logdirect(f, src, h, hbar, T)
+    g = np.stack(np.meshgrid(*[np.arange(n) for n in dims], indexing="ij"), -1)
+    e = np.stack([-1.3 * np.linalg.norm(g - s, axis=-1) * h / hbar for s in src])
+    ref = -hbar * np.logaddexp.reduce(e, axis=0)
+    assert np.max(np.abs(L["S"] - ref) / np.maximum(np.abs(ref), hbar)) < 1e-14
+    plain = oracle.solve(f, src, h, hbar, T, ft_mode="fmax", method="direct")["S"]
+    far = -e.max(0) > 745.0
+    assert far.mean() > 0.3 and np.isinf(plain[far]).all() and np.isfinite(L["S"]).all()
+
+
+def test_logdirect_monotone_in_terms():
+    """Sup f reference forcing: every term is non-negative, so S decreases
+    with every added term at every point (Section 5.1), also where phi
+    itself is far below the double range."""
+    p = workloads.problem(1)
+    f = p.f.astype(np.float64)
+    prev = None
+    for T in range(0, 6):
+        S = oracle.solve_logdirect(f, p.src, 1.0, 0.02, T)["S"]  # Lambda up to ~4000
+        assert np.isfinite(S).all()
+        if prev is not None:
+            assert np.all(S <= prev * (1 + 1e-14) + 1e-300)
+            assert np.any(S < prev)
+        prev = S
+
+
+def test_logdirect_brute_force_extended_precision():
+    """A 6 x 7 grid with exp(-S/hbar) down to ~1e-600: the series summed
+    term by term in 60-digit decimal arithmetic (kernel values from their
+    logarithms) against the log-domain path."""
+    from decimal import Decimal, getcontext
+    getcontext().prec = 60
+    rng = np.random.default_rng(8)
+    dims, h, hbar, T = (6, 7), 1.0, 0.005, 3
+    f = rng.uniform(1.0, 1.6, dims)
+    src = np.array([[1, 2], [4, 6]], np.int32)
+    L = oracle.solve_logdirect(f, src, h, hbar, T)
+    ft = Decimal(repr(float(f.max())))
+    beta = ft * Decimal(repr(h)) / Decimal(repr(hbar))
+    lk = oracle.log_kappa(dims, float(beta))
+    kap = [[Decimal(repr(float(v))).exp() for v in row] for row in lk]
+    N = dims[0] * dims[1]
+    pts = [(i, j) for i in range(dims[0]) for j in range(dims[1])]
+    neg_gamma = [1 - (Decimal(repr(float(f[i, j]))) / ft) ** 2 for i, j in pts]
+    t = [sum((-(beta * Decimal(repr(float(np.hypot(i - a, j - b)))))).exp() for a, b in src)
+         for i, j in pts]
+    phi = list(t)
+    for _ in range(T):
+        t = [sum(kap[abs(i - k)][abs(j - l)] * neg_gamma[y] * t[y]
+                 for y, (k, l) in enumerate(pts)) for i, j in pts]
+        phi = [a + b for a, b in zip(phi, t)]
+    ref = np.array([float(-Decimal(repr(hbar)) * v.ln()) for v in phi]).reshape(dims)
+    assert np.max(np.abs(L["S"] - ref) / np.maximum(np.abs(ref), hbar)) < 1e-13
+    assert min(phi) < Decimal("1e-330")  # far below the double range
