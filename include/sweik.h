@@ -149,6 +149,24 @@ sweik_status sweik_solve_seeded(sweik_plan plan, const void *f,
                                 void *ws, size_t ws_bytes, void *ckpt,
                                 void *stream, sweik_info *info);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid device allocation): sweik_solve
+ * without a caller workspace.  The workspace is a static device array of
+ * sweik_noalloc_scratch_bytes() bytes (64 MiB) inside the library; each GPU
+ * the library runs on holds its own copy until the process ends.  The call
+ * allocates nothing (no hipMalloc, no library allocation); its first call on
+ * a device looks up that device's copy of the array.
+ *   f, src, S, stream, info  as sweik_solve (no checkpoint)
+ * Returns SWEIK_EWORKSPACE when sweik_workspace_bytes(plan) exceeds the
+ * array (e.g. 1024^2 in FP32 with T = 16 needs about 109 MB), before
+ * anything is enqueued.  Every call on one GPU uses the same array, which
+ * keeps the last call's contents (a solve writes every workspace buffer
+ * before reading it, so nothing needs clearing): calls that overlap in time
+ * on one GPU (other streams, other threads) race and give wrong results. */
+size_t sweik_noalloc_scratch_bytes(void);
+sweik_status sweik_solve_noalloc(sweik_plan plan, const void *f, const int32_t *src, void *S,
+                                 void *stream, sweik_info *info);
+
 /* Adjoint (2D) of the solve with ftilde held fixed (reverse sweep of the
  * recurrence eq. phiRecRelation; the kernel is even, so the transposed
  * convolution is the convolution itself).

@@ -80,6 +80,8 @@ def load_library():
     lib.sweik_check_sources.argtypes = [vp, C.POINTER(C.c_int32)]
     lib.sweik_solve.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp, vp]
     lib.sweik_solve_seeded.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
+    lib.sweik_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
+    lib.sweik_noalloc_scratch_bytes.restype = sz
     lib.sweik_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.sweik_solve_timed.argtypes = [vp, vp, vp, vp, vp, sz, vp, C.POINTER(C.c_float),
                                       C.POINTER(C.c_int32)]

@@ -846,6 +846,35 @@ template <typename R> int32_t autotune2d(sweik_plan_s *pl, void *ws, hipStream_t
 
 }  // namespace
 
+// Workspace of sweik_solve_noalloc: a static device array, one copy per GPU
+// the library runs on (held until the process ends).  Its host-side name
+// only stands for the symbol; the device address comes from
+// hipGetSymbolAddress, once per device with that device current, and only
+// that address is ever passed to kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kScratchDevices] = {};
+
+sweik_status scratch_address(void **out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return SWEIK_EDEVICE;
+  if (dev < 0 || dev >= kScratchDevices) return SWEIK_EUNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr)
+      return SWEIK_EDEVICE;
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return SWEIK_OK;
+}
+}  // namespace
+
 extern "C" {
 
 sweik_status sweik_plan_create(const sweik_problem *problem, sweik_plan *out) {
@@ -912,6 +941,20 @@ sweik_status sweik_solve_seeded(sweik_plan plan, const void *f, const int32_t *s
 sweik_status sweik_solve(sweik_plan plan, const void *f, const int32_t *src, void *S, void *ws,
                          size_t ws_bytes, void *ckpt, void *stream, sweik_info *info) {
   return sweik_solve_seeded(plan, f, src, nullptr, S, ws, ws_bytes, ckpt, stream, info);
+}
+
+size_t sweik_noalloc_scratch_bytes(void) { return kScratchBytes; }
+
+sweik_status sweik_solve_noalloc(sweik_plan plan, const void *f, const int32_t *src, void *S,
+                                 void *stream, sweik_info *info) {
+  if (!plan || !f || !src || !S) return SWEIK_EINVAL;
+  if (plan->ws.total > kScratchBytes) return SWEIK_EWORKSPACE;
+  void *ws = nullptr;
+  const sweik_status rc = scratch_address(&ws);
+  if (rc != SWEIK_OK) return rc;
+  // every workspace buffer of a solve is written before it is read, so the
+  // previous call's contents need no clearing
+  return sweik_solve_seeded(plan, f, src, nullptr, S, ws, kScratchBytes, nullptr, stream, info);
 }
 
 sweik_status sweik_solve_timed(sweik_plan plan, const void *f, const int32_t *src, void *S,

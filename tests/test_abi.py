@@ -199,6 +199,19 @@ def test_batch_solve_before_prepare_is_rejected(lib):
     assert lib.sweik_batch_prepare(None) == 1
 
 
+def test_noalloc_entry_checks(lib):
+    # argument errors and plans larger than the static array are rejected
+    # before any HIP call
+    vp = C.c_void_p
+    small = _plan()
+    assert lib.sweik_noalloc_scratch_bytes() == 64 << 20
+    assert lib.sweik_solve_noalloc(small.handle, None, vp(16), vp(16), None, None) == 1
+    assert lib.sweik_solve_noalloc(None, vp(16), vp(16), vp(16), None, None) == 1
+    big = _plan(dims=(1024, 1024), T=16, n_src=16)
+    assert big.workspace_bytes > lib.sweik_noalloc_scratch_bytes()
+    assert lib.sweik_solve_noalloc(big.handle, vp(16), vp(16), vp(16), None, None) == 3
+
+
 def test_host_only_calls_create_no_hip_resource(lib):
     # plans, batches and argument checks make no HIP call
     from paper_1403_1937_amd import Batch
