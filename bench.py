@@ -734,6 +734,52 @@ def traffic_summary(fetch_path, write_path, command):
     return head + "\n---\n" + json.dumps(d, indent=1) + "\n"
 
 
+def sq_summary(paths, command, kernels=("k_row2<float, 2,", "k_col2<float, 1,")):
+    """Per-dispatch averages of the SQ_* counters of one or more rocprofv3
+    --pmc runs for the kernels whose names contain the given fragments (the
+    term-row and column-convolution passes by default), with the ratios used
+    to read them: cycles per wave waiting, VALU issue per SIMD, LDS
+    instructions and bank-conflict cycles per wave."""
+    agg = {}
+    for path in paths:
+        for r in _counter_rows(path):
+            name = r["Kernel_Name"]
+            key = next((k for k in kernels if k in name), None)
+            if key is None:
+                continue
+            full = name.split("(")[0]
+            d = agg.setdefault(full, {}).setdefault(r["Counter_Name"], {})
+            disp = int(r["Dispatch_Id"])
+            d[disp] = d.get(disp, 0.0) + float(r["Counter_Value"])
+    out = {}
+    for name, cnt in agg.items():
+        avg = {c: float(np.mean(list(v.values()))) for c, v in cnt.items()}
+        n = {c: len(v) for c, v in cnt.items()}
+        row = {"dispatches": max(n.values()), "per_dispatch": avg}
+        w = avg.get("SQ_WAVES")
+        if w:
+            if "SQ_WAVE_CYCLES" in avg:
+                row["wave_cycles_per_wave"] = avg["SQ_WAVE_CYCLES"] / w
+            if "SQ_WAIT_INST_ANY" in avg and "SQ_WAVE_CYCLES" in avg:
+                row["frac_wave_cycles_waiting_inst"] = avg["SQ_WAIT_INST_ANY"] / avg["SQ_WAVE_CYCLES"]
+            if "SQ_WAIT_ANY" in avg and "SQ_WAVE_CYCLES" in avg:
+                row["frac_wave_cycles_waiting_any"] = avg["SQ_WAIT_ANY"] / avg["SQ_WAVE_CYCLES"]
+            for c in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_VMEM_RD",
+                      "SQ_INSTS_VMEM_WR", "SQ_INSTS_SMEM", "SQ_INSTS_BRANCH"):
+                if c in avg:
+                    row[c.lower().replace("sq_insts_", "insts_") + "_per_wave"] = avg[c] / w
+        if "SQ_INSTS_VALU" in avg:
+            # one wave64 VALU instruction occupies a SIMD for 4 cycles (16 lanes)
+            row["valu_issue_us_per_simd"] = avg["SQ_INSTS_VALU"] * 4 / (256 * 4) / 2.4e3
+        if "SQ_ACTIVE_INST_VALU" in avg:
+            row["valu_active_us_per_simd"] = avg["SQ_ACTIVE_INST_VALU"] / (256 * 4) / 2.4e3
+        out[name] = row
+    head = ("SQ counters of the 2D term passes (per-dispatch averages over the runs; one\n"
+            "rocprofv3 --pmc run per counter group), with derived ratios.\n"
+            f"command: {command}\n")
+    return head + "\n---\n" + json.dumps(out, indent=1) + "\n"
+
+
 def stats_summary(csv_path, command, top=12):
     with open(csv_path) as fh:
         rows = list(csv.DictReader(fh))
@@ -765,12 +811,15 @@ def main():
     ap.add_argument("--pmc-run", action="store_true")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH", "WRITE"))
     ap.add_argument("--stats-summary", metavar="CSV")
+    ap.add_argument("--sq-summary", nargs="+", metavar="DIR",
+                    help="summarise the SQ_* counters of rocprofv3 --pmc runs")
     ap.add_argument("--command", default="", help="command text recorded in a summary")
     ap.add_argument("--out", help="summary output file")
     args = ap.parse_args()
 
-    if args.traffic_summary or args.stats_summary:
+    if args.traffic_summary or args.stats_summary or args.sq_summary:
         text = (traffic_summary(*args.traffic_summary, args.command) if args.traffic_summary
+                else sq_summary(args.sq_summary, args.command) if args.sq_summary
                 else stats_summary(args.stats_summary, args.command))
         if args.out:
             with open(args.out, "w") as fh:
