@@ -54,6 +54,7 @@ extern "C" {
 
 #define SWEIK_ABI_VERSION 1
 #define SWEIK_MAX_TERMS 64 /* largest T */
+#define SWEIK_MAX_TILTS 64 /* most tilts of one sweik_solve_tilted */
 
 typedef enum {
   SWEIK_OK = 0,
@@ -147,6 +148,38 @@ sweik_status sweik_solve(sweik_plan plan, const void *f, const int32_t *src,
 sweik_status sweik_solve_seeded(sweik_plan plan, const void *f,
                                 const int32_t *src, const void *src_s, void *S,
                                 void *ws, size_t ws_bytes, void *ckpt,
+                                void *stream, sweik_info *info);
+
+/* Far-field stabilised solve (2D).  FFT convolution rounds with an absolute
+ * error of about eps max|phi_i| over the whole grid while phi decays like
+ * exp(-S/hbar), so far from the sources the plain solve loses all relative
+ * accuracy (Section 5.3; the paper turns to multiprecision there).  This
+ * solve runs the same series once per tilt a = beta (tilts[2d],
+ * tilts[2d+1]) (a per grid index along axes 0 and 1) on the tilted terms
+ * phi_i(x) exp(a . x - A) with the kernel kappa(m) exp(a . m): in exact
+ * arithmetic the same convolution (kappa (*) psi times exp(a . x) equals
+ * (kappa exp(a . m)) (*) (psi exp(a . y))), so S is unchanged, but the terms
+ * are flat in the direction of a and their rounding noise is small there.
+ * A = max_k (a . y_k) keeps the tilted phi_0 at most n_src.  Per point the
+ * result of the tilt with the best score ln(tilted phi) - ln B is kept,
+ * B = sum_i max|tilted phi_i| / (1 - |tilt|^2) being the tilt's noise scale
+ * (exp(-score) is about the relative error to expect).
+ *   tilts  HOST, n_tilt pairs (tilt0, tilt1) in units of beta, each with
+ *          tilt0^2 + tilt1^2 < 1 (the tilted kernel must decay); (0, 0) is
+ *          the plain solve.  E.g. (0, 0) and 8 directions at 0.9.
+ *   n_tilt 1 .. SWEIK_MAX_TILTS
+ *   ws     device workspace of ws_bytes >= sweik_tilted_workspace_bytes(plan)
+ *          (the solve's plus the tilted kernel's complex spectrum, (H1 + 1) M0
+ *          complex values, and a float per point)
+ *   f, src, S, stream, info as sweik_solve (no checkpoint); info counts the
+ *          points that no tilt resolved (S = +inf).
+ * Costs about one solve per tilt (the kernel spectrum of a tilt is complex:
+ * about 1.6 x the column pass's bytes).  With T = 0 it is sweik_solve.
+ * SWEIK_EINVAL for a tilt outside the unit disc or n_tilt out of range,
+ * SWEIK_EUNSUPPORTED in 3D (sweik_tilted_workspace_bytes returns 0 there). */
+size_t sweik_tilted_workspace_bytes(sweik_plan plan);
+sweik_status sweik_solve_tilted(sweik_plan plan, const void *f, const int32_t *src, void *S,
+                                const double *tilts, int32_t n_tilt, void *ws, size_t ws_bytes,
                                 void *stream, sweik_info *info);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight

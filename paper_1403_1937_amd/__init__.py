@@ -9,15 +9,17 @@ built, importing the solver functions raises.
     S, info = solve(..., return_info=True)
     path, n_points, status = backtrack(S, src, start)   # Section 6 paths
     S_fd = fd_solve(f, src, h, hbar)                    # Section 6 FD system
+    S = solve_tilted(f, src, h, hbar, T)                # far field (tilted convolutions)
 """
 from __future__ import annotations
 
 from ._native import (  # noqa: F401
     SweikError, Plan, Batch, solve, solve_adjoint, solve_with_checkpoint,
     EikonalFn, eikonal, batch_solve, lib_path, load_library, INFO_FLAGS, backtrack, TRACE_STATUS,
-    fd_solve, solve_gradient,
+    fd_solve, solve_gradient, solve_tilted, default_tilts,
 )
 
 __all__ = ["SweikError", "Plan", "Batch", "solve", "solve_adjoint",
            "solve_with_checkpoint", "EikonalFn", "eikonal", "batch_solve",
-           "lib_path", "load_library", "INFO_FLAGS", "backtrack", "TRACE_STATUS", "fd_solve", "solve_gradient"]
+           "lib_path", "load_library", "INFO_FLAGS", "backtrack", "TRACE_STATUS", "fd_solve", "solve_gradient",
+           "solve_tilted", "default_tilts"]

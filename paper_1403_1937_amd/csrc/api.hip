@@ -167,7 +167,7 @@ sweik_status plan2d(sweik_plan_s *pl) {
   g.nb = (g.n0 + g.RB - 1) / g.RB;
   // every pass must fit the work-group LDS limit
   const bool f64 = p.prec == SWEIK_F64;
-  for (int mode = ROW_GHAT; mode <= ROW_ADJ_B; ++mode) {
+  for (int mode = ROW_GHAT; mode <= ROW_LASTT; ++mode) {
     if (!(f64 ? row_fits<double>(g.H1, mode) : row_fits<float>(g.H1, mode)))
       return SWEIK_EUNSUPPORTED;
   }
@@ -215,6 +215,11 @@ sweik_status plan2d(sweik_plan_s *pl) {
   L.fg_part = take(sizeof(double) * kGradSlots * g.nbr);
   L.fg_ext = take(sizeof(long long) * 2 * kRedBlocks);
   L.fg_total = off;
+  off = L.total;
+  L.tl_gc = take((size_t)csz * (g.ldk + 1) * g.M0);
+  L.tl_best = take(sizeof(float) * N);
+  L.tl_tmax = take(sizeof(double) * (size_t)(p.T + 2));
+  L.tl_total = off;
   off = 0;
   L.ck_expo = take(sizeof(int) * (SWEIK_MAX_TERMS + 1));
   L.ck_par = take(sizeof(Params));
@@ -272,6 +277,15 @@ Args2<R> make_args2(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.dLdf = nullptr;
   a.spec2 = nullptr;
   a.gpart = nullptr;
+  a.tilt0 = 0.0;
+  a.tilt1 = 0.0;
+  a.tsign = 1;
+  a.tfirst = 0;
+  a.tlast = 0;
+  a.gc = nullptr;
+  a.spec_neg = nullptr;
+  a.best = nullptr;
+  a.tmax = nullptr;
   a.info = info;
   char *c = (char *)ckpt;
   if (c) {  // the kernel spectrum and scalars live in the checkpoint
@@ -366,6 +380,52 @@ sweik_status enqueue2d(const sweik_plan_s *pl, const void *f, const int32_t *src
     launch(lastp ? SWEIK_KC_LAST_ROW : SWEIK_KC_TERM_ROW, [&] {
       return launch_row2<R>(lastp ? ROW_LAST : ROW_TERM, g.H1, g.erow, grow, st, a, i);
     });
+  }
+  return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
+}
+
+// Far-field stabilised solve (2D): the series of Table 1 once per tilt a =
+// beta (tilts[2d], tilts[2d+1]), each on phi_i exp(a . x) with the kernel
+// kappa(m) exp(a . m) (the same convolution, exactly, in tilted variables);
+// per point the last pass keeps the tilt whose rounding noise is smallest
+// relative to its value.  The tilted passes run with radix-16 teams; the
+// term passes use the plan's row schedule.
+template <typename R>
+sweik_status enqueue2d_tilted(const sweik_plan_s *pl, const void *f, const int32_t *src,
+                              void *S, const double *tilts, int n_tilt, void *ws, hipStream_t st,
+                              sweik_info *info) {
+  const Geo2 &g = pl->g2;
+  const Layout &L = pl->ws;
+  char *w = (char *)ws;
+  Args2<R> a = make_args2<R>(pl, f, src, S, ws, nullptr, info);
+  a.gc = (cplx<R> *)(w + L.tl_gc);
+  a.best = (float *)(w + L.tl_best);
+  a.tmax = (double *)(w + L.tl_tmax);
+  a.spec_neg = (cplx<R> *)(w + L.spec0);
+  const long long N = (long long)g.n0 * g.n1;
+  const dim3 grow(g.nbr), gcol(g.ncw);
+  hipError_t err = launch_prep<R>((const R *)f, N, a.red, (cplx<R> *)a.tw, g.lmax, st);
+  for (int d = 0; d < n_tilt && err == hipSuccess; ++d) {
+    a.tilt0 = tilts[2 * d];
+    a.tilt1 = tilts[2 * d + 1];
+    a.tfirst = d == 0;
+    a.tlast = d == n_tilt - 1;
+    // the tilted kernel's spectrum: table rows m0 >= 0 into spec, m0 <= 0 into
+    // spec_neg, then the complex column transforms into gc
+    Args2<R> an = a;
+    an.tsign = -1;
+    an.spec = a.spec_neg;
+    err = launch_row2<R>(ROW_GHATT, g.H1, 16, grow, st, a, 0);
+    if (err == hipSuccess) err = launch_row2<R>(ROW_GHATT, g.H1, 16, grow, st, an, 0);
+    if (err == hipSuccess) err = launch_col2<R>(COL_GHATC, g.M0, 16, gcol, st, a);
+    if (err == hipSuccess) err = launch_row2<R>(ROW_PHI0, g.H1, g.erow, grow, st, a, 0);
+    for (int i = 1; i <= pl->p.T && err == hipSuccess; ++i) {
+      err = launch_col2<R>(COL_CONVC, g.M0, 16, gcol, st, a);
+      const bool lastp = i == pl->p.T;
+      if (err == hipSuccess)
+        err = launch_row2<R>(lastp ? ROW_LASTT : ROW_TERM, g.H1, lastp ? 16 : g.erow, grow, st, a,
+                             i);
+    }
   }
   return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
@@ -941,6 +1001,30 @@ sweik_status sweik_solve_seeded(sweik_plan plan, const void *f, const int32_t *s
 sweik_status sweik_solve(sweik_plan plan, const void *f, const int32_t *src, void *S, void *ws,
                          size_t ws_bytes, void *ckpt, void *stream, sweik_info *info) {
   return sweik_solve_seeded(plan, f, src, nullptr, S, ws, ws_bytes, ckpt, stream, info);
+}
+
+size_t sweik_tilted_workspace_bytes(sweik_plan plan) {
+  return (plan && plan->p.ndim == 2) ? plan->ws.tl_total : 0;
+}
+
+sweik_status sweik_solve_tilted(sweik_plan plan, const void *f, const int32_t *src, void *S,
+                                const double *tilts, int32_t n_tilt, void *ws, size_t ws_bytes,
+                                void *stream, sweik_info *info) {
+  if (!plan || !f || !src || !S || !ws || !tilts) return SWEIK_EINVAL;
+  if (plan->p.ndim != 2) return SWEIK_EUNSUPPORTED;
+  if (n_tilt < 1 || n_tilt > SWEIK_MAX_TILTS) return SWEIK_EINVAL;
+  for (int d = 0; d < n_tilt; ++d) {
+    const double t0 = tilts[2 * d], t1 = tilts[2 * d + 1];
+    if (!std::isfinite(t0) || !std::isfinite(t1) || !(t0 * t0 + t1 * t1 < 1.0)) return SWEIK_EINVAL;
+  }
+  if (ws_bytes < plan->ws.tl_total) return SWEIK_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  const bool f64 = plan->p.prec == SWEIK_F64;
+  if (plan->p.T == 0)  // phi = phi_0 in closed form: nothing for a tilt to stabilise
+    return f64 ? enqueue2d<double>(plan, f, src, S, ws, nullptr, st, info)
+               : enqueue2d<float>(plan, f, src, S, ws, nullptr, st, info);
+  return f64 ? enqueue2d_tilted<double>(plan, f, src, S, tilts, n_tilt, ws, st, info)
+             : enqueue2d_tilted<float>(plan, f, src, S, tilts, n_tilt, ws, st, info);
 }
 
 size_t sweik_noalloc_scratch_bytes(void) { return kScratchBytes; }

@@ -10,6 +10,10 @@
 //             kernel spectrum Ghat[k0][k1], inverse FFT, keep the first rows
 //   COL_GHAT  even extension of the column of the kernel table's row
 //             transforms, forward FFT, keep the real part: Ghat
+//   COL_GHATC the tilted kernel's column (rows m0 >= 0 and m0 < 0 from two
+//             row-transform tables), forward FFT: its complex spectrum, all
+//             M0 frequencies (the tilted kernel is not even)
+//   COL_CONVC COL_CONV with that complex kernel spectrum
 // Column k1 = 0 holds two real sequences, the DC (re) and Nyquist (im) bins
 // of the rows.  Their transforms A, B are Hermitian, so the product with
 // their own kernel columns is Y = (Ga + Gb)/2 F + (Ga - Gb)/2 conj F(-k)
@@ -29,6 +33,8 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
   constexpr int P = M0 / E, CPW = col_cpw(M0), RB = spec_rb<R>(), LL = col_line_len<R>(M0);
   constexpr int NT = team_threads(E);
   constexpr int H0 = M0 / 2;
+  constexpr bool CONV = MODE == COL_CONV || MODE == COL_CONVC;
+  constexpr bool CPLX = MODE == COL_CONVC;  // complex (tilted) kernel spectrum
   static_assert(P % RB == 0, "column team must cover whole row blocks");
   C *twl = reinterpret_cast<C *>(smem_raw);  // stage twiddle tables
   C *lines = twl + col_stage_tw<R>(M0);
@@ -44,37 +50,66 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
   const int spec_rows = a.nb * RB;
   const size_t cstride = (size_t)a.ldk * RB;  // elements between blocks
   C *col = a.spec + (size_t)(active ? k1 : 0) * RB;
+  auto at = [&](const C *base, int rho) -> C {  // row rho of this column
+    const int b = rho / RB;
+    return base[b * cstride + (rho - b * RB)];
+  };
 
   // ---- issue the global reads -----------------------------------------------
   constexpr int NSR = (stage_tw_len(M0, E) + NT - 1) / NT;
   C twr[NSR > 0 ? NSR : 1];
   stage_tw_issue<M0, E>(twr, a.tw, a.lmax_log, tid, NT);
   C v[E];
-  R gv[E], gb[E];
-  if constexpr (MODE == COL_CONV) {
+  R gv[CPLX ? 1 : E], gb[CPLX ? 1 : E];
+  C gvc[CPLX ? E : 1], gbc[CPLX ? E : 1];
+  if constexpr (CONV) {
 #pragma unroll
     for (int j = 0; j < E; ++j) {
       const int rho = t + P * j;
       C x = cmake<C>((R)0, (R)0);
-      if (j < E / 2 && (FULL || (active && rho < spec_rows))) {
-        const int b = rho / RB;
-        x = col[b * cstride + (rho - b * RB)];
-      }
+      if (j < E / 2 && (FULL || (active && rho < spec_rows))) x = at(col, rho);
       v[j] = x;
     }
-    const R *gcol = a.g + (size_t)(active ? k1 : 0) * a.ldg;
+    if constexpr (CPLX) {
+      // the tilted kernel is not even: all M0 frequencies of the column
+      const C *gcol = a.gc + (size_t)(active ? k1 : 0) * M0;
 #pragma unroll
-    for (int j = 0; j < E; ++j) {
-      const int k0 = t + P * j;
-      gv[j] = gcol[k0 <= H0 ? k0 : M0 - k0];
-    }
-    if (packed_wg && k1 == 0) {
-      const R *gnyq = a.g + (size_t)a.ldk * a.ldg;  // kernel column of bin H1
+      for (int j = 0; j < E; ++j) gvc[j] = gcol[t + P * j];
+      if (packed_wg && k1 == 0) {
+        const C *gnyq = a.gc + (size_t)a.ldk * M0;  // kernel column of bin H1
+#pragma unroll
+        for (int j = 0; j < E; ++j) gbc[j] = gnyq[t + P * j];
+      }
+    } else {
+      const R *gcol = a.g + (size_t)(active ? k1 : 0) * a.ldg;
 #pragma unroll
       for (int j = 0; j < E; ++j) {
         const int k0 = t + P * j;
-        gb[j] = gnyq[k0 <= H0 ? k0 : M0 - k0];
+        gv[j] = gcol[k0 <= H0 ? k0 : M0 - k0];
       }
+      if (packed_wg && k1 == 0) {
+        const R *gnyq = a.g + (size_t)a.ldk * a.ldg;  // kernel column of bin H1
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          const int k0 = t + P * j;
+          gb[j] = gnyq[k0 <= H0 ? k0 : M0 - k0];
+        }
+      }
+    }
+  } else if constexpr (MODE == COL_GHATC) {
+    // the tilted kernel's column: rows m0 = rho >= 0 from the row transforms
+    // of the table rows m0 >= 0, rows m0 = rho - M0 < 0 from those of the
+    // rows m0 <= 0 (row -m0 of spec_neg), zero in between
+    const C *cneg = a.spec_neg + (size_t)(active ? k1 : 0) * RB;
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int rho = t + P * j;
+      C x = cmake<C>((R)0, (R)0);
+      if (active) {
+        if (rho < a.n0) x = at(col, rho);
+        else if (M0 - rho < a.n0) x = at(cneg, M0 - rho);
+      }
+      v[j] = x;
     }
   } else {
     // even extension of the column: x[rho] = x[M0 - rho]
@@ -83,10 +118,7 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
       const int rho = t + P * j;
       const int sr = rho <= H0 ? rho : M0 - rho;
       C x = cmake<C>((R)0, (R)0);
-      if (active && sr < spec_rows) {
-        const int b = sr / RB;
-        x = col[b * cstride + (sr - b * RB)];
-      }
+      if (active && sr < spec_rows) x = at(col, sr);
       v[j] = x;
     }
   }
@@ -94,28 +126,40 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
   __syncthreads();
 
   team_fft<M0, false>(v, t, line, twl, false);
-  if constexpr (MODE == COL_CONV) {
+  // Column 0 holds two real sequences, A (the rows' DC bins) and B (their
+  // Nyquist bins): with F = A^ + i B^ their transforms are A^ = (F(k) +
+  // conj F(-k)) / 2 and B^ = (F(k) - conj F(-k)) / 2i.  The partner values
+  // F(-k) come through LDS (every team of the work-group takes part).
+  C pv[(CONV || MODE == COL_GHATC) ? E : 1];
+  if constexpr (CONV || MODE == COL_GHATC) {
     if (packed_wg) {
-      C pv[E];
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < E; ++j) line[lpad(t + P * j)] = v[j];
       __syncthreads();
 #pragma unroll
       for (int j = 0; j < E; ++j) pv[j] = line[lpad((M0 - (t + P * j)) & (M0 - 1))];
-      if (k1 == 0) {
+    }
+  }
+  if constexpr (CONV) {
+    if (packed_wg && k1 == 0) {
+      // Y = A^ Ga + i B^ Gb = F (Ga + Gb) / 2 + conj F(-k) (Ga - Gb) / 2
 #pragma unroll
-        for (int j = 0; j < E; ++j) {
+      for (int j = 0; j < E; ++j) {
+        if constexpr (CPLX) {
+          const C al = cscale(cadd(gvc[j], gbc[j]), (R)0.5), de = cscale(csub(gvc[j], gbc[j]), (R)0.5);
+          v[j] = cadd(cmul(v[j], al), cmul(cconj(pv[j]), de));
+        } else {
           const R al = (gv[j] + gb[j]) * (R)0.5, de = (gv[j] - gb[j]) * (R)0.5;
           v[j] = cadd(cscale(v[j], al), cscale(cconj(pv[j]), de));
         }
-      } else {
-#pragma unroll
-        for (int j = 0; j < E; ++j) v[j] = cscale(v[j], gv[j]);
       }
     } else {
 #pragma unroll
-      for (int j = 0; j < E; ++j) v[j] = cscale(v[j], gv[j]);
+      for (int j = 0; j < E; ++j) {
+        if constexpr (CPLX) v[j] = cmul(v[j], gvc[j]);
+        else v[j] = cscale(v[j], gv[j]);
+      }
     }
     team_fft<M0, true>(v, t, line, twl, true);
     if (active) {
@@ -125,6 +169,26 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
         if (FULL || rho < spec_rows) {
           const int b = rho / RB;
           col[b * cstride + (rho - b * RB)] = v[j];
+        }
+      }
+    }
+  } else if constexpr (MODE == COL_GHATC) {
+    if (active) {
+      // scaled as Ghat below; all M0 frequencies, complex
+      const R sc = (R)(1.0 / (4.0 * (double)M0 * (double)(2 * a.H1)));
+      C *gcol = a.gc + (size_t)k1 * M0;
+      C *gnyq = a.gc + (size_t)a.ldk * M0;
+#pragma unroll
+      for (int j = 0; j < E; ++j) {
+        const int k0 = t + P * j;
+        if (k1 == 0) {
+          const C fa = cscale(cadd(v[j], cconj(pv[j])), (R)0.5);   // A^
+          const C d = csub(v[j], cconj(pv[j]));
+          const C fb = cmake<C>(d.y * (R)0.5, -d.x * (R)0.5);    // B^ = d / 2i
+          gcol[k0] = cscale(fa, sc);
+          gnyq[k0] = cscale(fb, sc);
+        } else {
+          gcol[k0] = cscale(v[j], sc);
         }
       }
     }

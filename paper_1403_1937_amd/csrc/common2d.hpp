@@ -91,6 +91,16 @@ template <typename R> struct Args2 {
   // full gradient
   cplx<R> *spec2;  // spectrum convolved with the kernel's beta-derivative
   double *gpart;   // kGradSlots x nbr per-work-group partial sums
+  // far-field stabilised (tilted) solve: the convolution runs on
+  // phi_i exp(a . x) with the kernel kappa(m) exp(a . m), a = beta (tilt0, tilt1)
+  // per grid index (|tilt| < 1); tmax: 0 when not tilted
+  double tilt0, tilt1;
+  int tsign;         // ROW_GHATT: +1 kernel rows m0 >= 0, -1 rows m0 <= 0
+  int tfirst, tlast; // ROW_LASTT: first / last tilt of the solve
+  cplx<R> *gc;       // tilted kernel spectrum, (H1 + 1) x M0 complex, column k1 contiguous
+  cplx<R> *spec_neg; // COL_GHATC: row transforms of the kernel rows m0 <= 0
+  float *best;       // per point: score of the tilt whose S is stored
+  double *tmax;      // T + 2: max |phi_i| per stored term, then the tilt's offset A
 };
 
 // Per-work-group partial sums of the full gradient (each slot nbr long):
@@ -305,6 +315,29 @@ __device__ __forceinline__ int write_S(const A &a, size_t i, double phi) {
   return ok ? 0 : 1;
 }
 
+// Tilted solve, last pass: phi~ = phi exp(a . x - A) at point i (ax =
+// a . x - A).  The result replaces the stored one when its score
+// ln phi~ - ln B (B the tilt's noise scale: FFT rounding is about eps B in
+// phi~ everywhere, so exp(-score) is the relative error to expect) beats the
+// score stored by an earlier tilt (prev), or on the first tilt.  Returns 1,
+// on the last tilt, for a point that no tilt resolved (phi~ <= 0 in every
+// tilt: S = +inf).
+template <typename A>
+__device__ __forceinline__ int write_S_tilt(const A &a, size_t i, double phit, double ax,
+                                            double lnB, float prev) {
+  using R = typename std::remove_pointer<decltype(a.S)>::type;
+  const bool ok = phit > 0.0 && isfinite(phit);
+  const double lp = ok ? log(phit) : 0.0;
+  const float sc = ok ? (float)(lp - lnB) : -__builtin_huge_valf();
+  const bool take = a.tfirst || sc > prev;
+  if (take) {
+    a.S[i] = ok ? (R)(-a.hbar * (lp - ax)) : (R)__builtin_huge_val();
+    a.best[i] = sc;
+  }
+  const float now = take ? sc : prev;
+  return (a.tlast && !(now > -__builtin_huge_valf())) ? 1 : 0;
+}
+
 // One instance of an uneven batch: its arguments and the first work-group
 // of its share of a batched launch.
 template <typename R> struct BatchItem {
@@ -346,6 +379,10 @@ template <typename R> __device__ __forceinline__ Args2<R> item_args(const BatchI
   a.ck_terms = as_global(a.ck_terms);
   a.spec2 = as_global(a.spec2);
   a.gpart = as_global(a.gpart);
+  a.gc = as_global(a.gc);
+  a.spec_neg = as_global(a.spec_neg);
+  a.best = as_global(a.best);
+  a.tmax = as_global(a.tmax);
   return a;
 }
 

@@ -22,12 +22,16 @@ namespace sweik {
 // kernel so that the term passes are not sized for its registers.
 // ROW_DGHAT, ROW_ADJ0_B and ROW_ADJ_B serve the full gradient: the kernel
 // table's beta-derivative, and the adjoint passes that also carry the
-// convolutions with it and the scalar partial sums.
+// convolutions with it and the scalar partial sums.  ROW_GHATT and ROW_LASTT
+// serve the far-field stabilised (tilted) solve: the rows of the tilted
+// kernel table, and the last pass that undoes the tilt and keeps, per
+// point, the best-conditioned of the tilts solved so far; COL_GHATC and
+// COL_CONVC are the column passes with the tilted kernel's complex spectrum.
 enum RowMode {
   ROW_GHAT = 0, ROW_PHI0 = 1, ROW_TERM = 2, ROW_ADJ0 = 3, ROW_ADJ = 4, ROW_SEED = 5, ROW_LAST = 6,
-  ROW_DGHAT = 7, ROW_ADJ0_B = 8, ROW_ADJ_B = 9
+  ROW_DGHAT = 7, ROW_ADJ0_B = 8, ROW_ADJ_B = 9, ROW_GHATT = 10, ROW_LASTT = 11
 };
-enum ColMode { COL_GHAT = 0, COL_CONV = 1 };
+enum ColMode { COL_GHAT = 0, COL_CONV = 1, COL_GHATC = 2, COL_CONVC = 3 };
 
 template <typename R> constexpr int spec_rb() { return sizeof(R) == 4 ? 4 : 2; }
 constexpr int kThreads = 256;

@@ -186,6 +186,53 @@ __device__ inline float kappa_2d_t<float>(double beta, int r2, double k0v, const
   return b * b * (float)(0.5 / kPi) * bessel_k0_f32(b * sqrtf((float)r2), tab);
 }
 
+// The tilted kernel kappa(m) exp(e), e = a . m with |a| < beta (the
+// far-field stabilised convolution): the exponent is folded into the
+// exponentially scaled K0 for x = beta |m| > 2, so that neither factor
+// underflows or overflows where the product matters.  m = 0 gives k0v.
+__device__ inline double kappa_2d_tilt(double beta, int m0, int m1, double e, double k0v,
+                                       const ChebK0 &tab) {
+  if (m0 == 0 && m1 == 0) return k0v;
+  const double x = beta * sqrt((double)m0 * m0 + (double)m1 * m1);
+  const double c = beta * beta * (0.5 / kPi);
+  if (x <= 2.0) return c * bessel_k0_series(x) * exp(e);
+  const double t = 4.0 / x - 1.0, t2 = 2.0 * t;
+  double b1 = 0.0, b2 = 0.0;
+#pragma unroll
+  for (int k = kChebK0 - 1; k >= 1; --k) {
+    const double b0 = fma(t2, b1, tab.c[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return c * fma(t, b1, tab.c[0] - b2) / sqrt(x) * exp(e - x);
+}
+template <typename R>
+__device__ inline R kappa_2d_tilt_t(double beta, int m0, int m1, double e, double k0v,
+                                    const ChebK0 &tab);
+template <>
+__device__ inline double kappa_2d_tilt_t<double>(double beta, int m0, int m1, double e, double k0v,
+                                                 const ChebK0 &tab) {
+  return kappa_2d_tilt(beta, m0, m1, e, k0v, tab);
+}
+template <>
+__device__ inline float kappa_2d_tilt_t<float>(double beta, int m0, int m1, double e, double k0v,
+                                               const ChebK0 &tab) {
+  if (m0 == 0 && m1 == 0) return (float)k0v;
+  const float b = (float)beta;
+  const float x = b * sqrtf((float)m0 * (float)m0 + (float)m1 * (float)m1);
+  const float c = b * b * (float)(0.5 / kPi);
+  if (x <= 2.0f) return c * bessel_k0_f32(x, tab) * expf((float)e);
+  const float t = 4.0f / x - 1.0f, t2 = 2.0f * t;
+  float b1 = 0.0f, b2 = 0.0f;
+#pragma unroll
+  for (int k = kChebK0 - 1; k >= 1; --k) {
+    const float b0 = fmaf(t2, b1, tab.c32[k] - b2);
+    b2 = b1;
+    b1 = b0;
+  }
+  return c * fmaf(t, b1, tab.c32[0] - b2) * rsqrtf(x) * expf((float)e - x);
+}
+
 // d kappa / d beta at an integer offset (2D), for the gradient with respect
 // to beta: off the origin (beta/pi) K0(x) - (beta/2pi) x K1(x), x = beta |m|;
 // at the origin the beta-derivative of the ball average 1 - a K1(a),

@@ -117,6 +117,13 @@ hipError_t launch_row2_e(int mode, int H, dim3 grid, hipStream_t st, const Args2
     case ROW_DGHAT: return RowLaunch<R, E, ROW_DGHAT>::run(H, grid, st, a, term);
     case ROW_ADJ0_B: return RowLaunch<R, E, ROW_ADJ0_B>::run(H, grid, st, a, term);
     case ROW_ADJ_B: return RowLaunch<R, E, ROW_ADJ_B>::run(H, grid, st, a, term);
+    // the tilted solve's own passes run with radix-16 teams only
+    case ROW_GHATT:
+      if constexpr (E == 16) return RowLaunch<R, E, ROW_GHATT>::run(H, grid, st, a, term);
+      break;
+    case ROW_LASTT:
+      if constexpr (E == 16) return RowLaunch<R, E, ROW_LASTT>::run(H, grid, st, a, term);
+      break;
   }
   return hipErrorInvalidValue;
 }
@@ -169,8 +176,18 @@ template <typename R, int E, int MODE> struct ColLaunch {
 
 template <typename R, int E>
 hipError_t launch_col2_e(int mode, int M0, dim3 grid, hipStream_t st, const Args2<R> &a) {
-  return mode == COL_GHAT ? ColLaunch<R, E, COL_GHAT>::run(M0, grid, st, a)
-                          : ColLaunch<R, E, COL_CONV>::run(M0, grid, st, a);
+  switch (mode) {
+    case COL_GHAT: return ColLaunch<R, E, COL_GHAT>::run(M0, grid, st, a);
+    case COL_CONV: return ColLaunch<R, E, COL_CONV>::run(M0, grid, st, a);
+    // the tilted solve's column passes run with radix-16 teams only
+    case COL_GHATC:
+      if constexpr (E == 16) return ColLaunch<R, E, COL_GHATC>::run(M0, grid, st, a);
+      break;
+    case COL_CONVC:
+      if constexpr (E == 16) return ColLaunch<R, E, COL_CONVC>::run(M0, grid, st, a);
+      break;
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename R, int E>

@@ -189,7 +189,8 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   constexpr int TWLOG = ilog2c(2 * H);
   constexpr bool STG = row_staged<R>(H, MODE);
   constexpr int NTW = (H + NT - 1) / NT;
-  constexpr bool TERMLIKE = MODE == ROW_TERM || MODE == ROW_LAST;
+  constexpr bool LASTLIKE = MODE == ROW_LAST || MODE == ROW_LASTT;
+  constexpr bool TERMLIKE = MODE == ROW_TERM || LASTLIKE;
   constexpr bool ADJ = MODE == ROW_ADJ || MODE == ROW_ADJ_B;
   constexpr bool ADJ0 = MODE == ROW_ADJ0 || MODE == ROW_ADJ0_B;
   constexpr bool FULLG = MODE == ROW_ADJ_B || MODE == ROW_ADJ0_B;  // full gradient
@@ -209,7 +210,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   const bool row_ok = FULL || r < a.n0;
   const size_t rowoff = (size_t)r * a.n1;
   const size_t N = (size_t)a.n0 * a.n1;
-  const bool last = MODE == ROW_LAST || (MODE == ROW_PHI0 && a.T == 0);
+  const bool last = LASTLIKE || (MODE == ROW_PHI0 && a.T == 0);
   // column c of this thread's pair j (c = 2(t + P j) + e) lies in the grid
   auto col_ok = [&](int c) { return FULL ? true : (row_ok && c < a.n1); };
   Tile tile;
@@ -299,7 +300,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
 
   // ---- 2. scalars ----------------------------------------------------------
   double beta, inv_ft2, ft;
-  if (MODE == ROW_GHAT) {
+  if (MODE == ROW_GHAT || MODE == ROW_GHATT) {
     double lo, hi;
     int fl;
     reduce_forcing(a.red, a.ft_mode, a.ftilde_given, &lo, &hi, &fl);
@@ -369,6 +370,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
 
   // exponents: forward phi_i = 2^E_i m_i; adjoint a_i = 2^e_lam (mantissa)
   int dstep = 0, Ei = 0, elam = 0;
+  double term_mu = 0.0;  // ROW_LASTT: max |m_{T-1}|
   if (TERMLIKE) {
     // the previous pass's per-work-group maxima: the first four rounds are
     // read before any is folded (one wait instead of one per round)
@@ -384,6 +386,9 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     mu = block_max(mu);
     dstep = exp_step(mu);
     Ei = a.expo[term - 1] + dstep;
+    // tilted solve: max |phi_{term-1}| (its mantissa maximum times its scale)
+    if (a.tmax && bid == 0 && tid == 0) a.tmax[term - 1] = mu * ldexp(1.0, a.expo[term - 1]);
+    if constexpr (MODE == ROW_LASTT) term_mu = mu;
   }
   if ((TERMLIKE || MODE == ROW_PHI0) && bid == 0 && tid == 0) {
     const int slot = TERMLIKE ? term : 0;
@@ -393,8 +398,8 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   }
   // last term: signed scales (-1)^i 2^E_i of the stored terms (read after
   // the barrier below)
-  __shared__ double s_sE[MODE == ROW_LAST ? SWEIK_MAX_TERMS + 1 : 1];
-  if (MODE == ROW_LAST)
+  __shared__ double s_sE[LASTLIKE ? SWEIK_MAX_TERMS + 1 : 1];
+  if (LASTLIKE)
     for (int i = tid; i < a.T; i += NT) s_sE[i] = ((i & 1) ? -1.0 : 1.0) * ldexp(1.0, a.expo[i]);
   if (ADJ0) {
     double mx = 0.0;
@@ -468,6 +473,26 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   C v[E];
 
   // ---- 4. kernel table ------------------------------------------------------
+  if constexpr (MODE == ROW_GHATT) {
+    // Row r of the tilted kernel table for the offsets m0 = tsign r:
+    // x[c] = kappa(r, m1) exp(beta (tsign tilt0 r + tilt1 m1)) with m1 = c
+    // for c < n1 and m1 = c - 2H for c > 2H - n1 (kappa is even, the tilt is
+    // not: both halves are evaluated), zero in between.
+    const double k0v = s_par[0];
+    const double a0 = (double)a.tsign * a.tilt0 * beta, a1 = a.tilt1 * beta;
+    auto tab = [&](int c) -> R {
+      const int m1 = c < a.n1 ? c : (c > 2 * H - a.n1 ? c - 2 * H : INT_MIN);
+      if (!row_ok || m1 == INT_MIN) return (R)0;
+      return kappa_2d_tilt_t<R>(beta, r, m1, a0 * r + a1 * m1, k0v, a.k0tab);
+    };
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      const int c0 = 2 * (t + P * j);
+      v[j] = cmake<C>(tab(c0), tab(c0 + 1));
+    }
+    row_r2c_store<FULL, R, H, E>(v, t, tid, line, lines, twl, tws, tile);
+    return;
+  }
   if constexpr (GHATLIKE) {
     // Row r of the evenly extended kernel table, x[m] = kappa(r, min(m,
     // 2H - m)) (zero for offsets >= n1): the first half is evaluated, the
@@ -537,6 +562,25 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   long long nbad = 0;
   if constexpr (MODE == ROW_PHI0 || TERMLIKE) {
     const bool even_n1 = FULL || (a.n1 & 1) == 0;
+    // tilted solve (tmax set): the terms are phi_i exp(a . x - A) with
+    // a = beta (tilt0, tilt1) and A = max_k (a . y_k - s_k / hbar), so that
+    // the tilted phi_0 stays below n_src; phi_0's pass forms A and keeps it
+    // for the last pass
+    const bool tilted = a.tmax != nullptr && (MODE == ROW_PHI0 || MODE == ROW_LASTT);
+    const double ta0 = a.tilt0 * beta, ta1 = a.tilt1 * beta;
+    double tA = 0.0;
+    if (MODE == ROW_PHI0 && tilted) {
+      double m = -__builtin_huge_val();
+      for (int k = 0; k < a.n_src; ++k) {
+        const int y0 = k < kSrcLds ? s_src[2 * k] : a.src[2 * k];
+        const int y1 = k < kSrcLds ? s_src[2 * k + 1] : a.src[2 * k + 1];
+        const double lw = a.src_s ? -(double)a.src_s[k] / a.hbar : 0.0;
+        m = fmax(m, ta0 * y0 + ta1 * y1 + lw);
+      }
+      tA = m;
+      if (bid == 0 && tid == 0) a.tmax[a.T + 1] = tA;
+    }
+    if (MODE == ROW_LASTT) tA = a.tmax[a.T + 1];
     const R sm = (R)ldexp(1.0, -dstep);
     const double sE = ((TERMLIKE && (term & 1)) ? -1.0 : 1.0) * ldexp(1.0, Ei);
     R mlr = (R)0;
@@ -558,10 +602,26 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
       if constexpr (PRE) return opre[q];
       else return op1(cc, g);
     };
+    // tilted solve, last pass: the tilt's noise scale B (sum of the terms'
+    // maxima over the kernel's tilted mass 1 / (1 - |tilt|^2)) and the scores
+    // stored by the earlier tilts at this thread's columns
+    double lnB = 0.0;
+    float bprev[MODE == ROW_LASTT ? E : 1];
+    if constexpr (MODE == ROW_LASTT) {
+      double B = term_mu * ldexp(1.0, a.expo[a.T - 1]);
+      for (int i = 0; i + 1 < a.T; ++i) B += a.tmax[i];
+      B /= 1.0 - (a.tilt0 * a.tilt0 + a.tilt1 * a.tilt1);
+      lnB = (B > 0.0 && isfinite(B)) ? log(B) : __builtin_huge_val();
+#pragma unroll
+      for (int q = 0; q < E; ++q) {
+        const int cc = 2 * (t + P * (q >> 1)) + (q & 1);
+        bprev[q] = (!a.tfirst && col_ok(cc)) ? a.best[rowoff + cc] : -__builtin_huge_valf();
+      }
+    }
     // last term: the float64 sum of the stored terms 0..T-1 at this thread's
     // columns, in the order of the terms (as a running accumulation would)
     double ps[E];
-    if constexpr (MODE == ROW_LAST) {
+    if constexpr (LASTLIKE) {
       using V = cplx<R>;
       auto pair = [&](const R *q, int c0) -> V {
         V x = cmake<V>((R)0, (R)0);
@@ -616,13 +676,16 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
             s1 = (double)v[j].y;
           } else if constexpr (sizeof(R) == 4) {
             const float nb = (float)(-beta * 1.4426950408889634);  // exp(x) = 2^(x log2 e)
+            // the tilt's exponent a . x - A of the two columns (0 untilted)
+            const float tl0 = tilted ? (float)((ta0 * r + ta1 * c0 - tA) * 1.4426950408889634) : 0.0f;
+            const float tl1 = tilted ? tl0 + (float)(ta1 * 1.4426950408889634) : 0.0f;
             float f0 = 0.0f, f1 = 0.0f;
             auto add = [&](int y0, int y1, float lw) {
               const float d0 = (float)(r - y0);
               const float d1 = (float)(c0 - y1);
               const float q0 = d0 * d0;
-              f0 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + d1 * d1) + lw);
-              f1 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + (d1 + 1.0f) * (d1 + 1.0f)) + lw);
+              f0 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + d1 * d1) + (lw + tl0));
+              f1 += __builtin_amdgcn_exp2f(nb * __builtin_amdgcn_sqrtf(q0 + (d1 + 1.0f) * (d1 + 1.0f)) + (lw + tl1));
             };
             // the first kSrcLds sources from LDS, the rest from global memory
             // (two loops, so that no load picks its address space at run time)
@@ -632,11 +695,13 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
             s0 = f0;
             s1 = f1;
           } else {
+            const double tl0 = tilted ? ta0 * r + ta1 * c0 - tA : 0.0;
+            const double tl1 = tilted ? tl0 + ta1 : 0.0;
             auto add = [&](int y0, int y1, double lw) {
               const double d0 = (double)(r - y0);
               const double d1 = (double)(c0 - y1);
-              s0 += exp(lw - beta * sqrt(d0 * d0 + d1 * d1));
-              s1 += exp(lw - beta * sqrt(d0 * d0 + (d1 + 1) * (d1 + 1)));
+              s0 += exp((lw + tl0) - beta * sqrt(d0 * d0 + d1 * d1));
+              s1 += exp((lw + tl1) - beta * sqrt(d0 * d0 + (d1 + 1) * (d1 + 1)));
             };
             const int nl = min(a.n_src, kSrcLds);
             for (int k = 0; k < nl; ++k) add(s_src[2 * k], s_src[2 * k + 1], (double)s_lw[k]);
@@ -653,11 +718,17 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
           p1 = (last && ok1) ? fma((double)m1, sE, ps[2 * j + 1]) : 0.0;
         }
         if (last) {
-          nbad += write_S(a, rowoff + c0, p0);
-          if (a.ck_phi) a.ck_phi[rowoff + c0] = p0;
-          if (ok1) {
-            nbad += write_S(a, rowoff + c0 + 1, p1);
-            if (a.ck_phi) a.ck_phi[rowoff + c0 + 1] = p1;
+          if constexpr (MODE == ROW_LASTT) {
+            const double ax = ta0 * r + ta1 * c0 - tA;
+            nbad += write_S_tilt(a, rowoff + c0, p0, ax, lnB, bprev[2 * j]);
+            if (ok1) nbad += write_S_tilt(a, rowoff + c0 + 1, p1, ax + ta1, lnB, bprev[2 * j + 1]);
+          } else {
+            nbad += write_S(a, rowoff + c0, p0);
+            if (a.ck_phi) a.ck_phi[rowoff + c0] = p0;
+            if (ok1) {
+              nbad += write_S(a, rowoff + c0 + 1, p1);
+              if (a.ck_phi) a.ck_phi[rowoff + c0 + 1] = p1;
+            }
           }
         } else {
           (void)p0;
