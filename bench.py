@@ -19,6 +19,10 @@ Also reported on the same JSON line:
   solve3d          256^3 grid, f from 32 Gaussian blobs in [0.5, 2], one
                    source at the centre, hbar = 0.1, T = 16; FP32-scaled and
                    FP64, per-kernel classes and the dominant kernel's roofline
+  config1          the 64 x 64 bump workload (h = 1, T = 8) in FP64: latency
+  far_field        the far-field stabilised (tilted) solve of the same
+                   workload, FP64 and FP32-scaled: latency, and the fraction
+                   of the grid within tolerance of the direct sums
   backtrack        256 descent paths on the main workload's S (Section 6),
                    path points per second
   fd               the finite-difference screened Poisson system of the main
@@ -28,7 +32,15 @@ Also reported on the same JSON line:
                    its HIP-event-timed duration; `traffic` from the committed
                    FETCH_SIZE / WRITE_SIZE counter summary when it was taken
                    on the current kernel sources, else null
-  cpu_baseline     the FP64 CPU oracle timed on the host cores
+  cpu_baseline     the FP64 CPU oracle timed on the host cores (threads and
+                   CPU model stated)
+  accuracy         |S - S_oracle| / max(|S_oracle|, hbar) of every GPU result
+                   above against the oracle on the same inputs (computed in
+                   the oracle leg): the maximum on the resolvable set
+                   (Lambda <= 9 FP32, <= 16 FP64) and on the wider set
+                   (12 / 20), full-grid percentiles, the maximum per Lambda
+                   bin and the +inf counts; for the 2048^2 gradient the
+                   normwise error against the oracle's adjoint
 
 Other modes (for profiling runs):
   --pmc-run                 a copy-calibration kernel, then a few solves of
@@ -515,6 +527,42 @@ def run_config1(pk, torch, dev, steps, warmup):
     return out, (p, S.double().cpu().numpy())
 
 
+def run_far_field(pk, torch, dev, steps, warmup):
+    """The far-field stabilised solve (sweik_solve_tilted: the plain solve
+    and 8 tilt directions at 0.9 beta) on the 64 x 64 bump workload, FP64
+    and FP32-scaled: latency of one solve (median of event-timed solves)."""
+    import workloads
+    p = workloads.problem(1)
+    tilts = pk.default_tilts(8, 0.9)
+    out = {"workload": "bumps2d_64x64_T8_src1_h1", "tilts": len(tilts),
+           "tilt_strength": 0.9, "unit": "grid pts/s"}
+    results = {}
+    for prec in ("fp64", "fp32"):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        f = torch.as_tensor(p.f.astype(np.float64)).to(dev, dt)
+        src = torch.as_tensor(p.src).to(dev)
+        plan = pk.Plan(p.dims, p.h, p.hbar, p.T, len(p.src), prec)
+        ws = torch.empty(plan.tilted_workspace_bytes, dtype=torch.uint8, device=dev)
+        S = torch.empty_like(f)
+        for _ in range(max(1, warmup)):
+            plan.solve_tilted(f, src, S, ws, tilts)
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        times = []
+        for _ in range(steps):
+            e0, e1 = _events(torch, st)
+            e0.record(st)
+            plan.solve_tilted(f, src, S, ws, tilts)
+            e1.record(st)
+            e1.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        out[prec] = {"latency_ms_median": ms,
+                     "value": p.dims[0] * p.dims[1] / (ms * 1e-3)}
+        results[prec] = S.double().cpu().numpy()
+    return out, (p, results)
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -650,6 +698,24 @@ def reference_accuracy(gpu, o_main, threads):
             a["n_src"] = int(len(q.src))
             res[str(n)] = a
         out["batched"] = {"sample": "the first instance of each edge length", "fp32": res}
+    if "far_field" in gpu:
+        pf, rf = gpu["far_field"]
+        od = oracle.solve(pf.f.astype(np.float64), pf.src, pf.h, pf.hbar, pf.T, method="direct",
+                          nthreads=threads)
+        res = {"reference": "the oracle's direct sums (the ground truth at every Lambda here)"}
+        for prec, Sf in rf.items():
+            a = accuracy(Sf, od, pf.hbar, prec)
+            with np.errstate(invalid="ignore"):
+                rel = np.abs(Sf - od["S"]) / np.maximum(np.abs(od["S"]), pf.hbar)
+            a["frac_grid_within_tol"] = float(np.mean(np.nan_to_num(rel, nan=np.inf)
+                                                      <= TOLERANCE[prec]))
+            res[prec] = a
+        if "config1" in gpu:  # the plain FP64 solve of the same workload, for comparison
+            with np.errstate(invalid="ignore"):
+                rel = np.abs(gpu["config1"][1] - od["S"]) / np.maximum(np.abs(od["S"]), pf.hbar)
+            res["plain_fp64_frac_grid_within_tol"] = float(
+                np.mean(np.nan_to_num(rel, nan=np.inf) <= TOLERANCE["fp64"]))
+        out["far_field"] = res
     if "solve3d" in gpu:
         p3, r3 = gpu["solve3d"]
         o3 = oracle.solve(p3.f.astype(np.float64), p3.src, p3.h, p3.hbar, p3.T, nthreads=threads)
@@ -806,7 +872,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip fwd+bwd and batched")
-    ap.add_argument("--only", choices=["fwd_bwd", "batched", "solve3d", "backtrack", "fd"],
+    ap.add_argument("--only", choices=["fwd_bwd", "batched", "solve3d", "backtrack", "fd",
+                                       "config1", "far_field"],
                     help="run one extra section alone and print its JSON (profiling runs)")
     ap.add_argument("--pmc-run", action="store_true")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH", "WRITE"))
@@ -846,7 +913,8 @@ def main():
 
     if args.only:
         fn = {"fwd_bwd": run_fwd_bwd, "batched": run_batched, "solve3d": run_3d,
-              "backtrack": run_backtrack, "fd": run_fd, "config1": run_config1}[args.only]
+              "backtrack": run_backtrack, "fd": run_fd, "config1": run_config1,
+              "far_field": run_far_field}[args.only]
         r = fn(pk, torch, dev, args.steps, args.warmup)
         print(json.dumps(r[0] if isinstance(r, tuple) else r))
         return
@@ -907,6 +975,7 @@ def main():
     gpu["main"] = (p, S_main, S64_main) if args.precision == "fp32" else (p, None, S_main)
     if not args.no_extra:
         out["config1"], gpu["config1"] = run_config1(pk, torch, dev, max(20, args.steps), 3)
+        out["far_field"], gpu["far_field"] = run_far_field(pk, torch, dev, max(10, args.steps // 2), 2)
         out["fwd_bwd"], gpu["fwd_bwd"] = run_fwd_bwd(pk, torch, dev, max(3, args.steps // 2), 2)
         out["batched"], gpu["batched"] = run_batched(pk, torch, dev, max(3, args.steps // 4), 1)
         out["solve3d"], gpu["solve3d"] = run_3d(pk, torch, dev, max(3, args.steps // 4), 1)
