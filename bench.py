@@ -806,7 +806,7 @@ def sq_summary(paths, command, kernels=("k_row2<float, 2,", "k_col2<float, 1,"))
     term-row and column-convolution passes by default), with the ratios used
     to read them: cycles per wave waiting, VALU issue per SIMD, LDS
     instructions and bank-conflict cycles per wave."""
-    agg = {}
+    agg, dur = {}, {}
     for path in paths:
         for r in _counter_rows(path):
             name = r["Kernel_Name"]
@@ -815,13 +815,16 @@ def sq_summary(paths, command, kernels=("k_row2<float, 2,", "k_col2<float, 1,"))
                 continue
             full = name.split("(")[0]
             d = agg.setdefault(full, {}).setdefault(r["Counter_Name"], {})
-            disp = int(r["Dispatch_Id"])
+            disp = (path, int(r["Dispatch_Id"]))  # dispatch ids restart in every run
             d[disp] = d.get(disp, 0.0) + float(r["Counter_Value"])
+            dur.setdefault(full, {})[disp] = (int(r["End_Timestamp"]) -
+                                               int(r["Start_Timestamp"])) * 1e-3
     out = {}
     for name, cnt in agg.items():
         avg = {c: float(np.mean(list(v.values()))) for c, v in cnt.items()}
         n = {c: len(v) for c, v in cnt.items()}
-        row = {"dispatches": max(n.values()), "per_dispatch": avg}
+        us = float(np.median(list(dur[name].values())))
+        row = {"dispatches": max(n.values()), "median_us_under_counters": us, "per_dispatch": avg}
         w = avg.get("SQ_WAVES")
         if w:
             if "SQ_WAVE_CYCLES" in avg:
@@ -835,13 +838,16 @@ def sq_summary(paths, command, kernels=("k_row2<float, 2,", "k_col2<float, 1,"))
                 if c in avg:
                     row[c.lower().replace("sq_insts_", "insts_") + "_per_wave"] = avg[c] / w
         if "SQ_INSTS_VALU" in avg:
-            # one wave64 VALU instruction occupies a SIMD for 4 cycles (16 lanes)
+            # one wave64 VALU instruction occupies a SIMD for 4 cycles (16 lanes);
+            # 1024 SIMDs at 2.4 GHz
             row["valu_issue_us_per_simd"] = avg["SQ_INSTS_VALU"] * 4 / (256 * 4) / 2.4e3
+            row["valu_busy_frac"] = row["valu_issue_us_per_simd"] / us
         if "SQ_ACTIVE_INST_VALU" in avg:
             row["valu_active_us_per_simd"] = avg["SQ_ACTIVE_INST_VALU"] / (256 * 4) / 2.4e3
         out[name] = row
-    head = ("SQ counters of the 2D term passes (per-dispatch averages over the runs; one\n"
-            "rocprofv3 --pmc run per counter group), with derived ratios.\n"
+    head = ("SQ counters of the named kernels (per-dispatch averages over the runs; one\n"
+            "rocprofv3 --pmc run per counter group), with derived ratios; valu_busy_frac is\n"
+            "the VALU issue time per SIMD over the kernel's duration under the counters.\n"
             f"command: {command}\n")
     return head + "\n---\n" + json.dumps(out, indent=1) + "\n"
 
@@ -880,13 +886,16 @@ def main():
     ap.add_argument("--stats-summary", metavar="CSV")
     ap.add_argument("--sq-summary", nargs="+", metavar="DIR",
                     help="summarise the SQ_* counters of rocprofv3 --pmc runs")
+    ap.add_argument("--sq-kernels", default="k_row2<float, 2,;k_col2<float, 1,",
+                    help="kernel-name fragments for --sq-summary, separated by ';'")
     ap.add_argument("--command", default="", help="command text recorded in a summary")
     ap.add_argument("--out", help="summary output file")
     args = ap.parse_args()
 
     if args.traffic_summary or args.stats_summary or args.sq_summary:
         text = (traffic_summary(*args.traffic_summary, args.command) if args.traffic_summary
-                else sq_summary(args.sq_summary, args.command) if args.sq_summary
+                else sq_summary(args.sq_summary, args.command, args.sq_kernels.split(";"))
+                if args.sq_summary
                 else stats_summary(args.stats_summary, args.command))
         if args.out:
             with open(args.out, "w") as fh:
