@@ -417,6 +417,11 @@ int32_t sweik_autotune(sweik_plan plan, void *ws, size_t ws_bytes,
 
 const char *sweik_status_string(sweik_status s);
 int32_t sweik_abi_version(void);
+/* Description of the last kernel launch that failed on the calling thread
+ * (the kernel family, mode, length, schedule and the HIP error name), or ""
+ * when none has; the text behind a SWEIK_EDEVICE.  Owned by the library,
+ * valid until the thread's next failing launch. */
+const char *sweik_last_error(void);
 /* Number of HIP resources (streams, events, pinned host buffers, graph
  * executables) the library has created in this process so far.  Solves,
  * adjoints, batch solves and graph replays create none; plan and batch

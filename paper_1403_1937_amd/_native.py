@@ -115,6 +115,7 @@ def load_library():
     lib.sweik_status_string.argtypes = [C.c_int]
     lib.sweik_status_string.restype = C.c_char_p
     lib.sweik_abi_version.restype = C.c_int32
+    lib.sweik_last_error.restype = C.c_char_p
     _lib = lib
     return lib
 
@@ -124,7 +125,8 @@ def _check(rc: int, what: str):
         return
     msg = f"{what}: {STATUS.get(rc, rc)}"
     if rc == 4:
-        raise SweikError(msg)
+        detail = _lib.sweik_last_error().decode() if _lib is not None else ""
+        raise SweikError(f"{msg} ({detail})" if detail else msg)
     raise ValueError(msg)
 
 

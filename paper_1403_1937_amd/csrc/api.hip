@@ -6,6 +6,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -81,6 +82,13 @@ namespace sweik {
 // Chebyshev coefficients of sqrt(x) e^x K0(x) and sqrt(x) e^x K1(x) on
 // x >= 2 in t = 4/x - 1,
 // from its values at the Chebyshev points (discrete cosine transform).
+thread_local char g_last_error[256] = "";
+
+void note_launch_error(const char *family, int mode, int length, int E, hipError_t err) {
+  std::snprintf(g_last_error, sizeof(g_last_error), "%s (mode %d, length %d, %d elements per thread): %s",
+                family, mode, length, E, hipGetErrorName(err));
+}
+
 const ChebK0 &bessel_cheb_k0() {
   static const ChebK0 tab = [] {
     ChebK0 t;
@@ -526,7 +534,8 @@ sweik_status plan3d(sweik_plan_s *pl) {
   const size_t xl = f64 ? x_lds_bytes<double>(g.H2) : x_lds_bytes<float>(g.H2);
   const size_t c0 = f64 ? c3_lds_bytes<double>(g.M0) : c3_lds_bytes<float>(g.M0);
   const size_t c1 = f64 ? c3_lds_bytes<double>(g.M1) : c3_lds_bytes<float>(g.M1);
-  if (xl + x_lds_static(X_PHI0) > kLdsDevice || c0 + kC3LdsStatic > kLdsDevice ||
+  const size_t xs = f64 ? x_lds_static<double>(X_PHI0) : x_lds_static<float>(X_PHI0);
+  if (xl + xs > kLdsDevice || c0 + kC3LdsStatic > kLdsDevice ||
       c1 + kC3LdsStatic > kLdsDevice)
     return SWEIK_EUNSUPPORTED;
   g.nlines = g.n0 * g.n1;
@@ -1296,5 +1305,7 @@ const char *sweik_status_string(sweik_status s) {
 }
 
 int32_t sweik_abi_version(void) { return SWEIK_ABI_VERSION; }
+
+const char *sweik_last_error(void) { return g_last_error; }
 
 }  // extern "C"

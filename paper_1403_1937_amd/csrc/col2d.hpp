@@ -129,29 +129,38 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
   // Column 0 holds two real sequences, A (the rows' DC bins) and B (their
   // Nyquist bins): with F = A^ + i B^ their transforms are A^ = (F(k) +
   // conj F(-k)) / 2 and B^ = (F(k) - conj F(-k)) / 2i.  The partner values
-  // F(-k) come through LDS (every team of the work-group takes part).
-  C pv[(CONV || MODE == COL_GHATC) ? E : 1];
-  if constexpr (CONV || MODE == COL_GHATC) {
-    if (packed_wg) {
-      __syncthreads();
+  // F(-k) come through LDS (every team of the work-group takes part); the
+  // partner array lives only in the work-group holding column 0, which keeps
+  // the registers of the other work-groups' path at their minimum.
+  auto partner = [&](C (&pv)[E]) {
+    __syncthreads();
 #pragma unroll
-      for (int j = 0; j < E; ++j) line[lpad(t + P * j)] = v[j];
-      __syncthreads();
+    for (int j = 0; j < E; ++j) line[lpad(t + P * j)] = v[j];
+    __syncthreads();
 #pragma unroll
-      for (int j = 0; j < E; ++j) pv[j] = line[lpad((M0 - (t + P * j)) & (M0 - 1))];
-    }
-  }
+    for (int j = 0; j < E; ++j) pv[j] = line[lpad((M0 - (t + P * j)) & (M0 - 1))];
+  };
   if constexpr (CONV) {
-    if (packed_wg && k1 == 0) {
-      // Y = A^ Ga + i B^ Gb = F (Ga + Gb) / 2 + conj F(-k) (Ga - Gb) / 2
+    if (packed_wg) {
+      C pv[E];
+      partner(pv);
+      if (k1 == 0) {
+        // Y = A^ Ga + i B^ Gb = F (Ga + Gb) / 2 + conj F(-k) (Ga - Gb) / 2
 #pragma unroll
-      for (int j = 0; j < E; ++j) {
-        if constexpr (CPLX) {
-          const C al = cscale(cadd(gvc[j], gbc[j]), (R)0.5), de = cscale(csub(gvc[j], gbc[j]), (R)0.5);
-          v[j] = cadd(cmul(v[j], al), cmul(cconj(pv[j]), de));
-        } else {
-          const R al = (gv[j] + gb[j]) * (R)0.5, de = (gv[j] - gb[j]) * (R)0.5;
-          v[j] = cadd(cscale(v[j], al), cscale(cconj(pv[j]), de));
+        for (int j = 0; j < E; ++j) {
+          if constexpr (CPLX) {
+            const C al = cscale(cadd(gvc[j], gbc[j]), (R)0.5), de = cscale(csub(gvc[j], gbc[j]), (R)0.5);
+            v[j] = cadd(cmul(v[j], al), cmul(cconj(pv[j]), de));
+          } else {
+            const R al = (gv[j] + gb[j]) * (R)0.5, de = (gv[j] - gb[j]) * (R)0.5;
+            v[j] = cadd(cscale(v[j], al), cscale(cconj(pv[j]), de));
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < E; ++j) {
+          if constexpr (CPLX) v[j] = cmul(v[j], gvc[j]);
+          else v[j] = cscale(v[j], gv[j]);
         }
       }
     } else {
@@ -173,6 +182,8 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
       }
     }
   } else if constexpr (MODE == COL_GHATC) {
+    C pv[E];
+    if (packed_wg) partner(pv);
     if (active) {
       // scaled as Ghat below; all M0 frequencies, complex
       const R sc = (R)(1.0 / (4.0 * (double)M0 * (double)(2 * a.H1)));

@@ -58,8 +58,12 @@ template <typename R> constexpr size_t x_lds_bytes(int H) {
 constexpr int c3_cpw(int M) { return 8192 / M < 32 ? 8192 / M : 32; }
 constexpr int c3_threads(int M) { return c3_cpw(M) * (M / 16); }
 // static shared memory of an x pass (reductions, scalars, term scales; phi_0
-// also holds up to 512 sources and their weights) and of a column pass
-constexpr size_t x_lds_static(int mode) { return 1536 + (mode == X_PHI0 ? 6144 + 4096 : 0); }
+// also holds up to 512 sources and their weights), at least what the compiled
+// kernels declare (group segment of the code objects: 1184 bytes for the
+// other modes; phi_0 16640 in float, 20736 in double), and of a column pass
+template <typename R> constexpr size_t x_lds_static(int mode) {
+  return mode == X_PHI0 ? (sizeof(R) == 4 ? 17408 : 21504) : 1536;
+}
 constexpr size_t kC3LdsStatic = 512;
 template <typename R> constexpr size_t c3_lds_bytes(int M) {
   // the FFT's stage tables and one padded line per column

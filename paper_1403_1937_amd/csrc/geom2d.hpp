@@ -76,8 +76,12 @@ template <typename R> constexpr size_t row_lds_core(int H) {
          ((size_t)H + (size_t)row_stage_tw<R>(H) + (size_t)row_rpw(H) * row_line_len<R>(H));
 }
 // static shared memory of a row pass (block reductions, scalars, the term
-// scales; phi_0 also holds up to 512 sources and their weights)
-constexpr size_t row_lds_static(int mode) { return 1536 + (mode == ROW_PHI0 ? 4096 + 4096 : 0); }
+// scales; phi_0 also holds up to 512 sources and their weights), at least
+// what the compiled kernels declare (group segment of the code objects:
+// 1312 bytes for the other modes; phi_0 12912 in float, 16960 in double)
+template <typename R> constexpr size_t row_lds_static(int mode) {
+  return mode == ROW_PHI0 ? (sizeof(R) == 4 ? 13312 : 17408) : 1536;
+}
 template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
   // per staged row: gamma (R) for the forward terms (f for phi_0, the source
   // grid for its transform); previous term, gamma or f, lambda (R) +
@@ -93,7 +97,7 @@ template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
 // are used.  The full gradient's adjoint pass keeps its staging: its
 // registers allow one work-group per CU anyway.
 template <typename R> constexpr bool row_staged(int H, int mode) {
-  const size_t plain = row_lds_core<R>(H) + row_lds_static(mode);
+  const size_t plain = row_lds_core<R>(H) + row_lds_static<R>(mode);
   const size_t staged = plain + row_stage_bytes<R>(H, mode);
   return row_stage_bytes<R>(H, mode) > 0 && staged <= kLdsDevice &&
          (staged <= kLdsDevice / 2 || plain > kLdsDevice / 2 || mode == ROW_ADJ_B);
@@ -103,7 +107,7 @@ template <typename R> constexpr size_t row_lds_bytes(int H, int mode) {
 }
 // dynamic + static shared memory of a row pass fits a work-group
 template <typename R> constexpr bool row_fits(int H, int mode) {
-  return row_lds_bytes<R>(H, mode) + row_lds_static(mode) <= kLdsDevice;
+  return row_lds_bytes<R>(H, mode) + row_lds_static<R>(mode) <= kLdsDevice;
 }
 // the paired kernel-table + phi_0 pass (both passes' static shared memory,
 // the larger dynamic size) is used where two of its work-groups fit a CU
@@ -112,7 +116,7 @@ template <typename R> constexpr size_t row_init_lds_bytes(int H) {
                                                                        : row_lds_bytes<R>(H, ROW_PHI0);
 }
 template <typename R> constexpr bool row_init_pairs(int H) {
-  return row_init_lds_bytes<R>(H) + row_lds_static(ROW_GHAT) + row_lds_static(ROW_PHI0) <=
+  return row_init_lds_bytes<R>(H) + row_lds_static<R>(ROW_GHAT) + row_lds_static<R>(ROW_PHI0) <=
          kLdsDevice / 2;
 }
 // Column pass LDS: the stage twiddle tables of the length-M0 FFT (room for

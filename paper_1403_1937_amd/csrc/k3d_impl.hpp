@@ -17,7 +17,7 @@ template <typename K> static hipError_t set_lds3(K kernel, size_t bytes) {
 template <typename R, int MODE, int H>
 static hipError_t x3_one(int nblocks, hipStream_t st, const Args3<R> &a, int term) {
   constexpr size_t lds = x_lds_bytes<R>(H);
-  if constexpr (lds + x_lds_static(MODE) > kLdsDevice) {  // rejected by the planner
+  if constexpr (lds + x_lds_static<R>(MODE) > kLdsDevice) {  // rejected by the planner
     return hipErrorInvalidValue;
   } else {
     static const hipError_t attr = set_lds3(k_x3<R, MODE, H>, lds);

@@ -10,6 +10,9 @@
 
 namespace sweik {
 
+// Keeps a description of a failed launch for sweik_last_error (thread-local).
+void note_launch_error(const char *family, int mode, int length, int E, hipError_t err);
+
 template <typename R, int E>
 hipError_t launch_row2_e(int mode, int H, dim3 grid, hipStream_t st, const Args2<R> &a, int term);
 template <typename R, int E>
@@ -86,27 +89,33 @@ template <> struct RadixFour<float> {
 template <typename R>
 inline hipError_t launch_row2(int mode, int H, int E, dim3 grid, hipStream_t st,
                               const Args2<R> &a, int term) {
-  return E == 16  ? launch_row2_e<R, 16>(mode, H, grid, st, a, term)
-         : E == 8 ? launch_row2_e<R, 8>(mode, H, grid, st, a, term)
-         : E == 4 ? RadixFour<R>::row(mode, H, grid, st, a, term)
-                  : hipErrorInvalidValue;
+  const hipError_t err = E == 16  ? launch_row2_e<R, 16>(mode, H, grid, st, a, term)
+                         : E == 8 ? launch_row2_e<R, 8>(mode, H, grid, st, a, term)
+                         : E == 4 ? RadixFour<R>::row(mode, H, grid, st, a, term)
+                                  : hipErrorInvalidValue;
+  if (err != hipSuccess) note_launch_error("row pass", mode, H, E, err);
+  return err;
 }
 // the paired kernel-table + phi_0 row pass (2 nbr work-groups)
 template <typename R>
 inline hipError_t launch_row2_init(int H, int E, int nbr, hipStream_t st, const Args2<R> &ag,
                                    const Args2<R> &ap) {
-  return E == 16  ? launch_row2_init_e<R, 16>(H, nbr, st, ag, ap)
-         : E == 8 ? launch_row2_init_e<R, 8>(H, nbr, st, ag, ap)
-         : E == 4 ? RadixFour<R>::row_init(H, nbr, st, ag, ap)
-                  : hipErrorInvalidValue;
+  const hipError_t err = E == 16  ? launch_row2_init_e<R, 16>(H, nbr, st, ag, ap)
+                         : E == 8 ? launch_row2_init_e<R, 8>(H, nbr, st, ag, ap)
+                         : E == 4 ? RadixFour<R>::row_init(H, nbr, st, ag, ap)
+                                  : hipErrorInvalidValue;
+  if (err != hipSuccess) note_launch_error("paired kernel-table and phi_0 row pass", -1, H, E, err);
+  return err;
 }
 template <typename R>
 inline hipError_t launch_col2(int mode, int M0, int E, dim3 grid, hipStream_t st,
                               const Args2<R> &a) {
-  return E == 16  ? launch_col2_e<R, 16>(mode, M0, grid, st, a)
-         : E == 8 ? launch_col2_e<R, 8>(mode, M0, grid, st, a)
-         : E == 4 ? RadixFour<R>::col(mode, M0, grid, st, a)
-                  : hipErrorInvalidValue;
+  const hipError_t err = E == 16  ? launch_col2_e<R, 16>(mode, M0, grid, st, a)
+                         : E == 8 ? launch_col2_e<R, 8>(mode, M0, grid, st, a)
+                         : E == 4 ? RadixFour<R>::col(mode, M0, grid, st, a)
+                                  : hipErrorInvalidValue;
+  if (err != hipSuccess) note_launch_error("column pass", mode, M0, E, err);
+  return err;
 }
 template <typename R>
 inline hipError_t launch_row2_batch(int mode, int H, int E, int nblocks, hipStream_t st,
