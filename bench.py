@@ -22,7 +22,11 @@ Also reported on the same JSON line:
   config1          the 64 x 64 bump workload (h = 1, T = 8) in FP64: latency
   far_field        the far-field stabilised (tilted) solve of the same
                    workload, FP64 and FP32-scaled: latency, and the fraction
-                   of the grid within tolerance of the direct sums
+                   of the grid within tolerance of the direct sums; and of the
+                   2048^2 differentiation workload in FP32 (4 sources),
+                   tilted over all sources and per source: time, and the
+                   share of the FP64 oracle's resolvable set within 1e-4,
+                   against the plain solve's
   backtrack        256 descent paths on the main workload's S (Section 6),
                    path points per second
   fd               the finite-difference screened Poisson system of the main
@@ -560,6 +564,33 @@ def run_far_field(pk, torch, dev, steps, warmup):
         out[prec] = {"latency_ms_median": ms,
                      "value": p.dims[0] * p.dims[1] / (ms * 1e-3)}
         results[prec] = S.double().cpu().numpy()
+    # the 2048^2 differentiation workload's forward solve (4 sources, Lambda
+    # up to ~32) in FP32: tilted over all sources, tilted per source, plain
+    p5 = workloads.problem(5)
+    f5 = torch.as_tensor(p5.f).to(dev)
+    src5 = torch.as_tensor(p5.src).to(dev)
+    plan5 = pk.Plan(p5.dims, p5.h, p5.hbar, p5.T, len(p5.src), "fp32")
+    ws5 = torch.empty(plan5.tilted_workspace_bytes, dtype=torch.uint8, device=dev)
+    S5 = torch.empty_like(f5)
+    st = torch.cuda.current_stream()
+    big = {}
+    for name, per_source in (("tilted", False), ("tilted_per_source", True)):
+        plan5.solve_tilted(f5, src5, S5, ws5, tilts, per_source=per_source)
+        torch.cuda.synchronize()
+        e0, e1 = _events(torch, st)
+        e0.record(st)
+        for _ in range(3):
+            plan5.solve_tilted(f5, src5, S5, ws5, tilts, per_source=per_source)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms5 = e0.elapsed_time(e1) / 3
+        out[f"noise2d_2048x2048_fp32_{name}"] = {
+            "ms_per_solve": ms5, "value": p5.dims[0] * p5.dims[1] / (ms5 * 1e-3)}
+        big[name] = S5.double().cpu().numpy()
+    plan5.solve(f5, src5, S5, ws5)
+    torch.cuda.synchronize()
+    big["plain"] = S5.double().cpu().numpy()
+    results["noise2d_2048x2048_fp32"] = (p5, big)
     return out, (p, results)
 
 
@@ -703,6 +734,7 @@ def reference_accuracy(gpu, o_main, threads):
         od = oracle.solve(pf.f.astype(np.float64), pf.src, pf.h, pf.hbar, pf.T, method="direct",
                           nthreads=threads)
         res = {"reference": "the oracle's direct sums (the ground truth at every Lambda here)"}
+        big = rf.pop("noise2d_2048x2048_fp32", None)
         for prec, Sf in rf.items():
             a = accuracy(Sf, od, pf.hbar, prec)
             with np.errstate(invalid="ignore"):
@@ -715,6 +747,24 @@ def reference_accuracy(gpu, o_main, threads):
                 rel = np.abs(gpu["config1"][1] - od["S"]) / np.maximum(np.abs(od["S"]), pf.hbar)
             res["plain_fp64_frac_grid_within_tol"] = float(
                 np.mean(np.nan_to_num(rel, nan=np.inf) <= TOLERANCE["fp64"]))
+        if big is not None:
+            # reference: the FP64 oracle FFT where it resolves phi (Lambda <= 16)
+            p5, runs = big
+            o5 = oracle.solve(p5.f.astype(np.float64), p5.src, p5.h, p5.hbar, p5.T,
+                              nthreads=threads)
+            phi = o5["phi"]
+            L = np.full(phi.shape, np.inf)
+            L[phi > 0] = np.log(phi[phi > 0].max() / phi[phi > 0])
+            r64 = L <= LAMBDA_SETS["fp64"][0]
+            r = {"reference": "the FP64 oracle on its resolvable set Lambda <= 16",
+                 "frac_grid_in_set": float(r64.mean())}
+            for name, Sr in runs.items():
+                with np.errstate(invalid="ignore"):
+                    e = np.abs(Sr - o5["S"]) / np.maximum(np.abs(o5["S"]), p5.hbar)
+                e = np.nan_to_num(e, nan=np.inf)
+                r[f"{name}_frac_of_set_within_1e-4"] = float(np.mean(e[r64] <= 1e-4))
+                r[f"{name}_max_rel_on_set"] = float(e[r64].max())
+            res["noise2d_2048x2048_fp32"] = r
         out["far_field"] = res
     if "solve3d" in gpu:
         p3, r3 = gpu["solve3d"]

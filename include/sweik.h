@@ -163,24 +163,31 @@ sweik_status sweik_solve_seeded(sweik_plan plan, const void *f,
  * A = max_k (a . y_k) keeps the tilted phi_0 at most n_src.  Per point the
  * result of the tilt with the best score ln(tilted phi) - ln B is kept,
  * B = sum_i max|tilted phi_i| / (1 - |tilt|^2) being the tilt's noise scale
- * (exp(-score) is about the relative error to expect).
+ * (exp(-score) is about the relative error to expect).  A tilt gains little
+ * near sources that lie behind the one furthest along it; with per_source
+ * set the solve is split over the sources instead (at a fixed reference
+ * forcing the series is linear in phi_0, so phi = sum_k phi^(k)): each
+ * source is solved alone with all tilts, and S = -hbar ln sum_k
+ * exp(-S_k / hbar) in float64, at n_src times the cost.
  *   tilts  HOST, n_tilt pairs (tilt0, tilt1) in units of beta, each with
  *          tilt0^2 + tilt1^2 < 1 (the tilted kernel must decay); (0, 0) is
  *          the plain solve.  E.g. (0, 0) and 8 directions at 0.9.
  *   n_tilt 1 .. SWEIK_MAX_TILTS
+ *   per_source  0: one tilted solve over all sources; 1: one per source
  *   ws     device workspace of ws_bytes >= sweik_tilted_workspace_bytes(plan)
  *          (the solve's plus the tilted kernel's complex spectrum, (H1 + 1) M0
  *          complex values, and a float per point)
  *   f, src, S, stream, info as sweik_solve (no checkpoint); info counts the
  *          points that no tilt resolved (S = +inf).
- * Costs about one solve per tilt (the kernel spectrum of a tilt is complex:
+ * Costs about one solve per tilt (per source with per_source; the kernel
+ * spectrum of a tilt is complex:
  * about 1.6 x the column pass's bytes).  With T = 0 it is sweik_solve.
  * SWEIK_EINVAL for a tilt outside the unit disc or n_tilt out of range,
  * SWEIK_EUNSUPPORTED in 3D (sweik_tilted_workspace_bytes returns 0 there). */
 size_t sweik_tilted_workspace_bytes(sweik_plan plan);
 sweik_status sweik_solve_tilted(sweik_plan plan, const void *f, const int32_t *src, void *S,
-                                const double *tilts, int32_t n_tilt, void *ws, size_t ws_bytes,
-                                void *stream, sweik_info *info);
+                                const double *tilts, int32_t n_tilt, int32_t per_source, void *ws,
+                                size_t ws_bytes, void *stream, sweik_info *info);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid device allocation): sweik_solve

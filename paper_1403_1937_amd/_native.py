@@ -83,8 +83,8 @@ def load_library():
     lib.sweik_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.sweik_tilted_workspace_bytes.argtypes = [vp]
     lib.sweik_tilted_workspace_bytes.restype = sz
-    lib.sweik_solve_tilted.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), C.c_int32, vp, sz,
-                                       vp, vp]
+    lib.sweik_solve_tilted.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), C.c_int32,
+                                       C.c_int32, vp, sz, vp, vp]
     lib.sweik_noalloc_scratch_bytes.restype = sz
     lib.sweik_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     lib.sweik_solve_timed.argtypes = [vp, vp, vp, vp, vp, sz, vp, C.POINTER(C.c_float),
@@ -233,15 +233,17 @@ class Plan:
         return int(self._lib.sweik_tilted_workspace_bytes(self._h))
 
     def solve_tilted(self, f: torch.Tensor, src: torch.Tensor, S: torch.Tensor, ws: torch.Tensor,
-                     tilts, info: Optional[torch.Tensor] = None, stream=None):
+                     tilts, info: Optional[torch.Tensor] = None, stream=None,
+                     per_source: bool = False):
         """Enqueue the far-field stabilised solve (sweik_solve_tilted):
         tilts is a host sequence of (tilt0, tilt1) pairs in units of beta;
-        ws must hold tilted_workspace_bytes."""
+        per_source splits the solve over the sources; ws must hold
+        tilted_workspace_bytes."""
         t = np.ascontiguousarray(np.asarray(tilts, np.float64).reshape(-1, 2))
         _check(self._lib.sweik_solve_tilted(
             self._h, f.data_ptr(), src.data_ptr(), S.data_ptr(),
-            t.ctypes.data_as(C.POINTER(C.c_double)), len(t), ws.data_ptr(), ws.numel(),
-            _stream_ptr(stream), info.data_ptr() if info is not None else None),
+            t.ctypes.data_as(C.POINTER(C.c_double)), len(t), int(bool(per_source)), ws.data_ptr(),
+            ws.numel(), _stream_ptr(stream), info.data_ptr() if info is not None else None),
             "sweik_solve_tilted")
 
     KERNEL_CLASSES = ("prep", "ghat_row", "ghat_col", "phi0_row", "conv_col", "term_row",
@@ -361,17 +363,19 @@ def default_tilts(directions: int = 8, strength: float = 0.9):
 
 def solve_tilted(f: torch.Tensor, src, h: float, hbar: float, T: int, tilts=None,
                  ftilde_mode: str = "nu", ftilde: Optional[float] = None,
-                 return_info: bool = False, stream=None):
+                 return_info: bool = False, stream=None, per_source: bool = False):
     """Far-field stabilised S (2D): the series solved once per tilt, each
     point from the best-conditioned tilt (sweik_solve_tilted).  tilts:
-    (tilt0, tilt1) pairs in units of beta, default default_tilts()."""
+    (tilt0, tilt1) pairs in units of beta, default default_tilts();
+    per_source: one tilted solve per source, summed (n_src times the cost)."""
     _check_f(f)
     pl = _plan_for(f, len(src), h, hbar, T, ftilde_mode, ftilde)
     d_src = _src_to_device(src, pl, f.device)
     S = torch.empty_like(f)
     ws = torch.empty(pl.tilted_workspace_bytes, dtype=torch.uint8, device=f.device)
     info = torch.zeros(C.sizeof(_Info), dtype=torch.uint8, device=f.device) if return_info else None
-    pl.solve_tilted(f, d_src, S, ws, default_tilts() if tilts is None else tilts, info, stream)
+    pl.solve_tilted(f, d_src, S, ws, default_tilts() if tilts is None else tilts, info, stream,
+                    per_source=per_source)
     if return_info:
         return S, _read_info(info)
     return S

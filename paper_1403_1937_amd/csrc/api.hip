@@ -399,9 +399,13 @@ sweik_status enqueue2d(const sweik_plan_s *pl, const void *f, const int32_t *src
 // relative to its value.  The tilted passes run with radix-16 teams; the
 // term passes use the plan's row schedule.
 template <typename R>
+hipError_t enqueue2d_tilts(const sweik_plan_s *pl, Args2<R> a, const double *tilts, int n_tilt,
+                           bool count, hipStream_t st);
+
+template <typename R>
 sweik_status enqueue2d_tilted(const sweik_plan_s *pl, const void *f, const int32_t *src,
-                              void *S, const double *tilts, int n_tilt, void *ws, hipStream_t st,
-                              sweik_info *info) {
+                              void *S, const double *tilts, int n_tilt, bool per_source, void *ws,
+                              hipStream_t st, sweik_info *info) {
   const Geo2 &g = pl->g2;
   const Layout &L = pl->ws;
   char *w = (char *)ws;
@@ -411,13 +415,35 @@ sweik_status enqueue2d_tilted(const sweik_plan_s *pl, const void *f, const int32
   a.tmax = (double *)(w + L.tl_tmax);
   a.spec_neg = (cplx<R> *)(w + L.spec0);
   const long long N = (long long)g.n0 * g.n1;
-  const dim3 grow(g.nbr), gcol(g.ncw);
   hipError_t err = launch_prep<R>((const R *)f, N, a.red, (cplx<R> *)a.tw, g.lmax, st);
+  // split over the sources: one tilted solve per source (its own tilt
+  // offsets), summed as phi = sum_k exp(-S_k / hbar) in float64 (acc, the
+  // adjoint's accumulator, is free in a forward solve); the count of
+  // points without a positive phi then comes from the sum
+  const int nsrc = pl->p.n_src;
+  const int parts = per_source && nsrc > 1 ? nsrc : 1;
+  if (parts > 1) a.n_src = 1;
+  for (int k = 0; k < parts && err == hipSuccess; ++k) {
+    if (parts > 1) a.src = src + 2 * k;
+    err = enqueue2d_tilts<R>(pl, a, tilts, n_tilt, parts == 1, st);
+    if (parts > 1 && err == hipSuccess)
+      err = launch_source_lse<R>((R *)S, a.acc, N, pl->p.hbar, k == 0, k == parts - 1, info, st);
+  }
+  return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
+}
+
+// The tilts of one tilted solve (all sources of `a`, or one).
+template <typename R>
+hipError_t enqueue2d_tilts(const sweik_plan_s *pl, Args2<R> a, const double *tilts, int n_tilt,
+                           bool count, hipStream_t st) {
+  const Geo2 &g = pl->g2;
+  const dim3 grow(g.nbr), gcol(g.ncw);
+  hipError_t err = hipSuccess;
   for (int d = 0; d < n_tilt && err == hipSuccess; ++d) {
     a.tilt0 = tilts[2 * d];
     a.tilt1 = tilts[2 * d + 1];
     a.tfirst = d == 0;
-    a.tlast = d == n_tilt - 1;
+    a.tlast = count && d == n_tilt - 1;
     // the tilted kernel's spectrum: table rows m0 >= 0 into spec, m0 <= 0 into
     // spec_neg, then the complex column transforms into gc
     Args2<R> an = a;
@@ -435,7 +461,7 @@ sweik_status enqueue2d_tilted(const sweik_plan_s *pl, const void *f, const int32
                              i);
     }
   }
-  return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
+  return err;
 }
 
 template <typename R>
@@ -1017,8 +1043,8 @@ size_t sweik_tilted_workspace_bytes(sweik_plan plan) {
 }
 
 sweik_status sweik_solve_tilted(sweik_plan plan, const void *f, const int32_t *src, void *S,
-                                const double *tilts, int32_t n_tilt, void *ws, size_t ws_bytes,
-                                void *stream, sweik_info *info) {
+                                const double *tilts, int32_t n_tilt, int32_t per_source, void *ws,
+                                size_t ws_bytes, void *stream, sweik_info *info) {
   if (!plan || !f || !src || !S || !ws || !tilts) return SWEIK_EINVAL;
   if (plan->p.ndim != 2) return SWEIK_EUNSUPPORTED;
   if (n_tilt < 1 || n_tilt > SWEIK_MAX_TILTS) return SWEIK_EINVAL;
@@ -1032,8 +1058,8 @@ sweik_status sweik_solve_tilted(sweik_plan plan, const void *f, const int32_t *s
   if (plan->p.T == 0)  // phi = phi_0 in closed form: nothing for a tilt to stabilise
     return f64 ? enqueue2d<double>(plan, f, src, S, ws, nullptr, st, info)
                : enqueue2d<float>(plan, f, src, S, ws, nullptr, st, info);
-  return f64 ? enqueue2d_tilted<double>(plan, f, src, S, tilts, n_tilt, ws, st, info)
-             : enqueue2d_tilted<float>(plan, f, src, S, tilts, n_tilt, ws, st, info);
+  return f64 ? enqueue2d_tilted<double>(plan, f, src, S, tilts, n_tilt, per_source != 0, ws, st, info)
+             : enqueue2d_tilted<float>(plan, f, src, S, tilts, n_tilt, per_source != 0, ws, st, info);
 }
 
 size_t sweik_noalloc_scratch_bytes(void) { return kScratchBytes; }

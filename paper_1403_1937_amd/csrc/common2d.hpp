@@ -338,6 +338,42 @@ __device__ __forceinline__ int write_S_tilt(const A &a, size_t i, double phit, d
   return (a.tlast && !(now > -__builtin_huge_valf())) ? 1 : 0;
 }
 
+// Tilted solve split over the sources (phi = sum_k phi^(k) at a fixed
+// reference forcing: the series is linear in phi_0): acc = ln sum over the
+// sources solved so far of exp(-S_k / hbar), S_k the source's result in S
+// (+inf contributes nothing).  The last source's call writes S = -hbar acc
+// and counts the points that no source resolved.
+template <typename R>
+__global__ void __launch_bounds__(256) k_source_lse(R *__restrict__ S, double *__restrict__ acc,
+                                                    long long N, double hbar, int first, int last,
+                                                    sweik_info *info) {
+  const double ninf = -__builtin_huge_val();
+  long long nbad = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const double s = (double)S[i];
+    const double l = s < __builtin_huge_val() ? -s / hbar : ninf;  // +inf and NaN: nothing
+    double a = l;
+    if (!first) {
+      const double b = acc[i];
+      const double m = fmax(a, b);
+      a = m > ninf ? m + log1p(exp(-fabs(a - b))) : ninf;
+    }
+    if (last) {
+      const bool ok = a > ninf;
+      S[i] = ok ? (R)(-hbar * a) : (R)__builtin_huge_val();
+      nbad += ok ? 0 : 1;
+    } else {
+      acc[i] = a;
+    }
+  }
+  if (last && info) {
+    const long long nb = block_sum_ll(nbad);
+    if (threadIdx.x == 0 && nb)
+      atomicAdd((unsigned long long *)&info->n_nonpositive_phi, (unsigned long long)nb);
+  }
+}
+
 // One instance of an uneven batch: its arguments and the first work-group
 // of its share of a batched launch.
 template <typename R> struct BatchItem {

@@ -237,6 +237,15 @@ hipError_t launch_adj_full_finish(const R *f, long long N, const Params *par, co
   return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_source_lse(R *S, double *acc, long long N, double hbar, int first, int last,
+                             sweik_info *info, hipStream_t st) {
+  const long long nb = std::min<long long>((N + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_source_lse<R>, dim3((unsigned)std::max<long long>(nb, 1)), dim3(256), 0, st,
+                     S, acc, N, hbar, first, last, info);
+  return hipGetLastError();
+}
+
 template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream_t st) {
   const long long nb = std::min<long long>((N + 255) / 256, 4096);
   hipLaunchKernelGGL(k_fill<R>, dim3((unsigned)std::max<long long>(nb, 1)), dim3(256), 0, st, out,
@@ -268,6 +277,8 @@ template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream
   template hipError_t launch_adj_prep<R>(const R *, const double *, long long, double,      \
                                          double *, cplx<R> *, int, hipStream_t);            \
   template hipError_t launch_fill<R>(R *, long long, R, hipStream_t);                       \
+  template hipError_t launch_source_lse<R>(R *, double *, long long, double, int, int,      \
+                                           sweik_info *, hipStream_t);                      \
   template hipError_t launch_adj_full_finish<R>(const R *, long long, const Params *,         \
                                                 const double *, int, long long *, int, double, \
                                                 double, R *, double *, hipStream_t);           \

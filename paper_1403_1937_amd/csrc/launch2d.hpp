@@ -33,6 +33,9 @@ template <typename R>
 hipError_t launch_adj_prep(const R *dLdS, const double *phi, long long N, double hbar,
                            double *red, cplx<R> *tw, int lmax, hipStream_t st);
 template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream_t st);
+template <typename R>
+hipError_t launch_source_lse(R *S, double *acc, long long N, double hbar, int first, int last,
+                             sweik_info *info, hipStream_t st);
 // full gradient: argmin / argmax of f (kRedBlocks partials in ext, 2 x
 // kRedBlocks long long) and the scalar derivatives (see k_adj_full_finish)
 template <typename R>
