@@ -83,11 +83,11 @@ template <typename R> constexpr size_t row_lds_static(int mode) {
   return mode == ROW_PHI0 ? (sizeof(R) == 4 ? 13312 : 17408) : 1536;
 }
 template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
-  // per staged row: gamma (R) for the forward terms (f for phi_0, the source
-  // grid for its transform); previous term, gamma or f, lambda (R) +
-  // gradient (double) for the adjoint
+  // per staged row: f for phi_0 (the source grid for its transform);
+  // previous term, gamma or f, lambda (R) + gradient (double) for the
+  // adjoint.  The forward terms hold gamma in registers.
   return (size_t)row_rpw(H) * H *
-         (mode == ROW_TERM || mode == ROW_PHI0 || mode == ROW_SEED
+         (mode == ROW_PHI0 || mode == ROW_SEED
               ? sizeof(R)
               : (mode == ROW_ADJ || mode == ROW_ADJ_B) ? 3 * sizeof(R) + 8 : 0);
 }

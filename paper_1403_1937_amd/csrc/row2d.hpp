@@ -101,7 +101,7 @@ __device__ __forceinline__ void tile_store(const RowTile<R, H, E> &tile, int tid
     if (FULL || e < total) {
       int rl, k1, off;
       tile.map(e, rl, k1, off);
-      tile.base[off] = out[u];
+      store_stream(tile.base + off, out[u]);
     }
   }
 }
@@ -250,7 +250,6 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     const double *pd = nullptr;
     if (MODE == ROW_PHI0) p1 = last ? nullptr : a.f;
     if (MODE == ROW_SEED) p1 = a.gam;  // the source grid
-    if (MODE == ROW_TERM) p1 = a.gam;
     if (ADJ) {
       p1 = a.ck_terms + (size_t)(term - 1) * N;
       p2 = term > 1 ? a.gam : a.f;
@@ -371,6 +370,11 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   // exponents: forward phi_i = 2^E_i m_i; adjoint a_i = 2^e_lam (mantissa)
   int dstep = 0, Ei = 0, elam = 0;
   double term_mu = 0.0;  // ROW_LASTT: max |m_{T-1}|
+  // ROW_TERM: gamma at this thread's columns c = 2(t + P j) + e, kept in
+  // registers until the pointwise step; issued after the previous term's
+  // maxima, so that their reduction (and the inverse FFT) waits only for
+  // the loads issued before them, while gamma arrives during the FFT
+  R og[MODE == ROW_TERM ? E : 1];
   if (TERMLIKE) {
     // the previous pass's per-work-group maxima: the first four rounds are
     // read before any is folded (one wait instead of one per round)
@@ -380,6 +384,25 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     for (int u = 0; u < 4; ++u) {
       const int i = tid + u * NT;
       mr[u] = i < a.nbr ? mp[i] : 0.0;
+    }
+    if constexpr (MODE == ROW_TERM) {
+      if ((a.n1 & 1) == 0) {  // column pairs are aligned: vector loads
+        using V = cplx<R>;
+#pragma unroll
+        for (int j = 0; j < E / 2; ++j) {
+          const int c0 = 2 * (t + P * j);
+          V x = cmake<V>((R)0, (R)0);
+          if (col_ok(c0)) x = *reinterpret_cast<const V *>(a.gam + rowoff + c0);
+          og[2 * j] = x.x;
+          og[2 * j + 1] = x.y;
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < E; ++q) {
+          const int cc = 2 * (t + P * (q >> 1)) + (q & 1);
+          og[q] = col_ok(cc) ? a.gam[rowoff + cc] : (R)0;
+        }
+      }
     }
     double mu = fmax(fmax(mr[0], mr[1]), fmax(mr[2], mr[3]));
     for (int i = tid + 4 * NT; i < a.nbr; i += NT) mu = fmax(mu, mp[i]);
@@ -586,9 +609,9 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
     R mlr = (R)0;
     const int slot = TERMLIKE ? term : 0;
     R *tout = a.terms + (size_t)slot * N + rowoff;  // this term's mantissas
-    // unstaged operand (f for phi_0, else gamma) of this thread's columns,
+    // unstaged operand (f for phi_0) of this thread's columns,
     // read before the loop's stores (see kOpChunk)
-    constexpr bool PRE = !STG && (MODE == ROW_PHI0 || MODE == ROW_TERM);
+    constexpr bool PRE = !STG && MODE == ROW_PHI0;
     R opre[PRE ? E : 1];
     if constexpr (PRE) {
       const R *po = MODE == ROW_PHI0 ? a.f : a.gam;
@@ -599,7 +622,8 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
       }
     }
     auto opr = [&](int q, int cc, const R *g) -> R {
-      if constexpr (PRE) return opre[q];
+      if constexpr (MODE == ROW_TERM) return og[q];
+      else if constexpr (PRE) return opre[q];
       else return op1(cc, g);
     };
     // tilted solve, last pass: the tilt's noise scale B (sum of the terms'
@@ -734,7 +758,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
           (void)p0;
           (void)p1;
           if (even_n1)
-            *reinterpret_cast<cplx<R> *>(tout + c0) = cmake<cplx<R>>(m0, m1);
+            store_stream(reinterpret_cast<cplx<R> *>(tout + c0), cmake<cplx<R>>(m0, m1));
           else {
             tout[c0] = m0;
             if (ok1) tout[c0 + 1] = m1;
