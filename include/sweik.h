@@ -59,7 +59,10 @@ extern "C" {
 typedef enum {
   SWEIK_OK = 0,
   SWEIK_EINVAL = 1,       /* invalid argument */
-  SWEIK_EUNSUPPORTED = 2, /* valid but not supported (dimension, size) */
+  SWEIK_EUNSUPPORTED = 2, /* valid but not supported: a grid beyond the sizes
+                             below (2D n0 <= 2048, n1 <= 4096; 3D every
+                             axis <= 512), a 2D-only call on a 3D plan, or a
+                             schedule the plan cannot run */
   SWEIK_EWORKSPACE = 3,   /* workspace or checkpoint buffer too small */
   SWEIK_EDEVICE = 4,      /* a HIP call failed */
   SWEIK_ENOMEM = 5        /* host allocation failed */
@@ -110,7 +113,11 @@ typedef struct sweik_plan_s *sweik_plan;
  * HIP call.  Returns SWEIK_EINVAL for invalid fields, SWEIK_EUNSUPPORTED for
  * grids beyond the supported sizes.  Padded FFT lengths (the next power of
  * two >= 2n-1, at least 64): 2D axis 0 <= 4096 and axis 1 <= 8192; 3D
- * every axis <= 1024. */
+ * every axis <= 1024.  In grid points: 2D n0 <= 2048 and n1 <= 4096, 3D
+ * n0, n1, n2 <= 512, in both precisions.  The bound is the line length one
+ * work-group transforms in its registers and LDS (a column of 4096 points,
+ * a real row of 8192); the method itself has none, and a larger grid would
+ * need a two-level (four-step) transform along the long axis. */
 sweik_status sweik_plan_create(const sweik_problem *problem, sweik_plan *out);
 void sweik_plan_destroy(sweik_plan plan);
 
