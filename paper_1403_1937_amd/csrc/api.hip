@@ -46,42 +46,10 @@ int ilog2(int64_t x) {
   return l;
 }
 
-// e^x K0(x) for x >= 2 by the trapezoid rule on int_0^inf exp(-2x sinh^2(t/2)) dt
-// e^x K_nu(x), nu = 0 or 1: Hankel's expansion (terms (4nu^2 - (2j-1)^2) /
-// (8 j x)) for x > 60, else the trapezoid rule on the integral
-// int_0^inf exp(-2 x sinh^2(t/2)) cosh(nu t) dt
-double k_scaled_host(double x, int nu) {
-  const double pi = 3.14159265358979323846;
-  const double mu = 4.0 * nu * nu;
-  if (x > 60.0) {
-    double term = 1.0, sum = 1.0;
-    for (int j = 1; j < 40; ++j) {
-      const double nt = term * (mu - (2.0 * j - 1.0) * (2.0 * j - 1.0)) / (8.0 * j * x);
-      if (std::fabs(nt) >= std::fabs(term)) break;
-      term = nt;
-      sum += term;
-    }
-    return std::sqrt(pi / (2.0 * x)) * sum;
-  }
-  const double eta = pi * pi / (x + 45.0);
-  double sum = 0.5;
-  for (int j = 1; j < 10000; ++j) {
-    const double sh = std::sinh(0.5 * eta * j);
-    double g = std::exp(-2.0 * x * sh * sh);
-    if (nu) g *= std::cosh(eta * j);
-    sum += g;
-    if (g < 1e-18 * sum) break;
-  }
-  return eta * sum;
-}
-
 }  // namespace
 
 namespace sweik {
 
-// Chebyshev coefficients of sqrt(x) e^x K0(x) and sqrt(x) e^x K1(x) on
-// x >= 2 in t = 4/x - 1,
-// from its values at the Chebyshev points (discrete cosine transform).
 thread_local char g_last_error[256] = "";
 
 void note_launch_error(const char *family, int mode, int length, int E, hipError_t err) {
@@ -89,6 +57,9 @@ void note_launch_error(const char *family, int mode, int length, int E, hipError
                 family, mode, length, E, hipGetErrorName(err));
 }
 
+// Chebyshev coefficients of sqrt(x) e^x K0(x) and sqrt(x) e^x K1(x) on
+// x >= 2 in t = 4/x - 1, from their values at the Chebyshev points
+// (discrete cosine transform).
 const ChebK0 &bessel_cheb_k0() {
   static const ChebK0 tab = [] {
     ChebK0 t;
@@ -98,8 +69,8 @@ const ChebK0 &bessel_cheb_k0() {
     for (int j = 0; j < n; ++j) {
       const double tj = std::cos(pi * (j + 0.5) / n);
       const double x = 4.0 / (tj + 1.0);
-      g0[j] = std::sqrt(x) * k_scaled_host(x, 0);
-      g1[j] = std::sqrt(x) * k_scaled_host(x, 1);
+      g0[j] = std::sqrt(x) * k_laplace_scaled(x, 0);
+      g1[j] = std::sqrt(x) * k_laplace_scaled(x, 1);
     }
     for (int k = 0; k < kChebK0; ++k) {
       double s0 = 0.0, s1 = 0.0;

@@ -121,6 +121,37 @@ def test_ftilde_modes(ft_mode):
     assert envelope_violations(S, o, 0.05, "fp64") == 0
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
+@pytest.mark.parametrize("a", [0.5, 2.5, 10.0, 40.0, 150.0])
+def test_kernel_origin_value(a, prec, tol):
+    """The kernel's value at the origin, 1 - a K1(a) with a = beta / sqrt(pi)
+    (the ball average at the singular point), through a solve that isolates
+    it: ftilde given as 1 and f = 1 everywhere except at the single source,
+    where gamma = g, so every term at the source is phi_i = (kappa(0) g)^i
+    and S there is -hbar ln sum_i (-kappa(0) g)^i.  kappa(0) is the oracle's
+    (pinned to scipy); a spans the ascending series (a <= 2) and the
+    integral route of K1 above it."""
+    dims, y = (7, 7), (3, 3)
+    beta = a * np.sqrt(np.pi)
+    hbar = 1.0 / beta  # h = 1, ftilde = 1
+    f = np.ones(dims)
+    f[y] = np.sqrt(1.5)
+    if prec == "fp32":  # the solve sees f in float32 and stores gamma in float32
+        f[y] = float(np.float32(f[y]))
+    g = (f[y] - 1.0) * (f[y] + 1.0)
+    if prec == "fp32":
+        g = float(np.float32(g))
+    T = 6
+    k0 = oracle.kappa0(2, beta)
+    expect = -hbar * np.log(sum((-k0 * g) ** i for i in range(T + 1)))
+    S, info = _run(f, np.array([y], np.int32), 1.0, hbar, T, prec, "given", 1.0)
+    assert abs(info["beta"] - beta) <= 1e-14 * beta
+    err = abs(S[y] - expect) / hbar
+    print(f"a = {a} {prec}: kappa(0) = {k0:.16f}, S at the source {S[y]:.15e}, "
+          f"closed form {expect:.15e}, |dS|/hbar {err:.1e}", flush=True)
+    assert err <= tol
+
+
 def test_constant_forcing_closed_form_gpu():
     """f = c => phi = phi_0 exactly: S = -hbar ln sum_k exp(-c|x-y_k|/hbar)."""
     dims = (50, 70)
