@@ -537,8 +537,8 @@ sweik_status plan3d(sweik_plan_s *pl) {
     return SWEIK_EUNSUPPORTED;
   g.nlines = g.n0 * g.n1;
   g.nbx = (g.nlines + x_lpw(g.H2) - 1) / x_lpw(g.H2);
-  g.ncb0 = g.H2 / c3_cpw(g.M0);
-  g.ncb1 = g.H2 / c3_cpw(g.M1);
+  g.ncb0 = g.H2 / (f64 ? c3_cpw<double>(g.M0) : c3_cpw<float>(g.M0));
+  g.ncb1 = g.H2 / (f64 ? c3_cpw<double>(g.M1) : c3_cpw<float>(g.M1));
   pl->g2.erow = pl->g2.ecol = 16;  // the 3D passes have one schedule
   pl->g2.phi0_fft = 0;
   g.lmax = std::max(2 * g.M2, std::max(g.M0, g.M1));

@@ -37,7 +37,7 @@ template <typename R, int MODE, int M, bool FULL>
 __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned char *smem_raw,
                                         const int g) {
   using C = cplx<R>;
-  constexpr int P = M / 16, CPW = c3_cpw(M), NT = c3_threads(M), LL = lds_line_len(M);
+  constexpr int P = M / 16, CPW = c3_cpw<R>(M), NT = c3_threads<R>(M), LL = lds_line_len(M);
   constexpr int HM = M / 2;
   C *twl = reinterpret_cast<C *>(smem_raw);  // stage twiddle tables
   C *lines = twl + stage_tw_len(M, 16);

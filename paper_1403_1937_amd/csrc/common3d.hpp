@@ -54,9 +54,18 @@ template <typename R> constexpr size_t x_lds_bytes(int H) {
 }
 // column passes: CPW neighbouring k2 columns per group, one team of M/16
 // threads per column, threads ordered column-fastest so that a wave reads
-// CPW contiguous spectrum entries per row
-constexpr int c3_cpw(int M) { return 8192 / M < 32 ? 8192 / M : 32; }
-constexpr int c3_threads(int M) { return c3_cpw(M) * (M / 16); }
+// CPW contiguous spectrum entries per row.  A work-group's lines hold 8192
+// float (4096 double) complex values: about 72 KB of LDS in either
+// precision, two work-groups per CU (with 8192 double values one work-group
+// filled a CU, and its load, FFT and store phases ran strictly one after
+// the other: 256^3 FP64 16.1 -> 13.0 ms; float with 4096 values, four
+// work-groups per CU, measured slower, 6.6 -> 7.0 ms)
+template <typename R> constexpr int c3_cpw(int M) {
+  return (sizeof(R) == 4 ? 8192 : 4096) / M < (sizeof(R) == 4 ? 32 : 16)
+             ? (sizeof(R) == 4 ? 8192 : 4096) / M
+             : (sizeof(R) == 4 ? 32 : 16);
+}
+template <typename R> constexpr int c3_threads(int M) { return c3_cpw<R>(M) * (M / 16); }
 // static shared memory of an x pass (reductions, scalars, term scales; phi_0
 // also holds up to 512 sources and their weights), at least what the compiled
 // kernels declare (group segment of the code objects: 1184 bytes for the
@@ -67,7 +76,7 @@ template <typename R> constexpr size_t x_lds_static(int mode) {
 constexpr size_t kC3LdsStatic = 512;
 template <typename R> constexpr size_t c3_lds_bytes(int M) {
   // the FFT's stage tables and one padded line per column
-  return sizeof(R) * 2 * ((size_t)stage_tw_len(M, 16) + (size_t)c3_cpw(M) * lds_line_len(M));
+  return sizeof(R) * 2 * ((size_t)stage_tw_len(M, 16) + (size_t)c3_cpw<R>(M) * lds_line_len(M));
 }
 
 template <typename R> struct Args3 {

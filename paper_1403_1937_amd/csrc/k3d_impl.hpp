@@ -58,7 +58,7 @@ static hipError_t c3_one(int nblocks, hipStream_t st, const Args3<R> &a, int ter
   } else {
     static const hipError_t attr = set_lds3(k_c3<R, MODE, M>, lds);
     if (attr != hipSuccess) return attr;
-    hipLaunchKernelGGL((k_c3<R, MODE, M>), dim3(nblocks), dim3(c3_threads(M)), lds, st, a,
+    hipLaunchKernelGGL((k_c3<R, MODE, M>), dim3(nblocks), dim3(c3_threads<R>(M)), lds, st, a,
                        term);
     return hipGetLastError();
   }

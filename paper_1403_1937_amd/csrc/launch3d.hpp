@@ -12,7 +12,7 @@ namespace sweik {
 template <typename R>
 hipError_t launch_x3(int mode, int H, int nblocks, hipStream_t st, const Args3<R> &a, int term);
 // column pass: mode C3Mode, transform length M (M1 for the y modes, M0 for
-// the z modes), nblocks = planes x H2 / c3_cpw(M)
+// the z modes), nblocks = planes x H2 / c3_cpw<R>(M)
 template <typename R>
 hipError_t launch_c3(int mode, int M, int nblocks, hipStream_t st, const Args3<R> &a, int term);
 
