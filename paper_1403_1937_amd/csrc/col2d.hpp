@@ -177,7 +177,7 @@ __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned c
         const int rho = t + P * j;
         if (FULL || rho < spec_rows) {
           const int b = rho / RB;
-          store_stream(col + b * cstride + (rho - b * RB), v[j]);
+          col[b * cstride + (rho - b * RB)] = v[j];
         }
       }
     }

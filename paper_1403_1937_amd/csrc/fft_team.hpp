@@ -35,21 +35,6 @@ template <> struct real_of<float2> { using type = float; };
 template <> struct real_of<double2v> { using type = double; };
 template <typename C> using real_t = typename real_of<C>::type;
 
-// Store of a pass output that only a later launch reads: non-temporal, so
-// that it streams to memory during the pass instead of waiting in L2 as a
-// dirty line for the write-back at the end of the launch (measured 1-2 %
-// faster on the 2D passes; no gain on the 3D ones, which keep plain stores).
-__device__ __forceinline__ void store_stream(float2 *p, float2 v) {
-  typedef float f2v __attribute__((ext_vector_type(2)));
-  f2v w;
-  w.x = v.x;
-  w.y = v.y;
-  __builtin_nontemporal_store(w, reinterpret_cast<f2v *>(p));
-}
-__device__ __forceinline__ void store_stream(double2v *p, double2v v) {
-  __builtin_nontemporal_store(v, p);
-}
-
 template <typename C> __device__ __forceinline__ C cmake(real_t<C> a, real_t<C> b) {
   C c;
   c.x = a;

@@ -101,7 +101,7 @@ __device__ __forceinline__ void tile_store(const RowTile<R, H, E> &tile, int tid
     if (FULL || e < total) {
       int rl, k1, off;
       tile.map(e, rl, k1, off);
-      store_stream(tile.base + off, out[u]);
+      tile.base[off] = out[u];
     }
   }
 }
@@ -758,7 +758,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
           (void)p0;
           (void)p1;
           if (even_n1)
-            store_stream(reinterpret_cast<cplx<R> *>(tout + c0), cmake<cplx<R>>(m0, m1));
+            *reinterpret_cast<cplx<R> *>(tout + c0) = cmake<cplx<R>>(m0, m1);
           else {
             tout[c0] = m0;
             if (ok1) tout[c0 + 1] = m1;
