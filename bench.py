@@ -20,8 +20,11 @@ Also reported on the same JSON line:
                    source at the centre, hbar = 0.1, T = 16; FP32-scaled and
                    FP64, per-kernel classes and the dominant kernel's roofline
   config1          the 64 x 64 bump workload (h = 1, T = 8) in FP64: latency
+                   of an eager solve and of a replay of the solve captured in
+                   a HIP graph
   far_field        the far-field stabilised (tilted) solve of the same
-                   workload, FP64 and FP32-scaled: latency, and the fraction
+                   workload, FP64 and FP32-scaled: latency (eager and graph
+                   replay), and the fraction
                    of the grid within tolerance of the direct sums; and of the
                    2048^2 differentiation workload in FP32 (4 sources),
                    tilted over all sources and per source: time, and the
@@ -498,6 +501,35 @@ def run_batched(pk, torch, dev, steps, warmup):
     return out, sample
 
 
+def graph_latency(torch, fn, out, steps):
+    """Capture fn (an enqueue of one solve into caller-owned buffers) into a
+    HIP graph and time `steps` replays one by one with events: the solve's
+    latency without the host's per-launch cost.  Returns (median ms, whether
+    the replayed result equals the eager one bit for bit)."""
+    fn()
+    torch.cuda.synchronize()
+    ref = out.clone()
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(graph):
+            fn()
+    torch.cuda.current_stream().wait_stream(side)
+    st = torch.cuda.current_stream()
+    times = []
+    for _ in range(steps):
+        e0, e1 = _events(torch, st)
+        e0.record(st)
+        graph.replay()
+        e1.record(st)
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1))
+    same = bool(torch.equal(out, ref))
+    del graph
+    return float(np.median(times)), same
+
+
 def run_config1(pk, torch, dev, steps, warmup):
     """The plain method on the 64 x 64 bump workload (h = 1, hbar = 0.5,
     one source at the centre, T = 8) in FP64: a few hundred kilobytes per
@@ -524,11 +556,17 @@ def run_config1(pk, torch, dev, steps, warmup):
         e1.synchronize()
         times.append(e0.elapsed_time(e1))
     ms = float(np.median(times))
+    S_host = S.double().cpu().numpy()
+    gms, same = graph_latency(torch, lambda: plan.solve(f, src, S, ws), S, steps)
     out = {"workload": "bumps2d_64x64_T8_src1_h1", "precision": "fp64",
            "latency_ms_median": ms, "latency_ms_min": float(min(times)),
            "value": p.dims[0] * p.dims[1] / (ms * 1e-3), "unit": "grid pts/s",
-           "launches_per_solve": 4 + 2 * p.T, "bound": "launch latency"}
-    return out, (p, S.double().cpu().numpy())
+           "launches_per_solve": 4 + 2 * p.T,
+           "bound": "pass latency: at 64^2 a row pass is one work-group (all 64 rows) and "
+                    "every pass a chain of dependent loads, LDS exchanges and barriers "
+                    "(about 8-10 us each); a graph replay takes as long as the eager solve",
+           "graph_replay_latency_ms_median": gms, "graph_replay_equals_eager": same}
+    return out, (p, S_host)
 
 
 def run_far_field(pk, torch, dev, steps, warmup):
@@ -561,9 +599,12 @@ def run_far_field(pk, torch, dev, steps, warmup):
             e1.synchronize()
             times.append(e0.elapsed_time(e1))
         ms = float(np.median(times))
-        out[prec] = {"latency_ms_median": ms,
-                     "value": p.dims[0] * p.dims[1] / (ms * 1e-3)}
         results[prec] = S.double().cpu().numpy()
+        gms, same = graph_latency(torch, lambda: plan.solve_tilted(f, src, S, ws, tilts), S,
+                                  steps)
+        out[prec] = {"latency_ms_median": ms,
+                     "value": p.dims[0] * p.dims[1] / (ms * 1e-3),
+                     "graph_replay_latency_ms_median": gms, "graph_replay_equals_eager": same}
     # the 2048^2 differentiation workload's forward solve (4 sources, Lambda
     # up to ~32) in FP32: tilted over all sources, tilted per source, plain
     p5 = workloads.problem(5)
