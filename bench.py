@@ -584,7 +584,7 @@ def run_far_field(pk, torch, dev, steps, warmup):
         f = torch.as_tensor(p.f.astype(np.float64)).to(dev, dt)
         src = torch.as_tensor(p.src).to(dev)
         plan = pk.Plan(p.dims, p.h, p.hbar, p.T, len(p.src), prec)
-        ws = torch.empty(plan.tilted_workspace_bytes, dtype=torch.uint8, device=dev)
+        ws = torch.empty(plan.tilted_workspace_bytes(len(tilts)), dtype=torch.uint8, device=dev)
         S = torch.empty_like(f)
         for _ in range(max(1, warmup)):
             plan.solve_tilted(f, src, S, ws, tilts)
@@ -611,7 +611,7 @@ def run_far_field(pk, torch, dev, steps, warmup):
     f5 = torch.as_tensor(p5.f).to(dev)
     src5 = torch.as_tensor(p5.src).to(dev)
     plan5 = pk.Plan(p5.dims, p5.h, p5.hbar, p5.T, len(p5.src), "fp32")
-    ws5 = torch.empty(plan5.tilted_workspace_bytes, dtype=torch.uint8, device=dev)
+    ws5 = torch.empty(plan5.tilted_workspace_bytes(len(tilts)), dtype=torch.uint8, device=dev)
     S5 = torch.empty_like(f5)
     st = torch.cuda.current_stream()
     big = {}

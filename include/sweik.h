@@ -181,17 +181,24 @@ sweik_status sweik_solve_seeded(sweik_plan plan, const void *f,
  *          the plain solve.  E.g. (0, 0) and 8 directions at 0.9.
  *   n_tilt 1 .. SWEIK_MAX_TILTS
  *   per_source  0: one tilted solve over all sources; 1: one per source
- *   ws     device workspace of ws_bytes >= sweik_tilted_workspace_bytes(plan)
- *          (the solve's plus the tilted kernel's complex spectrum, (H1 + 1) M0
- *          complex values, and a float per point)
+ *   ws     device workspace of ws_bytes >= sweik_tilted_workspace_bytes(plan,
+ *          n_tilt): the solve's, plus per tilt its own spectra, complex
+ *          kernel spectrum ((H1 + 1) M0 complex values), T stored terms, S
+ *          and a float score per point (about 9 N values of the plan's
+ *          precision plus T N per tilt), plus the tilts' work lists
  *   f, src, S, stream, info as sweik_solve (no checkpoint); info counts the
- *          points that no tilt resolved (S = +inf).
- * Costs about one solve per tilt (per source with per_source; the kernel
- * spectrum of a tilt is complex:
- * about 1.6 x the column pass's bytes).  With T = 0 it is sweik_solve.
+ *          points that no tilt resolved (S = +inf) and reports the first
+ *          tilt's term scales.
+ * The tilts run side by side: each pass is one launch over the work-groups
+ * of every tilt, so the launches do not grow with n_tilt; the work grows
+ * as about one solve per tilt (per source with per_source; the kernel
+ * spectrum of a tilt is complex: about 1.6 x the column pass's bytes).
+ * With T = 0 it is sweik_solve.  Enqueues kernels only (no copies, no
+ * memset): it can be captured into a HIP graph.
  * SWEIK_EINVAL for a tilt outside the unit disc or n_tilt out of range,
- * SWEIK_EUNSUPPORTED in 3D (sweik_tilted_workspace_bytes returns 0 there). */
-size_t sweik_tilted_workspace_bytes(sweik_plan plan);
+ * SWEIK_EUNSUPPORTED in 3D (sweik_tilted_workspace_bytes returns 0 there
+ * and for n_tilt out of range). */
+size_t sweik_tilted_workspace_bytes(sweik_plan plan, int32_t n_tilt);
 sweik_status sweik_solve_tilted(sweik_plan plan, const void *f, const int32_t *src, void *S,
                                 const double *tilts, int32_t n_tilt, int32_t per_source, void *ws,
                                 size_t ws_bytes, void *stream, sweik_info *info);

@@ -81,7 +81,7 @@ def load_library():
     lib.sweik_solve.argtypes = [vp, vp, vp, vp, vp, sz, vp, vp, vp]
     lib.sweik_solve_seeded.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp, vp, vp]
     lib.sweik_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
-    lib.sweik_tilted_workspace_bytes.argtypes = [vp]
+    lib.sweik_tilted_workspace_bytes.argtypes = [vp, C.c_int32]
     lib.sweik_tilted_workspace_bytes.restype = sz
     lib.sweik_solve_tilted.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), C.c_int32,
                                        C.c_int32, vp, sz, vp, vp]
@@ -228,9 +228,9 @@ class Plan:
             _stream_ptr(stream), info.data_ptr() if info is not None else None),
             "sweik_solve")
 
-    @property
-    def tilted_workspace_bytes(self) -> int:
-        return int(self._lib.sweik_tilted_workspace_bytes(self._h))
+    def tilted_workspace_bytes(self, n_tilt: int) -> int:
+        """Workspace bytes of a tilted solve with n_tilt tilts (0 in 3D)."""
+        return int(self._lib.sweik_tilted_workspace_bytes(self._h, int(n_tilt)))
 
     def solve_tilted(self, f: torch.Tensor, src: torch.Tensor, S: torch.Tensor, ws: torch.Tensor,
                      tilts, info: Optional[torch.Tensor] = None, stream=None,
@@ -238,7 +238,7 @@ class Plan:
         """Enqueue the far-field stabilised solve (sweik_solve_tilted):
         tilts is a host sequence of (tilt0, tilt1) pairs in units of beta;
         per_source splits the solve over the sources; ws must hold
-        tilted_workspace_bytes."""
+        tilted_workspace_bytes(len(tilts))."""
         t = np.ascontiguousarray(np.asarray(tilts, np.float64).reshape(-1, 2))
         _check(self._lib.sweik_solve_tilted(
             self._h, f.data_ptr(), src.data_ptr(), S.data_ptr(),
@@ -372,10 +372,10 @@ def solve_tilted(f: torch.Tensor, src, h: float, hbar: float, T: int, tilts=None
     pl = _plan_for(f, len(src), h, hbar, T, ftilde_mode, ftilde)
     d_src = _src_to_device(src, pl, f.device)
     S = torch.empty_like(f)
-    ws = torch.empty(pl.tilted_workspace_bytes, dtype=torch.uint8, device=f.device)
+    tilts = default_tilts() if tilts is None else tilts
+    ws = torch.empty(pl.tilted_workspace_bytes(len(tilts)), dtype=torch.uint8, device=f.device)
     info = torch.zeros(C.sizeof(_Info), dtype=torch.uint8, device=f.device) if return_info else None
-    pl.solve_tilted(f, d_src, S, ws, default_tilts() if tilts is None else tilts, info, stream,
-                    per_source=per_source)
+    pl.solve_tilted(f, d_src, S, ws, tilts, info, stream, per_source=per_source)
     if return_info:
         return S, _read_info(info)
     return S

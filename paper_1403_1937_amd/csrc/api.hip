@@ -194,11 +194,6 @@ sweik_status plan2d(sweik_plan_s *pl) {
   L.fg_part = take(sizeof(double) * kGradSlots * g.nbr);
   L.fg_ext = take(sizeof(long long) * 2 * kRedBlocks);
   L.fg_total = off;
-  off = L.total;
-  L.tl_gc = take((size_t)csz * (g.ldk + 1) * g.M0);
-  L.tl_best = take(sizeof(float) * N);
-  L.tl_tmax = take(sizeof(double) * (size_t)(p.T + 2));
-  L.tl_total = off;
   off = 0;
   L.ck_expo = take(sizeof(int) * (SWEIK_MAX_TERMS + 1));
   L.ck_par = take(sizeof(Params));
@@ -363,76 +358,102 @@ sweik_status enqueue2d(const sweik_plan_s *pl, const void *f, const int32_t *src
   return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
 
+// Workspace of a tilted solve with n_tilt tilts: the plan's solve workspace
+// (shared by the tilts: reductions of f, twiddles, gamma, and the float64
+// accumulator of the per-source split), then one slice per tilt, then the
+// tilts' three work lists.
+struct TiltWs {
+  TiltSlice sl;
+  size_t slices, items, total;
+};
+TiltWs tilt_ws(const sweik_plan_s *pl, int n_tilt) {
+  const Geo2 &g = pl->g2;
+  const sweik_problem &p = pl->p;
+  const size_t esz = p.prec == SWEIK_F64 ? 8 : 4, csz = 2 * esz;
+  const size_t N = (size_t)g.n0 * g.n1;
+  TiltWs t;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  t.sl.spec = take(csz * g.nb * g.ldk * g.RB);
+  t.sl.spec_neg = take(csz * g.nb * g.ldk * g.RB);
+  t.sl.gc = take(csz * (g.ldk + 1) * g.M0);
+  t.sl.terms = take(esz * N * (size_t)p.T);
+  t.sl.mu = take(sizeof(double) * (size_t)(p.T + 1) * g.nbr);
+  t.sl.expo = take(sizeof(int) * (SWEIK_MAX_TERMS + 1));
+  t.sl.tmax = take(sizeof(double) * (size_t)(p.T + 2));
+  t.sl.S = take(esz * N);
+  t.sl.best = take(sizeof(float) * N);
+  t.sl.bytes = off;
+  t.slices = align256(pl->ws.total);
+  t.items = align256(t.slices + (size_t)n_tilt * t.sl.bytes);
+  const size_t item = p.prec == SWEIK_F64 ? sizeof(BatchItem<double>) : sizeof(BatchItem<float>);
+  t.total = align256(t.items + 3 * (size_t)n_tilt * item);
+  return t;
+}
+
 // Far-field stabilised solve (2D): the series of Table 1 once per tilt a =
 // beta (tilts[2d], tilts[2d+1]), each on phi_i exp(a . x) with the kernel
-// kappa(m) exp(a . m) (the same convolution, exactly, in tilted variables);
-// per point the last pass keeps the tilt whose rounding noise is smallest
-// relative to its value.  The tilted passes run with radix-16 teams; the
-// term passes use the plan's row schedule.
-template <typename R>
-hipError_t enqueue2d_tilts(const sweik_plan_s *pl, Args2<R> a, const double *tilts, int n_tilt,
-                           bool count, hipStream_t st);
-
+// kappa(m) exp(a . m) (the same convolution, exactly, in tilted variables).
+// The tilts run side by side: every pass is one launch over the work-groups
+// of all tilts (an uneven batch whose work lists k_tilt_items forms on the
+// device), each tilt in its own workspace slice; per point k_tilt_select
+// then keeps the tilt whose rounding noise is smallest relative to its
+// value.  The tilted passes run with radix-16 teams; the term passes use the
+// plan's row schedule.  With per_source the solve is split over the sources
+// (one tilted solve per source, its own tilt offsets), summed as phi = sum_k
+// exp(-S_k / hbar) in float64 (acc, the adjoint's accumulator, is free in a
+// forward solve); the count of points without a positive phi then comes
+// from the sum.
 template <typename R>
 sweik_status enqueue2d_tilted(const sweik_plan_s *pl, const void *f, const int32_t *src,
                               void *S, const double *tilts, int n_tilt, bool per_source, void *ws,
                               hipStream_t st, sweik_info *info) {
   const Geo2 &g = pl->g2;
-  const Layout &L = pl->ws;
-  char *w = (char *)ws;
+  const TiltWs tw = tilt_ws(pl, n_tilt);
+  unsigned char *w = (unsigned char *)ws;
   Args2<R> a = make_args2<R>(pl, f, src, S, ws, nullptr, info);
-  a.gc = (cplx<R> *)(w + L.tl_gc);
-  a.best = (float *)(w + L.tl_best);
-  a.tmax = (double *)(w + L.tl_tmax);
-  a.spec_neg = (cplx<R> *)(w + L.spec0);
+  TiltTable tt;
+  for (int d = 0; d < SWEIK_MAX_TILTS; ++d) {
+    tt.t[2 * d] = d < n_tilt ? tilts[2 * d] : 0.0;
+    tt.t[2 * d + 1] = d < n_tilt ? tilts[2 * d + 1] : 0.0;
+  }
+  unsigned char *slices = w + tw.slices;
+  BatchItem<R> *rows = reinterpret_cast<BatchItem<R> *>(w + tw.items);
+  BatchItem<R> *negs = rows + n_tilt, *cols = negs + n_tilt;
   const long long N = (long long)g.n0 * g.n1;
+  const int nrow = n_tilt * g.nbr, ncol = n_tilt * g.ncw;
   hipError_t err = launch_prep<R>((const R *)f, N, a.red, (cplx<R> *)a.tw, g.lmax, st);
-  // split over the sources: one tilted solve per source (its own tilt
-  // offsets), summed as phi = sum_k exp(-S_k / hbar) in float64 (acc, the
-  // adjoint's accumulator, is free in a forward solve); the count of
-  // points without a positive phi then comes from the sum
   const int nsrc = pl->p.n_src;
   const int parts = per_source && nsrc > 1 ? nsrc : 1;
   if (parts > 1) a.n_src = 1;
   for (int k = 0; k < parts && err == hipSuccess; ++k) {
     if (parts > 1) a.src = src + 2 * k;
-    err = enqueue2d_tilts<R>(pl, a, tilts, n_tilt, parts == 1, st);
+    err = launch_tilt_items<R>(a, tt, n_tilt, slices, tw.sl, rows, negs, cols, st);
+    // the tilted kernels' spectra: table rows m0 >= 0 into spec, m0 <= 0
+    // into spec_neg, then the complex column transforms into gc
+    if (err == hipSuccess) err = launch_row2_batch<R>(ROW_GHATT, g.H1, 16, nrow, st, rows, n_tilt, 0);
+    if (err == hipSuccess) err = launch_row2_batch<R>(ROW_GHATT, g.H1, 16, nrow, st, negs, n_tilt, 0);
+    if (err == hipSuccess) err = launch_col2_batch<R>(COL_GHATC, g.M0, 16, ncol, st, cols, n_tilt);
+    if (err == hipSuccess)
+      err = launch_row2_batch<R>(ROW_PHI0, g.H1, g.erow, nrow, st, rows, n_tilt, 0);
+    for (int i = 1; i <= pl->p.T && err == hipSuccess; ++i) {
+      err = launch_col2_batch<R>(COL_CONVC, g.M0, 16, ncol, st, cols, n_tilt);
+      const bool lastp = i == pl->p.T;
+      if (err == hipSuccess)
+        err = launch_row2_batch<R>(lastp ? ROW_LASTT : ROW_TERM, g.H1, lastp ? 16 : g.erow, nrow,
+                                   st, rows, n_tilt, i);
+    }
+    if (err == hipSuccess)
+      err = launch_tilt_select<R>((R *)S, slices, tw.sl, n_tilt, N, parts == 1, info, st);
     if (parts > 1 && err == hipSuccess)
       err = launch_source_lse<R>((R *)S, a.acc, N, pl->p.hbar, k == 0, k == parts - 1, info, st);
   }
-  return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
-}
-
-// The tilts of one tilted solve (all sources of `a`, or one).
-template <typename R>
-hipError_t enqueue2d_tilts(const sweik_plan_s *pl, Args2<R> a, const double *tilts, int n_tilt,
-                           bool count, hipStream_t st) {
-  const Geo2 &g = pl->g2;
-  const dim3 grow(g.nbr), gcol(g.ncw);
-  hipError_t err = hipSuccess;
-  for (int d = 0; d < n_tilt && err == hipSuccess; ++d) {
-    a.tilt0 = tilts[2 * d];
-    a.tilt1 = tilts[2 * d + 1];
-    a.tfirst = d == 0;
-    a.tlast = count && d == n_tilt - 1;
-    // the tilted kernel's spectrum: table rows m0 >= 0 into spec, m0 <= 0 into
-    // spec_neg, then the complex column transforms into gc
-    Args2<R> an = a;
-    an.tsign = -1;
-    an.spec = a.spec_neg;
-    err = launch_row2<R>(ROW_GHATT, g.H1, 16, grow, st, a, 0);
-    if (err == hipSuccess) err = launch_row2<R>(ROW_GHATT, g.H1, 16, grow, st, an, 0);
-    if (err == hipSuccess) err = launch_col2<R>(COL_GHATC, g.M0, 16, gcol, st, a);
-    if (err == hipSuccess) err = launch_row2<R>(ROW_PHI0, g.H1, g.erow, grow, st, a, 0);
-    for (int i = 1; i <= pl->p.T && err == hipSuccess; ++i) {
-      err = launch_col2<R>(COL_CONVC, g.M0, 16, gcol, st, a);
-      const bool lastp = i == pl->p.T;
-      if (err == hipSuccess)
-        err = launch_row2<R>(lastp ? ROW_LASTT : ROW_TERM, g.H1, lastp ? 16 : g.erow, grow, st, a,
-                             i);
-    }
-  }
-  return err;
+  if (err != hipSuccess) return SWEIK_EDEVICE;
+  return SWEIK_OK;
 }
 
 template <typename R>
@@ -1009,8 +1030,9 @@ sweik_status sweik_solve(sweik_plan plan, const void *f, const int32_t *src, voi
   return sweik_solve_seeded(plan, f, src, nullptr, S, ws, ws_bytes, ckpt, stream, info);
 }
 
-size_t sweik_tilted_workspace_bytes(sweik_plan plan) {
-  return (plan && plan->p.ndim == 2) ? plan->ws.tl_total : 0;
+size_t sweik_tilted_workspace_bytes(sweik_plan plan, int32_t n_tilt) {
+  if (!plan || plan->p.ndim != 2 || n_tilt < 1 || n_tilt > SWEIK_MAX_TILTS) return 0;
+  return tilt_ws(plan, n_tilt).total;
 }
 
 sweik_status sweik_solve_tilted(sweik_plan plan, const void *f, const int32_t *src, void *S,
@@ -1023,7 +1045,7 @@ sweik_status sweik_solve_tilted(sweik_plan plan, const void *f, const int32_t *s
     const double t0 = tilts[2 * d], t1 = tilts[2 * d + 1];
     if (!std::isfinite(t0) || !std::isfinite(t1) || !(t0 * t0 + t1 * t1 < 1.0)) return SWEIK_EINVAL;
   }
-  if (ws_bytes < plan->ws.tl_total) return SWEIK_EWORKSPACE;
+  if (ws_bytes < tilt_ws(plan, n_tilt).total) return SWEIK_EWORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   const bool f64 = plan->p.prec == SWEIK_F64;
   if (plan->p.T == 0)  // phi = phi_0 in closed form: nothing for a tilt to stabilise

@@ -382,6 +382,89 @@ template <typename R> struct BatchItem {
   int pad_;
 };
 
+// Far-field stabilised solve, all tilts in one launch per pass: each tilt
+// owns a slice of the workspace (its spectra, kernel spectrum, terms,
+// scales, result and scores) at these byte offsets, and the passes run as
+// uneven batches over the tilts' work lists.
+struct TiltTable {
+  double t[2 * SWEIK_MAX_TILTS];  // (tilt0, tilt1) per tilt, in units of beta
+};
+struct TiltSlice {
+  size_t spec, spec_neg, gc, terms, mu, expo, tmax, S, best, bytes;
+};
+
+// The work lists of the tilts' passes from the solve's arguments: rows and
+// cols for the row and column passes, negs for the kernel-table rows
+// m0 <= 0 (into spec_neg).  Every tilt stores its own S and scores (tfirst);
+// only tilt 0 reports into info, and k_tilt_select counts.
+template <typename R>
+__global__ void __launch_bounds__(64) k_tilt_items(Args2<R> base, TiltTable tt, int n_tilt,
+                                                   unsigned char *slices, TiltSlice sl,
+                                                   BatchItem<R> *rows, BatchItem<R> *negs,
+                                                   BatchItem<R> *cols) {
+  const int d = threadIdx.x;
+  if (d >= n_tilt) return;
+  unsigned char *s = slices + (size_t)d * sl.bytes;
+  Args2<R> a = base;
+  a.spec = reinterpret_cast<cplx<R> *>(s + sl.spec);
+  a.spec_neg = reinterpret_cast<cplx<R> *>(s + sl.spec_neg);
+  a.gc = reinterpret_cast<cplx<R> *>(s + sl.gc);
+  a.terms = reinterpret_cast<R *>(s + sl.terms);
+  a.mu = reinterpret_cast<double *>(s + sl.mu);
+  a.expo = reinterpret_cast<int *>(s + sl.expo);
+  a.tmax = reinterpret_cast<double *>(s + sl.tmax);
+  a.S = reinterpret_cast<R *>(s + sl.S);
+  a.best = reinterpret_cast<float *>(s + sl.best);
+  a.tilt0 = tt.t[2 * d];
+  a.tilt1 = tt.t[2 * d + 1];
+  a.tsign = 1;
+  a.tfirst = 1;
+  a.tlast = 0;
+  if (d > 0) a.info = nullptr;
+  rows[d].a = a;
+  rows[d].begin = d * a.nbr;
+  rows[d].pad_ = 0;
+  cols[d].a = a;
+  cols[d].begin = d * a.ncw;
+  cols[d].pad_ = 0;
+  a.tsign = -1;
+  a.spec = a.spec_neg;
+  negs[d].a = a;
+  negs[d].begin = d * a.nbr;
+  negs[d].pad_ = 0;
+}
+
+// Per point the tilt with the highest score (the first on ties, as if the
+// tilts had been solved in turn): its S into the result; with count, the
+// points no tilt resolved (S = +inf) into info.
+template <typename R>
+__global__ void __launch_bounds__(256) k_tilt_select(R *__restrict__ S,
+                                                     const unsigned char *__restrict__ slices,
+                                                     TiltSlice sl, int n_tilt, long long N,
+                                                     int count, sweik_info *info) {
+  long long nbad = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    float best = -__builtin_huge_valf();
+    R v = (R)0;
+    for (int d = 0; d < n_tilt; ++d) {
+      const unsigned char *p = slices + (size_t)d * sl.bytes;
+      const float b = reinterpret_cast<const float *>(p + sl.best)[i];
+      if (d == 0 || b > best) {
+        best = b;
+        v = reinterpret_cast<const R *>(p + sl.S)[i];
+      }
+    }
+    S[i] = v;
+    nbad += best > -__builtin_huge_valf() ? 0 : 1;
+  }
+  if (count && info) {
+    const long long nb = block_sum_ll(nbad);
+    if (threadIdx.x == 0 && nb)
+      atomicAdd((unsigned long long *)&info->n_nonpositive_phi, (unsigned long long)nb);
+  }
+}
+
 // Pointers read from a work list in memory are generic to the compiler (flat
 // loads and stores).  Rebuilding each one as a global-address-space pointer
 // from its integer value lets it use global memory instructions (a plain

@@ -136,6 +136,15 @@ hipError_t launch_row2_batch_e(int mode, int H, int nblocks, hipStream_t st,
     case ROW_PHI0: return RowLaunch<R, E, ROW_PHI0>::run_batch(H, nblocks, st, items, nitems, term);
     case ROW_TERM: return RowLaunch<R, E, ROW_TERM>::run_batch(H, nblocks, st, items, nitems, term);
     case ROW_LAST: return RowLaunch<R, E, ROW_LAST>::run_batch(H, nblocks, st, items, nitems, term);
+    // the tilted solve's passes over all tilts (radix-16 teams only)
+    case ROW_GHATT:
+      if constexpr (E == 16)
+        return RowLaunch<R, E, ROW_GHATT>::run_batch(H, nblocks, st, items, nitems, term);
+      break;
+    case ROW_LASTT:
+      if constexpr (E == 16)
+        return RowLaunch<R, E, ROW_LASTT>::run_batch(H, nblocks, st, items, nitems, term);
+      break;
   }
   return hipErrorInvalidValue;
 }
@@ -193,8 +202,19 @@ hipError_t launch_col2_e(int mode, int M0, dim3 grid, hipStream_t st, const Args
 template <typename R, int E>
 hipError_t launch_col2_batch_e(int mode, int M0, int nblocks, hipStream_t st,
                                const BatchItem<R> *items, int nitems) {
-  return mode == COL_GHAT ? ColLaunch<R, E, COL_GHAT>::run_batch(M0, nblocks, st, items, nitems)
-                          : ColLaunch<R, E, COL_CONV>::run_batch(M0, nblocks, st, items, nitems);
+  switch (mode) {
+    case COL_GHAT: return ColLaunch<R, E, COL_GHAT>::run_batch(M0, nblocks, st, items, nitems);
+    case COL_CONV: return ColLaunch<R, E, COL_CONV>::run_batch(M0, nblocks, st, items, nitems);
+    case COL_GHATC:
+      if constexpr (E == 16)
+        return ColLaunch<R, E, COL_GHATC>::run_batch(M0, nblocks, st, items, nitems);
+      break;
+    case COL_CONVC:
+      if constexpr (E == 16)
+        return ColLaunch<R, E, COL_CONVC>::run_batch(M0, nblocks, st, items, nitems);
+      break;
+  }
+  return hipErrorInvalidValue;
 }
 
 template <typename R>
@@ -246,6 +266,24 @@ hipError_t launch_source_lse(R *S, double *acc, long long N, double hbar, int fi
   return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_tilt_items(const Args2<R> &base, const TiltTable &tt, int n_tilt,
+                             unsigned char *slices, const TiltSlice &sl, BatchItem<R> *rows,
+                             BatchItem<R> *negs, BatchItem<R> *cols, hipStream_t st) {
+  hipLaunchKernelGGL(k_tilt_items<R>, dim3(1), dim3(64), 0, st, base, tt, n_tilt, slices, sl, rows,
+                     negs, cols);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_tilt_select(R *S, const unsigned char *slices, const TiltSlice &sl, int n_tilt,
+                              long long N, int count, sweik_info *info, hipStream_t st) {
+  const long long nb = std::min<long long>((N + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_tilt_select<R>, dim3((unsigned)std::max<long long>(nb, 1)), dim3(256), 0,
+                     st, S, slices, sl, n_tilt, N, count, info);
+  return hipGetLastError();
+}
+
 template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream_t st) {
   const long long nb = std::min<long long>((N + 255) / 256, 4096);
   hipLaunchKernelGGL(k_fill<R>, dim3((unsigned)std::max<long long>(nb, 1)), dim3(256), 0, st, out,
@@ -279,6 +317,12 @@ template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream
   template hipError_t launch_fill<R>(R *, long long, R, hipStream_t);                       \
   template hipError_t launch_source_lse<R>(R *, double *, long long, double, int, int,      \
                                            sweik_info *, hipStream_t);                      \
+  template hipError_t launch_tilt_items<R>(const Args2<R> &, const TiltTable &, int,        \
+                                           unsigned char *, const TiltSlice &,              \
+                                           BatchItem<R> *, BatchItem<R> *, BatchItem<R> *,  \
+                                           hipStream_t);                                    \
+  template hipError_t launch_tilt_select<R>(R *, const unsigned char *, const TiltSlice &,  \
+                                            int, long long, int, sweik_info *, hipStream_t); \
   template hipError_t launch_adj_full_finish<R>(const R *, long long, const Params *,         \
                                                 const double *, int, long long *, int, double, \
                                                 double, R *, double *, hipStream_t);           \

@@ -36,6 +36,15 @@ template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream
 template <typename R>
 hipError_t launch_source_lse(R *S, double *acc, long long N, double hbar, int first, int last,
                              sweik_info *info, hipStream_t st);
+// the tilted solve: the tilts' work lists (k_tilt_items) and the per-point
+// choice of tilt (k_tilt_select)
+template <typename R>
+hipError_t launch_tilt_items(const Args2<R> &base, const TiltTable &tt, int n_tilt,
+                             unsigned char *slices, const TiltSlice &sl, BatchItem<R> *rows,
+                             BatchItem<R> *negs, BatchItem<R> *cols, hipStream_t st);
+template <typename R>
+hipError_t launch_tilt_select(R *S, const unsigned char *slices, const TiltSlice &sl, int n_tilt,
+                              long long N, int count, sweik_info *info, hipStream_t st);
 // full gradient: argmin / argmax of f (kRedBlocks partials in ext, 2 x
 // kRedBlocks long long) and the scalar derivatives (see k_adj_full_finish)
 template <typename R>
@@ -123,18 +132,23 @@ inline hipError_t launch_col2(int mode, int M0, int E, dim3 grid, hipStream_t st
 template <typename R>
 inline hipError_t launch_row2_batch(int mode, int H, int E, int nblocks, hipStream_t st,
                                     const BatchItem<R> *items, int nitems, int term) {
-  return E == 16  ? launch_row2_batch_e<R, 16>(mode, H, nblocks, st, items, nitems, term)
-         : E == 8 ? launch_row2_batch_e<R, 8>(mode, H, nblocks, st, items, nitems, term)
-         : E == 4 ? RadixFour<R>::row_batch(mode, H, nblocks, st, items, nitems, term)
-                  : hipErrorInvalidValue;
+  const hipError_t err =
+      E == 16  ? launch_row2_batch_e<R, 16>(mode, H, nblocks, st, items, nitems, term)
+      : E == 8 ? launch_row2_batch_e<R, 8>(mode, H, nblocks, st, items, nitems, term)
+      : E == 4 ? RadixFour<R>::row_batch(mode, H, nblocks, st, items, nitems, term)
+               : hipErrorInvalidValue;
+  if (err != hipSuccess) note_launch_error("batched row pass", mode, H, E, err);
+  return err;
 }
 template <typename R>
 inline hipError_t launch_col2_batch(int mode, int M0, int E, int nblocks, hipStream_t st,
                                     const BatchItem<R> *items, int nitems) {
-  return E == 16  ? launch_col2_batch_e<R, 16>(mode, M0, nblocks, st, items, nitems)
-         : E == 8 ? launch_col2_batch_e<R, 8>(mode, M0, nblocks, st, items, nitems)
-         : E == 4 ? RadixFour<R>::col_batch(mode, M0, nblocks, st, items, nitems)
-                  : hipErrorInvalidValue;
+  const hipError_t err = E == 16  ? launch_col2_batch_e<R, 16>(mode, M0, nblocks, st, items, nitems)
+                         : E == 8 ? launch_col2_batch_e<R, 8>(mode, M0, nblocks, st, items, nitems)
+                         : E == 4 ? RadixFour<R>::col_batch(mode, M0, nblocks, st, items, nitems)
+                                  : hipErrorInvalidValue;
+  if (err != hipSuccess) note_launch_error("batched column pass", mode, M0, E, err);
+  return err;
 }
 
 }  // namespace sweik

@@ -38,9 +38,6 @@ struct Layout {      // byte offsets into the workspace / checkpoint
   // partial sums and the argmin / argmax partials (the kernel table's
   // beta-derivative spectrum reuses g0)
   size_t fg_spec2, fg_part, fg_ext, fg_total;
-  // tilted solve: after `total`, the tilted kernel's complex spectrum
-  // ((H1 + 1) x M0), the per-point score and the per-term maxima
-  size_t tl_gc, tl_best, tl_tmax, tl_total;
 };
 
 }  // namespace sweik

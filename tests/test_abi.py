@@ -226,8 +226,14 @@ def test_tilted_entry_checks(lib):
     # argument errors return before any HIP call; 3D is unsupported
     vp = C.c_void_p
     p = _plan(T=4)
-    need = lib.sweik_tilted_workspace_bytes(p.handle)
+    need = lib.sweik_tilted_workspace_bytes(p.handle, 1)
     assert need > lib.sweik_workspace_bytes(p.handle)
+    # one slice per tilt: the workspace grows linearly with the tilt count
+    w2, w9 = (lib.sweik_tilted_workspace_bytes(p.handle, n) for n in (2, 9))
+    assert need < w2 < w9
+    assert abs((w9 - w2) - 7 * (w2 - need)) <= 4096  # up to the alignment of the work lists
+    assert lib.sweik_tilted_workspace_bytes(p.handle, 0) == 0
+    assert lib.sweik_tilted_workspace_bytes(p.handle, 65) == 0
     D = C.POINTER(C.c_double)
 
     def call(tilts, n=None, ws_bytes=None, plan=p):
@@ -244,5 +250,5 @@ def test_tilted_entry_checks(lib):
     assert lib.sweik_solve_tilted(p.handle, None, vp(16), vp(16), None, 1, 0, vp(16), need, None,
                                   None) == 1
     cube = _plan(dims=(16, 16, 16))
-    assert lib.sweik_tilted_workspace_bytes(cube.handle) == 0
+    assert lib.sweik_tilted_workspace_bytes(cube.handle, 1) == 0
     assert call([(0.0, 0.0)], plan=cube) == 2

@@ -173,9 +173,9 @@ def test_tilted_solve_graph_replays():
     pl = pk.Plan(p.dims, p.h, p.hbar, p.T, 1, "fp64")
     f = torch.as_tensor(p.f.astype(np.float64)).cuda()
     d_src = torch.as_tensor(p.src).cuda()
-    ws = torch.empty(pl.tilted_workspace_bytes, dtype=torch.uint8, device="cuda")
-    S = torch.empty_like(f)
     tilts = pk.default_tilts(8, 0.9)
+    ws = torch.empty(pl.tilted_workspace_bytes(len(tilts)), dtype=torch.uint8, device="cuda")
+    S = torch.empty_like(f)
     pl.solve_tilted(f, d_src, S, ws, tilts)
     torch.cuda.synchronize()
     ref = S.clone()
@@ -245,11 +245,11 @@ def test_per_source_counts_and_graph(prec):
     pl = pk.Plan(dims, h, hbar, T, len(src), prec)
     f = torch.as_tensor(fm).to("cuda", _dt(prec))
     d_src = torch.as_tensor(src).cuda()
-    ws = torch.empty(pl.tilted_workspace_bytes, dtype=torch.uint8, device="cuda")
+    tilts = pk.default_tilts()
+    ws = torch.empty(pl.tilted_workspace_bytes(len(tilts)), dtype=torch.uint8, device="cuda")
     S = torch.empty_like(f)
     from paper_1403_1937_amd import _native
     info = torch.zeros(_native.info_struct_size(), dtype=torch.uint8, device="cuda")
-    tilts = pk.default_tilts()
     pl.solve_tilted(f, d_src, S, ws, tilts, info, per_source=True)
     torch.cuda.synchronize()
     Sn = S.double().cpu().numpy()
