@@ -85,6 +85,14 @@ KERNEL_SOURCES_2D = ("fft_team.hpp", "geom2d.hpp", "green.hpp", "common2d.hpp", 
                      "k2d_col_f32.hip")
 
 
+_T0 = time.perf_counter()
+
+
+def progress(msg: str) -> None:
+    """A line on stderr as each section ends (stdout carries only the JSON)."""
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def source_hash() -> str:
     """Hash of the device sources of the FP32 2D kernels: counter figures
     are valid only for these."""
@@ -734,6 +742,7 @@ def reference_accuracy(gpu, o_main, threads):
     if S64 is not None:
         out["main"]["fp64"] = accuracy(S64, o_main, p.hbar, "fp64")
     if "config1" in gpu:
+        progress("accuracy: config1")
         p1, S1 = gpu["config1"]
         f1 = p1.f.astype(np.float64)
         od = oracle.solve(f1, p1.src, p1.h, p1.hbar, p1.T, method="direct", nthreads=threads)
@@ -744,6 +753,7 @@ def reference_accuracy(gpu, o_main, threads):
                           "note": "the direct sum is the ground truth where FFT noise dominates "
                                   "(Lambda beyond ~30)"}
     if "fwd_bwd" in gpu:
+        progress("accuracy: fwd_bwd")
         p5, rec, f_t, S5, gradient = gpu["fwd_bwd"]
         f5 = p5.f.astype(np.float64)
         o5 = oracle.solve(f5, p5.src, p5.h, p5.hbar, p5.T, nthreads=threads)
@@ -761,6 +771,7 @@ def reference_accuracy(gpu, o_main, threads):
                               "dLdS": "2 (S - target) at 256 receivers, from the oracle's solves "
                                       "of f and the perturbed forcing"}}
     if "batched" in gpu:
+        progress("accuracy: batched")
         res = {}
         for n, (j, q, Sq) in sorted(gpu["batched"].items()):
             oq = oracle.solve(q.f.astype(np.float64), q.src, q.h, q.hbar, q.T, nthreads=threads)
@@ -771,6 +782,7 @@ def reference_accuracy(gpu, o_main, threads):
             res[str(n)] = a
         out["batched"] = {"sample": "the first instance of each edge length", "fp32": res}
     if "far_field" in gpu:
+        progress("accuracy: far_field")
         pf, rf = gpu["far_field"]
         od = oracle.solve(pf.f.astype(np.float64), pf.src, pf.h, pf.hbar, pf.T, method="direct",
                           nthreads=threads)
@@ -808,6 +820,7 @@ def reference_accuracy(gpu, o_main, threads):
             res["noise2d_2048x2048_fp32"] = r
         out["far_field"] = res
     if "solve3d" in gpu:
+        progress("accuracy: solve3d")
         p3, r3 = gpu["solve3d"]
         o3 = oracle.solve(p3.f.astype(np.float64), p3.src, p3.h, p3.hbar, p3.T, nthreads=threads)
         out["solve3d"] = {"workload": "blobs3d_256x256x256_T16",
@@ -1033,6 +1046,7 @@ def main():
 
     ms, kern, total_bytes, S_main = run_main(pk, torch, dev, p, args.precision, args.steps,
                                              args.warmup)
+    progress(f"main workload: {ms:.3f} ms per solve")
     gpu = {}  # host copies of the GPU results, for the accuracy figures
     value = N / (ms * 1e-3)
     sched = kern.pop("schedule")
@@ -1072,20 +1086,30 @@ def main():
         out["fp64_comparator"] = {"value": N / (ms64 * 1e-3), "ms_per_step": ms64,
                                   "solve_alg_GBps": tb64 / (ms64 * 1e-3) / 1e9,
                                   "speedup_fp32_over_fp64": ms64 / ms}
+        progress(f"fp64 comparator: {ms64:.3f} ms per solve")
     gpu["main"] = (p, S_main, S64_main) if args.precision == "fp32" else (p, None, S_main)
     if not args.no_extra:
         out["config1"], gpu["config1"] = run_config1(pk, torch, dev, max(20, args.steps), 3)
+        progress("config1")
         out["far_field"], gpu["far_field"] = run_far_field(pk, torch, dev, max(10, args.steps // 2), 2)
+        progress("far_field")
         out["fwd_bwd"], gpu["fwd_bwd"] = run_fwd_bwd(pk, torch, dev, max(3, args.steps // 2), 2)
+        progress("fwd_bwd")
         out["batched"], gpu["batched"] = run_batched(pk, torch, dev, max(3, args.steps // 4), 1)
+        progress("batched")
         out["solve3d"], gpu["solve3d"] = run_3d(pk, torch, dev, max(3, args.steps // 4), 1)
+        progress("solve3d")
         out["backtrack"] = run_backtrack(pk, torch, dev, max(3, args.steps // 4), 1)
+        progress("backtrack")
         out["fd"] = run_fd(pk, torch, dev, 3, 1)
+        progress("fd")
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"], o_main = cpu_baseline(p, threads)
+        progress("cpu_baseline")
         if args.precision == "fp32":
             out["accuracy"] = reference_accuracy(gpu, o_main, threads)
+            progress("accuracy against the oracle")
     print(json.dumps(out))
 
 

@@ -425,7 +425,8 @@ sweik_status sweik_plan_set_schedule(sweik_plan plan, const sweik_schedule *s);
 /* Times every candidate schedule of the 2D per-term passes with HIP events
  * on `stream` (radix 16, 8 and, in float32, 4): each (col_e, row_e) pair
  * as 4 back-to-back [column
- * convolution; row pass] launches, 3 times, keeping the median (with T < 2
+ * convolution; row pass] launches, 5 times (the pairs taking turns within
+ * each repetition), keeping the median (with T < 2
  * only the column pass is timed).  Works on the workspace `ws`, whose
  * contents are overwritten: run it before a solve, not between a solve and
  * its adjoint.  Keeps the fastest in the plan and in the process-wide table

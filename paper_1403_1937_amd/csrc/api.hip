@@ -896,31 +896,41 @@ template <typename R> int32_t autotune2d(sweik_plan_s *pl, void *ws, hipStream_t
   const bool rows = pl->p.T >= 2;
   const int cand[3] = {16, 8, 4};
   const int ncand = pl->p.prec == SWEIK_F64 ? 2 : 3;  // radix 4: float32 only
+  int pc[9], pr[9], npair = 0;
+  for (int ic = 0; ic < ncand; ++ic)
+    for (int ir = 0; ir < ncand; ++ir) {
+      if (!rows && ir != 0) continue;
+      if (rows && g.H1 < cand[ir]) continue;
+      pc[npair] = cand[ic];
+      pr[npair] = cand[ir];
+      ++npair;
+    }
+  // the pairs take turns within every repetition, so that a drift of the
+  // clocks during tuning does not favour the pairs timed first; the median
+  // of the repetitions decides
+  constexpr int kReps = 5;
+  float t[9][kReps];
+  for (int rep = 0; rep < kReps; ++rep)
+    for (int k = 0; k < npair; ++k) {
+      bool ok = true;
+      t[k][rep] = time_launches(st, 4, [&] {
+        hipError_t e = launch_col2<R>(COL_CONV, g.M0, pc[k], gcol, st, a);
+        if (e == hipSuccess && rows) e = launch_row2<R>(ROW_TERM, g.H1, pr[k], grow, st, a, 1);
+        return e;
+      }, &ok);
+      if (!ok) return -1;
+    }
   int timed = 0, bc = g.ecol, br = g.erow;
   float best = 0.0f;
-  for (int ic = 0; ic < ncand; ++ic) {
-    for (int ir = 0; ir < ncand; ++ir) {
-      const int ec = cand[ic], er = cand[ir];
-      if (!rows && ir != 0) continue;
-      if (rows && g.H1 < er) continue;
-      bool ok = true;
-      float t[3];
-      for (int rep = 0; rep < 3; ++rep) {
-        t[rep] = time_launches(st, 4, [&] {
-          hipError_t e = launch_col2<R>(COL_CONV, g.M0, ec, gcol, st, a);
-          if (e == hipSuccess && rows) e = launch_row2<R>(ROW_TERM, g.H1, er, grow, st, a, 1);
-          return e;
-        }, &ok);
-        if (!ok) return -1;
-      }
-      std::sort(t, t + 3);
-      if (timed == 0 || t[1] < best) {
-        best = t[1];
-        bc = ec;
-        br = rows ? er : g.erow;
-      }
-      ++timed;
+  for (int k = 0; k < npair; ++k) {
+    std::sort(t[k], t[k] + kReps);
+    const float med = t[k][kReps / 2];
+    if (timed == 0 || med < best) {
+      best = med;
+      bc = pc[k];
+      br = rows ? pr[k] : g.erow;
     }
+    ++timed;
   }
   g.ecol = bc;
   sched_store(SCHED_COL2, g.M0, pl->p.prec, bc);
