@@ -272,3 +272,22 @@ def test_per_source_counts_and_graph(prec):
         graph.replay()
         torch.cuda.synchronize()
         assert torch.equal(S, ref_t), f"replay {rep}"
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_most_tilts_first_wins_on_ties(prec):
+    """The most tilts a solve takes (64), side by side in one launch per
+    pass: the default nine followed by 55 repeats of them.  A repeat scores
+    exactly as its first occurrence and never replaces it (the first tilt
+    wins ties), so S equals the nine-tilt solve bit for bit."""
+    import paper_1403_1937_amd as pk
+    p = workloads.problem(1)
+    f = torch.as_tensor(p.f.astype(np.float64)).to("cuda", _dt(prec))
+    base = pk.default_tilts()
+    many = (base * 8)[:64]
+    assert len(many) == 64
+    S9 = pk.solve_tilted(f, p.src, p.h, p.hbar, p.T, tilts=base)
+    S64, info = pk.solve_tilted(f, p.src, p.h, p.hbar, p.T, tilts=many, return_info=True)
+    torch.cuda.synchronize()
+    assert torch.equal(S9, S64)
+    assert info["n_nonpositive_phi"] == int(torch.isinf(S64).sum())
