@@ -31,7 +31,7 @@ def _lib():
 
 
 def _supported(dims, h, hbar, T, n_src, prec):
-    """The planner's verdict (host only): False when it rejects the sizes."""
+    """The planner's decision (host only): False when it rejects the sizes."""
     import paper_1403_1937_amd as pk
     try:
         pk.Plan(dims, h, hbar, T, n_src, prec)
