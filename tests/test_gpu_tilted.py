@@ -291,3 +291,26 @@ def test_most_tilts_first_wins_on_ties(prec):
     torch.cuda.synchronize()
     assert torch.equal(S9, S64)
     assert info["n_nonpositive_phi"] == int(torch.isinf(S64).sum())
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims,T,n_src", [((2, 70), 3, 2), ((70, 2), 3, 2), ((3, 5), 1, 1),
+                                          ((9, 130), 2, 3)])
+@pytest.mark.parametrize("per_source", [False, True])
+def test_thin_and_tiny_grids(dims, T, n_src, per_source, prec):
+    """Thin and tiny grids (two rows, two columns, 3 x 5, one term): every
+    point within the precision's tolerance of the direct sums, and no point
+    without a positive phi."""
+    import paper_1403_1937_amd as pk
+    rng = np.random.default_rng(21)
+    f = rng.uniform(1.0, 2.0, dims)
+    src = workloads.distinct_sources(dims, n_src, rng)
+    h, hbar = 1.0 / max(dims), 0.1
+    ref = oracle.solve(f, src, h, hbar, T, method="direct")["S"]
+    S, info = pk.solve_tilted(torch.as_tensor(f).to("cuda", _dt(prec)), src, h, hbar, T,
+                              per_source=per_source, return_info=True)
+    ok, e = _resolved(S.double().cpu().numpy(), ref, hbar, prec)
+    print(f"{dims} T={T} {n_src} sources per_source={per_source} {prec}: max rel {e.max():.2e}",
+          flush=True)
+    assert ok.all()
+    assert info["n_nonpositive_phi"] == 0
