@@ -138,8 +138,8 @@ sweik_status sweik_check_sources(sweik_plan plan, const int32_t *src_host);
  *   S      device, dims, same type as f (output)
  *   ws     device workspace of ws_bytes >= sweik_workspace_bytes(plan)
  *   ckpt   device, nullable: when given, the series terms and phi are kept
- *          for sweik_solve_adjoint (sweik_checkpoint_bytes(plan) bytes);
- *          2D only (SWEIK_EUNSUPPORTED in 3D)
+ *          for sweik_solve_adjoint (sweik_checkpoint_bytes(plan) bytes; 2D
+ *          and 3D)
  *   stream hipStream_t
  *   info   device, nullable: sweik_info written asynchronously */
 sweik_status sweik_solve(sweik_plan plan, const void *f, const int32_t *src,
@@ -221,8 +221,8 @@ size_t sweik_noalloc_scratch_bytes(void);
 sweik_status sweik_solve_noalloc(sweik_plan plan, const void *f, const int32_t *src, void *S,
                                  void *stream, sweik_info *info);
 
-/* Adjoint (2D) of the solve with ftilde held fixed (reverse sweep of the
- * recurrence eq. phiRecRelation; the kernel is even, so the transposed
+/* Adjoint (2D and 3D) of the solve with ftilde held fixed (reverse sweep of
+ * the recurrence eq. phiRecRelation; the kernel is even, so the transposed
  * convolution is the convolution itself).
  *   dLdS   device, dims, same type as f: gradient of a loss w.r.t. S
  *   dLdf   device, dims, same type as f (output)

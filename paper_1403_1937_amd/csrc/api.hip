@@ -584,18 +584,26 @@ sweik_status plan3d(sweik_plan_s *pl) {
   L.spec = take((size_t)csz * g.nlines * g.H2);
   g.ld2 = (long long)g.M1 * g.H2 + kS2PlanePad;
   L.s2 = take((size_t)csz * g.n0 * (size_t)g.ld2);
-  L.acc = 0;
+  L.acc = take(sizeof(double) * N);  // the adjoint's dL/dgamma
   L.terms = take((size_t)esz * N * (size_t)p.T);
   L.gam = take((size_t)esz * N);
-  L.lam = 0;
+  L.lam = take((size_t)esz * N);
   L.total = off;
-  L.ck_total = 0;  // no adjoint in 3D
+  // checkpoint of a solve for its adjoint: scalars, kernel spectrum, term
+  // exponents, phi in float64 and the stored terms
+  off = 0;
+  L.ck_expo = take(sizeof(int) * (SWEIK_MAX_TERMS + 1));
+  L.ck_par = take(sizeof(Params));
+  L.ck_g = take((size_t)esz * (g.H1 + 1) * (g.H0 + 1) * g.H2);
+  L.ck_phi = take(sizeof(double) * N);
+  L.ck_terms = take((size_t)esz * N * (size_t)p.T);
+  L.ck_total = off;
   return SWEIK_OK;
 }
 
 template <typename R>
 Args3<R> make_args3(const sweik_plan_s *pl, const void *f, const int32_t *src, void *S,
-                    void *ws, sweik_info *info) {
+                    void *ws, sweik_info *info, void *ckpt = nullptr) {
   const Geo3 &g = pl->g3;
   const sweik_problem &p = pl->p;
   const Layout &L = pl->ws;
@@ -636,6 +644,18 @@ Args3<R> make_args3(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.terms = (R *)(w + L.terms);
   a.gam = (R *)(w + L.gam);
   a.info = info;
+  a.dLdS = nullptr;
+  a.dLdf = nullptr;
+  a.lam = (R *)(w + L.lam);
+  a.acc = (double *)(w + L.acc);
+  char *c = (char *)ckpt;
+  if (c) {  // the scalars, kernel spectrum and terms live in the checkpoint
+    a.par = (Params *)(c + L.ck_par);
+    a.g = (R *)(c + L.ck_g);
+    a.terms = (R *)(c + L.ck_terms);
+  }
+  a.ck_expo = c ? (int *)(c + L.ck_expo) : nullptr;
+  a.ck_phi = c ? (double *)(c + L.ck_phi) : nullptr;
   return a;
 }
 
@@ -644,9 +664,9 @@ Args3<R> make_args3(const sweik_plan_s *pl, const void *f, const int32_t *src, v
 template <typename R>
 sweik_status enqueue3d(const sweik_plan_s *pl, const void *f, const int32_t *src, void *S,
                        void *ws, hipStream_t st, sweik_info *info, KernelTimer *tm = nullptr,
-                       const void *src_s = nullptr) {
+                       const void *src_s = nullptr, void *ckpt = nullptr) {
   const Geo3 &g = pl->g3;
-  Args3<R> a = make_args3<R>(pl, f, src, S, ws, info);
+  Args3<R> a = make_args3<R>(pl, f, src, S, ws, info, ckpt);
   a.src_s = (const R *)src_s;
   const long long N = (long long)g.n0 * g.n1 * g.n2;
   hipError_t err = hipSuccess;
@@ -676,6 +696,36 @@ sweik_status enqueue3d(const sweik_plan_s *pl, const void *f, const int32_t *src
     launch(SWEIK_KC_Y_INV, [&] { return launch_c3<R>(C3_YI, g.M1, ny, st, a, -1); });
     launch(i == T ? SWEIK_KC_LAST_ROW : SWEIK_KC_TERM_ROW,
            [&] { return launch_x3<R>(i == T ? X_LAST : X_TERM, g.H2, g.nbx, st, a, i); });
+  }
+  return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
+}
+
+// Adjoint of a 3D solve (f~ held fixed) from its checkpoint: lambda =
+// -hbar dL/dS / phi, a_T = (-1)^T lambda; for i = T..1 b_i = kappa (*) a_i
+// through the same y, z and y passes as the forward (kappa is even),
+// dL/dgamma += phi_{i-1} b_i and a_{i-1} = (-1)^(i-1) lambda + gamma b_i in
+// the x passes; dL/df = dL/dgamma 2 f / f~^2.
+template <typename R>
+sweik_status enqueue3d_adjoint(const sweik_plan_s *pl, const void *f, const int32_t *src,
+                               const void *ckpt, const void *dLdS, void *dLdf, void *ws,
+                               hipStream_t st) {
+  const Geo3 &g = pl->g3;
+  Args3<R> a = make_args3<R>(pl, f, src, nullptr, ws, nullptr, const_cast<void *>(ckpt));
+  a.dLdS = (const R *)dLdS;
+  a.dLdf = (R *)dLdf;
+  const long long N = (long long)g.n0 * g.n1 * g.n2;
+  const int T = pl->p.T;
+  if (T == 0)  // f~ fixed: no term depends on f
+    return launch_fill<R>((R *)dLdf, N, (R)0, st) == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
+  const int ny = g.n0 * g.ncb1;
+  hipError_t err = launch_adj_prep<R>((const R *)dLdS, (const double *)a.ck_phi, N, pl->p.hbar,
+                                      a.red, (cplx<R> *)a.tw, g.lmax, st);
+  if (err == hipSuccess) err = launch_x3<R>(X_ADJ0, g.H2, g.nbx, st, a, T);
+  for (int i = T; i >= 1 && err == hipSuccess; --i) {
+    err = launch_c3<R>(C3_YF, g.M1, ny, st, a, -1);
+    if (err == hipSuccess) err = launch_c3<R>(C3_Z, g.M0, g.M1 * g.ncb0, st, a, -1);
+    if (err == hipSuccess) err = launch_c3<R>(C3_YI, g.M1, ny, st, a, -1);
+    if (err == hipSuccess) err = launch_x3<R>(X_ADJ, g.H2, g.nbx, st, a, i);
   }
   return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
@@ -1030,9 +1080,8 @@ sweik_status sweik_solve_seeded(sweik_plan plan, const void *f, const int32_t *s
     return f64 ? enqueue2d<double>(plan, f, src, S, ws, ckpt, st, info, nullptr, src_s)
                : enqueue2d<float>(plan, f, src, S, ws, ckpt, st, info, nullptr, src_s);
   }
-  if (ckpt) return SWEIK_EUNSUPPORTED;  // the adjoint is 2D only
-  return f64 ? enqueue3d<double>(plan, f, src, S, ws, st, info, nullptr, src_s)
-             : enqueue3d<float>(plan, f, src, S, ws, st, info, nullptr, src_s);
+  return f64 ? enqueue3d<double>(plan, f, src, S, ws, st, info, nullptr, src_s, ckpt)
+             : enqueue3d<float>(plan, f, src, S, ws, st, info, nullptr, src_s, ckpt);
 }
 
 sweik_status sweik_solve(sweik_plan plan, const void *f, const int32_t *src, void *S, void *ws,
@@ -1121,7 +1170,9 @@ sweik_status sweik_solve_adjoint(sweik_plan plan, const void *f, const int32_t *
                ? enqueue2d_adjoint<double>(plan, f, src, ckpt, dLdS, dLdf, ws, st)
                : enqueue2d_adjoint<float>(plan, f, src, ckpt, dLdS, dLdf, ws, st);
   }
-  return SWEIK_EUNSUPPORTED;
+  return plan->p.prec == SWEIK_F64
+             ? enqueue3d_adjoint<double>(plan, f, src, ckpt, dLdS, dLdf, ws, st)
+             : enqueue3d_adjoint<float>(plan, f, src, ckpt, dLdS, dLdf, ws, st);
 }
 
 size_t sweik_adjoint_full_workspace_bytes(sweik_plan plan) {

@@ -32,8 +32,9 @@
 namespace sweik {
 
 // X_LAST: the pass after the last convolution (float64 sum of the stored
-// terms and the log), its own kernel so that X_TERM is not sized for it
-enum XMode { X_GHAT = 0, X_PHI0 = 1, X_TERM = 2, X_LAST = 3 };
+// terms and the log), its own kernel so that X_TERM is not sized for it.
+// X_ADJ0, X_ADJ: the adjoint sweep's start and steps (see x3d.hpp).
+enum XMode { X_GHAT = 0, X_PHI0 = 1, X_TERM = 2, X_LAST = 3, X_ADJ0 = 4, X_ADJ = 5 };
 enum C3Mode { C3_YF = 0, C3_Z = 1, C3_YI = 2, C3_GY = 3, C3_GZ = 4 };
 
 // x pass: one team of P = H2/16 threads per line, 256 threads per group
@@ -100,9 +101,17 @@ template <typename R> struct Args3 {
   const cplx<R> *tw;
   cplx<R> *s1, *s2;
   R *g;            // kernel spectrum orthant
-  R *terms;        // T x N mantissas of phi_0..phi_{T-1}
+  R *terms;        // T x N mantissas of phi_0..phi_{T-1} (the checkpoint's when kept)
   R *gam;          // N
   sweik_info *info;
+  // checkpoint of a solve for its adjoint (null when none is kept)
+  int *ck_expo;    // T+1 exponents of the stored terms
+  double *ck_phi;  // N, phi in float64
+  // adjoint
+  const R *dLdS;
+  R *dLdf;
+  R *lam;          // N, lambda mantissas (scale 2^expo[0])
+  double *acc;     // N, dL/dgamma in float64
 };
 
 }  // namespace sweik

@@ -46,6 +46,8 @@ hipError_t launch_x3(int mode, int H, int nblocks, hipStream_t st, const Args3<R
     case X_PHI0: return x3_mode<R, X_PHI0>(H, nblocks, st, a, term);
     case X_TERM: return x3_mode<R, X_TERM>(H, nblocks, st, a, term);
     case X_LAST: return x3_mode<R, X_LAST>(H, nblocks, st, a, term);
+    case X_ADJ0: return x3_mode<R, X_ADJ0>(H, nblocks, st, a, term);
+    case X_ADJ: return x3_mode<R, X_ADJ>(H, nblocks, st, a, term);
   }
   return hipErrorInvalidValue;
 }

@@ -7,6 +7,11 @@
 //           the next forcing term and its FFT
 //   X_LAST  term T: inverse real FFT, the float64 sum of all terms and
 //           S = -hbar ln phi
+//   X_ADJ0  adjoint start: lambda = -hbar dL/dS / phi, a_T = (-1)^T lambda,
+//           forward real FFT (gamma formed from f again)
+//   X_ADJ   adjoint step `term` = i: inverse real FFT of b_i = kappa (*) a_i,
+//           dL/dgamma += phi_{i-1} b_i, a_{i-1} = (-1)^(i-1) lambda + gamma
+//           b_i and its FFT; at i = 1, dL/df = dL/dgamma 2 f / ftilde^2
 #pragma once
 
 #include "common3d.hpp"
@@ -87,6 +92,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   C *line = lines + team * LL;
   const size_t rowoff = (size_t)rs * a.n2;
   constexpr bool TERMLIKE = MODE == X_TERM || MODE == X_LAST;
+  constexpr bool ADJ0 = MODE == X_ADJ0, ADJ = MODE == X_ADJ;
   const bool last = MODE == X_LAST || (MODE == X_PHI0 && a.T == 0);
   auto col_ok = [&](int c) { return FULL ? true : (line_ok && c < a.n2); };
   const bool vec = FULL || (a.n2 & 1) == 0;  // column pairs aligned: vector access
@@ -103,7 +109,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   stage_tw_issue<H, 16>(tsr, a.tw, a.lmax_log, tid, kThreads);
   const C w1 = a.tw[1 << (a.lmax_log - TWLOG)];  // w(1) = exp(-2 pi i / 4H)
   C v[16];
-  if constexpr (TERMLIKE) {
+  if constexpr (TERMLIKE || ADJ) {
     const C *sl = a.s1 + (size_t)rs * H;
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = line_ok ? sl[t + P * j] : cmake<C>((R)0, (R)0);
@@ -201,6 +207,21 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     const int slot = TERMLIKE ? term : 0;
     a.expo[slot] = E;
     if (a.info) a.info->scale_exp[slot] = E;
+    if (a.ck_expo) a.ck_expo[slot] = E;
+  }
+  // adjoint: lambda's exponent (from the partial maxima of |lambda|), and
+  // the stored exponent of phi_{i-1}
+  int elam = 0, Eprev = 0;
+  if constexpr (ADJ0) {
+    double mx = 0.0;
+    for (int i = tid; i < kRedBlocks; i += kThreads) mx = fmax(mx, a.red[i]);
+    mx = block_max(mx);
+    elam = exp_step(mx);
+    if (bid == 0 && tid == 0) a.expo[0] = elam;
+  }
+  if constexpr (ADJ) {
+    elam = a.expo[0];
+    Eprev = a.ck_expo[term - 1];
   }
   // last term: signed scales (-1)^i 2^E_i of the stored terms
   __shared__ double s_sE[MODE == X_LAST ? SWEIK_MAX_TERMS + 1 : 1];
@@ -247,7 +268,99 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     }
   }
 
-  if constexpr (TERMLIKE) odd_c2r<R, H>(v, t, line, twl, tws, w1);
+  if constexpr (TERMLIKE || ADJ) odd_c2r<R, H>(v, t, line, twl, tws, w1);
+
+  // ---- 4a. adjoint pointwise steps (columns c = 2m, 2m+1, m = t + P j) --------
+  // Each chunk of four column pairs reads its operands before any store (a
+  // read after a store would wait for it: the arrays may alias as far as the
+  // compiler knows).
+  if constexpr (ADJ0) {
+    const double lam_scale = ldexp(1.0, -elam);
+    const double sgnT = (a.T & 1) ? -1.0 : 1.0;
+#pragma unroll
+    for (int j0 = 0; j0 < 8; j0 += 4) {
+      R qf[4][2], qs[4][2];
+      double qp[4][2];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int cc = 2 * (t + P * (j0 + jj)) + e;
+          const bool ok = col_ok(cc);
+          qf[jj][e] = ok ? a.f[rowoff + cc] : (R)1;
+          qs[jj][e] = ok ? a.dLdS[rowoff + cc] : (R)0;
+          qp[jj][e] = ok ? a.ck_phi[rowoff + cc] : 1.0;
+        }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        R zz[2] = {(R)0, (R)0};
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int cc = 2 * (t + P * (j0 + jj)) + e;
+          if (col_ok(cc)) {
+            const double fa = (double)qf[jj][e];
+            a.gam[rowoff + cc] = (R)((fa - ft) * (fa + ft) * inv_ft2);
+            const double ph = qp[jj][e];
+            double l = 0.0;
+            if (ph > 0.0 && isfinite(ph)) l = -a.hbar * (double)qs[jj][e] / ph * lam_scale;
+            const R q = (R)l;
+            a.lam[rowoff + cc] = q;
+            zz[e] = (R)(sgnT * (double)q);
+          }
+        }
+        v[j0 + jj] = cmake<C>(zz[0], zz[1]);
+      }
+    }
+#pragma unroll
+    for (int j = 8; j < 16; ++j) v[j] = cmake<C>((R)0, (R)0);
+  }
+  if constexpr (ADJ) {
+    const double gscale = ldexp(1.0, Eprev + elam);
+    const double sgn_prev = ((term - 1) & 1) ? -1.0 : 1.0;  // (-1)^(i-1)
+    const R *mprev = a.terms + (size_t)(term - 1) * ((size_t)a.nlines * a.n2);
+    const R *p2 = term > 1 ? a.gam : a.f;  // gamma, or f at the last step
+#pragma unroll
+    for (int j0 = 0; j0 < 8; j0 += 4) {
+      R q1[4][2], q2[4][2], q3[4][2];
+      double qd[4][2];
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int cc = 2 * (t + P * (j0 + jj)) + e;
+          const bool ok = col_ok(cc);
+          q1[jj][e] = ok ? mprev[rowoff + cc] : (R)0;
+          q2[jj][e] = ok ? p2[rowoff + cc] : (R)0;
+          q3[jj][e] = (ok && term > 1) ? a.lam[rowoff + cc] : (R)0;
+          qd[jj][e] = (ok && term != a.T) ? a.acc[rowoff + cc] : 0.0;
+        }
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) {
+        const int j = j0 + jj;
+        R zz[2] = {(R)0, (R)0};
+        const double bb[2] = {(double)v[j].x, (double)v[j].y};
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int cc = 2 * (t + P * j) + e;
+          if (col_ok(cc)) {
+            // dL/dgamma += phi_{i-1} b_i  (true scale 2^(E_{i-1} + e_lam))
+            const double g = (double)q1[jj][e] * bb[e] * gscale + qd[jj][e];
+            if (term > 1) {
+              a.acc[rowoff + cc] = g;
+              zz[e] = (R)(sgn_prev * (double)q3[jj][e] + (double)q2[jj][e] * bb[e]);
+            } else {
+              // dL/df = dL/dgamma * 2 f / ftilde^2
+              a.dLdf[rowoff + cc] = (R)(g * 2.0 * (double)q2[jj][e] * inv_ft2);
+            }
+          }
+        }
+        v[j] = cmake<C>(zz[0], zz[1]);
+      }
+    }
+    if (term == 1) return;
+#pragma unroll
+    for (int j = 8; j < 16; ++j) v[j] = cmake<C>((R)0, (R)0);
+  }
 
   // ---- 4. pointwise step -------------------------------------------------------
   if constexpr (MODE == X_PHI0 || TERMLIKE) {
@@ -349,7 +462,11 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
         }
         if (last) {
           nbad += write_S(a, rowoff + c0, p0);
-          if (ok1) nbad += write_S(a, rowoff + c0 + 1, p1);
+          if (a.ck_phi) a.ck_phi[rowoff + c0] = p0;
+          if (ok1) {
+            nbad += write_S(a, rowoff + c0 + 1, p1);
+            if (a.ck_phi) a.ck_phi[rowoff + c0 + 1] = p1;
+          }
         } else {
           if (vec)
             *reinterpret_cast<cplx<R> *>(tout + c0) = cmake<cplx<R>>(m0, m1);
