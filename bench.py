@@ -18,7 +18,8 @@ Also reported on the same JSON line:
                    T = 12, FP32-scaled) solved by one replay of a HIP graph
   solve3d          256^3 grid, f from 32 Gaussian blobs in [0.5, 2], one
                    source at the centre, hbar = 0.1, T = 16; FP32-scaled and
-                   FP64, per-kernel classes and the dominant kernel's roofline
+                   FP64, per-kernel classes and the dominant kernel's roofline;
+                   forward with checkpoints + adjoint in FP32
   config1          the 64 x 64 bump workload (h = 1, T = 8) in FP64: latency
                    of an eager solve and of a replay of the solve captured in
                    a HIP graph
@@ -270,7 +271,55 @@ def run_3d(pk, torch, dev, steps, warmup):
                                   "frac": kern[dom]["GBps"] / HBM_PEAK_GBPS},
                      "kernels": kern}
     out["speedup_fp32_over_fp64"] = out["fp64"]["ms_per_step"] / out["fp32"]["ms_per_step"]
-    return out, (p, results)
+
+    # forward with checkpoints + adjoint (FP32) for a loss at 256 receivers
+    # near the source: dL/dS = 2 (S - 0.97 S_0) there, S_0 the first solve
+    f = torch.as_tensor(p.f).to(dev)
+    src = torch.as_tensor(p.src).to(dev)
+    plan = pk.Plan(p.dims, p.h, p.hbar, p.T, len(p.src), "fp32")
+    ws, ck = plan.workspace(dev), plan.checkpoint(dev)
+    S = torch.empty_like(f)
+    dLdf = torch.empty_like(f)
+    rng = np.random.default_rng(11)
+    rec = workloads.receivers_near_sources(p.dims, p.src, 256, 0.25 * p.dims[0], rng)
+    ridx = torch.as_tensor(np.ravel_multi_index(tuple(rec.T), p.dims).astype(np.int64)).to(dev)
+    plan.solve(f, src, S, ws)
+    tgt = 0.97 * S.view(-1)[ridx]
+    dLdS = torch.zeros(N, dtype=torch.float32, device=dev)
+
+    def step():
+        plan.solve(f, src, S, ws, ck)
+        dLdS[ridx] = 2.0 * (S.view(-1)[ridx] - tgt)
+        plan.adjoint(f, src, ck, dLdS.view(p.dims), dLdf, ws)
+
+    for _ in range(max(1, warmup)):
+        step()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream()
+    e0, e1 = _events(torch, st)
+    e0.record(st)
+    for _ in range(steps):
+        step()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    e0.record(st)
+    for _ in range(steps):
+        plan.adjoint(f, src, ck, dLdS.view(p.dims), dLdf, ws)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms_adj = e0.elapsed_time(e1) / steps
+    out["fwd_bwd_fp32"] = {"value": N / (ms * 1e-3), "ms_per_step": ms, "ms_adjoint": ms_adj,
+                           "loss": "sum over 256 receivers near the source of (S - 0.97 S_0)^2",
+                           "gradient_finite": bool(torch.isfinite(dLdf).all().item())}
+
+    def gradient(dLdS_host):
+        d = torch.as_tensor(dLdS_host).to(dev, torch.float32)
+        plan.solve(f, src, S, ws, ck)
+        plan.adjoint(f, src, ck, d, dLdf, ws)
+        return dLdf.double().cpu().numpy()
+
+    return out, (p, results, (rec, gradient))
 
 
 def run_fwd_bwd(pk, torch, dev, steps, warmup):
@@ -821,10 +870,20 @@ def reference_accuracy(gpu, o_main, threads):
         out["far_field"] = res
     if "solve3d" in gpu:
         progress("accuracy: solve3d")
-        p3, r3 = gpu["solve3d"]
-        o3 = oracle.solve(p3.f.astype(np.float64), p3.src, p3.h, p3.hbar, p3.T, nthreads=threads)
+        p3, r3, (rec3, gradient3) = gpu["solve3d"]
+        f3 = p3.f.astype(np.float64)
+        o3 = oracle.solve(f3, p3.src, p3.h, p3.hbar, p3.T, nthreads=threads)
         out["solve3d"] = {"workload": "blobs3d_256x256x256_T16",
                           **{k: accuracy(v, o3, p3.hbar, k) for k, v in r3.items()}}
+        # the gradient of the same kind of loss, formed from the oracle's S
+        idx = tuple(rec3.T)
+        dLdS3 = np.zeros(p3.dims)
+        dLdS3[idx] = 2.0 * (o3["S"][idx] - 0.97 * o3["S"][idx])
+        g_o, _ = oracle.adjoint(f3, p3.src, p3.h, p3.hbar, p3.T, dLdS3, nthreads=threads)
+        g3 = gradient3(dLdS3)
+        out["solve3d"]["gradient_fp32"] = {
+            "normwise_rel": float(np.linalg.norm(g3 - g_o) / np.linalg.norm(g_o)), "tol": 1e-3,
+            "dLdS": "2 (S - 0.97 S) at 256 receivers near the source, S the oracle's"}
     return out
 
 
