@@ -186,6 +186,7 @@ sweik_status sweik_solve_seeded(sweik_plan plan, const void *f,
  *          kernel spectrum ((H1 + 1) M0 complex values), T stored terms, S
  *          and a float score per point (about 9 N values of the plan's
  *          precision plus T N per tilt), plus the tilts' work lists
+ *   src_s  device, nullable: values of S at the sources, as sweik_solve_seeded
  *   f, src, S, stream, info as sweik_solve (no checkpoint); info counts the
  *          points that no tilt resolved (S = +inf) and reports the first
  *          tilt's term scales.
@@ -199,9 +200,10 @@ sweik_status sweik_solve_seeded(sweik_plan plan, const void *f,
  * SWEIK_EUNSUPPORTED in 3D (sweik_tilted_workspace_bytes returns 0 there
  * and for n_tilt out of range). */
 size_t sweik_tilted_workspace_bytes(sweik_plan plan, int32_t n_tilt);
-sweik_status sweik_solve_tilted(sweik_plan plan, const void *f, const int32_t *src, void *S,
-                                const double *tilts, int32_t n_tilt, int32_t per_source, void *ws,
-                                size_t ws_bytes, void *stream, sweik_info *info);
+sweik_status sweik_solve_tilted(sweik_plan plan, const void *f, const int32_t *src,
+                                const void *src_s, void *S, const double *tilts, int32_t n_tilt,
+                                int32_t per_source, void *ws, size_t ws_bytes, void *stream,
+                                sweik_info *info);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid device allocation): sweik_solve

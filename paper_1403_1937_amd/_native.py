@@ -83,7 +83,7 @@ def load_library():
     lib.sweik_solve_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
     lib.sweik_tilted_workspace_bytes.argtypes = [vp, C.c_int32]
     lib.sweik_tilted_workspace_bytes.restype = sz
-    lib.sweik_solve_tilted.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), C.c_int32,
+    lib.sweik_solve_tilted.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_double), C.c_int32,
                                        C.c_int32, vp, sz, vp, vp]
     lib.sweik_noalloc_scratch_bytes.restype = sz
     lib.sweik_solve_adjoint.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
@@ -234,14 +234,19 @@ class Plan:
 
     def solve_tilted(self, f: torch.Tensor, src: torch.Tensor, S: torch.Tensor, ws: torch.Tensor,
                      tilts, info: Optional[torch.Tensor] = None, stream=None,
-                     per_source: bool = False):
+                     per_source: bool = False, src_s: Optional[torch.Tensor] = None):
         """Enqueue the far-field stabilised solve (sweik_solve_tilted):
         tilts is a host sequence of (tilt0, tilt1) pairs in units of beta;
-        per_source splits the solve over the sources; ws must hold
+        per_source splits the solve over the sources; src_s: device values
+        of S at the sources (dtype of f); ws must hold
         tilted_workspace_bytes(len(tilts))."""
+        if src_s is not None and (src_s.dtype != f.dtype or src_s.numel() != self.n_src
+                                  or not src_s.is_contiguous()):
+            raise ValueError("src_s must be a contiguous tensor of n_src values of f's dtype")
         t = np.ascontiguousarray(np.asarray(tilts, np.float64).reshape(-1, 2))
         _check(self._lib.sweik_solve_tilted(
-            self._h, f.data_ptr(), src.data_ptr(), S.data_ptr(),
+            self._h, f.data_ptr(), src.data_ptr(),
+            src_s.data_ptr() if src_s is not None else None, S.data_ptr(),
             t.ctypes.data_as(C.POINTER(C.c_double)), len(t), int(bool(per_source)), ws.data_ptr(),
             ws.numel(), _stream_ptr(stream), info.data_ptr() if info is not None else None),
             "sweik_solve_tilted")
@@ -363,11 +368,13 @@ def default_tilts(directions: int = 8, strength: float = 0.9):
 
 def solve_tilted(f: torch.Tensor, src, h: float, hbar: float, T: int, tilts=None,
                  ftilde_mode: str = "nu", ftilde: Optional[float] = None,
-                 return_info: bool = False, stream=None, per_source: bool = False):
+                 return_info: bool = False, stream=None, per_source: bool = False,
+                 src_s=None):
     """Far-field stabilised S (2D): the series solved once per tilt, each
     point from the best-conditioned tilt (sweik_solve_tilted).  tilts:
     (tilt0, tilt1) pairs in units of beta, default default_tilts();
-    per_source: one tilted solve per source, summed (n_src times the cost)."""
+    per_source: one tilted solve per source, summed (n_src times the cost);
+    src_s: values of S at the sources (default 0)."""
     _check_f(f)
     pl = _plan_for(f, len(src), h, hbar, T, ftilde_mode, ftilde)
     d_src = _src_to_device(src, pl, f.device)
@@ -375,7 +382,10 @@ def solve_tilted(f: torch.Tensor, src, h: float, hbar: float, T: int, tilts=None
     tilts = default_tilts() if tilts is None else tilts
     ws = torch.empty(pl.tilted_workspace_bytes(len(tilts)), dtype=torch.uint8, device=f.device)
     info = torch.zeros(C.sizeof(_Info), dtype=torch.uint8, device=f.device) if return_info else None
-    pl.solve_tilted(f, d_src, S, ws, tilts, info, stream, per_source=per_source)
+    d_s = None
+    if src_s is not None:
+        d_s = torch.as_tensor(np.asarray(src_s, np.float64)).to(f.device, f.dtype).contiguous()
+    pl.solve_tilted(f, d_src, S, ws, tilts, info, stream, per_source=per_source, src_s=d_s)
     if return_info:
         return S, _read_info(info)
     return S

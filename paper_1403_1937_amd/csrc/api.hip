@@ -410,12 +410,13 @@ TiltWs tilt_ws(const sweik_plan_s *pl, int n_tilt) {
 // from the sum.
 template <typename R>
 sweik_status enqueue2d_tilted(const sweik_plan_s *pl, const void *f, const int32_t *src,
-                              void *S, const double *tilts, int n_tilt, bool per_source, void *ws,
-                              hipStream_t st, sweik_info *info) {
+                              const void *src_s, void *S, const double *tilts, int n_tilt,
+                              bool per_source, void *ws, hipStream_t st, sweik_info *info) {
   const Geo2 &g = pl->g2;
   const TiltWs tw = tilt_ws(pl, n_tilt);
   unsigned char *w = (unsigned char *)ws;
   Args2<R> a = make_args2<R>(pl, f, src, S, ws, nullptr, info);
+  a.src_s = (const R *)src_s;
   TiltTable tt;
   for (int d = 0; d < SWEIK_MAX_TILTS; ++d) {
     tt.t[2 * d] = d < n_tilt ? tilts[2 * d] : 0.0;
@@ -431,7 +432,10 @@ sweik_status enqueue2d_tilted(const sweik_plan_s *pl, const void *f, const int32
   const int parts = per_source && nsrc > 1 ? nsrc : 1;
   if (parts > 1) a.n_src = 1;
   for (int k = 0; k < parts && err == hipSuccess; ++k) {
-    if (parts > 1) a.src = src + 2 * k;
+    if (parts > 1) {
+      a.src = src + 2 * k;
+      a.src_s = src_s ? (const R *)src_s + k : nullptr;
+    }
     err = launch_tilt_items<R>(a, tt, n_tilt, slices, tw.sl, rows, negs, cols, st);
     // the tilted kernels' spectra: table rows m0 >= 0 into spec, m0 <= 0
     // into spec_neg, then the complex column transforms into gc
@@ -1094,9 +1098,10 @@ size_t sweik_tilted_workspace_bytes(sweik_plan plan, int32_t n_tilt) {
   return tilt_ws(plan, n_tilt).total;
 }
 
-sweik_status sweik_solve_tilted(sweik_plan plan, const void *f, const int32_t *src, void *S,
-                                const double *tilts, int32_t n_tilt, int32_t per_source, void *ws,
-                                size_t ws_bytes, void *stream, sweik_info *info) {
+sweik_status sweik_solve_tilted(sweik_plan plan, const void *f, const int32_t *src,
+                                const void *src_s, void *S, const double *tilts, int32_t n_tilt,
+                                int32_t per_source, void *ws, size_t ws_bytes, void *stream,
+                                sweik_info *info) {
   if (!plan || !f || !src || !S || !ws || !tilts) return SWEIK_EINVAL;
   if (plan->p.ndim != 2) return SWEIK_EUNSUPPORTED;
   if (n_tilt < 1 || n_tilt > SWEIK_MAX_TILTS) return SWEIK_EINVAL;
@@ -1108,10 +1113,12 @@ sweik_status sweik_solve_tilted(sweik_plan plan, const void *f, const int32_t *s
   hipStream_t st = (hipStream_t)stream;
   const bool f64 = plan->p.prec == SWEIK_F64;
   if (plan->p.T == 0)  // phi = phi_0 in closed form: nothing for a tilt to stabilise
-    return f64 ? enqueue2d<double>(plan, f, src, S, ws, nullptr, st, info)
-               : enqueue2d<float>(plan, f, src, S, ws, nullptr, st, info);
-  return f64 ? enqueue2d_tilted<double>(plan, f, src, S, tilts, n_tilt, per_source != 0, ws, st, info)
-             : enqueue2d_tilted<float>(plan, f, src, S, tilts, n_tilt, per_source != 0, ws, st, info);
+    return f64 ? enqueue2d<double>(plan, f, src, S, ws, nullptr, st, info, nullptr, src_s)
+               : enqueue2d<float>(plan, f, src, S, ws, nullptr, st, info, nullptr, src_s);
+  return f64 ? enqueue2d_tilted<double>(plan, f, src, src_s, S, tilts, n_tilt, per_source != 0, ws,
+                                        st, info)
+             : enqueue2d_tilted<float>(plan, f, src, src_s, S, tilts, n_tilt, per_source != 0, ws,
+                                       st, info);
 }
 
 size_t sweik_noalloc_scratch_bytes(void) { return kScratchBytes; }

@@ -238,7 +238,7 @@ def test_tilted_entry_checks(lib):
 
     def call(tilts, n=None, ws_bytes=None, plan=p):
         t = np.ascontiguousarray(np.asarray(tilts, np.float64).reshape(-1, 2))
-        return lib.sweik_solve_tilted(plan.handle, vp(16), vp(16), vp(16),
+        return lib.sweik_solve_tilted(plan.handle, vp(16), vp(16), None, vp(16),
                                       t.ctypes.data_as(D), len(t) if n is None else n, 0, vp(16),
                                       need if ws_bytes is None else ws_bytes, None, None)
     assert call([(0.0, 0.0)], n=0) == 1
@@ -247,8 +247,8 @@ def test_tilted_entry_checks(lib):
     assert call([(0.8, 0.7)]) == 1
     assert call([(float("nan"), 0.0)]) == 1
     assert call([(0.0, 0.0)], ws_bytes=need - 1) == 3
-    assert lib.sweik_solve_tilted(p.handle, None, vp(16), vp(16), None, 1, 0, vp(16), need, None,
-                                  None) == 1
+    assert lib.sweik_solve_tilted(p.handle, None, vp(16), None, vp(16), None, 1, 0, vp(16), need,
+                                  None, None) == 1
     cube = _plan(dims=(16, 16, 16))
     assert lib.sweik_tilted_workspace_bytes(cube.handle, 1) == 0
     assert call([(0.0, 0.0)], plan=cube) == 2
