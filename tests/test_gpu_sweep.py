@@ -56,3 +56,36 @@ def test_sweep(ndim, k, prec):
     assert worst <= TOL[prec]
     assert envelope_violations(S, o, hbar, prec) == 0
     assert info["n_nonpositive_phi"] == int(np.isinf(S).sum())
+
+
+def _dLdS_near(dims, src, S_o, rng, count=16):
+    rec = workloads.receivers_near_sources(dims, src, count, 0.2 * max(dims), rng)
+    g = np.zeros(dims)
+    for r in rec:
+        g[tuple(r)] = 2.0 * 0.03 * S_o[tuple(r)]  # loss sum (S - 0.97 S_o)^2 at S = S_o
+    return g
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-3)])
+@pytest.mark.parametrize("ndim,k", [(2, k) for k in range(8)] + [(3, k) for k in range(4)])
+def test_sweep_adjoint(ndim, k, prec, tol):
+    """The adjoint (f~ fixed) on the sweep's shapes with T >= 1, against the
+    oracle's adjoint: normwise relative error."""
+    import paper_1403_1937_amd as pk
+    dims, T, f, src, s, h, hbar, mode, ft = _case(ndim, k)
+    T = max(T, 1)
+    hbar = max(hbar, 0.05)  # receivers where phi is far above rounding noise
+    rng = np.random.default_rng(7 + k)
+    o = oracle.solve(f, src, h, hbar, T, ft_mode=mode, ftilde=ft)
+    if min(dims) < 3 or int(np.prod(dims)) < 64:
+        pytest.skip("too few points for receivers")
+    dLdS = _dLdS_near(dims, src, o["S"], rng)
+    g_o, _ = oracle.adjoint(f, src, h, hbar, T, dLdS, ft_mode=mode, ftilde=ft)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    print(f"adjoint sweep {ndim}D {dims} T={T} {mode} {prec}", flush=True)
+    g = pk.solve_adjoint(torch.as_tensor(f).to("cuda", dt), src, h, hbar, T,
+                         torch.as_tensor(dLdS).to("cuda", dt), ftilde_mode=mode, ftilde=ft)
+    g = g.double().cpu().numpy()
+    err = np.linalg.norm(g - g_o) / np.linalg.norm(g_o)
+    print(f"  normwise rel {err:.2e}", flush=True)
+    assert err <= tol
