@@ -1,4 +1,4 @@
-"""Plain FP64 oracle of the full gradient of a loss L(S) of the 2D solve.
+"""Plain FP64 oracle of the full gradient of a loss L(S) of the 2D or 3D solve.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).  Not in the paper: the
 derivative of the steps of Table 1 with respect to all of their inputs,
@@ -28,19 +28,30 @@ import oracle
 
 
 def kappa_dbeta(dims, beta: float) -> np.ndarray:
-    """d kappa / d beta on the orthant 0 <= m_d < n_d (2D):
-    (beta/pi) K0(beta r) - (beta^2 r / 2 pi) K1(beta r) off the origin; at
-    the origin the beta-derivative of the ball average 1 - a K1(a),
-    a = beta/sqrt(pi), which is (beta/pi) K0(beta/sqrt(pi))."""
-    n0, n1 = (int(d) for d in dims)
-    m0, m1 = np.meshgrid(np.arange(n0, dtype=np.float64), np.arange(n1, dtype=np.float64),
-                         indexing="ij")
-    r = np.hypot(m0, m1)
-    out = np.zeros((n0, n1))
+    """d kappa / d beta on the orthant 0 <= m_d < n_d.
+    2D: (beta/pi) K0(beta r) - (beta^2 r / 2 pi) K1(beta r) off the origin;
+    at the origin the beta-derivative of the ball average 1 - a K1(a),
+    a = beta/sqrt(pi), which is (beta/pi) K0(beta/sqrt(pi)).
+    3D: kappa = beta^2 exp(-beta r) / (4 pi r) gives
+    beta exp(-beta r) (2 - beta r) / (4 pi r); at the origin the ball
+    average 1 - (1 + a) exp(-a), a = c beta, c = (3/(4 pi))^(1/3), has the
+    derivative c a exp(-a)."""
+    dims = tuple(int(d) for d in dims)
+    grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in dims], indexing="ij")
+    r = np.sqrt(sum(g * g for g in grids))
+    out = np.zeros(dims)
     nz = r > 0
-    x = beta * r[nz]
-    out[nz] = beta / np.pi * oracle.k0(x) - beta * beta * r[nz] / (2 * np.pi) * oracle.k1(x)
-    out[0, 0] = beta / np.pi * float(oracle.k0(beta / np.sqrt(np.pi)))
+    if len(dims) == 2:
+        x = beta * r[nz]
+        out[nz] = beta / np.pi * oracle.k0(x) - beta * beta * r[nz] / (2 * np.pi) * oracle.k1(x)
+        out[(0,) * 2] = beta / np.pi * float(oracle.k0(beta / np.sqrt(np.pi)))
+    elif len(dims) == 3:
+        rr = r[nz]
+        out[nz] = beta * np.exp(-beta * rr) * (2.0 - beta * rr) / (4 * np.pi * rr)
+        c = (3.0 / (4.0 * np.pi)) ** (1.0 / 3.0)
+        out[(0,) * 3] = c * c * beta * np.exp(-c * beta)
+    else:
+        raise ValueError("2D or 3D")
     return out
 
 
@@ -50,16 +61,13 @@ def conv_table(x: np.ndarray, table: np.ndarray) -> np.ndarray:
     dims = x.shape
     M = oracle.pad_sizes(dims)
     K = np.zeros(M)
-    n0, n1 = dims
-    for s0 in (1, -1):
-        for s1 in (1, -1):
-            i0 = (s0 * np.arange(n0)) % M[0]
-            i1 = (s1 * np.arange(n1)) % M[1]
-            K[np.ix_(i0, i1)] = table
+    for signs in np.ndindex(*(2,) * len(dims)):
+        idx = [((1 - 2 * s) * np.arange(n)) % m for s, n, m in zip(signs, dims, M)]
+        K[np.ix_(*idx)] = table
     X = np.zeros(M)
-    X[:n0, :n1] = x
-    y = np.fft.ifft2(np.fft.fft2(X) * np.fft.fft2(K)).real
-    return y[:n0, :n1]
+    X[tuple(slice(0, n) for n in dims)] = x
+    y = np.fft.ifftn(np.fft.fftn(X) * np.fft.fftn(K)).real
+    return y[tuple(slice(0, n) for n in dims)]
 
 
 def full_gradient(f: np.ndarray, src: np.ndarray, h: float, hbar: float, T: int,
@@ -67,7 +75,8 @@ def full_gradient(f: np.ndarray, src: np.ndarray, h: float, hbar: float, T: int,
                   src_s: Optional[np.ndarray] = None) -> dict:
     f = np.asarray(f, np.float64)
     dims = f.shape
-    src = np.asarray(src, np.int32).reshape(-1, 2)
+    nd = f.ndim
+    src = np.asarray(src, np.int32).reshape(-1, nd)
     dLdS = np.asarray(dLdS, np.float64)
     lo, hi = float(f.min()), float(f.max())
     ft = {"nu": np.sqrt(0.5 * (lo * lo + hi * hi)), "fmax": hi, "given": ftilde}[ft_mode]
@@ -95,9 +104,8 @@ def full_gradient(f: np.ndarray, src: np.ndarray, h: float, hbar: float, T: int,
     dLdf = dLdg * 2.0 * f / (ft * ft)
 
     # forward tangents of the three scalar paths
-    m0, m1 = np.meshgrid(np.arange(dims[0], dtype=np.float64),
-                         np.arange(dims[1], dtype=np.float64), indexing="ij")
-    dist = [np.hypot(m0 - y[0], m1 - y[1]) for y in src]
+    grids = np.meshgrid(*[np.arange(n, dtype=np.float64) for n in dims], indexing="ij")
+    dist = [np.sqrt(sum((g - yd) ** 2 for g, yd in zip(grids, y))) for y in src]
     ex = [np.exp(-beta * d) for d in dist]
     dkap = kappa_dbeta(dims, beta)
     dgam = -2.0 * f * f / ft ** 3
