@@ -309,9 +309,24 @@ def run_3d(pk, torch, dev, steps, warmup):
     e1.record(st)
     torch.cuda.synchronize()
     ms_adj = e0.elapsed_time(e1) / steps
+    # the full gradient (ftilde(f) and hbar as well) after the same forward
+    wsf = torch.empty(plan.adjoint_full_workspace_bytes, dtype=torch.uint8, device=dev)
+    grads = torch.zeros(4, dtype=torch.float64, device=dev)
+    plan.solve(f, src, S, wsf, ck)
+    for _ in range(max(1, warmup)):
+        plan.adjoint_full(f, src, ck, dLdS.view(p.dims), dLdf, grads, wsf)
+    torch.cuda.synchronize()
+    e0.record(st)
+    for _ in range(steps):
+        plan.adjoint_full(f, src, ck, dLdS.view(p.dims), dLdf, grads, wsf)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms_full = e0.elapsed_time(e1) / steps
     out["fwd_bwd_fp32"] = {"value": N / (ms * 1e-3), "ms_per_step": ms, "ms_adjoint": ms_adj,
+                           "ms_adjoint_full": ms_full,
                            "loss": "sum over 256 receivers near the source of (S - 0.97 S_0)^2",
-                           "gradient_finite": bool(torch.isfinite(dLdf).all().item())}
+                           "gradient_finite": bool(torch.isfinite(dLdf).all().item()),
+                           "full_gradient_dLdhbar": float(grads[0].item())}
 
     def gradient(dLdS_host):
         d = torch.as_tensor(dLdS_host).to(dev, torch.float32)

@@ -234,7 +234,7 @@ sweik_status sweik_solve_adjoint(sweik_plan plan, const void *f,
                                  const void *dLdS, void *dLdf, void *ws,
                                  size_t ws_bytes, void *stream);
 
-/* Full gradient (2D) of a loss L(S) of a solve: not in the paper, the
+/* Full gradient (2D and 3D) of a loss L(S) of a solve: not in the paper, the
  * derivative of all of its steps.  With beta = ftilde h / hbar,
  * gamma = f^2/ftilde^2 - 1 and w_k = exp(-s_k / hbar):
  *   dLdf   device, dims, type of f (output): dL/df including the dependence
@@ -249,9 +249,9 @@ sweik_status sweik_solve_adjoint(sweik_plan plan, const void *f,
  *          (sweik_solve_seeded); ckpt its checkpoint
  *   ws     device workspace of ws_bytes >= sweik_adjoint_full_workspace_bytes
  * The beta-derivative of the kernel (2D: (beta/pi) K0(x) - (beta/2pi) x
- * K1(x), x = beta|m|; at the origin that of the ball average) is convolved
- * with every adjoint term, so the sweep costs about 1.7 adjoints.
- * SWEIK_EUNSUPPORTED in 3D. */
+ * K1(x), x = beta|m|; 3D: beta e^{-x} (2 - x) / (4 pi |m|); at the origin
+ * that of the cell average) is convolved with every adjoint term, so the
+ * sweep costs about 1.7 adjoints (3D: two y, z, y chains per term). */
 size_t sweik_adjoint_full_workspace_bytes(sweik_plan plan);
 sweik_status sweik_solve_adjoint_full(sweik_plan plan, const void *f, const int32_t *src,
                                       const void *src_s, const void *ckpt, const void *dLdS,

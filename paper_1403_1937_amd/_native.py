@@ -475,7 +475,7 @@ def solve_adjoint(f: torch.Tensor, src, h, hbar, T, dLdS: torch.Tensor, ftilde_m
 
 def solve_gradient(f: torch.Tensor, src, h, hbar, T, dLdS: torch.Tensor, ftilde_mode="nu",
                    ftilde=None, src_s=None, stream=None):
-    """Full gradient of a loss with gradient dLdS w.r.t. S (2D): returns
+    """Full gradient of a loss with gradient dLdS w.r.t. S (2D or 3D): returns
     (dL/df including the dependence of ftilde on f, {"dLdhbar", "dLdftilde",
     "dLdbeta"}).  src_s: values of S at the sources (default 0)."""
     _check_f(f)

@@ -593,6 +593,13 @@ sweik_status plan3d(sweik_plan_s *pl) {
   L.gam = take((size_t)esz * N);
   L.lam = take((size_t)esz * N);
   L.total = off;
+  // full gradient: the kernel's beta-derivative spectrum, the second x-pass
+  // spectrum, the per-work-group partial sums and the argmin / argmax partials
+  L.g0 = take((size_t)esz * (g.H1 + 1) * (g.H0 + 1) * g.H2);
+  L.fg_spec2 = take((size_t)csz * g.nlines * g.H2);
+  L.fg_part = take(sizeof(double) * kGradSlots * g.nbx);
+  L.fg_ext = take(sizeof(long long) * 2 * kRedBlocks);
+  L.fg_total = off;
   // checkpoint of a solve for its adjoint: scalars, kernel spectrum, term
   // exponents, phi in float64 and the stored terms
   off = 0;
@@ -644,6 +651,9 @@ Args3<R> make_args3(const sweik_plan_s *pl, const void *f, const int32_t *src, v
   a.tw = (const cplx<R> *)(w + L.tw);
   a.s1 = (cplx<R> *)(w + L.spec);
   a.s2 = (cplx<R> *)(w + L.s2);
+  a.s1o = a.s1;
+  a.s1b = nullptr;
+  a.gpart = nullptr;
   a.g = (R *)(w + L.g);
   a.terms = (R *)(w + L.terms);
   a.gam = (R *)(w + L.gam);
@@ -731,6 +741,58 @@ sweik_status enqueue3d_adjoint(const sweik_plan_s *pl, const void *f, const int3
     if (err == hipSuccess) err = launch_c3<R>(C3_YI, g.M1, ny, st, a, -1);
     if (err == hipSuccess) err = launch_x3<R>(X_ADJ, g.H2, g.nbx, st, a, i);
   }
+  return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
+}
+
+// Full gradient (3D): the adjoint sweep of enqueue3d_adjoint with every
+// convolution of a_i done twice, first with the kernel's beta-derivative
+// (its y inverse pass writes the second spectrum s1b), then with the kernel;
+// the x passes form the scalar partial sums; then the argmin / argmax of f
+// and the scalar derivatives.
+template <typename R>
+sweik_status enqueue3d_adjoint_full(const sweik_plan_s *pl, const void *f, const int32_t *src,
+                                    const void *src_s, const void *ckpt, const void *dLdS,
+                                    void *dLdf, double *grads, void *ws, hipStream_t st) {
+  const Geo3 &g = pl->g3;
+  const Layout &L = pl->ws;
+  char *w = (char *)ws;
+  Args3<R> a = make_args3<R>(pl, f, src, nullptr, ws, nullptr, const_cast<void *>(ckpt));
+  a.src_s = (const R *)src_s;
+  a.dLdS = (const R *)dLdS;
+  a.dLdf = (R *)dLdf;
+  a.s1b = (cplx<R> *)(w + L.fg_spec2);
+  a.gpart = (double *)(w + L.fg_part);
+  // the same arguments with the beta-derivative's kernel spectrum and output
+  Args3<R> ab = a;
+  ab.g = (R *)(w + L.g0);
+  ab.s1o = a.s1b;
+  const long long N = (long long)g.n0 * g.n1 * g.n2;
+  const int T = pl->p.T;
+  const int ny = g.n0 * g.ncb1;
+  hipError_t err = launch_adj_prep<R>((const R *)dLdS, (const double *)a.ck_phi, N, pl->p.hbar,
+                                      a.red, (cplx<R> *)a.tw, g.lmax, st);
+  if (T == 0) {
+    if (err == hipSuccess) err = launch_fill<R>((R *)dLdf, N, (R)0, st);
+    if (err == hipSuccess) err = launch_x3<R>(X_ADJ0_B, g.H2, g.nbx, st, a, 0);
+  } else {
+    // spectrum of dkappa/dbeta (x pass into s1, y and z passes into g0)
+    if (err == hipSuccess) err = launch_x3<R>(X_DGHAT, g.H2, g.nbx, st, ab, 0);
+    if (err == hipSuccess) err = launch_c3<R>(C3_GY, g.M1, ny, st, ab, -1);
+    if (err == hipSuccess) err = launch_c3<R>(C3_GZ, g.M0, (g.H1 + 1) * g.ncb0, st, ab, -1);
+    if (err == hipSuccess) err = launch_x3<R>(X_ADJ0_B, g.H2, g.nbx, st, a, T);
+    for (int i = T; i >= 1 && err == hipSuccess; --i) {
+      for (const Args3<R> *q : {&ab, &a}) {
+        if (err == hipSuccess) err = launch_c3<R>(C3_YF, g.M1, ny, st, *q, -1);
+        if (err == hipSuccess) err = launch_c3<R>(C3_Z, g.M0, g.M1 * g.ncb0, st, *q, -1);
+        if (err == hipSuccess) err = launch_c3<R>(C3_YI, g.M1, ny, st, *q, -1);
+      }
+      if (err == hipSuccess) err = launch_x3<R>(X_ADJ_B, g.H2, g.nbx, st, a, i);
+    }
+  }
+  if (err == hipSuccess)
+    err = launch_adj_full_finish<R>((const R *)f, N, a.par, a.gpart, g.nbx,
+                                    (long long *)(w + L.fg_ext), pl->p.ft_mode, pl->p.h,
+                                    pl->p.hbar, (R *)dLdf, grads, st);
   return err == hipSuccess ? SWEIK_OK : SWEIK_EDEVICE;
 }
 
@@ -1183,7 +1245,7 @@ sweik_status sweik_solve_adjoint(sweik_plan plan, const void *f, const int32_t *
 }
 
 size_t sweik_adjoint_full_workspace_bytes(sweik_plan plan) {
-  if (!plan || plan->p.ndim != 2) return 0;
+  if (!plan) return 0;
   return plan->ws.fg_total;
 }
 
@@ -1192,9 +1254,12 @@ sweik_status sweik_solve_adjoint_full(sweik_plan plan, const void *f, const int3
                                       void *dLdf, double *grads, void *ws, size_t ws_bytes,
                                       void *stream) {
   if (!plan || !f || !src || !ckpt || !dLdS || !dLdf || !ws) return SWEIK_EINVAL;
-  if (plan->p.ndim != 2) return SWEIK_EUNSUPPORTED;
   if (ws_bytes < plan->ws.fg_total) return SWEIK_EWORKSPACE;
   hipStream_t st = (hipStream_t)stream;
+  if (plan->p.ndim == 3)
+    return plan->p.prec == SWEIK_F64
+               ? enqueue3d_adjoint_full<double>(plan, f, src, src_s, ckpt, dLdS, dLdf, grads, ws, st)
+               : enqueue3d_adjoint_full<float>(plan, f, src, src_s, ckpt, dLdS, dLdf, grads, ws, st);
   return plan->p.prec == SWEIK_F64
              ? enqueue2d_adjoint_full<double>(plan, f, src, src_s, ckpt, dLdS, dLdf, grads, ws, st)
              : enqueue2d_adjoint_full<float>(plan, f, src, src_s, ckpt, dLdS, dLdf, grads, ws, st);

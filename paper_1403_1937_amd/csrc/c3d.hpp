@@ -9,7 +9,7 @@
 //          kernel spectrum g[min(k1, M1-k1)][min(k0, M0-k0)][k2], inverse
 //          FFT, first n0 rows back into s2
 //   C3_YI  plane i0: inverse FFT along axis 1 of the M1 rows of s2 -> first
-//          n1 rows of s1
+//          n1 rows of s1o (s1, or a second spectrum of the full gradient)
 //   C3_GY  kernel spectrum, plane d0: even extension along axis 1 of the
 //          kernel table's line transforms, FFT, real part of k1 <= H1 -> s2
 //   C3_GZ  kernel spectrum, plane k1 <= H1: even extension along axis 0,
@@ -129,7 +129,7 @@ __device__ __forceinline__ void c3_pass(const Args3<R> &a, int term, unsigned ch
       if (FULL || p < a.n0) io[(size_t)p * st] = v[j];
     }
   } else if constexpr (MODE == C3_YI) {
-    C *out = a.s1 + (size_t)plane * a.n1 * H2 + k2;
+    C *out = a.s1o + (size_t)plane * a.n1 * H2 + k2;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const int p = t + P * j;

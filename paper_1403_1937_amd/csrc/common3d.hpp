@@ -34,7 +34,12 @@ namespace sweik {
 // X_LAST: the pass after the last convolution (float64 sum of the stored
 // terms and the log), its own kernel so that X_TERM is not sized for it.
 // X_ADJ0, X_ADJ: the adjoint sweep's start and steps (see x3d.hpp).
-enum XMode { X_GHAT = 0, X_PHI0 = 1, X_TERM = 2, X_LAST = 3, X_ADJ0 = 4, X_ADJ = 5 };
+// X_DGHAT, X_ADJ0_B, X_ADJ_B: the same for the full gradient (the kernel's
+// beta-derivative table, and the sweep with the scalar partial sums).
+enum XMode {
+  X_GHAT = 0, X_PHI0 = 1, X_TERM = 2, X_LAST = 3, X_ADJ0 = 4, X_ADJ = 5,
+  X_DGHAT = 6, X_ADJ0_B = 7, X_ADJ_B = 8
+};
 enum C3Mode { C3_YF = 0, C3_Z = 1, C3_YI = 2, C3_GY = 3, C3_GZ = 4 };
 
 // x pass: one team of P = H2/16 threads per line, 256 threads per group
@@ -70,9 +75,11 @@ template <typename R> constexpr int c3_threads(int M) { return c3_cpw<R>(M) * (M
 // static shared memory of an x pass (reductions, scalars, term scales; phi_0
 // also holds up to 512 sources and their weights), at least what the compiled
 // kernels declare (group segment of the code objects: 1184 bytes for the
-// other modes; phi_0 16640 in float, 20736 in double), and of a column pass
+// other modes, 512 more for the full gradient's partial sums; phi_0 16640
+// in float, 20736 in double), and of a column pass
 template <typename R> constexpr size_t x_lds_static(int mode) {
-  return mode == X_PHI0 ? (sizeof(R) == 4 ? 17408 : 21504) : 1536;
+  return mode == X_PHI0 ? (sizeof(R) == 4 ? 17408 : 21504)
+         : (mode == X_ADJ0_B || mode == X_ADJ_B) ? 2048 : 1536;
 }
 constexpr size_t kC3LdsStatic = 512;
 template <typename R> constexpr size_t c3_lds_bytes(int M) {
@@ -100,6 +107,8 @@ template <typename R> struct Args3 {
   int *expo;       // T+1 exponents
   const cplx<R> *tw;
   cplx<R> *s1, *s2;
+  cplx<R> *s1o;    // where the y inverse pass writes (s1, or the full gradient's s1b)
+  cplx<R> *s1b;    // full gradient: dkappa/dbeta (*) a_i after the y inverse pass
   R *g;            // kernel spectrum orthant
   R *terms;        // T x N mantissas of phi_0..phi_{T-1} (the checkpoint's when kept)
   R *gam;          // N
@@ -112,6 +121,7 @@ template <typename R> struct Args3 {
   R *dLdf;
   R *lam;          // N, lambda mantissas (scale 2^expo[0])
   double *acc;     // N, dL/dgamma in float64
+  double *gpart;   // full gradient: kGradSlots x nbx per-work-group partial sums
 };
 
 }  // namespace sweik

@@ -266,6 +266,20 @@ __device__ inline double kappa_3d(double beta, long long r2, double k0v) {
   return beta * beta * exp(-beta * r) / (4.0 * kPi * r);
 }
 
+// d kappa / d beta at an integer offset (3D), for the gradient with respect
+// to beta: off the origin beta e^{-beta r} (2 - beta r) / (4 pi r); at the
+// origin that of the ball average 1 - (1 + a) e^{-a}, a = c beta,
+// c = (3 / (4 pi))^(1/3), which is c a e^{-a}.  Float64 for either precision
+// (evaluated once per gradient).
+__device__ inline double dkappa_3d(double beta, long long r2) {
+  if (r2 == 0) {
+    const double c = cbrt(3.0 / (4.0 * kPi));
+    return c * c * beta * exp(-c * beta);
+  }
+  const double r = sqrt((double)r2);
+  return beta * exp(-beta * r) * (2.0 - beta * r) / (4.0 * kPi * r);
+}
+
 // the 3D kernel in the working precision: float32 evaluation (hardware exp2,
 // relative error ~1e-6 at beta |m| ~ 25) for the float32 spectrum, which
 // stores it rounded to float anyway

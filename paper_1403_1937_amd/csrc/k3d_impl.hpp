@@ -48,6 +48,9 @@ hipError_t launch_x3(int mode, int H, int nblocks, hipStream_t st, const Args3<R
     case X_LAST: return x3_mode<R, X_LAST>(H, nblocks, st, a, term);
     case X_ADJ0: return x3_mode<R, X_ADJ0>(H, nblocks, st, a, term);
     case X_ADJ: return x3_mode<R, X_ADJ>(H, nblocks, st, a, term);
+    case X_DGHAT: return x3_mode<R, X_DGHAT>(H, nblocks, st, a, term);
+    case X_ADJ0_B: return x3_mode<R, X_ADJ0_B>(H, nblocks, st, a, term);
+    case X_ADJ_B: return x3_mode<R, X_ADJ_B>(H, nblocks, st, a, term);
   }
   return hipErrorInvalidValue;
 }

@@ -36,7 +36,8 @@ struct Layout {      // byte offsets into the workspace / checkpoint
   size_t ck_expo, ck_par, ck_g, ck_phi, ck_terms, ck_total;
   // full gradient: after `total`, a second spectrum, the per-work-group
   // partial sums and the argmin / argmax partials (the kernel table's
-  // beta-derivative spectrum reuses g0)
+  // beta-derivative spectrum: g0, in 2D part of the solve's workspace, in 3D
+  // also after `total`)
   size_t fg_spec2, fg_part, fg_ext, fg_total;
 };
 

@@ -12,6 +12,11 @@
 //   X_ADJ   adjoint step `term` = i: inverse real FFT of b_i = kappa (*) a_i,
 //           dL/dgamma += phi_{i-1} b_i, a_{i-1} = (-1)^(i-1) lambda + gamma
 //           b_i and its FFT; at i = 1, dL/df = dL/dgamma 2 f / ftilde^2
+//   X_DGHAT  the kernel's beta-derivative table lines, forward real FFT
+//            (scalars from the checkpoint)
+//   X_ADJ0_B, X_ADJ_B  X_ADJ0 and X_ADJ for the full gradient: also the
+//            per-work-group partial sums of the scalar derivatives (slots
+//            G_*), X_ADJ_B from the second spectrum c_i = dkappa/dbeta (*) a_i
 #pragma once
 
 #include "common3d.hpp"
@@ -92,7 +97,10 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   C *line = lines + team * LL;
   const size_t rowoff = (size_t)rs * a.n2;
   constexpr bool TERMLIKE = MODE == X_TERM || MODE == X_LAST;
-  constexpr bool ADJ0 = MODE == X_ADJ0, ADJ = MODE == X_ADJ;
+  constexpr bool ADJ0 = MODE == X_ADJ0 || MODE == X_ADJ0_B;
+  constexpr bool ADJ = MODE == X_ADJ || MODE == X_ADJ_B;
+  constexpr bool FULLG = MODE == X_ADJ0_B || MODE == X_ADJ_B;  // full gradient
+  constexpr bool TABLE = MODE == X_GHAT || MODE == X_DGHAT;
   const bool last = MODE == X_LAST || (MODE == X_PHI0 && a.T == 0);
   auto col_ok = [&](int c) { return FULL ? true : (line_ok && c < a.n2); };
   const bool vec = FULL || (a.n2 & 1) == 0;  // column pairs aligned: vector access
@@ -113,6 +121,13 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     const C *sl = a.s1 + (size_t)rs * H;
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = line_ok ? sl[t + P * j] : cmake<C>((R)0, (R)0);
+  }
+  // full gradient: the spectrum of c_i = dkappa/dbeta (*) a_i
+  C vc[MODE == X_ADJ_B ? 16 : 1];
+  if constexpr (MODE == X_ADJ_B) {
+    const C *sl = a.s1b + (size_t)rs * H;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) vc[j] = line_ok ? sl[t + P * j] : cmake<C>((R)0, (R)0);
   }
   // pointwise operands of columns c = 2m, 2m+1, m = t + P j (only j < 8
   // can lie in the grid since n2 <= H)
@@ -248,17 +263,21 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   __syncthreads();
 
   // ---- 3. kernel table -------------------------------------------------------
-  if constexpr (MODE == X_GHAT) {
+  if constexpr (TABLE) {
     // line (d0, d1) = (i0, i1): x(c) = kappa(|d|) for c < n2, -kappa at M2 - c
-    // for 0 < c < n2, zero between
-    const double k0v = s_par[0];
+    // for 0 < c < n2, zero between (the same for dkappa/dbeta)
+    const double k0v = MODE == X_GHAT ? s_par[0] : 0.0;
     const long long r01 = (long long)i0 * i0 + (long long)i1 * i1;
     const int M2 = 2 * H;
+    auto kv = [&](long long r2) -> R {
+      if constexpr (MODE == X_GHAT) return kappa_3d_t<R>(beta, r2, k0v);
+      else return (R)dkappa_3d(beta, r2);
+    };
     auto tab = [&](int c) -> R {
       if (!line_ok) return (R)0;
-      if (c < a.n2) return kappa_3d_t<R>(beta, r01 + (long long)c * c, k0v);
+      if (c < a.n2) return kv(r01 + (long long)c * c);
       const int d = M2 - c;
-      if (d < a.n2) return -kappa_3d_t<R>(beta, r01 + (long long)d * d, k0v);
+      if (d < a.n2) return -kv(r01 + (long long)d * d);
       return (R)0;
     };
 #pragma unroll
@@ -269,6 +288,25 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   }
 
   if constexpr (TERMLIKE || ADJ) odd_c2r<R, H>(v, t, line, twl, tws, w1);
+  if constexpr (MODE == X_ADJ_B) odd_c2r<R, H>(vc, t, line, twl, tws, w1);
+
+  // full gradient: d phi_0 / d beta and d phi_0 / d hbar (through the
+  // weights w_k = exp(-s_k / hbar)) at column cc of this line, in float64
+  auto dphi0 = [&](int cc, double &dbeta, double &dhbar) {
+    dbeta = 0.0;
+    dhbar = 0.0;
+    for (int k = 0; k < a.n_src; ++k) {
+      const double d0 = (double)(i0 - a.src[3 * k]), d1 = (double)(i1 - a.src[3 * k + 1]);
+      const double d2 = (double)(cc - a.src[3 * k + 2]);
+      const double dist = sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+      const double sk = a.src_s ? (double)a.src_s[k] : 0.0;
+      const double e = exp(-sk / a.hbar - beta * dist);
+      dbeta -= dist * e;
+      dhbar += e * sk / (a.hbar * a.hbar);
+    }
+  };
+  // per-work-group slot of the full gradient's partial sums
+  auto gslot = [&](int slot) -> double & { return a.gpart[(size_t)slot * a.nbx + bid]; };
 
   // ---- 4a. adjoint pointwise steps (columns c = 2m, 2m+1, m = t + P j) --------
   // Each chunk of four column pairs reads its operands before any store (a
@@ -277,6 +315,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   if constexpr (ADJ0) {
     const double lam_scale = ldexp(1.0, -elam);
     const double sgnT = (a.T & 1) ? -1.0 : 1.0;
+    double ps[FULLG ? 3 : 1] = {};  // S/hbar, a_0 d phi_0/d beta, a_0 d phi_0/d hbar
 #pragma unroll
     for (int j0 = 0; j0 < 8; j0 += 4) {
       R qf[4][2], qs[4][2];
@@ -306,6 +345,15 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
             const R q = (R)l;
             a.lam[rowoff + cc] = q;
             zz[e] = (R)(sgnT * (double)q);
+            if constexpr (FULLG) {
+              if (ph > 0.0 && isfinite(ph)) ps[0] += (double)qs[jj][e] * -log(ph);
+              if (a.T == 0) {  // phi = phi_0: a_0 = lambda
+                double db, dh;
+                dphi0(cc, db, dh);
+                ps[1] += (double)q * db;
+                ps[2] += (double)q * dh;
+              }
+            }
           }
         }
         v[j0 + jj] = cmake<C>(zz[0], zz[1]);
@@ -313,12 +361,28 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     }
 #pragma unroll
     for (int j = 8; j < 16; ++j) v[j] = cmake<C>((R)0, (R)0);
+    if constexpr (FULLG) {
+      block_sums_d(ps);
+      if (tid == 0) {
+        const double sl = ldexp(1.0, elam);
+        gslot(G_S) = ps[0];
+        gslot(G_C) = 0.0;
+        gslot(G_B0) = ps[1] * sl;
+        gslot(G_H0) = ps[2] * sl;
+        gslot(G_GF) = 0.0;
+      }
+      if (a.T == 0) return;
+    }
   }
   if constexpr (ADJ) {
     const double gscale = ldexp(1.0, Eprev + elam);
     const double sgn_prev = ((term - 1) & 1) ? -1.0 : 1.0;  // (-1)^(i-1)
     const R *mprev = a.terms + (size_t)(term - 1) * ((size_t)a.nlines * a.n2);
     const R *p2 = term > 1 ? a.gam : a.f;  // gamma, or f at the last step
+    const bool need3 = term > 1 || FULLG;   // lambda
+    // full gradient: <c_i, gamma phi_{i-1}>, and at term 1 a_0 d phi_0 and
+    // dL/dgamma f^2 (mantissa sums; scales applied per work-group)
+    double ps[FULLG ? 4 : 1] = {};
 #pragma unroll
     for (int j0 = 0; j0 < 8; j0 += 4) {
       R q1[4][2], q2[4][2], q3[4][2];
@@ -331,7 +395,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
           const bool ok = col_ok(cc);
           q1[jj][e] = ok ? mprev[rowoff + cc] : (R)0;
           q2[jj][e] = ok ? p2[rowoff + cc] : (R)0;
-          q3[jj][e] = (ok && term > 1) ? a.lam[rowoff + cc] : (R)0;
+          q3[jj][e] = (ok && need3) ? a.lam[rowoff + cc] : (R)0;
           qd[jj][e] = (ok && term != a.T) ? a.acc[rowoff + cc] : 0.0;
         }
 #pragma unroll
@@ -344,17 +408,46 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
           const int cc = 2 * (t + P * j) + e;
           if (col_ok(cc)) {
             // dL/dgamma += phi_{i-1} b_i  (true scale 2^(E_{i-1} + e_lam))
-            const double g = (double)q1[jj][e] * bb[e] * gscale + qd[jj][e];
+            const double mp = (double)q1[jj][e];
+            const double g = mp * bb[e] * gscale + qd[jj][e];
+            double ga;  // gamma at this point
             if (term > 1) {
               a.acc[rowoff + cc] = g;
-              zz[e] = (R)(sgn_prev * (double)q3[jj][e] + (double)q2[jj][e] * bb[e]);
+              ga = (double)q2[jj][e];
+              zz[e] = (R)(sgn_prev * (double)q3[jj][e] + ga * bb[e]);
             } else {
               // dL/df = dL/dgamma * 2 f / ftilde^2
-              a.dLdf[rowoff + cc] = (R)(g * 2.0 * (double)q2[jj][e] * inv_ft2);
+              const double fa = (double)q2[jj][e];
+              a.dLdf[rowoff + cc] = (R)(g * 2.0 * fa * inv_ft2);
+              ga = (fa - ft) * (fa + ft) * inv_ft2;
+            }
+            if constexpr (MODE == X_ADJ_B) {
+              if (term == 1) {
+                const double fa = (double)q2[jj][e];
+                const double a0 = (double)q3[jj][e] + ga * bb[e];  // a_0 = lambda + gamma b_1
+                double db, dh;
+                dphi0(cc, db, dh);
+                ps[1] += a0 * db;
+                ps[2] += a0 * dh;
+                ps[3] += g * fa * fa;
+              }
+              ps[0] += (double)(e ? vc[j].y : vc[j].x) * ga * mp;
             }
           }
         }
         v[j] = cmake<C>(zz[0], zz[1]);
+      }
+    }
+    if constexpr (MODE == X_ADJ_B) {
+      block_sums_d(ps);
+      if (tid == 0) {
+        gslot(G_C) += ps[0] * gscale;
+        if (term == 1) {
+          const double sl = ldexp(1.0, elam);
+          gslot(G_B0) = ps[1] * sl;
+          gslot(G_H0) = ps[2] * sl;
+          gslot(G_GF) = ps[3];
+        }
       }
     }
     if (term == 1) return;

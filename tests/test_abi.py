@@ -183,6 +183,14 @@ def test_full_gradient_entry_checks(lib):
     rc = lib.sweik_solve_adjoint_full(p.handle, vp(16), vp(16), None, vp(16), vp(16), vp(16),
                                       None, vp(16), need - 1, None)
     assert rc == 3  # SWEIK_EWORKSPACE
+    # 3D: the kernel's beta-derivative spectrum and a second x-pass spectrum
+    # come after the solve's workspace as well
+    p3 = _plan(dims=(20, 18, 22), T=4)
+    need3 = lib.sweik_adjoint_full_workspace_bytes(p3.handle)
+    assert need3 > lib.sweik_workspace_bytes(p3.handle)
+    rc = lib.sweik_solve_adjoint_full(p3.handle, vp(16), vp(16), None, vp(16), vp(16), vp(16),
+                                      None, vp(16), need3 - 1, None)
+    assert rc == 3
 
 
 def test_batch_solve_before_prepare_is_rejected(lib):
