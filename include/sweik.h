@@ -343,7 +343,7 @@ enum {
   SWEIK_KC_Y_FWD = 7,     /* 3D: FFT along axis 1 */
   SWEIK_KC_Y_INV = 8,     /* 3D: inverse FFT along axis 1 */
   SWEIK_KC_GHAT_Z = 9,    /* 3D: kernel spectrum along axis 0 */
-  SWEIK_KC_PHI0_FFT = 10, /* 2D phi_0 by FFT: exp(-beta|m|) spectrum, source grid, product */
+  SWEIK_KC_PHI0_FFT = 10, /* phi_0 by FFT: exp(-beta|m|) spectrum, source grid, product */
   SWEIK_KC_COUNT = 11
 };
 
@@ -404,11 +404,12 @@ sweik_status sweik_batch_solve_graph(sweik_batch batch, const void *const *f,
  * threads per work-group (the rows or columns per work-group do not change).
  *   row_e     2D row passes (all modes): 16, 8, or 4 (float32 only)
  *   col_e     2D column passes (all modes): 16, 8, or 4 (float32 only)
- *   phi0_fft  2D: 0 = phi_0 by the direct sum over the sources (eq.
+ *   phi0_fft  2D and 3D: 0 = phi_0 by the direct sum over the sources (eq.
  *             phi_0Solution), 1 = by FFT as in Table 1 steps 1-5 (the
  *             spectrum of exp(-beta |m|) times the transform of the source
- *             grid).  Plans start with 1 when n_src > 64.
- * 3D plans have the single schedule {16, 16, 0}.  New plans take row_e and
+ *             grid).  2D plans start with 1 when n_src > 64, 3D plans
+ *             when n_src > 128 (float32) or n_src > 32 (float64).
+ * 3D plans have row_e = col_e = 16 (phi0_fft as above).  New plans take row_e and
  * col_e from the process-wide table filled by sweik_autotune (default 16).
  * Batches always sum over the sources. */
 typedef struct {
@@ -419,8 +420,8 @@ typedef struct {
 
 sweik_status sweik_plan_get_schedule(sweik_plan plan, sweik_schedule *out);
 /* SWEIK_EINVAL for a value other than 16, 8 or 4 (0 or 1 for phi0_fft);
- * SWEIK_EUNSUPPORTED for 4 in a float64 plan or a 3D plan with another
- * schedule than {16, 16, 0}.  Host only.  Not to be called while a
+ * SWEIK_EUNSUPPORTED for 4 in a float64 plan or a 3D plan with a radix
+ * other than 16.  Host only.  Not to be called while a
  * solve with this plan is being enqueued on another thread. */
 sweik_status sweik_plan_set_schedule(sweik_plan plan, const sweik_schedule *s);
 

@@ -124,6 +124,10 @@ void sched_store(int fam, int len, int prec, int e) {
 // Sources beyond which a 2D plan takes the FFT route of phi_0: at 1024^2 the
 // direct sum costs about 1.4 us per source, the route about 80 us.
 constexpr int kPhi0FftSources = 64;
+// The same for a 3D plan, per precision: at 256^3 the direct sum costs about
+// 3.4 us per source in float32 and 32 us in float64, the route about 0.43 ms
+// and 0.97 ms.
+constexpr int kPhi0FftSources3F32 = 128, kPhi0FftSources3F64 = 32;
 
 // Schedule and workspace layout of a 2D problem.
 sweik_status plan2d(sweik_plan_s *pl) {
@@ -340,7 +344,7 @@ sweik_status enqueue2d(const sweik_plan_s *pl, const void *f, const int32_t *src
     launch(SWEIK_KC_PHI0_FFT, [&] { return launch_fill<R>(a.gam, N2, (R)0, st); });
     launch(SWEIK_KC_PHI0_FFT, [&] {
       return launch_seed_scatter<R>(a.gam, src, (const R *)src_s, pl->p.n_src, pl->p.hbar, g.n0,
-                                    g.n1, st);
+                                    g.n1, 0, st);
     });
     launch(SWEIK_KC_PHI0_FFT, [&] { return launch_row2<R>(ROW_SEED, g.H1, g.erow, grow, st, a0, 0); });
     launch(SWEIK_KC_PHI0_FFT, [&] { return launch_col2<R>(COL_CONV, g.M0, g.ecol, gcol, st, a0); });
@@ -564,8 +568,8 @@ sweik_status plan3d(sweik_plan_s *pl) {
   g.nbx = (g.nlines + x_lpw(g.H2) - 1) / x_lpw(g.H2);
   g.ncb0 = g.H2 / (f64 ? c3_cpw<double>(g.M0) : c3_cpw<float>(g.M0));
   g.ncb1 = g.H2 / (f64 ? c3_cpw<double>(g.M1) : c3_cpw<float>(g.M1));
-  pl->g2.erow = pl->g2.ecol = 16;  // the 3D passes have one schedule
-  pl->g2.phi0_fft = 0;
+  pl->g2.erow = pl->g2.ecol = 16;  // the 3D passes have one radix schedule
+  pl->g2.phi0_fft = p.n_src > (f64 ? kPhi0FftSources3F64 : kPhi0FftSources3F32) ? 1 : 0;
   g.lmax = std::max(2 * g.M2, std::max(g.M0, g.M1));
   g.lmax_log = ilog2(g.lmax);
   for (int d = 0; d < 3; ++d) pl->padded[d] = M[d];
@@ -585,6 +589,8 @@ sweik_status plan3d(sweik_plan_s *pl) {
   L.mu_red = take(sizeof(double) * (size_t)(p.T + 1));
   L.tw = take((size_t)csz * g.lmax);
   L.g = take((size_t)esz * (g.H1 + 1) * (g.H0 + 1) * g.H2);
+  // spectrum of exp(-beta |m|) (phi_0 by FFT), or of dkappa/dbeta (full gradient)
+  L.g0 = take((size_t)esz * (g.H1 + 1) * (g.H0 + 1) * g.H2);
   L.spec = take((size_t)csz * g.nlines * g.H2);
   g.ld2 = (long long)g.M1 * g.H2 + kS2PlanePad;
   L.s2 = take((size_t)csz * g.n0 * (size_t)g.ld2);
@@ -593,9 +599,8 @@ sweik_status plan3d(sweik_plan_s *pl) {
   L.gam = take((size_t)esz * N);
   L.lam = take((size_t)esz * N);
   L.total = off;
-  // full gradient: the kernel's beta-derivative spectrum, the second x-pass
-  // spectrum, the per-work-group partial sums and the argmin / argmax partials
-  L.g0 = take((size_t)esz * (g.H1 + 1) * (g.H0 + 1) * g.H2);
+  // full gradient: the second x-pass spectrum, the per-work-group partial
+  // sums and the argmin / argmax partials
   L.fg_spec2 = take((size_t)csz * g.nlines * g.H2);
   L.fg_part = take(sizeof(double) * kGradSlots * g.nbx);
   L.fg_ext = take(sizeof(long long) * 2 * kRedBlocks);
@@ -703,7 +708,28 @@ sweik_status enqueue3d(const sweik_plan_s *pl, const void *f, const int32_t *src
     launch(SWEIK_KC_GHAT_COL, [&] { return launch_c3<R>(C3_GY, g.M1, ny, st, a, -1); });
     launch(SWEIK_KC_GHAT_Z, [&] { return launch_c3<R>(C3_GZ, g.M0, (g.H1 + 1) * g.ncb0, st, a, -1); });
   }
-  launch(SWEIK_KC_PHI0_ROW, [&] { return launch_x3<R>(X_PHI0, g.H2, g.nbx, st, a, 0); });
+  if (pl->g2.phi0_fft) {
+    // Table 1 steps 1-5: spectrum of exp(-beta |m|) into g0, transform of the
+    // source grid (weights exp(-s_k/hbar), held in gamma), product, inverse
+    // in the phi_0 pass
+    Args3<R> a0 = a;
+    a0.g = (R *)((char *)ws + pl->ws.g0);
+    launch(SWEIK_KC_PHI0_FFT, [&] { return launch_x3<R>(X_ETAB, g.H2, g.nbx, st, a0, 0); });
+    launch(SWEIK_KC_PHI0_FFT, [&] { return launch_c3<R>(C3_GY, g.M1, ny, st, a0, -1); });
+    launch(SWEIK_KC_PHI0_FFT, [&] { return launch_c3<R>(C3_GZ, g.M0, (g.H1 + 1) * g.ncb0, st, a0, -1); });
+    launch(SWEIK_KC_PHI0_FFT, [&] { return launch_fill<R>(a.gam, N, (R)0, st); });
+    launch(SWEIK_KC_PHI0_FFT, [&] {
+      return launch_seed_scatter<R>(a.gam, src, (const R *)src_s, pl->p.n_src, pl->p.hbar, g.n0,
+                                    g.n1, g.n2, st);
+    });
+    launch(SWEIK_KC_PHI0_FFT, [&] { return launch_x3<R>(X_SEED, g.H2, g.nbx, st, a0, 0); });
+    launch(SWEIK_KC_PHI0_FFT, [&] { return launch_c3<R>(C3_YF, g.M1, ny, st, a0, -1); });
+    launch(SWEIK_KC_PHI0_FFT, [&] { return launch_c3<R>(C3_Z, g.M0, g.M1 * g.ncb0, st, a0, -1); });
+    launch(SWEIK_KC_PHI0_FFT, [&] { return launch_c3<R>(C3_YI, g.M1, ny, st, a0, -1); });
+    launch(SWEIK_KC_PHI0_ROW, [&] { return launch_x3<R>(X_PHI0F, g.H2, g.nbx, st, a, 0); });
+  } else {
+    launch(SWEIK_KC_PHI0_ROW, [&] { return launch_x3<R>(X_PHI0, g.H2, g.nbx, st, a, 0); });
+  }
   for (int i = 1; i <= T; ++i) {
     launch(SWEIK_KC_Y_FWD, [&] { return launch_c3<R>(C3_YF, g.M1, ny, st, a, i - 1); });
     launch(SWEIK_KC_CONV_COL, [&] { return launch_c3<R>(C3_Z, g.M0, g.M1 * g.ncb0, st, a, -1); });
@@ -1414,7 +1440,7 @@ sweik_status sweik_plan_get_schedule(sweik_plan plan, sweik_schedule *out) {
   std::memset(out, 0, sizeof(*out));
   out->row_e = plan->g2.erow;
   out->col_e = plan->g2.ecol;
-  out->phi0_fft = plan->p.ndim == 2 ? plan->g2.phi0_fft : 0;
+  out->phi0_fft = plan->g2.phi0_fft;
   return SWEIK_OK;
 }
 
@@ -1424,15 +1450,14 @@ sweik_status sweik_plan_set_schedule(sweik_plan plan, const sweik_schedule *sc) 
   if (!ok(sc->row_e) || !ok(sc->col_e)) return SWEIK_EINVAL;
   if (plan->p.prec == SWEIK_F64 && (sc->row_e == 4 || sc->col_e == 4)) return SWEIK_EUNSUPPORTED;
   if (sc->phi0_fft != 0 && sc->phi0_fft != 1) return SWEIK_EINVAL;
-  if (plan->p.ndim == 3 && (sc->row_e != 16 || sc->col_e != 16 || sc->phi0_fft))
-    return SWEIK_EUNSUPPORTED;
+  if (plan->p.ndim == 3 && (sc->row_e != 16 || sc->col_e != 16)) return SWEIK_EUNSUPPORTED;
   if (plan->p.ndim == 2) {
     const int H = plan->g2.H1;
     if (H < sc->row_e) return SWEIK_EUNSUPPORTED;
   }
   plan->g2.erow = sc->row_e;
   plan->g2.ecol = sc->col_e;
-  if (plan->p.ndim == 2) plan->g2.phi0_fft = sc->phi0_fft;
+  plan->g2.phi0_fft = sc->phi0_fft;
   return SWEIK_OK;
 }
 

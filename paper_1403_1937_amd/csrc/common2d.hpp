@@ -526,15 +526,18 @@ __global__ void __launch_bounds__(256) k_prep_batch(const BatchItem<R> *__restri
 }
 
 // Source grid of phi_0 by FFT: the weight exp(-s_k/hbar) (1 without values)
-// at every source of a zeroed grid.
+// at every source of a zeroed grid (n0 x n1, or n0 x n1 x n2 when n2 > 0).
 template <typename R>
 __global__ void __launch_bounds__(256) k_seed_scatter(R *__restrict__ grid, const int *__restrict__ src,
                                                       const R *__restrict__ src_s, int n_src,
-                                                      double hbar, int n0, int n1) {
+                                                      double hbar, int n0, int n1, int n2) {
+  const int nd = n2 > 0 ? 3 : 2;
   for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < n_src; k += gridDim.x * blockDim.x) {
-    const int y0 = src[2 * k], y1 = src[2 * k + 1];
-    if (y0 < 0 || y0 >= n0 || y1 < 0 || y1 >= n1) continue;  // flagged by the kernel-table pass
-    grid[(size_t)y0 * n1 + y1] = src_s ? (R)exp(-(double)src_s[k] / hbar) : (R)1;
+    const int y0 = src[nd * k], y1 = src[nd * k + 1], y2 = nd == 3 ? src[nd * k + 2] : 0;
+    // sources outside the grid are flagged by the kernel-table pass
+    if (y0 < 0 || y0 >= n0 || y1 < 0 || y1 >= n1 || (nd == 3 && (y2 < 0 || y2 >= n2))) continue;
+    const size_t at = nd == 3 ? ((size_t)y0 * n1 + y1) * n2 + y2 : (size_t)y0 * n1 + y1;
+    grid[at] = src_s ? (R)exp(-(double)src_s[k] / hbar) : (R)1;
   }
 }
 

@@ -36,9 +36,12 @@ namespace sweik {
 // X_ADJ0, X_ADJ: the adjoint sweep's start and steps (see x3d.hpp).
 // X_DGHAT, X_ADJ0_B, X_ADJ_B: the same for the full gradient (the kernel's
 // beta-derivative table, and the sweep with the scalar partial sums).
+// X_ETAB, X_SEED, X_PHI0F: phi_0 by FFT (Table 1 steps 1-5): the table of
+// exp(-beta |m|), the source grid's transform, and the phi_0 pass that takes
+// phi_0 from the inverse transform of their product.
 enum XMode {
   X_GHAT = 0, X_PHI0 = 1, X_TERM = 2, X_LAST = 3, X_ADJ0 = 4, X_ADJ = 5,
-  X_DGHAT = 6, X_ADJ0_B = 7, X_ADJ_B = 8
+  X_DGHAT = 6, X_ADJ0_B = 7, X_ADJ_B = 8, X_PHI0F = 9, X_ETAB = 10, X_SEED = 11
 };
 enum C3Mode { C3_YF = 0, C3_Z = 1, C3_YI = 2, C3_GY = 3, C3_GZ = 4 };
 

@@ -240,10 +240,10 @@ hipError_t launch_adj_prep(const R *dLdS, const double *phi, long long N, double
 
 template <typename R>
 hipError_t launch_seed_scatter(R *grid, const int *src, const R *src_s, int n_src, double hbar,
-                               int n0, int n1, hipStream_t st) {
+                               int n0, int n1, int n2, hipStream_t st) {
   const int nb = std::max(1, std::min((n_src + 255) / 256, 1024));
   hipLaunchKernelGGL(k_seed_scatter<R>, dim3(nb), dim3(256), 0, st, grid, src, src_s, n_src, hbar,
-                     n0, n1);
+                     n0, n1, n2);
   return hipGetLastError();
 }
 
@@ -327,7 +327,7 @@ template <typename R> hipError_t launch_fill(R *out, long long N, R v, hipStream
                                                 const double *, int, long long *, int, double, \
                                                 double, R *, double *, hipStream_t);           \
   template hipError_t launch_seed_scatter<R>(R *, const int *, const R *, int, double, int, int, \
-                                             hipStream_t);                                  \
+                                             int, hipStream_t);                                  \
   template hipError_t launch_prep_batch<R>(int, hipStream_t, const BatchItem<R> *);
 
 }  // namespace sweik

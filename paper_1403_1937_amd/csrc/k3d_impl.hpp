@@ -51,6 +51,9 @@ hipError_t launch_x3(int mode, int H, int nblocks, hipStream_t st, const Args3<R
     case X_DGHAT: return x3_mode<R, X_DGHAT>(H, nblocks, st, a, term);
     case X_ADJ0_B: return x3_mode<R, X_ADJ0_B>(H, nblocks, st, a, term);
     case X_ADJ_B: return x3_mode<R, X_ADJ_B>(H, nblocks, st, a, term);
+    case X_PHI0F: return x3_mode<R, X_PHI0F>(H, nblocks, st, a, term);
+    case X_ETAB: return x3_mode<R, X_ETAB>(H, nblocks, st, a, term);
+    case X_SEED: return x3_mode<R, X_SEED>(H, nblocks, st, a, term);
   }
   return hipErrorInvalidValue;
 }

@@ -53,7 +53,7 @@ hipError_t launch_adj_full_finish(const R *f, long long N, const Params *par, co
                                   R *dLdf, double *out, hipStream_t st);
 template <typename R>
 hipError_t launch_seed_scatter(R *grid, const int *src, const R *src_s, int n_src, double hbar,
-                               int n0, int n1, hipStream_t st);
+                               int n0, int n1, int n2, hipStream_t st);  // 2D: n2 = 0
 template <typename R>
 hipError_t launch_prep_batch(int nitems, hipStream_t st, const BatchItem<R> *items);
 

@@ -17,6 +17,10 @@
 //   X_ADJ0_B, X_ADJ_B  X_ADJ0 and X_ADJ for the full gradient: also the
 //            per-work-group partial sums of the scalar derivatives (slots
 //            G_*), X_ADJ_B from the second spectrum c_i = dkappa/dbeta (*) a_i
+//   X_ETAB   phi_0 by FFT: table lines of exp(-beta |m|), forward real FFT
+//   X_SEED   phi_0 by FFT: forward real FFT of the source grid (held in gamma)
+//   X_PHI0F  X_PHI0 with phi_0 the inverse real FFT of the convolved source
+//            grid instead of the sum over the sources
 #pragma once
 
 #include "common3d.hpp"
@@ -97,11 +101,12 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   C *line = lines + team * LL;
   const size_t rowoff = (size_t)rs * a.n2;
   constexpr bool TERMLIKE = MODE == X_TERM || MODE == X_LAST;
+  constexpr bool PHI0 = MODE == X_PHI0 || MODE == X_PHI0F;
   constexpr bool ADJ0 = MODE == X_ADJ0 || MODE == X_ADJ0_B;
   constexpr bool ADJ = MODE == X_ADJ || MODE == X_ADJ_B;
   constexpr bool FULLG = MODE == X_ADJ0_B || MODE == X_ADJ_B;  // full gradient
-  constexpr bool TABLE = MODE == X_GHAT || MODE == X_DGHAT;
-  const bool last = MODE == X_LAST || (MODE == X_PHI0 && a.T == 0);
+  constexpr bool TABLE = MODE == X_GHAT || MODE == X_DGHAT || MODE == X_ETAB;
+  const bool last = MODE == X_LAST || (PHI0 && a.T == 0);
   auto col_ok = [&](int c) { return FULL ? true : (line_ok && c < a.n2); };
   const bool vec = FULL || (a.n2 & 1) == 0;  // column pairs aligned: vector access
 
@@ -117,7 +122,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   stage_tw_issue<H, 16>(tsr, a.tw, a.lmax_log, tid, kThreads);
   const C w1 = a.tw[1 << (a.lmax_log - TWLOG)];  // w(1) = exp(-2 pi i / 4H)
   C v[16];
-  if constexpr (TERMLIKE || ADJ) {
+  if constexpr (TERMLIKE || ADJ || MODE == X_PHI0F) {
     const C *sl = a.s1 + (size_t)rs * H;
 #pragma unroll
     for (int j = 0; j < 16; ++j) v[j] = line_ok ? sl[t + P * j] : cmake<C>((R)0, (R)0);
@@ -133,8 +138,9 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   // can lie in the grid since n2 <= H)
   R o1[16];
   double od[16];
-  if constexpr (TERMLIKE || MODE == X_PHI0) {
-    const R *p1 = last ? nullptr : (MODE == X_PHI0 ? a.f : a.gam);
+  if constexpr (TERMLIKE || PHI0 || MODE == X_SEED) {
+    // f (phi_0), gamma (terms) or the source grid (held in gamma)
+    const R *p1 = last ? nullptr : (PHI0 ? a.f : a.gam);
     const double *pd = nullptr;  // no operand in float64
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -218,7 +224,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     dstep = exp_step(a.mu_red[term - 1]);
     E = a.expo[term - 1] + dstep;
   }
-  if ((TERMLIKE || MODE == X_PHI0) && bid == 0 && tid == 0) {
+  if ((TERMLIKE || PHI0) && bid == 0 && tid == 0) {
     const int slot = TERMLIKE ? term : 0;
     a.expo[slot] = E;
     if (a.info) a.info->scale_exp[slot] = E;
@@ -271,6 +277,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     const int M2 = 2 * H;
     auto kv = [&](long long r2) -> R {
       if constexpr (MODE == X_GHAT) return kappa_3d_t<R>(beta, r2, k0v);
+      else if constexpr (MODE == X_ETAB) return exp_kernel_t<R>(beta, (int)r2);
       else return (R)dkappa_3d(beta, r2);
     };
     auto tab = [&](int c) -> R {
@@ -287,7 +294,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
     }
   }
 
-  if constexpr (TERMLIKE || ADJ) odd_c2r<R, H>(v, t, line, twl, tws, w1);
+  if constexpr (TERMLIKE || ADJ || MODE == X_PHI0F) odd_c2r<R, H>(v, t, line, twl, tws, w1);
   if constexpr (MODE == X_ADJ_B) odd_c2r<R, H>(vc, t, line, twl, tws, w1);
 
   // full gradient: d phi_0 / d beta and d phi_0 / d hbar (through the
@@ -456,7 +463,13 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
   }
 
   // ---- 4. pointwise step -------------------------------------------------------
-  if constexpr (MODE == X_PHI0 || TERMLIKE) {
+  if constexpr (MODE == X_SEED) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = cmake<C>(o1[2 * j], o1[2 * j + 1]);
+#pragma unroll
+    for (int j = 8; j < 16; ++j) v[j] = cmake<C>((R)0, (R)0);
+  }
+  if constexpr (PHI0 || TERMLIKE) {
     long long nbad = 0;
     const R sm = (R)ldexp(1.0, -dstep);
     const double sE = ((TERMLIKE && (term & 1)) ? -1.0 : 1.0) * ldexp(1.0, E);
@@ -511,7 +524,14 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
         const bool ok1 = FULL || c0 + 1 < a.n2;
         double p0, p1 = 0.0;
         R m0, m1;
-        if constexpr (MODE == X_PHI0) {
+        if constexpr (MODE == X_PHI0F) {
+          // phi_0 = exp(-beta |m|) (*) source grid (Table 1 steps 1-5): the
+          // kernel spectrum carries the transforms' scale
+          m0 = v[j].x;
+          m1 = v[j].y;
+          p0 = (double)m0;
+          p1 = (double)m1;
+        } else if constexpr (MODE == X_PHI0) {
           // phi_0 = sum_k exp(-beta |m - y_k|)  (eq. phi_0Solution, C = 1)
           double s0 = 0.0, s1 = 0.0;
           // the first kSrcLds sources from LDS, the rest from global memory
@@ -568,7 +588,7 @@ __device__ __forceinline__ void x_pass(const Args3<R> &a, int term, unsigned cha
             if (ok1) tout[c0 + 1] = m1;
           }
           R g0, g1 = (R)0;
-          if constexpr (MODE == X_PHI0) {
+          if constexpr (PHI0) {
             const double fa = (double)o1[2 * j];
             g0 = (R)((fa - ft) * (fa + ft) * inv_ft2);
             a.gam[rowoff + c0] = g0;

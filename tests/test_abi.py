@@ -138,10 +138,16 @@ def test_phi0_route_defaults_and_checks(lib):
     assert many.schedule["phi0_fft"] == 0
     with pytest.raises(ValueError):
         many.set_schedule(16, 16, phi0_fft=2)
-    cube = _plan(dims=(16, 16, 16), n_src=100)
+    # 3D: the measured crossovers, 128 sources in float32 and 32 in float64
+    cube = _plan(dims=(16, 16, 16), n_src=200)
+    assert cube.schedule["phi0_fft"] == 1
+    cube.set_schedule(16, 16, phi0_fft=0)
     assert cube.schedule["phi0_fft"] == 0
+    assert _plan(dims=(16, 16, 16), n_src=100).schedule["phi0_fft"] == 0
+    assert _plan(dims=(16, 16, 16), n_src=40, precision="fp64").schedule["phi0_fft"] == 1
+    assert _plan(dims=(16, 16, 16), n_src=32, precision="fp64").schedule["phi0_fft"] == 0
     with pytest.raises(ValueError, match="unsupported"):
-        cube.set_schedule(16, 16, phi0_fft=1)
+        cube.set_schedule(8, 16, phi0_fft=1)
 
 
 def test_backtrack_rejects_invalid_arguments(lib):

@@ -18,7 +18,8 @@ import torch
 
 import oracle
 import workloads
-from common import TOL, ensure_built, envelope_violations, rel_err, report, resolvable
+from common import (EPS, LAMBDA_MAX, TOL, ensure_built, envelope_violations, rel_err, report,
+                    resolvable)
 
 pytestmark = pytest.mark.gpu
 
@@ -189,3 +190,98 @@ def test_seed_values_parity_3d(prec):
                      src_s=np.asarray(s, np.float32 if prec == "fp32" else np.float64))
     worst, frac, _ = report(S, o, hbar, prec)
     assert frac > 0.1 and worst <= TOL[prec]
+
+
+def _sphere_sources(dims, count, rng):
+    """Distinct grid points near a sphere (a dense seed surface)."""
+    c = np.array(dims, np.float64) / 2
+    rad = 0.3 * min(dims)
+    v = rng.standard_normal((4 * count, 3))
+    v /= np.linalg.norm(v, axis=1, keepdims=True)
+    pts = np.unique(np.round(c + rad * v).astype(np.int32), axis=0)
+    return np.ascontiguousarray(pts[rng.permutation(len(pts))[:count]])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("seeded", [False, True], ids=["plain", "seed_values"])
+def test_phi0_by_fft_many_sources_3d(prec, seeded):
+    """300 sources on a sphere: the 3D plan takes the FFT route of phi_0
+    (Table 1 steps 1-5), checked against the oracle's direct sum."""
+    import paper_1403_1937_amd as pk
+    rng = np.random.default_rng(93)
+    dims, h, hbar, T = (40, 44, 36), 1 / 44, 0.06, 4
+    f = workloads.smoothed_noise(dims, 3.0, 1.0, 2.0, rng).astype(np.float32)
+    src = _sphere_sources(dims, 300, rng)
+    assert len(src) == 300
+    s = rng.uniform(0.0, 0.05, len(src)) if seeded else None
+    pl = pk.Plan(dims, h, hbar, T, len(src), prec)
+    assert pl.schedule["phi0_fft"] == 1
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    print(f"3D phi0 by FFT {prec} {'seeded' if seeded else 'plain'}", flush=True)
+    S = pk.solve(torch.as_tensor(f.astype(np.float64)).to("cuda", dt), src, h, hbar, T,
+                 src_s=s).double().cpu().numpy()
+    o = oracle.solve(f.astype(np.float64), src, h, hbar, T,
+                     src_s=None if s is None else
+                     np.asarray(s, np.float32 if prec == "fp32" else np.float64))
+    worst, frac, _ = report(S, o, hbar, prec)
+    print(f"  max rel {worst:.3e} on {frac:.3f}", flush=True)
+    assert frac > 0.1 and worst <= TOL[prec]
+    assert envelope_violations(S, o, hbar, prec) == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("dims,T", [((20, 9, 33), 5), ((33, 12, 40), 0), ((16, 16, 16), 3)])
+def test_phi0_routes_agree_3d(prec, dims, T):
+    """Few sources, both routes of phi_0 forced: each against the oracle
+    (ragged grids, T = 0 where S comes from phi_0 alone)."""
+    import paper_1403_1937_amd as pk
+    from paper_1403_1937_amd._native import _read_info, info_struct_size
+    rng = np.random.default_rng(94 + T)
+    h, hbar = 1 / max(dims), 0.1
+    f = workloads.smoothed_noise(dims, 3.0, 1.0, 2.5, rng).astype(np.float32)
+    src = workloads.distinct_sources(dims, 3, rng)
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    o = oracle.solve(f.astype(np.float64), src, h, hbar, T)
+    for route in (0, 1):
+        pl = pk.Plan(dims, h, hbar, T, len(src), prec)
+        pl.set_schedule(16, 16, phi0_fft=route)
+        ft = torch.as_tensor(f.astype(np.float64)).to("cuda", dt)
+        S = torch.empty_like(ft)
+        info = torch.zeros(info_struct_size(), dtype=torch.uint8, device="cuda")
+        print(f"3D phi0 route {route} {prec} {dims} T={T}", flush=True)
+        pl.solve(ft, torch.as_tensor(src).cuda(), S, pl.workspace("cuda"), None, info)
+        torch.cuda.synchronize()
+        worst, frac, _ = report(S.double().cpu().numpy(), o, hbar, prec)
+        print(f"  max rel {worst:.3e} on {frac:.3f}", flush=True)
+        assert _read_info(info)["flags"] == 0
+        assert frac > 0.1 and worst <= TOL[prec]
+
+
+def test_full_size_256_phi0_fft_closed_form():
+    """At 256^3 with 400 sources on a sphere and constant forcing (phi =
+    phi_0): the FFT route of phi_0 against the closed form
+    -hbar ln sum_k exp(-c |x - y_k| h / hbar) on a sample of points."""
+    import paper_1403_1937_amd as pk
+    n, c, hbar, T = 256, 1.3, 0.1, 2
+    rng = np.random.default_rng(33)
+    src = _sphere_sources((n, n, n), 400, rng)
+    f = torch.full((n, n, n), c, dtype=torch.float32, device="cuda")
+    pl = pk.Plan((n, n, n), 1 / n, hbar, T, len(src), "fp32")
+    assert pl.schedule["phi0_fft"] == 1
+    print("256^3 phi0 by FFT, 400 sources, fp32", flush=True)
+    S = pk.solve(f, src, 1 / n, hbar, T)
+    idx = np.concatenate([rng.integers(0, n, (4096, 3)), src[:64]])
+    phi = np.exp(-c * np.linalg.norm(idx[:, None, :] - src[None, :, :], axis=-1) / n / hbar)
+    phi = phi.sum(axis=1)
+    ref = -hbar * np.log(phi)
+    got = S[tuple(torch.as_tensor(idx.T).cuda().long())].double().cpu().numpy()
+    err = np.abs(got - ref) / np.maximum(np.abs(ref), hbar)
+    # Lambda against the largest phi of the sample (sources included): the
+    # FP32 tolerance on the resolvable set, the conditioning envelope beyond
+    L = np.log(phi.max() / phi)
+    m = L <= LAMBDA_MAX["fp32"]
+    print(f"  max rel {err[m].max():.3e} on {m.mean():.3f} of the sample (Lambda up to "
+          f"{L.max():.1f})", flush=True)
+    assert m.mean() > 0.5 and err[m].max() <= TOL["fp32"]
+    env = TOL["fp32"] + EPS["fp32"] * np.exp(L) / np.maximum(L, 1.0)
+    assert np.all(err <= env)
