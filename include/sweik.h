@@ -60,9 +60,10 @@ typedef enum {
   SWEIK_OK = 0,
   SWEIK_EINVAL = 1,       /* invalid argument */
   SWEIK_EUNSUPPORTED = 2, /* valid but not supported: a grid beyond the sizes
-                             below (2D n0 <= 2048, n1 <= 4096; 3D every
-                             axis <= 512), a 2D-only call on a 3D plan, or a
-                             schedule the plan cannot run */
+                             below (2D n1 <= 4096 and n0 <= 4096 in float32,
+                             n0 <= 2048 in float64; 3D every axis <= 512), a
+                             2D-only call on a 3D plan, or a schedule the
+                             plan cannot run */
   SWEIK_EWORKSPACE = 3,   /* workspace or checkpoint buffer too small */
   SWEIK_EDEVICE = 4,      /* a HIP call failed */
   SWEIK_ENOMEM = 5        /* host allocation failed */
@@ -403,7 +404,8 @@ sweik_status sweik_batch_solve_graph(sweik_batch batch, const void *const *f,
  * E elements per team thread, i.e. radix-E Stockham stages and 4096/E
  * threads per work-group (the rows or columns per work-group do not change).
  *   row_e     2D row passes (all modes): 16, 8, or 4 (float32 only)
- *   col_e     2D column passes (all modes): 16, 8, or 4 (float32 only)
+ *   col_e     2D column passes (all modes): 16, 8, or 4 (float32 only);
+ *             16 only for n0 > 2048 (8192-point columns)
  *   phi0_fft  2D and 3D: 0 = phi_0 by the direct sum over the sources (eq.
  *             phi_0Solution), 1 = by FFT as in Table 1 steps 1-5 (the
  *             spectrum of exp(-beta |m|) times the transform of the source
@@ -420,7 +422,8 @@ typedef struct {
 
 sweik_status sweik_plan_get_schedule(sweik_plan plan, sweik_schedule *out);
 /* SWEIK_EINVAL for a value other than 16, 8 or 4 (0 or 1 for phi0_fft);
- * SWEIK_EUNSUPPORTED for 4 in a float64 plan or a 3D plan with a radix
+ * SWEIK_EUNSUPPORTED for 4 in a float64 plan, col_e other than 16 with
+ * n0 > 2048, or a 3D plan with a radix
  * other than 16.  Host only.  Not to be called while a
  * solve with this plan is being enqueued on another thread. */
 sweik_status sweik_plan_set_schedule(sweik_plan plan, const sweik_schedule *s);

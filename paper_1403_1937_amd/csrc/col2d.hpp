@@ -2,7 +2,7 @@
 //
 // One team of P = M0/E threads per spectral column k1 (E = 16 or 8 elements
 // per thread; 4096/E threads per work-group), CPW = 4096/M0 columns per
-// work-group.  Lanes interleave the teams in groups of RB so that one wave
+// work-group; an 8192-point column takes a work-group of its own.  Lanes interleave the teams in groups of RB so that one wave
 // reads RB contiguous rows of CPW neighbouring columns from each block of
 // the blocked spectrum; work-groups are mapped so that neighbouring columns
 // run on the same XCD (they share cache lines).
@@ -31,7 +31,7 @@ template <typename R, int MODE, int M0, int E, bool FULL>
 __device__ __forceinline__ void col_pass(const Args2<R> &a, int tile, unsigned char *smem_raw) {
   using C = cplx<R>;
   constexpr int P = M0 / E, CPW = col_cpw(M0), RB = spec_rb<R>(), LL = col_line_len<R>(M0);
-  constexpr int NT = team_threads(E);
+  constexpr int NT = col_threads(M0, E);
   constexpr int H0 = M0 / 2;
   constexpr bool CONV = MODE == COL_CONV || MODE == COL_CONVC;
   constexpr bool CPLX = MODE == COL_CONVC;  // complex (tilted) kernel spectrum
@@ -231,7 +231,7 @@ __device__ __forceinline__ void col_block(const Args2<R> &a, int tile, unsigned 
 }
 
 template <typename R, int MODE, int M0, int E>
-__global__ void __launch_bounds__(team_threads(E)) k_col2(Args2<R> a) {
+__global__ void __launch_bounds__(col_threads(M0, E)) k_col2(Args2<R> a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   col_block<R, MODE, M0, E>(a, xcd_tile(blockIdx.x, gridDim.x), smem_raw);
 }
@@ -239,7 +239,7 @@ __global__ void __launch_bounds__(team_threads(E)) k_col2(Args2<R> a) {
 // Uneven batch: one launch over the column work-groups of every instance of
 // a size class (neighbouring tiles of an instance share an XCD).
 template <typename R, int MODE, int M0, int E>
-__global__ void __launch_bounds__(team_threads(E)) k_col2_batch(const BatchItem<R> *__restrict__ items,
+__global__ void __launch_bounds__(col_threads(M0, E)) k_col2_batch(const BatchItem<R> *__restrict__ items,
                                                          int nitems) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int g = xcd_tile(blockIdx.x, gridDim.x);

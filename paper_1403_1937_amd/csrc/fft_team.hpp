@@ -1,7 +1,7 @@
 // fft_team.hpp -- register/LDS Stockham FFT for gfx950 (wave64).
 //
 // A "team" of P = L/E threads transforms one complex line of length L
-// (compile-time power of two, E <= L <= 4096; E = 16 or 8 elements per
+// (compile-time power of two, E <= L <= 8192; E = 16 or 8 elements per
 // thread).  Thread t of the team always holds the E elements with indices
 // t + P*j, j < E, in registers: on entry the input samples, on exit the
 // transform values at the same indices.  Stages are Stockham autosort steps
@@ -285,7 +285,7 @@ __device__ __forceinline__ void team_stages(C (&v)[E], int t, C *lds, const C *t
 template <int L, bool INV, bool PACKED = false, int E, typename C>
 __device__ __forceinline__ void team_fft(C (&v)[E], int t, C *lds, const C *tws,
                                          bool lead_sync = true) {
-  static_assert(L >= E && L <= 4096 && (L & (L - 1)) == 0, "line length");
+  static_assert(L >= E && L <= 8192 && (L & (L - 1)) == 0, "line length");
   static_assert(E == 4 || E == 8 || E == 16, "elements per thread");
   if (lead_sync) __syncthreads();
   team_stages<L, INV, PACKED, E, 1>(v, t, lds, tws);

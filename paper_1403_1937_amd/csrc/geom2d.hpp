@@ -5,7 +5,8 @@
 //                elements per thread); 4096/E threads per work-group, i.e.
 //                rpw = 4096 / H1 rows (at least 1) for either E
 //   column pass  one team of P = M0/E threads per spectral column; cpw =
-//                4096 / M0 columns per work-group
+//                4096 / M0 columns per work-group (one 8192-point column,
+//                8192/E threads, in float32 with E = 16)
 //   spectrum     half spectrum of the rows, blocked transposed:
 //                spec[b][k1][rr], RB = 4 (float) or 2 (double) rows per block,
 //                so that one block entry is 32 bytes
@@ -43,6 +44,8 @@ constexpr int kRowThreads = 256;
 constexpr int row_rpw(int H) { return H / 16 >= kRowThreads ? 1 : kRowThreads / (H / 16); }
 constexpr int row_threads(int H, int E) { return row_rpw(H) * (H / E); }
 constexpr int col_cpw(int M0) { return M0 / 16 >= kThreads ? 1 : kThreads / (M0 / 16); }
+// threads of a column-pass work-group: 4096/E up to M0 = 4096, M0/E beyond
+constexpr int col_threads(int M0, int E) { return col_cpw(M0) * (M0 / E); }
 constexpr size_t kLdsDevice = 163840;  // gfx950 limit per work-group
 
 // Row pass LDS: twiddle table of the split steps (H entries of
@@ -141,6 +144,12 @@ template <typename R> constexpr size_t col_lds_bytes(int M0) {
 constexpr size_t kColLdsStatic = 512;  // static shared memory of a column pass
 template <typename R> constexpr bool col_fits(int M0) {
   return col_lds_bytes<R>(M0) + kColLdsStatic <= kLdsDevice;
+}
+// a column pass of length M0 with radix-E teams is built and planned: it fits
+// the LDS, and columns beyond 4096 points (one per work-group) take E = 16
+// only (512 threads; E = 8 would need 1024 threads at 128 registers each)
+template <typename R> constexpr bool col_ok(int M0, int E) {
+  return col_fits<R>(M0) && (M0 <= 4096 || E == 16);
 }
 
 }  // namespace sweik

@@ -41,6 +41,7 @@ template <typename K> static hipError_t set_lds(K kernel, size_t bytes) {
     case 1024: return F<1024>(__VA_ARGS__);                                          \
     case 2048: return F<2048>(__VA_ARGS__);                                          \
     case 4096: return F<4096>(__VA_ARGS__);                                          \
+    case 8192: return F<8192>(__VA_ARGS__);                                          \
   }                                                                                 \
   return hipErrorInvalidValue;
 
@@ -152,24 +153,24 @@ hipError_t launch_row2_batch_e(int mode, int H, int nblocks, hipStream_t st,
 template <typename R, int E, int MODE> struct ColLaunch {
   template <int M0> static hipError_t one(dim3 grid, hipStream_t st, const Args2<R> &a) {
     constexpr size_t lds = col_lds_bytes<R>(M0);
-    if constexpr (!col_fits<R>(M0)) {  // rejected by the planner
+    if constexpr (!col_ok<R>(M0, E)) {  // rejected by the planner
       return hipErrorInvalidValue;
     } else {
       static const hipError_t attr = set_lds(k_col2<R, MODE, M0, E>, lds);
       if (attr != hipSuccess) return attr;
-      hipLaunchKernelGGL((k_col2<R, MODE, M0, E>), grid, dim3(team_threads(E)), lds, st, a);
+      hipLaunchKernelGGL((k_col2<R, MODE, M0, E>), grid, dim3(col_threads(M0, E)), lds, st, a);
       return hipGetLastError();
     }
   }
   template <int M0>
   static hipError_t batch(int nblocks, hipStream_t st, const BatchItem<R> *items, int nitems) {
     constexpr size_t lds = col_lds_bytes<R>(M0);
-    if constexpr (!col_fits<R>(M0)) {
+    if constexpr (!col_ok<R>(M0, E)) {
       return hipErrorInvalidValue;
     } else {
       static const hipError_t attr = set_lds(k_col2_batch<R, MODE, M0, E>, lds);
       if (attr != hipSuccess) return attr;
-      hipLaunchKernelGGL((k_col2_batch<R, MODE, M0, E>), dim3(nblocks), dim3(team_threads(E)),
+      hipLaunchKernelGGL((k_col2_batch<R, MODE, M0, E>), dim3(nblocks), dim3(col_threads(M0, E)),
                          lds, st, items, nitems);
       return hipGetLastError();
     }
