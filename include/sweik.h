@@ -61,7 +61,7 @@ typedef enum {
   SWEIK_EINVAL = 1,       /* invalid argument */
   SWEIK_EUNSUPPORTED = 2, /* valid but not supported: a grid beyond the sizes
                              below (2D n1 <= 4096 and n0 <= 4096 in float32,
-                             n0 <= 2048 in float64; 3D every axis <= 512), a
+                             n0 <= 2048 in float64; 3D every axis <= 1024), a
                              2D-only call on a 3D plan, or a schedule the
                              plan cannot run */
   SWEIK_EWORKSPACE = 3,   /* workspace or checkpoint buffer too small */

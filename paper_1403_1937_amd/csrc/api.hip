@@ -547,7 +547,7 @@ sweik_status plan3d(sweik_plan_s *pl) {
   int64_t M[3];
   for (int d = 0; d < 3; ++d) {
     M[d] = std::max<int64_t>(64, next_pow2(2 * p.dims[d] - 1));
-    if (M[d] > 1024) return SWEIK_EUNSUPPORTED;
+    if (M[d] > 2048) return SWEIK_EUNSUPPORTED;
   }
   g.n0 = (int)p.dims[0];
   g.n1 = (int)p.dims[1];

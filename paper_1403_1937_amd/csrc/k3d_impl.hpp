@@ -35,6 +35,7 @@ static hipError_t x3_mode(int H, int nblocks, hipStream_t st, const Args3<R> &a,
     case 128: return x3_one<R, MODE, 128>(nblocks, st, a, term);
     case 256: return x3_one<R, MODE, 256>(nblocks, st, a, term);
     case 512: return x3_one<R, MODE, 512>(nblocks, st, a, term);
+    case 1024: return x3_one<R, MODE, 1024>(nblocks, st, a, term);
   }
   return hipErrorInvalidValue;
 }
@@ -80,6 +81,7 @@ static hipError_t c3_mode(int M, int nblocks, hipStream_t st, const Args3<R> &a,
     case 256: return c3_one<R, MODE, 256>(nblocks, st, a, term);
     case 512: return c3_one<R, MODE, 512>(nblocks, st, a, term);
     case 1024: return c3_one<R, MODE, 1024>(nblocks, st, a, term);
+    case 2048: return c3_one<R, MODE, 2048>(nblocks, st, a, term);
   }
   return hipErrorInvalidValue;
 }

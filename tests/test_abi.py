@@ -74,9 +74,9 @@ def test_unsupported_sizes(lib):
     with pytest.raises(ValueError, match="unsupported"):
         _plan(dims=(64, 4097), precision="fp64")  # row FFT length 16384
     for prec in ("fp32", "fp64"):
-        _plan(dims=(512, 512, 512), precision=prec)  # largest 3D grid
+        _plan(dims=(1024, 1024, 1024), precision=prec)  # largest 3D grid
         with pytest.raises(ValueError, match="unsupported"):
-            _plan(dims=(513, 8, 8), precision=prec)
+            _plan(dims=(1025, 8, 8), precision=prec)
 
 
 def test_workspace_sizes_scale_with_grid(lib):

@@ -38,8 +38,10 @@ def _dLdS(dims, rec, w, S, target):
     return g
 
 
-# padded lengths 64 (the smallest), 128 and 256 along some axes, ragged sizes
-CASES = [((20, 18, 22), 4), ((33, 12, 40), 5), ((16, 50, 16), 3), ((96, 80, 64), 6)]
+# padded lengths 64 (the smallest), 128 and 256 along some axes, ragged sizes;
+# 2048 (the largest) along the contiguous axis and along axis 0
+CASES = [((20, 18, 22), 4), ((33, 12, 40), 5), ((16, 50, 16), 3), ((96, 80, 64), 6),
+         ((6, 5, 700), 3), ((700, 5, 6), 3)]
 
 
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-9), ("fp32", 1e-3)])

@@ -67,6 +67,13 @@ CASES = [
     ("thin300x5x5", (300, 5, 5), 1 / 300, 0.1, 4, 2, 43),
     ("thin5x300x5", (5, 300, 5), 1 / 300, 0.1, 4, 2, 44),
     ("thin5x5x300", (5, 5, 300), 1 / 300, 0.1, 4, 2, 45),
+    # padded length 2048 (x pass with 1024 odd-frequency bins, 2048-point
+    # column passes): the largest supported axis, 1024
+    ("thin600x5x5", (600, 5, 5), 1 / 600, 0.1, 4, 2, 46),
+    ("thin5x600x5", (5, 600, 5), 1 / 600, 0.1, 4, 2, 47),
+    ("thin5x5x600", (5, 5, 600), 1 / 600, 0.1, 4, 2, 48),
+    ("thin1024x4x4", (1024, 4, 4), 1 / 1024, 0.1, 3, 2, 49),
+    ("thin4x4x1024", (4, 4, 1024), 1 / 1024, 0.1, 3, 2, 50),
 ]
 
 
