@@ -113,12 +113,13 @@ typedef struct sweik_plan_s *sweik_plan;
 /* Validate a problem and choose the kernel schedule.  Host only: makes no
  * HIP call.  Returns SWEIK_EINVAL for invalid fields, SWEIK_EUNSUPPORTED for
  * grids beyond the supported sizes.  Padded FFT lengths (the next power of
- * two >= 2n-1, at least 64): 2D axis 0 <= 4096 and axis 1 <= 8192; 3D
- * every axis <= 1024.  In grid points: 2D n0 <= 2048 and n1 <= 4096, 3D
- * n0, n1, n2 <= 512, in both precisions.  The bound is the line length one
- * work-group transforms in its registers and LDS (a column of 4096 points,
- * a real row of 8192); the method itself has none, and a larger grid would
- * need a two-level (four-step) transform along the long axis. */
+ * two >= 2n-1, at least 64): 2D axis 0 <= 8192 in float32 and <= 4096 in
+ * float64, axis 1 <= 8192; 3D every axis <= 2048.  In grid points: 2D
+ * n0 <= 4096 (float32) or 2048 (float64) and n1 <= 4096, 3D n0, n1,
+ * n2 <= 1024.  The bound is the line length one work-group transforms in
+ * its registers and LDS (a column of 8192 points, a real row of 8192); the
+ * method itself has none, and a larger grid would need a two-level
+ * (four-step) transform along the long axis. */
 sweik_status sweik_plan_create(const sweik_problem *problem, sweik_plan *out);
 void sweik_plan_destroy(sweik_plan plan);
 
