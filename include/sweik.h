@@ -60,8 +60,9 @@ typedef enum {
   SWEIK_OK = 0,
   SWEIK_EINVAL = 1,       /* invalid argument */
   SWEIK_EUNSUPPORTED = 2, /* valid but not supported: a grid beyond the sizes
-                             below (2D n1 <= 4096 and n0 <= 4096 in float32,
-                             n0 <= 2048 in float64; 3D every axis <= 1024), a
+                             below (2D n0 <= 4096 and n1 <= 8192 in float32,
+                             n0 <= 2048 and n1 <= 4096 in float64; 3D every
+                             axis <= 1024), a
                              2D-only call on a 3D plan, or a schedule the
                              plan cannot run */
   SWEIK_EWORKSPACE = 3,   /* workspace or checkpoint buffer too small */
@@ -113,11 +114,12 @@ typedef struct sweik_plan_s *sweik_plan;
 /* Validate a problem and choose the kernel schedule.  Host only: makes no
  * HIP call.  Returns SWEIK_EINVAL for invalid fields, SWEIK_EUNSUPPORTED for
  * grids beyond the supported sizes.  Padded FFT lengths (the next power of
- * two >= 2n-1, at least 64): 2D axis 0 <= 8192 in float32 and <= 4096 in
- * float64, axis 1 <= 8192; 3D every axis <= 2048.  In grid points: 2D
- * n0 <= 4096 (float32) or 2048 (float64) and n1 <= 4096, 3D n0, n1,
- * n2 <= 1024.  The bound is the line length one work-group transforms in
- * its registers and LDS (a column of 8192 points, a real row of 8192); the
+ * two >= 2n-1, at least 64): 2D axis 0 <= 8192 and axis 1 <= 16384 in
+ * float32, 4096 and 8192 in float64; 3D every axis <= 2048.  In grid
+ * points: 2D n0 <= 4096 and n1 <= 8192 (float32) or n0 <= 2048 and
+ * n1 <= 4096 (float64), 3D n0, n1, n2 <= 1024.  The bound is the line
+ * length one work-group transforms in its registers and LDS (a column of
+ * 8192 points, a real row of 16384); the
  * method itself has none, and a larger grid would need a two-level
  * (four-step) transform along the long axis. */
 sweik_status sweik_plan_create(const sweik_problem *problem, sweik_plan *out);
@@ -406,7 +408,8 @@ sweik_status sweik_batch_solve_graph(sweik_batch batch, const void *const *f,
  * threads per work-group (the rows or columns per work-group do not change).
  *   row_e     2D row passes (all modes): 16, 8, or 4 (float32 only)
  *   col_e     2D column passes (all modes): 16, 8, or 4 (float32 only);
- *             16 only for n0 > 2048 (8192-point columns)
+ *             16 only for n0 > 2048 (8192-point columns); likewise row_e
+ *             for n1 > 4096
  *   phi0_fft  2D and 3D: 0 = phi_0 by the direct sum over the sources (eq.
  *             phi_0Solution), 1 = by FFT as in Table 1 steps 1-5 (the
  *             spectrum of exp(-beta |m|) times the transform of the source
@@ -424,7 +427,7 @@ typedef struct {
 sweik_status sweik_plan_get_schedule(sweik_plan plan, sweik_schedule *out);
 /* SWEIK_EINVAL for a value other than 16, 8 or 4 (0 or 1 for phi0_fft);
  * SWEIK_EUNSUPPORTED for 4 in a float64 plan, col_e other than 16 with
- * n0 > 2048, or a 3D plan with a radix
+ * n0 > 2048, row_e other than 16 with n1 > 4096, or a 3D plan with a radix
  * other than 16.  Host only.  Not to be called while a
  * solve with this plan is being enqueued on another thread. */
 sweik_status sweik_plan_set_schedule(sweik_plan plan, const sweik_schedule *s);

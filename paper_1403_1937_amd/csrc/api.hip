@@ -139,13 +139,13 @@ sweik_status plan2d(sweik_plan_s *pl) {
   g.n1 = (int)p.dims[1];
   const int64_t M0 = std::max<int64_t>(64, next_pow2(2 * p.dims[0] - 1));
   const int64_t M1 = std::max<int64_t>(64, next_pow2(2 * p.dims[1] - 1));
-  if (M0 > 8192 || M1 > 8192) return SWEIK_EUNSUPPORTED;
+  if (M0 > 8192 || M1 > 16384) return SWEIK_EUNSUPPORTED;
   g.M0 = (int)M0;
   g.H0 = (int)(M0 / 2);
   g.ldg = g.H0 + 1;
   g.H1 = (int)(M1 / 2);
   g.ldk = g.H1;  // spectral columns; column 0 carries bins 0 and H1
-  if (g.H1 > 4096 || g.H1 < 32) return SWEIK_EUNSUPPORTED;
+  if (g.H1 > 8192 || g.H1 < 32) return SWEIK_EUNSUPPORTED;
   g.RB = p.prec == SWEIK_F64 ? spec_rb<double>() : spec_rb<float>();
   g.nb = (g.n0 + g.RB - 1) / g.RB;
   // every pass must fit the work-group LDS limit
@@ -163,6 +163,7 @@ sweik_status plan2d(sweik_plan_s *pl) {
   g.lmax = (int)std::max(M0, M1);
   g.lmax_log = ilog2(g.lmax);
   g.erow = sched_lookup(SCHED_ROW2, g.H1, p.prec, 16);
+  if (g.H1 > 4096) g.erow = 16;  // 8192-point rows: radix 16 only
   g.ecol = sched_lookup(SCHED_COL2, g.M0, p.prec, 16);
   if (!(f64 ? col_ok<double>(g.M0, g.ecol) : col_ok<float>(g.M0, g.ecol))) g.ecol = 16;
   // phi_0 by FFT (Table 1 steps 1-5) when the direct sum over the sources
@@ -1044,7 +1045,7 @@ template <typename R> int32_t autotune2d(sweik_plan_s *pl, void *ws, hipStream_t
     for (int ir = 0; ir < ncand; ++ir) {
       if (!col_ok<R>(g.M0, cand[ic])) continue;
       if (!rows && ir != 0) continue;
-      if (rows && g.H1 < cand[ir]) continue;
+      if (rows && !row_ok<R>(g.H1, cand[ir], ROW_TERM)) continue;
       pc[npair] = cand[ic];
       pr[npair] = cand[ir];
       ++npair;
@@ -1455,7 +1456,7 @@ sweik_status sweik_plan_set_schedule(sweik_plan plan, const sweik_schedule *sc) 
   if (plan->p.ndim == 3 && (sc->row_e != 16 || sc->col_e != 16)) return SWEIK_EUNSUPPORTED;
   if (plan->p.ndim == 2) {
     const int H = plan->g2.H1;
-    if (H < sc->row_e) return SWEIK_EUNSUPPORTED;
+    if (H < sc->row_e || (H > 4096 && sc->row_e != 16)) return SWEIK_EUNSUPPORTED;
     const int M0 = plan->g2.M0;
     if (!(plan->p.prec == SWEIK_F64 ? col_ok<double>(M0, sc->col_e) : col_ok<float>(M0, sc->col_e)))
       return SWEIK_EUNSUPPORTED;

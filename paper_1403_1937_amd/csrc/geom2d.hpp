@@ -48,8 +48,16 @@ constexpr int col_cpw(int M0) { return M0 / 16 >= kThreads ? 1 : kThreads / (M0 
 constexpr int col_threads(int M0, int E) { return col_cpw(M0) * (M0 / E); }
 constexpr size_t kLdsDevice = 163840;  // gfx950 limit per work-group
 
-// Row pass LDS: twiddle table of the split steps (H entries of
-// exp(-2 pi i k / 2H)), the stage
+// Split-step twiddles exp(-2 pi i k / 2H), k < H: one table of H entries up to
+// H = 4096; beyond, a coarse table (k a multiple of 64) and a fine one
+// (k < 64) whose product is the twiddle, so that an 8192-point row (float32)
+// fits the LDS.
+constexpr int kSplitFineBits = 6;
+constexpr bool row_split2(int H) { return H > 4096; }
+constexpr int row_twl_len(int H) {
+  return row_split2(H) ? (H >> kSplitFineBits) + (1 << kSplitFineBits) : H;
+}
+// Row pass LDS: twiddle table(s) of the split steps (row_twl_len), the stage
 // tables of the length-H FFT (room for either schedule), one padded line per
 // row, and (when it fits) staging rows for the pointwise operands so that
 // their loads are issued with the spectrum's.
@@ -76,7 +84,8 @@ template <typename R> constexpr int row_line_len(int H) {
 }
 template <typename R> constexpr size_t row_lds_core(int H) {
   return sizeof(R) * 2 *
-         ((size_t)H + (size_t)row_stage_tw<R>(H) + (size_t)row_rpw(H) * row_line_len<R>(H));
+         ((size_t)row_twl_len(H) + (size_t)row_stage_tw<R>(H) +
+          (size_t)row_rpw(H) * row_line_len<R>(H));
 }
 // static shared memory of a row pass (block reductions, scalars, the term
 // scales; phi_0 also holds up to 512 sources and their weights), at least
@@ -111,6 +120,12 @@ template <typename R> constexpr size_t row_lds_bytes(int H, int mode) {
 // dynamic + static shared memory of a row pass fits a work-group
 template <typename R> constexpr bool row_fits(int H, int mode) {
   return row_lds_bytes<R>(H, mode) + row_lds_static<R>(mode) <= kLdsDevice;
+}
+// a row pass of length H with radix-E teams is built and planned: it fits the
+// LDS, E <= H, and rows beyond 4096 complex points (one per work-group) take
+// E = 16 only (512 threads)
+template <typename R> constexpr bool row_ok(int H, int E, int mode) {
+  return row_fits<R>(H, mode) && E <= H && (H <= 4096 || E == 16);
 }
 // the paired kernel-table + phi_0 pass (both passes' static shared memory,
 // the larger dynamic size) is used where two of its work-groups fit a CU

@@ -30,6 +30,7 @@ template <typename K> static hipError_t set_lds(K kernel, size_t bytes) {
     case 1024: return F<1024>(__VA_ARGS__);                                          \
     case 2048: return F<2048>(__VA_ARGS__);                                          \
     case 4096: return F<4096>(__VA_ARGS__);                                          \
+    case 8192: return F<8192>(__VA_ARGS__);                                          \
   }                                                                                 \
   return hipErrorInvalidValue;
 #define SWEIK_COL_LENGTHS(F, ...)                                                   \
@@ -48,7 +49,7 @@ template <typename K> static hipError_t set_lds(K kernel, size_t bytes) {
 template <typename R, int E, int MODE> struct RowLaunch {
   template <int H> static hipError_t one(dim3 grid, hipStream_t st, const Args2<R> &a, int term) {
     constexpr size_t lds = row_lds_bytes<R>(H, MODE);
-    if constexpr (!row_fits<R>(H, MODE) || H < E) {  // rejected by the planner
+    if constexpr (!row_ok<R>(H, E, MODE)) {  // rejected by the planner
       return hipErrorInvalidValue;
     } else {
       static const hipError_t attr = set_lds(k_row2<R, MODE, H, E>, lds);
@@ -61,7 +62,7 @@ template <typename R, int E, int MODE> struct RowLaunch {
   static hipError_t batch(int nblocks, hipStream_t st, const BatchItem<R> *items, int nitems,
                           int term) {
     constexpr size_t lds = row_lds_bytes<R>(H, MODE);
-    if constexpr (!row_fits<R>(H, MODE) || H < E) {
+    if constexpr (!row_ok<R>(H, E, MODE)) {
       return hipErrorInvalidValue;
     } else {
       static const hipError_t attr = set_lds(k_row2_batch<R, MODE, H, E>, lds);

@@ -106,6 +106,24 @@ __device__ __forceinline__ void tile_store(const RowTile<R, H, E> &tile, int tid
   }
 }
 
+// Split-step twiddle k from the LDS table(s) (see row_twl_len): the entry
+// itself, or beyond 4096 points the product of the coarse entry k >> 6 and
+// the fine entry k & 63.  split_tw_k: the twiddle index held by table entry e.
+__host__ __device__ constexpr int split_tw_k(int H, int e) {
+  return !row_split2(H) ? e
+         : e < (H >> kSplitFineBits) ? e << kSplitFineBits
+                                     : e - (H >> kSplitFineBits);
+}
+template <typename R, int H>
+__device__ __forceinline__ cplx<R> split_tw(const cplx<R> *twl, int k) {
+  if constexpr (!row_split2(H)) {
+    return twl[k];
+  } else {
+    constexpr int NA = H >> kSplitFineBits, MASK = (1 << kSplitFineBits) - 1;
+    return cmul(twl[k >> kSplitFineBits], twl[NA + (k & MASK)]);
+  }
+}
+
 // Inverse real FFT of this team's row (already in LDS): on return
 // v[j] = (x[2k], x[2k+1]) * 2 M1, k = t + P j, x the real row (M1 = 2H).
 template <typename R, int H, int E>
@@ -121,7 +139,7 @@ __device__ __forceinline__ void row_c2r(cplx<R> (&v)[E], int t, cplx<R> *line,
     C xk = line[lslot<cplx<R>>(k)];
     C xc = cconj(line[lslot<cplx<R>>((H - k) & (H - 1))]);
     C e = cadd(xk, xc);
-    C o = cmulc(csub(xk, xc), twl[k]);
+    C o = cmulc(csub(xk, xc), split_tw<R, H>(twl, k));
     v[j] = cmake<C>(e.x - o.y, e.y + o.x);
     if (k == 0) v[j] = cmake<C>(xk.x + xk.y, xk.x - xk.y);
   }
@@ -152,7 +170,7 @@ __device__ __forceinline__ void row_r2c_store(cplx<R> (&v)[E], int t, int tid,
     C e = cadd(zk, zc);
     C d = csub(zk, zc);
     C o = cmake<C>(d.y, -d.x);  // d / i
-    x[j] = cadd(e, cmul(twl[k], o));
+    x[j] = cadd(e, cmul(split_tw<R, H>(twl, k), o));
     // k = 0: the real bins X_0 and X_H travel together
     if (k == 0) x[j] = cmake<C>((R)2 * (zk.x + zk.y), (R)2 * (zk.x - zk.y));
   }
@@ -188,7 +206,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   constexpr int P = H / E, RPW = row_rpw(H), LL = row_line_len<R>(H), NT = row_threads(H, E);
   constexpr int TWLOG = ilog2c(2 * H);
   constexpr bool STG = row_staged<R>(H, MODE);
-  constexpr int NTW = (H + NT - 1) / NT;
+  constexpr int TWL = row_twl_len(H), NTW = (TWL + NT - 1) / NT;
   constexpr bool LASTLIKE = MODE == ROW_LAST || MODE == ROW_LASTT;
   constexpr bool TERMLIKE = MODE == ROW_TERM || LASTLIKE;
   constexpr bool ADJ = MODE == ROW_ADJ || MODE == ROW_ADJ_B;
@@ -199,7 +217,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   // phi_0 reads the spectrum only on its FFT route
   const bool tile_in = MODE != ROW_PHI0 || a.phi0_fft;
   C *twl = reinterpret_cast<C *>(smem_raw);  // exp(-2 pi i k / 2H), k < H (split steps)
-  C *tws = twl + H;                          // stage tables of the length-H FFT
+  C *tws = twl + TWL;                        // stage tables of the length-H FFT
   C *lines = tws + row_stage_tw<R>(H);
   unsigned char *stg = reinterpret_cast<unsigned char *>(lines + RPW * LL);
   __shared__ double s_par[2];
@@ -226,8 +244,8 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   C twr[NTW];
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
-    const int k = tid + u * NT;
-    twr[u] = a.tw[min(k, H - 1) << (a.lmax_log - TWLOG)];  // stored only if k < H
+    const int e = tid + u * NT;
+    twr[u] = a.tw[min(split_tw_k(H, e), H - 1) << (a.lmax_log - TWLOG)];  // stored if e < TWL
   }
   constexpr int NSR = (stage_tw_len(H, E) + NT - 1) / NT;
   C tsr[NSR > 0 ? NSR : 1];
@@ -459,8 +477,8 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
   // ---- 3. operands into LDS -------------------------------------------------
 #pragma unroll
   for (int u = 0; u < NTW; ++u) {
-    const int k = tid + u * NT;
-    if (k < H) twl[k] = twr[u];
+    const int e = tid + u * NT;
+    if (e < TWL) twl[e] = twr[u];
   }
   stage_tw_store<H, E>(tsr, tws, tid, NT);
   if (LOADS_TILE && tile_in) tile_to_lds<FULL>(tile, tid, tl, lines);

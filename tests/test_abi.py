@@ -68,11 +68,15 @@ def test_unsupported_sizes(lib):
     with pytest.raises(ValueError, match="unsupported"):
         _plan(dims=(4096, 64), precision="fp64")  # float64 column FFT length 8192
     with pytest.raises(ValueError, match="unsupported"):
-        _plan(dims=(64, 8192))      # row FFT length 16384
-    _plan(dims=(4096, 4096))        # largest 2D grid
+        _plan(dims=(64, 8193))      # row FFT length 32768
+    _plan(dims=(4096, 8192))        # largest 2D grid (float32)
     _plan(dims=(2048, 4096), precision="fp64")  # largest float64 grid
     with pytest.raises(ValueError, match="unsupported"):
-        _plan(dims=(64, 4097), precision="fp64")  # row FFT length 16384
+        _plan(dims=(64, 4097), precision="fp64")  # float64 row FFT length 16384
+    wide = _plan(dims=(40, 5000))   # 8192-point complex rows: radix 16 only
+    assert wide.schedule["row_e"] == 16
+    with pytest.raises(ValueError, match="unsupported"):
+        wide.set_schedule(8, 16)
     for prec in ("fp32", "fp64"):
         _plan(dims=(1024, 1024, 1024), precision=prec)  # largest 3D grid
         with pytest.raises(ValueError, match="unsupported"):

@@ -1,6 +1,7 @@
-"""2D grids with more than 2048 rows (float32): the column passes transform
-8192-point columns, one per work-group.  Forward, adjoint, tilted and
-batched solves against the FP64 oracle or the single solve."""
+"""2D grids beyond 2048 rows or 4096 columns (float32): the column passes
+transform 8192-point columns and the row passes 8192-point complex rows
+(16384 real points), one per work-group.  Forward, adjoint, full gradient,
+tilted and batched solves against the FP64 oracle or the single solve."""
 import numpy as np
 import pytest
 import torch
@@ -22,6 +23,9 @@ TALL = [
     ("tall3000x24", (3000, 24), 1 / 3000, 0.3, 4, 2, 9),     # partial last row block
     ("tall4096x96", (4096, 96), 1 / 4096, 0.2, 6, 3, 10),    # every column work-group full
     ("tall2049x130", (2049, 130), 1 / 2049, 0.15, 5, 4, 11),  # smallest n0 past 2048
+    ("wide24x5000", (24, 5000), 1 / 5000, 0.3, 4, 2, 15),     # 8192-point complex rows
+    ("wide40x8192", (40, 8192), 1 / 8192, 0.2, 4, 3, 16),     # every row full
+    ("both2100x4200", (2100, 4200), 1 / 4200, 0.1, 3, 4, 17),  # both long axes
 ]
 
 
@@ -35,7 +39,7 @@ def test_forward_parity_tall(case):
     s = rng.uniform(0.0, 0.05, n_src)
     print(f"tall case {name} {dims} fp32", flush=True)
     pl = pk.Plan(dims, h, hbar, T, n_src, "fp32")
-    assert pl.padded[0] == 8192
+    assert pl.padded[0] == 8192 or pl.padded[1] == 16384
     ft = torch.as_tensor(f).cuda()
     S, info = pk.solve(ft, src, h, hbar, T, src_s=s, return_info=True)
     S = S.double().cpu().numpy()
@@ -66,6 +70,35 @@ def test_adjoint_tall():
     err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     print(f"  normwise rel {err:.3e}", flush=True)
     assert err <= 1e-3
+
+
+def test_full_gradient_wide():
+    """The full gradient's row passes at 8192-point complex rows."""
+    import paper_1403_1937_amd as pk
+    from oracle import grad
+    rng = np.random.default_rng(18)
+    dims, h, hbar, T = (20, 5000), 1 / 5000, 0.3, 3
+    f = workloads.smoothed_noise(dims, 4.0, 1.0, 3.0, rng).astype(np.float32).astype(np.float64)
+    src = workloads.distinct_sources(dims, 2, rng)
+    rec = workloads.receivers_near_sources(dims, src, 24, 300.0, rng)
+    o = oracle.solve(f, src, h, hbar, T)
+    dLdS = np.zeros(dims)
+    for r in rec:
+        dLdS[tuple(r)] += 0.06 * o["S"][tuple(r)]
+    go = grad.full_gradient(f, src, h, hbar, T, dLdS)
+    print("wide full gradient (20, 5000) fp32", flush=True)
+    g, sc = pk.solve_gradient(torch.as_tensor(f, dtype=torch.float32).cuda(), src, h, hbar, T,
+                              torch.as_tensor(dLdS, dtype=torch.float32).cuda())
+    g = g.double().cpu().numpy()
+    err = np.linalg.norm(g - go["dLdf"]) / np.linalg.norm(go["dLdf"])
+    eh = abs(sc["dLdhbar"] - go["dLdhbar"]) / abs(go["dLdhbar"])
+    # the same without the two extreme points of f, whose reference-forcing
+    # part (formed in float64) can dominate the norm
+    bulk = np.ones(dims, bool)
+    bulk.reshape(-1)[[int(np.argmin(f)), int(np.argmax(f))]] = False
+    eb = np.linalg.norm((g - go["dLdf"])[bulk]) / np.linalg.norm(go["dLdf"][bulk])
+    print(f"  dLdf {err:.3e} (without the extreme points {eb:.3e}), dLdhbar {eh:.3e}", flush=True)
+    assert err <= 1e-3 and eb <= 1e-3 and eh <= 1e-3
 
 
 def test_tilted_tall():
