@@ -484,6 +484,66 @@ def run_backtrack(pk, torch, dev, steps, warmup):
             "bound": "latency (one thread per path, dependent reads of S)"}
 
 
+def run_large(pk, torch, dev, steps, warmup):
+    """The largest grids a plan takes, in float32 (T = 16): 2D 4096 x 8192
+    (16 sources) and 3D 1024^3 (one source, a 112 GiB workspace).  f is a
+    smooth field made on the device; each grid also gets a constant-forcing
+    solve (phi = phi_0) checked against its closed form on 4096 sampled
+    points."""
+    import math
+    out = {}
+    rng = np.random.default_rng(23)
+    for dims, n_src in (((4096, 8192), 16), ((1024, 1024, 1024), 1)):
+        n = max(dims)
+        ax = [torch.arange(d, dtype=torch.float32, device=dev) / d for d in dims]
+        if len(dims) == 2:
+            f = 2.0 + 0.8 * torch.sin(6 * math.pi * ax[0])[:, None] * torch.cos(4 * math.pi * ax[1])[None, :]
+        else:
+            f = (1.25 + 0.35 * torch.sin(2 * math.pi * ax[0])[:, None, None]
+                 * torch.cos(4 * math.pi * ax[1])[None, :, None]
+                 + 0.2 * torch.sin(6 * math.pi * ax[2])[None, None, :])
+        f = f.contiguous()
+        src = np.stack([rng.integers(0, d, n_src) for d in dims], 1).astype(np.int32)
+        src = np.unique(src, axis=0)
+        h, hbar, T = 1.0 / n, 0.05 if len(dims) == 2 else 0.1, 16
+        plan = pk.Plan(dims, h, hbar, T, len(src), "fp32")
+        ws = plan.workspace(dev)
+        d_src = torch.as_tensor(src).to(dev)
+        S = torch.empty_like(f)
+        for _ in range(max(1, warmup)):
+            plan.solve(f, d_src, S, ws)
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = _events(torch, st)
+        e0.record(st)
+        for _ in range(steps):
+            plan.solve(f, d_src, S, ws)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        finite = float(torch.isfinite(S).float().mean().item())
+        del ws, S
+        # constant forcing: S = -hbar ln sum_k exp(-c |x - y_k| h / hbar)
+        c = 1.3
+        fc = torch.full_like(f, c)
+        del f
+        Sc = pk.solve(fc, src, h, hbar, 2)
+        idx = np.stack([rng.integers(0, d, 4096) for d in dims], 1)
+        dist = np.linalg.norm(idx[:, None, :] - src[None, :, :], axis=-1) * h
+        ref = -hbar * np.log(np.exp(-c * dist / hbar).sum(axis=1))
+        got = Sc[tuple(torch.as_tensor(idx.T).to(dev).long())].double().cpu().numpy()
+        err = float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), hbar)))
+        del Sc, fc
+        torch.cuda.empty_cache()
+        N = int(np.prod(dims))
+        name = ("noise2d" if len(dims) == 2 else "smooth3d") + "_" + "x".join(map(str, dims))
+        out[f"{name}_T{T}_src{len(src)}"] = {
+            "value": N / (ms * 1e-3), "unit": "grid pts/s", "ms_per_step": ms,
+            "workspace_GiB": plan.workspace_bytes / 2**30, "finite_frac": finite,
+            "constant_forcing_closed_form_max_rel": err, "precision": "fp32-scaled"}
+    return out
+
+
 def run_fd(pk, torch, dev, steps, warmup):
     """The paper's second method (Section 6): the finite-difference screened
     Poisson system of the 1024^2 main workload, CG in float64 to
@@ -1057,7 +1117,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip fwd+bwd and batched")
     ap.add_argument("--only", choices=["fwd_bwd", "batched", "solve3d", "backtrack", "fd",
-                                       "config1", "far_field"],
+                                       "config1", "far_field", "large"],
                     help="run one extra section alone and print its JSON (profiling runs)")
     ap.add_argument("--pmc-run", action="store_true")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH", "WRITE"))
@@ -1101,7 +1161,7 @@ def main():
     if args.only:
         fn = {"fwd_bwd": run_fwd_bwd, "batched": run_batched, "solve3d": run_3d,
               "backtrack": run_backtrack, "fd": run_fd, "config1": run_config1,
-              "far_field": run_far_field}[args.only]
+              "far_field": run_far_field, "large": run_large}[args.only]
         r = fn(pk, torch, dev, args.steps, args.warmup)
         print(json.dumps(r[0] if isinstance(r, tuple) else r))
         return
@@ -1177,6 +1237,8 @@ def main():
         progress("backtrack")
         out["fd"] = run_fd(pk, torch, dev, 3, 1)
         progress("fd")
+        out["large_grids"] = run_large(pk, torch, dev, 3, 1)
+        progress("large_grids")
     if not args.no_cpu_baseline:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         out["cpu_baseline"], o_main = cpu_baseline(p, threads)
