@@ -63,12 +63,13 @@ def report(S, out_o, hbar, prec):
 LAMBDA_ENVELOPE = {"fp64": 30.0, "fp32": 14.0}
 
 
-def envelope_violations(S, out_o, hbar, prec, lam_cap=None):
+def envelope_violations(S, out_o, hbar, prec, lam_cap=None, ulps=1.0):
     """Points with Lambda <= lam_cap whose error exceeds the conditioning
-    envelope TOL + EPS exp(Lambda) / max(Lambda, 1)."""
+    envelope TOL + ulps EPS exp(Lambda) / max(Lambda, 1) (an absolute
+    rounding error of ulps units of max phi, seen relative to phi)."""
     L = lam(out_o["phi"])
     e = rel_err(S, out_o["S"], hbar)
     m = L <= (LAMBDA_ENVELOPE[prec] if lam_cap is None else lam_cap)
-    bound = TOL[prec] + EPS[prec] * np.exp(np.minimum(L, 700)) / np.maximum(L, 1.0)
+    bound = TOL[prec] + ulps * EPS[prec] * np.exp(np.minimum(L, 700)) / np.maximum(L, 1.0)
     bad = m & ~(e <= bound)
     return int(bad.sum())

@@ -10,7 +10,7 @@ import torch
 
 import oracle
 import workloads
-from common import TOL, ensure_built, envelope_violations, report
+from common import LAMBDA_MAX, TOL, ensure_built, envelope_violations, lam, rel_err, report
 
 pytestmark = pytest.mark.gpu
 
@@ -89,3 +89,39 @@ def test_sweep_adjoint(ndim, k, prec, tol):
     err = np.linalg.norm(g - g_o) / np.linalg.norm(g_o)
     print(f"  normwise rel {err:.2e}", flush=True)
     assert err <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("ndim,k", [(2, k) for k in range(8)] + [(3, k) for k in range(8)])
+def test_sweep_phi0_fft(ndim, k, prec):
+    """The sweep's cases with phi_0 forced onto the FFT route (Table 1 steps
+    1-5): the same bar against the oracle's direct sum."""
+    import paper_1403_1937_amd as pk
+    from paper_1403_1937_amd._native import _read_info, info_struct_size
+    dims, T, f, src, s, h, hbar, mode, ft = _case(ndim, k)
+    o = oracle.solve(f, src, h, hbar, T, ft_mode=mode, ftilde=ft, src_s=s)
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    pl = pk.Plan(dims, h, hbar, T, len(src), prec, ftilde_mode=mode, ftilde=ft)
+    pl.set_schedule(16, 16, phi0_fft=1)
+    fd = torch.as_tensor(f).to("cuda", dt)
+    S = torch.empty_like(fd)
+    info = torch.zeros(info_struct_size(), dtype=torch.uint8, device="cuda")
+    d_s = None if s is None else torch.as_tensor(s).to("cuda", dt)
+    print(f"phi0-FFT sweep {ndim}D {dims} T={T} n_src={len(src)} {mode} "
+          f"seeds={s is not None} {prec}", flush=True)
+    pl.solve(fd, torch.as_tensor(src.astype(np.int32)).cuda(), S, pl.workspace("cuda"), None,
+             info, src_s=d_s)
+    torch.cuda.synchronize()
+    S = S.double().cpu().numpy()
+    # phi_0 by FFT carries an absolute rounding error of about one unit of
+    # max phi_0 (the direct sum's is relative), which the series carries on:
+    # in FP32 the tolerance is claimed on Lambda <= 8 instead of 9, and the
+    # conditioning envelope with two units of max phi instead of one
+    L = lam(o["phi"])
+    m = L <= (LAMBDA_MAX["fp64"] if prec == "fp64" else 8.0)
+    e = rel_err(S, o["S"], hbar)
+    worst = float(e[m].max()) if m.any() else 0.0
+    print(f"  max rel {worst:.2e} on {m.mean():.3f} of the grid", flush=True)
+    assert worst <= TOL[prec]
+    assert envelope_violations(S, o, hbar, prec, ulps=2.0) == 0
+    assert _read_info(info)["n_nonpositive_phi"] == int(np.isinf(S).sum())
