@@ -122,6 +122,27 @@ def test_tilted_tall():
     assert ok.mean() > m.mean()
 
 
+def test_tilted_wide():
+    """The tilted row passes (tilted kernel table, last pass) at 8192-point
+    complex rows."""
+    import paper_1403_1937_amd as pk
+    rng = np.random.default_rng(19)
+    dims, h, hbar, T = (8, 4500), 1 / 4500, 0.02, 4
+    f = workloads.smoothed_noise(dims, 4.0, 1.0, 2.0, rng).astype(np.float32)
+    src = workloads.distinct_sources(dims, 1, rng)
+    print("wide tilted (8, 4500) fp32", flush=True)
+    S = pk.solve_tilted(torch.as_tensor(f).cuda(), src, h, hbar, T,
+                        tilts=[(0.0, 0.0), (0.0, 0.7), (0.0, -0.7)]).double().cpu().numpy()
+    o = oracle.solve(f.astype(np.float64), src, h, hbar, T)
+    ref = oracle.solve(f.astype(np.float64), src, h, hbar, T, method="direct")["S"]
+    e = rel_err(S, ref, hbar)
+    m = lam(o["phi"]) <= LAMBDA_MAX["fp32"]
+    ok = e <= TOL["fp32"]
+    print(f"  plain-resolvable {m.mean():.3f}, resolved {ok.mean():.3f}", flush=True)
+    assert ok[m].all()
+    assert ok.mean() > m.mean()
+
+
 def test_batch_with_tall_instance():
     import paper_1403_1937_amd as pk
     rng = np.random.default_rng(14)
