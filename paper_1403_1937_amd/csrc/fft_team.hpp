@@ -192,15 +192,24 @@ template <int p, int R, bool PACKED, typename C> __device__ __forceinline__ int 
 // Stage twiddle tables: for every stage of span p > 1 (p = E, E^2, ... < L)
 // the p entries exp(-2 pi i k / (p R)), k < p, stored contiguously in LDS one
 // stage after the other, so that the butterflies of consecutive k read
-// consecutive entries (no bank conflicts from strided table reads).
+// consecutive entries (no bank conflicts from strided table reads).  A span
+// beyond 2048 (the last stage of an 8192-point line) keeps two shorter
+// tables instead, the entries k = 64 j (j < p/64) and k < 64, whose product
+// is entry k: 128 entries instead of 4096, so that an 8192-point line fits
+// the LDS with room for a second work-group (float) or at all (double).
+constexpr bool stage_tw_split(int p) { return p > 2048; }
+constexpr int kStageFineBits = 6;
+constexpr int stage_tw_entries(int p) {
+  return stage_tw_split(p) ? (p >> kStageFineBits) + (1 << kStageFineBits) : p;
+}
 constexpr int stage_tw_len(int L, int E) {
   int n = 0;
-  for (int p = E; p < L; p *= E) n += p;
+  for (int p = E; p < L; p *= E) n += stage_tw_entries(p);
   return n;
 }
 constexpr int stage_tw_off(int p, int E) {
   int n = 0;
-  for (int q = E; q < p; q *= E) n += q;
+  for (int q = E; q < p; q *= E) n += stage_tw_entries(q);
   return n;
 }
 // index into a global table of 2^lmax_log entries exp(-2 pi i j / 2^lmax_log)
@@ -210,8 +219,13 @@ template <int L, int E> __device__ __forceinline__ int stage_tw_index(int e, int
 #pragma unroll
   for (int p = E; p < L; p *= E) {
     const int R = L / p < E ? L / p : E;
-    if (e < off + p) return (e - off) << (lmax_log - ilog2c(p * R));
-    off += p;
+    if (e < off + stage_tw_entries(p)) {
+      int k = e - off;  // entry k of the stage's table, or of its two tables
+      if (stage_tw_split(p))
+        k = k < (p >> kStageFineBits) ? k << kStageFineBits : k - (p >> kStageFineBits);
+      return k << (lmax_log - ilog2c(p * R));
+    }
+    off += stage_tw_entries(p);
   }
   return 0;
 }
@@ -235,7 +249,13 @@ __device__ __forceinline__ void stage(C (&v)[E], int t, C *lds, const C *tws) {
     if constexpr (p > 1) {
       // one table read per butterfly; the other twiddles are its powers
       C w[R];
-      w[1] = tws[stage_tw_off(p, E) + k];
+      if constexpr (stage_tw_split(p)) {
+        constexpr int o = stage_tw_off(p, E);
+        w[1] = cmul(tws[o + (k >> kStageFineBits)],
+                    tws[o + (p >> kStageFineBits) + (k & ((1 << kStageFineBits) - 1))]);
+      } else {
+        w[1] = tws[stage_tw_off(p, E) + k];
+      }
       if (INV) w[1] = cconj(w[1]);
 #pragma unroll
       for (int q = 2; q < R; ++q) w[q] = cmul(w[q / 2], w[q - q / 2]);

@@ -63,6 +63,7 @@ constexpr int row_twl_len(int H) {
 // their loads are issued with the spectrum's.
 template <typename R> constexpr int row_stage_tw(int H) {
   int n = stage_tw_len(H, 16);
+  if (H > 4096) return n;  // rows beyond 4096 points run at radix 16 only
   n = stage_tw_len(H, 8) > n ? stage_tw_len(H, 8) : n;
   if (sizeof(R) == 4) n = stage_tw_len(H, 4) > n ? stage_tw_len(H, 4) : n;  // radix 4: float only
   return n;
@@ -141,6 +142,7 @@ template <typename R> constexpr bool row_init_pairs(int H) {
 // any schedule) and one padded line per column.
 template <typename R> constexpr int col_stage_tw(int M0) {
   int n = stage_tw_len(M0, 16);
+  if (M0 > 4096) return n;  // columns beyond 4096 points run at radix 16 only
   n = stage_tw_len(M0, 8) > n ? stage_tw_len(M0, 8) : n;
   if (sizeof(R) == 4) n = stage_tw_len(M0, 4) > n ? stage_tw_len(M0, 4) : n;  // radix 4: float only
   return n;

@@ -65,12 +65,11 @@ def test_plan_rejects_unknown_modes(lib):
 def test_unsupported_sizes(lib):
     with pytest.raises(ValueError, match="unsupported"):
         _plan(dims=(4097, 64))      # column FFT length 16384
-    with pytest.raises(ValueError, match="unsupported"):
-        _plan(dims=(4096, 64), precision="fp64")  # float64 column FFT length 8192
+    _plan(dims=(4096, 64), precision="fp64")  # float64 column FFT length 8192
     with pytest.raises(ValueError, match="unsupported"):
         _plan(dims=(64, 8193))      # row FFT length 32768
     _plan(dims=(4096, 8192))        # largest 2D grid (float32)
-    _plan(dims=(2048, 4096), precision="fp64")  # largest float64 grid
+    _plan(dims=(4096, 4096), precision="fp64")  # largest float64 grid
     with pytest.raises(ValueError, match="unsupported"):
         _plan(dims=(64, 4097), precision="fp64")  # float64 row FFT length 16384
     wide = _plan(dims=(40, 5000))   # 8192-point complex rows: radix 16 only
@@ -135,19 +134,20 @@ def test_batch_create_checks_and_layout(lib):
     assert singles < b.workspace_bytes < singles + 64 * 1024
 
 
-def test_tall_grids_float32_only(lib):
-    # n0 up to 4096 takes 8192-point columns (float32, radix 16 only)
+def test_tall_grids(lib):
+    # n0 up to 4096 takes 8192-point columns (radix 16 only), in both precisions
     p = _plan(dims=(3000, 40))
     assert p.padded == (8192, 128)
     assert p.schedule["col_e"] == 16
     with pytest.raises(ValueError, match="unsupported"):
         p.set_schedule(16, 8)
     p.set_schedule(8, 16)
+    q = _plan(dims=(3000, 40), precision="fp64")
+    assert q.schedule["col_e"] == 16
     with pytest.raises(ValueError, match="unsupported"):
-        _plan(dims=(3000, 40), precision="fp64")
+        q.set_schedule(16, 8)
     with pytest.raises(ValueError, match="unsupported"):
         _plan(dims=(4097, 40))
-    _plan(dims=(2048, 40), precision="fp64")
 
 
 def test_phi0_route_defaults_and_checks(lib):

@@ -29,26 +29,31 @@ TALL = [
 ]
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
 @pytest.mark.parametrize("case", TALL, ids=[c[0] for c in TALL])
-def test_forward_parity_tall(case):
+def test_forward_parity_tall(case, prec):
     import paper_1403_1937_amd as pk
     name, dims, h, hbar, T, n_src, seed = case
+    if prec == "fp64" and dims[1] > 4096:
+        pytest.skip("float64 rows end at 4096 points (planner limit)")
     rng = np.random.default_rng(seed)
     f = workloads.smoothed_noise(dims, 4.0, 1.0, 3.0, rng).astype(np.float32)
     src = workloads.distinct_sources(dims, n_src, rng)
     s = rng.uniform(0.0, 0.05, n_src)
-    print(f"tall case {name} {dims} fp32", flush=True)
-    pl = pk.Plan(dims, h, hbar, T, n_src, "fp32")
+    print(f"tall case {name} {dims} {prec}", flush=True)
+    pl = pk.Plan(dims, h, hbar, T, n_src, prec)
     assert pl.padded[0] == 8192 or pl.padded[1] == 16384
-    ft = torch.as_tensor(f).cuda()
+    dt = torch.float32 if prec == "fp32" else torch.float64
+    ft = torch.as_tensor(f.astype(np.float64)).to("cuda", dt)
     S, info = pk.solve(ft, src, h, hbar, T, src_s=s, return_info=True)
     S = S.double().cpu().numpy()
-    o = oracle.solve(f.astype(np.float64), src, h, hbar, T, src_s=np.asarray(s, np.float32))
+    o = oracle.solve(f.astype(np.float64), src, h, hbar, T,
+                     src_s=np.asarray(s, np.float32 if prec == "fp32" else np.float64))
     assert info["flags"] == 0
-    worst, frac, _ = report(S, o, hbar, "fp32")
-    nbad = envelope_violations(S, o, hbar, "fp32")
+    worst, frac, _ = report(S, o, hbar, prec)
+    nbad = envelope_violations(S, o, hbar, prec)
     print(f"  max rel {worst:.3e} on {frac:.3f}; envelope violations {nbad}", flush=True)
-    assert frac > 0.1 and worst <= TOL["fp32"] and nbad == 0
+    assert frac > 0.1 and worst <= TOL[prec] and nbad == 0
 
 
 def test_adjoint_tall():
