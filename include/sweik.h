@@ -60,9 +60,8 @@ typedef enum {
   SWEIK_OK = 0,
   SWEIK_EINVAL = 1,       /* invalid argument */
   SWEIK_EUNSUPPORTED = 2, /* valid but not supported: a grid beyond the sizes
-                             below (2D n0 <= 4096, n1 <= 8192 in float32
-                             and n1 <= 4096 in float64; 3D every axis
-                             <= 1024), a
+                             below (2D n0 <= 4096 and n1 <= 8192; 3D every
+                             axis <= 1024), a
                              2D-only call on a 3D plan, or a schedule the
                              plan cannot run */
   SWEIK_EWORKSPACE = 3,   /* workspace or checkpoint buffer too small */
@@ -114,9 +113,9 @@ typedef struct sweik_plan_s *sweik_plan;
 /* Validate a problem and choose the kernel schedule.  Host only: makes no
  * HIP call.  Returns SWEIK_EINVAL for invalid fields, SWEIK_EUNSUPPORTED for
  * grids beyond the supported sizes.  Padded FFT lengths (the next power of
- * two >= 2n-1, at least 64): 2D axis 0 <= 8192, axis 1 <= 16384 in float32
- * and 8192 in float64; 3D every axis <= 2048.  In grid points: 2D
- * n0 <= 4096, n1 <= 8192 (float32) or 4096 (float64), 3D n0, n1, n2 <= 1024.  The bound is the line
+ * two >= 2n-1, at least 64): 2D axis 0 <= 8192 and axis 1 <= 16384; 3D
+ * every axis <= 2048.  In grid points: 2D n0 <= 4096 and n1 <= 8192, 3D n0,
+ * n1, n2 <= 1024, in both precisions.  The bound is the line
  * length one work-group transforms in its registers and LDS (a column of
  * 8192 points, a real row of 16384); the
  * method itself has none, and a larger grid would need a two-level

@@ -88,12 +88,19 @@ template <typename R> constexpr size_t row_lds_core(int H) {
          ((size_t)row_twl_len(H) + (size_t)row_stage_tw<R>(H) +
           (size_t)row_rpw(H) * row_line_len<R>(H));
 }
+// sources of the phi_0 row pass held in LDS (the rest are read from memory):
+// 512, or 128 for rows beyond 4096 points, so that a double 8192-point row
+// fits
+constexpr int row_src_lds(int H) { return H > 4096 ? 128 : 512; }
 // static shared memory of a row pass (block reductions, scalars, the term
-// scales; phi_0 also holds up to 512 sources and their weights), at least
-// what the compiled kernels declare (group segment of the code objects:
-// 1312 bytes for the other modes; phi_0 12912 in float, 16960 in double)
-template <typename R> constexpr size_t row_lds_static(int mode) {
-  return mode == ROW_PHI0 ? (sizeof(R) == 4 ? 13312 : 17408) : 1536;
+// scales; phi_0 also holds up to row_src_lds sources and their weights), at
+// least what the compiled kernels declare (group segment of the code
+// objects: 1312 bytes for the other modes; phi_0 with 512 sources 12912 in
+// float, 16960 in double, each source 8 + sizeof(R) bytes of it)
+template <typename R> constexpr size_t row_lds_static(int mode, int H) {
+  return mode == ROW_PHI0 ? (sizeof(R) == 4 ? 13312 : 17408) -
+                                (size_t)(512 - row_src_lds(H)) * (8 + sizeof(R))
+                          : 1536;
 }
 template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
   // per staged row: f for phi_0 (the source grid for its transform);
@@ -110,7 +117,7 @@ template <typename R> constexpr size_t row_stage_bytes(int H, int mode) {
 // are used.  The full gradient's adjoint pass keeps its staging: its
 // registers allow one work-group per CU anyway.
 template <typename R> constexpr bool row_staged(int H, int mode) {
-  const size_t plain = row_lds_core<R>(H) + row_lds_static<R>(mode);
+  const size_t plain = row_lds_core<R>(H) + row_lds_static<R>(mode, H);
   const size_t staged = plain + row_stage_bytes<R>(H, mode);
   return row_stage_bytes<R>(H, mode) > 0 && staged <= kLdsDevice &&
          (staged <= kLdsDevice / 2 || plain > kLdsDevice / 2 || mode == ROW_ADJ_B);
@@ -120,7 +127,7 @@ template <typename R> constexpr size_t row_lds_bytes(int H, int mode) {
 }
 // dynamic + static shared memory of a row pass fits a work-group
 template <typename R> constexpr bool row_fits(int H, int mode) {
-  return row_lds_bytes<R>(H, mode) + row_lds_static<R>(mode) <= kLdsDevice;
+  return row_lds_bytes<R>(H, mode) + row_lds_static<R>(mode, H) <= kLdsDevice;
 }
 // a row pass of length H with radix-E teams is built and planned: it fits the
 // LDS, E <= H, and rows beyond 4096 complex points (one per work-group) take
@@ -135,7 +142,7 @@ template <typename R> constexpr size_t row_init_lds_bytes(int H) {
                                                                        : row_lds_bytes<R>(H, ROW_PHI0);
 }
 template <typename R> constexpr bool row_init_pairs(int H) {
-  return row_init_lds_bytes<R>(H) + row_lds_static<R>(ROW_GHAT) + row_lds_static<R>(ROW_PHI0) <=
+  return row_init_lds_bytes<R>(H) + row_lds_static<R>(ROW_GHAT, H) + row_lds_static<R>(ROW_PHI0, H) <=
          kLdsDevice / 2;
 }
 // Column pass LDS: the stage twiddle tables of the length-M0 FFT (room for

@@ -462,7 +462,7 @@ __device__ __forceinline__ void row_pass(const Args2<R> &a, int term, unsigned c
 
   // sources of phi_0 and their log-weights -s_k/hbar (the first kSrcLds of
   // them through LDS)
-  constexpr int kSrcLds = MODE == ROW_PHI0 ? 512 : 1;
+  constexpr int kSrcLds = MODE == ROW_PHI0 ? row_src_lds(H) : 1;
   __shared__ int s_src[2 * kSrcLds];
   __shared__ R s_lw[kSrcLds];
   auto logw = [&](int k) -> double {  // -s_k / hbar (log2 e times that in float32)

@@ -69,9 +69,9 @@ def test_unsupported_sizes(lib):
     with pytest.raises(ValueError, match="unsupported"):
         _plan(dims=(64, 8193))      # row FFT length 32768
     _plan(dims=(4096, 8192))        # largest 2D grid (float32)
-    _plan(dims=(4096, 4096), precision="fp64")  # largest float64 grid
+    _plan(dims=(4096, 8192), precision="fp64")  # largest float64 grid
     with pytest.raises(ValueError, match="unsupported"):
-        _plan(dims=(64, 4097), precision="fp64")  # float64 row FFT length 16384
+        _plan(dims=(64, 8193), precision="fp64")  # float64 row FFT length 32768
     wide = _plan(dims=(40, 5000))   # 8192-point complex rows: radix 16 only
     assert wide.schedule["row_e"] == 16
     with pytest.raises(ValueError, match="unsupported"):

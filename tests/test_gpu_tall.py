@@ -34,8 +34,6 @@ TALL = [
 def test_forward_parity_tall(case, prec):
     import paper_1403_1937_amd as pk
     name, dims, h, hbar, T, n_src, seed = case
-    if prec == "fp64" and dims[1] > 4096:
-        pytest.skip("float64 rows end at 4096 points (planner limit)")
     rng = np.random.default_rng(seed)
     f = workloads.smoothed_noise(dims, 4.0, 1.0, 3.0, rng).astype(np.float32)
     src = workloads.distinct_sources(dims, n_src, rng)
